@@ -1,0 +1,183 @@
+/*
+ * askit.h -- C ABI of the MI355X (gfx950) ASKIT kernel-summation library.
+ *
+ * ASKIT (March, Xiao, Biros, arXiv 1410.0260) approximates the kernel sum
+ *
+ *     u_i = sum_{j=1..N} K(x_i, x_j) w_j,   i = 1..N        (Eq. e:problem)
+ *
+ * with the Gaussian kernel K(x, y_j) = exp(-|x - y_j|^2 / (2 h_j^2)), h
+ * fixed or per source point.  Near interactions are summed directly over the
+ * leaves kept by neighbour-based pruning (Eq. e:prune, Alg. 4); far
+ * interactions use the skeleton S_alpha of each pruned node and its skeleton
+ * weights w~_alpha = w(S_alpha) + P_alpha w(R_alpha) (Sec. 2.1); P_alpha
+ * comes from an interpolative decomposition of a row-sampled kernel block
+ * (Sec. 2.1 "Approximate skeletonization", Eq. e:sk_targets, Alg. 3).
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers, row-major, with an explicit
+ *     leading dimension in elements (ldx >= d, ldw >= nrhs, ...).  The
+ *     caller owns them; the library never frees or retains them.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued on it; setup and update_weights additionally synchronise the
+ *     stream before returning (they read back sizes).  evaluate and query
+ *     return once their work is enqueued: outputs are valid after the caller
+ *     synchronises the stream.  Inputs must stay valid until then.
+ *   - Results are returned in the caller's original point order.
+ *   - Errors are reported by status code; askit_last_error() returns a
+ *     thread-local message for the last failing call on the calling thread.
+ *     No C++ exception crosses this boundary.
+ *   - A handle is not thread-safe: one thread at a time per handle.
+ */
+#ifndef ASKIT_H
+#define ASKIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ASKIT_ABI_VERSION 1u
+
+typedef enum {
+    ASKIT_OK = 0,
+    ASKIT_ERR_INVALID_ARG = 1,   /* bad shape, parameter or non-finite input */
+    ASKIT_ERR_OUT_OF_MEMORY = 2, /* device allocation failed */
+    ASKIT_ERR_DEVICE = 3,        /* no usable gfx950 device, or a HIP call failed */
+    ASKIT_ERR_NOT_READY = 4,     /* evaluate before any update_weights */
+    ASKIT_ERR_UNSUPPORTED = 5    /* valid request outside the built limits */
+} askit_status;
+
+typedef enum {
+    ASKIT_PREC_FP32 = 0,   /* distances on MFMA in FP32, kernel and sums in FP32 */
+    ASKIT_PREC_BF16X3 = 1  /* distance products as bf16 hi/lo split (hi*hi + hi*lo + lo*hi)
+                              on MFMA with FP32 accumulation */
+} askit_precision;
+
+/* Method parameters (Sec. 4 "Complexity and error", parameter list). */
+typedef struct {
+    uint32_t struct_size;   /* sizeof(askit_params) */
+    uint32_t abi_version;   /* ASKIT_ABI_VERSION */
+    int32_t leaf_size;      /* m: points per leaf (a node with more than m points is split) */
+    int32_t kappa;          /* kappa: nearest neighbours per point, 1 <= kappa < N */
+    int32_t max_skeleton;   /* s_max: largest skeleton size, >= 1 */
+    int32_t sample_rows;    /* l: sampled rows per node; 0 selects s_max + 20; must be >= s_max */
+    double id_tol;          /* tau >= 0: rank = first t with |R_tt| <= max(tau, 64 eps)|R_00| */
+    double bandwidth;       /* h > 0 for the fixed-bandwidth Gaussian */
+    int32_t bw_neighbor;    /* > 0: variable bandwidth h_j = distance from x_j to its
+                               bw_neighbor-th nearest neighbour (1-based, <= kappa) */
+    int32_t precision;      /* askit_precision */
+    uint64_t seed;          /* sampler stream (SplitMix64) seed */
+} askit_params;
+
+typedef struct askit_handle askit_handle;
+
+/* Fills *p with defaults: m = 128, kappa = 16, s_max = 64, l = 0, tau = 1e-6,
+ * h = 1, fixed bandwidth, FP32, seed 0. */
+askit_status askit_params_default(askit_params *p);
+
+/*
+ * Builds everything that does not depend on the weights (Alg. 5 lines 1-3):
+ * exact kappa-nearest-neighbour lists, the median-split tree (Sec. 3.2), the
+ * node neighbour lists (Alg. 2), sampled rows (Eq. e:sk_targets), the
+ * skeletons and projections P_alpha (Alg. 3), and the interaction lists of
+ * the downward pass (Eq. e:prune).
+ *   X    device, N x d FP32, row stride ldx >= d; read only during the call.
+ *   N    number of points, 2 <= N < 2^31; d >= 1.
+ *   out  receives a new handle that owns device copies of all it keeps.
+ * Returns ASKIT_ERR_INVALID_ARG for N < 2, d < 1, kappa >= N, m < 1,
+ * s_max < 1, l < s_max, h <= 0 with a fixed bandwidth, non-finite X, or a
+ * zero variable bandwidth (duplicate points).  Synchronises `stream`.
+ */
+askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx,
+                         const askit_params *p, void *stream, askit_handle **out);
+
+/*
+ * Upward pass (Sec. 2.1, Alg. 3): computes the skeleton weights of every
+ * node from W (device, N x nrhs FP32, original point order, row stride
+ * ldw >= nrhs), 1 <= nrhs <= 64.  W is read only during the call.
+ * Synchronises `stream`.
+ */
+askit_status askit_update_weights(askit_handle *h, const float *W, int64_t ldw, int32_t nrhs,
+                                  void *stream);
+
+/*
+ * Downward pass (Alg. 4) at every point: U (device, N x nrhs FP32, row
+ * stride ldu >= nrhs) receives u in the original point order.
+ * ASKIT_ERR_NOT_READY before the first askit_update_weights.
+ */
+askit_status askit_evaluate(askit_handle *h, float *U, int64_t ldu, void *stream);
+
+/*
+ * Evaluation at M new target points Y (device, M x d FP32, row stride ldy)
+ * that are not sources (an extension of Alg. 4: a node is pruned for y when
+ * it holds none of y's kappa nearest sources).  U (device, M x nrhs FP32,
+ * row stride ldu).  1 <= M; synchronises `stream` (it reads back list sizes).
+ */
+askit_status askit_query(askit_handle *h, const float *Y, int64_t M, int64_t ldy, float *U,
+                         int64_t ldu, void *stream);
+
+void askit_destroy(askit_handle *h);
+
+/* Thread-local description of the last error on the calling thread ("" if none). */
+const char *askit_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Diagnostics.  Sizes, counters and host copies of the internal structures,
+ * for verification against a reference implementation and for reporting.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t N;
+    int32_t d, kappa, leaf_size, max_skeleton, sample_rows, nrhs;
+    int32_t num_nodes, num_leaves, depth, ncol_max, num_slabs;
+    int64_t near_entries, far_entries;   /* interaction-list entries (slab, node) */
+    int64_t near_pairs, far_pairs;       /* algorithmic (target, source) pairs of one evaluation */
+    int64_t knn_uncertified_rows;        /* rows that needed the exact fallback */
+    double t_knn_ms, t_tree_ms, t_lists_ms, t_skel_ms, t_inter_ms; /* last setup, per phase */
+    double t_update_ms;                  /* last update_weights */
+    double t_knn_sweep_ms;               /* last setup: the approximate kNN sweep kernel alone */
+    double t_qr_ms;                      /* last setup: the QR kernels alone (all levels) */
+} askit_info;
+
+askit_status askit_get_info(const askit_handle *h, askit_info *out);
+
+/* Node record, breadth-first numbering (root = 0, left before right). */
+typedef struct {
+    int32_t lo, hi;          /* tree positions [lo, hi) */
+    int32_t level, parent, left, right;  /* -1 where absent */
+    int64_t path;            /* Morton path bits: left = 0, right = 1 */
+} askit_node;
+
+typedef enum {
+    ASKIT_X_PERM = 1,        /* int32[N]: original id at each tree position */
+    ASKIT_X_KNN_IDX = 2,     /* int32[N*kappa]: neighbours (original ids), original row order */
+    ASKIT_X_KNN_DIST = 3,    /* double[N*kappa]: squared distances, ascending per row */
+    ASKIT_X_NODES = 4,       /* askit_node[num_nodes] */
+    ASKIT_X_NLIST_POS = 5,   /* int32[num_nodes*l]: node neighbour lists (tree positions) */
+    ASKIT_X_NLIST_KEY = 6,   /* double[num_nodes*l] */
+    ASKIT_X_NLIST_CNT = 7,   /* int32[num_nodes] */
+    ASKIT_X_ROWS = 8,        /* int32[num_nodes*l]: sampled rows T_alpha (tree positions) */
+    ASKIT_X_ROWS_CNT = 9,    /* int32[num_nodes] */
+    ASKIT_X_SKEL = 10,       /* int32[num_nodes*s_max]: skeleton (tree positions) */
+    ASKIT_X_SKEL_K = 11,     /* int32[num_nodes]: skeleton sizes */
+    ASKIT_X_COLPERM = 12,    /* int32[num_nodes*ncol_max]: ID column pivot order */
+    ASKIT_X_NCOLS = 13,      /* int32[num_nodes]: ID column counts */
+    ASKIT_X_PROJ = 14,       /* float[num_nodes*s_max*ncol_max]: P_alpha, row stride ncols-k */
+    ASKIT_X_SKEL_W = 15,     /* float[num_nodes*s_max*nrhs]: skeleton weights */
+    ASKIT_X_SLAB_PTR = 16,   /* int32[2*num_slabs+2]: near offsets then far offsets (CSR) */
+    ASKIT_X_SLAB_NODE = 17,  /* int32[near_entries+far_entries]: node ids, near block first */
+    ASKIT_X_SLAB_MASK = 18,  /* uint64[near_entries+far_entries]: row masks */
+    ASKIT_X_SLAB_ROW0 = 19,  /* int32[num_slabs]: first tree position of each slab */
+    ASKIT_X_BANDWIDTH = 20   /* double[N]: per-source bandwidth, original order */
+} askit_export_item;
+
+/* Copies item `what` into host buffer `dst` of `cap` bytes; *bytes receives
+ * the size needed (call with dst = NULL to query it). */
+askit_status askit_export(const askit_handle *h, int32_t what, void *dst, size_t cap,
+                          size_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ASKIT_H */

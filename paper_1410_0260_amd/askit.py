@@ -1,0 +1,219 @@
+"""Thin Python binding of the gfx950 ASKIT library (`libaskit.so`).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch supplies device memory (CUDA/HIP tensors) and the
+current stream; the library is called through its C ABI (include/askit.h).
+Importing this module loads the library and fails loudly when it has not
+been built: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaskit.so")
+
+OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_READY, ERR_UNSUPPORTED = range(6)
+PREC_FP32, PREC_BF16X3 = 0, 1
+ABI_VERSION = 1
+
+X_PERM, X_KNN_IDX, X_KNN_DIST, X_NODES, X_NLIST_POS, X_NLIST_KEY, X_NLIST_CNT = 1, 2, 3, 4, 5, 6, 7
+X_ROWS, X_ROWS_CNT, X_SKEL, X_SKEL_K, X_COLPERM, X_NCOLS, X_PROJ, X_SKEL_W = 8, 9, 10, 11, 12, 13, 14, 15
+X_SLAB_PTR, X_SLAB_NODE, X_SLAB_MASK, X_SLAB_ROW0, X_BANDWIDTH = 16, 17, 18, 19, 20
+
+NODE_DTYPE = np.dtype([("lo", "<i4"), ("hi", "<i4"), ("level", "<i4"), ("parent", "<i4"),
+                       ("left", "<i4"), ("right", "<i4"), ("path", "<i8")])
+
+
+class Params(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("abi_version", C.c_uint32),
+                ("leaf_size", C.c_int32), ("kappa", C.c_int32), ("max_skeleton", C.c_int32),
+                ("sample_rows", C.c_int32), ("id_tol", C.c_double), ("bandwidth", C.c_double),
+                ("bw_neighbor", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64)]
+
+
+class Info(C.Structure):
+    _fields_ = [("N", C.c_int64), ("d", C.c_int32), ("kappa", C.c_int32), ("leaf_size", C.c_int32),
+                ("max_skeleton", C.c_int32), ("sample_rows", C.c_int32), ("nrhs", C.c_int32),
+                ("num_nodes", C.c_int32), ("num_leaves", C.c_int32), ("depth", C.c_int32),
+                ("ncol_max", C.c_int32), ("num_slabs", C.c_int32), ("near_entries", C.c_int64),
+                ("far_entries", C.c_int64), ("near_pairs", C.c_int64), ("far_pairs", C.c_int64),
+                ("knn_uncertified_rows", C.c_int64), ("t_knn_ms", C.c_double),
+                ("t_tree_ms", C.c_double), ("t_lists_ms", C.c_double), ("t_skel_ms", C.c_double),
+                ("t_inter_ms", C.c_double), ("t_update_ms", C.c_double),
+                ("t_knn_sweep_ms", C.c_double), ("t_qr_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class AskitError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"askit error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+EXPORTED = ["askit_params_default", "askit_setup", "askit_update_weights", "askit_evaluate",
+            "askit_query", "askit_destroy", "askit_last_error", "askit_get_info", "askit_export"]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        P, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.askit_params_default.argtypes = [C.POINTER(Params)]
+        L.askit_setup.argtypes = [P, i64, i32, i64, C.POINTER(Params), P, C.POINTER(P)]
+        L.askit_update_weights.argtypes = [P, P, i64, i32, P]
+        L.askit_evaluate.argtypes = [P, P, i64, P]
+        L.askit_query.argtypes = [P, P, i64, i64, P, i64, P]
+        L.askit_destroy.argtypes = [P]
+        L.askit_destroy.restype = None
+        L.askit_last_error.restype = C.c_char_p
+        L.askit_get_info.argtypes = [P, C.POINTER(Info)]
+        L.askit_export.argtypes = [P, i32, P, C.c_size_t, C.POINTER(C.c_size_t)]
+        for f in EXPORTED:
+            if f not in ("askit_destroy", "askit_last_error"):
+                getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise AskitError(rc, lib().askit_last_error().decode())
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    _check(lib().askit_params_default(C.byref(p)))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def params_from_workload(w, precision=PREC_FP32) -> Params:
+    return default_params(leaf_size=w.m, kappa=w.kappa, max_skeleton=w.smax, sample_rows=w.ell_eff,
+                          id_tol=w.tau, bandwidth=w.h if w.h > 0 else 1.0,
+                          bw_neighbor=w.bw_neighbor, precision=precision, seed=w.seed)
+
+
+def _stream(torch):
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f32(torch, a):
+    t = a if torch.is_tensor(a) else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32))
+    t = t.to(device="cuda", dtype=torch.float32)
+    if t.dim() == 1:
+        t = t[:, None]
+    return t.contiguous()
+
+
+@dataclass
+class Handle:
+    ptr: C.c_void_p
+    N: int
+    d: int
+    nrhs: int = 0
+
+    # -------------------------------------------------------------- calls
+    def update_weights(self, W):
+        import torch
+        Wd = _dev_f32(torch, W)
+        assert Wd.shape[0] == self.N
+        _check(lib().askit_update_weights(self.ptr, C.c_void_p(Wd.data_ptr()), Wd.stride(0),
+                                          Wd.shape[1], _stream(torch)))
+        self.nrhs = Wd.shape[1]
+
+    def evaluate(self, out=None):
+        import torch
+        U = out if out is not None else torch.empty((self.N, self.nrhs), device="cuda",
+                                                     dtype=torch.float32)
+        _check(lib().askit_evaluate(self.ptr, C.c_void_p(U.data_ptr()), U.stride(0), _stream(torch)))
+        return U
+
+    def query(self, Y, out=None):
+        import torch
+        Yd = _dev_f32(torch, Y)
+        M = Yd.shape[0]
+        U = out if out is not None else torch.empty((M, self.nrhs), device="cuda", dtype=torch.float32)
+        _check(lib().askit_query(self.ptr, C.c_void_p(Yd.data_ptr()), M, Yd.stride(0),
+                                 C.c_void_p(U.data_ptr()), U.stride(0), _stream(torch)))
+        return U
+
+    def info(self) -> dict:
+        i = Info()
+        _check(lib().askit_get_info(self.ptr, C.byref(i)))
+        return i.as_dict()
+
+    def export(self, item, dtype):
+        n = C.c_size_t(0)
+        _check(lib().askit_export(self.ptr, item, None, 0, C.byref(n)))
+        dt = np.dtype(dtype)
+        buf = np.empty(max(1, n.value // dt.itemsize), dtype=dt)
+        _check(lib().askit_export(self.ptr, item, buf.ctypes.data_as(C.c_void_p), buf.nbytes,
+                                  C.byref(n)))
+        return buf[: n.value // dt.itemsize]
+
+    def close(self):
+        if self.ptr:
+            lib().askit_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------- exports
+    def structures(self) -> dict:
+        """Host copies of every internal structure (for verification)."""
+        inf = self.info()
+        nn, ell, smax, ncm = inf["num_nodes"], inf["sample_rows"], inf["max_skeleton"], inf["ncol_max"]
+        kap = inf["kappa"]
+        out = dict(info=inf)
+        out["perm"] = self.export(X_PERM, np.int32)
+        out["knn_idx"] = self.export(X_KNN_IDX, np.int32).reshape(self.N, kap)
+        out["knn_d"] = self.export(X_KNN_DIST, np.float64).reshape(self.N, kap)
+        out["nodes"] = self.export(X_NODES, np.uint8).view(NODE_DTYPE)
+        out["nl_pos"] = self.export(X_NLIST_POS, np.int32).reshape(nn, ell)
+        out["nl_key"] = self.export(X_NLIST_KEY, np.float64).reshape(nn, ell)
+        out["nl_cnt"] = self.export(X_NLIST_CNT, np.int32)
+        out["T"] = self.export(X_ROWS, np.int32).reshape(nn, ell)
+        out["T_cnt"] = self.export(X_ROWS_CNT, np.int32)
+        out["S"] = self.export(X_SKEL, np.int32).reshape(nn, smax)
+        out["k"] = self.export(X_SKEL_K, np.int32)
+        out["colperm"] = self.export(X_COLPERM, np.int32).reshape(nn, ncm)
+        out["ncols"] = self.export(X_NCOLS, np.int32)
+        out["P"] = self.export(X_PROJ, np.float32)
+        out["slab_ptr"] = self.export(X_SLAB_PTR, np.int32)
+        out["slab_node"] = self.export(X_SLAB_NODE, np.int32)
+        out["slab_mask"] = self.export(X_SLAB_MASK, np.uint64)
+        out["slab_row0"] = self.export(X_SLAB_ROW0, np.int32)
+        out["hsrc"] = self.export(X_BANDWIDTH, np.float64)
+        if self.nrhs:
+            out["Wsk"] = self.export(X_SKEL_W, np.float32).reshape(nn, smax, self.nrhs)
+        return out
+
+
+def setup(X, params: Params) -> Handle:
+    """Build the ASKIT structures for the points X (N x d, any array or tensor)."""
+    import torch
+    Xd = _dev_f32(torch, X)
+    N, d = Xd.shape
+    h = C.c_void_p()
+    rc = lib().askit_setup(C.c_void_p(Xd.data_ptr()), N, d, Xd.stride(0), C.byref(params),
+                           _stream(torch), C.byref(h))
+    _check(rc)
+    return Handle(h, N, d)

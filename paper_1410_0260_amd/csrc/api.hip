@@ -1,0 +1,598 @@
+// C ABI of the library: argument checks, host orchestration of the setup
+// phases (Alg. 5), the upward pass, evaluation and queries.
+#include "askit_impl.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+using namespace askit;
+
+namespace askit {
+
+thread_local std::string g_err;
+
+void fail(askit_status code, const std::string &msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return;
+    askit_status c = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? ASKIT_ERR_OUT_OF_MEMORY
+                                                                              : ASKIT_ERR_DEVICE;
+    fail(c, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+__global__ void k_gather_f64(const double *__restrict__ src, const int32_t *__restrict__ idx, int64_t n,
+                             double *__restrict__ dst)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[idx[i]];
+}
+
+void gather_f64(const double *src, const int32_t *idx, int64_t n, double *dst, hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gather_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, idx, n, dst);
+    HIPC(hipGetLastError());
+}
+
+// Bandwidth per source: fixed h, or the distance to the b-th neighbour.
+__global__ void k_bandwidth(const double *__restrict__ knn_d, int64_t N, int kappa, int b, double h,
+                            double *__restrict__ hs, int32_t *bad)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double v = b > 0 ? sqrt(knn_d[j * kappa + (b - 1)]) : h;
+    if (!(v > 0.0)) atomicOr(bad, 1);
+    hs[j] = v;
+}
+
+// g = -log2(e) / (2 h^2) per tree position (FP32 exponent factor of exp2).
+__global__ void k_gfactor(const double *__restrict__ hs, const int32_t *__restrict__ perm, int64_t N,
+                          float *__restrict__ g)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    double h = hs[perm[p]];
+    g[p] = (float)(-1.4426950408889634 / (2.0 * h * h));
+}
+
+__global__ void k_leaf_of(const Node *__restrict__ nodes, const int32_t *__restrict__ leaves, int nl,
+                          int32_t *__restrict__ leaf_of)
+{
+    int q = blockIdx.x;
+    if (q >= nl) return;
+    Node nd = nodes[leaves[q]];
+    for (int p = nd.lo + threadIdx.x; p < nd.hi; p += blockDim.x) leaf_of[p] = leaves[q];
+}
+
+__global__ void k_permute_w(const float *__restrict__ W, int64_t ldw, const int32_t *__restrict__ perm,
+                            int64_t N, int R, float *__restrict__ Wt)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t p = t / R;
+    if (p >= N) return;
+    int r = (int)(t - p * R);
+    Wt[t] = W[(int64_t)perm[p] * ldw + r];
+}
+
+__global__ void k_map_pos(const int32_t *__restrict__ ids, int64_t n, const int32_t *__restrict__ iperm,
+                          int32_t *__restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = iperm[ids[i]];
+}
+
+}  // namespace askit
+
+#define API_BEGIN                                                                                 \
+    try {                                                                                         \
+        g_err.clear();
+#define API_END                                                                                   \
+    }                                                                                             \
+    catch (const Error &e)                                                                        \
+    {                                                                                             \
+        g_err = e.msg;                                                                            \
+        return e.code;                                                                            \
+    }                                                                                             \
+    catch (const std::bad_alloc &)                                                                \
+    {                                                                                             \
+        g_err = "host allocation failed";                                                         \
+        return ASKIT_ERR_OUT_OF_MEMORY;                                                           \
+    }                                                                                             \
+    catch (...)                                                                                   \
+    {                                                                                             \
+        g_err = "internal error";                                                                 \
+        return ASKIT_ERR_DEVICE;                                                                  \
+    }                                                                                             \
+    return ASKIT_OK;
+
+askit_handle::~askit_handle()
+{
+    for (void *p : allocs) (void)hipFree(p);
+}
+
+void *askit_handle::alloc(size_t bytes, bool zero)
+{
+    void *p = nullptr;
+    HIPC(hipMalloc(&p, std::max<size_t>(bytes, 16)));
+    allocs.push_back(p);
+    if (zero) HIPC(hipMemset(p, 0, std::max<size_t>(bytes, 16)));
+    return p;
+}
+
+static void check_device()
+{
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n < 1) fail(ASKIT_ERR_DEVICE, "no HIP device");
+    int dev = 0;
+    HIPC(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPC(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        fail(ASKIT_ERR_DEVICE, std::string("library is built for gfx950, device is ") + prop.gcnArchName);
+}
+
+// Tree shape (depends on N and m only): breadth-first, left before right.
+static void make_shape(askit_handle *h)
+{
+    h->nodes.clear();
+    h->nodes.push_back(Node{0, (int32_t)h->N, 0, -1, -1, -1, 0});
+    for (size_t a = 0; a < h->nodes.size(); ++a) {
+        Node nd = h->nodes[a];
+        int n = nd.hi - nd.lo;
+        if (n <= h->m) continue;
+        int nl = (n + 1) / 2;
+        int L = (int)h->nodes.size();
+        h->nodes.push_back(Node{nd.lo, nd.lo + nl, nd.level + 1, (int32_t)a, -1, -1, nd.path << 1});
+        h->nodes.push_back(Node{nd.lo + nl, nd.hi, nd.level + 1, (int32_t)a, -1, -1, (nd.path << 1) | 1});
+        h->nodes[a].left = L;
+        h->nodes[a].right = L + 1;
+    }
+    h->depth = 0;
+    for (auto &nd : h->nodes) h->depth = std::max(h->depth, (int)nd.level);
+    h->level_nodes.assign(h->depth + 1, {});
+    h->leaves.clear();
+    for (size_t a = 0; a < h->nodes.size(); ++a) {
+        h->level_nodes[h->nodes[a].level].push_back((int)a);
+        if (h->nodes[a].left < 0) h->leaves.push_back((int)a);
+    }
+    std::sort(h->leaves.begin(), h->leaves.end(),
+              [&](int x, int y) { return h->nodes[x].lo < h->nodes[y].lo; });
+    int maxleaf = 0;
+    for (int a : h->leaves) maxleaf = std::max(maxleaf, h->nodes[a].hi - h->nodes[a].lo);
+    h->ncol_max = std::max(maxleaf, 2 * h->smax);
+    h->slabs.clear();
+    for (int a : h->leaves)
+        for (int r0 = h->nodes[a].lo; r0 < h->nodes[a].hi; r0 += SLAB)
+            h->slabs.push_back(Slab{r0, std::min(SLAB, h->nodes[a].hi - r0), a, 0});
+    h->pslot.assign(h->nodes.size() + 1, 0);
+    int64_t off = 0;
+    for (size_t a = 0; a < h->nodes.size(); ++a) {
+        h->pslot[a] = off;
+        if (a == 0) continue;
+        const Node &nd = h->nodes[a];
+        int64_t n = nd.hi - nd.lo;
+        int64_t ncap = nd.left < 0 ? n : 2 * (int64_t)h->smax;
+        int64_t rows = std::min<int64_t>(h->ell, h->N - n);
+        int64_t kcap = std::min<int64_t>(std::min<int64_t>(h->smax, rows), ncap);
+        off += kcap * ncap;
+    }
+    h->pslot[h->nodes.size()] = off;
+    h->pslot_total = off;
+}
+
+extern "C" {
+
+askit_status askit_params_default(askit_params *p)
+{
+    if (!p) return ASKIT_ERR_INVALID_ARG;
+    std::memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(askit_params);
+    p->abi_version = ASKIT_ABI_VERSION;
+    p->leaf_size = 128;
+    p->kappa = 16;
+    p->max_skeleton = 64;
+    p->sample_rows = 0;
+    p->id_tol = 1e-6;
+    p->bandwidth = 1.0;
+    p->bw_neighbor = 0;
+    p->precision = ASKIT_PREC_FP32;
+    p->seed = 0;
+    return ASKIT_OK;
+}
+
+const char *askit_last_error(void) { return g_err.c_str(); }
+
+askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, const askit_params *p,
+                         void *stream, askit_handle **out)
+{
+    API_BEGIN
+    if (!out) fail(ASKIT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p || !X) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    if (p->struct_size != sizeof(askit_params) || p->abi_version != ASKIT_ABI_VERSION)
+        fail(ASKIT_ERR_INVALID_ARG, "askit_params size or ABI version mismatch");
+    if (N < 2 || N >= (1ll << 31)) fail(ASKIT_ERR_INVALID_ARG, "N must be in [2, 2^31)");
+    if (d < 1 || ldx < d) fail(ASKIT_ERR_INVALID_ARG, "need d >= 1 and ldx >= d");
+    if (p->kappa < 1 || p->kappa >= N) fail(ASKIT_ERR_INVALID_ARG, "need 1 <= kappa < N");
+    if (p->kappa > 64) fail(ASKIT_ERR_UNSUPPORTED, "kappa above 64 is not supported");
+    if (p->leaf_size < 1 || p->max_skeleton < 1) fail(ASKIT_ERR_INVALID_ARG, "need m >= 1, s_max >= 1");
+    int ell = p->sample_rows == 0 ? p->max_skeleton + 20 : p->sample_rows;
+    if (ell < p->max_skeleton) fail(ASKIT_ERR_INVALID_ARG, "need sample_rows >= max_skeleton");
+    if (!(p->id_tol >= 0.0)) fail(ASKIT_ERR_INVALID_ARG, "need id_tol >= 0");
+    if (p->bw_neighbor < 0 || p->bw_neighbor > p->kappa)
+        fail(ASKIT_ERR_INVALID_ARG, "need 0 <= bw_neighbor <= kappa");
+    if (p->bw_neighbor == 0 && !(p->bandwidth > 0.0 && std::isfinite(p->bandwidth)))
+        fail(ASKIT_ERR_INVALID_ARG, "need a positive finite bandwidth");
+    if (p->precision != ASKIT_PREC_FP32 && p->precision != ASKIT_PREC_BF16X3)
+        fail(ASKIT_ERR_INVALID_ARG, "unknown precision");
+    if (d > 1024) fail(ASKIT_ERR_UNSUPPORTED, "d above 1024 is not supported");
+    check_device();
+    hipStream_t s = (hipStream_t)stream;
+
+    std::unique_ptr<askit_handle> h(new askit_handle());
+    HIPC(hipGetDevice(&h->device));
+    h->N = N;
+    h->d = d;
+    h->dp = round_up(d, 16);
+    h->prm = *p;
+    h->prm.sample_rows = ell;
+    h->kappa = p->kappa;
+    h->m = p->leaf_size;
+    h->smax = p->max_skeleton;
+    h->ell = ell;
+    h->varh = p->bw_neighbor > 0;
+    make_shape(h.get());
+    const int64_t nn = (int64_t)h->nodes.size();
+    const int dp = h->dp, kappa = h->kappa;
+
+    hipEvent_t ev[6];
+    for (auto &e : ev) HIPC(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() { for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]); }
+    } evg{ev};
+
+    // device state
+    h->Xo = (float *)h->alloc(sizeof(float) * N * dp, false);
+    h->Xh = (uint16_t *)h->alloc(sizeof(uint16_t) * N * dp, false);
+    h->Xl = (uint16_t *)h->alloc(sizeof(uint16_t) * N * dp, false);
+    h->Xn = (float *)h->alloc(sizeof(float) * N, false);
+    h->Xt = (float *)h->alloc(sizeof(float) * N * dp, false);
+    h->gt = (float *)h->alloc(sizeof(float) * N, false);
+    h->hsrc = (double *)h->alloc(sizeof(double) * N, false);
+    h->perm = (int32_t *)h->alloc(sizeof(int32_t) * N, false);
+    h->iperm = (int32_t *)h->alloc(sizeof(int32_t) * N, false);
+    h->knn_idx = (int32_t *)h->alloc(sizeof(int32_t) * N * kappa, false);
+    h->knn_d = (double *)h->alloc(sizeof(double) * N * kappa, false);
+    h->d_nodes = (Node *)h->alloc(sizeof(Node) * nn, false);
+    h->leaf_of = (int32_t *)h->alloc(sizeof(int32_t) * N, false);
+    h->nl_pos = (int32_t *)h->alloc(sizeof(int32_t) * nn * ell, true);
+    h->nl_key = (double *)h->alloc(sizeof(double) * nn * ell, true);
+    h->nl_cnt = (int32_t *)h->alloc(sizeof(int32_t) * nn, true);
+    h->T = (int32_t *)h->alloc(sizeof(int32_t) * nn * ell, true);
+    h->T_cnt = (int32_t *)h->alloc(sizeof(int32_t) * nn, true);
+    h->S = (int32_t *)h->alloc(sizeof(int32_t) * nn * h->smax, true);
+    h->skk = (int32_t *)h->alloc(sizeof(int32_t) * nn, true);
+    h->colperm = (int32_t *)h->alloc(sizeof(int32_t) * nn * h->ncol_max, true);
+    h->ncols = (int32_t *)h->alloc(sizeof(int32_t) * nn, true);
+    h->P = (float *)h->alloc(sizeof(float) * std::max<int64_t>(h->pslot_total, 1), false);
+    h->d_pslot = (int64_t *)h->alloc(sizeof(int64_t) * (nn + 1), false);
+    h->Xs = (float *)h->alloc(sizeof(float) * nn * h->smax * dp, true);
+    h->gs = (float *)h->alloc(sizeof(float) * nn * h->smax, true);
+    h->d_slabs = (Slab *)h->alloc(sizeof(Slab) * h->slabs.size(), false);
+    HIPC(hipMemcpy(h->d_nodes, h->nodes.data(), sizeof(Node) * nn, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(h->d_pslot, h->pslot.data(), sizeof(int64_t) * (nn + 1), hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(h->d_slabs, h->slabs.data(), sizeof(Slab) * h->slabs.size(), hipMemcpyHostToDevice));
+    int32_t *flag = (int32_t *)h->alloc(sizeof(int32_t) * 4, true);
+
+    HIPC(hipEventRecord(ev[0], s));
+    // ---- points and exact neighbours
+    pack_points(X, N, d, ldx, dp, h->Xo, flag, s);
+    int32_t hflag = 0;
+    HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hflag) fail(ASKIT_ERR_INVALID_ARG, "X holds a non-finite value");
+    split_bf16(h->Xo, N, dp, h->Xh, h->Xl, h->Xn, s);
+    float mx = max_norm(h->Xn, N, s);
+    {
+        int32_t *cand, *bad;
+        float *thr;
+        HIPC(hipMallocAsync((void **)&cand, sizeof(int32_t) * N * KNN_CAND, s));
+        HIPC(hipMallocAsync((void **)&thr, sizeof(float) * N, s));
+        HIPC(hipMallocAsync((void **)&bad, sizeof(int32_t) * (N + 1), s));
+        HIPC(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
+        hipEvent_t k0, k1;
+        HIPC(hipEventCreate(&k0));
+        HIPC(hipEventCreate(&k1));
+        HIPC(hipEventRecord(k0, s));
+        knn_candidates(h->Xh, h->Xl, h->Xn, N, h->Xh, h->Xl, h->Xn, N, dp, true, cand, thr, s);
+        HIPC(hipEventRecord(k1, s));
+        knn_refine(h->Xo, N, h->Xo, N, d, dp, kappa, cand, thr, h->Xn, mx, true, h->knn_idx,
+                   h->knn_d, bad + 1, bad, s);
+        int32_t nbad = 0;
+        HIPC(hipMemcpyAsync(&nbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        h->knn_uncertified = nbad;
+        float kms = 0.f;
+        HIPC(hipEventElapsedTime(&kms, k0, k1));
+        h->t_knn_sweep = kms;
+        (void)hipEventDestroy(k0);
+        (void)hipEventDestroy(k1);
+        knn_exact_rows(h->Xo, h->Xo, N, d, dp, kappa, true, bad + 1, nbad, h->knn_idx, h->knn_d, s);
+        HIPC(hipFreeAsync(cand, s));
+        HIPC(hipFreeAsync(thr, s));
+        HIPC(hipFreeAsync(bad, s));
+    }
+    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_bandwidth, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, h->knn_d, N,
+                       kappa, p->bw_neighbor, p->bandwidth, h->hsrc, flag);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipEventRecord(ev[1], s));
+    HIPC(hipStreamSynchronize(s));
+    if (hflag) fail(ASKIT_ERR_INVALID_ARG, "zero bandwidth (duplicate points with variable bandwidth)");
+
+    // ---- tree
+    build_tree(h.get(), s);
+    gather_rows(h->Xo, h->perm, N, dp, h->Xt, s);
+    hipLaunchKernelGGL(k_gfactor, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, h->hsrc, h->perm,
+                       N, h->gt);
+    {
+        int32_t *dl;
+        HIPC(hipMallocAsync((void **)&dl, sizeof(int32_t) * h->leaves.size(), s));
+        HIPC(hipMemcpyAsync(dl, h->leaves.data(), sizeof(int32_t) * h->leaves.size(),
+                            hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_leaf_of, dim3((unsigned)h->leaves.size()), dim3(256), 0, s, h->d_nodes, dl,
+                           (int)h->leaves.size(), h->leaf_of);
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize(s));
+        HIPC(hipFreeAsync(dl, s));
+    }
+    HIPC(hipEventRecord(ev[2], s));
+    // ---- node lists and sampled rows
+    build_node_lists(h.get(), s);
+    sample_rows(h.get(), s);
+    HIPC(hipEventRecord(ev[3], s));
+    // ---- skeletons
+    skeletonize(h.get(), s);
+    HIPC(hipEventRecord(ev[4], s));
+    // ---- interaction lists
+    build_interactions(h.get(), s);
+    HIPC(hipEventRecord(ev[5], s));
+    HIPC(hipStreamSynchronize(s));
+    float ms;
+    HIPC(hipEventElapsedTime(&ms, ev[0], ev[1])); h->t_knn = ms;
+    HIPC(hipEventElapsedTime(&ms, ev[1], ev[2])); h->t_tree = ms;
+    HIPC(hipEventElapsedTime(&ms, ev[2], ev[3])); h->t_lists = ms;
+    HIPC(hipEventElapsedTime(&ms, ev[3], ev[4])); h->t_skel = ms;
+    HIPC(hipEventElapsedTime(&ms, ev[4], ev[5])); h->t_inter = ms;
+    *out = h.release();
+    API_END
+}
+
+askit_status askit_update_weights(askit_handle *h, const float *W, int64_t ldw, int32_t nrhs, void *stream)
+{
+    API_BEGIN
+    if (!h || !W) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    if (nrhs < 1 || nrhs > MAX_RHS) fail(ASKIT_ERR_INVALID_ARG, "need 1 <= nrhs <= 64");
+    if (ldw < nrhs) fail(ASKIT_ERR_INVALID_ARG, "need ldw >= nrhs");
+    hipStream_t s = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t nn = (int64_t)h->nodes.size();
+    if (nrhs > h->wcap) {
+        HIPC(hipStreamSynchronize(s));
+        auto drop = [&](void *p) {
+            if (!p) return;
+            (void)hipFree(p);
+            h->allocs.erase(std::remove(h->allocs.begin(), h->allocs.end(), p), h->allocs.end());
+        };
+        drop(h->Wt);
+        drop(h->Wsk);
+        h->Wt = (float *)h->alloc(sizeof(float) * h->N * nrhs, false);
+        h->Wsk = (float *)h->alloc(sizeof(float) * nn * h->smax * nrhs, true);
+        h->wcap = nrhs;
+    }
+    h->nrhs = nrhs;
+    int64_t tot = h->N * nrhs;
+    hipLaunchKernelGGL(k_permute_w, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, W, ldw,
+                       h->perm, h->N, nrhs, h->Wt);
+    HIPC(hipGetLastError());
+    upward(h, s);
+    HIPC(hipStreamSynchronize(s));
+    h->t_update = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    API_END
+}
+
+askit_status askit_evaluate(askit_handle *h, float *U, int64_t ldu, void *stream)
+{
+    API_BEGIN
+    if (!h || !U) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    if (h->nrhs < 1) fail(ASKIT_ERR_NOT_READY, "askit_update_weights has not been called");
+    if (ldu < h->nrhs) fail(ASKIT_ERR_INVALID_ARG, "need ldu >= nrhs");
+    EvalArgs a;
+    a.Y = h->Xt;
+    a.nslab = (int64_t)h->slabs.size();
+    a.slabs = h->d_slabs;
+    a.ptr = h->sl_ptr;
+    a.node = h->sl_node;
+    a.mask = h->sl_mask;
+    a.outmap = h->perm;
+    a.U = U;
+    a.ldu = ldu;
+    evaluate(h, a, (hipStream_t)stream);
+    API_END
+}
+
+askit_status askit_query(askit_handle *h, const float *Y, int64_t M, int64_t ldy, float *U, int64_t ldu,
+                         void *stream)
+{
+    API_BEGIN
+    if (!h || !Y || !U) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    if (M < 1 || M >= (1ll << 31)) fail(ASKIT_ERR_INVALID_ARG, "need 1 <= M < 2^31");
+    if (ldy < h->d) fail(ASKIT_ERR_INVALID_ARG, "need ldy >= d");
+    if (h->nrhs < 1) fail(ASKIT_ERR_NOT_READY, "askit_update_weights has not been called");
+    if (ldu < h->nrhs) fail(ASKIT_ERR_INVALID_ARG, "need ldu >= nrhs");
+    hipStream_t s = (hipStream_t)stream;
+    const int dp = h->dp, kappa = h->kappa;
+    std::vector<void *> tmp;
+    struct Guard {
+        std::vector<void *> &t;
+        hipStream_t s;
+        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+    } guard{tmp, s};
+    auto ta = [&](size_t b) {
+        void *p;
+        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        tmp.push_back(p);
+        return p;
+    };
+    float *Yp = (float *)ta(sizeof(float) * M * dp);
+    uint16_t *Yh = (uint16_t *)ta(sizeof(uint16_t) * M * dp);
+    uint16_t *Yl = (uint16_t *)ta(sizeof(uint16_t) * M * dp);
+    float *Yn = (float *)ta(sizeof(float) * M);
+    int32_t *flag = (int32_t *)ta(sizeof(int32_t) * (M + 1));
+    int32_t *cand = (int32_t *)ta(sizeof(int32_t) * M * KNN_CAND);
+    float *thr = (float *)ta(sizeof(float) * M);
+    int32_t *qidx = (int32_t *)ta(sizeof(int32_t) * M * kappa);
+    double *qd = (double *)ta(sizeof(double) * M * kappa);
+    int32_t *nb = (int32_t *)ta(sizeof(int32_t) * M * kappa);
+    int32_t *nbs = (int32_t *)ta(sizeof(int32_t) * M * kappa);
+    int32_t *order = (int32_t *)ta(sizeof(int32_t) * M);
+    float *Ys = (float *)ta(sizeof(float) * M * dp);
+    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    pack_points(Y, M, h->d, ldy, dp, Yp, flag, s);
+    int32_t hflag = 0;
+    HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hflag) fail(ASKIT_ERR_INVALID_ARG, "Y holds a non-finite value");
+    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    split_bf16(Yp, M, dp, Yh, Yl, Yn, s);
+    float mx = max_norm(h->Xn, h->N, s);
+    knn_candidates(Yh, Yl, Yn, M, h->Xh, h->Xl, h->Xn, h->N, dp, false, cand, thr, s);
+    knn_refine(Yp, M, h->Xo, h->N, h->d, dp, kappa, cand, thr, Yn, mx, false, qidx, qd, flag + 1, flag, s);
+    int32_t nbad = 0;
+    HIPC(hipMemcpyAsync(&nbad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    knn_exact_rows(Yp, h->Xo, h->N, h->d, dp, kappa, false, flag + 1, nbad, qidx, qd, s);
+    hipLaunchKernelGGL(k_map_pos, dim3((unsigned)((M * kappa + 255) / 256)), dim3(256), 0, s, qidx,
+                       M * kappa, h->iperm, nb);
+    HIPC(hipGetLastError());
+    int32_t *ptr, *node;
+    uint64_t *mask;
+    Slab *qslabs;
+    int64_t nen, nef;
+    sort_queries(h, nb, M, order, nbs, tmp, s);
+    gather_rows(Yp, order, M, dp, Ys, s);
+    build_query_interactions(h, nbs, M, qslabs, ptr, node, mask, nen, nef, tmp, s);
+    EvalArgs a;
+    a.Y = Ys;
+    a.nslab = (M + SLAB - 1) / SLAB;
+    a.slabs = qslabs;
+    a.ptr = ptr;
+    a.node = node;
+    a.mask = mask;
+    a.outmap = order;
+    a.U = U;
+    a.ldu = ldu;
+    evaluate(h, a, s);
+    HIPC(hipStreamSynchronize(s));
+    API_END
+}
+
+void askit_destroy(askit_handle *h)
+{
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    delete h;
+}
+
+askit_status askit_get_info(const askit_handle *h, askit_info *o)
+{
+    API_BEGIN
+    if (!h || !o) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    std::memset(o, 0, sizeof(*o));
+    o->N = h->N;
+    o->d = h->d;
+    o->kappa = h->kappa;
+    o->leaf_size = h->m;
+    o->max_skeleton = h->smax;
+    o->sample_rows = h->ell;
+    o->nrhs = h->nrhs;
+    o->num_nodes = (int32_t)h->nodes.size();
+    o->num_leaves = (int32_t)h->leaves.size();
+    o->depth = h->depth;
+    o->ncol_max = h->ncol_max;
+    o->num_slabs = (int32_t)h->slabs.size();
+    o->near_entries = h->near_entries;
+    o->far_entries = h->far_entries;
+    o->near_pairs = h->near_pairs;
+    o->far_pairs = h->far_pairs;
+    o->knn_uncertified_rows = h->knn_uncertified;
+    o->t_knn_ms = h->t_knn;
+    o->t_tree_ms = h->t_tree;
+    o->t_lists_ms = h->t_lists;
+    o->t_skel_ms = h->t_skel;
+    o->t_inter_ms = h->t_inter;
+    o->t_update_ms = h->t_update;
+    o->t_knn_sweep_ms = h->t_knn_sweep;
+    o->t_qr_ms = h->t_qr;
+    API_END
+}
+
+askit_status askit_export(const askit_handle *h, int32_t what, void *dst, size_t cap, size_t *bytes)
+{
+    API_BEGIN
+    if (!h) fail(ASKIT_ERR_INVALID_ARG, "NULL handle");
+    const int64_t nn = (int64_t)h->nodes.size();
+    const void *src = nullptr;
+    size_t n = 0;
+    bool host = false;
+    const int64_t nslab = (int64_t)h->slabs.size();
+    std::vector<int32_t> row0;
+    switch (what) {
+    case ASKIT_X_PERM: src = h->perm; n = 4 * h->N; break;
+    case ASKIT_X_KNN_IDX: src = h->knn_idx; n = 4 * h->N * h->kappa; break;
+    case ASKIT_X_KNN_DIST: src = h->knn_d; n = 8 * h->N * h->kappa; break;
+    case ASKIT_X_NODES: src = h->nodes.data(); n = sizeof(Node) * nn; host = true; break;
+    case ASKIT_X_NLIST_POS: src = h->nl_pos; n = 4 * nn * h->ell; break;
+    case ASKIT_X_NLIST_KEY: src = h->nl_key; n = 8 * nn * h->ell; break;
+    case ASKIT_X_NLIST_CNT: src = h->nl_cnt; n = 4 * nn; break;
+    case ASKIT_X_ROWS: src = h->T; n = 4 * nn * h->ell; break;
+    case ASKIT_X_ROWS_CNT: src = h->T_cnt; n = 4 * nn; break;
+    case ASKIT_X_SKEL: src = h->S; n = 4 * nn * h->smax; break;
+    case ASKIT_X_SKEL_K: src = h->skk; n = 4 * nn; break;
+    case ASKIT_X_COLPERM: src = h->colperm; n = 4 * nn * h->ncol_max; break;
+    case ASKIT_X_NCOLS: src = h->ncols; n = 4 * nn; break;
+    case ASKIT_X_PROJ: src = h->P; n = 4 * h->pslot_total; break;
+    case ASKIT_X_SKEL_W: src = h->Wsk; n = h->Wsk ? 4 * nn * h->smax * h->nrhs : 0; break;
+    case ASKIT_X_SLAB_PTR: src = h->sl_ptr; n = 4 * (2 * nslab + 2); break;
+    case ASKIT_X_SLAB_NODE: src = h->sl_node; n = 4 * (h->near_entries + h->far_entries); break;
+    case ASKIT_X_SLAB_MASK: src = h->sl_mask; n = 8 * (h->near_entries + h->far_entries); break;
+    case ASKIT_X_SLAB_ROW0:
+        row0.resize(nslab);
+        for (int64_t i = 0; i < nslab; ++i) row0[i] = h->slabs[i].row0;
+        src = row0.data();
+        n = 4 * nslab;
+        host = true;
+        break;
+    case ASKIT_X_BANDWIDTH: src = h->hsrc; n = 8 * h->N; break;
+    default: fail(ASKIT_ERR_INVALID_ARG, "unknown export item");
+    }
+    if (bytes) *bytes = n;
+    if (!dst) return ASKIT_OK;
+    if (cap < n) fail(ASKIT_ERR_INVALID_ARG, "destination buffer too small");
+    if (n == 0) return ASKIT_OK;
+    if (host) std::memcpy(dst, src, n);
+    else {
+        HIPC(hipDeviceSynchronize());
+        HIPC(hipMemcpy(dst, src, n, hipMemcpyDeviceToHost));
+    }
+    API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,203 @@
+// Internal declarations of the gfx950 ASKIT library: the handle, device
+// helpers shared by the kernel files, and the host-side launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/askit.h"
+
+namespace askit {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    askit_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(askit_status code, const std::string &msg);
+void hip_check(hipError_t e, const char *what);
+#define HIPC(x) ::askit::hip_check((x), #x)
+
+// ---------------------------------------------------------------- sizes
+constexpr int WAVE = 64;
+constexpr int SLAB = 64;           // target rows per evaluation work item (one bit per row)
+constexpr int KNN_CAND = 64;       // candidates kept per row by the approximate pass
+constexpr int MAX_RHS = 64;
+
+inline int round_up(int x, int a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- device helpers
+// Canonical squared distance: FP64, increasing k, no fused multiply-add.
+__device__ __forceinline__ double canon_sqdist(const float *a, const float *b, int d)
+{
+#pragma clang fp contract(off)
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double t = (double)a[k] - (double)b[k];
+        s += t * t;
+    }
+    return s;
+}
+
+__device__ __forceinline__ double canon_sqdist_c(const float *a, const double *c, int d)
+{
+#pragma clang fp contract(off)
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double t = (double)a[k] - c[k];
+        s += t * t;
+    }
+    return s;
+}
+
+// Order-preserving map of a double onto uint64 (total order for non-NaN).
+__device__ __forceinline__ uint64_t dkey(double x)
+{
+    uint64_t b = (uint64_t)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// ---------------------------------------------------------------- tree node
+struct Node {
+    int32_t lo, hi, level, parent, left, right;
+    int64_t path;
+};
+static_assert(sizeof(Node) == sizeof(askit_node), "node layout");
+
+// ---------------------------------------------------------------- handle
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Slab {              // SLAB consecutive tree positions of one leaf
+    int32_t row0, nrows, leaf, pad;
+};
+
+}  // namespace askit
+
+struct askit_handle {
+    // problem
+    int64_t N = 0;
+    int d = 0, dp = 0;                 // dp: coordinate stride (d rounded up to 16)
+    askit_params prm{};
+    int kappa = 0, m = 0, smax = 0, ell = 0, ncol_max = 0;
+    bool varh = false;
+    int nrhs = 0;                      // set by update_weights
+    int device = 0;
+
+    // tree (host copy; shape depends only on N and m)
+    std::vector<askit::Node> nodes;
+    std::vector<std::vector<int>> level_nodes;   // node ids per level
+    std::vector<int> leaves;                     // leaf node ids in position order
+    int depth = 0;                               // deepest level
+    std::vector<askit::Slab> slabs;
+    std::vector<int64_t> pslot;                  // per node offset of its P slot (floats)
+    int64_t pslot_total = 0;
+
+    // device state (owned)
+    std::vector<void *> allocs;
+    float *Xo = nullptr;          // N x dp, original order (FP32, zero padded)
+    uint16_t *Xh = nullptr, *Xl = nullptr;   // bf16 hi / lo split of Xo (N x dp)
+    float *Xn = nullptr;          // FP32 squared norms of Xo rows
+    float *Xt = nullptr;          // N x dp, tree order
+    float *gt = nullptr;          // per tree position: -log2(e) / (2 h^2)
+    double *hsrc = nullptr;       // per original id bandwidth
+    int32_t *perm = nullptr, *iperm = nullptr;
+    int32_t *knn_idx = nullptr;   // N x kappa original ids
+    double *knn_d = nullptr;      // N x kappa
+    askit::Node *d_nodes = nullptr;
+    int32_t *leaf_of = nullptr;   // per tree position: leaf node id
+    int32_t *nl_pos = nullptr;    // nn x ell
+    double *nl_key = nullptr;
+    int32_t *nl_cnt = nullptr;
+    int32_t *T = nullptr, *T_cnt = nullptr;   // nn x ell
+    int32_t *S = nullptr, *skk = nullptr;     // nn x smax, nn
+    int32_t *colperm = nullptr, *ncols = nullptr;   // nn x ncol_max, nn
+    float *P = nullptr;           // pslot_total floats
+    int64_t *d_pslot = nullptr;
+    float *Xs = nullptr;          // nn x smax x dp skeleton coordinates
+    float *gs = nullptr;          // nn x smax skeleton bandwidth factors
+    float *Wt = nullptr;          // N x nrhs tree order weights
+    float *Wsk = nullptr;         // nn x smax x nrhs skeleton weights
+    int wcap = 0;                 // columns allocated in Wt / Wsk
+    askit::Slab *d_slabs = nullptr;
+    int32_t *sl_ptr = nullptr;    // 2*nslab+2: near offsets [0..nslab], far offsets [nslab+1..]
+    int32_t *sl_node = nullptr;
+    uint64_t *sl_mask = nullptr;
+    int64_t near_entries = 0, far_entries = 0;
+
+    // diagnostics
+    int64_t near_pairs = 0, far_pairs = 0, knn_uncertified = 0;
+    double t_knn = 0, t_tree = 0, t_lists = 0, t_skel = 0, t_inter = 0, t_update = 0;
+    double t_knn_sweep = 0, t_qr = 0;
+
+    ~askit_handle();
+    void *alloc(size_t bytes, bool zero = true);
+};
+
+namespace askit {
+
+// ---------------------------------------------------------------- launchers
+// points.hip
+void pack_points(const float *X, int64_t N, int d, int64_t ldx, int dp, float *out, int32_t *bad,
+                 hipStream_t s);
+void split_bf16(const float *X, int64_t N, int dp, uint16_t *hi, uint16_t *lo, float *nrm,
+                hipStream_t s);
+void gather_rows(const float *src, const int32_t *idx, int64_t n, int dp, float *dst, hipStream_t s);
+
+// knn.hip
+void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int64_t M,
+                    const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int dp,
+                    bool exclude_self, int32_t *cand, float *thr, hipStream_t s);
+// exact re-rank of the candidates; rows whose certificate fails are appended to
+// `bad_rows` (count in *bad_count, device)
+void knn_refine(const float *Q, int64_t M, const float *X, int64_t N, int d, int dp, int kappa,
+                const int32_t *cand, const float *thr, const float *Qn, float maxnorm,
+                bool exclude_self, int32_t *idx, double *dist, int32_t *bad_rows,
+                int32_t *bad_count, hipStream_t s);
+void knn_exact_rows(const float *Q, const float *X, int64_t N, int d, int dp, int kappa,
+                    bool exclude_self, const int32_t *rows, int nrows, int32_t *idx, double *dist,
+                    hipStream_t s);
+float max_norm(const float *nrm, int64_t N, hipStream_t s);
+
+// tree.hip
+void build_tree(askit_handle *h, hipStream_t s);
+
+// lists.hip
+void build_node_lists(askit_handle *h, hipStream_t s);
+void sample_rows(askit_handle *h, hipStream_t s);
+void build_interactions(askit_handle *h, hipStream_t s);
+// query lists: nb is M x kappa neighbour positions; slabs of consecutive queries
+void build_query_interactions(askit_handle *h, const int32_t *nb, int64_t M, Slab *&slabs,
+                              int32_t *&ptr, int32_t *&node, uint64_t *&mask, int64_t &ne_near,
+                              int64_t &ne_far, std::vector<void *> &tmp, hipStream_t s);
+
+void gather_f64(const double *src, const int32_t *idx, int64_t n, double *dst, hipStream_t s);
+
+// queries sorted by (leaf of the nearest source, index): order[M], nb rows permuted
+void sort_queries(askit_handle *h, const int32_t *nb, int64_t M, int32_t *order, int32_t *nb_sorted,
+                  std::vector<void *> &tmp, hipStream_t s);
+
+// skel.hip
+void skeletonize(askit_handle *h, hipStream_t s);
+void upward(askit_handle *h, hipStream_t s);
+
+// eval.hip
+struct EvalArgs {
+    const float *Y;            // targets, rows of stride dp
+    int64_t nslab;
+    const Slab *slabs;         // row0 index into Y, nrows
+    const int32_t *ptr, *node; // CSR: near [0..nslab], far [nslab+1 .. 2 nslab + 1]
+    const uint64_t *mask;
+    const int32_t *outmap;     // output row of target row (NULL: identity)
+    float *U;
+    int64_t ldu;
+};
+void evaluate(askit_handle *h, const EvalArgs &a, hipStream_t s);
+
+}  // namespace askit

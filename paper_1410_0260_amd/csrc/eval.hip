@@ -1,0 +1,236 @@
+// Downward pass (Alg. 4) over the slab interaction lists.
+//
+// One workgroup per slab of up to 64 targets.  For every near entry (a leaf:
+// its points and weights) and far entry (a pruned node: its skeleton points
+// and skeleton weights), sources are taken in tiles of 64:
+//   r^2 = |x - c|^2 + |y - c|^2 - 2 (x - c).(y - c),  c = the slab's first
+//   target (centring keeps the cancellation small),
+// with the 64 x 64 dot products on MFMA (v_mfma_f32_32x32x2_f32, each wave a
+// 32 x 32 quadrant, operands staged through LDS in 64-dimension chunks), then
+// K = exp2(g_j r^2), g_j = -log2(e) / (2 h_j^2), and u_i += K_ij w_j for
+// the rows i whose bit is set in the entry's mask.  Every slab owns its
+// output rows, so the sums are deterministic (no atomics).
+#include "askit_impl.h"
+
+#include <algorithm>
+
+namespace askit {
+
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+constexpr int EV_T = 256;
+constexpr int EV_KC = 64;              // dimensions per LDS chunk
+constexpr int EV_LD = EV_KC + 4;       // padded LDS row (floats)
+constexpr int EV_RB = 4;               // right-hand sides per pass
+
+struct EvalParams {
+    const float *Y;            // targets (rows of stride dp)
+    const Slab *slabs;
+    const int32_t *ptr, *node;
+    const uint64_t *mask;
+    const int32_t *outmap;
+    float *U;
+    int64_t ldu;
+    int64_t nslab;
+    const Node *nodes;
+    const float *Xt, *gt, *Wt;   // near sources (tree order)
+    const float *Xs, *gs, *Wsk;  // far sources (skeletons)
+    const int32_t *skk;
+    int smax, dp, R, r0, rb;
+};
+
+template <int RB>
+__global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
+{
+    __shared__ __attribute__((aligned(16))) float sA[64 * EV_LD];
+    __shared__ __attribute__((aligned(16))) float sB[64 * EV_LD];
+    __shared__ float sC[1024 + 64];      // centre (dp <= 1024)
+    __shared__ float sAn[64], sBn[64], sBg[64], sBw[64 * RB];
+    __shared__ float sRed[2][64 * RB];
+
+    const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+    const int half = lane >> 5, l32 = lane & 31;
+    const int rq = 32 * (wv >> 1), cq = 32 * (wv & 1);
+    const int64_t slab = blockIdx.x;
+    const Slab sb = p.slabs[slab];
+    const int dp = p.dp;
+    const float *Yb = p.Y + (int64_t)sb.row0 * dp;
+    const int nchunk = (dp + EV_KC - 1) / EV_KC;
+
+    for (int k = tid; k < dp; k += EV_T) sC[k] = Yb[k];
+    __syncthreads();
+
+    // load one 64 x EV_KC chunk of rows (centred) into dst; row r valid when r < nrow
+    // src row r at base + r * dp; returns the per-row partial squared norms in nrm
+    auto load_chunk = [&](float *dst, const float *base, int nrow, int k0, float *nrm, bool accum) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int idx = tid + EV_T * u;
+            int row = idx >> 4, qd = (idx & 15) * 4;
+            float4 v = {0.f, 0.f, 0.f, 0.f};
+            int kk = k0 + qd;
+            if (row < nrow && kk < dp) {
+                float4 x = *reinterpret_cast<const float4 *>(base + (int64_t)row * dp + kk);
+                v.x = x.x - sC[kk];
+                v.y = x.y - sC[kk + 1];
+                v.z = x.z - sC[kk + 2];
+                v.w = x.w - sC[kk + 3];
+            }
+            *reinterpret_cast<float4 *>(dst + row * EV_LD + qd) = v;
+            if (nrm) {
+                float s = v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o);
+                if ((idx & 15) == 0) nrm[row] = accum ? nrm[row] + s : s;
+            }
+        }
+    };
+
+    // target norms (all chunks); the target chunk stays resident when dp <= EV_KC
+    for (int ch = 0; ch < nchunk; ++ch) {
+        load_chunk(sA, Yb, sb.nrows, ch * EV_KC, sAn, ch > 0);
+        __syncthreads();
+    }
+
+    float accu[16][RB];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) accu[r][j] = 0.0f;
+
+    const int e_near0 = p.ptr[slab], e_near1 = p.ptr[slab + 1];
+    const int e_far0 = p.ptr[p.nslab + 1 + slab], e_far1 = p.ptr[p.nslab + 2 + slab];
+    const int ne = (e_near1 - e_near0) + (e_far1 - e_far0);
+    for (int e = 0; e < ne; ++e) {
+        const bool near = e < e_near1 - e_near0;
+        const int eid = near ? e_near0 + e : e_far0 + (e - (e_near1 - e_near0));
+        const int a = p.node[eid];
+        const uint64_t msk = p.mask[eid];
+        const float *src, *g, *w;
+        int ns;
+        if (near) {
+            const Node nd = p.nodes[a];
+            ns = nd.hi - nd.lo;
+            src = p.Xt + (int64_t)nd.lo * dp;
+            g = p.gt + nd.lo;
+            w = p.Wt + (int64_t)nd.lo * p.R;
+        } else {
+            ns = p.skk[a];
+            src = p.Xs + (int64_t)a * p.smax * dp;
+            g = p.gs + (int64_t)a * p.smax;
+            w = p.Wsk + (int64_t)a * p.smax * p.R;
+        }
+        float mb[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            int row = rq + 8 * (r / 4) + 4 * half + (r % 4);
+            mb[r] = (float)((msk >> row) & 1ull);
+        }
+        for (int s0 = 0; s0 < ns; s0 += 64) {
+            const int nt = min(64, ns - s0);
+            f32x16 acc = {};
+            for (int ch = 0; ch < nchunk; ++ch) {
+                __syncthreads();
+                if (nchunk > 1) load_chunk(sA, Yb, sb.nrows, ch * EV_KC, nullptr, false);
+                load_chunk(sB, src + (int64_t)s0 * dp, nt, ch * EV_KC, sBn, ch > 0);
+                if (ch == 0 && tid < 64) {
+                    bool ok = tid < nt;
+                    sBg[tid] = ok ? g[s0 + tid] : 0.0f;
+#pragma unroll
+                    for (int j = 0; j < RB; ++j)
+                        sBw[tid * RB + j] = (ok && j < p.rb) ? w[(int64_t)(s0 + tid) * p.R + p.r0 + j] : 0.0f;
+                }
+                __syncthreads();
+                const float *pa = sA + (rq + l32) * EV_LD + 4 * half;
+                const float *pb = sB + (cq + l32) * EV_LD + 4 * half;
+                const int kc = min(EV_KC, dp - ch * EV_KC);
+                for (int g8 = 0; g8 < kc; g8 += 8) {
+                    float4 a4 = *reinterpret_cast<const float4 *>(pa + g8);
+                    float4 b4 = *reinterpret_cast<const float4 *>(pb + g8);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, b4.x, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, b4.y, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, b4.z, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, b4.w, acc, 0, 0, 0);
+                }
+            }
+            const int col = cq + l32;
+            const float bn = sBn[col], bg = sBg[col];
+            float bw[RB];
+#pragma unroll
+            for (int j = 0; j < RB; ++j) bw[j] = sBw[col * RB + j];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = rq + 8 * (r / 4) + 4 * half + (r % 4);
+                float r2 = fmaxf(sAn[row] + bn - 2.0f * acc[r], 0.0f);
+                float kv = exp2f(bg * r2) * mb[r];
+#pragma unroll
+                for (int j = 0; j < RB; ++j) accu[r][j] = fmaf(kv, bw[j], accu[r][j]);
+            }
+        }
+    }
+    // reduce over the 32 columns held by the lanes of each half, then over the two
+    // waves that share the same rows
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            float v = accu[r][j];
+#pragma unroll
+            for (int o = 1; o < 32; o <<= 1) v += __shfl_xor(v, o);
+            accu[r][j] = v;
+        }
+    __syncthreads();
+    if (l32 == 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = rq + 8 * (r / 4) + 4 * half + (r % 4);
+#pragma unroll
+            for (int j = 0; j < RB; ++j) sRed[wv & 1][row * RB + j] = accu[r][j];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < sb.nrows * p.rb; e += EV_T) {
+        int row = e / p.rb, j = e % p.rb;
+        float v = sRed[0][row * RB + j] + sRed[1][row * RB + j];
+        int64_t orow = p.outmap ? p.outmap[sb.row0 + row] : (int64_t)sb.row0 + row;
+        p.U[orow * p.ldu + p.r0 + j] = v;
+    }
+}
+
+void evaluate(askit_handle *h, const EvalArgs &a, hipStream_t s)
+{
+    if (h->dp > 1024) fail(ASKIT_ERR_UNSUPPORTED, "dimension above 1024 is not supported");
+    EvalParams p;
+    p.Y = a.Y;
+    p.slabs = a.slabs;
+    p.ptr = a.ptr;
+    p.node = a.node;
+    p.mask = a.mask;
+    p.outmap = a.outmap;
+    p.U = a.U;
+    p.ldu = a.ldu;
+    p.nslab = a.nslab;
+    p.nodes = h->d_nodes;
+    p.Xt = h->Xt;
+    p.gt = h->gt;
+    p.Wt = h->Wt;
+    p.Xs = h->Xs;
+    p.gs = h->gs;
+    p.Wsk = h->Wsk;
+    p.skk = h->skk;
+    p.smax = h->smax;
+    p.dp = h->dp;
+    p.R = h->nrhs;
+    if (a.nslab == 0) return;
+    for (int r0 = 0; r0 < h->nrhs; r0 += EV_RB) {
+        p.r0 = r0;
+        p.rb = std::min(EV_RB, h->nrhs - r0);
+        if (p.rb == 1)
+            hipLaunchKernelGGL(k_eval<1>, dim3((unsigned)a.nslab), dim3(EV_T), 0, s, p);
+        else
+            hipLaunchKernelGGL(k_eval<EV_RB>, dim3((unsigned)a.nslab), dim3(EV_T), 0, s, p);
+        HIPC(hipGetLastError());
+    }
+}
+
+}  // namespace askit

@@ -1,0 +1,394 @@
+// Median-split binary tree on the GPU (Sec. 3.2, Fig. "The tree").
+//
+// A node with n > m points is split by: centre c (mean), x_l = the point
+// farthest from c, x_r = the point farthest from x_l, projection p_i =
+// (x_i - x_l).(x_r - x_l), and a median split: the ceil(n/2) smallest
+// (p_i, i) go left, the rest right, each child keeping its points in the
+// parent's order (which is increasing point id, by induction from the root).
+// All values that decide the split are FP64 and computed in a fixed order,
+// so the permutation is reproducible bit for bit:
+//   - c: blocks of 64 consecutive points summed by pairwise halving within
+//     a wave (lane t adds lane t+32, then t+16, ..., t+1), block sums added
+//     in block order, divided by n;
+//   - distances and projections: sums over increasing k without FMA;
+//   - argmax ties go to the smaller point id;
+//   - the median is found by an 8-pass radix select on an order-preserving
+//     64-bit image of p, ties resolved by position (= point id order).
+// The tree shape depends only on N and m, so every level's node ranges are
+// known on the host before the level runs.
+#include "askit_impl.h"
+
+#include <algorithm>
+
+namespace askit {
+
+struct Split {
+    int32_t lo, n;
+};
+
+struct BestD {
+    double d;
+    int32_t id;
+    int32_t pad;
+};
+
+__device__ __forceinline__ bool better(double d1, int i1, double d2, int i2)
+{
+    return d1 > d2 || (d1 == d2 && i1 < i2);
+}
+
+__global__ void k_block_sums(const float *__restrict__ X, int dp, int d,
+                             const int32_t *__restrict__ perm, const Split *__restrict__ sp,
+                             int maxblk, double *__restrict__ bsum)
+{
+    int b = blockIdx.x, q = blockIdx.y, lane = threadIdx.x;
+    Split s = sp[q];
+    if (b * 64 >= s.n) return;
+    int i = b * 64 + lane;
+    bool ok = i < s.n;
+    const float *x = ok ? X + (int64_t)perm[s.lo + i] * dp : X;
+    double *out = bsum + ((int64_t)q * maxblk + b) * d;
+    for (int k = 0; k < d; ++k) {
+        double v = ok ? (double)x[k] : 0.0;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            double w = __shfl_down(v, o);
+            v = v + w;
+        }
+        if (lane == 0) out[k] = v;
+    }
+}
+
+__global__ void k_centroid(const double *__restrict__ bsum, const Split *__restrict__ sp, int maxblk,
+                           int d, double *__restrict__ cen)
+{
+    int q = blockIdx.x;
+    Split s = sp[q];
+    int nb = (s.n + 63) / 64;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) {
+        double acc = 0.0;
+        for (int b = 0; b < nb; ++b) acc += bsum[((int64_t)q * maxblk + b) * d + k];
+        cen[(int64_t)q * d + k] = acc / (double)s.n;
+    }
+}
+
+// mode 0: D(x, centre); mode 1: D(x, x_ref[q]) (reference given as point id)
+__global__ __launch_bounds__(256) void k_far_partial(const float *__restrict__ X, int dp, int d,
+                                                     const int32_t *__restrict__ perm,
+                                                     const Split *__restrict__ sp,
+                                                     const double *__restrict__ cen,
+                                                     const int32_t *__restrict__ ref, int mode,
+                                                     int nchunk, BestD *__restrict__ part)
+{
+    __shared__ double sd[256];
+    __shared__ int si[256];
+    int c = blockIdx.x, q = blockIdx.y, tid = threadIdx.x;
+    Split s = sp[q];
+    int i = c * 256 + tid;
+    double D = -1.0;
+    int id = 0x7fffffff;
+    if (i < s.n) {
+        id = perm[s.lo + i];
+        const float *x = X + (int64_t)id * dp;
+        D = mode == 0 ? canon_sqdist_c(x, cen + (int64_t)q * d, d)
+                      : canon_sqdist(x, X + (int64_t)ref[q] * dp, d);
+    }
+    sd[tid] = D;
+    si[tid] = id;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o && better(sd[tid + o], si[tid + o], sd[tid], si[tid])) {
+            sd[tid] = sd[tid + o];
+            si[tid] = si[tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) part[(int64_t)q * nchunk + c] = BestD{sd[0], si[0], 0};
+}
+
+__global__ void k_far_final(const BestD *__restrict__ part, const Split *__restrict__ sp, int nchunk,
+                            int32_t *__restrict__ out)
+{
+    int q = blockIdx.x, lane = threadIdx.x;
+    int nc = (sp[q].n + 255) / 256;
+    double bd = -1.0;
+    int bi = 0x7fffffff;
+    for (int c = lane; c < nc; c += 64) {
+        BestD b = part[(int64_t)q * nchunk + c];
+        if (better(b.d, b.id, bd, bi)) { bd = b.d; bi = b.id; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        double od = __shfl_xor(bd, o);
+        int oi = __shfl_xor(bi, o);
+        if (better(od, oi, bd, bi)) { bd = od; bi = oi; }
+    }
+    if (lane == 0) out[q] = bi;
+}
+
+__global__ void k_project(const float *__restrict__ X, int dp, int d, const int32_t *__restrict__ perm,
+                          const Split *__restrict__ sp, const int32_t *__restrict__ L,
+                          const int32_t *__restrict__ Rr, uint64_t *__restrict__ key)
+{
+#pragma clang fp contract(off)
+    int c = blockIdx.x, q = blockIdx.y;
+    Split s = sp[q];
+    int i = c * 256 + threadIdx.x;
+    if (i >= s.n) return;
+    const float *x = X + (int64_t)perm[s.lo + i] * dp;
+    const float *xl = X + (int64_t)L[q] * dp;
+    const float *xr = X + (int64_t)Rr[q] * dp;
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double a = (double)x[k] - (double)xl[k];
+        double b = (double)xr[k] - (double)xl[k];
+        acc += a * b;
+    }
+    key[s.lo + i] = dkey(acc);
+}
+
+// Radix select state per split: prefix of the pivot key, remaining rank.
+struct Sel {
+    uint64_t prefix;
+    int64_t krem;
+};
+
+__global__ __launch_bounds__(256) void k_radix_hist(const uint64_t *__restrict__ key,
+                                                    const Split *__restrict__ sp,
+                                                    const Sel *__restrict__ sel, int shift,
+                                                    uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t lh[256];
+    int c = blockIdx.x, q = blockIdx.y, tid = threadIdx.x;
+    Split s = sp[q];
+    lh[tid] = 0;
+    __syncthreads();
+    uint64_t hm = shift >= 56 ? 0ull : (~0ull << (shift + 8));
+    uint64_t pre = sel[q].prefix;
+    for (int i = c * 1024 + tid; i < min(s.n, (c + 1) * 1024); i += 256) {
+        uint64_t k = key[s.lo + i];
+        if (((k ^ pre) & hm) == 0) atomicAdd(&lh[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (lh[tid]) atomicAdd(&hist[q * 256 + tid], lh[tid]);
+}
+
+__global__ void k_radix_pick(uint32_t *__restrict__ hist, Sel *__restrict__ sel, int nsp, int shift)
+{
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nsp) return;
+    Sel st = sel[q];
+    int64_t cum = 0;
+    for (int dg = 0; dg < 256; ++dg) {
+        int64_t c = hist[q * 256 + dg];
+        if (cum + c > st.krem) {
+            st.prefix |= (uint64_t)dg << shift;
+            st.krem -= cum;
+            break;
+        }
+        cum += c;
+    }
+    for (int dg = 0; dg < 256; ++dg) hist[q * 256 + dg] = 0;
+    sel[q] = st;
+}
+
+struct PartCnt {
+    int32_t less, eq;
+};
+
+// Block-wide exclusive prefix of two flags; returns totals in *tl, *te.
+__device__ __forceinline__ void block_scan2(int fl, int fe, int &pl, int &pe, int &tl, int &te)
+{
+    __shared__ int wl[4], we[4];
+    int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+    uint64_t bl = __ballot(fl), be = __ballot(fe);
+    uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int il = __popcll(bl & lt), ie = __popcll(be & lt);
+    if (lane == 0) {
+        wl[w] = __popcll(bl);
+        we[w] = __popcll(be);
+    }
+    __syncthreads();
+    int ol = 0, oe = 0;
+    tl = 0;
+    te = 0;
+    for (int v = 0; v < 4; ++v) {
+        if (v < w) { ol += wl[v]; oe += we[v]; }
+        tl += wl[v];
+        te += we[v];
+    }
+    pl = ol + il;
+    pe = oe + ie;
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_part_count(const uint64_t *__restrict__ key,
+                                                    const Split *__restrict__ sp,
+                                                    const Sel *__restrict__ sel, int nchunk,
+                                                    PartCnt *__restrict__ cnt)
+{
+    int c = blockIdx.x, q = blockIdx.y, tid = threadIdx.x;
+    Split s = sp[q];
+    int i = c * 256 + tid;
+    uint64_t pv = sel[q].prefix;
+    int fl = 0, fe = 0;
+    if (i < s.n) {
+        uint64_t k = key[s.lo + i];
+        fl = k < pv;
+        fe = k == pv;
+    }
+    int pl, pe, tl, te;
+    block_scan2(fl, fe, pl, pe, tl, te);
+    if (tid == 0) cnt[(int64_t)q * nchunk + c] = PartCnt{tl, te};
+}
+
+__global__ void k_part_scan(PartCnt *__restrict__ cnt, const Split *__restrict__ sp, int nsp,
+                            int nchunk)
+{
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nsp) return;
+    int nc = (sp[q].n + 255) / 256;
+    int al = 0, ae = 0;
+    for (int c = 0; c < nc; ++c) {
+        PartCnt v = cnt[(int64_t)q * nchunk + c];
+        cnt[(int64_t)q * nchunk + c] = PartCnt{al, ae};
+        al += v.less;
+        ae += v.eq;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_part_scatter(const uint64_t *__restrict__ key,
+                                                      const int32_t *__restrict__ perm,
+                                                      const Split *__restrict__ sp,
+                                                      const Sel *__restrict__ sel, int nchunk,
+                                                      const PartCnt *__restrict__ cnt,
+                                                      int32_t *__restrict__ out)
+{
+    int c = blockIdx.x, q = blockIdx.y, tid = threadIdx.x;
+    Split s = sp[q];
+    int i = c * 256 + tid;
+    uint64_t pv = sel[q].prefix;
+    int64_t take = sel[q].krem + 1;
+    int fl = 0, fe = 0;
+    uint64_t k = 0;
+    if (i < s.n) {
+        k = key[s.lo + i];
+        fl = k < pv;
+        fe = k == pv;
+    }
+    int pl, pe, tl, te;
+    block_scan2(fl, fe, pl, pe, tl, te);
+    if (i >= s.n) return;
+    PartCnt base = cnt[(int64_t)q * nchunk + c];
+    int64_t lb = base.less + pl, eb = base.eq + pe;
+    int64_t gb = i - lb - eb;
+    int64_t nl = (s.n + 1) / 2;
+    int64_t dst;
+    if (fl) dst = lb + min(eb, take);
+    else if (fe) dst = eb < take ? lb + eb : nl + gb + (eb - take);
+    else dst = nl + gb + max((int64_t)0, eb - take);
+    if (dst >= 0 && dst < s.n) out[s.lo + dst] = perm[s.lo + i];
+}
+
+__global__ void k_iota(int32_t *p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
+}
+
+__global__ void k_invert(const int32_t *__restrict__ p, int64_t n, int32_t *__restrict__ ip)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) ip[p[i]] = (int32_t)i;
+}
+
+void build_tree(askit_handle *h, hipStream_t s)
+{
+    const int64_t N = h->N;
+    const int d = h->d, dp = h->dp;
+    unsigned nb = (unsigned)((N + 255) / 256);
+    hipLaunchKernelGGL(k_iota, dim3(nb), dim3(256), 0, s, h->perm, N);
+    HIPC(hipGetLastError());
+    if (h->depth == 0) {
+        hipLaunchKernelGGL(k_invert, dim3(nb), dim3(256), 0, s, h->perm, N, h->iperm);
+        return;
+    }
+    // scratch sized for the root level (largest node, one split)
+    int64_t maxsp = 1;
+    for (auto &lv : h->level_nodes) maxsp = std::max<int64_t>(maxsp, (int64_t)lv.size());
+    int64_t blk_total = (N + 63) / 64 + 2 * maxsp;       // 64-point blocks over one level
+    std::vector<void *> tmp;
+    auto talloc = [&](size_t b) {
+        void *p;
+        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        tmp.push_back(p);
+        return p;
+    };
+    Split *d_sp = (Split *)talloc(sizeof(Split) * maxsp);
+    double *bsum = (double *)talloc(sizeof(double) * blk_total * d + 64);
+    double *cen = (double *)talloc(sizeof(double) * maxsp * d);
+    int64_t chunk_total = (N + 255) / 256 + 2 * maxsp;
+    BestD *part = (BestD *)talloc(sizeof(BestD) * chunk_total);
+    int32_t *L = (int32_t *)talloc(sizeof(int32_t) * maxsp);
+    int32_t *Rr = (int32_t *)talloc(sizeof(int32_t) * maxsp);
+    uint64_t *key = (uint64_t *)talloc(sizeof(uint64_t) * N);
+    Sel *sel = (Sel *)talloc(sizeof(Sel) * maxsp);
+    uint32_t *hist = (uint32_t *)talloc(sizeof(uint32_t) * 256 * maxsp);
+    PartCnt *pc = (PartCnt *)talloc(sizeof(PartCnt) * chunk_total);
+    int32_t *pout = (int32_t *)talloc(sizeof(int32_t) * N);
+    HIPC(hipMemsetAsync(hist, 0, sizeof(uint32_t) * 256 * maxsp, s));
+
+    std::vector<Split> hsp;
+    std::vector<Sel> hsel;
+    for (int lev = 0; lev < (int)h->level_nodes.size(); ++lev) {
+        hsp.clear();
+        hsel.clear();
+        int maxn = 0;
+        for (int a : h->level_nodes[lev]) {
+            const Node &nd = h->nodes[a];
+            if (nd.left < 0) continue;
+            int n = nd.hi - nd.lo;
+            hsp.push_back(Split{nd.lo, n});
+            hsel.push_back(Sel{0ull, (int64_t)((n + 1) / 2 - 1)});
+            maxn = std::max(maxn, n);
+        }
+        int nsp = (int)hsp.size();
+        if (nsp == 0) continue;
+        HIPC(hipMemcpyAsync(d_sp, hsp.data(), sizeof(Split) * nsp, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(sel, hsel.data(), sizeof(Sel) * nsp, hipMemcpyHostToDevice, s));
+        int maxblk = (maxn + 63) / 64;
+        int nchunk = (maxn + 255) / 256;
+        hipLaunchKernelGGL(k_block_sums, dim3(maxblk, nsp), dim3(64), 0, s, h->Xo, dp, d, h->perm,
+                           d_sp, maxblk, bsum);
+        hipLaunchKernelGGL(k_centroid, dim3(nsp), dim3(std::min(256, round_up(d, 64))), 0, s, bsum,
+                           d_sp, maxblk, d, cen);
+        hipLaunchKernelGGL(k_far_partial, dim3(nchunk, nsp), dim3(256), 0, s, h->Xo, dp, d, h->perm,
+                           d_sp, cen, (const int32_t *)nullptr, 0, nchunk, part);
+        hipLaunchKernelGGL(k_far_final, dim3(nsp), dim3(64), 0, s, part, d_sp, nchunk, L);
+        hipLaunchKernelGGL(k_far_partial, dim3(nchunk, nsp), dim3(256), 0, s, h->Xo, dp, d, h->perm,
+                           d_sp, cen, L, 1, nchunk, part);
+        hipLaunchKernelGGL(k_far_final, dim3(nsp), dim3(64), 0, s, part, d_sp, nchunk, Rr);
+        hipLaunchKernelGGL(k_project, dim3(nchunk, nsp), dim3(256), 0, s, h->Xo, dp, d, h->perm, d_sp,
+                           L, Rr, key);
+        int hchunk = (maxn + 1023) / 1024;
+        for (int pass = 0; pass < 8; ++pass) {
+            int shift = 56 - 8 * pass;
+            hipLaunchKernelGGL(k_radix_hist, dim3(hchunk, nsp), dim3(256), 0, s, key, d_sp, sel, shift,
+                               hist);
+            hipLaunchKernelGGL(k_radix_pick, dim3((nsp + 63) / 64), dim3(64), 0, s, hist, sel, nsp,
+                               shift);
+        }
+        hipLaunchKernelGGL(k_part_count, dim3(nchunk, nsp), dim3(256), 0, s, key, d_sp, sel, nchunk,
+                           pc);
+        hipLaunchKernelGGL(k_part_scan, dim3((nsp + 63) / 64), dim3(64), 0, s, pc, d_sp, nsp, nchunk);
+        HIPC(hipMemcpyAsync(pout, h->perm, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_part_scatter, dim3(nchunk, nsp), dim3(256), 0, s, key, h->perm, d_sp, sel,
+                           nchunk, pc, pout);
+        HIPC(hipGetLastError());
+        HIPC(hipMemcpyAsync(h->perm, pout, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
+    }
+    hipLaunchKernelGGL(k_invert, dim3(nb), dim3(256), 0, s, h->perm, N, h->iperm);
+    HIPC(hipGetLastError());
+    for (void *p : tmp) HIPC(hipFreeAsync(p, s));
+}
+
+}  // namespace askit

@@ -1,0 +1,87 @@
+"""The C ABI: the library loads, exports every function of include/askit.h,
+and validates arguments before it touches a device (runs without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1410_0260_amd import askit as A
+    if not os.path.exists(A.LIB_PATH):
+        pytest.skip("libaskit.so is not built")
+    return A
+
+
+def test_header_symbols_exported():
+    A = _lib()
+    hdr = open(os.path.join(ROOT, "include", "askit.h")).read()
+    decl = set(re.findall(r"^\s*(?:askit_status|void|const char \*)\s*(askit_\w+)\s*\(", hdr, re.M))
+    assert decl == set(A.EXPORTED)
+    L = C.CDLL(A.LIB_PATH)
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def test_params_struct_layout():
+    A = _lib()
+    p = A.default_params()
+    assert p.struct_size == C.sizeof(A.Params) == 56
+    assert p.abi_version == A.ABI_VERSION
+    assert p.leaf_size == 128 and p.kappa == 16 and p.max_skeleton == 64
+
+
+def _setup(A, N=100, d=3, ldx=3, **kw):
+    p = A.default_params(**kw)
+    h = C.c_void_p()
+    dummy = C.c_void_p(0x1000)   # never dereferenced: validation fails or no device
+    rc = A.lib().askit_setup(dummy, N, d, ldx, C.byref(p), None, C.byref(h))
+    return rc, A.lib().askit_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(N=1), "N must be"),
+    (dict(d=0), "d >= 1"),
+    (dict(ldx=2), "ldx >= d"),
+    (dict(kappa=100), "kappa < N"),
+    (dict(kappa=0), "kappa < N"),
+    (dict(leaf_size=0), "m >= 1"),
+    (dict(sample_rows=10), "sample_rows >= max_skeleton"),
+    (dict(bandwidth=0.0), "positive finite bandwidth"),
+    (dict(bw_neighbor=17), "bw_neighbor <= kappa"),
+    (dict(id_tol=-1.0), "id_tol"),
+    (dict(precision=7), "unknown precision"),
+])
+def test_invalid_arguments(kw, msg):
+    A = _lib()
+    setup_kw = {k: kw.pop(k) for k in ("N", "d", "ldx") if k in kw}
+    rc, err = _setup(A, **setup_kw, **kw)
+    assert rc == A.ERR_INVALID_ARG
+    assert msg in err
+
+
+def test_unsupported_kappa():
+    A = _lib()
+    rc, err = _setup(A, N=1000, kappa=65, max_skeleton=8)
+    assert rc == A.ERR_UNSUPPORTED
+
+
+def test_no_device_reports_device_error():
+    A = _lib()
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, err = _setup(A)
+    assert rc == A.ERR_DEVICE
+
+
+def test_null_handle_calls():
+    A = _lib()
+    L = A.lib()
+    assert L.askit_update_weights(None, None, 1, 1, None) == A.ERR_INVALID_ARG
+    assert L.askit_evaluate(None, None, 1, None) == A.ERR_INVALID_ARG
+    assert L.askit_query(None, None, 1, 1, None, 1, None) == A.ERR_INVALID_ARG
+    L.askit_destroy(None)
