@@ -18,10 +18,11 @@
  *     leading dimension in elements (ldx >= d, ldw >= nrhs, ...).  The
  *     caller owns them; the library never frees or retains them.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
- *     enqueued on it; setup and update_weights additionally synchronise the
- *     stream before returning (they read back sizes).  evaluate and query
- *     return once their work is enqueued: outputs are valid after the caller
- *     synchronises the stream.  Inputs must stay valid until then.
+ *     enqueued on it.  setup and query synchronise the stream before
+ *     returning (they read back list sizes).  update_weights and evaluate
+ *     only enqueue work and never synchronise (so they can be captured in a
+ *     HIP graph): outputs are valid after the caller synchronises the
+ *     stream, and inputs must stay valid until then.
  *   - Results are returned in the caller's original point order.
  *   - Errors are reported by status code; askit_last_error() returns a
  *     thread-local message for the last failing call on the calling thread.
@@ -96,8 +97,8 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx,
 /*
  * Upward pass (Sec. 2.1, Alg. 3): computes the skeleton weights of every
  * node from W (device, N x nrhs FP32, original point order, row stride
- * ldw >= nrhs), 1 <= nrhs <= 64.  W is read only during the call.
- * Synchronises `stream`.
+ * ldw >= nrhs), 1 <= nrhs <= 64.  Enqueued on `stream`; W must stay valid
+ * until the stream reaches the end of the call's work.
  */
 askit_status askit_update_weights(askit_handle *h, const float *W, int64_t ldw, int32_t nrhs,
                                   void *stream);

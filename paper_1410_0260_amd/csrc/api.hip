@@ -86,6 +86,84 @@ __global__ void k_map_pos(const int32_t *__restrict__ ids, int64_t n, const int3
     if (i < n) out[i] = iperm[ids[i]];
 }
 
+void permute_weights(askit_handle *h, const float *W, int64_t ldw, WeightSet &ws, hipStream_t s)
+{
+    int64_t tot = h->N * ws.R;
+    hipLaunchKernelGGL(k_permute_w, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, W, ldw,
+                       h->perm, h->N, ws.R, ws.Wt);
+    HIPC(hipGetLastError());
+}
+
+void query_points(askit_handle *h, const WeightSet &ws, const float *Y, int64_t M, int64_t ldy, float *U,
+                  int64_t ldu, hipStream_t s)
+{
+    const int dp = h->dp, kappa = h->kappa;
+    std::vector<void *> tmp;
+    struct Guard {
+        std::vector<void *> &t;
+        hipStream_t s;
+        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+    } guard{tmp, s};
+    auto ta = [&](size_t b) {
+        void *p;
+        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        tmp.push_back(p);
+        return p;
+    };
+    float *Yp = (float *)ta(sizeof(float) * M * dp);
+    uint16_t *Yh = (uint16_t *)ta(sizeof(uint16_t) * M * dp);
+    uint16_t *Yl = (uint16_t *)ta(sizeof(uint16_t) * M * dp);
+    float *Yn = (float *)ta(sizeof(float) * M);
+    int32_t *flag = (int32_t *)ta(sizeof(int32_t) * (M + 1));
+    int32_t *cand = (int32_t *)ta(sizeof(int32_t) * M * KNN_CAND);
+    float *thr = (float *)ta(sizeof(float) * M);
+    int32_t *qidx = (int32_t *)ta(sizeof(int32_t) * M * kappa);
+    double *qd = (double *)ta(sizeof(double) * M * kappa);
+    int32_t *nb = (int32_t *)ta(sizeof(int32_t) * M * kappa);
+    int32_t *nbs = (int32_t *)ta(sizeof(int32_t) * M * kappa);
+    int32_t *order = (int32_t *)ta(sizeof(int32_t) * M);
+    float *Ys = (float *)ta(sizeof(float) * M * dp);
+    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    pack_points(Y, M, h->d, ldy, dp, Yp, flag, s);
+    int32_t hflag = 0;
+    HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hflag) fail(ASKIT_ERR_INVALID_ARG, "Y holds a non-finite value");
+    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    split_bf16(Yp, M, dp, Yh, Yl, Yn, s);
+    knn_candidates(Yh, Yl, Yn, M, h->Xh, h->Xl, h->Xn, h->N, dp, false, false, cand, thr, flag + 1,
+                   flag, s);
+    knn_refine(Yp, M, h->Xt, h->N, h->d, dp, kappa, cand, thr, Yn, h->maxnorm, h->perm, nullptr, qidx,
+               qd, flag + 1, flag, s);
+    int32_t nbad = 0;
+    HIPC(hipMemcpyAsync(&nbad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    knn_exact_rows(Yp, h->Xt, h->N, h->d, dp, kappa, false, flag + 1, nbad, h->perm, nullptr, qidx,
+                   qd, s);
+    hipLaunchKernelGGL(k_map_pos, dim3((unsigned)((M * kappa + 255) / 256)), dim3(256), 0, s, qidx,
+                       M * kappa, h->iperm, nb);
+    HIPC(hipGetLastError());
+    sort_queries(h, nb, M, order, nbs, tmp, s);
+    gather_rows(Yp, order, M, dp, Ys, s);
+    int32_t *ptr, *node;
+    uint64_t *mask;
+    Slab *qslabs;
+    int64_t nen, nef;
+    build_query_interactions(h, nbs, M, qslabs, ptr, node, mask, nen, nef, tmp, s);
+    EvalArgs a;
+    a.Y = Ys;
+    a.nslab = (M + SLAB - 1) / SLAB;
+    a.slabs = qslabs;
+    a.ptr = ptr;
+    a.node = node;
+    a.mask = mask;
+    a.outmap = order;
+    a.U = U;
+    a.ldu = ldu;
+    evaluate(h, ws, a, s);
+    HIPC(hipStreamSynchronize(s));
+}
+
 }  // namespace askit
 
 #define API_BEGIN                                                                                 \
@@ -112,6 +190,8 @@ __global__ void k_map_pos(const int32_t *__restrict__ ids, int64_t n, const int3
 
 askit_handle::~askit_handle()
 {
+    if (ev_up0) (void)hipEventDestroy(ev_up0);
+    if (ev_up1) (void)hipEventDestroy(ev_up1);
     for (void *p : allocs) (void)hipFree(p);
 }
 
@@ -291,57 +371,14 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
     int32_t *flag = (int32_t *)h->alloc(sizeof(int32_t) * 4, true);
 
     HIPC(hipEventRecord(ev[0], s));
-    // ---- points and exact neighbours
+    // ---- points and tree (the tree needs only the coordinates)
     pack_points(X, N, d, ldx, dp, h->Xo, flag, s);
     int32_t hflag = 0;
     HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     if (hflag) fail(ASKIT_ERR_INVALID_ARG, "X holds a non-finite value");
-    split_bf16(h->Xo, N, dp, h->Xh, h->Xl, h->Xn, s);
-    float mx = max_norm(h->Xn, N, s);
-    {
-        int32_t *cand, *bad;
-        float *thr;
-        HIPC(hipMallocAsync((void **)&cand, sizeof(int32_t) * N * KNN_CAND, s));
-        HIPC(hipMallocAsync((void **)&thr, sizeof(float) * N, s));
-        HIPC(hipMallocAsync((void **)&bad, sizeof(int32_t) * (N + 1), s));
-        HIPC(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
-        hipEvent_t k0, k1;
-        HIPC(hipEventCreate(&k0));
-        HIPC(hipEventCreate(&k1));
-        HIPC(hipEventRecord(k0, s));
-        knn_candidates(h->Xh, h->Xl, h->Xn, N, h->Xh, h->Xl, h->Xn, N, dp, true, cand, thr, s);
-        HIPC(hipEventRecord(k1, s));
-        knn_refine(h->Xo, N, h->Xo, N, d, dp, kappa, cand, thr, h->Xn, mx, true, h->knn_idx,
-                   h->knn_d, bad + 1, bad, s);
-        int32_t nbad = 0;
-        HIPC(hipMemcpyAsync(&nbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIPC(hipStreamSynchronize(s));
-        h->knn_uncertified = nbad;
-        float kms = 0.f;
-        HIPC(hipEventElapsedTime(&kms, k0, k1));
-        h->t_knn_sweep = kms;
-        (void)hipEventDestroy(k0);
-        (void)hipEventDestroy(k1);
-        knn_exact_rows(h->Xo, h->Xo, N, d, dp, kappa, true, bad + 1, nbad, h->knn_idx, h->knn_d, s);
-        HIPC(hipFreeAsync(cand, s));
-        HIPC(hipFreeAsync(thr, s));
-        HIPC(hipFreeAsync(bad, s));
-    }
-    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_bandwidth, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, h->knn_d, N,
-                       kappa, p->bw_neighbor, p->bandwidth, h->hsrc, flag);
-    HIPC(hipGetLastError());
-    HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPC(hipEventRecord(ev[1], s));
-    HIPC(hipStreamSynchronize(s));
-    if (hflag) fail(ASKIT_ERR_INVALID_ARG, "zero bandwidth (duplicate points with variable bandwidth)");
-
-    // ---- tree
     build_tree(h.get(), s);
     gather_rows(h->Xo, h->perm, N, dp, h->Xt, s);
-    hipLaunchKernelGGL(k_gfactor, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, h->hsrc, h->perm,
-                       N, h->gt);
     {
         int32_t *dl;
         HIPC(hipMallocAsync((void **)&dl, sizeof(int32_t) * h->leaves.size(), s));
@@ -353,6 +390,52 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
         HIPC(hipStreamSynchronize(s));
         HIPC(hipFreeAsync(dl, s));
     }
+    HIPC(hipEventRecord(ev[1], s));
+    // ---- exact neighbours, swept in tree order (each block starts at its own leaf)
+    split_bf16(h->Xt, N, dp, h->Xh, h->Xl, h->Xn, s);
+    float mx = max_norm(h->Xn, N, s);
+    h->maxnorm = mx;
+    {
+        int32_t *cand, *bad;
+        float *thr;
+        HIPC(hipMallocAsync((void **)&cand, sizeof(int32_t) * N * KNN_CAND, s));
+        HIPC(hipMallocAsync((void **)&thr, sizeof(float) * N, s));
+        HIPC(hipMallocAsync((void **)&bad, sizeof(int32_t) * (N + 1), s));
+        HIPC(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
+        hipEvent_t k0, k1;
+        HIPC(hipEventCreate(&k0));
+        HIPC(hipEventCreate(&k1));
+        HIPC(hipEventRecord(k0, s));
+        knn_candidates(h->Xh, h->Xl, h->Xn, N, h->Xh, h->Xl, h->Xn, N, dp, true, true, cand, thr,
+                       bad + 1, bad, s);
+        HIPC(hipEventRecord(k1, s));
+        knn_refine(h->Xt, N, h->Xt, N, d, dp, kappa, cand, thr, h->Xn, mx, h->perm, h->perm,
+                   h->knn_idx, h->knn_d, bad + 1, bad, s);
+        int32_t nbad = 0;
+        HIPC(hipMemcpyAsync(&nbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        h->knn_uncertified = nbad;
+        float kms = 0.f;
+        HIPC(hipEventElapsedTime(&kms, k0, k1));
+        h->t_knn_sweep = kms;
+        (void)hipEventDestroy(k0);
+        (void)hipEventDestroy(k1);
+        knn_exact_rows(h->Xt, h->Xt, N, d, dp, kappa, true, bad + 1, nbad, h->perm, h->perm,
+                       h->knn_idx, h->knn_d, s);
+        HIPC(hipFreeAsync(cand, s));
+        HIPC(hipFreeAsync(thr, s));
+        HIPC(hipFreeAsync(bad, s));
+    }
+    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_bandwidth, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, h->knn_d, N,
+                       kappa, p->bw_neighbor, p->bandwidth, h->hsrc, flag);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hflag) fail(ASKIT_ERR_INVALID_ARG, "zero bandwidth (duplicate points with variable bandwidth)");
+    hipLaunchKernelGGL(k_gfactor, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, h->hsrc, h->perm,
+                       N, h->gt);
+    HIPC(hipGetLastError());
     HIPC(hipEventRecord(ev[2], s));
     // ---- node lists and sampled rows
     build_node_lists(h.get(), s);
@@ -365,9 +448,12 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
     build_interactions(h.get(), s);
     HIPC(hipEventRecord(ev[5], s));
     HIPC(hipStreamSynchronize(s));
+    prepare_upward(h.get());
+    HIPC(hipEventCreate(&h->ev_up0));
+    HIPC(hipEventCreate(&h->ev_up1));
     float ms;
-    HIPC(hipEventElapsedTime(&ms, ev[0], ev[1])); h->t_knn = ms;
-    HIPC(hipEventElapsedTime(&ms, ev[1], ev[2])); h->t_tree = ms;
+    HIPC(hipEventElapsedTime(&ms, ev[0], ev[1])); h->t_tree = ms;
+    HIPC(hipEventElapsedTime(&ms, ev[1], ev[2])); h->t_knn = ms;
     HIPC(hipEventElapsedTime(&ms, ev[2], ev[3])); h->t_lists = ms;
     HIPC(hipEventElapsedTime(&ms, ev[3], ev[4])); h->t_skel = ms;
     HIPC(hipEventElapsedTime(&ms, ev[4], ev[5])); h->t_inter = ms;
@@ -382,7 +468,6 @@ askit_status askit_update_weights(askit_handle *h, const float *W, int64_t ldw, 
     if (nrhs < 1 || nrhs > MAX_RHS) fail(ASKIT_ERR_INVALID_ARG, "need 1 <= nrhs <= 64");
     if (ldw < nrhs) fail(ASKIT_ERR_INVALID_ARG, "need ldw >= nrhs");
     hipStream_t s = (hipStream_t)stream;
-    auto t0 = std::chrono::steady_clock::now();
     const int64_t nn = (int64_t)h->nodes.size();
     if (nrhs > h->wcap) {
         HIPC(hipStreamSynchronize(s));
@@ -391,20 +476,18 @@ askit_status askit_update_weights(askit_handle *h, const float *W, int64_t ldw, 
             (void)hipFree(p);
             h->allocs.erase(std::remove(h->allocs.begin(), h->allocs.end(), p), h->allocs.end());
         };
-        drop(h->Wt);
-        drop(h->Wsk);
-        h->Wt = (float *)h->alloc(sizeof(float) * h->N * nrhs, false);
-        h->Wsk = (float *)h->alloc(sizeof(float) * nn * h->smax * nrhs, true);
+        drop(h->ws.Wt);
+        drop(h->ws.Wsk);
+        h->ws.Wt = (float *)h->alloc(sizeof(float) * h->N * nrhs, false);
+        h->ws.Wsk = (float *)h->alloc(sizeof(float) * nn * h->smax * nrhs, true);
         h->wcap = nrhs;
     }
-    h->nrhs = nrhs;
-    int64_t tot = h->N * nrhs;
-    hipLaunchKernelGGL(k_permute_w, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, W, ldw,
-                       h->perm, h->N, nrhs, h->Wt);
-    HIPC(hipGetLastError());
-    upward(h, s);
-    HIPC(hipStreamSynchronize(s));
-    h->t_update = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    h->ws.R = nrhs;
+    HIPC(hipEventRecord(h->ev_up0, s));
+    permute_weights(h, W, ldw, h->ws, s);
+    upward(h, h->ws, s);
+    HIPC(hipEventRecord(h->ev_up1, s));
+    h->up_pending = true;
     API_END
 }
 
@@ -412,8 +495,8 @@ askit_status askit_evaluate(askit_handle *h, float *U, int64_t ldu, void *stream
 {
     API_BEGIN
     if (!h || !U) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
-    if (h->nrhs < 1) fail(ASKIT_ERR_NOT_READY, "askit_update_weights has not been called");
-    if (ldu < h->nrhs) fail(ASKIT_ERR_INVALID_ARG, "need ldu >= nrhs");
+    if (h->ws.R < 1) fail(ASKIT_ERR_NOT_READY, "askit_update_weights has not been called");
+    if (ldu < h->ws.R) fail(ASKIT_ERR_INVALID_ARG, "need ldu >= nrhs");
     EvalArgs a;
     a.Y = h->Xt;
     a.nslab = (int64_t)h->slabs.size();
@@ -424,7 +507,7 @@ askit_status askit_evaluate(askit_handle *h, float *U, int64_t ldu, void *stream
     a.outmap = h->perm;
     a.U = U;
     a.ldu = ldu;
-    evaluate(h, a, (hipStream_t)stream);
+    evaluate(h, h->ws, a, (hipStream_t)stream);
     API_END
 }
 
@@ -435,72 +518,9 @@ askit_status askit_query(askit_handle *h, const float *Y, int64_t M, int64_t ldy
     if (!h || !Y || !U) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
     if (M < 1 || M >= (1ll << 31)) fail(ASKIT_ERR_INVALID_ARG, "need 1 <= M < 2^31");
     if (ldy < h->d) fail(ASKIT_ERR_INVALID_ARG, "need ldy >= d");
-    if (h->nrhs < 1) fail(ASKIT_ERR_NOT_READY, "askit_update_weights has not been called");
-    if (ldu < h->nrhs) fail(ASKIT_ERR_INVALID_ARG, "need ldu >= nrhs");
-    hipStream_t s = (hipStream_t)stream;
-    const int dp = h->dp, kappa = h->kappa;
-    std::vector<void *> tmp;
-    struct Guard {
-        std::vector<void *> &t;
-        hipStream_t s;
-        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
-    } guard{tmp, s};
-    auto ta = [&](size_t b) {
-        void *p;
-        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
-        tmp.push_back(p);
-        return p;
-    };
-    float *Yp = (float *)ta(sizeof(float) * M * dp);
-    uint16_t *Yh = (uint16_t *)ta(sizeof(uint16_t) * M * dp);
-    uint16_t *Yl = (uint16_t *)ta(sizeof(uint16_t) * M * dp);
-    float *Yn = (float *)ta(sizeof(float) * M);
-    int32_t *flag = (int32_t *)ta(sizeof(int32_t) * (M + 1));
-    int32_t *cand = (int32_t *)ta(sizeof(int32_t) * M * KNN_CAND);
-    float *thr = (float *)ta(sizeof(float) * M);
-    int32_t *qidx = (int32_t *)ta(sizeof(int32_t) * M * kappa);
-    double *qd = (double *)ta(sizeof(double) * M * kappa);
-    int32_t *nb = (int32_t *)ta(sizeof(int32_t) * M * kappa);
-    int32_t *nbs = (int32_t *)ta(sizeof(int32_t) * M * kappa);
-    int32_t *order = (int32_t *)ta(sizeof(int32_t) * M);
-    float *Ys = (float *)ta(sizeof(float) * M * dp);
-    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    pack_points(Y, M, h->d, ldy, dp, Yp, flag, s);
-    int32_t hflag = 0;
-    HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    if (hflag) fail(ASKIT_ERR_INVALID_ARG, "Y holds a non-finite value");
-    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    split_bf16(Yp, M, dp, Yh, Yl, Yn, s);
-    float mx = max_norm(h->Xn, h->N, s);
-    knn_candidates(Yh, Yl, Yn, M, h->Xh, h->Xl, h->Xn, h->N, dp, false, cand, thr, s);
-    knn_refine(Yp, M, h->Xo, h->N, h->d, dp, kappa, cand, thr, Yn, mx, false, qidx, qd, flag + 1, flag, s);
-    int32_t nbad = 0;
-    HIPC(hipMemcpyAsync(&nbad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    knn_exact_rows(Yp, h->Xo, h->N, h->d, dp, kappa, false, flag + 1, nbad, qidx, qd, s);
-    hipLaunchKernelGGL(k_map_pos, dim3((unsigned)((M * kappa + 255) / 256)), dim3(256), 0, s, qidx,
-                       M * kappa, h->iperm, nb);
-    HIPC(hipGetLastError());
-    int32_t *ptr, *node;
-    uint64_t *mask;
-    Slab *qslabs;
-    int64_t nen, nef;
-    sort_queries(h, nb, M, order, nbs, tmp, s);
-    gather_rows(Yp, order, M, dp, Ys, s);
-    build_query_interactions(h, nbs, M, qslabs, ptr, node, mask, nen, nef, tmp, s);
-    EvalArgs a;
-    a.Y = Ys;
-    a.nslab = (M + SLAB - 1) / SLAB;
-    a.slabs = qslabs;
-    a.ptr = ptr;
-    a.node = node;
-    a.mask = mask;
-    a.outmap = order;
-    a.U = U;
-    a.ldu = ldu;
-    evaluate(h, a, s);
-    HIPC(hipStreamSynchronize(s));
+    if (h->ws.R < 1) fail(ASKIT_ERR_NOT_READY, "askit_update_weights has not been called");
+    if (ldu < h->ws.R) fail(ASKIT_ERR_INVALID_ARG, "need ldu >= nrhs");
+    query_points(h, h->ws, Y, M, ldy, U, ldu, (hipStream_t)stream);
     API_END
 }
 
@@ -522,7 +542,7 @@ askit_status askit_get_info(const askit_handle *h, askit_info *o)
     o->leaf_size = h->m;
     o->max_skeleton = h->smax;
     o->sample_rows = h->ell;
-    o->nrhs = h->nrhs;
+    o->nrhs = h->ws.R;
     o->num_nodes = (int32_t)h->nodes.size();
     o->num_leaves = (int32_t)h->leaves.size();
     o->depth = h->depth;
@@ -538,6 +558,13 @@ askit_status askit_get_info(const askit_handle *h, askit_info *o)
     o->t_lists_ms = h->t_lists;
     o->t_skel_ms = h->t_skel;
     o->t_inter_ms = h->t_inter;
+    if (h->up_pending) {
+        float ms = 0.f;
+        HIPC(hipEventSynchronize(h->ev_up1));
+        HIPC(hipEventElapsedTime(&ms, h->ev_up0, h->ev_up1));
+        const_cast<askit_handle *>(h)->t_update = ms;
+        const_cast<askit_handle *>(h)->up_pending = false;
+    }
     o->t_update_ms = h->t_update;
     o->t_knn_sweep_ms = h->t_knn_sweep;
     o->t_qr_ms = h->t_qr;
@@ -569,7 +596,7 @@ askit_status askit_export(const askit_handle *h, int32_t what, void *dst, size_t
     case ASKIT_X_COLPERM: src = h->colperm; n = 4 * nn * h->ncol_max; break;
     case ASKIT_X_NCOLS: src = h->ncols; n = 4 * nn; break;
     case ASKIT_X_PROJ: src = h->P; n = 4 * h->pslot_total; break;
-    case ASKIT_X_SKEL_W: src = h->Wsk; n = h->Wsk ? 4 * nn * h->smax * h->nrhs : 0; break;
+    case ASKIT_X_SKEL_W: src = h->ws.Wsk; n = h->ws.Wsk ? 4 * nn * h->smax * h->ws.R : 0; break;
     case ASKIT_X_SLAB_PTR: src = h->sl_ptr; n = 4 * (2 * nslab + 2); break;
     case ASKIT_X_SLAB_NODE: src = h->sl_node; n = 4 * (h->near_entries + h->far_entries); break;
     case ASKIT_X_SLAB_MASK: src = h->sl_mask; n = 8 * (h->near_entries + h->far_entries); break;

@@ -78,6 +78,13 @@ struct Slab {              // SLAB consecutive tree positions of one leaf
     int32_t row0, nrows, leaf, pad;
 };
 
+// Weights of one evaluation: W in tree order and the skeleton weights.
+struct WeightSet {
+    float *Wt = nullptr;       // N x R
+    float *Wsk = nullptr;      // nn x smax x R
+    int R = 0;
+};
+
 }  // namespace askit
 
 struct askit_handle {
@@ -87,7 +94,7 @@ struct askit_handle {
     askit_params prm{};
     int kappa = 0, m = 0, smax = 0, ell = 0, ncol_max = 0;
     bool varh = false;
-    int nrhs = 0;                      // set by update_weights
+    float maxnorm = 0.0f;              // largest FP32 squared norm of the points
     int device = 0;
 
     // tree (host copy; shape depends only on N and m)
@@ -122,9 +129,10 @@ struct askit_handle {
     int64_t *d_pslot = nullptr;
     float *Xs = nullptr;          // nn x smax x dp skeleton coordinates
     float *gs = nullptr;          // nn x smax skeleton bandwidth factors
-    float *Wt = nullptr;          // N x nrhs tree order weights
-    float *Wsk = nullptr;         // nn x smax x nrhs skeleton weights
-    int wcap = 0;                 // columns allocated in Wt / Wsk
+    askit::WeightSet ws;          // weights of askit_update_weights / askit_evaluate
+    int wcap = 0;                 // columns allocated in ws
+    int32_t *up_ids = nullptr;    // non-root node ids, deepest level first
+    std::vector<std::pair<int, int>> up_seg;   // (offset, count) per level, bottom-up
     askit::Slab *d_slabs = nullptr;
     int32_t *sl_ptr = nullptr;    // 2*nslab+2: near offsets [0..nslab], far offsets [nslab+1..]
     int32_t *sl_node = nullptr;
@@ -135,6 +143,8 @@ struct askit_handle {
     int64_t near_pairs = 0, far_pairs = 0, knn_uncertified = 0;
     double t_knn = 0, t_tree = 0, t_lists = 0, t_skel = 0, t_inter = 0, t_update = 0;
     double t_knn_sweep = 0, t_qr = 0;
+    hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr;
+    bool up_pending = false;
 
     ~askit_handle();
     void *alloc(size_t bytes, bool zero = true);
@@ -150,19 +160,22 @@ void split_bf16(const float *X, int64_t N, int dp, uint16_t *hi, uint16_t *lo, f
                 hipStream_t s);
 void gather_rows(const float *src, const int32_t *idx, int64_t n, int dp, float *dst, hipStream_t s);
 
-// knn.hip
+// knn.hip -- references are tree-ordered points (positions); idmap maps a
+// position to its point id (ties are broken by point id); rowmap maps a query
+// row to its output row (NULL = identity).
+// candidates + threshold per row; rows that need the exact scan are appended to
+// bad_rows (count in *bad_count, device)
 void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int64_t M,
                     const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int dp,
-                    bool exclude_self, int32_t *cand, float *thr, hipStream_t s);
-// exact re-rank of the candidates; rows whose certificate fails are appended to
-// `bad_rows` (count in *bad_count, device)
+                    bool exclude_self, bool start_local, int32_t *cand, float *thr,
+                    int32_t *bad_rows, int32_t *bad_count, hipStream_t s);
 void knn_refine(const float *Q, int64_t M, const float *X, int64_t N, int d, int dp, int kappa,
                 const int32_t *cand, const float *thr, const float *Qn, float maxnorm,
-                bool exclude_self, int32_t *idx, double *dist, int32_t *bad_rows,
-                int32_t *bad_count, hipStream_t s);
+                const int32_t *idmap, const int32_t *rowmap, int32_t *idx, double *dist,
+                int32_t *bad_rows, int32_t *bad_count, hipStream_t s);
 void knn_exact_rows(const float *Q, const float *X, int64_t N, int d, int dp, int kappa,
-                    bool exclude_self, const int32_t *rows, int nrows, int32_t *idx, double *dist,
-                    hipStream_t s);
+                    bool exclude_self, const int32_t *rows, int nrows, const int32_t *idmap,
+                    const int32_t *rowmap, int32_t *idx, double *dist, hipStream_t s);
 float max_norm(const float *nrm, int64_t N, hipStream_t s);
 
 // tree.hip
@@ -185,7 +198,9 @@ void sort_queries(askit_handle *h, const int32_t *nb, int64_t M, int32_t *order,
 
 // skel.hip
 void skeletonize(askit_handle *h, hipStream_t s);
-void upward(askit_handle *h, hipStream_t s);
+void upward(askit_handle *h, const WeightSet &ws, hipStream_t s);   // no host sync
+void prepare_upward(askit_handle *h);                                  // once, after setup
+void permute_weights(askit_handle *h, const float *W, int64_t ldw, WeightSet &ws, hipStream_t s);
 
 // eval.hip
 struct EvalArgs {
@@ -198,6 +213,9 @@ struct EvalArgs {
     float *U;
     int64_t ldu;
 };
-void evaluate(askit_handle *h, const EvalArgs &a, hipStream_t s);
+void evaluate(askit_handle *h, const WeightSet &ws, const EvalArgs &a, hipStream_t s);
+// queries at M new points against the weights ws (U: M x ws.R, row stride ldu)
+void query_points(askit_handle *h, const WeightSet &ws, const float *Y, int64_t M, int64_t ldy,
+                  float *U, int64_t ldu, hipStream_t s);
 
 }  // namespace askit

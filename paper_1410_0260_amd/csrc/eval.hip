@@ -17,11 +17,22 @@
 namespace askit {
 
 typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+
+// Round-to-nearest-even FP32 -> bf16 (finite inputs).
+__device__ __forceinline__ uint32_t ev_f2bf(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float ev_bf2f(uint32_t b) { return __uint_as_float(b << 16); }
 
 constexpr int EV_T = 256;
 constexpr int EV_KC = 64;              // dimensions per LDS chunk
 constexpr int EV_LD = EV_KC + 4;       // padded LDS row (floats)
-constexpr int EV_RB = 4;               // right-hand sides per pass
+constexpr int EV_RB = 8;               // largest right-hand-side block per pass
+constexpr int EV_LH = EV_KC + 8;       // padded LDS row of the bf16 operands (elements)
 
 struct EvalParams {
     const float *Y;            // targets (rows of stride dp)
@@ -39,11 +50,16 @@ struct EvalParams {
     int smax, dp, R, r0, rb;
 };
 
-template <int RB>
+// BF: distance products as bf16 hi/lo split (hi*hi + hi*lo + lo*hi) on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation and an FP64 final combine of
+// |x|^2 + |y|^2 - 2 x.y; otherwise FP32 products on v_mfma_f32_32x32x2_f32.
+template <int RB, bool BF>
 __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
 {
-    __shared__ __attribute__((aligned(16))) float sA[64 * EV_LD];
-    __shared__ __attribute__((aligned(16))) float sB[64 * EV_LD];
+    __shared__ __attribute__((aligned(16))) float sA[BF ? 16 : 64 * EV_LD];
+    __shared__ __attribute__((aligned(16))) float sB[BF ? 16 : 64 * EV_LD];
+    __shared__ __attribute__((aligned(16))) uint16_t sAh[BF ? 64 * EV_LH : 8], sAl[BF ? 64 * EV_LH : 8];
+    __shared__ __attribute__((aligned(16))) uint16_t sBh[BF ? 64 * EV_LH : 8], sBl[BF ? 64 * EV_LH : 8];
     __shared__ float sC[1024 + 64];      // centre (dp <= 1024)
     __shared__ float sAn[64], sBn[64], sBg[64], sBw[64 * RB];
     __shared__ float sRed[2][64 * RB];
@@ -62,7 +78,8 @@ __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
 
     // load one 64 x EV_KC chunk of rows (centred) into dst; row r valid when r < nrow
     // src row r at base + r * dp; returns the per-row partial squared norms in nrm
-    auto load_chunk = [&](float *dst, const float *base, int nrow, int k0, float *nrm, bool accum) {
+    auto load_chunk = [&](float *dst, uint16_t *dh, uint16_t *dl, const float *base, int nrow, int k0,
+                          float *nrm, bool accum) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             int idx = tid + EV_T * u;
@@ -76,7 +93,15 @@ __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
                 v.z = x.z - sC[kk + 2];
                 v.w = x.w - sC[kk + 3];
             }
-            *reinterpret_cast<float4 *>(dst + row * EV_LD + qd) = v;
+            if constexpr (BF) {
+                uint32_t h0 = ev_f2bf(v.x), h1 = ev_f2bf(v.y), h2 = ev_f2bf(v.z), h3 = ev_f2bf(v.w);
+                uint32_t l0 = ev_f2bf(v.x - ev_bf2f(h0)), l1 = ev_f2bf(v.y - ev_bf2f(h1));
+                uint32_t l2 = ev_f2bf(v.z - ev_bf2f(h2)), l3 = ev_f2bf(v.w - ev_bf2f(h3));
+                *reinterpret_cast<uint2 *>(dh + row * EV_LH + qd) = uint2{h0 | (h1 << 16), h2 | (h3 << 16)};
+                *reinterpret_cast<uint2 *>(dl + row * EV_LH + qd) = uint2{l0 | (l1 << 16), l2 | (l3 << 16)};
+            } else {
+                *reinterpret_cast<float4 *>(dst + row * EV_LD + qd) = v;
+            }
             if (nrm) {
                 float s = v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
 #pragma unroll
@@ -88,7 +113,7 @@ __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
 
     // target norms (all chunks); the target chunk stays resident when dp <= EV_KC
     for (int ch = 0; ch < nchunk; ++ch) {
-        load_chunk(sA, Yb, sb.nrows, ch * EV_KC, sAn, ch > 0);
+        load_chunk(sA, sAh, sAl, Yb, sb.nrows, ch * EV_KC, sAn, ch > 0);
         __syncthreads();
     }
 
@@ -131,8 +156,8 @@ __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
             f32x16 acc = {};
             for (int ch = 0; ch < nchunk; ++ch) {
                 __syncthreads();
-                if (nchunk > 1) load_chunk(sA, Yb, sb.nrows, ch * EV_KC, nullptr, false);
-                load_chunk(sB, src + (int64_t)s0 * dp, nt, ch * EV_KC, sBn, ch > 0);
+                if (nchunk > 1) load_chunk(sA, sAh, sAl, Yb, sb.nrows, ch * EV_KC, nullptr, false);
+                load_chunk(sB, sBh, sBl, src + (int64_t)s0 * dp, nt, ch * EV_KC, sBn, ch > 0);
                 if (ch == 0 && tid < 64) {
                     bool ok = tid < nt;
                     sBg[tid] = ok ? g[s0 + tid] : 0.0f;
@@ -141,16 +166,32 @@ __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
                         sBw[tid * RB + j] = (ok && j < p.rb) ? w[(int64_t)(s0 + tid) * p.R + p.r0 + j] : 0.0f;
                 }
                 __syncthreads();
-                const float *pa = sA + (rq + l32) * EV_LD + 4 * half;
-                const float *pb = sB + (cq + l32) * EV_LD + 4 * half;
                 const int kc = min(EV_KC, dp - ch * EV_KC);
-                for (int g8 = 0; g8 < kc; g8 += 8) {
-                    float4 a4 = *reinterpret_cast<const float4 *>(pa + g8);
-                    float4 b4 = *reinterpret_cast<const float4 *>(pb + g8);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, b4.x, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, b4.y, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, b4.z, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, b4.w, acc, 0, 0, 0);
+                if constexpr (BF) {
+                    const uint16_t *ph = sAh + (rq + l32) * EV_LH + 8 * half;
+                    const uint16_t *pl = sAl + (rq + l32) * EV_LH + 8 * half;
+                    const uint16_t *qh = sBh + (cq + l32) * EV_LH + 8 * half;
+                    const uint16_t *ql = sBl + (cq + l32) * EV_LH + 8 * half;
+                    for (int k16 = 0; k16 < kc; k16 += 16) {
+                        bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(ph + k16));
+                        bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(pl + k16));
+                        bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(qh + k16));
+                        bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(ql + k16));
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+                    }
+                } else {
+                    const float *pa = sA + (rq + l32) * EV_LD + 4 * half;
+                    const float *pb = sB + (cq + l32) * EV_LD + 4 * half;
+                    for (int g8 = 0; g8 < kc; g8 += 8) {
+                        float4 a4 = *reinterpret_cast<const float4 *>(pa + g8);
+                        float4 b4 = *reinterpret_cast<const float4 *>(pb + g8);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, b4.x, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, b4.y, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, b4.z, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, b4.w, acc, 0, 0, 0);
+                    }
                 }
             }
             const int col = cq + l32;
@@ -161,7 +202,11 @@ __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = rq + 8 * (r / 4) + 4 * half + (r % 4);
-                float r2 = fmaxf(sAn[row] + bn - 2.0f * acc[r], 0.0f);
+                float r2;
+                if constexpr (BF)
+                    r2 = (float)fmax((double)sAn[row] + (double)bn - 2.0 * (double)acc[r], 0.0);
+                else
+                    r2 = fmaxf(sAn[row] + bn - 2.0f * acc[r], 0.0f);
                 float kv = exp2f(bg * r2) * mb[r];
 #pragma unroll
                 for (int j = 0; j < RB; ++j) accu[r][j] = fmaf(kv, bw[j], accu[r][j]);
@@ -197,7 +242,7 @@ __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
     }
 }
 
-void evaluate(askit_handle *h, const EvalArgs &a, hipStream_t s)
+void evaluate(askit_handle *h, const WeightSet &ws, const EvalArgs &a, hipStream_t s)
 {
     if (h->dp > 1024) fail(ASKIT_ERR_UNSUPPORTED, "dimension above 1024 is not supported");
     EvalParams p;
@@ -213,22 +258,30 @@ void evaluate(askit_handle *h, const EvalArgs &a, hipStream_t s)
     p.nodes = h->d_nodes;
     p.Xt = h->Xt;
     p.gt = h->gt;
-    p.Wt = h->Wt;
+    p.Wt = ws.Wt;
     p.Xs = h->Xs;
     p.gs = h->gs;
-    p.Wsk = h->Wsk;
+    p.Wsk = ws.Wsk;
     p.skk = h->skk;
     p.smax = h->smax;
     p.dp = h->dp;
-    p.R = h->nrhs;
+    p.R = ws.R;
     if (a.nslab == 0) return;
-    for (int r0 = 0; r0 < h->nrhs; r0 += EV_RB) {
+    const bool bf = h->prm.precision == ASKIT_PREC_BF16X3;
+    for (int r0 = 0; r0 < ws.R; r0 += EV_RB) {
         p.r0 = r0;
-        p.rb = std::min(EV_RB, h->nrhs - r0);
-        if (p.rb == 1)
-            hipLaunchKernelGGL(k_eval<1>, dim3((unsigned)a.nslab), dim3(EV_T), 0, s, p);
-        else
-            hipLaunchKernelGGL(k_eval<EV_RB>, dim3((unsigned)a.nslab), dim3(EV_T), 0, s, p);
+        p.rb = std::min(EV_RB, ws.R - r0);
+        dim3 g((unsigned)a.nslab), b(EV_T);
+        if (p.rb == 1) {
+            if (bf) hipLaunchKernelGGL((k_eval<1, true>), g, b, 0, s, p);
+            else hipLaunchKernelGGL((k_eval<1, false>), g, b, 0, s, p);
+        } else if (p.rb <= 4) {
+            if (bf) hipLaunchKernelGGL((k_eval<4, true>), g, b, 0, s, p);
+            else hipLaunchKernelGGL((k_eval<4, false>), g, b, 0, s, p);
+        } else {
+            if (bf) hipLaunchKernelGGL((k_eval<EV_RB, true>), g, b, 0, s, p);
+            else hipLaunchKernelGGL((k_eval<EV_RB, false>), g, b, 0, s, p);
+        }
         HIPC(hipGetLastError());
     }
 }

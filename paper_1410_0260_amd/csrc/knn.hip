@@ -14,6 +14,9 @@
 //   3. k_knn_exact: full FP64 scan for the rows that are not certified.
 #include "askit_impl.h"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace askit {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
@@ -83,7 +86,124 @@ __device__ __forceinline__ bf16x8 ld_bf8(const uint16_t *p)
     return __builtin_bit_cast(bf16x8, v);
 }
 
-// KS = dp / 16 MFMA k-steps; the query fragments stay in registers.
+#define QMAPPED false
+#define QROW(q) (q)
+
+// Survivor handling for one (column half c, register r) of the 32 x 64 tile
+// held by a wave: values below the row's threshold are appended to the row's
+// LDS buffer; a full buffer is first merged into the row's sorted list.
+#define KNN_SURVIVORS(ACC, C, R)                                                                   \
+    {                                                                                              \
+        const int64_t colg = tbase + 32 * (C) + l32;                                               \
+        const float dv = ACC[R];                                                                   \
+        bool pred = dv < thrv[R];                                                                  \
+        uint64_t mask = __ballot(pred);                                                            \
+        if (mask) {                                                                                \
+            _Pragma("unroll") for (int h = 0; h < 2; ++h)                                          \
+            {                                                                                      \
+                const int RR = 8 * ((R) / 4) + ((R) % 4) + 4 * h;                                  \
+                uint32_t mh = (uint32_t)(mask >> (32 * h));                                        \
+                if (mh == 0) continue;                                                             \
+                int nnew = __popc(mh);                                                             \
+                if (cnt[RR] + nnew > KCB) {                                                        \
+                    ListEntry e = merge_list(list_d[RR], list_i[RR], bd + RR * KCB, bi + RR * KCB, \
+                                             cnt[RR], lane);                                       \
+                    list_d[RR] = e.d;                                                              \
+                    list_i[RR] = e.i;                                                              \
+                    cnt[RR] = 0;                                                                   \
+                    if (half == h) thrv[R] = e.thr;                                                \
+                    pred = dv < thrv[R];                                                           \
+                    mh = (uint32_t)(__ballot(pred) >> (32 * h));                                   \
+                    nnew = __popc(mh);                                                             \
+                }                                                                                  \
+                if (half == h && pred) {                                                           \
+                    int pos = cnt[RR] + __popc(mh & ((1u << l32) - 1u));                           \
+                    bd[RR * KCB + pos] = dv;                                                       \
+                    bi[RR * KCB + pos] = (int)colg;                                                \
+                }                                                                                  \
+                cnt[RR] += nnew;                                                                   \
+            }                                                                                      \
+        }                                                                                          \
+    }
+
+// Approximate squared distances of one tile (from ACC0/ACC1 into the local
+// arrays dA/dB, norms of the tile's points in NB): sets `any` when a value of
+// the wave is below its row's threshold.  Only the last tile (ragged) and the tile holding the
+// wave's own rows (self exclusion) need per-element checks.
+#define KNN_DISTANCES(ACC0, ACC1, NB)                                                              \
+    bool any = false;                                                                              \
+    float dA[16], dB[16];                                                                          \
+    {                                                                                              \
+        const float ny0 = (NB)[l32], ny1 = (NB)[32 + l32];                                         \
+        const int edge = __builtin_amdgcn_readfirstlane(                                           \
+            (int)((tbase + KB_N > N) || (excl && (QMAPPED || (tbase < q0 + 32 && q0 < tbase + KB_N))))); \
+        if (edge) {                                                                                \
+            _Pragma("unroll") for (int r = 0; r < 16; ++r)                                         \
+            {                                                                                      \
+                float d0 = fmaf(-2.0f, ACC0[r], qn[r] + ny0);                                      \
+                float d1 = fmaf(-2.0f, ACC1[r], qn[r] + ny1);                                      \
+                const int64_t qrow = QROW(q0 + 8 * (r / 4) + 4 * half + (r % 4));                  \
+                const int64_t c0 = tbase + l32, c1 = tbase + 32 + l32;                             \
+                if (c0 >= N || (excl && c0 == qrow)) d0 = INFINITY;                                \
+                if (c1 >= N || (excl && c1 == qrow)) d1 = INFINITY;                                \
+                dA[r] = d0;                                                                        \
+                dB[r] = d1;                                                                        \
+                any |= (d0 < thrv[r]) | (d1 < thrv[r]);                                            \
+            }                                                                                      \
+        } else {                                                                                   \
+            _Pragma("unroll") for (int r = 0; r < 16; ++r)                                         \
+            {                                                                                      \
+                float d0 = fmaf(-2.0f, ACC0[r], qn[r] + ny0);                                      \
+                float d1 = fmaf(-2.0f, ACC1[r], qn[r] + ny1);                                      \
+                dA[r] = d0;                                                                        \
+                dB[r] = d1;                                                                        \
+                any |= (d0 < thrv[r]) | (d1 < thrv[r]);                                            \
+            }                                                                                      \
+        }                                                                                          \
+    }
+
+// Tile loads (global -> registers stage st) and stores (stage st -> LDS buffer b).
+#define KNN_TILE_IO()                                                                              \
+    auto load_tile = [&](int st, int64_t tt) {                                                     \
+        _Pragma("unroll") for (int u = 0; u < PER; ++u)                                            \
+        {                                                                                          \
+            int c = tid + 256 * u;                                                                 \
+            int row = c / (DP / 8), off = (c % (DP / 8)) * 8;                                      \
+            int64_t g = tt * KB_N + row;                                                           \
+            if (c < CHUNKS && g < N) {                                                             \
+                rh[st][u] = *reinterpret_cast<const uint4 *>(Xh + g * DP + off);                   \
+                rl[st][u] = *reinterpret_cast<const uint4 *>(Xl + g * DP + off);                   \
+            } else {                                                                               \
+                rh[st][u] = uint4{0, 0, 0, 0};                                                     \
+                rl[st][u] = uint4{0, 0, 0, 0};                                                     \
+            }                                                                                      \
+        }                                                                                          \
+        int64_t g = tt * KB_N + tid;                                                               \
+        rn[st] = (tid < KB_N && g < N) ? Xn[g] : 0.0f;                                             \
+    };                                                                                             \
+    auto store_tile = [&](int st, int b) {                                                         \
+        _Pragma("unroll") for (int u = 0; u < PER; ++u)                                            \
+        {                                                                                          \
+            int c = tid + 256 * u;                                                                 \
+            if (c < CHUNKS) {                                                                      \
+                int row = c / (DP / 8), off = (c % (DP / 8)) * 8;                                  \
+                *reinterpret_cast<uint4 *>(&sBh[b * TB + row * LDB + off]) = rh[st][u];            \
+                *reinterpret_cast<uint4 *>(&sBl[b * TB + row * LDB + off]) = rl[st][u];            \
+            }                                                                                      \
+        }                                                                                          \
+        if (tid < KB_N) sBn[b * KB_N + tid] = rn[st];                                              \
+    };
+
+// KS = dp / 16 MFMA k-steps; the query fragments stay in registers.  Three
+// LDS buffers and two accumulator sets software-pipeline the sweep: while
+// the distances of tile t are checked on the VALU, the MFMAs of tile t+1 run,
+// and the points of tile t+2 (loaded one iteration earlier) go to LDS.  With
+// start_local the sweep starts at the tile holding the block's own rows and
+// wraps around: on tree-ordered points the first tiles hold each row's
+// neighbourhood, so the lists fill at once and later tiles rarely add
+// candidates.
+// qpos (optional): query row q is row qpos[q] of Qh/Ql/Qn and of the outputs
+// (self exclusion and the sweep start use that row); M counts mapped rows.
 template <int KS>
 __global__ __launch_bounds__(256) void k_knn_cand(const uint16_t *__restrict__ Qh,
                                                   const uint16_t *__restrict__ Ql,
@@ -91,31 +211,36 @@ __global__ __launch_bounds__(256) void k_knn_cand(const uint16_t *__restrict__ Q
                                                   const uint16_t *__restrict__ Xh,
                                                   const uint16_t *__restrict__ Xl,
                                                   const float *__restrict__ Xn, int64_t N,
-                                                  int excl, int32_t *__restrict__ cand,
+                                                  int excl, int start_local, int win_tiles,
+                                                  const int32_t *__restrict__ qpos,
+                                                  int32_t *__restrict__ cand,
                                                   float *__restrict__ thr_out)
 {
     constexpr int DP = KS * 16;
     constexpr int LDB = DP + 8;                      // padded LDS row (bf16 elements)
-    __shared__ __attribute__((aligned(16))) uint16_t sBh[KB_N * LDB];
-    __shared__ __attribute__((aligned(16))) uint16_t sBl[KB_N * LDB];
-    __shared__ float sBn[KB_N];
+    constexpr int TB = KB_N * LDB;                   // one operand tile
+    __shared__ __attribute__((aligned(16))) uint16_t sBh[3 * TB];
+    __shared__ __attribute__((aligned(16))) uint16_t sBl[3 * TB];
+    __shared__ float sBn[3 * KB_N];
     __shared__ float sbd[KB_M * KCB];
     __shared__ int sbi[KB_M * KCB];
 
-    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    const int tid = threadIdx.x, lane = tid % WAVE;
+    const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const int half = lane >> 5, l32 = lane & 31;
     const int64_t q0 = (int64_t)blockIdx.x * KB_M + wv * 32;
+    auto qmap = [&](int64_t q) -> int64_t { return qpos ? (int64_t)qpos[q] : q; };
 
-    // query fragments and norms
     bf16x8 ah[KS], al[KS];
     {
         int64_t row = q0 + l32;
         bool ok = row < M;
+        int64_t src = ok ? qmap(row) : 0;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             if (ok) {
-                ah[s] = ld_bf8(Qh + row * DP + 16 * s + 8 * half);
-                al[s] = ld_bf8(Ql + row * DP + 16 * s + 8 * half);
+                ah[s] = ld_bf8(Qh + src * DP + 16 * s + 8 * half);
+                al[s] = ld_bf8(Ql + src * DP + 16 * s + 8 * half);
             } else {
                 ah[s] = bf16x8{};
                 al[s] = bf16x8{};
@@ -126,7 +251,7 @@ __global__ __launch_bounds__(256) void k_knn_cand(const uint16_t *__restrict__ Q
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         int64_t row = q0 + 8 * (r / 4) + 4 * half + (r % 4);
-        qn[r] = row < M ? Qn[row] : 0.0f;
+        qn[r] = row < M ? Qn[qmap(row)] : 0.0f;
         thrv[r] = INFINITY;
     }
     float list_d[32];
@@ -140,53 +265,36 @@ __global__ __launch_bounds__(256) void k_knn_cand(const uint16_t *__restrict__ Q
     float *bd = sbd + wv * 32 * KCB;
     int *bi = sbi + wv * 32 * KCB;
 
-    const int64_t ntiles = (N + KB_N - 1) / KB_N;
+    const int64_t ntiles_all = (N + KB_N - 1) / KB_N;
+    // win_tiles > 0: sweep only the win_tiles tiles around the block's own rows
+    // (tree order), which gives every row an upper bound of its 64th distance
+    const int64_t qfirst = qmap(min((int64_t)blockIdx.x * KB_M, M - 1));
+    int64_t t0 = start_local ? (qfirst / KB_N) % ntiles_all : 0;
+    int64_t ntiles = ntiles_all;
+    if (win_tiles > 0 && win_tiles < ntiles_all) {
+        ntiles = win_tiles;
+        int64_t c = (int64_t)blockIdx.x * KB_M / KB_N + (KB_M / KB_N) / 2 - win_tiles / 2;
+        t0 = c < 0 ? 0 : (c + win_tiles > ntiles_all ? ntiles_all - win_tiles : c);
+    }
     constexpr int CHUNKS = KB_N * DP / 8;            // 16-byte chunks per operand tile
     constexpr int PER = (CHUNKS + 255) / 256;
-    uint4 rh[PER], rl[PER];
-    float rn = 0.0f;
-    auto load_tile = [&](int64_t t) {
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            int c = tid + 256 * u;
-            int row = c / (DP / 8), off = (c % (DP / 8)) * 8;
-            int64_t g = t * KB_N + row;
-            if (c < CHUNKS && g < N) {
-                rh[u] = *reinterpret_cast<const uint4 *>(Xh + g * DP + off);
-                rl[u] = *reinterpret_cast<const uint4 *>(Xl + g * DP + off);
-            } else {
-                rh[u] = uint4{0, 0, 0, 0};
-                rl[u] = uint4{0, 0, 0, 0};
-            }
-        }
-        int64_t g = t * KB_N + tid;
-        rn = (tid < KB_N && g < N) ? Xn[g] : 0.0f;
+    uint4 rh[2][PER], rl[2][PER];
+    float rn[2] = {0.0f, 0.0f};
+    auto tile_of = [&](int64_t t) {
+        int64_t tt = t0 + t;
+        return tt >= ntiles_all ? tt - ntiles_all : tt;
     };
-    auto store_tile = [&]() {
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            int c = tid + 256 * u;
-            if (c < CHUNKS) {
-                int row = c / (DP / 8), off = (c % (DP / 8)) * 8;
-                *reinterpret_cast<uint4 *>(sBh + row * LDB + off) = rh[u];
-                *reinterpret_cast<uint4 *>(sBl + row * LDB + off) = rl[u];
-            }
-        }
-        if (tid < KB_N) sBn[tid] = rn;
-    };
-
-    load_tile(0);
-    store_tile();
-    __syncthreads();
-    for (int64_t t = 0; t < ntiles; ++t) {
-        if (t + 1 < ntiles) load_tile(t + 1);
-        f32x16 acc0 = {}, acc1 = {};
+    KNN_TILE_IO();
+    auto mfma_tile = [&](int b, f32x16 &acc0, f32x16 &acc1) {
+        const uint16_t *ph = sBh + b * TB, *pl = sBl + b * TB;
+        acc0 = f32x16{};
+        acc1 = f32x16{};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            bf16x8 bh0 = ld_bf8(sBh + l32 * LDB + 16 * s + 8 * half);
-            bf16x8 bl0 = ld_bf8(sBl + l32 * LDB + 16 * s + 8 * half);
-            bf16x8 bh1 = ld_bf8(sBh + (32 + l32) * LDB + 16 * s + 8 * half);
-            bf16x8 bl1 = ld_bf8(sBl + (32 + l32) * LDB + 16 * s + 8 * half);
+            bf16x8 bh0 = ld_bf8(ph + l32 * LDB + 16 * s + 8 * half);
+            bf16x8 bl0 = ld_bf8(pl + l32 * LDB + 16 * s + 8 * half);
+            bf16x8 bh1 = ld_bf8(ph + (32 + l32) * LDB + 16 * s + 8 * half);
+            bf16x8 bl1 = ld_bf8(pl + (32 + l32) * LDB + 16 * s + 8 * half);
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s], bh0, acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s], bh1, acc1, 0, 0, 0);
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s], bl0, acc0, 0, 0, 0);
@@ -194,89 +302,91 @@ __global__ __launch_bounds__(256) void k_knn_cand(const uint16_t *__restrict__ Q
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], bh0, acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], bh1, acc1, 0, 0, 0);
         }
+    };
+
+    // prologue: tiles 0 and 1 in LDS buffers 0 and 1, tile 2 in register stage 0
+    load_tile(0, tile_of(0));
+    store_tile(0, 0);
+    if (ntiles > 1) {
+        load_tile(1, tile_of(1));
+        store_tile(1, 1);
+    }
+    if (ntiles > 2) load_tile(0, tile_of(2));
+    __syncthreads();
+    f32x16 accA0, accA1, accB0, accB1;
+    mfma_tile(0, accA0, accA1);
+
+    // iteration t: the accumulators of tile t are ready (CUR selects the set);
+    // MFMAs of tile t+1 read LDS buffer (t+1)%3; register stage t%2 holds tile
+    // t+2, stored to buffer (t+2)%3; loads of tile t+3 go to stage (t+1)%2
+#undef QMAPPED
+#undef QROW
+#define QMAPPED (qpos != nullptr)
+#define QROW(q) ((q) < M ? qmap(q) : (int64_t)-1)
+    auto iter = [&](auto CUR, int64_t t, f32x16 &c0, f32x16 &c1, f32x16 &n0, f32x16 &n1) {
+        constexpr int st = decltype(CUR)::value;
+        const int64_t tbase = tile_of(t) * KB_N;
+        if (t + 3 < ntiles) load_tile(st ^ 1, tile_of(t + 3));
+        if (t + 1 < ntiles) mfma_tile((int)((t + 1) % 3), n0, n1);
+        KNN_DISTANCES(c0, c1, sBn + (t % 3) * KB_N);
+        if (__ballot(any)) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int64_t colg = t * KB_N + 32 * c + l32;
-            const float ny = sBn[32 * c + l32];
-            const bool colok = colg < N;
+            for (int r = 0; r < 16; ++r) KNN_SURVIVORS(dA, 0, r);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t qrow = q0 + 8 * (r / 4) + 4 * half + (r % 4);
-                float a = c == 0 ? acc0[r] : acc1[r];
-                float dv = qn[r] + ny - 2.0f * a;
-                if (!colok || (excl && colg == qrow)) dv = INFINITY;
-                bool pred = dv < thrv[r];
-                uint64_t mask = __ballot(pred);
-                if (mask == 0) continue;
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int R = 8 * (r / 4) + (r % 4) + 4 * h;
-                    uint32_t mh = (uint32_t)(mask >> (32 * h));
-                    if (mh == 0) continue;
-                    int nnew = __popc(mh);
-                    if (cnt[R] + nnew > KCB) {
-                        ListEntry e = merge_list(list_d[R], list_i[R], bd + R * KCB, bi + R * KCB,
-                                                 cnt[R], lane);
-                        list_d[R] = e.d;
-                        list_i[R] = e.i;
-                        cnt[R] = 0;
-                        if (half == h) thrv[r] = e.thr;
-                        pred = dv < thrv[r];
-                        mh = (uint32_t)(__ballot(pred) >> (32 * h));
-                        nnew = __popc(mh);
-                    }
-                    if (half == h && pred) {
-                        int pos = cnt[R] + __popc(mh & ((1u << l32) - 1u));
-                        bd[R * KCB + pos] = dv;
-                        bi[R * KCB + pos] = (int)colg;
-                    }
-                    cnt[R] += nnew;
-                }
-            }
+            for (int r = 0; r < 16; ++r) KNN_SURVIVORS(dB, 1, r);
         }
+        if (t + 2 < ntiles) store_tile(st, (int)((t + 2) % 3));
         __syncthreads();
-        if (t + 1 < ntiles) {
-            store_tile();
-            __syncthreads();
-        }
+    };
+    for (int64_t t = 0; t < ntiles; t += 2) {
+        iter(std::integral_constant<int, 0>{}, t, accA0, accA1, accB0, accB1);
+        if (t + 1 < ntiles) iter(std::integral_constant<int, 1>{}, t + 1, accB0, accB1, accA0, accA1);
     }
     // final merge and output
 #pragma unroll
     for (int R = 0; R < 32; ++R) {
-        float th = list_d[R];
         if (cnt[R] > 0) {
             ListEntry e = merge_list(list_d[R], list_i[R], bd + R * KCB, bi + R * KCB, cnt[R], lane);
             list_d[R] = e.d;
             list_i[R] = e.i;
         }
-        th = __shfl(list_d[R], 63);
+        float th = __shfl(list_d[R], 63);
         int64_t row = q0 + R;
         if (row < M) {
-            cand[row * KNN_CAND + lane] = list_i[R] == 0x7fffffff ? -1 : list_i[R];
-            if (lane == 0) thr_out[row] = th;
+            int64_t orow = qmap(row);
+            cand[orow * KNN_CAND + lane] = list_i[R] == 0x7fffffff ? -1 : list_i[R];
+            if (lane == 0) thr_out[orow] = th;
         }
     }
+#undef QMAPPED
+#undef QROW
+#define QMAPPED false
+#define QROW(q) (q)
 }
 
-// Generic variant for dp > 128: query fragments re-read from memory per tile.
+// Generic variant for dp > 128: query fragments re-read from memory per tile,
+// reference tiles staged in LDS in chunks of 128 dimensions.
 __global__ __launch_bounds__(256) void k_knn_cand_wide(const uint16_t *__restrict__ Qh,
                                                        const uint16_t *__restrict__ Ql,
                                                        const float *__restrict__ Qn, int64_t M,
                                                        const uint16_t *__restrict__ Xh,
                                                        const uint16_t *__restrict__ Xl,
                                                        const float *__restrict__ Xn, int64_t N,
-                                                       int dp, int excl, int32_t *__restrict__ cand,
+                                                       int dp, int excl, int start_local,
+                                                       int32_t *__restrict__ cand,
                                                        float *__restrict__ thr_out)
 {
     constexpr int KC = 128;                          // dims per LDS chunk
     constexpr int LDB = KC + 8;
-    __shared__ __attribute__((aligned(16))) uint16_t sBh[KB_N * LDB];
-    __shared__ __attribute__((aligned(16))) uint16_t sBl[KB_N * LDB];
-    __shared__ float sBn[KB_N];
+    __shared__ __attribute__((aligned(16))) uint16_t sBh[1][KB_N * LDB];
+    __shared__ __attribute__((aligned(16))) uint16_t sBl[1][KB_N * LDB];
+    __shared__ float sBn[1][KB_N];
     __shared__ float sbd[KB_M * KCB];
     __shared__ int sbi[KB_M * KCB];
+    const int cur = 0;
 
-    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    const int tid = threadIdx.x, lane = tid % WAVE;
+    const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const int half = lane >> 5, l32 = lane & 31;
     const int64_t q0 = (int64_t)blockIdx.x * KB_M + wv * 32;
     const int64_t arow = q0 + l32;
@@ -300,35 +410,39 @@ __global__ __launch_bounds__(256) void k_knn_cand_wide(const uint16_t *__restric
     float *bd = sbd + wv * 32 * KCB;
     int *bi = sbi + wv * 32 * KCB;
     const int64_t ntiles = (N + KB_N - 1) / KB_N;
+    const int64_t t0 = start_local ? ((int64_t)blockIdx.x * KB_M / KB_N) % ntiles : 0;
 
     for (int64_t t = 0; t < ntiles; ++t) {
+        int64_t tt = t0 + t;
+        if (tt >= ntiles) tt -= ntiles;
+        const int64_t tbase = tt * KB_N;
         f32x16 acc0 = {}, acc1 = {};
         for (int k0 = 0; k0 < dp; k0 += KC) {
             const int kc = min(KC, dp - k0);
             __syncthreads();
             for (int c = tid; c < KB_N * (KC / 8); c += 256) {
                 int row = c / (KC / 8), off = (c % (KC / 8)) * 8;
-                int64_t g = t * KB_N + row;
+                int64_t g = tbase + row;
                 uint4 vh = {0, 0, 0, 0}, vl = {0, 0, 0, 0};
                 if (g < N && off < kc) {
                     vh = *reinterpret_cast<const uint4 *>(Xh + g * dp + k0 + off);
                     vl = *reinterpret_cast<const uint4 *>(Xl + g * dp + k0 + off);
                 }
-                *reinterpret_cast<uint4 *>(sBh + row * LDB + off) = vh;
-                *reinterpret_cast<uint4 *>(sBl + row * LDB + off) = vl;
+                *reinterpret_cast<uint4 *>(&sBh[0][row * LDB + off]) = vh;
+                *reinterpret_cast<uint4 *>(&sBl[0][row * LDB + off]) = vl;
             }
             if (k0 == 0 && tid < KB_N) {
-                int64_t g = t * KB_N + tid;
-                sBn[tid] = g < N ? Xn[g] : 0.0f;
+                int64_t g = tbase + tid;
+                sBn[0][tid] = g < N ? Xn[g] : 0.0f;
             }
             __syncthreads();
             for (int s = 0; s < kc / 16; ++s) {
                 bf16x8 qa = aok ? ld_bf8(Qh + arow * dp + k0 + 16 * s + 8 * half) : bf16x8{};
                 bf16x8 qb = aok ? ld_bf8(Ql + arow * dp + k0 + 16 * s + 8 * half) : bf16x8{};
-                bf16x8 bh0 = ld_bf8(sBh + l32 * LDB + 16 * s + 8 * half);
-                bf16x8 bl0 = ld_bf8(sBl + l32 * LDB + 16 * s + 8 * half);
-                bf16x8 bh1 = ld_bf8(sBh + (32 + l32) * LDB + 16 * s + 8 * half);
-                bf16x8 bl1 = ld_bf8(sBl + (32 + l32) * LDB + 16 * s + 8 * half);
+                bf16x8 bh0 = ld_bf8(&sBh[0][l32 * LDB + 16 * s + 8 * half]);
+                bf16x8 bl0 = ld_bf8(&sBl[0][l32 * LDB + 16 * s + 8 * half]);
+                bf16x8 bh1 = ld_bf8(&sBh[0][(32 + l32) * LDB + 16 * s + 8 * half]);
+                bf16x8 bl1 = ld_bf8(&sBl[0][(32 + l32) * LDB + 16 * s + 8 * half]);
                 acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa, bh0, acc0, 0, 0, 0);
                 acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa, bh1, acc1, 0, 0, 0);
                 acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa, bl0, acc0, 0, 0, 0);
@@ -337,45 +451,12 @@ __global__ __launch_bounds__(256) void k_knn_cand_wide(const uint16_t *__restric
                 acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qb, bh1, acc1, 0, 0, 0);
             }
         }
+        KNN_DISTANCES(acc0, acc1, sBn[0]);
+        if (__ballot(any)) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int64_t colg = t * KB_N + 32 * c + l32;
-            const float ny = sBn[32 * c + l32];
-            const bool colok = colg < N;
+            for (int r = 0; r < 16; ++r) KNN_SURVIVORS(dA, 0, r);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t qrow = q0 + 8 * (r / 4) + 4 * half + (r % 4);
-                float a = c == 0 ? acc0[r] : acc1[r];
-                float dv = qn[r] + ny - 2.0f * a;
-                if (!colok || (excl && colg == qrow)) dv = INFINITY;
-                bool pred = dv < thrv[r];
-                uint64_t mask = __ballot(pred);
-                if (mask == 0) continue;
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int R = 8 * (r / 4) + (r % 4) + 4 * h;
-                    uint32_t mh = (uint32_t)(mask >> (32 * h));
-                    if (mh == 0) continue;
-                    int nnew = __popc(mh);
-                    if (cnt[R] + nnew > KCB) {
-                        ListEntry e = merge_list(list_d[R], list_i[R], bd + R * KCB, bi + R * KCB,
-                                                 cnt[R], lane);
-                        list_d[R] = e.d;
-                        list_i[R] = e.i;
-                        cnt[R] = 0;
-                        if (half == h) thrv[r] = e.thr;
-                        pred = dv < thrv[r];
-                        mh = (uint32_t)(__ballot(pred) >> (32 * h));
-                        nnew = __popc(mh);
-                    }
-                    if (half == h && pred) {
-                        int pos = cnt[R] + __popc(mh & ((1u << l32) - 1u));
-                        bd[R * KCB + pos] = dv;
-                        bi[R * KCB + pos] = (int)colg;
-                    }
-                    cnt[R] += nnew;
-                }
-            }
+            for (int r = 0; r < 16; ++r) KNN_SURVIVORS(dB, 1, r);
         }
     }
 #pragma unroll
@@ -394,26 +475,287 @@ __global__ __launch_bounds__(256) void k_knn_cand_wide(const uint16_t *__restric
     }
 }
 
+
+// Filter sweep: every reference point whose approximate squared distance to
+// query row i is at most T_i (an upper bound of the row's 64th smallest
+// approximate distance, from the window pass, slightly widened) is appended
+// to the row's segment of `out` (capacity cap; count in ocnt).  Same MFMA
+// arithmetic and pipelining as k_knn_cand, without per-row lists.
+template <int KS>
+__global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restrict__ Qh,
+                                                       const uint16_t *__restrict__ Ql,
+                                                       const float *__restrict__ Qn, int64_t M,
+                                                       const uint16_t *__restrict__ Xh,
+                                                       const uint16_t *__restrict__ Xl,
+                                                       const float *__restrict__ Xn, int64_t N,
+                                                       int excl, int64_t row0,
+                                                       const float *__restrict__ Tin,
+                                                       int cap, int32_t *__restrict__ ocnt,
+                                                       float *__restrict__ od,
+                                                       int32_t *__restrict__ oi)
+{
+    constexpr int DP = KS * 16;
+    constexpr int LDB = DP + 8;
+    constexpr int TB = KB_N * LDB;
+    __shared__ __attribute__((aligned(16))) uint16_t sBh[3 * TB];
+    __shared__ __attribute__((aligned(16))) uint16_t sBl[3 * TB];
+    __shared__ float sBn[3 * KB_N];
+
+    const int tid = threadIdx.x, lane = tid % WAVE;
+    const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const int half = lane >> 5, l32 = lane & 31;
+    const int64_t q0 = (int64_t)blockIdx.x * KB_M + wv * 32;     // local row (output segments)
+
+    bf16x8 ah[KS], al[KS];
+    {
+        int64_t row = q0 + l32;
+        bool ok = row < M;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if (ok) {
+                ah[s] = ld_bf8(Qh + (row0 + row) * DP + 16 * s + 8 * half);
+                al[s] = ld_bf8(Ql + (row0 + row) * DP + 16 * s + 8 * half);
+            } else {
+                ah[s] = bf16x8{};
+                al[s] = bf16x8{};
+            }
+        }
+    }
+    float qn[16], thrv[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        int64_t row = q0 + 8 * (r / 4) + 4 * half + (r % 4);
+        qn[r] = row < M ? Qn[row0 + row] : 0.0f;
+        thrv[r] = row < M ? Tin[row0 + row] : -INFINITY;
+    }
+    // 32-bit row indices (M < 2^31) keep the survivor path's state small
+    const uint32_t qbase = (uint32_t)q0 + 4u * (uint32_t)half;
+    const int64_t ntiles_all = (N + KB_N - 1) / KB_N;
+    const int64_t ntiles = ntiles_all;
+    const int64_t t0 = ((row0 + (int64_t)blockIdx.x * KB_M) / KB_N) % ntiles_all;
+    constexpr int CHUNKS = KB_N * DP / 8;
+    constexpr int PER = (CHUNKS + 255) / 256;
+    uint4 rh[1][PER], rl[1][PER];
+    float rn[1] = {0.0f};
+    auto tile_of = [&](int64_t t) {
+        int64_t tt = t0 + t;
+        return tt >= ntiles_all ? tt - ntiles_all : tt;
+    };
+    KNN_TILE_IO();
+    auto mfma_tile = [&](int b, f32x16 &acc0, f32x16 &acc1) {
+        const uint16_t *ph = sBh + b * TB, *pl = sBl + b * TB;
+        acc0 = f32x16{};
+        acc1 = f32x16{};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            bf16x8 bh0 = ld_bf8(ph + l32 * LDB + 16 * s + 8 * half);
+            bf16x8 bl0 = ld_bf8(pl + l32 * LDB + 16 * s + 8 * half);
+            bf16x8 bh1 = ld_bf8(ph + (32 + l32) * LDB + 16 * s + 8 * half);
+            bf16x8 bl1 = ld_bf8(pl + (32 + l32) * LDB + 16 * s + 8 * half);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s], bh0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s], bh1, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s], bl0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s], bl1, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], bh0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], bh1, acc1, 0, 0, 0);
+        }
+    };
+    load_tile(0, tile_of(0));
+    store_tile(0, 0);
+    if (ntiles > 1) {
+        load_tile(0, tile_of(1));
+        store_tile(0, 1);
+    }
+    __syncthreads();
+    f32x16 accA0, accA1, accB0, accB1;
+    mfma_tile(0, accA0, accA1);
+    // iteration t: accumulators of tile t ready; MFMAs of tile t+1 read buffer
+    // (t+1)%3; the points of tile t+2 are loaded and stored to buffer (t+2)%3
+    auto iter = [&](auto CUR, int64_t t, f32x16 &c0, f32x16 &c1, f32x16 &n0, f32x16 &n1) {
+        const int64_t tbase = tile_of(t) * KB_N;
+        if (t + 2 < ntiles) load_tile(0, tile_of(t + 2));
+        if (t + 1 < ntiles) mfma_tile((int)((t + 1) % 3), n0, n1);
+        // <= keeps the window's own 64 points (same arithmetic as the window pass)
+        const float *nb = sBn + (t % 3) * KB_N;
+        const float ny0 = nb[l32], ny1 = nb[32 + l32];
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            any |= (fmaf(-2.0f, c0[r], qn[r] + ny0) <= thrv[r]) | (fmaf(-2.0f, c1[r], qn[r] + ny1) <= thrv[r]);
+        if (__ballot(any)) {
+            const uint32_t cA = (uint32_t)tbase + (uint32_t)l32, cB = cA + 32u;
+            const uint32_t n32 = (uint32_t)N;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t qrow = qbase + (uint32_t)(8 * (r / 4) + (r % 4));
+                const float dA = fmaf(-2.0f, c0[r], qn[r] + ny0);
+                const float dB = fmaf(-2.0f, c1[r], qn[r] + ny1);
+                if (dA <= thrv[r] && cA < n32 && !(excl && cA == qrow + (uint32_t)row0)) {
+                    uint32_t p = (uint32_t)atomicAdd(&ocnt[qrow], 1);
+                    if (p < (uint32_t)cap) {
+                        const size_t o = (size_t)qrow * (uint32_t)cap + p;
+                        od[o] = dA;
+                        oi[o] = (int32_t)cA;
+                    }
+                }
+                if (dB <= thrv[r] && cB < n32 && !(excl && cB == qrow + (uint32_t)row0)) {
+                    uint32_t p = (uint32_t)atomicAdd(&ocnt[qrow], 1);
+                    if (p < (uint32_t)cap) {
+                        const size_t o = (size_t)qrow * (uint32_t)cap + p;
+                        od[o] = dB;
+                        oi[o] = (int32_t)cB;
+                    }
+                }
+            }
+        }
+        if (t + 2 < ntiles) store_tile(0, (int)((t + 2) % 3));
+        __syncthreads();
+    };
+    for (int64_t t = 0; t < ntiles; t += 2) {
+        iter(std::integral_constant<int, 0>{}, t, accA0, accA1, accB0, accB1);
+        if (t + 1 < ntiles) iter(std::integral_constant<int, 1>{}, t + 1, accB0, accB1, accA0, accA1);
+    }
+}
+
+// Per row (one wave): the 64 smallest (approximate distance, position) of the
+// filter's output, as candidates + the 64th value as threshold.  Rows whose
+// segment overflowed are sent to the exact fallback.
+__global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int cap,
+                                                    const int32_t *__restrict__ ocnt,
+                                                    const float *__restrict__ od,
+                                                    const int32_t *__restrict__ oi,
+                                                    int32_t *__restrict__ cand,
+                                                    float *__restrict__ thr,
+                                                    int32_t *__restrict__ bad_rows,
+                                                    int32_t *__restrict__ bad_count)
+{
+    int64_t lrow = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    int lane = threadIdx.x % WAVE;
+    if (lrow >= M) return;
+    const int64_t row = row0 + lrow;
+    const int n = ocnt[lrow];
+    float ld = INFINITY;
+    int li = 0x7fffffff;
+    if (n > cap) {
+        if (lane == 0) {
+            int p = atomicAdd(bad_count, 1);
+            bad_rows[p] = (int32_t)row;
+        }
+    } else {
+        for (int c0 = 0; c0 < n; c0 += 64) {
+            ListEntry e = merge_list(ld, li, od + lrow * cap + c0, oi + lrow * cap + c0, min(64, n - c0),
+                                     lane);
+            ld = e.d;
+            li = e.i;
+        }
+    }
+    cand[row * KNN_CAND + lane] = li == 0x7fffffff ? -1 : li;
+    float th = __shfl(ld, 63);
+    if (lane == 0) thr[row] = th;
+}
+
+template <int KS>
+static void launch_cand(dim3 g, dim3 b, hipStream_t s, const uint16_t *Qh, const uint16_t *Ql,
+                        const float *Qn, int64_t M, const uint16_t *Xh, const uint16_t *Xl,
+                        const float *Xn, int64_t N, int ex, int sl, int win, const int32_t *qpos,
+                        int32_t *cand, float *thr)
+{
+    hipLaunchKernelGGL(k_knn_cand<KS>, g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, win, qpos, cand,
+                       thr);
+}
+
+template <int KS>
+static void launch_filter(dim3 g, dim3 b, hipStream_t s, const uint16_t *Qh, const uint16_t *Ql,
+                          const float *Qn, int64_t M, const uint16_t *Xh, const uint16_t *Xl,
+                          const float *Xn, int64_t N, int ex, int64_t row0, const float *T, int cap,
+                          int32_t *ocnt, float *od, int32_t *oi)
+{
+    hipLaunchKernelGGL(k_knn_filter<KS>, g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, row0, T, cap, ocnt,
+                       od, oi);
+}
+
+__global__ void k_widen(float *__restrict__ T, int64_t M)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) {
+        float t = T[i];
+        T[i] = t + fabsf(t) * 1e-5f + 1e-30f;
+    }
+}
+
+#define KNN_DISPATCH(FN, ...)                                                                      \
+    switch (dp) {                                                                                  \
+    case 16: FN<1>(__VA_ARGS__); break;                                                            \
+    case 32: FN<2>(__VA_ARGS__); break;                                                            \
+    case 48: FN<3>(__VA_ARGS__); break;                                                            \
+    case 64: FN<4>(__VA_ARGS__); break;                                                            \
+    case 80: FN<5>(__VA_ARGS__); break;                                                            \
+    case 96: FN<6>(__VA_ARGS__); break;                                                            \
+    case 112: FN<7>(__VA_ARGS__); break;                                                           \
+    default: FN<8>(__VA_ARGS__); break;                                                            \
+    }
+
 void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int64_t M,
                     const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int dp,
-                    bool exclude_self, int32_t *cand, float *thr, hipStream_t s)
+                    bool exclude_self, bool start_local, int32_t *cand, float *thr,
+                    int32_t *bad_rows, int32_t *bad_count, hipStream_t s)
 {
     dim3 grid((unsigned)((M + KB_M - 1) / KB_M)), block(256);
-    int ex = exclude_self ? 1 : 0;
-    switch (dp) {
-    case 16: hipLaunchKernelGGL(k_knn_cand<1>, grid, block, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, cand, thr); break;
-    case 32: hipLaunchKernelGGL(k_knn_cand<2>, grid, block, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, cand, thr); break;
-    case 48: hipLaunchKernelGGL(k_knn_cand<3>, grid, block, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, cand, thr); break;
-    case 64: hipLaunchKernelGGL(k_knn_cand<4>, grid, block, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, cand, thr); break;
-    case 80: hipLaunchKernelGGL(k_knn_cand<5>, grid, block, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, cand, thr); break;
-    case 96: hipLaunchKernelGGL(k_knn_cand<6>, grid, block, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, cand, thr); break;
-    case 112: hipLaunchKernelGGL(k_knn_cand<7>, grid, block, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, cand, thr); break;
-    case 128: hipLaunchKernelGGL(k_knn_cand<8>, grid, block, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, cand, thr); break;
-    default:
-        hipLaunchKernelGGL(k_knn_cand_wide, grid, block, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, dp, ex,
+    int ex = exclude_self ? 1 : 0, sl = start_local ? 1 : 0;
+    const int64_t ntiles = (N + KB_N - 1) / KB_N;
+    if (dp > 128) {
+        hipLaunchKernelGGL(k_knn_cand_wide, grid, block, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, dp, ex, sl,
                            cand, thr);
+        HIPC(hipGetLastError());
+        return;
     }
-    HIPC(hipGetLastError());
+    constexpr int WIN = 64;                 // window tiles (4096 points)
+    constexpr int CAP = 1024;               // filter output per row
+    constexpr int64_t CHUNK = 1 << 20;      // query rows per filter pass (bounds the buffers)
+    if (!start_local || ntiles <= 4 * WIN) {
+        KNN_DISPATCH(launch_cand, grid, block, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, 0,
+                     (const int32_t *)nullptr, cand, thr);
+        HIPC(hipGetLastError());
+        return;
+    }
+    // window pass: thr = 64th approximate distance among 4096 tree-order neighbours
+    KNN_DISPATCH(launch_cand, grid, block, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, WIN,
+                 (const int32_t *)nullptr, cand, thr);
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M);
+    const int64_t mc = std::min<int64_t>(M, CHUNK);
+    int32_t *ocnt, *oi, *retry;
+    float *od;
+    HIPC(hipMallocAsync((void **)&ocnt, sizeof(int32_t) * mc, s));
+    HIPC(hipMallocAsync((void **)&od, sizeof(float) * mc * CAP, s));
+    HIPC(hipMallocAsync((void **)&oi, sizeof(int32_t) * mc * CAP, s));
+    HIPC(hipMallocAsync((void **)&retry, sizeof(int32_t) * (M + 1), s));
+    HIPC(hipMemsetAsync(retry, 0, sizeof(int32_t), s));
+    for (int64_t r0 = 0; r0 < M; r0 += CHUNK) {
+        const int64_t m = std::min<int64_t>(CHUNK, M - r0);
+        dim3 g((unsigned)((m + KB_M - 1) / KB_M));
+        HIPC(hipMemsetAsync(ocnt, 0, sizeof(int32_t) * m, s));
+        KNN_DISPATCH(launch_filter, g, block, s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, CAP, ocnt, od,
+                     oi);
+        hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, CAP, ocnt,
+                           od, oi, cand, thr, retry + 1, retry);
+        HIPC(hipGetLastError());
+    }
+    // rows whose segment overflowed: full list sweep on the compacted rows
+    int32_t nretry = 0;
+    HIPC(hipMemcpyAsync(&nretry, retry, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (nretry > 0) {
+        dim3 g((unsigned)((nretry + KB_M - 1) / KB_M));
+        KNN_DISPATCH(launch_cand, g, block, s, Qh, Ql, Qn, (int64_t)nretry, Xh, Xl, Xn, N, ex, sl, 0,
+                     (const int32_t *)(retry + 1), cand, thr);
+        HIPC(hipGetLastError());
+    }
+    HIPC(hipFreeAsync(ocnt, s));
+    HIPC(hipFreeAsync(od, s));
+    HIPC(hipFreeAsync(oi, s));
+    HIPC(hipFreeAsync(retry, s));
+    (void)bad_rows;
+    (void)bad_count;
 }
 
 // ---------------------------------------------------------------- refine
@@ -422,15 +764,19 @@ __device__ __forceinline__ bool lt_di(double d1, int i1, double d2, int i2)
     return d1 < d2 || (d1 == d2 && i1 < i2);
 }
 
-// One wave per query row: exact distances of the 64 candidates, sorted by
-// (D, id); kappa first kept; certificate against the approximate threshold.
+// One wave per query row: exact distances of the 64 candidates (reference
+// positions), sorted by (D, point id) with id = idmap[position]; the kappa
+// first are written as point ids to output row rowmap[row] (identity when
+// NULL); certificate against the approximate threshold.
 __global__ __launch_bounds__(256) void k_knn_refine(const float *__restrict__ Q, int64_t M,
                                                     const float *__restrict__ X, int64_t N, int d,
                                                     int dp, int kappa,
                                                     const int32_t *__restrict__ cand,
                                                     const float *__restrict__ thr,
                                                     const float *__restrict__ Qn, double maxnorm,
-                                                    double gamma, int32_t *__restrict__ idx,
+                                                    double gamma, const int32_t *__restrict__ idmap,
+                                                    const int32_t *__restrict__ rowmap,
+                                                    int32_t *__restrict__ idx,
                                                     double *__restrict__ dist,
                                                     int32_t *__restrict__ bad_rows,
                                                     int32_t *__restrict__ bad_count)
@@ -440,8 +786,12 @@ __global__ __launch_bounds__(256) void k_knn_refine(const float *__restrict__ Q,
     if (row >= M) return;
     int j = cand[row * KNN_CAND + lane];
     double D = INFINITY;
-    if (j >= 0 && j < N) D = canon_sqdist(Q + row * dp, X + (int64_t)j * dp, d);
-    else j = 0x7fffffff;
+    if (j >= 0 && j < N) {
+        D = canon_sqdist(Q + row * dp, X + (int64_t)j * dp, d);
+        j = idmap[j];
+    } else {
+        j = 0x7fffffff;
+    }
 #pragma unroll
     for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
@@ -454,9 +804,10 @@ __global__ __launch_bounds__(256) void k_knn_refine(const float *__restrict__ Q,
             if (take) { D = od; j = oj; }
         }
     }
+    const int64_t orow = rowmap ? rowmap[row] : row;
     if (lane < kappa) {
-        idx[row * kappa + lane] = j;
-        dist[row * kappa + lane] = D;
+        idx[orow * kappa + lane] = j;
+        dist[orow * kappa + lane] = D;
     }
     double Dk = __shfl(D, kappa - 1);
     double th = (double)thr[row];
@@ -470,16 +821,15 @@ __global__ __launch_bounds__(256) void k_knn_refine(const float *__restrict__ Q,
 
 void knn_refine(const float *Q, int64_t M, const float *X, int64_t N, int d, int dp, int kappa,
                 const int32_t *cand, const float *thr, const float *Qn, float maxnorm,
-                bool exclude_self, int32_t *idx, double *dist, int32_t *bad_rows,
-                int32_t *bad_count, hipStream_t s)
+                const int32_t *idmap, const int32_t *rowmap, int32_t *idx, double *dist,
+                int32_t *bad_rows, int32_t *bad_count, hipStream_t s)
 {
-    (void)exclude_self;
     // |approx - exact| <= g (|q|^2 + |x|^2) with g = 3.1 2^-16 (hi/lo split) +
-    // (4 dp + 4) 2^-24 (FP32 accumulation, norms, final combine); doubled.
-    double g = 2.0 * (3.1 * ldexp(1.0, -16) + (4.0 * dp + 4.0) * ldexp(1.0, -24));
+    // (4 dp + 8) 2^-24 (FP32 accumulation, norms, final combine); doubled.
+    double g = 2.0 * (3.1 * ldexp(1.0, -16) + (4.0 * dp + 8.0) * ldexp(1.0, -24));
     hipLaunchKernelGGL(k_knn_refine, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, s, Q, M, X, N, d,
-                       dp, kappa, cand, thr, Qn, (double)maxnorm * (1.0 + 1e-5), g, idx, dist,
-                       bad_rows, bad_count);
+                       dp, kappa, cand, thr, Qn, (double)maxnorm * (1.0 + 1e-5), g, idmap, rowmap, idx,
+                       dist, bad_rows, bad_count);
     HIPC(hipGetLastError());
 }
 
@@ -493,6 +843,8 @@ __global__ __launch_bounds__(KX_T) void k_knn_exact(const float *__restrict__ Qb
                                                     const float *__restrict__ X, int64_t N, int d,
                                                     int dp, int kappa, int excl,
                                                     const int32_t *__restrict__ rows,
+                                                    const int32_t *__restrict__ idmap,
+                                                    const int32_t *__restrict__ rowmap,
                                                     int32_t *__restrict__ idx,
                                                     double *__restrict__ dist)
 {
@@ -511,15 +863,16 @@ __global__ __launch_bounds__(KX_T) void k_knn_exact(const float *__restrict__ Qb
     for (int64_t j = tid; j < N; j += KX_T) {
         if (excl && j == row) continue;
         double D = canon_sqdist(q, X + j * dp, d);
-        if (!lt_di(D, (int)j, md[kappa - 1], mi[kappa - 1])) continue;
+        const int id = idmap[j];
+        if (!lt_di(D, id, md[kappa - 1], mi[kappa - 1])) continue;
         int p = kappa - 1;
-        while (p > 0 && lt_di(D, (int)j, md[p - 1], mi[p - 1])) {
+        while (p > 0 && lt_di(D, id, md[p - 1], mi[p - 1])) {
             md[p] = md[p - 1];
             mi[p] = mi[p - 1];
             --p;
         }
         md[p] = D;
-        mi[p] = (int)j;
+        mi[p] = id;
     }
     __syncthreads();
     for (int st = 1; st < KX_T; st <<= 1) {
@@ -541,20 +894,21 @@ __global__ __launch_bounds__(KX_T) void k_knn_exact(const float *__restrict__ Qb
         __syncthreads();
     }
     if (tid < kappa) {
-        idx[row * kappa + tid] = li[tid];
-        dist[row * kappa + tid] = ld[tid];
+        const int64_t orow = rowmap ? rowmap[row] : row;
+        idx[orow * kappa + tid] = li[tid];
+        dist[orow * kappa + tid] = ld[tid];
     }
 }
 
 void knn_exact_rows(const float *Q, const float *X, int64_t N, int d, int dp, int kappa,
-                    bool exclude_self, const int32_t *rows, int nrows, int32_t *idx, double *dist,
-                    hipStream_t s)
+                    bool exclude_self, const int32_t *rows, int nrows, const int32_t *idmap,
+                    const int32_t *rowmap, int32_t *idx, double *dist, hipStream_t s)
 {
     if (nrows <= 0) return;
     if (kappa > KX_K) fail(ASKIT_ERR_UNSUPPORTED, "kappa above 64 is not supported");
     size_t sh = (size_t)KX_T * kappa * (sizeof(double) + sizeof(int));
     hipLaunchKernelGGL(k_knn_exact, dim3(nrows), dim3(KX_T), sh, s, Q, X, N, d, dp, kappa,
-                       exclude_self ? 1 : 0, rows, idx, dist);
+                       exclude_self ? 1 : 0, rows, idmap, rowmap, idx, dist);
     HIPC(hipGetLastError());
 }
 

@@ -40,28 +40,76 @@ __global__ void k_cols(const Node *__restrict__ nodes, const int32_t *__restrict
     if (threadIdx.x == 0) ncols[a] = n;
 }
 
-// G[q][c][t] = exp(-D(x_T[t], x_C[c]) / (2 h_c^2)), FP64.  Block per (column, node).
-__global__ __launch_bounds__(256) void k_form_G(const float *__restrict__ Xt, int dp, int d,
-                                                const int32_t *__restrict__ ids,
-                                                const int32_t *__restrict__ T,
-                                                const int32_t *__restrict__ T_cnt, int ell,
-                                                const int32_t *__restrict__ colpos,
-                                                const int32_t *__restrict__ ncols, int ncol_max,
-                                                const double *__restrict__ hpos, double h,
-                                                double *__restrict__ G)
+// G[q][c][t] = exp(-D(x_T[t], x_C[c]) / (2 h_c^2)), FP64.  Block per (node,
+// chunk of FG_C columns): the sampled-row points and the chunk's column points
+// are staged in LDS FG_K dimensions at a time; every thread keeps the partial
+// canonical distances of its (row, column) pairs and adds the dimensions in
+// increasing order, so D is the same sequential FP64 sum as everywhere else.
+constexpr int FG_T = 256;
+constexpr int FG_C = 8;           // columns per block
+constexpr int FG_K = 32;          // dimensions per LDS stage
+constexpr int FG_MAXROW = 1024;
+
+// PP: (row, column) pairs per thread, >= rows * FG_C / FG_T
+template <int PP>
+__global__ __launch_bounds__(FG_T) void k_form_G(const float *__restrict__ Xt, int dp, int d,
+                                                 const int32_t *__restrict__ ids,
+                                                 const int32_t *__restrict__ T,
+                                                 const int32_t *__restrict__ T_cnt, int ell,
+                                                 const int32_t *__restrict__ colpos,
+                                                 const int32_t *__restrict__ ncols, int ncol_max,
+                                                 const double *__restrict__ hpos, double h,
+                                                 double *__restrict__ G)
 {
-    int c = blockIdx.x, q = blockIdx.y, a = ids[q];
-    if (c >= ncols[a]) return;
-    int rows = T_cnt[a];
-    int32_t cpos = colpos[(int64_t)q * ncol_max + c];
-    const float *xc = Xt + (int64_t)cpos * dp;
-    double hc = hpos ? hpos[cpos] : h;
-    double den = 2.0 * hc * hc;
-    double *g = G + ((int64_t)q * ncol_max + c) * ell;
-    for (int t = threadIdx.x; t < rows; t += blockDim.x) {
-        int32_t tp = T[(int64_t)a * ell + t];
-        double D = canon_sqdist(Xt + (int64_t)tp * dp, xc, d);
-        g[t] = exp(-D / den);
+#pragma clang fp contract(off)
+    extern __shared__ float fsm[];
+    const int q = blockIdx.y, a = ids[q];
+    const int c0 = blockIdx.x * FG_C;
+    const int nc = min(FG_C, ncols[a] - c0);
+    if (nc <= 0) return;
+    const int rows = T_cnt[a];
+    float *sT = fsm;                           // rows x FG_K
+    float *sC = fsm + (size_t)rows * FG_K;     // FG_C x FG_K
+    const int npair = rows * nc;
+    double acc[PP];
+#pragma unroll
+    for (int u = 0; u < PP; ++u) acc[u] = 0.0;
+    for (int k0 = 0; k0 < d; k0 += FG_K) {
+        const int kk = min(FG_K, d - k0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < rows * FG_K; e += FG_T) {
+            int t = e / FG_K, j = e % FG_K;
+            sT[e] = j < kk ? Xt[(int64_t)T[(int64_t)a * ell + t] * dp + k0 + j] : 0.0f;
+        }
+        for (int e = threadIdx.x; e < nc * FG_K; e += FG_T) {
+            int c = e / FG_K, j = e % FG_K;
+            sC[e] = j < kk ? Xt[(int64_t)colpos[(int64_t)q * ncol_max + c0 + c] * dp + k0 + j] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PP; ++u) {
+            const int pi = threadIdx.x + FG_T * u;
+            if (pi < npair) {
+                const int t = pi % rows, c = pi / rows;
+                const float *x = sT + t * FG_K, *y = sC + c * FG_K;
+                double s = acc[u];
+                for (int j = 0; j < kk; ++j) {
+                    double df = (double)x[j] - (double)y[j];
+                    s += df * df;
+                }
+                acc[u] = s;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+        const int pi = threadIdx.x + FG_T * u;
+        if (pi < npair) {
+            const int t = pi % rows, c = pi / rows;
+            const int32_t cpos = colpos[(int64_t)q * ncol_max + c0 + c];
+            const double hc = hpos ? hpos[cpos] : h;
+            G[((int64_t)q * ncol_max + c0 + c) * ell + t] = exp(-acc[u] / (2.0 * hc * hc));
+        }
     }
 }
 
@@ -72,10 +120,19 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-constexpr int QR_T = 256;
+constexpr int QR_T = 512;
 constexpr int QR_MAXCOL = 2048;
 constexpr int QR_MAXROW = 1024;
 
+__device__ __forceinline__ double group16_sum(double v)
+{
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// One block per node.  Every wave works on 4 columns at a time, 16 lanes per
+// column, so each wave keeps 4 columns' loads in flight.
 __global__ __launch_bounds__(QR_T) void k_qrcp(double *__restrict__ Gall, int ell, int ncol_max,
                                                const int32_t *__restrict__ ids,
                                                const int32_t *__restrict__ T_cnt,
@@ -88,17 +145,21 @@ __global__ __launch_bounds__(QR_T) void k_qrcp(double *__restrict__ Gall, int el
     __shared__ double v[QR_MAXROW];
     __shared__ double rd[QR_T / 64];
     __shared__ int ri[QR_T / 64];
-    __shared__ double sh_beta;
+    constexpr int NW = QR_T / 64;              // waves
+    constexpr int CG = NW * 4;                 // columns in flight per block
     const int q = blockIdx.x, a = ids[q];
     const int rows = T_cnt[a], cols = ncols[a];
     const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+    const int g16 = lane >> 4, l16 = lane & 15;
     double *G = Gall + (int64_t)q * ncol_max * ell;
     for (int c = tid; c < cols; c += QR_T) piv[c] = c;
-    for (int c = wv; c < cols; c += QR_T / 64) {
+    for (int cb = 0; cb < cols; cb += CG) {
+        const int c = cb + wv * 4 + g16;
         double s = 0.0;
-        for (int i = lane; i < rows; i += 64) s += G[(int64_t)c * ell + i] * G[(int64_t)c * ell + i];
-        s = wave_sum(s);
-        if (lane == 0) nrm2[c] = s;
+        if (c < cols)
+            for (int i = l16; i < rows; i += 16) s += G[(int64_t)c * ell + i] * G[(int64_t)c * ell + i];
+        s = group16_sum(s);
+        if (c < cols && l16 == 0) nrm2[c] = s;
     }
     __syncthreads();
     const double teff = tau > TAU_FLOOR ? tau : TAU_FLOOR;
@@ -123,7 +184,7 @@ __global__ __launch_bounds__(QR_T) void k_qrcp(double *__restrict__ Gall, int el
         __syncthreads();
         bv = rd[0];
         bi = ri[0];
-        for (int w = 1; w < QR_T / 64; ++w)
+        for (int w = 1; w < NW; ++w)
             if (rd[w] > bv || (rd[w] == bv && ri[w] < bi)) { bv = rd[w]; bi = ri[w]; }
         const double nrm = sqrt(bv);
         bool stop = false;
@@ -135,7 +196,6 @@ __global__ __launch_bounds__(QR_T) void k_qrcp(double *__restrict__ Gall, int el
             stop = true;
         }
         if (stop) break;
-        // swap columns t and bi
         if (bi != t) {
             for (int i = tid; i < rows; i += QR_T) {
                 double x = G[(int64_t)t * ell + i];
@@ -154,27 +214,29 @@ __global__ __launch_bounds__(QR_T) void k_qrcp(double *__restrict__ Gall, int el
         const double beta = (rtt - x0) / rtt;
         for (int i = t + 1 + tid; i < rows; i += QR_T) v[i] = G[(int64_t)t * ell + i] / denom;
         __syncthreads();
-        if (tid == 0) {
-            G[(int64_t)t * ell + t] = rtt;
-            sh_beta = beta;
-        }
+        if (tid == 0) G[(int64_t)t * ell + t] = rtt;
         for (int i = t + 1 + tid; i < rows; i += QR_T) G[(int64_t)t * ell + i] = 0.0;
         // apply the reflector to the trailing columns and recompute their norms
-        for (int c = t + 1 + wv; c < cols; c += QR_T / 64) {
-            double *gc = G + (int64_t)c * ell;
+        for (int cb = t + 1; cb < cols; cb += CG) {
+            const int c = cb + wv * 4 + g16;
+            const bool on = c < cols;
+            double *gc = G + (int64_t)(on ? c : t) * ell;
             double s = 0.0;
-            for (int i = t + 1 + lane; i < rows; i += 64) s += v[i] * gc[i];
-            s = wave_sum(s) + gc[t];
-            const double f = beta * s;
+            if (on)
+                for (int i = t + 1 + l16; i < rows; i += 16) s += v[i] * gc[i];
+            s = group16_sum(s);
+            const double top = on ? gc[t] : 0.0;
+            const double f = beta * (s + top);
             double ns = 0.0;
-            for (int i = t + 1 + lane; i < rows; i += 64) {
-                double y = gc[i] - f * v[i];
-                gc[i] = y;
-                ns += y * y;
-            }
-            ns = wave_sum(ns);
-            if (lane == 0) {
-                gc[t] -= f;
+            if (on)
+                for (int i = t + 1 + l16; i < rows; i += 16) {
+                    double y = gc[i] - f * v[i];
+                    gc[i] = y;
+                    ns += y * y;
+                }
+            ns = group16_sum(ns);
+            if (on && l16 == 0) {
+                gc[t] = top - f;
                 nrm2[c] = ns;
             }
         }
@@ -184,22 +246,43 @@ __global__ __launch_bounds__(QR_T) void k_qrcp(double *__restrict__ Gall, int el
     if (tid == 0) kout[a] = k;
 }
 
-// P = R11^{-1} R12 in place over R12 (FP64).  Thread per column of R12.
-__global__ __launch_bounds__(256) void k_solve(double *__restrict__ Gall, int ell, int ncol_max,
-                                               const int32_t *__restrict__ ids,
-                                               const int32_t *__restrict__ ncols,
-                                               const int32_t *__restrict__ skk)
+// P = R11^{-1} R12 in place over R12 (FP64).  Block per (node, chunk of SV_C
+// columns of R12): the chunk is held in LDS and solved right-looking: for
+// t = k-1 .. 0, P[t] = R12'[t] / R_tt, then R12'[u] -= R_ut P[t] for u < t.
+constexpr int SV_T = 256;
+constexpr int SV_C = 16;
+
+__global__ __launch_bounds__(SV_T) void k_solve(double *__restrict__ Gall, int ell, int ncol_max,
+                                                const int32_t *__restrict__ ids,
+                                                const int32_t *__restrict__ ncols,
+                                                const int32_t *__restrict__ skk)
 {
+    extern __shared__ double sP[];             // k x SV_C
     const int q = blockIdx.y, a = ids[q];
     const int k = skk[a], n = ncols[a];
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n - k) return;
+    const int c0 = blockIdx.x * SV_C;
+    const int cw = min(SV_C, n - k - c0);
+    if (cw <= 0 || k == 0) return;
     double *G = Gall + (int64_t)q * ncol_max * ell;
-    double *pc = G + (int64_t)(k + c) * ell;        // column k+c: rows 0..k-1 = R12, becomes P
+    for (int e = threadIdx.x; e < k * SV_C; e += SV_T) {
+        int c = e / k, t = e % k;
+        sP[t * SV_C + c] = c < cw ? G[(int64_t)(k + c0 + c) * ell + t] : 0.0;
+    }
+    __syncthreads();
     for (int t = k - 1; t >= 0; --t) {
-        double s = pc[t];
-        for (int u = t + 1; u < k; ++u) s -= G[(int64_t)u * ell + t] * pc[u];
-        pc[t] = s / G[(int64_t)t * ell + t];
+        const double rtt = G[(int64_t)t * ell + t];
+        if (threadIdx.x < SV_C) sP[t * SV_C + threadIdx.x] /= rtt;
+        __syncthreads();
+        const double *rcol = G + (int64_t)t * ell;     // R[u][t], u < t
+        for (int e = threadIdx.x; e < t * SV_C; e += SV_T) {
+            int u = e / SV_C, c = e % SV_C;
+            sP[u * SV_C + c] -= rcol[u] * sP[t * SV_C + c];
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < k * SV_C; e += SV_T) {
+        int c = e / k, t = e % k;
+        if (c < cw) G[(int64_t)(k + c0 + c) * ell + t] = sP[t * SV_C + c];
     }
 }
 
@@ -241,7 +324,7 @@ void skeletonize(askit_handle *h, hipStream_t s)
 {
     const int nn = (int)h->nodes.size();
     const int ell = h->ell, ncm = h->ncol_max, smax = h->smax;
-    if (ncm > QR_MAXCOL || ell > QR_MAXROW)
+    if (ncm > QR_MAXCOL || ell > QR_MAXROW || ell > FG_MAXROW)
         fail(ASKIT_ERR_UNSUPPORTED, "ID block larger than 1024 rows x 2048 columns");
     HIPC(hipMemsetAsync(h->skk, 0, sizeof(int32_t) * nn, s));
     HIPC(hipMemsetAsync(h->ncols, 0, sizeof(int32_t) * nn, s));
@@ -264,6 +347,17 @@ void skeletonize(askit_handle *h, hipStream_t s)
         gather_f64(h->hsrc, h->perm, h->N, hp_tmp, s);
         hpos = hp_tmp;
     }
+    const size_t fg_lds = sizeof(float) * ((size_t)ell + FG_C) * FG_K;
+    const size_t sv_lds = sizeof(double) * (size_t)std::min(smax, ell) * SV_C;
+    if (fg_lds > 64 * 1024) {
+        HIPC(hipFuncSetAttribute((const void *)k_form_G<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)fg_lds));
+        HIPC(hipFuncSetAttribute((const void *)k_form_G<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)fg_lds));
+    }
+    if (sv_lds > 64 * 1024)
+        HIPC(hipFuncSetAttribute((const void *)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sv_lds));
     std::vector<int32_t> ids;
     hipEvent_t q0, q1;
     HIPC(hipEventCreate(&q0));
@@ -278,14 +372,28 @@ void skeletonize(askit_handle *h, hipStream_t s)
             HIPC(hipMemcpyAsync(d_ids, ids.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_cols, dim3(nb), dim3(256), 0, s, h->d_nodes, d_ids, smax, ncm, h->S,
                                h->skk, colpos, h->ncols);
-            hipLaunchKernelGGL(k_form_G, dim3(ncm, nb), dim3(256), 0, s, h->Xt, h->dp, h->d, d_ids,
-                               h->T, h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
+            {
+                dim3 gg((ncm + FG_C - 1) / FG_C, nb), gb(FG_T);
+                const int pp = (ell * FG_C + FG_T - 1) / FG_T;
+                if (pp <= 4)
+                    hipLaunchKernelGGL(k_form_G<4>, gg, gb, fg_lds, s, h->Xt, h->dp, h->d, d_ids, h->T,
+                                       h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
+                else if (pp <= 8)
+                    hipLaunchKernelGGL(k_form_G<8>, gg, gb, fg_lds, s, h->Xt, h->dp, h->d, d_ids, h->T,
+                                       h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
+                else if (pp <= 16)
+                    hipLaunchKernelGGL(k_form_G<16>, gg, gb, fg_lds, s, h->Xt, h->dp, h->d, d_ids, h->T,
+                                       h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
+                else
+                    hipLaunchKernelGGL(k_form_G<32>, gg, gb, fg_lds, s, h->Xt, h->dp, h->d, d_ids, h->T,
+                                       h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
+            }
             HIPC(hipEventRecord(q0, s));
             hipLaunchKernelGGL(k_qrcp, dim3(nb), dim3(QR_T), 0, s, G, ell, ncm, d_ids, h->T_cnt,
                                h->ncols, smax, h->prm.id_tol, h->colperm, h->skk);
             HIPC(hipEventRecord(q1, s));
-            hipLaunchKernelGGL(k_solve, dim3((ncm + 255) / 256, nb), dim3(256), 0, s, G, ell, ncm,
-                               d_ids, h->ncols, h->skk);
+            hipLaunchKernelGGL(k_solve, dim3((ncm + SV_C - 1) / SV_C, nb), dim3(SV_T), sv_lds, s, G, ell,
+                               ncm, d_ids, h->ncols, h->skk);
             hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(256), 0, s, G, ell, ncm, d_ids, colpos,
                                h->ncols, h->skk, h->colperm, smax, h->d_pslot, h->Xt, h->dp, h->gt,
                                h->S, h->P, h->Xs, h->gs);
@@ -340,29 +448,28 @@ __global__ __launch_bounds__(64) void k_upward(const Node *__restrict__ nodes,
     }
 }
 
-void upward(askit_handle *h, hipStream_t s)
+void prepare_upward(askit_handle *h)
 {
-    const int nn = (int)h->nodes.size();
-    if (h->depth == 0) return;
-    int32_t *d_ids;
-    HIPC(hipMallocAsync((void **)&d_ids, sizeof(int32_t) * nn, s));
-    // all level lists packed once, launched bottom-up
     std::vector<int32_t> all;
-    std::vector<std::pair<int, int>> seg;
+    h->up_seg.clear();
     for (int lev = h->depth; lev >= 1; --lev) {
-        seg.push_back({(int)all.size(), (int)h->level_nodes[lev].size()});
+        h->up_seg.push_back({(int)all.size(), (int)h->level_nodes[lev].size()});
         all.insert(all.end(), h->level_nodes[lev].begin(), h->level_nodes[lev].end());
     }
-    HIPC(hipMemcpyAsync(d_ids, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice, s));
-    for (auto &sg : seg) {
+    h->up_ids = (int32_t *)h->alloc(sizeof(int32_t) * std::max<size_t>(all.size(), 1), false);
+    if (!all.empty())
+        HIPC(hipMemcpy(h->up_ids, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice));
+}
+
+void upward(askit_handle *h, const WeightSet &ws, hipStream_t s)
+{
+    for (auto &sg : h->up_seg) {
         if (sg.second == 0) continue;
         hipLaunchKernelGGL(k_upward, dim3(sg.second, h->smax), dim3(64), 0, s, h->d_nodes,
-                           d_ids + sg.first, h->skk, h->ncols, h->colperm, h->ncol_max, h->d_pslot,
-                           h->P, h->smax, h->Wt, h->nrhs, h->Wsk);
+                           h->up_ids + sg.first, h->skk, h->ncols, h->colperm, h->ncol_max, h->d_pslot,
+                           h->P, h->smax, ws.Wt, ws.R, ws.Wsk);
         HIPC(hipGetLastError());
     }
-    HIPC(hipStreamSynchronize(s));
-    HIPC(hipFreeAsync(d_ids, s));
 }
 
 }  // namespace askit

@@ -32,6 +32,8 @@ CASES = {
     "varh": (2500, 16, 4, 1, O.Params(m=64, kappa=16, smax=32, ell=52, tau=1e-5, h=0.0, bw_neighbor=16,
                                       seed=11)),
     "d40": (3000, 40, 5, 6, O.Params(m=96, kappa=12, smax=48, ell=68, tau=1e-5, h=1.5, seed=3)),
+    # above 64 reference tiles: window pass + filter sweep + select path of the kNN
+    "filter-path": (20000, 24, 4, 8, O.Params(m=256, kappa=32, smax=64, ell=84, tau=1e-5, h=1.0, seed=9)),
 }
 
 
@@ -182,3 +184,36 @@ def test_edge_sizes(N, m, kappa):
     Ud = O.direct(X, X, W, p.h)
     if m >= N or kappa == N - 1:
         assert rel(g["U"][:, 0], Ud[:, 0]) < U_TOL
+
+
+@pytest.mark.parametrize("d", [40, 200])
+def test_bf16x3_precision_form(d):
+    """Distances as bf16 hi/lo split products (FP32 accumulation, FP64
+    combine): the same structures as the FP32 form, u within 1e-4."""
+    import torch
+    from paper_1410_0260_amd import askit as A
+    N = 3000
+    X = synth.mixture_points(N, d, 5, 6, 1e-3, 40 + d)
+    W = synth.weights(N, 3, 41)
+    p = O.Params(m=96, kappa=12, smax=48, ell=68, tau=1e-5, h=1.5 if d == 40 else 2.5, seed=3)
+    st, g = run_both(X, W, p, gparams(p, precision=A.PREC_BF16X3))
+    assert np.array_equal(g["perm"], st["perm"]) and np.array_equal(g["knn_idx"], st["knn_idx"])
+    for r in range(W.shape[1]):
+        assert rel(g["U"][:, r], st["ev"].U[:, r]) < 1e-4
+
+
+def test_many_rhs_blocks():
+    """nrhs = 11 runs as blocks of 8 and 3 columns; each column equals its own run."""
+    import torch
+    from paper_1410_0260_amd import askit as A
+    N, d = 2500, 20
+    X = synth.mixture_points(N, d, 4, 3, 1e-3, 8)
+    W = synth.weights(N, 11, 8)
+    p = O.Params(m=64, kappa=10, smax=32, ell=52, tau=1e-6, h=1.0, seed=6)
+    st = O.run_askit(X, W, p, record=False)
+    h = A.setup(torch.from_numpy(X).cuda(), gparams(p))
+    h.update_weights(torch.from_numpy(W).cuda())
+    U = h.evaluate().cpu().numpy().astype(np.float64)
+    h.close()
+    for r in range(11):
+        assert rel(U[:, r], st["ev"].U[:, r]) < U_TOL
