@@ -137,8 +137,10 @@ typedef struct {
     int64_t knn_uncertified_rows;        /* rows that needed the exact fallback */
     double t_knn_ms, t_tree_ms, t_lists_ms, t_skel_ms, t_inter_ms; /* last setup, per phase */
     double t_update_ms;                  /* last update_weights */
-    double t_knn_sweep_ms;               /* last setup: the approximate kNN sweep kernel alone */
+    double t_knn_sweep_ms;               /* last setup: approximate kNN candidates (window, filter, select) */
     double t_qr_ms;                      /* last setup: the QR kernels alone (all levels) */
+    double t_knn_filter_ms;              /* last setup: the kNN filter sweep launches alone (sum) */
+    int64_t knn_filter_launches;         /* ... and their number */
 } askit_info;
 
 askit_status askit_get_info(const askit_handle *h, askit_info *out);
@@ -177,6 +179,134 @@ typedef enum {
  * the size needed (call with dst = NULL to query it). */
 askit_status askit_export(const askit_handle *h, int32_t what, void *dst, size_t cap,
                           size_t *bytes);
+
+/* ---------------------------------------------------------------------------
+ * Serving.  A server keeps one setup resident (tree, skeletons, P_alpha and
+ * interaction lists stay in device memory) and answers two kinds of request
+ * with continuous batching:
+ *   - weights: u = K w at all N points for the request's own weights (the
+ *     per-iteration cost that setup amortizes, Sec. 5);
+ *   - query:   u at M new points for the resident weights W0.
+ * Requests are admitted against a device-memory budget; pending requests of
+ * one kind are batched (weight columns side by side, query points stacked)
+ * and run by `workers` threads, each on its own stream, so batches overlap on
+ * the device.  Results are independent of the batch a request rides in: a
+ * weight request's columns are bit-identical to running it alone, a query's
+ * values agree to FP32 rounding (its slab of targets may differ).
+ * ------------------------------------------------------------------------- */
+typedef struct askit_server askit_server;
+
+typedef struct {
+    uint32_t struct_size;       /* sizeof(askit_server_config) */
+    int32_t workers;            /* concurrent batches, 1..16 */
+    int32_t max_batch_rhs;      /* weight columns per batch, 1..64 */
+    int32_t max_batch_queries;  /* query points per batch, >= 1 */
+    uint64_t mem_budget;        /* device bytes for in-flight requests (0: 8 GiB) */
+} askit_server_config;
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t deferred;           /* requests that reached the queue head and waited for memory */
+    int64_t batches, batched_requests;
+    double p50_ms, p99_ms, mean_ms;                 /* submit -> result ready, all requests */
+    double p50_weights_ms, p99_weights_ms, p50_query_ms, p99_query_ms;
+    double targets_rhs;         /* sum over completed requests of targets x RHS */
+    double busy_s;              /* wall time from first submit to last completion */
+    uint64_t peak_mem;          /* largest admitted total */
+} askit_serving_stats;
+
+/* Fills *c with defaults: 2 workers, 64 columns, 65536 points, 8 GiB. */
+askit_status askit_server_config_default(askit_server_config *c);
+
+/* Creates a server over a set-up handle (the handle must outlive the server
+ * and must not be used by the caller meanwhile).  W0 (device, N x nrhs0,
+ * original point order, row stride ldw0) are the resident weights of query
+ * requests; they are copied. */
+askit_status askit_server_create(askit_handle *h, const float *W0, int64_t ldw0, int32_t nrhs0,
+                                 const askit_server_config *cfg, askit_server **out);
+
+/* Weight request: W (device, N x nrhs, stride ldw) in, U (device, N x nrhs,
+ * stride ldu) out.  Both must stay valid until the request completes, and W
+ * must already hold its values (work that writes it has finished): the
+ * server reads it on its own streams, unordered with the caller's.
+ * ASKIT_ERR_OUT_OF_MEMORY if the request alone exceeds the budget. */
+askit_status askit_server_submit_weights(askit_server *s, const float *W, int64_t ldw, int32_t nrhs,
+                                         float *U, int64_t ldu, uint64_t *ticket);
+
+/* Query request: Y (device, M x d, stride ldy) in, U (device, M x nrhs0,
+ * stride ldu) out; valid until completion, Y already written (as above). */
+askit_status askit_server_submit_query(askit_server *s, const float *Y, int64_t M, int64_t ldy,
+                                       float *U, int64_t ldu, uint64_t *ticket);
+
+/* *state: 0 pending, 1 done, -1 failed (askit_last_error() then describes the failure). */
+askit_status askit_server_poll(askit_server *s, uint64_t ticket, int32_t *state);
+/* Waits up to timeout_s seconds (< 0: no limit). */
+askit_status askit_server_wait(askit_server *s, uint64_t ticket, double timeout_s, int32_t *state);
+askit_status askit_server_stats(askit_server *s, askit_serving_stats *out);
+/* Finishes pending requests, then stops the workers and frees the server. */
+void askit_server_destroy(askit_server *s);
+
+/* ---------------------------------------------------------------------------
+ * Batched form.  Many independent problems (each with its own N and d, the
+ * same parameters) behind one handle, for workloads of many small instances
+ * where one launch per instance would leave the device idle.  The work per
+ * weight vector (permutation, upward pass, evaluation: the per-iteration cost
+ * of Sec. 5 that setup amortizes) runs as a few launches over all instances;
+ * every instance's result is the one askit_setup/askit_update_weights/
+ * askit_evaluate give for it alone (same kernels, same arithmetic).
+ *
+ * Row layout: W and U hold the rows of instance 0, then instance 1, ... in
+ * each instance's original point order (instance i starts at row
+ * N_0 + ... + N_{i-1}); nrhs columns, row strides ldw / ldu.
+ * ------------------------------------------------------------------------- */
+typedef struct askit_batch askit_batch;
+
+typedef struct {
+    int32_t count, nrhs;
+    int64_t total_points, total_slabs;
+    int64_t near_entries, far_entries, near_pairs, far_pairs;
+    double t_setup_ms;
+    int32_t tuned;              /* 1 once a launch shape is chosen for nrhs */
+    int32_t launch_blocks;      /* chosen shape: 0 = one workgroup per slab, else persistent grid size */
+    double candidate_ms[4];     /* evaluation time of: one workgroup per slab; persistent 2, 4, 8 per CU */
+    int32_t graphs;             /* cached graphs of askit_batch_run */
+} askit_batch_info;
+
+/* Sets up `count` instances: X[i] (device, N[i] x d[i], row stride ldx[i])
+ * with the parameters *p.  Synchronises `stream` (the point sets must be
+ * written), then builds the instances several at a time on worker streams;
+ * the point sets are copied.  Errors name the failing instance. */
+askit_status askit_batch_setup(int32_t count, const float *const *X, const int64_t *N, const int32_t *d,
+                               const int64_t *ldx, const askit_params *p, void *stream, askit_batch **out);
+
+/* Skeleton weights of every instance from W (device, rows as above). */
+askit_status askit_batch_update_weights(askit_batch *b, const float *W, int64_t ldw, int32_t nrhs,
+                                        void *stream);
+
+/* u of every instance into U (device, rows as above).  Uses the launch shape
+ * the tuner chose for nrhs, else one workgroup per slab. */
+askit_status askit_batch_evaluate(askit_batch *b, float *U, int64_t ldu, void *stream);
+
+/* update_weights + evaluate as one HIP graph, replayed on `stream`.  The first
+ * call for an nrhs times the evaluation's launch shapes (eagerly, on
+ * `stream`) and keeps the fastest; the graph is captured once per (W, ldw,
+ * nrhs, U, ldu) and replayed afterwards, so later calls must pass buffers
+ * that are still allocated (new values in the same buffers are fine). */
+askit_status askit_batch_run(askit_batch *b, const float *W, int64_t ldw, int32_t nrhs, float *U, int64_t ldu,
+                             void *stream);
+
+/* Fixes the evaluation's launch shape for nrhs instead of timing them:
+ * blocks = 0 for one workgroup per slab, else the persistent grid size
+ * (1 .. 64 x compute units).  Graphs captured before keep their shape. */
+askit_status askit_batch_set_launch(askit_batch *b, int32_t nrhs, int32_t blocks);
+
+askit_status askit_batch_get_info(const askit_batch *b, askit_batch_info *out);
+
+/* Instance i's handle (owned by the batch; for exports and queries), NULL if out of range. */
+askit_handle *askit_batch_instance(askit_batch *b, int32_t i);
+
+/* Waits for the device, then frees the batch and its instances. */
+void askit_batch_destroy(askit_batch *b);
 
 #ifdef __cplusplus
 }

@@ -45,7 +45,8 @@ class Info(C.Structure):
                 ("knn_uncertified_rows", C.c_int64), ("t_knn_ms", C.c_double),
                 ("t_tree_ms", C.c_double), ("t_lists_ms", C.c_double), ("t_skel_ms", C.c_double),
                 ("t_inter_ms", C.c_double), ("t_update_ms", C.c_double),
-                ("t_knn_sweep_ms", C.c_double), ("t_qr_ms", C.c_double)]
+                ("t_knn_sweep_ms", C.c_double), ("t_qr_ms", C.c_double),
+                ("t_knn_filter_ms", C.c_double), ("knn_filter_launches", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -167,7 +168,8 @@ class Handle:
 
     def close(self):
         if self.ptr:
-            lib().askit_destroy(self.ptr)
+            if getattr(self, "owned", True):
+                lib().askit_destroy(self.ptr)
             self.ptr = None
 
     def __del__(self):
@@ -217,3 +219,253 @@ def setup(X, params: Params) -> Handle:
                            _stream(torch), C.byref(h))
     _check(rc)
     return Handle(h, N, d)
+
+
+# ----------------------------------------------------------------- serving
+class ServerConfig(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("workers", C.c_int32), ("max_batch_rhs", C.c_int32),
+                ("max_batch_queries", C.c_int32), ("mem_budget", C.c_uint64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("deferred", C.c_int64), ("batches", C.c_int64), ("batched_requests", C.c_int64),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
+                ("p50_weights_ms", C.c_double), ("p99_weights_ms", C.c_double),
+                ("p50_query_ms", C.c_double), ("p99_query_ms", C.c_double),
+                ("targets_rhs", C.c_double), ("busy_s", C.c_double), ("peak_mem", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+SERVER_EXPORTED = ["askit_server_config_default", "askit_server_create", "askit_server_submit_weights",
+                   "askit_server_submit_query", "askit_server_poll", "askit_server_wait",
+                   "askit_server_stats", "askit_server_destroy"]
+EXPORTED += SERVER_EXPORTED
+
+
+def _server_lib():
+    L = lib()
+    if not getattr(L, "_server_ready", False):
+        P, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.askit_server_config_default.argtypes = [C.POINTER(ServerConfig)]
+        L.askit_server_create.argtypes = [P, P, i64, i32, C.POINTER(ServerConfig), C.POINTER(P)]
+        L.askit_server_submit_weights.argtypes = [P, P, i64, i32, P, i64, C.POINTER(C.c_uint64)]
+        L.askit_server_submit_query.argtypes = [P, P, i64, i64, P, i64, C.POINTER(C.c_uint64)]
+        L.askit_server_poll.argtypes = [P, C.c_uint64, C.POINTER(i32)]
+        L.askit_server_wait.argtypes = [P, C.c_uint64, C.c_double, C.POINTER(i32)]
+        L.askit_server_stats.argtypes = [P, C.POINTER(ServerStats)]
+        L.askit_server_destroy.argtypes = [P]
+        L.askit_server_destroy.restype = None
+        for f in SERVER_EXPORTED[:-1]:
+            getattr(L, f).restype = C.c_int
+        L._server_ready = True
+    return L
+
+
+def server_config(**kw) -> ServerConfig:
+    c = ServerConfig()
+    _check(_server_lib().askit_server_config_default(C.byref(c)))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def _input_ready(torch):
+    """Waits for the work queued so far on the caller's stream (which wrote
+    the request's input), and for nothing else: a stream synchronisation of
+    the legacy default stream would also wait for the server's own streams."""
+    ev = torch.cuda.Event()
+    ev.record(torch.cuda.current_stream())
+    ev.synchronize()
+
+
+class Server:
+    """Continuous-batching server over a set-up handle (see include/askit.h).
+    Device tensors passed to submit_* must stay alive until the request is done;
+    the server keeps references to them until then."""
+
+    def __init__(self, handle: Handle, W0, cfg: ServerConfig | None = None):
+        import torch
+        self.h = handle
+        self.W0 = _dev_f32(torch, W0)
+        self.nrhs0 = self.W0.shape[1]
+        cfg = cfg or server_config()
+        p = C.c_void_p()
+        _check(_server_lib().askit_server_create(handle.ptr, C.c_void_p(self.W0.data_ptr()),
+                                                 self.W0.stride(0), self.nrhs0, C.byref(cfg), C.byref(p)))
+        self.ptr = p
+        self._keep = {}
+
+    def submit_weights(self, W, out=None):
+        import torch
+        Wd = _dev_f32(torch, W)
+        U = out if out is not None else torch.empty_like(Wd)
+        _input_ready(torch)   # the server reads W on its own streams
+        t = C.c_uint64()
+        _check(_server_lib().askit_server_submit_weights(self.ptr, C.c_void_p(Wd.data_ptr()), Wd.stride(0),
+                                                         Wd.shape[1], C.c_void_p(U.data_ptr()), U.stride(0),
+                                                         C.byref(t)))
+        self._keep[t.value] = (Wd, U)
+        return t.value
+
+    def submit_query(self, Y, out=None):
+        import torch
+        Yd = _dev_f32(torch, Y)
+        U = out if out is not None else torch.empty((Yd.shape[0], self.nrhs0), device="cuda",
+                                                     dtype=torch.float32)
+        _input_ready(torch)
+        t = C.c_uint64()
+        _check(_server_lib().askit_server_submit_query(self.ptr, C.c_void_p(Yd.data_ptr()), Yd.shape[0],
+                                                       Yd.stride(0), C.c_void_p(U.data_ptr()), U.stride(0),
+                                                       C.byref(t)))
+        self._keep[t.value] = (Yd, U)
+        return t.value
+
+    def poll(self, ticket) -> int:
+        st = C.c_int32()
+        _check(_server_lib().askit_server_poll(self.ptr, ticket, C.byref(st)))
+        return st.value
+
+    def wait(self, ticket, timeout_s=-1.0):
+        """Returns the output tensor of a finished request (raises if it failed)."""
+        st = C.c_int32()
+        _check(_server_lib().askit_server_wait(self.ptr, ticket, timeout_s, C.byref(st)))
+        if st.value < 0:
+            raise AskitError(ERR_DEVICE, lib().askit_last_error().decode())
+        if st.value == 0:
+            raise TimeoutError(f"request {ticket} still pending")
+        return self._keep.pop(ticket)[1]
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(_server_lib().askit_server_stats(self.ptr, C.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if self.ptr:
+            _server_lib().askit_server_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------- batched form
+class BatchInfo(C.Structure):
+    _fields_ = [("count", C.c_int32), ("nrhs", C.c_int32), ("total_points", C.c_int64),
+                ("total_slabs", C.c_int64), ("near_entries", C.c_int64), ("far_entries", C.c_int64),
+                ("near_pairs", C.c_int64), ("far_pairs", C.c_int64), ("t_setup_ms", C.c_double),
+                ("tuned", C.c_int32), ("launch_blocks", C.c_int32), ("candidate_ms", C.c_double * 4),
+                ("graphs", C.c_int32)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["candidate_ms"] = list(self.candidate_ms)
+        return d
+
+
+BATCH_EXPORTED = ["askit_batch_setup", "askit_batch_update_weights", "askit_batch_evaluate", "askit_batch_run",
+                  "askit_batch_get_info", "askit_batch_instance", "askit_batch_destroy",
+                  "askit_batch_set_launch"]
+EXPORTED += BATCH_EXPORTED
+
+
+def _batch_lib():
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        P, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.askit_batch_setup.argtypes = [i32, P, P, P, P, C.POINTER(Params), P, C.POINTER(P)]
+        L.askit_batch_update_weights.argtypes = [P, P, i64, i32, P]
+        L.askit_batch_evaluate.argtypes = [P, P, i64, P]
+        L.askit_batch_run.argtypes = [P, P, i64, i32, P, i64, P]
+        L.askit_batch_get_info.argtypes = [P, C.POINTER(BatchInfo)]
+        L.askit_batch_set_launch.argtypes = [P, i32, i32]
+        L.askit_batch_instance.argtypes = [P, i32]
+        L.askit_batch_instance.restype = P
+        L.askit_batch_destroy.argtypes = [P]
+        L.askit_batch_destroy.restype = None
+        for f in ("askit_batch_setup", "askit_batch_update_weights", "askit_batch_evaluate", "askit_batch_run",
+                  "askit_batch_get_info", "askit_batch_set_launch"):
+            getattr(L, f).restype = C.c_int
+        L._batch_ready = True
+    return L
+
+
+class Batch:
+    """Many independent problems behind one handle (see include/askit.h).
+    W and U stack the instances' rows in order (instance i from offsets[i])."""
+
+    def __init__(self, Xs, params: Params):
+        import torch
+        ts = [_dev_f32(torch, X) for X in Xs]
+        n = len(ts)
+        ptrs = (C.c_void_p * n)(*[t.data_ptr() for t in ts])
+        Ns = (C.c_int64 * n)(*[t.shape[0] for t in ts])
+        ds = (C.c_int32 * n)(*[t.shape[1] for t in ts])
+        lds = (C.c_int64 * n)(*[t.stride(0) for t in ts])
+        p = C.c_void_p()
+        _check(_batch_lib().askit_batch_setup(n, ptrs, Ns, ds, lds, C.byref(params), _stream(torch),
+                                              C.byref(p)))
+        self.ptr = p
+        self.sizes = [t.shape[0] for t in ts]
+        self.dims = [t.shape[1] for t in ts]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        self.rows = int(self.offsets[-1])
+        self.nrhs = 0
+
+    def update_weights(self, W):
+        import torch
+        Wd = _dev_f32(torch, W)
+        assert Wd.shape[0] == self.rows
+        _check(_batch_lib().askit_batch_update_weights(self.ptr, C.c_void_p(Wd.data_ptr()), Wd.stride(0),
+                                                       Wd.shape[1], _stream(torch)))
+        self.nrhs = Wd.shape[1]
+
+    def evaluate(self, out=None):
+        import torch
+        U = out if out is not None else torch.empty((self.rows, self.nrhs), device="cuda", dtype=torch.float32)
+        _check(_batch_lib().askit_batch_evaluate(self.ptr, C.c_void_p(U.data_ptr()), U.stride(0),
+                                                 _stream(torch)))
+        return U
+
+    def run(self, W, out):
+        """update_weights + evaluate through the cached graph; W and out are
+        device tensors that must stay allocated while the batch may replay them."""
+        import torch
+        assert torch.is_tensor(W) and W.is_cuda and W.dtype == torch.float32 and W.shape[0] == self.rows
+        _check(_batch_lib().askit_batch_run(self.ptr, C.c_void_p(W.data_ptr()), W.stride(0), W.shape[1],
+                                            C.c_void_p(out.data_ptr()), out.stride(0), _stream(torch)))
+        self.nrhs = W.shape[1]
+        return out
+
+    def set_launch(self, nrhs, blocks):
+        _check(_batch_lib().askit_batch_set_launch(self.ptr, nrhs, blocks))
+
+    def info(self) -> dict:
+        i = BatchInfo()
+        _check(_batch_lib().askit_batch_get_info(self.ptr, C.byref(i)))
+        return i.as_dict()
+
+    def instance(self, i) -> Handle:
+        hp = _batch_lib().askit_batch_instance(self.ptr, i)
+        if not hp:
+            raise IndexError(i)
+        h = Handle(C.c_void_p(hp), self.sizes[i], self.dims[i])
+        h.owned = False
+        return h
+
+    def close(self):
+        if self.ptr:
+            _batch_lib().askit_batch_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -86,6 +86,16 @@ __global__ void k_map_pos(const int32_t *__restrict__ ids, int64_t n, const int3
     if (i < n) out[i] = iperm[ids[i]];
 }
 
+void permute_rows(const float *W, int64_t ldw, const int32_t *gperm, int64_t rows, int R, float *Wt,
+                  hipStream_t s)
+{
+    const int64_t tot = rows * R;
+    if (tot == 0) return;
+    hipLaunchKernelGGL(k_permute_w, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, W, ldw, gperm, rows,
+                       R, Wt);
+    HIPC(hipGetLastError());
+}
+
 void permute_weights(askit_handle *h, const float *W, int64_t ldw, WeightSet &ws, hipStream_t s)
 {
     int64_t tot = h->N * ws.R;
@@ -200,7 +210,7 @@ void *askit_handle::alloc(size_t bytes, bool zero)
     void *p = nullptr;
     HIPC(hipMalloc(&p, std::max<size_t>(bytes, 16)));
     allocs.push_back(p);
-    if (zero) HIPC(hipMemset(p, 0, std::max<size_t>(bytes, 16)));
+    if (zero) HIPC(hipMemsetAsync(p, 0, std::max<size_t>(bytes, 16), astream));
     return p;
 }
 
@@ -315,6 +325,7 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
     hipStream_t s = (hipStream_t)stream;
 
     std::unique_ptr<askit_handle> h(new askit_handle());
+    h->astream = s;
     HIPC(hipGetDevice(&h->device));
     h->N = N;
     h->d = d;
@@ -406,8 +417,10 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
         HIPC(hipEventCreate(&k0));
         HIPC(hipEventCreate(&k1));
         HIPC(hipEventRecord(k0, s));
+        float fms = 0.f;
         knn_candidates(h->Xh, h->Xl, h->Xn, N, h->Xh, h->Xl, h->Xn, N, dp, true, true, cand, thr,
-                       bad + 1, bad, s);
+                       bad + 1, bad, s, &fms, &h->knn_filter_launches);
+        h->t_knn_filter = fms;
         HIPC(hipEventRecord(k1, s));
         knn_refine(h->Xt, N, h->Xt, N, d, dp, kappa, cand, thr, h->Xn, mx, h->perm, h->perm,
                    h->knn_idx, h->knn_d, bad + 1, bad, s);
@@ -471,6 +484,7 @@ askit_status askit_update_weights(askit_handle *h, const float *W, int64_t ldw, 
     const int64_t nn = (int64_t)h->nodes.size();
     if (nrhs > h->wcap) {
         HIPC(hipStreamSynchronize(s));
+        h->astream = s;
         auto drop = [&](void *p) {
             if (!p) return;
             (void)hipFree(p);
@@ -567,6 +581,8 @@ askit_status askit_get_info(const askit_handle *h, askit_info *o)
     }
     o->t_update_ms = h->t_update;
     o->t_knn_sweep_ms = h->t_knn_sweep;
+    o->t_knn_filter_ms = h->t_knn_filter;
+    o->knn_filter_launches = h->knn_filter_launches;
     o->t_qr_ms = h->t_qr;
     API_END
 }

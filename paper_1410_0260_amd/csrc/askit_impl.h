@@ -142,12 +142,14 @@ struct askit_handle {
     // diagnostics
     int64_t near_pairs = 0, far_pairs = 0, knn_uncertified = 0;
     double t_knn = 0, t_tree = 0, t_lists = 0, t_skel = 0, t_inter = 0, t_update = 0;
-    double t_knn_sweep = 0, t_qr = 0;
+    double t_knn_sweep = 0, t_qr = 0, t_knn_filter = 0;
+    int knn_filter_launches = 0;
     hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr;
     bool up_pending = false;
 
     ~askit_handle();
     void *alloc(size_t bytes, bool zero = true);
+    hipStream_t astream = nullptr;     // stream that orders alloc's zero fill (the calling API's)
 };
 
 namespace askit {
@@ -168,7 +170,8 @@ void gather_rows(const float *src, const int32_t *idx, int64_t n, int dp, float 
 void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int64_t M,
                     const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int dp,
                     bool exclude_self, bool start_local, int32_t *cand, float *thr,
-                    int32_t *bad_rows, int32_t *bad_count, hipStream_t s);
+                    int32_t *bad_rows, int32_t *bad_count, hipStream_t s,
+                    float *t_filter_ms = nullptr, int *n_filter = nullptr);
 void knn_refine(const float *Q, int64_t M, const float *X, int64_t N, int d, int dp, int kappa,
                 const int32_t *cand, const float *thr, const float *Qn, float maxnorm,
                 const int32_t *idmap, const int32_t *rowmap, int32_t *idx, double *dist,
@@ -214,6 +217,49 @@ struct EvalArgs {
     int64_t ldu;
 };
 void evaluate(askit_handle *h, const WeightSet &ws, const EvalArgs &a, hipStream_t s);
+
+// ---------------------------------------------------------------- batched form
+// One entry per instance of a batch (device tables).  Weights of all
+// instances live in shared buffers: the instance's tree-order weights start
+// at row wt_off (times R) and its skeleton weights at slot wsk_off (times R).
+struct EvalInst {
+    const Node *nodes;
+    const float *Y, *Xt, *gt, *Xs, *gs;
+    const int32_t *skk;
+    const int32_t *outmap;     // batch output row of each tree position of the instance
+    int64_t wt_off, wsk_off;
+    int smax, dp;
+};
+struct UpInst {
+    const Node *nodes;
+    const int32_t *skk, *ncols, *colperm;
+    const int64_t *pslot;
+    const float *P;
+    int64_t wt_off, wsk_off;
+    int ncol_max, smax;
+};
+struct BatchEvalArgs {
+    const EvalInst *inst;
+    const Slab *slabs;         // pad = instance
+    const int32_t *ptr, *node; // CSR over all slabs, near then far (as EvalArgs)
+    const uint64_t *mask;
+    int64_t nslab;
+    const float *Wt, *Wsk;
+    float *U;
+    int64_t ldu;
+    int R;
+    bool bf;
+    int persistent;            // 0: one workgroup per slab; else the persistent grid size
+    const int32_t *order;      // persistent: slab of each queue item
+    int32_t *queue;            // persistent: one counter per RHS pass
+};
+void evaluate_batch(const BatchEvalArgs &b, hipStream_t s);
+// One launch per level (deepest first): items are (instance, node) pairs.
+void upward_batch(const UpInst *inst, const int2 *items, const std::vector<std::pair<int64_t, int64_t>> &levels,
+                  int smax, const float *Wt, float *Wsk, int R, hipStream_t s);
+// Wt[t, r] = W[gperm[t], r] over all rows of a batch (gperm: original row of tree row t).
+void permute_rows(const float *W, int64_t ldw, const int32_t *gperm, int64_t rows, int R, float *Wt,
+                  hipStream_t s);
 // queries at M new points against the weights ws (U: M x ws.R, row stride ldu)
 void query_points(askit_handle *h, const WeightSet &ws, const float *Y, int64_t M, int64_t ldy,
                   float *U, int64_t ldu, hipStream_t s);

@@ -1,0 +1,501 @@
+// Batched form: many independent problems (uneven sizes and dimensions)
+// behind one handle.
+//
+// Setup runs the single-problem setup of every instance, several at a time
+// on worker threads with their own streams.  The per-weight-vector work of
+// all instances is then fused: one permutation launch over all rows, one
+// upward launch per tree level across every instance (deepest level first,
+// so each instance still sees its children before its parents), and one
+// evaluation launch over the slabs of every instance, reading each slab's
+// instance tables from a device array.  The evaluation runs either as one
+// workgroup per slab or as a persistent grid that takes
+// slabs from a work queue in decreasing cost order; a small autotuner times
+// these launch shapes once per right-hand-side count and keeps the fastest.
+// askit_batch_run captures the whole weights -> u sequence in a HIP graph
+// (kernels only: the queue counters are cleared by a kernel) and replays it.
+#include "askit_impl.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <thread>
+
+using namespace askit;
+
+namespace askit {
+extern thread_local std::string g_err;
+}
+
+namespace {
+
+constexpr int MAX_PASSES = (MAX_RHS + 7) / 8;     // RHS passes of the evaluation (8 columns each)
+constexpr int NUM_CAND = 4;                       // launch shapes tried by the tuner
+constexpr int CAND_BLOCKS_PER_CU[NUM_CAND] = {0, 2, 4, 8};   // 0: one workgroup per slab
+
+struct GraphEntry {
+    const float *W;
+    int64_t ldw;
+    int R;
+    float *U;
+    int64_t ldu;
+    int blocks;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+// Launch shapes already chosen in this process, by problem class.
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, std::vector<double>>> g_tune_cache;
+
+}  // namespace
+
+struct askit_batch {
+    std::vector<askit_handle *> inst;
+    int device = 0;
+    int num_cu = 256;
+    askit_params prm{};
+    int smax = 0;
+    int64_t rows = 0, wsk_slots = 0, nslab = 0, ne = 0, fe = 0;
+    int64_t near_pairs = 0, far_pairs = 0;
+    double t_setup_ms = 0.0;
+    std::vector<void *> own;
+
+    EvalInst *d_einst = nullptr;
+    UpInst *d_uinst = nullptr;
+    int2 *d_items = nullptr;
+    std::vector<std::pair<int64_t, int64_t>> levels;
+    Slab *d_slabs = nullptr;
+    int32_t *d_ptr = nullptr, *d_node = nullptr, *d_order = nullptr, *d_queue = nullptr, *d_outrow = nullptr;
+    uint64_t *d_mask = nullptr;
+
+    float *Wt = nullptr, *Wsk = nullptr;
+    int wcap = 0, R = 0;
+
+    int blocks_for_R[MAX_RHS + 1] = {};      // -1: not tuned
+    std::vector<double> cand_ms[MAX_RHS + 1];
+    std::string tune_key_base;
+
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap = nullptr;
+
+    void *dev(size_t bytes)
+    {
+        void *p = nullptr;
+        HIPC(hipMalloc(&p, std::max<size_t>(bytes, 16)));
+        own.push_back(p);
+        return p;
+    }
+    void drop_graphs()
+    {
+        for (auto &g : graphs) {
+            (void)hipGraphExecDestroy(g.exec);
+            (void)hipGraphDestroy(g.graph);
+        }
+        graphs.clear();
+    }
+    ~askit_batch()
+    {
+        (void)hipDeviceSynchronize();
+        drop_graphs();
+        if (cap) (void)hipStreamDestroy(cap);
+        for (void *p : own) (void)hipFree(p);
+        if (Wt) (void)hipFree(Wt);
+        if (Wsk) (void)hipFree(Wsk);
+        for (auto *h : inst) askit_destroy(h);
+    }
+    BatchEvalArgs eval_args(float *U, int64_t ldu, int blocks) const
+    {
+        BatchEvalArgs a{};
+        a.inst = d_einst;
+        a.slabs = d_slabs;
+        a.ptr = d_ptr;
+        a.node = d_node;
+        a.mask = d_mask;
+        a.nslab = nslab;
+        a.Wt = Wt;
+        a.Wsk = Wsk;
+        a.U = U;
+        a.ldu = ldu;
+        a.R = R;
+        a.bf = prm.precision == ASKIT_PREC_BF16X3;
+        a.persistent = blocks;
+        a.order = d_order;
+        a.queue = d_queue;
+        return a;
+    }
+    void update(const float *W, int64_t ldw, hipStream_t s)
+    {
+        permute_rows(W, ldw, d_outrow, rows, R, Wt, s);
+        upward_batch(d_uinst, d_items, levels, smax, Wt, Wsk, R, s);
+    }
+};
+
+#define API_BEGIN                                                                                 \
+    try {                                                                                         \
+        g_err.clear();
+#define API_END                                                                                   \
+    }                                                                                             \
+    catch (const Error &e)                                                                        \
+    {                                                                                             \
+        g_err = e.msg;                                                                            \
+        return e.code;                                                                            \
+    }                                                                                             \
+    catch (...)                                                                                   \
+    {                                                                                             \
+        g_err = "internal error";                                                                 \
+        return ASKIT_ERR_DEVICE;                                                                  \
+    }                                                                                             \
+    return ASKIT_OK;
+
+static void ensure_weights(askit_batch *b, int R, hipStream_t s)
+{
+    if (R > b->wcap) {
+        HIPC(hipStreamSynchronize(s));
+        b->drop_graphs();
+        if (b->Wt) HIPC(hipFree(b->Wt));
+        if (b->Wsk) HIPC(hipFree(b->Wsk));
+        b->Wt = b->Wsk = nullptr;
+        HIPC(hipMalloc((void **)&b->Wt, sizeof(float) * std::max<int64_t>(b->rows * R, 4)));
+        HIPC(hipMalloc((void **)&b->Wsk, sizeof(float) * std::max<int64_t>(b->wsk_slots * R, 4)));
+        b->wcap = R;
+    }
+    b->R = R;
+}
+
+// Times every launch shape of the evaluation for the current R (the weights
+// must be in place) and keeps the fastest; all shapes give identical results.
+static void autotune(askit_batch *b, float *U, int64_t ldu, hipStream_t s)
+{
+    const int R = b->R;
+    const std::string key = b->tune_key_base + "/R" + std::to_string(R);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            b->blocks_for_R[R] = it->second.first;
+            b->cand_ms[R] = it->second.second;
+            return;
+        }
+    }
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    std::vector<double> ms(NUM_CAND, 0.0);
+    int best = 0;
+    for (int c = 0; c < NUM_CAND; ++c) {
+        const int blocks = CAND_BLOCKS_PER_CU[c] * b->num_cu;
+        const BatchEvalArgs a = b->eval_args(U, ldu, blocks);
+        evaluate_batch(a, s);                        // warm-up
+        std::vector<float> t;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPC(hipEventRecord(e0, s));
+            evaluate_batch(a, s);
+            HIPC(hipEventRecord(e1, s));
+            HIPC(hipEventSynchronize(e1));
+            float v = 0.f;
+            HIPC(hipEventElapsedTime(&v, e0, e1));
+            t.push_back(v);
+        }
+        std::sort(t.begin(), t.end());
+        ms[c] = t[1];
+        if (ms[c] < ms[best]) best = c;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->blocks_for_R[R] = CAND_BLOCKS_PER_CU[best] * b->num_cu;
+    b->cand_ms[R] = ms;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {b->blocks_for_R[R], ms};
+}
+
+extern "C" {
+
+askit_status askit_batch_setup(int32_t count, const float *const *X, const int64_t *N, const int32_t *d,
+                               const int64_t *ldx, const askit_params *p, void *stream, askit_batch **out)
+{
+    API_BEGIN
+    if (!out) fail(ASKIT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1) fail(ASKIT_ERR_INVALID_ARG, "need count >= 1");
+    if (!X || !N || !d || !ldx || !p) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    for (int32_t i = 0; i < count; ++i)
+        if (!X[i]) fail(ASKIT_ERR_INVALID_ARG, "NULL point set");
+    hipStream_t s = (hipStream_t)stream;
+    HIPC(hipStreamSynchronize(s));           // the point sets are written
+    const auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<askit_batch> b(new askit_batch());
+    HIPC(hipGetDevice(&b->device));
+    hipDeviceProp_t prop;
+    HIPC(hipGetDeviceProperties(&prop, b->device));
+    b->num_cu = prop.multiProcessorCount;
+    b->prm = *p;
+    b->inst.assign(count, nullptr);
+
+    // instance setups, several at once on worker threads with their own streams
+    std::atomic<int32_t> next{0};
+    std::mutex emu;
+    askit_status first_code = ASKIT_OK;
+    std::string first_msg;
+    const int nthreads = std::min<int>(count, 8);
+    std::vector<std::thread> th;
+    for (int w = 0; w < nthreads; ++w)
+        th.emplace_back([&, dev = b->device] {
+            hipStream_t ws = nullptr;
+            if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) {
+                std::lock_guard<std::mutex> lk(emu);
+                if (first_code == ASKIT_OK) {
+                    first_code = ASKIT_ERR_DEVICE;
+                    first_msg = "worker stream creation failed";
+                }
+                return;
+            }
+            for (;;) {
+                const int32_t i = next++;
+                if (i >= count) break;
+                askit_handle *h = nullptr;
+                askit_status rc = askit_setup(X[i], N[i], d[i], ldx[i], p, ws, &h);
+                if (rc != ASKIT_OK) {
+                    std::lock_guard<std::mutex> lk(emu);
+                    if (first_code == ASKIT_OK) {
+                        first_code = rc;
+                        first_msg = "instance " + std::to_string(i) + ": " + askit_last_error();
+                    }
+                    next = count;
+                    break;
+                }
+                b->inst[i] = h;
+            }
+            (void)hipStreamSynchronize(ws);
+            (void)hipStreamDestroy(ws);
+        });
+    for (auto &t : th) t.join();
+    if (first_code != ASKIT_OK) fail(first_code, first_msg);
+
+    // host tables
+    const int smax = b->inst[0]->smax;
+    b->smax = smax;
+    std::vector<int64_t> row_off(count + 1, 0), wsk_off(count + 1, 0), ns_off(count + 1, 0), ne_off(count + 1, 0),
+        fe_off(count + 1, 0);
+    int maxdepth = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const askit_handle *h = b->inst[i];
+        row_off[i + 1] = row_off[i] + h->N;
+        wsk_off[i + 1] = wsk_off[i] + (int64_t)h->nodes.size() * h->smax;
+        ns_off[i + 1] = ns_off[i] + (int64_t)h->slabs.size();
+        ne_off[i + 1] = ne_off[i] + h->near_entries;
+        fe_off[i + 1] = fe_off[i] + h->far_entries;
+        maxdepth = std::max(maxdepth, h->depth);
+        b->near_pairs += h->near_pairs;
+        b->far_pairs += h->far_pairs;
+    }
+    if (row_off[count] >= (1ll << 31)) fail(ASKIT_ERR_UNSUPPORTED, "batch above 2^31 points");
+    if (ne_off[count] + fe_off[count] >= (1ll << 31)) fail(ASKIT_ERR_UNSUPPORTED, "batch lists exceed 2^31 entries");
+    b->rows = row_off[count];
+    b->wsk_slots = wsk_off[count];
+    b->nslab = ns_off[count];
+    b->ne = ne_off[count];
+    b->fe = fe_off[count];
+    const int64_t S = b->nslab;
+
+    std::vector<int32_t> outrow(b->rows);
+    std::vector<Slab> slabs(S);
+    std::vector<int32_t> ptr(2 * S + 2);
+    std::vector<int64_t> cost(S);
+    std::vector<EvalInst> einst(count);
+    std::vector<UpInst> uinst(count);
+    b->d_node = (int32_t *)b->dev(sizeof(int32_t) * (b->ne + b->fe));
+    b->d_mask = (uint64_t *)b->dev(sizeof(uint64_t) * (b->ne + b->fe));
+    b->d_outrow = (int32_t *)b->dev(sizeof(int32_t) * b->rows);
+    for (int32_t i = 0; i < count; ++i) {
+        const askit_handle *h = b->inst[i];
+        const int64_t ns = (int64_t)h->slabs.size();
+        std::vector<int32_t> perm(h->N), hp(2 * ns + 2);
+        HIPC(hipMemcpy(perm.data(), h->perm, sizeof(int32_t) * h->N, hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(hp.data(), h->sl_ptr, sizeof(int32_t) * hp.size(), hipMemcpyDeviceToHost));
+        for (int64_t t = 0; t < h->N; ++t) outrow[row_off[i] + t] = (int32_t)(row_off[i] + perm[t]);
+        const int64_t nei = h->near_entries;
+        for (int64_t k = 0; k < ns; ++k) {
+            Slab sl = h->slabs[k];
+            sl.pad = i;
+            slabs[ns_off[i] + k] = sl;
+            ptr[ns_off[i] + k] = (int32_t)(hp[k] + ne_off[i]);
+            ptr[S + 1 + ns_off[i] + k] = (int32_t)(hp[ns + 1 + k] - nei + b->ne + fe_off[i]);
+            cost[ns_off[i] + k] = (int64_t)(hp[k + 1] - hp[k]) * h->m + (int64_t)(hp[ns + 2 + k] - hp[ns + 1 + k]) * h->smax;
+        }
+        if (nei > 0) {
+            HIPC(hipMemcpy(b->d_node + ne_off[i], h->sl_node, sizeof(int32_t) * nei, hipMemcpyDeviceToDevice));
+            HIPC(hipMemcpy(b->d_mask + ne_off[i], h->sl_mask, sizeof(uint64_t) * nei, hipMemcpyDeviceToDevice));
+        }
+        if (h->far_entries > 0) {
+            HIPC(hipMemcpy(b->d_node + b->ne + fe_off[i], h->sl_node + nei, sizeof(int32_t) * h->far_entries,
+                           hipMemcpyDeviceToDevice));
+            HIPC(hipMemcpy(b->d_mask + b->ne + fe_off[i], h->sl_mask + nei, sizeof(uint64_t) * h->far_entries,
+                           hipMemcpyDeviceToDevice));
+        }
+        einst[i] = EvalInst{h->d_nodes, h->Xt, h->Xt, h->gt, h->Xs, h->gs, h->skk, b->d_outrow + row_off[i],
+                            row_off[i], wsk_off[i], h->smax, h->dp};
+        uinst[i] = UpInst{h->d_nodes, h->skk, h->ncols, h->colperm, h->d_pslot, h->P, row_off[i], wsk_off[i],
+                          h->ncol_max, h->smax};
+    }
+    ptr[S] = (int32_t)b->ne;
+    ptr[2 * S + 1] = (int32_t)(b->ne + b->fe);
+    // upward items, deepest level first across all instances
+    std::vector<int2> items;
+    for (int lev = maxdepth; lev >= 1; --lev) {
+        const int64_t first = (int64_t)items.size();
+        for (int32_t i = 0; i < count; ++i) {
+            const askit_handle *h = b->inst[i];
+            if (lev > h->depth) continue;
+            for (int a : h->level_nodes[lev]) items.push_back(int2{i, a});
+        }
+        b->levels.push_back({first, (int64_t)items.size() - first});
+    }
+    std::vector<int32_t> order(S);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+
+    b->d_einst = (EvalInst *)b->dev(sizeof(EvalInst) * count);
+    b->d_uinst = (UpInst *)b->dev(sizeof(UpInst) * count);
+    b->d_items = (int2 *)b->dev(sizeof(int2) * std::max<size_t>(items.size(), 1));
+    b->d_slabs = (Slab *)b->dev(sizeof(Slab) * std::max<int64_t>(S, 1));
+    b->d_ptr = (int32_t *)b->dev(sizeof(int32_t) * ptr.size());
+    b->d_order = (int32_t *)b->dev(sizeof(int32_t) * std::max<int64_t>(S, 1));
+    b->d_queue = (int32_t *)b->dev(sizeof(int32_t) * MAX_PASSES);
+    HIPC(hipMemcpy(b->d_einst, einst.data(), sizeof(EvalInst) * count, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(b->d_uinst, uinst.data(), sizeof(UpInst) * count, hipMemcpyHostToDevice));
+    if (!items.empty())
+        HIPC(hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
+    if (S > 0) {
+        HIPC(hipMemcpy(b->d_slabs, slabs.data(), sizeof(Slab) * S, hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice));
+    }
+    HIPC(hipMemcpy(b->d_ptr, ptr.data(), sizeof(int32_t) * ptr.size(), hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(b->d_outrow, outrow.data(), sizeof(int32_t) * b->rows, hipMemcpyHostToDevice));
+    HIPC(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    for (int r = 0; r <= MAX_RHS; ++r) b->blocks_for_R[r] = -1;
+    // problem class of the tuner: points, slabs, list entries (rounded to powers of two), d, s, precision
+    auto lg = [](int64_t v) { int k = 0; while ((int64_t)1 << k < v) ++k; return k; };
+    int maxdp = 0;
+    for (auto *h : b->inst) maxdp = std::max(maxdp, h->dp);
+    b->tune_key_base = "n" + std::to_string(lg(b->rows)) + "s" + std::to_string(lg(S)) + "e" +
+                       std::to_string(lg(b->ne + b->fe)) + "d" + std::to_string(maxdp) + "k" + std::to_string(smax) +
+                       "p" + std::to_string((int)p->precision) + "c" + std::to_string(count);
+    HIPC(hipDeviceSynchronize());
+    b->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = b.release();
+    API_END
+}
+
+askit_status askit_batch_update_weights(askit_batch *b, const float *W, int64_t ldw, int32_t nrhs, void *stream)
+{
+    API_BEGIN
+    if (!b || !W) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    if (nrhs < 1 || nrhs > MAX_RHS) fail(ASKIT_ERR_INVALID_ARG, "need 1 <= nrhs <= 64");
+    if (ldw < nrhs) fail(ASKIT_ERR_INVALID_ARG, "need ldw >= nrhs");
+    hipStream_t s = (hipStream_t)stream;
+    ensure_weights(b, nrhs, s);
+    b->update(W, ldw, s);
+    API_END
+}
+
+askit_status askit_batch_evaluate(askit_batch *b, float *U, int64_t ldu, void *stream)
+{
+    API_BEGIN
+    if (!b || !U) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    if (b->R < 1) fail(ASKIT_ERR_NOT_READY, "askit_batch_update_weights has not been called");
+    if (ldu < b->R) fail(ASKIT_ERR_INVALID_ARG, "need ldu >= nrhs");
+    const int blocks = b->blocks_for_R[b->R];
+    evaluate_batch(b->eval_args(U, ldu, blocks > 0 ? blocks : 0), (hipStream_t)stream);
+    API_END
+}
+
+askit_status askit_batch_run(askit_batch *b, const float *W, int64_t ldw, int32_t nrhs, float *U, int64_t ldu,
+                             void *stream)
+{
+    API_BEGIN
+    if (!b || !W || !U) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    if (nrhs < 1 || nrhs > MAX_RHS) fail(ASKIT_ERR_INVALID_ARG, "need 1 <= nrhs <= 64");
+    if (ldw < nrhs || ldu < nrhs) fail(ASKIT_ERR_INVALID_ARG, "need ldw, ldu >= nrhs");
+    hipStream_t s = (hipStream_t)stream;
+    ensure_weights(b, nrhs, s);
+    if (b->blocks_for_R[nrhs] < 0) {
+        b->update(W, ldw, s);
+        autotune(b, U, ldu, s);
+    }
+    const int blocks = b->blocks_for_R[nrhs];
+    GraphEntry *ge = nullptr;
+    for (auto &g : b->graphs)
+        if (g.W == W && g.ldw == ldw && g.R == nrhs && g.U == U && g.ldu == ldu && g.blocks == blocks) ge = &g;
+    if (!ge) {
+        if (b->graphs.size() >= 8) {
+            HIPC(hipStreamSynchronize(s));
+            (void)hipGraphExecDestroy(b->graphs.front().exec);
+            (void)hipGraphDestroy(b->graphs.front().graph);
+            b->graphs.erase(b->graphs.begin());
+        }
+        GraphEntry g{W, ldw, nrhs, U, ldu, blocks, nullptr, nullptr};
+        HIPC(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        try {
+            b->update(W, ldw, b->cap);
+            evaluate_batch(b->eval_args(U, ldu, blocks), b->cap);
+        } catch (...) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(b->cap, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            throw;
+        }
+        HIPC(hipStreamEndCapture(b->cap, &g.graph));
+        HIPC(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+        b->graphs.push_back(g);
+        ge = &b->graphs.back();
+    }
+    HIPC(hipGraphLaunch(ge->exec, s));
+    API_END
+}
+
+askit_status askit_batch_set_launch(askit_batch *b, int32_t nrhs, int32_t blocks)
+{
+    API_BEGIN
+    if (!b) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    if (nrhs < 1 || nrhs > MAX_RHS) fail(ASKIT_ERR_INVALID_ARG, "need 1 <= nrhs <= 64");
+    if (blocks < 0 || blocks > 64 * b->num_cu) fail(ASKIT_ERR_INVALID_ARG, "need 0 <= blocks <= 64 x CUs");
+    b->blocks_for_R[nrhs] = blocks;
+    b->cand_ms[nrhs].clear();
+    API_END
+}
+
+askit_status askit_batch_get_info(const askit_batch *b, askit_batch_info *o)
+{
+    API_BEGIN
+    if (!b || !o) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    std::memset(o, 0, sizeof(*o));
+    o->count = (int32_t)b->inst.size();
+    o->nrhs = b->R;
+    o->total_points = b->rows;
+    o->total_slabs = b->nslab;
+    o->near_entries = b->ne;
+    o->far_entries = b->fe;
+    o->near_pairs = b->near_pairs;
+    o->far_pairs = b->far_pairs;
+    o->t_setup_ms = b->t_setup_ms;
+    const int R = b->R;
+    o->tuned = R > 0 && b->blocks_for_R[R] >= 0;
+    o->launch_blocks = o->tuned ? b->blocks_for_R[R] : 0;
+    for (int c = 0; c < NUM_CAND && o->tuned && c < (int)b->cand_ms[R].size(); ++c) o->candidate_ms[c] = b->cand_ms[R][c];
+    o->graphs = (int32_t)b->graphs.size();
+    API_END
+}
+
+askit_handle *askit_batch_instance(askit_batch *b, int32_t i)
+{
+    if (!b || i < 0 || i >= (int32_t)b->inst.size()) return nullptr;
+    return b->inst[i];
+}
+
+void askit_batch_destroy(askit_batch *b) { delete b; }
+
+}  // extern "C"

@@ -48,12 +48,17 @@ struct EvalParams {
     const float *Xs, *gs, *Wsk;  // far sources (skeletons)
     const int32_t *skk;
     int smax, dp, R, r0, rb;
+    // batched form: per-instance tables (slab.pad = instance), optional work queue
+    const EvalInst *inst;
+    const int32_t *order;      // persistent mode: item -> slab (cost order)
+    int32_t *queue;            // persistent mode: next item (zeroed before the launch)
+    int persistent;
 };
 
 // BF: distance products as bf16 hi/lo split (hi*hi + hi*lo + lo*hi) on
 // v_mfma_f32_32x32x16_bf16 with FP32 accumulation and an FP64 final combine of
 // |x|^2 + |y|^2 - 2 x.y; otherwise FP32 products on v_mfma_f32_32x32x2_f32.
-template <int RB, bool BF>
+template <int RB, bool BF, bool MULTI>
 __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
 {
     __shared__ __attribute__((aligned(16))) float sA[BF ? 16 : 64 * EV_LD];
@@ -67,10 +72,30 @@ __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
     const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
     const int half = lane >> 5, l32 = lane & 31;
     const int rq = 32 * (wv >> 1), cq = 32 * (wv & 1);
-    const int64_t slab = blockIdx.x;
+    __shared__ int64_t sItem;
+
+  auto process = [&](const int64_t slab) {
     const Slab sb = p.slabs[slab];
-    const int dp = p.dp;
-    const float *Yb = p.Y + (int64_t)sb.row0 * dp;
+    const Node *nodes = p.nodes;
+    const float *Y = p.Y, *Xt = p.Xt, *gt = p.gt, *Xs = p.Xs, *gs = p.gs, *Wt = p.Wt, *Wsk = p.Wsk;
+    const int32_t *skk = p.skk, *outmap = p.outmap;
+    int smax = p.smax, dp = p.dp;
+    if constexpr (MULTI) {
+        const EvalInst &I = p.inst[sb.pad];
+        nodes = I.nodes;
+        Y = I.Y;
+        Xt = I.Xt;
+        gt = I.gt;
+        Xs = I.Xs;
+        gs = I.gs;
+        skk = I.skk;
+        outmap = I.outmap;
+        smax = I.smax;
+        dp = I.dp;
+        Wt = p.Wt + I.wt_off * p.R;
+        Wsk = p.Wsk + I.wsk_off * p.R;
+    }
+    const float *Yb = Y + (int64_t)sb.row0 * dp;
     const int nchunk = (dp + EV_KC - 1) / EV_KC;
 
     for (int k = tid; k < dp; k += EV_T) sC[k] = Yb[k];
@@ -134,16 +159,16 @@ __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
         const float *src, *g, *w;
         int ns;
         if (near) {
-            const Node nd = p.nodes[a];
+            const Node nd = nodes[a];
             ns = nd.hi - nd.lo;
-            src = p.Xt + (int64_t)nd.lo * dp;
-            g = p.gt + nd.lo;
-            w = p.Wt + (int64_t)nd.lo * p.R;
+            src = Xt + (int64_t)nd.lo * dp;
+            g = gt + nd.lo;
+            w = Wt + (int64_t)nd.lo * p.R;
         } else {
-            ns = p.skk[a];
-            src = p.Xs + (int64_t)a * p.smax * dp;
-            g = p.gs + (int64_t)a * p.smax;
-            w = p.Wsk + (int64_t)a * p.smax * p.R;
+            ns = skk[a];
+            src = Xs + (int64_t)a * smax * dp;
+            g = gs + (int64_t)a * smax;
+            w = Wsk + (int64_t)a * smax * p.R;
         }
         float mb[16];
 #pragma unroll
@@ -237,8 +262,23 @@ __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
     for (int e = tid; e < sb.nrows * p.rb; e += EV_T) {
         int row = e / p.rb, j = e % p.rb;
         float v = sRed[0][row * RB + j] + sRed[1][row * RB + j];
-        int64_t orow = p.outmap ? p.outmap[sb.row0 + row] : (int64_t)sb.row0 + row;
+        int64_t orow = outmap ? outmap[sb.row0 + row] : (int64_t)sb.row0 + row;
         p.U[orow * p.ldu + p.r0 + j] = v;
+    }
+  };
+
+    if (!MULTI || !p.persistent) {
+        process(blockIdx.x);
+        return;
+    }
+    // persistent: take slabs from the queue (largest first) until it is empty
+    for (;;) {
+        __syncthreads();            // the previous item is done with the shared buffers
+        if (tid == 0) sItem = atomicAdd(p.queue, 1);
+        __syncthreads();
+        const int64_t item = sItem;
+        if (item >= p.nslab) break;
+        process(p.order ? (int64_t)p.order[item] : item);
     }
 }
 
@@ -266,6 +306,10 @@ void evaluate(askit_handle *h, const WeightSet &ws, const EvalArgs &a, hipStream
     p.smax = h->smax;
     p.dp = h->dp;
     p.R = ws.R;
+    p.inst = nullptr;
+    p.order = nullptr;
+    p.queue = nullptr;
+    p.persistent = 0;
     if (a.nslab == 0) return;
     const bool bf = h->prm.precision == ASKIT_PREC_BF16X3;
     for (int r0 = 0; r0 < ws.R; r0 += EV_RB) {
@@ -273,14 +317,63 @@ void evaluate(askit_handle *h, const WeightSet &ws, const EvalArgs &a, hipStream
         p.rb = std::min(EV_RB, ws.R - r0);
         dim3 g((unsigned)a.nslab), b(EV_T);
         if (p.rb == 1) {
-            if (bf) hipLaunchKernelGGL((k_eval<1, true>), g, b, 0, s, p);
-            else hipLaunchKernelGGL((k_eval<1, false>), g, b, 0, s, p);
+            if (bf) hipLaunchKernelGGL((k_eval<1, true, false>), g, b, 0, s, p);
+            else hipLaunchKernelGGL((k_eval<1, false, false>), g, b, 0, s, p);
         } else if (p.rb <= 4) {
-            if (bf) hipLaunchKernelGGL((k_eval<4, true>), g, b, 0, s, p);
-            else hipLaunchKernelGGL((k_eval<4, false>), g, b, 0, s, p);
+            if (bf) hipLaunchKernelGGL((k_eval<4, true, false>), g, b, 0, s, p);
+            else hipLaunchKernelGGL((k_eval<4, false, false>), g, b, 0, s, p);
         } else {
-            if (bf) hipLaunchKernelGGL((k_eval<EV_RB, true>), g, b, 0, s, p);
-            else hipLaunchKernelGGL((k_eval<EV_RB, false>), g, b, 0, s, p);
+            if (bf) hipLaunchKernelGGL((k_eval<EV_RB, true, false>), g, b, 0, s, p);
+            else hipLaunchKernelGGL((k_eval<EV_RB, false, false>), g, b, 0, s, p);
+        }
+        HIPC(hipGetLastError());
+    }
+}
+
+__global__ void k_zero_i32(int32_t *__restrict__ p, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+void evaluate_batch(const BatchEvalArgs &b, hipStream_t s)
+{
+    if (b.nslab == 0) return;
+    EvalParams p{};
+    p.slabs = b.slabs;
+    p.ptr = b.ptr;
+    p.node = b.node;
+    p.mask = b.mask;
+    p.nslab = b.nslab;
+    p.U = b.U;
+    p.ldu = b.ldu;
+    p.Wt = b.Wt;
+    p.Wsk = b.Wsk;
+    p.R = b.R;
+    p.inst = b.inst;
+    p.order = b.order;
+    p.persistent = b.persistent > 0;
+    const int passes = (b.R + EV_RB - 1) / EV_RB;
+    if (p.persistent) {
+        // counters are cleared by a kernel, not a memset node, so that the
+        // sequence can be captured in a graph and replayed
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, b.queue, passes);
+        HIPC(hipGetLastError());
+    }
+    for (int r0 = 0, pass = 0; r0 < b.R; r0 += EV_RB, ++pass) {
+        p.r0 = r0;
+        p.rb = std::min(EV_RB, b.R - r0);
+        p.queue = b.queue ? b.queue + pass : nullptr;
+        dim3 g((unsigned)(p.persistent ? std::min<int64_t>(b.persistent, b.nslab) : b.nslab)), blk(EV_T);
+        if (p.rb == 1) {
+            if (b.bf) hipLaunchKernelGGL((k_eval<1, true, true>), g, blk, 0, s, p);
+            else hipLaunchKernelGGL((k_eval<1, false, true>), g, blk, 0, s, p);
+        } else if (p.rb <= 4) {
+            if (b.bf) hipLaunchKernelGGL((k_eval<4, true, true>), g, blk, 0, s, p);
+            else hipLaunchKernelGGL((k_eval<4, false, true>), g, blk, 0, s, p);
+        } else {
+            if (b.bf) hipLaunchKernelGGL((k_eval<EV_RB, true, true>), g, blk, 0, s, p);
+            else hipLaunchKernelGGL((k_eval<EV_RB, false, true>), g, blk, 0, s, p);
         }
         HIPC(hipGetLastError());
     }

@@ -698,8 +698,11 @@ __global__ void k_widen(float *__restrict__ T, int64_t M)
 void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int64_t M,
                     const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int dp,
                     bool exclude_self, bool start_local, int32_t *cand, float *thr,
-                    int32_t *bad_rows, int32_t *bad_count, hipStream_t s)
+                    int32_t *bad_rows, int32_t *bad_count, hipStream_t s, float *t_filter_ms,
+                    int *n_filter)
 {
+    if (t_filter_ms) *t_filter_ms = 0.f;
+    if (n_filter) *n_filter = 0;
     dim3 grid((unsigned)((M + KB_M - 1) / KB_M)), block(256);
     int ex = exclude_self ? 1 : 0, sl = start_local ? 1 : 0;
     const int64_t ntiles = (N + KB_N - 1) / KB_N;
@@ -730,12 +733,20 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     HIPC(hipMallocAsync((void **)&oi, sizeof(int32_t) * mc * CAP, s));
     HIPC(hipMallocAsync((void **)&retry, sizeof(int32_t) * (M + 1), s));
     HIPC(hipMemsetAsync(retry, 0, sizeof(int32_t), s));
+    std::vector<hipEvent_t> ev;             // brackets of each filter launch (timing only)
     for (int64_t r0 = 0; r0 < M; r0 += CHUNK) {
         const int64_t m = std::min<int64_t>(CHUNK, M - r0);
         dim3 g((unsigned)((m + KB_M - 1) / KB_M));
         HIPC(hipMemsetAsync(ocnt, 0, sizeof(int32_t) * m, s));
+        if (t_filter_ms) {
+            ev.resize(ev.size() + 2);
+            HIPC(hipEventCreate(&ev[ev.size() - 2]));
+            HIPC(hipEventCreate(&ev.back()));
+            HIPC(hipEventRecord(ev[ev.size() - 2], s));
+        }
         KNN_DISPATCH(launch_filter, g, block, s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, CAP, ocnt, od,
                      oi);
+        if (t_filter_ms) HIPC(hipEventRecord(ev.back(), s));
         hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, CAP, ocnt,
                            od, oi, cand, thr, retry + 1, retry);
         HIPC(hipGetLastError());
@@ -744,6 +755,17 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     int32_t nretry = 0;
     HIPC(hipMemcpyAsync(&nretry, retry, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
+    if (t_filter_ms) {
+        float tot = 0.f;
+        for (size_t e = 0; e < ev.size(); e += 2) {
+            float ms = 0.f;
+            HIPC(hipEventElapsedTime(&ms, ev[e], ev[e + 1]));
+            tot += ms;
+        }
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        *t_filter_ms = tot;
+        if (n_filter) *n_filter = (int)(ev.size() / 2);
+    }
     if (nretry > 0) {
         dim3 g((unsigned)((nretry + KB_M - 1) / KB_M));
         KNN_DISPATCH(launch_cand, g, block, s, Qh, Ql, Qn, (int64_t)nretry, Xh, Xl, Xn, N, ex, sl, 0,

@@ -472,4 +472,49 @@ void upward(askit_handle *h, const WeightSet &ws, hipStream_t s)
     }
 }
 
+// Batched upward pass: the same computation as k_upward, one wave per
+// ((instance, node), t) with the instance's tables and weight offsets.
+__global__ __launch_bounds__(64) void k_upward_multi(const UpInst *__restrict__ inst,
+                                                     const int2 *__restrict__ items, int R,
+                                                     const float *__restrict__ Wt_all,
+                                                     float *__restrict__ Wsk_all)
+{
+    const int2 it = items[blockIdx.x];
+    const UpInst &I = inst[it.x];
+    const int a = it.y, t = blockIdx.y, lane = threadIdx.x;
+    const int k = I.skk[a];
+    if (t >= k) return;
+    const int smax = I.smax;
+    const float *Wt = Wt_all + I.wt_off * R;
+    float *Wsk = Wsk_all + I.wsk_off * R;
+    const Node nd = I.nodes[a];
+    const int n = I.ncols[a], nr = n - k;
+    const int32_t *pv = I.colperm + (int64_t)a * I.ncol_max;
+    const float *Pt = I.P + I.pslot[a] + (int64_t)t * nr;
+    const int kl = nd.left >= 0 ? I.skk[nd.left] : 0;
+    auto wc = [&](int c, int r) -> float {
+        if (nd.left < 0) return Wt[(int64_t)(nd.lo + c) * R + r];
+        return c < kl ? Wsk[((int64_t)nd.left * smax + c) * R + r]
+                      : Wsk[((int64_t)nd.right * smax + (c - kl)) * R + r];
+    };
+    for (int r = 0; r < R; ++r) {
+        float acc = 0.0f;
+        for (int c = lane; c < nr; c += 64) acc = fmaf(Pt[c], wc(pv[k + c], r), acc);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) Wsk[((int64_t)a * smax + t) * R + r] = wc(pv[t], r) + acc;
+    }
+}
+
+void upward_batch(const UpInst *inst, const int2 *items, const std::vector<std::pair<int64_t, int64_t>> &levels,
+                  int smax, const float *Wt, float *Wsk, int R, hipStream_t s)
+{
+    for (const auto &lv : levels) {
+        if (lv.second == 0) continue;
+        hipLaunchKernelGGL(k_upward_multi, dim3((unsigned)lv.second, (unsigned)smax), dim3(64), 0, s, inst,
+                           items + lv.first, R, Wt, Wsk);
+        HIPC(hipGetLastError());
+    }
+}
+
 }  // namespace askit

@@ -19,7 +19,7 @@ def _lib():
 def test_header_symbols_exported():
     A = _lib()
     hdr = open(os.path.join(ROOT, "include", "askit.h")).read()
-    decl = set(re.findall(r"^\s*(?:askit_status|void|const char \*)\s*(askit_\w+)\s*\(", hdr, re.M))
+    decl = set(re.findall(r"^\s*(?:askit_status|void|const char \*|askit_handle \*)\s*(askit_\w+)\s*\(", hdr, re.M))
     assert decl == set(A.EXPORTED)
     L = C.CDLL(A.LIB_PATH)
     for name in decl:
@@ -85,3 +85,30 @@ def test_null_handle_calls():
     assert L.askit_evaluate(None, None, 1, None) == A.ERR_INVALID_ARG
     assert L.askit_query(None, None, 1, 1, None, 1, None) == A.ERR_INVALID_ARG
     L.askit_destroy(None)
+
+
+def test_server_argument_checks():
+    A = _lib()
+    c = A.server_config()
+    assert c.workers == 2 and c.max_batch_rhs == 64 and c.mem_budget == 8 << 30
+    L = A._server_lib()
+    out = C.c_void_p()
+    assert L.askit_server_create(None, None, 1, 1, C.byref(c), C.byref(out)) == A.ERR_INVALID_ARG
+    t = C.c_uint64()
+    assert L.askit_server_submit_weights(None, None, 1, 1, None, 1, C.byref(t)) == A.ERR_INVALID_ARG
+    st = C.c_int32()
+    assert L.askit_server_poll(None, 1, C.byref(st)) == A.ERR_INVALID_ARG
+    L.askit_server_destroy(None)
+
+
+def test_batch_argument_checks():
+    A = _lib()
+    L = A._batch_lib()
+    out = C.c_void_p()
+    p = A.default_params()
+    assert L.askit_batch_setup(0, None, None, None, None, C.byref(p), None, C.byref(out)) == A.ERR_INVALID_ARG
+    assert L.askit_batch_setup(1, None, None, None, None, C.byref(p), None, C.byref(out)) == A.ERR_INVALID_ARG
+    assert L.askit_batch_update_weights(None, None, 1, 1, None) == A.ERR_INVALID_ARG
+    assert L.askit_batch_run(None, None, 1, 1, None, 1, None) == A.ERR_INVALID_ARG
+    assert L.askit_batch_instance(None, 0) is None
+    L.askit_batch_destroy(None)
