@@ -63,15 +63,17 @@ def log(*a):
 
 
 def direct_fp64(Xt, Xs, W, h, chunk=4096):
-    """FP64 direct sum u(t) = sum_j exp(-|t - x_j|^2 / (2 h^2)) w_j (numpy, chunked)."""
+    """FP64 direct sum u(t) = sum_j exp(-|t - x_j|^2 / (2 h_j^2)) w_j (numpy,
+    chunked); h is a number or one bandwidth per source."""
     T = Xt.astype(np.float64)
     tn = (T * T).sum(1)
+    hv = np.broadcast_to(np.asarray(h, dtype=np.float64), (Xs.shape[0],))
     U = np.zeros((T.shape[0], W.shape[1]))
     for a in range(0, Xs.shape[0], chunk):
         S = Xs[a:a + chunk].astype(np.float64)
         D = tn[:, None] + (S * S).sum(1)[None, :] - 2.0 * T @ S.T
         np.maximum(D, 0.0, out=D)
-        U += np.exp(-D / (2.0 * h * h)) @ W[a:a + chunk].astype(np.float64)
+        U += np.exp(-D / (2.0 * hv[a:a + chunk] ** 2)[None, :]) @ W[a:a + chunk].astype(np.float64)
     return U
 
 
@@ -187,11 +189,12 @@ def serve_bench(args, wl, A, torch):
     def cost(r):
         return sec_per_col * r["R"] if r["kind"] == "weights" else sec_per_q * r["M"]
 
+    # the stream's first requests, up to (and including) the one whose work
+    # crosses the budget: a prefix, so the arrival process stays the stream's
     n, work = 0, 0.0
-    while n < len(reqs) and work + cost(reqs[n]) < args.serve_budget_s:
+    while n < len(reqs) and work < args.serve_budget_s:
         work += cost(reqs[n])
         n += 1
-    n = max(n, 1)
     head = reqs[:n]
     span = head[-1]["t"] if n > 1 else 1.0
     offered_factor = work / max(span, 1e-9)
@@ -220,12 +223,138 @@ def serve_bench(args, wl, A, torch):
     }
 
 
+def batched_bench(args, A, torch):
+    """Batched form: 256 uneven instances (N log-uniform in [2048, 65536], d in
+    {16, 32, 64}, variable bandwidth).  After one setup of the whole batch, a
+    step is one weight vector for every instance: the plain path calls
+    update_weights + evaluate per instance; the batched path replays one graph
+    (fused permutation, per-level upward launches, one evaluation launch)."""
+    wls = synth.batched_instances()
+    log(f"[batched] {len(wls)} instances: generating points")
+    Xs = [synth.points(w) for w in wls]
+    w0 = wls[0]
+    prm = A.params_from_workload(w0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = A.Batch([torch.from_numpy(X).cuda() for X in Xs], prm)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    log(f"[batched] setup {t_setup:.2f} s, {b.rows} points")
+    R = args.batched_rhs
+    W = synth.weights(b.rows, R, 4242)
+    Wd = torch.from_numpy(W).cuda()
+    Ud = torch.empty((b.rows, R), device="cuda", dtype=torch.float32)
+    Up = torch.empty((b.rows, R), device="cuda", dtype=torch.float32)
+    hs = [b.instance(i) for i in range(len(wls))]
+    Wparts = [Wd[b.offsets[i]:b.offsets[i + 1]].contiguous() for i in range(len(wls))]
+
+    def plain():
+        for i, h in enumerate(hs):
+            h.update_weights(Wparts[i])
+            h.evaluate(out=Up[b.offsets[i]:b.offsets[i + 1]])
+
+    def fused():
+        b.run(Wd, Ud)
+
+    for fn in (plain, fused):
+        for _ in range(args.warmup + 1):
+            fn()
+        torch.cuda.synchronize()
+    res = {}
+    for name, fn in (("plain", plain), ("batched", fused)):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - ta) * 1e3 / args.steps
+        log(f"[batched] {name}: {res[name]:.2f} ms per weight vector")
+    same = bool(torch.equal(Ud, Up))
+    # the fused evaluation alone, in the tuned launch shape
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.update_weights(Wd)
+    ev_ms = []
+    for _ in range(max(3, args.steps)):
+        ev0.record()
+        b.evaluate(out=Ud)
+        ev1.record()
+        torch.cuda.synchronize()
+        ev_ms.append(ev0.elapsed_time(ev1))
+    ev_kernel_ms = float(np.median(ev_ms))
+    inf = b.info()
+    flops = 0.0
+    for i, h in enumerate(hs):
+        ii = h.info()
+        flops += (ii["near_pairs"] + ii["far_pairs"]) * (2.0 * wls[i].d + 3.0 + 2.0 * R)
+    achieved = flops / (ev_kernel_ms * 1e-3) / 1e12
+    # accuracy on a few instances against an FP64 direct sum
+    rng = np.random.default_rng(7)
+    U = Ud.cpu().numpy().astype(np.float64)
+    eps = []
+    for i in rng.choice(len(wls), 4, replace=False):
+        X = Xs[i]
+        hsrc = hs[i].export(A.X_BANDWIDTH, np.float64)
+        tg = rng.choice(len(X), min(500, len(X)), replace=False)
+        Ud_ = direct_fp64(X[tg], X, W[b.offsets[i]:b.offsets[i + 1]], hsrc)
+        eps.append(float(np.linalg.norm(U[b.offsets[i] + tg, 0] - Ud_[:, 0]) / np.linalg.norm(Ud_[:, 0])))
+    out = {
+        "metric": "kernel-sum targets*RHS/s, batched instances (per weight vector, setup amortized)",
+        "value": b.rows * R / (res["batched"] * 1e-3), "unit": "targets*RHS/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["batched"], "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(wls)} instances, N log-uniform [2048, 65536], d in {{16,32,64}}, "
+                               f"variable h (16th neighbour), m=256, kappa=16, s<=128",
+                   "total_points": b.rows, "nrhs": R},
+        "plain_path": {"ms_per_step": res["plain"], "value": b.rows * R / (res["plain"] * 1e-3)},
+        "batched_equals_plain": same,
+        "setup_s": t_setup,
+        "tuner": {"launch_blocks": inf["launch_blocks"], "candidate_ms": inf["candidate_ms"]},
+        "roofline_eval": {"kernel": "k_eval (batched)", "bound": "mfma", "achieved": achieved,
+                          "peak": PEAK["fp32"], "unit": "TFLOP/s", "frac": achieved / PEAK["fp32"],
+                          "avg_launch_ms": ev_kernel_ms},
+        "eps_vs_fp64_direct_sampled_instances": eps,
+    }
+    b.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = batched_cpu_baseline(wls, Xs, W, b.offsets)
+    return out
+
+
+def batched_cpu_baseline(wls, Xs, W, offsets, budget_s=20.0):
+    """The FP64 oracle's per-weight-vector work (upward pass + evaluation, setup
+    excluded as on the GPU side) on the smallest instances until the budget is
+    spent; the per-point rate is reported for the whole batch."""
+    from oracle import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    order = np.argsort([w.N for w in wls])
+    pts, t_eval, names = 0, 0.0, []
+    t_start = time.perf_counter()
+    for i in order:
+        w = wls[i]
+        p = O.Params.from_workload(w)
+        Wi = np.ascontiguousarray(W[offsets[i]:offsets[i + 1]])
+        st = O.setup(Xs[i], p)
+        ta = time.perf_counter()
+        Wsk = O.upward(st["nodes"], Wi[st["perm"]].astype(np.float64), st["sk"], p.smax)
+        nb = O.self_neighbours(st, np.arange(w.N))
+        O.evaluate(st["X"], nb, st["X"], st["perm"], st["nodes"], st["hsrc"], p.h, Wi, st["sk"], Wsk, p.smax,
+                   record=False)
+        t_eval += time.perf_counter() - ta
+        pts += w.N
+        names.append(w.N)
+        if time.perf_counter() - t_start > budget_s:
+            break
+    return {"value": pts * W.shape[1] / t_eval, "unit": "targets*RHS/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 oracle upward pass + evaluation (setup excluded) on the {len(names)} smallest "
+                       f"instances (N = {names}), per-point rate")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fp32_1m", choices=list(WORKLOADS))
+    ap.add_argument("--workload", default="fp32_1m", choices=list(WORKLOADS) + ["batched"])
     ap.add_argument("--eps-targets", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--evals", type=int, default=5, help="amortized update+evaluate repetitions")
@@ -234,6 +363,7 @@ def main():
     ap.add_argument("--serve-workers", type=int, default=2)
     ap.add_argument("--serve-mem-gib", type=int, default=64)
     ap.add_argument("--serve-budget-s", type=float, default=20.0, help="GPU work per serving replay")
+    ap.add_argument("--batched-rhs", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
@@ -243,6 +373,9 @@ def main():
     import torch
     from paper_1410_0260_amd import askit as A
 
+    if args.workload == "batched":
+        print(json.dumps(batched_bench(args, A, torch)))
+        return
     wl = WORKLOADS[args.workload]()
     if args.workload == "serving_4m":
         print(json.dumps(serve_bench(args, wl, A, torch)))

@@ -299,6 +299,22 @@ def test_exact_skeletons_reproduce_direct():
     assert sum(len(f) for f in st["ev"].far) > 0
 
 
+def test_duplicate_points_exact_with_nontrivial_projection():
+    """Every point appears three times, so duplicate columns of K(T, C) are
+    identical: the ID keeps one of each and P carries the others with
+    coefficient 1, and the skeleton sums (with w~ = w(S) + P w(R) from the
+    upward pass) are exact.  Checks the upward pass and P with k < n."""
+    base = small(120)
+    X = np.ascontiguousarray(np.repeat(base, 3, axis=0))
+    W = synth.weights(360, 2, 9)
+    e, st = _eps(X, W, base_params(kappa=3, ell=360, smax=360, tau=0.0))
+    sk = st["sk"]
+    shrunk = [a for a in range(1, len(st["nodes"])) if sk.ncols[a] > sk.k[a] > 0]
+    assert len(shrunk) > 0 and sum(len(f) for f in st["ev"].far) > 0
+    assert any(np.abs(sk.proj(a)).max() > 0.5 for a in shrunk)
+    assert e < 1e-10
+
+
 def test_variable_bandwidth_exact_case():
     X = small(300)
     W = synth.weights(300, 1, 4)
