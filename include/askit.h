@@ -141,6 +141,8 @@ typedef struct {
     double t_qr_ms;                      /* last setup: the QR kernels alone (all levels) */
     double t_knn_filter_ms;              /* last setup: the kNN filter sweep launches alone (sum) */
     int64_t knn_filter_launches;         /* ... and their number */
+    int64_t eval_pairs;                  /* (target, source node) pairs of one evaluation */
+    int64_t eval_chunks;                 /* evaluation work items (up to 64 targets of one source node) */
 } askit_info;
 
 askit_status askit_get_info(const askit_handle *h, askit_info *out);
@@ -263,7 +265,7 @@ typedef struct askit_batch askit_batch;
 
 typedef struct {
     int32_t count, nrhs;
-    int64_t total_points, total_slabs;
+    int64_t total_points, total_chunks;   /* chunks: evaluation work items of up to 64 targets */
     int64_t near_entries, far_entries, near_pairs, far_pairs;
     double t_setup_ms;
     int32_t tuned;              /* 1 once a launch shape is chosen for nrhs */

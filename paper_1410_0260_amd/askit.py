@@ -46,7 +46,8 @@ class Info(C.Structure):
                 ("t_tree_ms", C.c_double), ("t_lists_ms", C.c_double), ("t_skel_ms", C.c_double),
                 ("t_inter_ms", C.c_double), ("t_update_ms", C.c_double),
                 ("t_knn_sweep_ms", C.c_double), ("t_qr_ms", C.c_double),
-                ("t_knn_filter_ms", C.c_double), ("knn_filter_launches", C.c_int64)]
+                ("t_knn_filter_ms", C.c_double), ("knn_filter_launches", C.c_int64),
+                ("eval_pairs", C.c_int64), ("eval_chunks", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -358,7 +359,7 @@ class Server:
 # ----------------------------------------------------------------- batched form
 class BatchInfo(C.Structure):
     _fields_ = [("count", C.c_int32), ("nrhs", C.c_int32), ("total_points", C.c_int64),
-                ("total_slabs", C.c_int64), ("near_entries", C.c_int64), ("far_entries", C.c_int64),
+                ("total_chunks", C.c_int64), ("near_entries", C.c_int64), ("far_entries", C.c_int64),
                 ("near_pairs", C.c_int64), ("far_pairs", C.c_int64), ("t_setup_ms", C.c_double),
                 ("tuned", C.c_int32), ("launch_blocks", C.c_int32), ("candidate_ms", C.c_double * 4),
                 ("graphs", C.c_int32)]

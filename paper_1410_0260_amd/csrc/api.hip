@@ -160,17 +160,10 @@ void query_points(askit_handle *h, const WeightSet &ws, const float *Y, int64_t 
     Slab *qslabs;
     int64_t nen, nef;
     build_query_interactions(h, nbs, M, qslabs, ptr, node, mask, nen, nef, tmp, s);
-    EvalArgs a;
-    a.Y = Ys;
-    a.nslab = (M + SLAB - 1) / SLAB;
-    a.slabs = qslabs;
-    a.ptr = ptr;
-    a.node = node;
-    a.mask = mask;
-    a.outmap = order;
-    a.U = U;
-    a.ldu = ldu;
-    evaluate(h, ws, a, s);
+    PairLists L;
+    build_pairs(h, qslabs, (M + SLAB - 1) / SLAB, M, ptr, node, mask, nen, nef, L, ta, s);
+    float *part = (float *)ta(sizeof(float) * std::max<int64_t>(L.npairs, 1) * ws.R);
+    evaluate(h, ws, Ys, L, order, U, ldu, part, s);
     HIPC(hipStreamSynchronize(s));
 }
 
@@ -457,8 +450,11 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
     // ---- skeletons
     skeletonize(h.get(), s);
     HIPC(hipEventRecord(ev[4], s));
-    // ---- interaction lists
+    // ---- interaction lists, and the same pairs grouped by source node
     build_interactions(h.get(), s);
+    build_pairs(h.get(), h->d_slabs, (int64_t)h->slabs.size(), N, h->sl_ptr, h->sl_node, h->sl_mask,
+                h->near_entries, h->far_entries, h->pairs,
+                [hp = h.get()](size_t b) { return hp->alloc(b, false); }, s);
     HIPC(hipEventRecord(ev[5], s));
     HIPC(hipStreamSynchronize(s));
     prepare_upward(h.get());
@@ -492,8 +488,10 @@ askit_status askit_update_weights(askit_handle *h, const float *W, int64_t ldw, 
         };
         drop(h->ws.Wt);
         drop(h->ws.Wsk);
+        drop(h->ws.part);
         h->ws.Wt = (float *)h->alloc(sizeof(float) * h->N * nrhs, false);
         h->ws.Wsk = (float *)h->alloc(sizeof(float) * nn * h->smax * nrhs, true);
+        h->ws.part = (float *)h->alloc(sizeof(float) * std::max<int64_t>(h->pairs.npairs, 1) * nrhs, false);
         h->wcap = nrhs;
     }
     h->ws.R = nrhs;
@@ -511,17 +509,7 @@ askit_status askit_evaluate(askit_handle *h, float *U, int64_t ldu, void *stream
     if (!h || !U) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
     if (h->ws.R < 1) fail(ASKIT_ERR_NOT_READY, "askit_update_weights has not been called");
     if (ldu < h->ws.R) fail(ASKIT_ERR_INVALID_ARG, "need ldu >= nrhs");
-    EvalArgs a;
-    a.Y = h->Xt;
-    a.nslab = (int64_t)h->slabs.size();
-    a.slabs = h->d_slabs;
-    a.ptr = h->sl_ptr;
-    a.node = h->sl_node;
-    a.mask = h->sl_mask;
-    a.outmap = h->perm;
-    a.U = U;
-    a.ldu = ldu;
-    evaluate(h, h->ws, a, (hipStream_t)stream);
+    evaluate(h, h->ws, h->Xt, h->pairs, h->perm, U, ldu, h->ws.part, (hipStream_t)stream);
     API_END
 }
 
@@ -583,6 +571,8 @@ askit_status askit_get_info(const askit_handle *h, askit_info *o)
     o->t_knn_sweep_ms = h->t_knn_sweep;
     o->t_knn_filter_ms = h->t_knn_filter;
     o->knn_filter_launches = h->knn_filter_launches;
+    o->eval_pairs = h->pairs.npairs;
+    o->eval_chunks = h->pairs.nchunk;
     o->t_qr_ms = h->t_qr;
     API_END
 }

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -82,7 +83,24 @@ struct Slab {              // SLAB consecutive tree positions of one leaf
 struct WeightSet {
     float *Wt = nullptr;       // N x R
     float *Wsk = nullptr;      // nn x smax x R
+    float *part = nullptr;     // npairs x R partial sums of the evaluation
     int R = 0;
+};
+
+// Evaluation work item: up to 64 targets of one source node.
+struct Chunk {
+    int32_t node;
+    int32_t kind;              // 0: near (the leaf's points), 1: far (the skeleton); + 2 x instance (batch)
+    int32_t first, count;      // pairs [first, first + count) of the pair lists
+};
+
+// (target, source node) pairs grouped by source node and kind.
+struct PairLists {
+    int64_t npairs = 0, nchunk = 0, ntarget = 0;
+    int32_t *tpos = nullptr;   // target row of each pair
+    int32_t *tslot = nullptr;  // partial-sum slot of each pair
+    int32_t *sbase = nullptr;  // ntarget + 1: first slot of each target (slots of a target are contiguous)
+    Chunk *chunks = nullptr;
 };
 
 }  // namespace askit
@@ -138,6 +156,7 @@ struct askit_handle {
     int32_t *sl_node = nullptr;
     uint64_t *sl_mask = nullptr;
     int64_t near_entries = 0, far_entries = 0;
+    askit::PairLists pairs;       // the same pairs grouped by source node (evaluation work)
 
     // diagnostics
     int64_t near_pairs = 0, far_pairs = 0, knn_uncertified = 0;
@@ -206,17 +225,17 @@ void prepare_upward(askit_handle *h);                                  // once, 
 void permute_weights(askit_handle *h, const float *W, int64_t ldw, WeightSet &ws, hipStream_t s);
 
 // eval.hip
-struct EvalArgs {
-    const float *Y;            // targets, rows of stride dp
-    int64_t nslab;
-    const Slab *slabs;         // row0 index into Y, nrows
-    const int32_t *ptr, *node; // CSR: near [0..nslab], far [nslab+1 .. 2 nslab + 1]
-    const uint64_t *mask;
-    const int32_t *outmap;     // output row of target row (NULL: identity)
-    float *U;
-    int64_t ldu;
-};
-void evaluate(askit_handle *h, const WeightSet &ws, const EvalArgs &a, hipStream_t s);
+// Pair lists of the targets described by slab lists (ptr: near offsets
+// [0..nslab], far offsets [nslab+1 .. 2 nslab + 1] into node/mask); `al`
+// allocates the outputs (persistent or temporary).
+void build_pairs(const askit_handle *h, const Slab *d_slabs, int64_t nslab, int64_t ntarget, const int32_t *ptr,
+                 const int32_t *node, const uint64_t *mask, int64_t ne_near, int64_t ne_far, PairLists &L,
+                 const std::function<void *(size_t)> &al, hipStream_t s);
+// u at the targets Y (rows of stride dp) for the weights ws: partial sums per
+// pair slot into part (>= npairs x R floats), then per-target sums into
+// U[outmap[i]] (identity when NULL).
+void evaluate(const askit_handle *h, const WeightSet &ws, const float *Y, const PairLists &L,
+              const int32_t *outmap, float *U, int64_t ldu, float *part, hipStream_t s);
 
 // ---------------------------------------------------------------- batched form
 // One entry per instance of a batch (device tables).  Weights of all
@@ -226,7 +245,6 @@ struct EvalInst {
     const Node *nodes;
     const float *Y, *Xt, *gt, *Xs, *gs;
     const int32_t *skk;
-    const int32_t *outmap;     // batch output row of each tree position of the instance
     int64_t wt_off, wsk_off;
     int smax, dp;
 };
@@ -240,18 +258,20 @@ struct UpInst {
 };
 struct BatchEvalArgs {
     const EvalInst *inst;
-    const Slab *slabs;         // pad = instance
-    const int32_t *ptr, *node; // CSR over all slabs, near then far (as EvalArgs)
-    const uint64_t *mask;
-    int64_t nslab;
+    const Chunk *chunks;       // kind = 2 x instance + kind
+    int64_t nchunk;
+    const int32_t *tpos, *tslot;   // tpos: row in the instance's targets; tslot: batch-wide slot
+    const int32_t *sbase;      // batch rows + 1
+    const int32_t *outrow;     // batch output row of each batch tree row
+    int64_t rows;
     const float *Wt, *Wsk;
+    float *part;
     float *U;
     int64_t ldu;
     int R;
     bool bf;
-    int persistent;            // 0: one workgroup per slab; else the persistent grid size
-    const int32_t *order;      // persistent: slab of each queue item
-    int32_t *queue;            // persistent: one counter per RHS pass
+    int persistent;            // 0: one workgroup per chunk; else the persistent grid size
+    int32_t *queue;            // persistent: work counter (cleared by a kernel before the launch)
 };
 void evaluate_batch(const BatchEvalArgs &b, hipStream_t s);
 // One launch per level (deepest first): items are (instance, node) pairs.

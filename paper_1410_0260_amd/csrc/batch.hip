@@ -59,7 +59,7 @@ struct askit_batch {
     int num_cu = 256;
     askit_params prm{};
     int smax = 0;
-    int64_t rows = 0, wsk_slots = 0, nslab = 0, ne = 0, fe = 0;
+    int64_t rows = 0, wsk_slots = 0, npairs = 0, nchunk = 0, ne = 0, fe = 0;
     int64_t near_pairs = 0, far_pairs = 0;
     double t_setup_ms = 0.0;
     std::vector<void *> own;
@@ -68,11 +68,10 @@ struct askit_batch {
     UpInst *d_uinst = nullptr;
     int2 *d_items = nullptr;
     std::vector<std::pair<int64_t, int64_t>> levels;
-    Slab *d_slabs = nullptr;
-    int32_t *d_ptr = nullptr, *d_node = nullptr, *d_order = nullptr, *d_queue = nullptr, *d_outrow = nullptr;
-    uint64_t *d_mask = nullptr;
+    Chunk *d_chunks = nullptr;
+    int32_t *d_tpos = nullptr, *d_tslot = nullptr, *d_sbase = nullptr, *d_queue = nullptr, *d_outrow = nullptr;
 
-    float *Wt = nullptr, *Wsk = nullptr;
+    float *Wt = nullptr, *Wsk = nullptr, *part = nullptr;
     int wcap = 0, R = 0;
 
     int blocks_for_R[MAX_RHS + 1] = {};      // -1: not tuned
@@ -105,25 +104,28 @@ struct askit_batch {
         for (void *p : own) (void)hipFree(p);
         if (Wt) (void)hipFree(Wt);
         if (Wsk) (void)hipFree(Wsk);
+        if (part) (void)hipFree(part);
         for (auto *h : inst) askit_destroy(h);
     }
     BatchEvalArgs eval_args(float *U, int64_t ldu, int blocks) const
     {
         BatchEvalArgs a{};
         a.inst = d_einst;
-        a.slabs = d_slabs;
-        a.ptr = d_ptr;
-        a.node = d_node;
-        a.mask = d_mask;
-        a.nslab = nslab;
+        a.chunks = d_chunks;
+        a.nchunk = nchunk;
+        a.tpos = d_tpos;
+        a.tslot = d_tslot;
+        a.sbase = d_sbase;
+        a.outrow = d_outrow;
+        a.rows = rows;
         a.Wt = Wt;
         a.Wsk = Wsk;
+        a.part = part;
         a.U = U;
         a.ldu = ldu;
         a.R = R;
         a.bf = prm.precision == ASKIT_PREC_BF16X3;
         a.persistent = blocks;
-        a.order = d_order;
         a.queue = d_queue;
         return a;
     }
@@ -133,6 +135,19 @@ struct askit_batch {
         upward_batch(d_uinst, d_items, levels, smax, Wt, Wsk, R, s);
     }
 };
+
+__global__ void k_add_offset(int32_t *__restrict__ dst, const int32_t *__restrict__ src, int64_t n, int32_t off)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i] + off;
+}
+
+static void add_offset(int32_t *dst, const int32_t *src, int64_t n, int32_t off)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_add_offset, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, dst, src, n, off);
+    HIPC(hipGetLastError());
+}
 
 #define API_BEGIN                                                                                 \
     try {                                                                                         \
@@ -158,9 +173,11 @@ static void ensure_weights(askit_batch *b, int R, hipStream_t s)
         b->drop_graphs();
         if (b->Wt) HIPC(hipFree(b->Wt));
         if (b->Wsk) HIPC(hipFree(b->Wsk));
-        b->Wt = b->Wsk = nullptr;
+        if (b->part) HIPC(hipFree(b->part));
+        b->Wt = b->Wsk = b->part = nullptr;
         HIPC(hipMalloc((void **)&b->Wt, sizeof(float) * std::max<int64_t>(b->rows * R, 4)));
         HIPC(hipMalloc((void **)&b->Wsk, sizeof(float) * std::max<int64_t>(b->wsk_slots * R, 4)));
+        HIPC(hipMalloc((void **)&b->part, sizeof(float) * std::max<int64_t>(b->npairs * R, 4)));
         b->wcap = R;
     }
     b->R = R;
@@ -275,74 +292,62 @@ askit_status askit_batch_setup(int32_t count, const float *const *X, const int64
     for (auto &t : th) t.join();
     if (first_code != ASKIT_OK) fail(first_code, first_msg);
 
-    // host tables
+    // host tables: instance offsets of rows, skeleton-weight slots and pairs
     const int smax = b->inst[0]->smax;
     b->smax = smax;
-    std::vector<int64_t> row_off(count + 1, 0), wsk_off(count + 1, 0), ns_off(count + 1, 0), ne_off(count + 1, 0),
-        fe_off(count + 1, 0);
+    std::vector<int64_t> row_off(count + 1, 0), wsk_off(count + 1, 0), pair_off(count + 1, 0);
     int maxdepth = 0;
     for (int32_t i = 0; i < count; ++i) {
         const askit_handle *h = b->inst[i];
         row_off[i + 1] = row_off[i] + h->N;
         wsk_off[i + 1] = wsk_off[i] + (int64_t)h->nodes.size() * h->smax;
-        ns_off[i + 1] = ns_off[i] + (int64_t)h->slabs.size();
-        ne_off[i + 1] = ne_off[i] + h->near_entries;
-        fe_off[i + 1] = fe_off[i] + h->far_entries;
+        pair_off[i + 1] = pair_off[i] + h->pairs.npairs;
         maxdepth = std::max(maxdepth, h->depth);
         b->near_pairs += h->near_pairs;
         b->far_pairs += h->far_pairs;
+        b->ne += h->near_entries;
+        b->fe += h->far_entries;
     }
     if (row_off[count] >= (1ll << 31)) fail(ASKIT_ERR_UNSUPPORTED, "batch above 2^31 points");
-    if (ne_off[count] + fe_off[count] >= (1ll << 31)) fail(ASKIT_ERR_UNSUPPORTED, "batch lists exceed 2^31 entries");
+    if (pair_off[count] >= (1ll << 31)) fail(ASKIT_ERR_UNSUPPORTED, "batch above 2^31 evaluation pairs");
     b->rows = row_off[count];
     b->wsk_slots = wsk_off[count];
-    b->nslab = ns_off[count];
-    b->ne = ne_off[count];
-    b->fe = fe_off[count];
-    const int64_t S = b->nslab;
+    b->npairs = pair_off[count];
 
+    // concatenated pair lists: rows stay instance-local (targets are the
+    // instance's own points), slots and chunk pair ranges become batch-wide
     std::vector<int32_t> outrow(b->rows);
-    std::vector<Slab> slabs(S);
-    std::vector<int32_t> ptr(2 * S + 2);
-    std::vector<int64_t> cost(S);
+    std::vector<Chunk> chunks;
     std::vector<EvalInst> einst(count);
     std::vector<UpInst> uinst(count);
-    b->d_node = (int32_t *)b->dev(sizeof(int32_t) * (b->ne + b->fe));
-    b->d_mask = (uint64_t *)b->dev(sizeof(uint64_t) * (b->ne + b->fe));
     b->d_outrow = (int32_t *)b->dev(sizeof(int32_t) * b->rows);
+    b->d_sbase = (int32_t *)b->dev(sizeof(int32_t) * (b->rows + 1));
+    b->d_tpos = (int32_t *)b->dev(sizeof(int32_t) * std::max<int64_t>(b->npairs, 1));
+    b->d_tslot = (int32_t *)b->dev(sizeof(int32_t) * std::max<int64_t>(b->npairs, 1));
     for (int32_t i = 0; i < count; ++i) {
         const askit_handle *h = b->inst[i];
-        const int64_t ns = (int64_t)h->slabs.size();
-        std::vector<int32_t> perm(h->N), hp(2 * ns + 2);
+        const PairLists &L = h->pairs;
+        std::vector<int32_t> perm(h->N);
+        std::vector<Chunk> hc(L.nchunk);
         HIPC(hipMemcpy(perm.data(), h->perm, sizeof(int32_t) * h->N, hipMemcpyDeviceToHost));
-        HIPC(hipMemcpy(hp.data(), h->sl_ptr, sizeof(int32_t) * hp.size(), hipMemcpyDeviceToHost));
+        if (L.nchunk > 0) HIPC(hipMemcpy(hc.data(), L.chunks, sizeof(Chunk) * L.nchunk, hipMemcpyDeviceToHost));
         for (int64_t t = 0; t < h->N; ++t) outrow[row_off[i] + t] = (int32_t)(row_off[i] + perm[t]);
-        const int64_t nei = h->near_entries;
-        for (int64_t k = 0; k < ns; ++k) {
-            Slab sl = h->slabs[k];
-            sl.pad = i;
-            slabs[ns_off[i] + k] = sl;
-            ptr[ns_off[i] + k] = (int32_t)(hp[k] + ne_off[i]);
-            ptr[S + 1 + ns_off[i] + k] = (int32_t)(hp[ns + 1 + k] - nei + b->ne + fe_off[i]);
-            cost[ns_off[i] + k] = (int64_t)(hp[k + 1] - hp[k]) * h->m + (int64_t)(hp[ns + 2 + k] - hp[ns + 1 + k]) * h->smax;
+        for (Chunk c : hc) {
+            c.kind = (c.kind & 1) | (i << 1);
+            c.first += (int32_t)pair_off[i];
+            chunks.push_back(c);
         }
-        if (nei > 0) {
-            HIPC(hipMemcpy(b->d_node + ne_off[i], h->sl_node, sizeof(int32_t) * nei, hipMemcpyDeviceToDevice));
-            HIPC(hipMemcpy(b->d_mask + ne_off[i], h->sl_mask, sizeof(uint64_t) * nei, hipMemcpyDeviceToDevice));
+        if (L.npairs > 0) {
+            HIPC(hipMemcpy(b->d_tpos + pair_off[i], L.tpos, sizeof(int32_t) * L.npairs, hipMemcpyDeviceToDevice));
+            add_offset(b->d_tslot + pair_off[i], L.tslot, L.npairs, (int32_t)pair_off[i]);
         }
-        if (h->far_entries > 0) {
-            HIPC(hipMemcpy(b->d_node + b->ne + fe_off[i], h->sl_node + nei, sizeof(int32_t) * h->far_entries,
-                           hipMemcpyDeviceToDevice));
-            HIPC(hipMemcpy(b->d_mask + b->ne + fe_off[i], h->sl_mask + nei, sizeof(uint64_t) * h->far_entries,
-                           hipMemcpyDeviceToDevice));
-        }
-        einst[i] = EvalInst{h->d_nodes, h->Xt, h->Xt, h->gt, h->Xs, h->gs, h->skk, b->d_outrow + row_off[i],
-                            row_off[i], wsk_off[i], h->smax, h->dp};
+        add_offset(b->d_sbase + row_off[i], L.sbase, h->N + (i == count - 1 ? 1 : 0), (int32_t)pair_off[i]);
+        einst[i] = EvalInst{h->d_nodes, h->Xt, h->Xt, h->gt, h->Xs, h->gs, h->skk, row_off[i], wsk_off[i], h->smax,
+                            h->dp};
         uinst[i] = UpInst{h->d_nodes, h->skk, h->ncols, h->colperm, h->d_pslot, h->P, row_off[i], wsk_off[i],
                           h->ncol_max, h->smax};
     }
-    ptr[S] = (int32_t)b->ne;
-    ptr[2 * S + 1] = (int32_t)(b->ne + b->fe);
+    b->nchunk = (int64_t)chunks.size();
     // upward items, deepest level first across all instances
     std::vector<int2> items;
     for (int lev = maxdepth; lev >= 1; --lev) {
@@ -354,26 +359,18 @@ askit_status askit_batch_setup(int32_t count, const float *const *X, const int64
         }
         b->levels.push_back({first, (int64_t)items.size() - first});
     }
-    std::vector<int32_t> order(S);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
 
     b->d_einst = (EvalInst *)b->dev(sizeof(EvalInst) * count);
     b->d_uinst = (UpInst *)b->dev(sizeof(UpInst) * count);
     b->d_items = (int2 *)b->dev(sizeof(int2) * std::max<size_t>(items.size(), 1));
-    b->d_slabs = (Slab *)b->dev(sizeof(Slab) * std::max<int64_t>(S, 1));
-    b->d_ptr = (int32_t *)b->dev(sizeof(int32_t) * ptr.size());
-    b->d_order = (int32_t *)b->dev(sizeof(int32_t) * std::max<int64_t>(S, 1));
-    b->d_queue = (int32_t *)b->dev(sizeof(int32_t) * MAX_PASSES);
+    b->d_chunks = (Chunk *)b->dev(sizeof(Chunk) * std::max<int64_t>(b->nchunk, 1));
+    b->d_queue = (int32_t *)b->dev(sizeof(int32_t) * 4);
     HIPC(hipMemcpy(b->d_einst, einst.data(), sizeof(EvalInst) * count, hipMemcpyHostToDevice));
     HIPC(hipMemcpy(b->d_uinst, uinst.data(), sizeof(UpInst) * count, hipMemcpyHostToDevice));
     if (!items.empty())
         HIPC(hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
-    if (S > 0) {
-        HIPC(hipMemcpy(b->d_slabs, slabs.data(), sizeof(Slab) * S, hipMemcpyHostToDevice));
-        HIPC(hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice));
-    }
-    HIPC(hipMemcpy(b->d_ptr, ptr.data(), sizeof(int32_t) * ptr.size(), hipMemcpyHostToDevice));
+    if (b->nchunk > 0)
+        HIPC(hipMemcpy(b->d_chunks, chunks.data(), sizeof(Chunk) * b->nchunk, hipMemcpyHostToDevice));
     HIPC(hipMemcpy(b->d_outrow, outrow.data(), sizeof(int32_t) * b->rows, hipMemcpyHostToDevice));
     HIPC(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     for (int r = 0; r <= MAX_RHS; ++r) b->blocks_for_R[r] = -1;
@@ -381,7 +378,7 @@ askit_status askit_batch_setup(int32_t count, const float *const *X, const int64
     auto lg = [](int64_t v) { int k = 0; while ((int64_t)1 << k < v) ++k; return k; };
     int maxdp = 0;
     for (auto *h : b->inst) maxdp = std::max(maxdp, h->dp);
-    b->tune_key_base = "n" + std::to_string(lg(b->rows)) + "s" + std::to_string(lg(S)) + "e" +
+    b->tune_key_base = "n" + std::to_string(lg(b->rows)) + "s" + std::to_string(lg(b->nchunk)) + "e" +
                        std::to_string(lg(b->ne + b->fe)) + "d" + std::to_string(maxdp) + "k" + std::to_string(smax) +
                        "p" + std::to_string((int)p->precision) + "c" + std::to_string(count);
     HIPC(hipDeviceSynchronize());
@@ -476,7 +473,7 @@ askit_status askit_batch_get_info(const askit_batch *b, askit_batch_info *o)
     o->count = (int32_t)b->inst.size();
     o->nrhs = b->R;
     o->total_points = b->rows;
-    o->total_slabs = b->nslab;
+    o->total_chunks = b->nchunk;
     o->near_entries = b->ne;
     o->far_entries = b->fe;
     o->near_pairs = b->near_pairs;

@@ -1,15 +1,23 @@
-// Downward pass (Alg. 4) over the slab interaction lists.
+// Downward pass (Alg. 4) as sums over (target, source node) pairs.
 //
-// One workgroup per slab of up to 64 targets.  For every near entry (a leaf:
-// its points and weights) and far entry (a pruned node: its skeleton points
-// and skeleton weights), sources are taken in tiles of 64:
-//   r^2 = |x - c|^2 + |y - c|^2 - 2 (x - c).(y - c),  c = the slab's first
-//   target (centring keeps the cancellation small),
-// with the 64 x 64 dot products on MFMA (v_mfma_f32_32x32x2_f32, each wave a
-// 32 x 32 quadrant, operands staged through LDS in 64-dimension chunks), then
-// K = exp2(g_j r^2), g_j = -log2(e) / (2 h_j^2), and u_i += K_ij w_j for
-// the rows i whose bit is set in the entry's mask.  Every slab owns its
-// output rows, so the sums are deterministic (no atomics).
+// Work item: a chunk of up to 64 targets that all use one source node
+// (near: a leaf's points and weights; far: a pruned node's skeleton points
+// and skeleton weights).  Sources are taken in tiles of 64:
+//   r^2 = |x - c|^2 + |y - c|^2 - 2 (x - c).(y - c),  c = the source node's
+//   first point (the sources are compact around it, and the rounding error
+//   of r^2 then grows with r^2 itself, which the kernel damps; every pair's
+//   value is also independent of the other targets in the chunk),
+// with the 64 x 64 products on MFMA, sources as the rows and targets as the
+// columns (v_mfma_f32_32x32x2_f32, or the bf16 hi/lo split on
+// v_mfma_f32_32x32x16_bf16 with an FP64 final combine), each wave one
+// 32 x 32 quadrant, operands staged through LDS in 64-dimension chunks; then
+// K = exp2(g_j r^2), g_j = -log2(e) / (2 h_j^2), and the contraction with
+// the tile's weights: for up to 4 right-hand sides on the vector units, for
+// more as a second MFMA with the weights as the A operand (the kernel tile,
+// which the first MFMA left with targets along the lanes and sources along
+// the registers, is exactly the B operand layout), 32 or 64 columns per
+// pass.  Each pair's sum goes to its own slot; a second kernel adds a
+// target's slots in order, so the result is deterministic (no atomics).
 #include "askit_impl.h"
 
 #include <algorithm>
@@ -31,57 +39,57 @@ __device__ __forceinline__ float ev_bf2f(uint32_t b) { return __uint_as_float(b 
 constexpr int EV_T = 256;
 constexpr int EV_KC = 64;              // dimensions per LDS chunk
 constexpr int EV_LD = EV_KC + 4;       // padded LDS row (floats)
-constexpr int EV_RB = 8;               // largest right-hand-side block per pass
 constexpr int EV_LH = EV_KC + 8;       // padded LDS row of the bf16 operands (elements)
 
-struct EvalParams {
-    const float *Y;            // targets (rows of stride dp)
-    const Slab *slabs;
-    const int32_t *ptr, *node;
-    const uint64_t *mask;
-    const int32_t *outmap;
-    float *U;
-    int64_t ldu;
-    int64_t nslab;
+struct ChunkParams {
+    const Chunk *chunks;
+    int64_t nchunk;
+    const int32_t *tpos, *tslot;
+    // single problem (MULTI = false)
     const Node *nodes;
-    const float *Xt, *gt, *Wt;   // near sources (tree order)
-    const float *Xs, *gs, *Wsk;  // far sources (skeletons)
+    const float *Y, *Xt, *gt, *Xs, *gs;
     const int32_t *skk;
-    int smax, dp, R, r0, rb;
-    // batched form: per-instance tables (slab.pad = instance), optional work queue
+    int smax, dp;
+    // batch (MULTI = true)
     const EvalInst *inst;
-    const int32_t *order;      // persistent mode: item -> slab (cost order)
-    int32_t *queue;            // persistent mode: next item (zeroed before the launch)
+    int32_t *queue;
     int persistent;
+    // weights and output
+    const float *Wt, *Wsk;     // single: the problem's; batch: shared buffers (instance offsets)
+    float *part;
+    int R, r0, rb;             // columns [r0, r0 + rb) in this pass
 };
 
-// BF: distance products as bf16 hi/lo split (hi*hi + hi*lo + lo*hi) on
-// v_mfma_f32_32x32x16_bf16 with FP32 accumulation and an FP64 final combine of
-// |x|^2 + |y|^2 - 2 x.y; otherwise FP32 products on v_mfma_f32_32x32x2_f32.
-template <int RB, bool BF, bool MULTI>
-__global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
+// CM: columns per pass and contraction: 1 or 4 on the vector units, 32 or 64 on MFMA.
+template <int CM, bool BF, bool MULTI>
+__global__ __launch_bounds__(EV_T) void k_eval_chunks(ChunkParams p)
 {
-    __shared__ __attribute__((aligned(16))) float sA[BF ? 16 : 64 * EV_LD];
-    __shared__ __attribute__((aligned(16))) float sB[BF ? 16 : 64 * EV_LD];
-    __shared__ __attribute__((aligned(16))) uint16_t sAh[BF ? 64 * EV_LH : 8], sAl[BF ? 64 * EV_LH : 8];
-    __shared__ __attribute__((aligned(16))) uint16_t sBh[BF ? 64 * EV_LH : 8], sBl[BF ? 64 * EV_LH : 8];
-    __shared__ float sC[1024 + 64];      // centre (dp <= 1024)
-    __shared__ float sAn[64], sBn[64], sBg[64], sBw[64 * RB];
-    __shared__ float sRed[2][64 * RB];
+    constexpr bool MC = CM >= 32;
+    constexpr int NACC = MC ? CM / 32 : 1;
+    __shared__ __attribute__((aligned(16))) float sT[BF ? 16 : 64 * EV_LD];
+    __shared__ __attribute__((aligned(16))) float sS[BF ? 16 : 64 * EV_LD];
+    __shared__ __attribute__((aligned(16))) uint16_t sTh[BF ? 64 * EV_LH : 8], sTl[BF ? 64 * EV_LH : 8];
+    __shared__ __attribute__((aligned(16))) uint16_t sSh[BF ? 64 * EV_LH : 8], sSl[BF ? 64 * EV_LH : 8];
+    __shared__ float sC[1024];                 // centre (dp <= 1024)
+    __shared__ float sTn[64], sSn[64], sSg[64];
+    __shared__ float sW[64 * CM];               // weights of the source tile
+    __shared__ float sRed[MC ? 64 * CM : 2 * 64 * CM];
+    __shared__ int sRow[64], sSlot[64];
+    __shared__ int64_t sItem;
 
     const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
     const int half = lane >> 5, l32 = lane & 31;
-    const int rq = 32 * (wv >> 1), cq = 32 * (wv & 1);
-    __shared__ int64_t sItem;
+    const int sq = 32 * (wv >> 1), tq = 32 * (wv & 1);   // source rows / target columns of this wave
 
-  auto process = [&](const int64_t slab) {
-    const Slab sb = p.slabs[slab];
+  auto process = [&](const int64_t ci) {
+    const Chunk ch = p.chunks[ci];
+    const int kind = ch.kind & 1;
     const Node *nodes = p.nodes;
     const float *Y = p.Y, *Xt = p.Xt, *gt = p.gt, *Xs = p.Xs, *gs = p.gs, *Wt = p.Wt, *Wsk = p.Wsk;
-    const int32_t *skk = p.skk, *outmap = p.outmap;
+    const int32_t *skk = p.skk;
     int smax = p.smax, dp = p.dp;
     if constexpr (MULTI) {
-        const EvalInst &I = p.inst[sb.pad];
+        const EvalInst &I = p.inst[ch.kind >> 1];
         nodes = I.nodes;
         Y = I.Y;
         Xt = I.Xt;
@@ -89,30 +97,47 @@ __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
         Xs = I.Xs;
         gs = I.gs;
         skk = I.skk;
-        outmap = I.outmap;
         smax = I.smax;
         dp = I.dp;
         Wt = p.Wt + I.wt_off * p.R;
         Wsk = p.Wsk + I.wsk_off * p.R;
     }
-    const float *Yb = Y + (int64_t)sb.row0 * dp;
+    const int a = ch.node, nt = ch.count;
+    const float *src, *g, *w;
+    int ns;
+    if (kind == 0) {
+        const Node nd = nodes[a];
+        ns = nd.hi - nd.lo;
+        src = Xt + (int64_t)nd.lo * dp;
+        g = gt + nd.lo;
+        w = Wt + (int64_t)nd.lo * p.R;
+    } else {
+        ns = skk[a];
+        src = Xs + (int64_t)a * smax * dp;
+        g = gs + (int64_t)a * smax;
+        w = Wsk + (int64_t)a * smax * p.R;
+    }
     const int nchunk = (dp + EV_KC - 1) / EV_KC;
-
-    for (int k = tid; k < dp; k += EV_T) sC[k] = Yb[k];
+    if (tid < 64) {
+        sRow[tid] = tid < nt ? p.tpos[ch.first + tid] : -1;
+        sSlot[tid] = tid < nt ? p.tslot[ch.first + tid] : -1;
+    }
+    __syncthreads();
+    for (int k = tid; k < dp; k += EV_T) sC[k] = src[k];      // centre: the source node's first point
     __syncthreads();
 
-    // load one 64 x EV_KC chunk of rows (centred) into dst; row r valid when r < nrow
-    // src row r at base + r * dp; returns the per-row partial squared norms in nrm
-    auto load_chunk = [&](float *dst, uint16_t *dh, uint16_t *dl, const float *base, int nrow, int k0,
-                          float *nrm, bool accum) {
+    // one 64 x EV_KC chunk of (centred) rows into LDS; rows given by `row(r)`
+    // (negative: padding); per-row partial squared norms into nrm
+    auto load_chunk = [&](float *dst, uint16_t *dh, uint16_t *dl, auto row_ptr, int k0, float *nrm, bool accum) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             int idx = tid + EV_T * u;
             int row = idx >> 4, qd = (idx & 15) * 4;
             float4 v = {0.f, 0.f, 0.f, 0.f};
             int kk = k0 + qd;
-            if (row < nrow && kk < dp) {
-                float4 x = *reinterpret_cast<const float4 *>(base + (int64_t)row * dp + kk);
+            const float *rp = row_ptr(row);
+            if (rp && kk < dp) {
+                float4 x = *reinterpret_cast<const float4 *>(rp + kk);
                 v.x = x.x - sC[kk];
                 v.y = x.y - sC[kk + 1];
                 v.z = x.z - sC[kk + 2];
@@ -128,142 +153,144 @@ __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
                 *reinterpret_cast<float4 *>(dst + row * EV_LD + qd) = v;
             }
             if (nrm) {
-                float s = v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
+                float s2 = v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
 #pragma unroll
-                for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o);
-                if ((idx & 15) == 0) nrm[row] = accum ? nrm[row] + s : s;
+                for (int o = 1; o < 16; o <<= 1) s2 += __shfl_xor(s2, o);
+                if ((idx & 15) == 0) nrm[row] = accum ? nrm[row] + s2 : s2;
             }
         }
     };
+    auto trow = [&](int r) -> const float * { return sRow[r] >= 0 ? Y + (int64_t)sRow[r] * dp : nullptr; };
 
-    // target norms (all chunks); the target chunk stays resident when dp <= EV_KC
-    for (int ch = 0; ch < nchunk; ++ch) {
-        load_chunk(sA, sAh, sAl, Yb, sb.nrows, ch * EV_KC, sAn, ch > 0);
+    // target norms (all dimension chunks); the target chunk stays resident when dp <= EV_KC
+    for (int c = 0; c < nchunk; ++c) {
+        load_chunk(sT, sTh, sTl, trow, c * EV_KC, sTn, c > 0);
         __syncthreads();
     }
 
-    float accu[16][RB];
+    f32x16 uacc[NACC];
+    float vacc[MC ? 1 : CM];
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
+    for (int q = 0; q < NACC; ++q) uacc[q] = f32x16{};
 #pragma unroll
-        for (int j = 0; j < RB; ++j) accu[r][j] = 0.0f;
+    for (int j = 0; j < (MC ? 1 : CM); ++j) vacc[j] = 0.0f;
 
-    const int e_near0 = p.ptr[slab], e_near1 = p.ptr[slab + 1];
-    const int e_far0 = p.ptr[p.nslab + 1 + slab], e_far1 = p.ptr[p.nslab + 2 + slab];
-    const int ne = (e_near1 - e_near0) + (e_far1 - e_far0);
-    for (int e = 0; e < ne; ++e) {
-        const bool near = e < e_near1 - e_near0;
-        const int eid = near ? e_near0 + e : e_far0 + (e - (e_near1 - e_near0));
-        const int a = p.node[eid];
-        const uint64_t msk = p.mask[eid];
-        const float *src, *g, *w;
-        int ns;
-        if (near) {
-            const Node nd = nodes[a];
-            ns = nd.hi - nd.lo;
-            src = Xt + (int64_t)nd.lo * dp;
-            g = gt + nd.lo;
-            w = Wt + (int64_t)nd.lo * p.R;
-        } else {
-            ns = skk[a];
-            src = Xs + (int64_t)a * smax * dp;
-            g = gs + (int64_t)a * smax;
-            w = Wsk + (int64_t)a * smax * p.R;
-        }
-        float mb[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            int row = rq + 8 * (r / 4) + 4 * half + (r % 4);
-            mb[r] = (float)((msk >> row) & 1ull);
-        }
-        for (int s0 = 0; s0 < ns; s0 += 64) {
-            const int nt = min(64, ns - s0);
-            f32x16 acc = {};
-            for (int ch = 0; ch < nchunk; ++ch) {
-                __syncthreads();
-                if (nchunk > 1) load_chunk(sA, sAh, sAl, Yb, sb.nrows, ch * EV_KC, nullptr, false);
-                load_chunk(sB, sBh, sBl, src + (int64_t)s0 * dp, nt, ch * EV_KC, sBn, ch > 0);
-                if (ch == 0 && tid < 64) {
-                    bool ok = tid < nt;
-                    sBg[tid] = ok ? g[s0 + tid] : 0.0f;
-#pragma unroll
-                    for (int j = 0; j < RB; ++j)
-                        sBw[tid * RB + j] = (ok && j < p.rb) ? w[(int64_t)(s0 + tid) * p.R + p.r0 + j] : 0.0f;
-                }
-                __syncthreads();
-                const int kc = min(EV_KC, dp - ch * EV_KC);
-                if constexpr (BF) {
-                    const uint16_t *ph = sAh + (rq + l32) * EV_LH + 8 * half;
-                    const uint16_t *pl = sAl + (rq + l32) * EV_LH + 8 * half;
-                    const uint16_t *qh = sBh + (cq + l32) * EV_LH + 8 * half;
-                    const uint16_t *ql = sBl + (cq + l32) * EV_LH + 8 * half;
-                    for (int k16 = 0; k16 < kc; k16 += 16) {
-                        bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(ph + k16));
-                        bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(pl + k16));
-                        bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(qh + k16));
-                        bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(ql + k16));
-                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
-                    }
-                } else {
-                    const float *pa = sA + (rq + l32) * EV_LD + 4 * half;
-                    const float *pb = sB + (cq + l32) * EV_LD + 4 * half;
-                    for (int g8 = 0; g8 < kc; g8 += 8) {
-                        float4 a4 = *reinterpret_cast<const float4 *>(pa + g8);
-                        float4 b4 = *reinterpret_cast<const float4 *>(pb + g8);
-                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, b4.x, acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, b4.y, acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, b4.z, acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, b4.w, acc, 0, 0, 0);
-                    }
+    for (int s0 = 0; s0 < ns; s0 += 64) {
+        const int nsrc = min(64, ns - s0);
+        auto srow = [&](int r) -> const float * { return r < nsrc ? src + (int64_t)(s0 + r) * dp : nullptr; };
+        f32x16 acc = {};
+        for (int c = 0; c < nchunk; ++c) {
+            __syncthreads();
+            if (nchunk > 1) load_chunk(sT, sTh, sTl, trow, c * EV_KC, nullptr, false);
+            load_chunk(sS, sSh, sSl, srow, c * EV_KC, sSn, c > 0);
+            if (c == 0) {
+                if (tid < 64) sSg[tid] = tid < nsrc ? g[s0 + tid] : 0.0f;
+                for (int e = tid; e < 64 * CM; e += EV_T) {
+                    const int r = e / CM, j = e % CM;
+                    sW[e] = (r < nsrc && j < p.rb) ? w[(int64_t)(s0 + r) * p.R + p.r0 + j] : 0.0f;
                 }
             }
-            const int col = cq + l32;
-            const float bn = sBn[col], bg = sBg[col];
-            float bw[RB];
+            __syncthreads();
+            const int kc = min(EV_KC, dp - c * EV_KC);
+            if constexpr (BF) {
+                const uint16_t *ph = sSh + (sq + l32) * EV_LH + 8 * half;
+                const uint16_t *pl = sSl + (sq + l32) * EV_LH + 8 * half;
+                const uint16_t *qh = sTh + (tq + l32) * EV_LH + 8 * half;
+                const uint16_t *ql = sTl + (tq + l32) * EV_LH + 8 * half;
+                for (int k16 = 0; k16 < kc; k16 += 16) {
+                    bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(ph + k16));
+                    bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(pl + k16));
+                    bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(qh + k16));
+                    bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(ql + k16));
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+                }
+            } else {
+                const float *pa = sS + (sq + l32) * EV_LD + 4 * half;
+                const float *pb = sT + (tq + l32) * EV_LD + 4 * half;
+                for (int g8 = 0; g8 < kc; g8 += 8) {
+                    float4 a4 = *reinterpret_cast<const float4 *>(pa + g8);
+                    float4 b4 = *reinterpret_cast<const float4 *>(pb + g8);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, b4.x, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, b4.y, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, b4.z, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, b4.w, acc, 0, 0, 0);
+                }
+            }
+        }
+        // kernel values: lane = target tq + l32, register r = source sq + 8(r/4) + 4 half + r%4
+        const float tn = sTn[tq + l32];
+        float kv[16];
 #pragma unroll
-            for (int j = 0; j < RB; ++j) bw[j] = sBw[col * RB + j];
+        for (int r = 0; r < 16; ++r) {
+            const int sr = sq + 8 * (r / 4) + 4 * half + (r % 4);
+            float r2;
+            if constexpr (BF)
+                r2 = (float)fmax((double)sSn[sr] + (double)tn - 2.0 * (double)acc[r], 0.0);
+            else
+                r2 = fmaxf(sSn[sr] + tn - 2.0f * acc[r], 0.0f);
+            kv[r] = exp2f(sSg[sr] * r2);
+        }
+        if constexpr (MC) {
+            // U^T (columns x targets) += W^T (columns x sources) K (sources x targets), two sources per step
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int row = rq + 8 * (r / 4) + 4 * half + (r % 4);
-                float r2;
-                if constexpr (BF)
-                    r2 = (float)fmax((double)sAn[row] + (double)bn - 2.0 * (double)acc[r], 0.0);
-                else
-                    r2 = fmaxf(sAn[row] + bn - 2.0f * acc[r], 0.0f);
-                float kv = exp2f(bg * r2) * mb[r];
+                const int sr = sq + 8 * (r / 4) + 4 * half + (r % 4);
 #pragma unroll
-                for (int j = 0; j < RB; ++j) accu[r][j] = fmaf(kv, bw[j], accu[r][j]);
+                for (int q = 0; q < NACC; ++q)
+                    uacc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(sW[sr * CM + 32 * q + l32], kv[r], uacc[q], 0,
+                                                                   0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int sr = sq + 8 * (r / 4) + 4 * half + (r % 4);
+#pragma unroll
+                for (int j = 0; j < CM; ++j) vacc[j] = fmaf(kv[r], sW[sr * CM + j], vacc[j]);
             }
         }
     }
-    // reduce over the 32 columns held by the lanes of each half, then over the two
-    // waves that share the same rows
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-#pragma unroll
-        for (int j = 0; j < RB; ++j) {
-            float v = accu[r][j];
-#pragma unroll
-            for (int o = 1; o < 32; o <<= 1) v += __shfl_xor(v, o);
-            accu[r][j] = v;
-        }
+
+    // combine the two waves that share the target columns, then write each
+    // target's partial sum into its slot
     __syncthreads();
-    if (l32 == 0) {
+    if constexpr (MC) {
+        if (sq == 0) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = rq + 8 * (r / 4) + 4 * half + (r % 4);
+            for (int q = 0; q < NACC; ++q)
 #pragma unroll
-            for (int j = 0; j < RB; ++j) sRed[wv & 1][row * RB + j] = accu[r][j];
+                for (int r = 0; r < 16; ++r) {
+                    const int col = 32 * q + 8 * (r / 4) + 4 * half + (r % 4);
+                    sRed[col * 64 + tq + l32] = uacc[q][r];
+                }
         }
-    }
-    __syncthreads();
-    for (int e = tid; e < sb.nrows * p.rb; e += EV_T) {
-        int row = e / p.rb, j = e % p.rb;
-        float v = sRed[0][row * RB + j] + sRed[1][row * RB + j];
-        int64_t orow = outmap ? outmap[sb.row0 + row] : (int64_t)sb.row0 + row;
-        p.U[orow * p.ldu + p.r0 + j] = v;
+        __syncthreads();
+        if (sq == 32) {
+            const int t = tq + l32;
+            const int slot = sSlot[t];
+#pragma unroll
+            for (int q = 0; q < NACC; ++q)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int col = 32 * q + 8 * (r / 4) + 4 * half + (r % 4);
+                    if (t < nt && col < p.rb)
+                        p.part[(int64_t)slot * p.R + p.r0 + col] = sRed[col * 64 + t] + uacc[q][r];
+                }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < CM; ++j) vacc[j] += __shfl_xor(vacc[j], 32);   // the two source halves
+        if (half == 0) {
+#pragma unroll
+            for (int j = 0; j < CM; ++j) sRed[((sq >> 5) * 64 + tq + l32) * CM + j] = vacc[j];
+        }
+        __syncthreads();
+        for (int e = tid; e < 64 * CM; e += EV_T) {
+            const int t = e / CM, j = e % CM;
+            if (t < nt && j < p.rb)
+                p.part[(int64_t)sSlot[t] * p.R + p.r0 + j] = sRed[t * CM + j] + sRed[(64 + t) * CM + j];
+        }
     }
   };
 
@@ -271,63 +298,29 @@ __global__ __launch_bounds__(EV_T) void k_eval(EvalParams p)
         process(blockIdx.x);
         return;
     }
-    // persistent: take slabs from the queue (largest first) until it is empty
+    // persistent: take chunks from the queue until it is empty
     for (;;) {
         __syncthreads();            // the previous item is done with the shared buffers
         if (tid == 0) sItem = atomicAdd(p.queue, 1);
         __syncthreads();
         const int64_t item = sItem;
-        if (item >= p.nslab) break;
-        process(p.order ? (int64_t)p.order[item] : item);
+        if (item >= p.nchunk) break;
+        process(item);
     }
 }
 
-void evaluate(askit_handle *h, const WeightSet &ws, const EvalArgs &a, hipStream_t s)
+// u[i, r] = sum of target i's slots, in slot order.
+__global__ void k_sum_slots(const int32_t *__restrict__ sbase, int64_t ntarget, const float *__restrict__ part,
+                            int R, const int32_t *__restrict__ outmap, float *__restrict__ U, int64_t ldu)
 {
-    if (h->dp > 1024) fail(ASKIT_ERR_UNSUPPORTED, "dimension above 1024 is not supported");
-    EvalParams p;
-    p.Y = a.Y;
-    p.slabs = a.slabs;
-    p.ptr = a.ptr;
-    p.node = a.node;
-    p.mask = a.mask;
-    p.outmap = a.outmap;
-    p.U = a.U;
-    p.ldu = a.ldu;
-    p.nslab = a.nslab;
-    p.nodes = h->d_nodes;
-    p.Xt = h->Xt;
-    p.gt = h->gt;
-    p.Wt = ws.Wt;
-    p.Xs = h->Xs;
-    p.gs = h->gs;
-    p.Wsk = ws.Wsk;
-    p.skk = h->skk;
-    p.smax = h->smax;
-    p.dp = h->dp;
-    p.R = ws.R;
-    p.inst = nullptr;
-    p.order = nullptr;
-    p.queue = nullptr;
-    p.persistent = 0;
-    if (a.nslab == 0) return;
-    const bool bf = h->prm.precision == ASKIT_PREC_BF16X3;
-    for (int r0 = 0; r0 < ws.R; r0 += EV_RB) {
-        p.r0 = r0;
-        p.rb = std::min(EV_RB, ws.R - r0);
-        dim3 g((unsigned)a.nslab), b(EV_T);
-        if (p.rb == 1) {
-            if (bf) hipLaunchKernelGGL((k_eval<1, true, false>), g, b, 0, s, p);
-            else hipLaunchKernelGGL((k_eval<1, false, false>), g, b, 0, s, p);
-        } else if (p.rb <= 4) {
-            if (bf) hipLaunchKernelGGL((k_eval<4, true, false>), g, b, 0, s, p);
-            else hipLaunchKernelGGL((k_eval<4, false, false>), g, b, 0, s, p);
-        } else {
-            if (bf) hipLaunchKernelGGL((k_eval<EV_RB, true, false>), g, b, 0, s, p);
-            else hipLaunchKernelGGL((k_eval<EV_RB, false, false>), g, b, 0, s, p);
-        }
-        HIPC(hipGetLastError());
-    }
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / R;
+    if (i >= ntarget) return;
+    const int r = (int)(t - i * R);
+    float u = 0.0f;
+    for (int sl = sbase[i]; sl < sbase[i + 1]; ++sl) u += part[(int64_t)sl * R + r];
+    const int64_t o = outmap ? outmap[i] : i;
+    U[o * ldu + r] = u;
 }
 
 __global__ void k_zero_i32(int32_t *__restrict__ p, int n)
@@ -336,47 +329,88 @@ __global__ void k_zero_i32(int32_t *__restrict__ p, int n)
     if (i < n) p[i] = 0;
 }
 
+template <bool MULTI>
+static void launch_passes(ChunkParams p, bool bf, int R, int64_t grid, int32_t *queue, hipStream_t s)
+{
+    // passes of 64, 32, 4 or 1 columns
+    for (int r0 = 0; r0 < R;) {
+        const int left = R - r0;
+        const int cm = left > 32 ? 64 : left > 4 ? 32 : left > 1 ? 4 : 1;
+        p.r0 = r0;
+        p.rb = std::min(cm, left);
+        p.queue = queue;
+        if (MULTI && p.persistent) {
+            hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, queue, 1);
+            HIPC(hipGetLastError());
+        }
+        dim3 g((unsigned)grid), b(EV_T);
+#define EV_LAUNCH(CMV)                                                                             \
+    if (bf) hipLaunchKernelGGL((k_eval_chunks<CMV, true, MULTI>), g, b, 0, s, p);                 \
+    else hipLaunchKernelGGL((k_eval_chunks<CMV, false, MULTI>), g, b, 0, s, p);
+        if (cm == 1) { EV_LAUNCH(1) }
+        else if (cm == 4) { EV_LAUNCH(4) }
+        else if (cm == 32) { EV_LAUNCH(32) }
+        else { EV_LAUNCH(64) }
+#undef EV_LAUNCH
+        HIPC(hipGetLastError());
+        r0 += p.rb;
+    }
+}
+
+void evaluate(const askit_handle *h, const WeightSet &ws, const float *Y, const PairLists &L,
+              const int32_t *outmap, float *U, int64_t ldu, float *part, hipStream_t s)
+{
+    if (h->dp > 1024) fail(ASKIT_ERR_UNSUPPORTED, "dimension above 1024 is not supported");
+    if (L.ntarget == 0) return;
+    if (L.nchunk > 0) {
+        ChunkParams p{};
+        p.chunks = L.chunks;
+        p.nchunk = L.nchunk;
+        p.tpos = L.tpos;
+        p.tslot = L.tslot;
+        p.nodes = h->d_nodes;
+        p.Y = Y;
+        p.Xt = h->Xt;
+        p.gt = h->gt;
+        p.Xs = h->Xs;
+        p.gs = h->gs;
+        p.skk = h->skk;
+        p.smax = h->smax;
+        p.dp = h->dp;
+        p.Wt = ws.Wt;
+        p.Wsk = ws.Wsk;
+        p.part = part;
+        p.R = ws.R;
+        launch_passes<false>(p, h->prm.precision == ASKIT_PREC_BF16X3, ws.R, L.nchunk, nullptr, s);
+    }
+    const int64_t tot = L.ntarget * ws.R;
+    hipLaunchKernelGGL(k_sum_slots, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L.sbase, L.ntarget, part,
+                       ws.R, outmap, U, ldu);
+    HIPC(hipGetLastError());
+}
+
 void evaluate_batch(const BatchEvalArgs &b, hipStream_t s)
 {
-    if (b.nslab == 0) return;
-    EvalParams p{};
-    p.slabs = b.slabs;
-    p.ptr = b.ptr;
-    p.node = b.node;
-    p.mask = b.mask;
-    p.nslab = b.nslab;
-    p.U = b.U;
-    p.ldu = b.ldu;
-    p.Wt = b.Wt;
-    p.Wsk = b.Wsk;
-    p.R = b.R;
-    p.inst = b.inst;
-    p.order = b.order;
-    p.persistent = b.persistent > 0;
-    const int passes = (b.R + EV_RB - 1) / EV_RB;
-    if (p.persistent) {
-        // counters are cleared by a kernel, not a memset node, so that the
-        // sequence can be captured in a graph and replayed
-        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, b.queue, passes);
-        HIPC(hipGetLastError());
+    if (b.rows == 0) return;
+    if (b.nchunk > 0) {
+        ChunkParams p{};
+        p.chunks = b.chunks;
+        p.nchunk = b.nchunk;
+        p.tpos = b.tpos;
+        p.tslot = b.tslot;
+        p.inst = b.inst;
+        p.persistent = b.persistent > 0;
+        p.Wt = b.Wt;
+        p.Wsk = b.Wsk;
+        p.part = b.part;
+        p.R = b.R;
+        const int64_t grid = p.persistent ? std::min<int64_t>(b.persistent, b.nchunk) : b.nchunk;
+        launch_passes<true>(p, b.bf, b.R, grid, b.queue, s);
     }
-    for (int r0 = 0, pass = 0; r0 < b.R; r0 += EV_RB, ++pass) {
-        p.r0 = r0;
-        p.rb = std::min(EV_RB, b.R - r0);
-        p.queue = b.queue ? b.queue + pass : nullptr;
-        dim3 g((unsigned)(p.persistent ? std::min<int64_t>(b.persistent, b.nslab) : b.nslab)), blk(EV_T);
-        if (p.rb == 1) {
-            if (b.bf) hipLaunchKernelGGL((k_eval<1, true, true>), g, blk, 0, s, p);
-            else hipLaunchKernelGGL((k_eval<1, false, true>), g, blk, 0, s, p);
-        } else if (p.rb <= 4) {
-            if (b.bf) hipLaunchKernelGGL((k_eval<4, true, true>), g, blk, 0, s, p);
-            else hipLaunchKernelGGL((k_eval<4, false, true>), g, blk, 0, s, p);
-        } else {
-            if (b.bf) hipLaunchKernelGGL((k_eval<EV_RB, true, true>), g, blk, 0, s, p);
-            else hipLaunchKernelGGL((k_eval<EV_RB, false, true>), g, blk, 0, s, p);
-        }
-        HIPC(hipGetLastError());
-    }
+    const int64_t tot = b.rows * b.R;
+    hipLaunchKernelGGL(k_sum_slots, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.sbase, b.rows, b.part,
+                       b.R, b.outrow, b.U, b.ldu);
+    HIPC(hipGetLastError());
 }
 
 }  // namespace askit

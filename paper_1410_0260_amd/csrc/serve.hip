@@ -77,12 +77,14 @@ struct askit_server {
     uint64_t weights_bytes(int32_t R) const
     {
         const int64_t nn = (int64_t)h->nodes.size();
-        return (uint64_t)R * (uint64_t)(12 * h->N + 4 * nn * h->smax) + (1u << 20);
+        return (uint64_t)R * (uint64_t)(12 * h->N + 4 * nn * h->smax + 4 * h->pairs.npairs) + (1u << 20);
     }
     uint64_t query_bytes(int64_t M) const
     {
-        return (uint64_t)M * (uint64_t)(24 * h->dp + 28 * h->kappa + 4 * KNN_CAND * 2 + 2048 +
-                                        4 * ws0.R) + (4u << 20);
+        // per query: points, kNN work, lists, and its pairs (about npairs / N of them)
+        const int64_t ppq = h->pairs.npairs / std::max<int64_t>(h->N, 1) + 1;
+        return (uint64_t)M * (uint64_t)(24 * h->dp + 28 * h->kappa + 4 * KNN_CAND * 2 + 2048 + 4 * ws0.R +
+                                        ppq * (8 + 4 * ws0.R + 40)) + (4u << 20);
     }
     void worker_loop(int wid);
     void run_batch(std::vector<Request> &b, hipStream_t s);
@@ -137,17 +139,8 @@ void askit_server::run_batch(std::vector<Request> &b, hipStream_t s)
         }
         permute_weights(h, Wb, R, ws, s);
         upward(h, ws, s);
-        EvalArgs a;
-        a.Y = h->Xt;
-        a.nslab = (int64_t)h->slabs.size();
-        a.slabs = h->d_slabs;
-        a.ptr = h->sl_ptr;
-        a.node = h->sl_node;
-        a.mask = h->sl_mask;
-        a.outmap = h->perm;
-        a.U = Ub;
-        a.ldu = R;
-        evaluate(h, ws, a, s);
+        float *part = (float *)ta(sizeof(float) * std::max<int64_t>(h->pairs.npairs, 1) * R);
+        evaluate(h, ws, h->Xt, h->pairs, h->perm, Ub, R, part, s);
         off = 0;
         for (auto &r : b) {
             HIPC(hipMemcpy2DAsync(r.out, sizeof(float) * r.ld_out, Ub + off, sizeof(float) * R,

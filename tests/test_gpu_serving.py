@@ -67,8 +67,8 @@ def test_serving_memory_admission():
     A, h, X = _setup(N=40000)
     N = X.shape[0]
     W0 = synth.weights(N, 1, 5)
-    nn = h.info()["num_nodes"]
-    col = 12 * N + 4 * nn * 48                       # the server's estimate per weight column
+    nn, npairs = h.info()["num_nodes"], h.info()["eval_pairs"]
+    col = 12 * N + 4 * nn * 48 + 4 * npairs          # the server's estimate per weight column
     req = 2 * col + (1 << 20)                        # ... for one request of 2 columns
     cfg = A.server_config(workers=2, max_batch_rhs=64, mem_budget=int(1.5 * req))
     srv = A.Server(h, torch.from_numpy(W0).cuda(), cfg)
