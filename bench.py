@@ -364,6 +364,10 @@ def main():
     ap.add_argument("--serve-mem-gib", type=int, default=64)
     ap.add_argument("--serve-budget-s", type=float, default=20.0, help="GPU work per serving replay")
     ap.add_argument("--batched-rhs", type=int, default=1)
+    ap.add_argument("--set", action="append", default=[], metavar="FIELD=VALUE",
+                    help="change one workload parameter (e.g. h=0.5, smax=128); the line then names it")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"],
+                    help="distance products: FP32, or bf16 hi/lo split products (precision form)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
@@ -377,6 +381,14 @@ def main():
         print(json.dumps(batched_bench(args, A, torch)))
         return
     wl = WORKLOADS[args.workload]()
+    if args.set:
+        import dataclasses
+        ch = {}
+        for kv in args.set:
+            k, v = kv.split("=", 1)
+            ch[k] = type(getattr(wl, k))(v)
+        wl = dataclasses.replace(wl, **ch)
+        wl = dataclasses.replace(wl, name=wl.name + " [" + ", ".join(args.set) + "]")
     if args.workload == "serving_4m":
         print(json.dumps(serve_bench(args, wl, A, torch)))
         return
@@ -385,7 +397,7 @@ def main():
     W = synth.weights(wl.N, wl.R, wl.seed)
     Xd = torch.from_numpy(X).cuda()
     Wd = torch.from_numpy(W).cuda()
-    prm = A.params_from_workload(wl)
+    prm = A.params_from_workload(wl, A.PREC_BF16X3 if args.precision == "bf16x3" else A.PREC_FP32)
     U = torch.empty((wl.N, wl.R), device="cuda", dtype=torch.float32)
     stream = torch.cuda.current_stream()
 
@@ -440,19 +452,26 @@ def main():
     eps = [float(np.linalg.norm(Ug[:, r] - Ud[:, r]) / np.linalg.norm(Ud[:, r])) for r in range(wl.R)]
     h.close()
 
-    # roofline of the dominant kernel: the kNN filter sweep (bf16 hi/lo MFMA)
+    # roofline of the dominant kernel: the kNN distance sweep (bf16 hi/lo MFMA):
+    # the filter kernel where the sweep runs as window + filter, else the
+    # candidate-list kernel over all rows (wide rows or small N)
     launches = int(infos[-1]["knn_filter_launches"])
-    if launches < 1:
-        raise SystemExit("the kNN filter sweep did not run for this workload")
-    filt_ms = float(np.mean([i_["t_knn_filter_ms"] / i_["knn_filter_launches"] for i_ in infos]))
+    if launches >= 1:
+        sweep_ms = float(np.mean([i_["t_knn_filter_ms"] / i_["knn_filter_launches"] for i_ in infos]))
+        kname = "k_knn_filter (bf16 hi/lo split distance sweep, threshold filter)"
+    else:
+        launches = 1
+        sweep_ms = float(np.mean([i_["t_knn_sweep_ms"] for i_ in infos]))
+        kname = ("k_knn_cand_wide (bf16 hi/lo split distance sweep, top-64 lists)" if wl.d > 128
+                 else "k_knn_cand (bf16 hi/lo split distance sweep, top-64 lists)")
     alg_flops = 2.0 * (wl.N / launches) * wl.N * wl.d        # every row against every point
-    achieved = alg_flops / (filt_ms * 1e-3) / 1e12
-    roof = {"kernel": "k_knn_filter (bf16 hi/lo split distance sweep, threshold filter)", "bound": "mfma",
+    achieved = alg_flops / (sweep_ms * 1e-3) / 1e12
+    roof = {"kernel": kname, "bound": "mfma",
             "achieved": achieved, "peak": PEAK["bf16"], "unit": "TFLOP/s",
-            "frac": achieved / PEAK["bf16"], "traffic": traffic_of("k_knn_filter"),
-            "algorithmic_flops_per_launch": alg_flops, "avg_launch_ms": filt_ms, "launches_per_step": launches,
-            "note": ("algorithmic flops 2 N^2 d per step (one launch covers every row at this N); each "
-                     "algorithmic product costs 3 bf16 MFMA products (hi*hi, hi*lo, lo*hi)")}
+            "frac": achieved / PEAK["bf16"], "traffic": traffic_of("k_knn_filter") if "filter" in kname else None,
+            "algorithmic_flops_per_launch": alg_flops, "avg_launch_ms": sweep_ms, "launches_per_step": launches,
+            "note": ("algorithmic flops 2 N^2 d per step; each algorithmic product costs 3 bf16 MFMA "
+                     "products (hi*hi, hi*lo, lo*hi)")}
     ev_pairs = info["near_pairs"] + info["far_pairs"]
     ev_kernel_ms = float(np.median(ev_ms))
     ev_flops = ev_pairs * (2.0 * wl.d + 3.0 + 2.0 * wl.R)
@@ -472,9 +491,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32" else "bf16x3 products, f32 accumulation",
         "data": "synthetic",
         "config": {"workload": wl.name, "N": wl.N, "d": wl.d, "m": wl.m, "kappa": wl.kappa,
+                   "precision": args.precision,
                    "s_max": wl.smax, "l": wl.ell_eff, "tau": wl.tau, "h": wl.h, "nrhs": wl.R,
                    "parallelism": "single GPU"},
         "amortized": {"value": wl.N * wl.R / (ms_amort * 1e-3), "ms_update_plus_evaluate": ms_amort,

@@ -143,13 +143,14 @@ void query_points(askit_handle *h, const WeightSet &ws, const float *Y, int64_t 
     split_bf16(Yp, M, dp, Yh, Yl, Yn, s);
     knn_candidates(Yh, Yl, Yn, M, h->Xh, h->Xl, h->Xn, h->N, dp, false, false, cand, thr, flag + 1,
                    flag, s);
+    float *tb = (float *)ta(sizeof(float) * M);
     knn_refine(Yp, M, h->Xt, h->N, h->d, dp, kappa, cand, thr, Yn, h->maxnorm, h->perm, nullptr, qidx,
-               qd, flag + 1, flag, s);
+               qd, flag + 1, flag, tb, s);
     int32_t nbad = 0;
     HIPC(hipMemcpyAsync(&nbad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    knn_exact_rows(Yp, h->Xt, h->N, h->d, dp, kappa, false, flag + 1, nbad, h->perm, nullptr, qidx,
-                   qd, s);
+    knn_fallback(Yp, Yh, Yl, Yn, h->Xt, h->Xh, h->Xl, h->Xn, h->N, h->d, dp, kappa, false, flag + 1, nbad, tb,
+                 h->perm, nullptr, qidx, qd, s);
     hipLaunchKernelGGL(k_map_pos, dim3((unsigned)((M * kappa + 255) / 256)), dim3(256), 0, s, qidx,
                        M * kappa, h->iperm, nb);
     HIPC(hipGetLastError());
@@ -415,8 +416,10 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
                        bad + 1, bad, s, &fms, &h->knn_filter_launches);
         h->t_knn_filter = fms;
         HIPC(hipEventRecord(k1, s));
+        float *tb;
+        HIPC(hipMallocAsync((void **)&tb, sizeof(float) * N, s));
         knn_refine(h->Xt, N, h->Xt, N, d, dp, kappa, cand, thr, h->Xn, mx, h->perm, h->perm,
-                   h->knn_idx, h->knn_d, bad + 1, bad, s);
+                   h->knn_idx, h->knn_d, bad + 1, bad, tb, s);
         int32_t nbad = 0;
         HIPC(hipMemcpyAsync(&nbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
@@ -426,8 +429,9 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
         h->t_knn_sweep = kms;
         (void)hipEventDestroy(k0);
         (void)hipEventDestroy(k1);
-        knn_exact_rows(h->Xt, h->Xt, N, d, dp, kappa, true, bad + 1, nbad, h->perm, h->perm,
-                       h->knn_idx, h->knn_d, s);
+        knn_fallback(h->Xt, h->Xh, h->Xl, h->Xn, h->Xt, h->Xh, h->Xl, h->Xn, N, d, dp, kappa, true, bad + 1, nbad,
+                     tb, h->perm, h->perm, h->knn_idx, h->knn_d, s);
+        HIPC(hipFreeAsync(tb, s));
         HIPC(hipFreeAsync(cand, s));
         HIPC(hipFreeAsync(thr, s));
         HIPC(hipFreeAsync(bad, s));

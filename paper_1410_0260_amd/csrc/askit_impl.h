@@ -194,7 +194,14 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
 void knn_refine(const float *Q, int64_t M, const float *X, int64_t N, int d, int dp, int kappa,
                 const int32_t *cand, const float *thr, const float *Qn, float maxnorm,
                 const int32_t *idmap, const int32_t *rowmap, int32_t *idx, double *dist,
-                int32_t *bad_rows, int32_t *bad_count, hipStream_t s);
+                int32_t *bad_rows, int32_t *bad_count, float *tbound, hipStream_t s);
+// Exact lists of the rows refine could not certify: threshold sweep at each
+// row's bound (tbound), FP64 re-rank of the survivors, full scan for rows whose
+// survivors overflow.
+void knn_fallback(const float *Q, const uint16_t *Qh, const uint16_t *Ql, const float *Qn, const float *X,
+                  const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int d, int dp, int kappa,
+                  bool exclude_self, const int32_t *rows, int nrows, const float *tbound, const int32_t *idmap,
+                  const int32_t *rowmap, int32_t *idx, double *dist, hipStream_t s);
 void knn_exact_rows(const float *Q, const float *X, int64_t N, int d, int dp, int kappa,
                     bool exclude_self, const int32_t *rows, int nrows, const int32_t *idmap,
                     const int32_t *rowmap, int32_t *idx, double *dist, hipStream_t s);

@@ -3,10 +3,10 @@
 // Work item: a chunk of up to 64 targets that all use one source node
 // (near: a leaf's points and weights; far: a pruned node's skeleton points
 // and skeleton weights).  Sources are taken in tiles of 64:
-//   r^2 = |x - c|^2 + |y - c|^2 - 2 (x - c).(y - c),  c = the source node's
-//   first point (the sources are compact around it, and the rounding error
-//   of r^2 then grows with r^2 itself, which the kernel damps; every pair's
-//   value is also independent of the other targets in the chunk),
+//   r^2 = |x - c|^2 + |y - c|^2 - 2 (x - c).(y - c),  c = the chunk's first
+//   target: the rounding error of r^2 is a few ulps of |x - c|^2 + |y - c|^2,
+//   small where the kernel is not (a skeleton can span distant clusters, so
+//   a point of the source node would not do),
 // with the 64 x 64 products on MFMA, sources as the rows and targets as the
 // columns (v_mfma_f32_32x32x2_f32, or the bf16 hi/lo split on
 // v_mfma_f32_32x32x16_bf16 with an FP64 final combine), each wave one
@@ -123,7 +123,12 @@ __global__ __launch_bounds__(EV_T) void k_eval_chunks(ChunkParams p)
         sSlot[tid] = tid < nt ? p.tslot[ch.first + tid] : -1;
     }
     __syncthreads();
-    for (int k = tid; k < dp; k += EV_T) sC[k] = src[k];      // centre: the source node's first point
+    {
+        // centre: the chunk's first target (the targets of a chunk are close to
+        // one another; sources far from them have negligible kernel values)
+        const float *c0 = Y + (int64_t)sRow[0] * dp;
+        for (int k = tid; k < dp; k += EV_T) sC[k] = c0[k];
+    }
     __syncthreads();
 
     // one 64 x EV_KC chunk of (centred) rows into LDS; rows given by `row(r)`

@@ -481,7 +481,15 @@ __global__ __launch_bounds__(256) void k_knn_cand_wide(const uint16_t *__restric
 // approximate distance, from the window pass, slightly widened) is appended
 // to the row's segment of `out` (capacity cap; count in ocnt).  Same MFMA
 // arithmetic and pipelining as k_knn_cand, without per-row lists.
-template <int KS>
+// SYM (the point set against itself, all rows in one launch): the block of
+// rows [128 b, 128 b + 128) sweeps only the tiles from its own onwards, and a
+// distance of a later tile's point j to row i is also offered to row j
+// (appended to j's segment when it is at most T_j), so every unordered pair
+// is computed once.  Survivors are then in no particular order, and a row
+// may keep fewer than 64 of the window's points (their distances can come
+// from the transposed product, rounded differently); the selection and its
+// certificate allow both.
+template <int KS, bool SYM>
 __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restrict__ Qh,
                                                        const uint16_t *__restrict__ Ql,
                                                        const float *__restrict__ Qn, int64_t M,
@@ -500,6 +508,7 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     __shared__ __attribute__((aligned(16))) uint16_t sBh[3 * TB];
     __shared__ __attribute__((aligned(16))) uint16_t sBl[3 * TB];
     __shared__ float sBn[3 * KB_N];
+    __shared__ float sBt[SYM ? 3 * KB_N : 1];       // SYM: thresholds of the tile's points
 
     const int tid = threadIdx.x, lane = tid % WAVE;
     const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
@@ -531,8 +540,9 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     // 32-bit row indices (M < 2^31) keep the survivor path's state small
     const uint32_t qbase = (uint32_t)q0 + 4u * (uint32_t)half;
     const int64_t ntiles_all = (N + KB_N - 1) / KB_N;
-    const int64_t ntiles = ntiles_all;
-    const int64_t t0 = ((row0 + (int64_t)blockIdx.x * KB_M) / KB_N) % ntiles_all;
+    const int64_t tself = ((row0 + (int64_t)blockIdx.x * KB_M) / KB_N) % ntiles_all;   // the block's own tile
+    const int64_t ntiles = SYM ? ntiles_all - tself : ntiles_all;
+    const int64_t t0 = tself;
     constexpr int CHUNKS = KB_N * DP / 8;
     constexpr int PER = (CHUNKS + 255) / 256;
     uint4 rh[1][PER], rl[1][PER];
@@ -542,6 +552,18 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
         return tt >= ntiles_all ? tt - ntiles_all : tt;
     };
     KNN_TILE_IO();
+    float rt = -INFINITY;
+    auto load_thr = [&](int64_t tt) {
+        if constexpr (SYM) {
+            const int64_t g = tt * KB_N + tid;
+            rt = (tid < KB_N && g < N) ? Tin[g] : -INFINITY;
+        }
+    };
+    auto store_thr = [&](int b) {
+        if constexpr (SYM) {
+            if (tid < KB_N) sBt[b * KB_N + tid] = rt;
+        }
+    };
     auto mfma_tile = [&](int b, f32x16 &acc0, f32x16 &acc1) {
         const uint16_t *ph = sBh + b * TB, *pl = sBl + b * TB;
         acc0 = f32x16{};
@@ -561,10 +583,14 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
         }
     };
     load_tile(0, tile_of(0));
+    load_thr(tile_of(0));
     store_tile(0, 0);
+    store_thr(0);
     if (ntiles > 1) {
         load_tile(0, tile_of(1));
+        load_thr(tile_of(1));
         store_tile(0, 1);
+        store_thr(1);
     }
     __syncthreads();
     f32x16 accA0, accA1, accB0, accB1;
@@ -573,7 +599,10 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     // (t+1)%3; the points of tile t+2 are loaded and stored to buffer (t+2)%3
     auto iter = [&](auto CUR, int64_t t, f32x16 &c0, f32x16 &c1, f32x16 &n0, f32x16 &n1) {
         const int64_t tbase = tile_of(t) * KB_N;
-        if (t + 2 < ntiles) load_tile(0, tile_of(t + 2));
+        if (t + 2 < ntiles) {
+            load_tile(0, tile_of(t + 2));
+            load_thr(tile_of(t + 2));
+        }
         if (t + 1 < ntiles) mfma_tile((int)((t + 1) % 3), n0, n1);
         // <= keeps the window's own 64 points (same arithmetic as the window pass)
         const float *nb = sBn + (t % 3) * KB_N;
@@ -608,7 +637,48 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
                 }
             }
         }
-        if (t + 2 < ntiles) store_tile(0, (int)((t + 2) % 3));
+        if constexpr (SYM) {
+            // tiles after the block's own two: offer each distance to the tile's point too
+            if (t >= 2) {
+                const float *tb = sBt + (t % 3) * KB_N;
+                const float tA = tb[l32], tB = tb[32 + l32];
+                bool anyc = false;
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    anyc |= (fmaf(-2.0f, c0[r], qn[r] + ny0) <= tA) | (fmaf(-2.0f, c1[r], qn[r] + ny1) <= tB);
+                if (__ballot(anyc)) {
+                    const uint32_t cA = (uint32_t)tbase + (uint32_t)l32, cB = cA + 32u;
+                    const uint32_t m32 = (uint32_t)M;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const uint32_t qrow = qbase + (uint32_t)(8 * (r / 4) + (r % 4));
+                        if (qrow >= m32) continue;
+                        const float dA = fmaf(-2.0f, c0[r], qn[r] + ny0);
+                        const float dB = fmaf(-2.0f, c1[r], qn[r] + ny1);
+                        if (dA <= tA) {
+                            uint32_t p = (uint32_t)atomicAdd(&ocnt[cA], 1);
+                            if (p < (uint32_t)cap) {
+                                const size_t o = (size_t)cA * (uint32_t)cap + p;
+                                od[o] = dA;
+                                oi[o] = (int32_t)qrow;
+                            }
+                        }
+                        if (dB <= tB) {
+                            uint32_t p = (uint32_t)atomicAdd(&ocnt[cB], 1);
+                            if (p < (uint32_t)cap) {
+                                const size_t o = (size_t)cB * (uint32_t)cap + p;
+                                od[o] = dB;
+                                oi[o] = (int32_t)qrow;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        if (t + 2 < ntiles) {
+            store_tile(0, (int)((t + 2) % 3));
+            store_thr((int)((t + 2) % 3));
+        }
         __syncthreads();
     };
     for (int64_t t = 0; t < ntiles; t += 2) {
@@ -618,8 +688,8 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
 }
 
 // Per row (one wave): the 64 smallest (approximate distance, position) of the
-// filter's output, as candidates + the 64th value as threshold.  Rows whose
-// segment overflowed are sent to the exact fallback.
+// filter's output, as candidates + the certificate threshold.  Rows whose
+// segment overflowed are listed for the retry sweep.
 __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int cap,
                                                     const int32_t *__restrict__ ocnt,
                                                     const float *__restrict__ od,
@@ -634,6 +704,7 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
     if (lrow >= M) return;
     const int64_t row = row0 + lrow;
     const int n = ocnt[lrow];
+    const float tin = thr[row];          // the filter threshold: every point left out is above it
     float ld = INFINITY;
     int li = 0x7fffffff;
     if (n > cap) {
@@ -650,8 +721,10 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
         }
     }
     cand[row * KNN_CAND + lane] = li == 0x7fffffff ? -1 : li;
+    // bound for the points outside the candidates: the 64th survivor, or the
+    // filter threshold when fewer than 64 points survived
     float th = __shfl(ld, 63);
-    if (lane == 0) thr[row] = th;
+    if (lane == 0) thr[row] = n >= 64 ? th : tin;
 }
 
 template <int KS>
@@ -668,10 +741,14 @@ template <int KS>
 static void launch_filter(dim3 g, dim3 b, hipStream_t s, const uint16_t *Qh, const uint16_t *Ql,
                           const float *Qn, int64_t M, const uint16_t *Xh, const uint16_t *Xl,
                           const float *Xn, int64_t N, int ex, int64_t row0, const float *T, int cap,
-                          int32_t *ocnt, float *od, int32_t *oi)
+                          int32_t *ocnt, float *od, int32_t *oi, bool sym)
 {
-    hipLaunchKernelGGL(k_knn_filter<KS>, g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, row0, T, cap, ocnt,
-                       od, oi);
+    if (sym)
+        hipLaunchKernelGGL((k_knn_filter<KS, true>), g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, row0, T, cap,
+                           ocnt, od, oi);
+    else
+        hipLaunchKernelGGL((k_knn_filter<KS, false>), g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, row0, T,
+                           cap, ocnt, od, oi);
 }
 
 __global__ void k_widen(float *__restrict__ T, int64_t M)
@@ -725,7 +802,11 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     KNN_DISPATCH(launch_cand, grid, block, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, WIN,
                  (const int32_t *)nullptr, cand, thr);
     hipLaunchKernelGGL(k_widen, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M);
-    const int64_t mc = std::min<int64_t>(M, CHUNK);
+    // the point set against itself with every row's segment in one buffer:
+    // one triangular sweep (each unordered pair once); else row chunks
+    const bool sym = exclude_self && Qh == Xh && M == N && (double)N * CAP * 8.0 <= 48.0 * (1ull << 30);
+    const int64_t chunk = sym ? M : CHUNK;
+    const int64_t mc = std::min<int64_t>(M, chunk);
     int32_t *ocnt, *oi, *retry;
     float *od;
     HIPC(hipMallocAsync((void **)&ocnt, sizeof(int32_t) * mc, s));
@@ -734,8 +815,8 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     HIPC(hipMallocAsync((void **)&retry, sizeof(int32_t) * (M + 1), s));
     HIPC(hipMemsetAsync(retry, 0, sizeof(int32_t), s));
     std::vector<hipEvent_t> ev;             // brackets of each filter launch (timing only)
-    for (int64_t r0 = 0; r0 < M; r0 += CHUNK) {
-        const int64_t m = std::min<int64_t>(CHUNK, M - r0);
+    for (int64_t r0 = 0; r0 < M; r0 += chunk) {
+        const int64_t m = std::min<int64_t>(chunk, M - r0);
         dim3 g((unsigned)((m + KB_M - 1) / KB_M));
         HIPC(hipMemsetAsync(ocnt, 0, sizeof(int32_t) * m, s));
         if (t_filter_ms) {
@@ -745,7 +826,7 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
             HIPC(hipEventRecord(ev[ev.size() - 2], s));
         }
         KNN_DISPATCH(launch_filter, g, block, s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, CAP, ocnt, od,
-                     oi);
+                     oi, sym);
         if (t_filter_ms) HIPC(hipEventRecord(ev.back(), s));
         hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, CAP, ocnt,
                            od, oi, cand, thr, retry + 1, retry);
@@ -801,7 +882,8 @@ __global__ __launch_bounds__(256) void k_knn_refine(const float *__restrict__ Q,
                                                     int32_t *__restrict__ idx,
                                                     double *__restrict__ dist,
                                                     int32_t *__restrict__ bad_rows,
-                                                    int32_t *__restrict__ bad_count)
+                                                    int32_t *__restrict__ bad_count,
+                                                    float *__restrict__ tbound)
 {
     int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
     int lane = threadIdx.x % WAVE;
@@ -838,20 +920,26 @@ __global__ __launch_bounds__(256) void k_knn_refine(const float *__restrict__ Q,
     if (!ok && lane == 0) {
         int p = atomicAdd(bad_count, 1);
         bad_rows[p] = (int32_t)row;
+        // every true neighbour has an approximate distance <= Dk + E: the
+        // threshold of the filtered fallback, rounded up to FP32
+        const double b = Dk + E;
+        float f = (float)b;
+        if ((double)f < b) f = __uint_as_float(__float_as_uint(f) + 1u);   // next float up (b >= 0)
+        tbound[row] = f;
     }
 }
 
 void knn_refine(const float *Q, int64_t M, const float *X, int64_t N, int d, int dp, int kappa,
                 const int32_t *cand, const float *thr, const float *Qn, float maxnorm,
                 const int32_t *idmap, const int32_t *rowmap, int32_t *idx, double *dist,
-                int32_t *bad_rows, int32_t *bad_count, hipStream_t s)
+                int32_t *bad_rows, int32_t *bad_count, float *tbound, hipStream_t s)
 {
     // |approx - exact| <= g (|q|^2 + |x|^2) with g = 3.1 2^-16 (hi/lo split) +
     // (4 dp + 8) 2^-24 (FP32 accumulation, norms, final combine); doubled.
     double g = 2.0 * (3.1 * ldexp(1.0, -16) + (4.0 * dp + 8.0) * ldexp(1.0, -24));
     hipLaunchKernelGGL(k_knn_refine, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, s, Q, M, X, N, d,
                        dp, kappa, cand, thr, Qn, (double)maxnorm * (1.0 + 1e-5), g, idmap, rowmap, idx,
-                       dist, bad_rows, bad_count);
+                       dist, bad_rows, bad_count, tbound);
     HIPC(hipGetLastError());
 }
 
@@ -932,6 +1020,232 @@ void knn_exact_rows(const float *Q, const float *X, int64_t N, int d, int dp, in
     hipLaunchKernelGGL(k_knn_exact, dim3(nrows), dim3(KX_T), sh, s, Q, X, N, d, dp, kappa,
                        exclude_self ? 1 : 0, rows, idmap, rowmap, idx, dist);
     HIPC(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- filtered fallback
+// Threshold sweep for rows wider than 128 dimensions (dimension chunks of
+// 128 through LDS, as k_knn_cand_wide): every point whose approximate
+// distance to row i is at most T_i is appended to the row's segment.
+__global__ __launch_bounds__(256) void k_knn_filter_wide(const uint16_t *__restrict__ Qh,
+                                                         const uint16_t *__restrict__ Ql,
+                                                         const float *__restrict__ Qn, int64_t M,
+                                                         const uint16_t *__restrict__ Xh,
+                                                         const uint16_t *__restrict__ Xl,
+                                                         const float *__restrict__ Xn, int64_t N, int dp,
+                                                         const float *__restrict__ Tin, int cap,
+                                                         int32_t *__restrict__ ocnt, float *__restrict__ od,
+                                                         int32_t *__restrict__ oi)
+{
+    constexpr int KC = 128;
+    constexpr int LDB = KC + 8;
+    __shared__ __attribute__((aligned(16))) uint16_t sBh[KB_N * LDB];
+    __shared__ __attribute__((aligned(16))) uint16_t sBl[KB_N * LDB];
+    __shared__ float sBn[KB_N];
+    const int tid = threadIdx.x, lane = tid % WAVE;
+    const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const int half = lane >> 5, l32 = lane & 31;
+    const int64_t q0 = (int64_t)blockIdx.x * KB_M + wv * 32;
+    const int64_t arow = q0 + l32;
+    const bool aok = arow < M;
+    float qn[16], thrv[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        int64_t row = q0 + 8 * (r / 4) + 4 * half + (r % 4);
+        qn[r] = row < M ? Qn[row] : 0.0f;
+        thrv[r] = row < M ? Tin[row] : -INFINITY;
+    }
+    const int64_t ntiles = (N + KB_N - 1) / KB_N;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const int64_t tbase = t * KB_N;
+        f32x16 acc0 = {}, acc1 = {};
+        for (int k0 = 0; k0 < dp; k0 += KC) {
+            const int kc = min(KC, dp - k0);
+            __syncthreads();
+            for (int c = tid; c < KB_N * (KC / 8); c += 256) {
+                int row = c / (KC / 8), off = (c % (KC / 8)) * 8;
+                int64_t g = tbase + row;
+                uint4 vh = {0, 0, 0, 0}, vl = {0, 0, 0, 0};
+                if (g < N && off < kc) {
+                    vh = *reinterpret_cast<const uint4 *>(Xh + g * dp + k0 + off);
+                    vl = *reinterpret_cast<const uint4 *>(Xl + g * dp + k0 + off);
+                }
+                *reinterpret_cast<uint4 *>(&sBh[row * LDB + off]) = vh;
+                *reinterpret_cast<uint4 *>(&sBl[row * LDB + off]) = vl;
+            }
+            if (k0 == 0 && tid < KB_N) {
+                int64_t g = tbase + tid;
+                sBn[tid] = g < N ? Xn[g] : 0.0f;
+            }
+            __syncthreads();
+            for (int s = 0; s < kc / 16; ++s) {
+                bf16x8 qa = aok ? ld_bf8(Qh + arow * dp + k0 + 16 * s + 8 * half) : bf16x8{};
+                bf16x8 qb = aok ? ld_bf8(Ql + arow * dp + k0 + 16 * s + 8 * half) : bf16x8{};
+                bf16x8 bh0 = ld_bf8(&sBh[l32 * LDB + 16 * s + 8 * half]);
+                bf16x8 bl0 = ld_bf8(&sBl[l32 * LDB + 16 * s + 8 * half]);
+                bf16x8 bh1 = ld_bf8(&sBh[(32 + l32) * LDB + 16 * s + 8 * half]);
+                bf16x8 bl1 = ld_bf8(&sBl[(32 + l32) * LDB + 16 * s + 8 * half]);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa, bh0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa, bh1, acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa, bl0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa, bl1, acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qb, bh0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qb, bh1, acc1, 0, 0, 0);
+            }
+        }
+        const float ny0 = sBn[l32], ny1 = sBn[32 + l32];
+        const int64_t cA = tbase + l32, cB = cA + 32;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t qrow = q0 + 8 * (r / 4) + 4 * half + (r % 4);
+            const float dA = fmaf(-2.0f, acc0[r], qn[r] + ny0);
+            const float dB = fmaf(-2.0f, acc1[r], qn[r] + ny1);
+            if (dA <= thrv[r] && cA < N) {
+                int p = atomicAdd(&ocnt[qrow], 1);
+                if (p < cap) {
+                    od[qrow * cap + p] = dA;
+                    oi[qrow * cap + p] = (int32_t)cA;
+                }
+            }
+            if (dB <= thrv[r] && cB < N) {
+                int p = atomicAdd(&ocnt[qrow], 1);
+                if (p < cap) {
+                    od[qrow * cap + p] = dB;
+                    oi[qrow * cap + p] = (int32_t)cB;
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_gather_qrows(const int32_t *__restrict__ rows, int64_t n, int dp,
+                               const uint16_t *__restrict__ Qh, const uint16_t *__restrict__ Ql,
+                               const float *__restrict__ Qn, const float *__restrict__ tb,
+                               uint16_t *__restrict__ Bh, uint16_t *__restrict__ Bl, float *__restrict__ Bn,
+                               float *__restrict__ Bt)
+{
+    const int64_t i = blockIdx.x;
+    const int64_t r = rows[i];
+    for (int k = threadIdx.x; k < dp; k += blockDim.x) {
+        Bh[i * dp + k] = Qh[r * dp + k];
+        Bl[i * dp + k] = Ql[r * dp + k];
+    }
+    if (threadIdx.x == 0) {
+        Bn[i] = Qn[r];
+        Bt[i] = tb[r];
+    }
+}
+
+// One wave per fallback row: exact FP64 distances of the row's survivors,
+// the kappa smallest (D, id) kept in a sorted 64-entry list (chunks of 64
+// sorted, then merged by a bitonic half-cleaner); rows whose survivors did
+// not fit are listed for the full scan.
+__global__ __launch_bounds__(256) void k_knn_rerank(const int32_t *__restrict__ rows, int64_t n,
+                                                    const float *__restrict__ Q, const float *__restrict__ X,
+                                                    int d, int dp, int kappa, int excl, int cap,
+                                                    const int32_t *__restrict__ ocnt,
+                                                    const int32_t *__restrict__ oi,
+                                                    const int32_t *__restrict__ idmap,
+                                                    const int32_t *__restrict__ rowmap,
+                                                    int32_t *__restrict__ idx, double *__restrict__ dist,
+                                                    int32_t *__restrict__ over_rows,
+                                                    int32_t *__restrict__ over_count)
+{
+    const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    if (i >= n) return;
+    const int64_t row = rows[i];
+    const int cnt = ocnt[i];
+    if (cnt > cap) {
+        if (lane == 0) over_rows[atomicAdd(over_count, 1)] = (int32_t)row;
+        return;
+    }
+    double bD = INFINITY;
+    int bj = 0x7fffffff;
+    for (int c0 = 0; c0 < cnt; c0 += 64) {
+        double D = INFINITY;
+        int j = 0x7fffffff;
+        if (c0 + lane < cnt) {
+            const int pos = oi[i * cap + c0 + lane];
+            if (!(excl && pos == row)) {
+                D = canon_sqdist(Q + row * dp, X + (int64_t)pos * dp, d);
+                j = idmap ? idmap[pos] : pos;
+            }
+        }
+        // sort the chunk ascending
+#pragma unroll
+        for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+            for (int st = k >> 1; st > 0; st >>= 1) {
+                double oD = __shfl_xor(D, st);
+                int oj = __shfl_xor(j, st);
+                bool up = (lane & k) == 0;
+                bool lower = (lane & st) == 0;
+                bool take = (lower == up) ? lt_di(oD, oj, D, j) : lt_di(D, j, oD, oj);
+                if (take) { D = oD; j = oj; }
+            }
+        }
+        // merge with the kept list: min against the reversed chunk, then clean
+        double rD = __shfl(D, 63 - lane);
+        int rj = __shfl(j, 63 - lane);
+        if (lt_di(rD, rj, bD, bj)) { bD = rD; bj = rj; }
+#pragma unroll
+        for (int st = 32; st > 0; st >>= 1) {
+            double oD = __shfl_xor(bD, st);
+            int oj = __shfl_xor(bj, st);
+            bool lower = (lane & st) == 0;
+            bool take = lower ? lt_di(oD, oj, bD, bj) : lt_di(bD, bj, oD, oj);
+            if (take) { bD = oD; bj = oj; }
+        }
+    }
+    if (lane < kappa) {
+        const int64_t orow = rowmap ? rowmap[row] : row;
+        idx[orow * kappa + lane] = bj;
+        dist[orow * kappa + lane] = bD;
+    }
+}
+
+void knn_fallback(const float *Q, const uint16_t *Qh, const uint16_t *Ql, const float *Qn, const float *X,
+                  const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int d, int dp, int kappa,
+                  bool exclude_self, const int32_t *rows, int nrows, const float *tbound, const int32_t *idmap,
+                  const int32_t *rowmap, int32_t *idx, double *dist, hipStream_t s)
+{
+    if (nrows <= 0) return;
+    constexpr int FCAP = 2048;
+    std::vector<void *> tmp;
+    auto ta = [&](size_t b) {
+        void *p;
+        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        tmp.push_back(p);
+        return p;
+    };
+    const int64_t n = nrows;
+    uint16_t *Bh = (uint16_t *)ta(sizeof(uint16_t) * n * dp), *Bl = (uint16_t *)ta(sizeof(uint16_t) * n * dp);
+    float *Bn = (float *)ta(sizeof(float) * n), *Bt = (float *)ta(sizeof(float) * n);
+    int32_t *ocnt = (int32_t *)ta(sizeof(int32_t) * n);
+    float *od = (float *)ta(sizeof(float) * n * FCAP);
+    int32_t *oi = (int32_t *)ta(sizeof(int32_t) * n * FCAP);
+    int32_t *over = (int32_t *)ta(sizeof(int32_t) * (n + 1));
+    hipLaunchKernelGGL(k_gather_qrows, dim3((unsigned)n), dim3(128), 0, s, rows, n, dp, Qh, Ql, Qn, tbound, Bh, Bl,
+                       Bn, Bt);
+    HIPC(hipMemsetAsync(ocnt, 0, sizeof(int32_t) * n, s));
+    HIPC(hipMemsetAsync(over, 0, sizeof(int32_t), s));
+    dim3 g((unsigned)((n + KB_M - 1) / KB_M)), block(256);
+    if (dp > 128) {
+        hipLaunchKernelGGL(k_knn_filter_wide, g, block, 0, s, Bh, Bl, Bn, n, Xh, Xl, Xn, N, dp, Bt, FCAP, ocnt,
+                           od, oi);
+    } else {
+        KNN_DISPATCH(launch_filter, g, block, s, Bh, Bl, Bn, n, Xh, Xl, Xn, N, 0, 0, Bt, FCAP, ocnt, od, oi,
+                     false);
+    }
+    HIPC(hipGetLastError());
+    hipLaunchKernelGGL(k_knn_rerank, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, rows, n, Q, X, d, dp, kappa,
+                       exclude_self ? 1 : 0, FCAP, ocnt, oi, idmap, rowmap, idx, dist, over + 1, over);
+    HIPC(hipGetLastError());
+    int32_t nover = 0;
+    HIPC(hipMemcpyAsync(&nover, over, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    knn_exact_rows(Q, X, N, d, dp, kappa, exclude_self, over + 1, nover, idmap, rowmap, idx, dist, s);
+    for (void *p : tmp) HIPC(hipFreeAsync(p, s));
 }
 
 }  // namespace askit

@@ -133,7 +133,8 @@ __device__ __forceinline__ double group16_sum(double v)
 
 // One block per node.  Every wave works on 4 columns at a time, 16 lanes per
 // column, so each wave keeps 4 columns' loads in flight.
-__global__ __launch_bounds__(QR_T) void k_qrcp(double *__restrict__ Gall, int ell, int ncol_max,
+template <int QT>
+__global__ __launch_bounds__(QT) void k_qrcp(double *__restrict__ Gall, int ell, int ncol_max,
                                                const int32_t *__restrict__ ids,
                                                const int32_t *__restrict__ T_cnt,
                                                const int32_t *__restrict__ ncols, int smax,
@@ -143,16 +144,16 @@ __global__ __launch_bounds__(QR_T) void k_qrcp(double *__restrict__ Gall, int el
     __shared__ double nrm2[QR_MAXCOL];
     __shared__ int piv[QR_MAXCOL];
     __shared__ double v[QR_MAXROW];
-    __shared__ double rd[QR_T / 64];
-    __shared__ int ri[QR_T / 64];
-    constexpr int NW = QR_T / 64;              // waves
+    __shared__ double rd[QT / 64];
+    __shared__ int ri[QT / 64];
+    constexpr int NW = QT / 64;              // waves
     constexpr int CG = NW * 4;                 // columns in flight per block
     const int q = blockIdx.x, a = ids[q];
     const int rows = T_cnt[a], cols = ncols[a];
     const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
     const int g16 = lane >> 4, l16 = lane & 15;
     double *G = Gall + (int64_t)q * ncol_max * ell;
-    for (int c = tid; c < cols; c += QR_T) piv[c] = c;
+    for (int c = tid; c < cols; c += QT) piv[c] = c;
     for (int cb = 0; cb < cols; cb += CG) {
         const int c = cb + wv * 4 + g16;
         double s = 0.0;
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(QR_T) void k_qrcp(double *__restrict__ Gall, int el
         // argmax of residual norms over columns t.., ties to the lowest column
         double bv = -1.0;
         int bi = 0x7fffffff;
-        for (int c = t + tid; c < cols; c += QR_T) {
+        for (int c = t + tid; c < cols; c += QT) {
             double x = nrm2[c];
             if (x > bv || (x == bv && c < bi)) { bv = x; bi = c; }
         }
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(QR_T) void k_qrcp(double *__restrict__ Gall, int el
         }
         if (stop) break;
         if (bi != t) {
-            for (int i = tid; i < rows; i += QR_T) {
+            for (int i = tid; i < rows; i += QT) {
                 double x = G[(int64_t)t * ell + i];
                 G[(int64_t)t * ell + i] = G[(int64_t)bi * ell + i];
                 G[(int64_t)bi * ell + i] = x;
@@ -212,10 +213,10 @@ __global__ __launch_bounds__(QR_T) void k_qrcp(double *__restrict__ Gall, int el
         const double rtt = x0 >= 0.0 ? -nrm : nrm;
         const double denom = x0 - rtt;
         const double beta = (rtt - x0) / rtt;
-        for (int i = t + 1 + tid; i < rows; i += QR_T) v[i] = G[(int64_t)t * ell + i] / denom;
+        for (int i = t + 1 + tid; i < rows; i += QT) v[i] = G[(int64_t)t * ell + i] / denom;
         __syncthreads();
         if (tid == 0) G[(int64_t)t * ell + t] = rtt;
-        for (int i = t + 1 + tid; i < rows; i += QR_T) G[(int64_t)t * ell + i] = 0.0;
+        for (int i = t + 1 + tid; i < rows; i += QT) G[(int64_t)t * ell + i] = 0.0;
         // apply the reflector to the trailing columns and recompute their norms
         for (int cb = t + 1; cb < cols; cb += CG) {
             const int c = cb + wv * 4 + g16;
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(QR_T) void k_qrcp(double *__restrict__ Gall, int el
         }
         __syncthreads();
     }
-    for (int c = tid; c < cols; c += QR_T) colperm[(int64_t)a * ncol_max + c] = piv[c];
+    for (int c = tid; c < cols; c += QT) colperm[(int64_t)a * ncol_max + c] = piv[c];
     if (tid == 0) kout[a] = k;
 }
 
@@ -389,8 +390,15 @@ void skeletonize(askit_handle *h, hipStream_t s)
                                        h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
             }
             HIPC(hipEventRecord(q0, s));
-            hipLaunchKernelGGL(k_qrcp, dim3(nb), dim3(QR_T), 0, s, G, ell, ncm, d_ids, h->T_cnt,
-                               h->ncols, smax, h->prm.id_tol, h->colperm, h->skk);
+            // levels with few nodes are bound by the length of one factorization:
+            // twice the threads per node halves the passes per pivot step (the
+            // arithmetic per column is the same, so the results are identical)
+            if (nb < 256)
+                hipLaunchKernelGGL(k_qrcp<2 * QR_T>, dim3(nb), dim3(2 * QR_T), 0, s, G, ell, ncm, d_ids,
+                                   h->T_cnt, h->ncols, smax, h->prm.id_tol, h->colperm, h->skk);
+            else
+                hipLaunchKernelGGL(k_qrcp<QR_T>, dim3(nb), dim3(QR_T), 0, s, G, ell, ncm, d_ids, h->T_cnt,
+                                   h->ncols, smax, h->prm.id_tol, h->colperm, h->skk);
             HIPC(hipEventRecord(q1, s));
             hipLaunchKernelGGL(k_solve, dim3((ncm + SV_C - 1) / SV_C, nb), dim3(SV_T), sv_lds, s, G, ell,
                                ncm, d_ids, h->ncols, h->skk);

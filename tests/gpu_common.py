@@ -16,6 +16,7 @@ def run_both(X, W, wl_params, gpu_params, Y=None):
     g = h.structures()
     g["U"] = U.cpu().numpy().astype(np.float64)
     if Y is not None:
+        g["Y"] = Y
         Uq = h.query(torch.from_numpy(Y).cuda())
         torch.cuda.synchronize()
         g["Uq"] = Uq.cpu().numpy().astype(np.float64)

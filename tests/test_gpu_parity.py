@@ -34,15 +34,21 @@ CASES = {
     "d40": (3000, 40, 5, 6, O.Params(m=96, kappa=12, smax=48, ell=68, tau=1e-5, h=1.5, seed=3)),
     # above 64 reference tiles: window pass + filter sweep + select path of the kNN
     "filter-path": (20000, 24, 4, 8, O.Params(m=256, kappa=32, smax=64, ell=84, tau=1e-5, h=1.0, seed=9)),
+    # wide rows far from the origin (component means spread 30): the bf16x3
+    # error bound, which grows with the squared norms, exceeds the neighbour
+    # gaps, so rows go through the filtered fallback
+    "wide-fallback": (5000, 600, 5, 6, O.Params(m=128, kappa=16, smax=32, ell=52, tau=1e-5, h=2.0, seed=13)),
 }
+SPREAD = {"wide-fallback": 30.0}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
 def case(request):
     N, d, q, comps, p = CASES[request.param]
-    X = synth.mixture_points(N, d, q, comps, 1e-3, 100 + N)
+    sp = SPREAD.get(request.param, 3.0)
+    X = synth.mixture_points(N, d, q, comps, 1e-3, 100 + N, spread=sp)
     W = synth.weights(N, 2, N)
-    Y = synth.mixture_points(300, d, q, comps, 1e-3, 999, basis_seed=100 + N)
+    Y = synth.mixture_points(300, d, q, comps, 1e-3, 999, spread=sp, basis_seed=100 + N)
     print(f"\n[case {request.param}] N={N} d={d} params={p}", flush=True)
     st, g = run_both(X, W, p, gparams(p), Y=Y)
     return request.param, X, W, p, st, g
@@ -50,6 +56,10 @@ def case(request):
 
 def test_knn_bit_exact(case):
     name, X, W, p, st, g = case
+    print(f"[knn] {name}: rows not certified by the approximate pass: {g['info']['knn_uncertified_rows']}",
+          flush=True)
+    if name == "wide-fallback":
+        assert g["info"]["knn_uncertified_rows"] > 0      # the fallback is exercised
     assert np.array_equal(g["knn_idx"], st["knn_idx"])
     assert np.array_equal(g["knn_d"], st["knn_d"])
 
@@ -130,10 +140,30 @@ def test_interaction_lists_bit_exact(case):
         assert far[pos] == sorted(ev.far[o].tolist()), f"target {o}"
 
 
+def _abs_scale(st, W, p):
+    """|u| of the same approximation with |w|: the size of the terms that
+    FP32 adds, whatever cancellation the signed sum has."""
+    Wa = np.abs(W).astype(np.float32)
+    Wsk = O.upward(st["nodes"], Wa[st["perm"]].astype(np.float64), st["sk"], p.smax)
+    nb = O.self_neighbours(st, np.arange(len(W)))
+    ev = O.evaluate(st["X"], nb, st["X"], st["perm"], st["nodes"], st["hsrc"], p.h, Wa, st["sk"], Wsk, p.smax,
+                    record=False)
+    return ev.U
+
+
 def test_u_matches_oracle(case):
+    """u within 1e-5 relative L2 of the oracle.  The wide case (clusters 30
+    apart in 600 dimensions) sums ~800 signed terms per target with
+    cancellation, so its error is measured against the same sums with |w|."""
     name, X, W, p, st, g = case
-    for r in range(W.shape[1]):
-        assert rel(g["U"][:, r], st["ev"].U[:, r]) < U_TOL
+    errs = [rel(g["U"][:, r], st["ev"].U[:, r]) for r in range(W.shape[1])]
+    print(f"[u] {name}: relative L2 error vs oracle per column {errs}", flush=True)
+    if name == "wide-fallback":
+        Ua = _abs_scale(st, W, p)
+        errs = [float(np.linalg.norm(g["U"][:, r] - st["ev"].U[:, r]) / np.linalg.norm(Ua[:, r]))
+                for r in range(W.shape[1])]
+        print(f"[u] {name}: error relative to the |w| sums {errs}", flush=True)
+    assert max(errs) < U_TOL
 
 
 def test_skeleton_weights(case):
@@ -148,8 +178,16 @@ def test_skeleton_weights(case):
 def test_query_matches_oracle(case):
     name, X, W, p, st, g = case
     qi, qd, ev = st["query"]
-    for r in range(W.shape[1]):
-        assert rel(g["Uq"][:, r], ev.U[:, r]) < U_TOL
+    errs = [rel(g["Uq"][:, r], ev.U[:, r]) for r in range(W.shape[1])]
+    print(f"[query] {name}: relative L2 error vs oracle per column {errs}", flush=True)
+    if name == "wide-fallback":           # measured against the |w| sums, as for u
+        Wa = np.abs(W).astype(np.float32)
+        sta = dict(st, W=Wa, Wsk=O.upward(st["nodes"], Wa[st["perm"]].astype(np.float64), st["sk"], p.smax))
+        Ua = O.query(sta, g["Y"], record=False)[2].U
+        errs = [float(np.linalg.norm(g["Uq"][:, r] - ev.U[:, r]) / np.linalg.norm(Ua[:, r]))
+                for r in range(W.shape[1])]
+        print(f"[query] {name}: error relative to the |w| sums {errs}", flush=True)
+    assert max(errs) < U_TOL
 
 
 def test_columns_independent_and_deterministic():
@@ -199,21 +237,30 @@ def test_bf16x3_precision_form(d):
     st, g = run_both(X, W, p, gparams(p, precision=A.PREC_BF16X3))
     assert np.array_equal(g["perm"], st["perm"]) and np.array_equal(g["knn_idx"], st["knn_idx"])
     for r in range(W.shape[1]):
-        assert rel(g["U"][:, r], st["ev"].U[:, r]) < 1e-4
+        e = rel(g["U"][:, r], st["ev"].U[:, r])
+        print(f"[bf16x3] d={d} column {r}: relative L2 error vs oracle {e}", flush=True)
+        assert e < 1e-4
 
 
-def test_many_rhs_blocks():
-    """nrhs = 11 runs as blocks of 8 and 3 columns; each column equals its own run."""
+@pytest.mark.parametrize("R", [3, 11, 40, 64])
+def test_many_rhs_blocks(R):
+    """R columns in one pass: up to 4 contracted on the vector units, up to 32
+    or 64 as a second MFMA with the weight tile; every column matches the
+    oracle, and the single-column run of the same weights to FP32 rounding."""
     import torch
     from paper_1410_0260_amd import askit as A
     N, d = 2500, 20
     X = synth.mixture_points(N, d, 4, 3, 1e-3, 8)
-    W = synth.weights(N, 11, 8)
+    W = synth.weights(N, R, 8)
     p = O.Params(m=64, kappa=10, smax=32, ell=52, tau=1e-6, h=1.0, seed=6)
     st = O.run_askit(X, W, p, record=False)
     h = A.setup(torch.from_numpy(X).cuda(), gparams(p))
     h.update_weights(torch.from_numpy(W).cuda())
     U = h.evaluate().cpu().numpy().astype(np.float64)
-    h.close()
-    for r in range(11):
+    for r in range(R):
         assert rel(U[:, r], st["ev"].U[:, r]) < U_TOL
+    for r in (0, R - 1):
+        h.update_weights(torch.from_numpy(W[:, r:r + 1].copy()).cuda())
+        U1 = h.evaluate().cpu().numpy().astype(np.float64)
+        assert rel(U1[:, 0], U[:, r]) < 1e-6
+    h.close()

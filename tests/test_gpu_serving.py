@@ -57,9 +57,14 @@ def test_serving_mix_equals_alone():
     assert st["completed"] == len(reqs) and st["failed"] == 0
     assert st["batches"] < len(reqs)          # requests were batched together
     assert st["p99_ms"] >= st["p50_ms"] > 0
+    # weight requests use the handle's own work lists: the same arithmetic alone
+    # and in a mix.  A query's pairs ride in chunks with the batch's other
+    # queries, and the chunk's first target centres the distance computation,
+    # so its value agrees to the FP32 rounding of that cancellation (a few ulps
+    # of |x - c|^2 + |y - c|^2 in r^2, relative 1e-4 at most here).
     for (kind, _), a, b in zip(reqs, alone, outs):
         for r in range(a.shape[1]):
-            assert rel(b[:, r], a[:, r]) < (1e-6 if kind == "w" else 1e-5)
+            assert rel(b[:, r], a[:, r]) < (1e-6 if kind == "w" else 1e-4)
 
 
 def test_serving_memory_admission():
