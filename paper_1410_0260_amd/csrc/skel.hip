@@ -48,6 +48,8 @@ __global__ void k_cols(const Node *__restrict__ nodes, const int32_t *__restrict
 constexpr int FG_T = 256;
 constexpr int FG_C = 8;           // columns per block
 constexpr int FG_K = 32;          // dimensions per LDS stage
+constexpr int FG_LT = FG_K + 1;   // LDS row stride of the sampled rows: lanes read different rows at
+                                  // the same offset, and an odd stride puts them in different banks
 constexpr int FG_MAXROW = 1024;
 
 // PP: (row, column) pairs per thread, >= rows * FG_C / FG_T
@@ -68,8 +70,8 @@ __global__ __launch_bounds__(FG_T) void k_form_G(const float *__restrict__ Xt, i
     const int nc = min(FG_C, ncols[a] - c0);
     if (nc <= 0) return;
     const int rows = T_cnt[a];
-    float *sT = fsm;                           // rows x FG_K
-    float *sC = fsm + (size_t)rows * FG_K;     // FG_C x FG_K
+    float *sT = fsm;                           // rows x FG_LT
+    float *sC = fsm + (size_t)rows * FG_LT;    // FG_C x FG_K
     const int npair = rows * nc;
     double acc[PP];
 #pragma unroll
@@ -79,7 +81,7 @@ __global__ __launch_bounds__(FG_T) void k_form_G(const float *__restrict__ Xt, i
         __syncthreads();
         for (int e = threadIdx.x; e < rows * FG_K; e += FG_T) {
             int t = e / FG_K, j = e % FG_K;
-            sT[e] = j < kk ? Xt[(int64_t)T[(int64_t)a * ell + t] * dp + k0 + j] : 0.0f;
+            sT[t * FG_LT + j] = j < kk ? Xt[(int64_t)T[(int64_t)a * ell + t] * dp + k0 + j] : 0.0f;
         }
         for (int e = threadIdx.x; e < nc * FG_K; e += FG_T) {
             int c = e / FG_K, j = e % FG_K;
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(FG_T) void k_form_G(const float *__restrict__ Xt, i
             const int pi = threadIdx.x + FG_T * u;
             if (pi < npair) {
                 const int t = pi % rows, c = pi / rows;
-                const float *x = sT + t * FG_K, *y = sC + c * FG_K;
+                const float *x = sT + t * FG_LT, *y = sC + c * FG_K;
                 double s = acc[u];
                 for (int j = 0; j < kk; ++j) {
                     double df = (double)x[j] - (double)y[j];
@@ -288,6 +290,65 @@ __global__ __launch_bounds__(SV_T) void k_solve(double *__restrict__ Gall, int e
 }
 
 // S, skeleton coordinates and bandwidth factors, P in FP32 (row stride n-k).
+// The same solve for k <= 256, register-blocked: a block takes 32 columns
+// of R12, each column spread over 8 lanes that hold rows j, j + 8, ... in
+// registers.  R's columns are staged in LDS 8 at a time, so a block
+// synchronises twice per 8 rows instead of twice per row; row t's value is
+// divided by R_tt by the lane that holds it and broadcast to the column's
+// lanes.  The updates of every element come in the same order as above
+// (t = k-1 down to the row + 1).
+constexpr int SR_L = 8;       // lanes per column
+constexpr int SR_R = 32;      // rows per lane (k <= 256)
+constexpr int SR_C = 32;      // columns per block
+
+__global__ __launch_bounds__(256) void k_solve_reg(double *__restrict__ Gall, int ell, int ncol_max,
+                                                   const int32_t *__restrict__ ids,
+                                                   const int32_t *__restrict__ ncols,
+                                                   const int32_t *__restrict__ skk)
+{
+    __shared__ double sR[SR_L * SR_L * SR_R];       // 8 columns of R, rows 0 .. 255
+    const int q = blockIdx.y, a = ids[q];
+    const int k = skk[a], m = ncols[a] - k;
+    const int c0 = blockIdx.x * SR_C;
+    if (k == 0 || c0 >= m) return;
+    const int tid = threadIdx.x, lane = tid % 64;
+    const int col = tid / SR_L, j = tid % SR_L, base = lane & ~(SR_L - 1);
+    const bool cok = c0 + col < m;
+    double *G = Gall + (int64_t)q * ncol_max * ell;
+    double *pc = G + (int64_t)(k + c0 + (cok ? col : 0)) * ell;
+    double P[SR_R];
+#pragma unroll
+    for (int i = 0; i < SR_R; ++i) {
+        const int u = SR_L * i + j;
+        P[i] = (cok && u < k) ? pc[u] : 0.0;
+    }
+#pragma clang loop unroll(full)
+    for (int ib = SR_R - 1; ib >= 0; --ib) {
+        if (SR_L * ib >= k) continue;
+        __syncthreads();
+        for (int e = tid; e < SR_L * SR_L * SR_R; e += 256) {
+            const int cc = e / (SR_L * SR_R), u = e % (SR_L * SR_R), t = SR_L * ib + cc;
+            sR[e] = (t < k && u <= t) ? G[(int64_t)t * ell + u] : 0.0;
+        }
+        __syncthreads();
+        for (int jj = SR_L - 1; jj >= 0; --jj) {
+            const int t = SR_L * ib + jj;
+            if (t >= k) continue;
+            const double *rc = sR + jj * (SR_L * SR_R);      // column t of R
+            const double pt = __shfl(P[ib], base + jj) / rc[t];
+            if (j == jj) P[ib] = pt;
+#pragma clang loop unroll(full)
+            for (int i = 0; i < ib; ++i) P[i] -= rc[SR_L * i + j] * pt;
+            if (j < jj) P[ib] -= rc[SR_L * ib + j] * pt;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < SR_R; ++i) {
+        const int u = SR_L * i + j;
+        if (cok && u < k) pc[u] = P[i];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ Gall, int ell,
                                                   int ncol_max, const int32_t *__restrict__ ids,
                                                   const int32_t *__restrict__ colpos,
@@ -348,7 +409,7 @@ void skeletonize(askit_handle *h, hipStream_t s)
         gather_f64(h->hsrc, h->perm, h->N, hp_tmp, s);
         hpos = hp_tmp;
     }
-    const size_t fg_lds = sizeof(float) * ((size_t)ell + FG_C) * FG_K;
+    const size_t fg_lds = sizeof(float) * ((size_t)ell * FG_LT + (size_t)FG_C * FG_K);
     const size_t sv_lds = sizeof(double) * (size_t)std::min(smax, ell) * SV_C;
     if (fg_lds > 64 * 1024) {
         HIPC(hipFuncSetAttribute((const void *)k_form_G<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -400,7 +461,11 @@ void skeletonize(askit_handle *h, hipStream_t s)
                 hipLaunchKernelGGL(k_qrcp<QR_T>, dim3(nb), dim3(QR_T), 0, s, G, ell, ncm, d_ids, h->T_cnt,
                                    h->ncols, smax, h->prm.id_tol, h->colperm, h->skk);
             HIPC(hipEventRecord(q1, s));
-            hipLaunchKernelGGL(k_solve, dim3((ncm + SV_C - 1) / SV_C, nb), dim3(SV_T), sv_lds, s, G, ell,
+            if (smax <= SR_L * SR_R)
+                hipLaunchKernelGGL(k_solve_reg, dim3((ncm + SR_C - 1) / SR_C, nb), dim3(256), 0, s, G, ell, ncm,
+                                   d_ids, h->ncols, h->skk);
+            else
+                hipLaunchKernelGGL(k_solve, dim3((ncm + SV_C - 1) / SV_C, nb), dim3(SV_T), sv_lds, s, G, ell,
                                ncm, d_ids, h->ncols, h->skk);
             hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(256), 0, s, G, ell, ncm, d_ids, colpos,
                                h->ncols, h->skk, h->colperm, smax, h->d_pslot, h->Xt, h->dp, h->gt,
