@@ -505,7 +505,7 @@ def main():
         "eps_vs_fp64_direct": {"per_rhs": eps, "targets_sampled": nt},
         "counts": {k: info[k] for k in ("num_nodes", "num_leaves", "depth", "num_slabs", "near_entries",
                                         "far_entries", "near_pairs", "far_pairs",
-                                        "knn_uncertified_rows")},
+                                        "knn_uncertified_rows", "knn_retry_rows", "eval_pairs", "eval_chunks")},
         "roofline": roof,
         "roofline_eval": eval_roof,
     }

@@ -143,6 +143,7 @@ typedef struct {
     int64_t knn_filter_launches;         /* ... and their number */
     int64_t eval_pairs;                  /* (target, source node) pairs of one evaluation */
     int64_t eval_chunks;                 /* evaluation work items (up to 64 targets of one source node) */
+    int64_t knn_retry_rows;              /* rows whose filter output overflowed (swept again with lists) */
 } askit_info;
 
 askit_status askit_get_info(const askit_handle *h, askit_info *out);

@@ -413,7 +413,7 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
         HIPC(hipEventRecord(k0, s));
         float fms = 0.f;
         knn_candidates(h->Xh, h->Xl, h->Xn, N, h->Xh, h->Xl, h->Xn, N, dp, true, true, cand, thr,
-                       bad + 1, bad, s, &fms, &h->knn_filter_launches);
+                       bad + 1, bad, s, &fms, &h->knn_filter_launches, &h->knn_retry_rows);
         h->t_knn_filter = fms;
         HIPC(hipEventRecord(k1, s));
         float *tb;
@@ -577,6 +577,7 @@ askit_status askit_get_info(const askit_handle *h, askit_info *o)
     o->knn_filter_launches = h->knn_filter_launches;
     o->eval_pairs = h->pairs.npairs;
     o->eval_chunks = h->pairs.nchunk;
+    o->knn_retry_rows = h->knn_retry_rows;
     o->t_qr_ms = h->t_qr;
     API_END
 }

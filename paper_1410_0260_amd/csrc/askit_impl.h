@@ -162,7 +162,7 @@ struct askit_handle {
     int64_t near_pairs = 0, far_pairs = 0, knn_uncertified = 0;
     double t_knn = 0, t_tree = 0, t_lists = 0, t_skel = 0, t_inter = 0, t_update = 0;
     double t_knn_sweep = 0, t_qr = 0, t_knn_filter = 0;
-    int knn_filter_launches = 0;
+    int knn_filter_launches = 0, knn_retry_rows = 0;
     hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr;
     bool up_pending = false;
 
@@ -190,7 +190,7 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
                     const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int dp,
                     bool exclude_self, bool start_local, int32_t *cand, float *thr,
                     int32_t *bad_rows, int32_t *bad_count, hipStream_t s,
-                    float *t_filter_ms = nullptr, int *n_filter = nullptr);
+                    float *t_filter_ms = nullptr, int *n_filter = nullptr, int *n_retry = nullptr);
 void knn_refine(const float *Q, int64_t M, const float *X, int64_t N, int d, int dp, int kappa,
                 const int32_t *cand, const float *thr, const float *Qn, float maxnorm,
                 const int32_t *idmap, const int32_t *rowmap, int32_t *idx, double *dist,

@@ -776,10 +776,11 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
                     const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int dp,
                     bool exclude_self, bool start_local, int32_t *cand, float *thr,
                     int32_t *bad_rows, int32_t *bad_count, hipStream_t s, float *t_filter_ms,
-                    int *n_filter)
+                    int *n_filter, int *n_retry)
 {
     if (t_filter_ms) *t_filter_ms = 0.f;
     if (n_filter) *n_filter = 0;
+    if (n_retry) *n_retry = 0;
     dim3 grid((unsigned)((M + KB_M - 1) / KB_M)), block(256);
     int ex = exclude_self ? 1 : 0, sl = start_local ? 1 : 0;
     const int64_t ntiles = (N + KB_N - 1) / KB_N;
@@ -847,6 +848,7 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
         *t_filter_ms = tot;
         if (n_filter) *n_filter = (int)(ev.size() / 2);
     }
+    if (n_retry) *n_retry = nretry;
     if (nretry > 0) {
         dim3 g((unsigned)((nretry + KB_M - 1) / KB_M));
         KNN_DISPATCH(launch_cand, g, block, s, Qh, Ql, Qn, (int64_t)nretry, Xh, Xl, Xn, N, ex, sl, 0,

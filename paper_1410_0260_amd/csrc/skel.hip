@@ -122,7 +122,7 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-constexpr int QR_T = 512;
+constexpr int QR_T = 1024;
 constexpr int QR_MAXCOL = 2048;
 constexpr int QR_MAXROW = 1024;
 
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(QT) void k_qrcp(double *__restrict__ Gall, int ell,
                                                const int32_t *__restrict__ T_cnt,
                                                const int32_t *__restrict__ ncols, int smax,
                                                double tau, int32_t *__restrict__ colperm,
-                                               int32_t *__restrict__ kout)
+                                               int32_t *__restrict__ kout, int nb)
 {
     __shared__ double nrm2[QR_MAXCOL];
     __shared__ int piv[QR_MAXCOL];
@@ -150,10 +150,14 @@ __global__ __launch_bounds__(QT) void k_qrcp(double *__restrict__ Gall, int ell,
     __shared__ int ri[QT / 64];
     constexpr int NW = QT / 64;              // waves
     constexpr int CG = NW * 4;                 // columns in flight per block
-    const int q = blockIdx.x, a = ids[q];
-    const int rows = T_cnt[a], cols = ncols[a];
     const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
     const int g16 = lane >> 4, l16 = lane & 15;
+  // nodes q = blockIdx.x, + gridDim.x, ... (launched with one block per node;
+  // a smaller grid would bound the factorizations in flight)
+  for (int q = blockIdx.x; q < nb; q += gridDim.x) {
+    __syncthreads();                           // the previous node is done with the shared arrays
+    const int a = ids[q];
+    const int rows = T_cnt[a], cols = ncols[a];
     double *G = Gall + (int64_t)q * ncol_max * ell;
     for (int c = tid; c < cols; c += QT) piv[c] = c;
     for (int cb = 0; cb < cols; cb += CG) {
@@ -247,6 +251,7 @@ __global__ __launch_bounds__(QT) void k_qrcp(double *__restrict__ Gall, int ell,
     }
     for (int c = tid; c < cols; c += QT) colperm[(int64_t)a * ncol_max + c] = piv[c];
     if (tid == 0) kout[a] = k;
+  }
 }
 
 // P = R11^{-1} R12 in place over R12 (FP64).  Block per (node, chunk of SV_C
@@ -451,15 +456,10 @@ void skeletonize(askit_handle *h, hipStream_t s)
                                        h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
             }
             HIPC(hipEventRecord(q0, s));
-            // levels with few nodes are bound by the length of one factorization:
-            // twice the threads per node halves the passes per pivot step (the
-            // arithmetic per column is the same, so the results are identical)
-            if (nb < 256)
-                hipLaunchKernelGGL(k_qrcp<2 * QR_T>, dim3(nb), dim3(2 * QR_T), 0, s, G, ell, ncm, d_ids,
-                                   h->T_cnt, h->ncols, smax, h->prm.id_tol, h->colperm, h->skk);
-            else
-                hipLaunchKernelGGL(k_qrcp<QR_T>, dim3(nb), dim3(QR_T), 0, s, G, ell, ncm, d_ids, h->T_cnt,
-                                   h->ncols, smax, h->prm.id_tol, h->colperm, h->skk);
+            // 1024 threads per node: twice the columns in flight per pivot step
+            // (the arithmetic per column is the same for any block size)
+            hipLaunchKernelGGL(k_qrcp<QR_T>, dim3((unsigned)nb), dim3(QR_T), 0, s, G, ell, ncm,
+                               d_ids, h->T_cnt, h->ncols, smax, h->prm.id_tol, h->colperm, h->skk, nb);
             HIPC(hipEventRecord(q1, s));
             if (smax <= SR_L * SR_R)
                 hipLaunchKernelGGL(k_solve_reg, dim3((ncm + SR_C - 1) / SR_C, nb), dim3(256), 0, s, G, ell, ncm,
