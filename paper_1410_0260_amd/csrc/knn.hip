@@ -214,7 +214,8 @@ __global__ __launch_bounds__(256) void k_knn_cand(const uint16_t *__restrict__ Q
                                                   int excl, int start_local, int win_tiles,
                                                   const int32_t *__restrict__ qpos,
                                                   int32_t *__restrict__ cand,
-                                                  float *__restrict__ thr_out)
+                                                  float *__restrict__ thr_out,
+                                                  float *__restrict__ cand_d)
 {
     constexpr int DP = KS * 16;
     constexpr int LDB = DP + 8;                      // padded LDS row (bf16 elements)
@@ -252,7 +253,8 @@ __global__ __launch_bounds__(256) void k_knn_cand(const uint16_t *__restrict__ Q
     for (int r = 0; r < 16; ++r) {
         int64_t row = q0 + 8 * (r / 4) + 4 * half + (r % 4);
         qn[r] = row < M ? Qn[qmap(row)] : 0.0f;
-        thrv[r] = INFINITY;
+        // segment sweeps start from the row's known bound (thr_out on entry)
+        thrv[r] = (cand_d && row < M) ? thr_out[qmap(row)] : INFINITY;
     }
     float list_d[32];
     int list_i[32], cnt[32];
@@ -275,6 +277,25 @@ __global__ __launch_bounds__(256) void k_knn_cand(const uint16_t *__restrict__ Q
         ntiles = win_tiles;
         int64_t c = (int64_t)blockIdx.x * KB_M / KB_N + (KB_M / KB_N) / 2 - win_tiles / 2;
         t0 = c < 0 ? 0 : (c + win_tiles > ntiles_all ? ntiles_all - win_tiles : c);
+    }
+    // cand_d != NULL: segment blockIdx.y of gridDim.y contiguous tile ranges;
+    // the lists and their distances go to (segment, row) slots for a merge
+    if (cand_d) {
+        const int64_t per = (ntiles_all + gridDim.y - 1) / gridDim.y;
+        t0 = (int64_t)blockIdx.y * per;
+        ntiles = t0 < ntiles_all ? min(per, ntiles_all - t0) : 0;
+    }
+    if (ntiles == 0) {
+        // empty segment: empty lists
+        for (int R = 0; R < 32; ++R) {
+            const int64_t row = q0 + R;
+            if (row < M) {
+                const int64_t o = ((int64_t)blockIdx.y * M + row) * KNN_CAND + lane;
+                cand[o] = -1;
+                cand_d[o] = INFINITY;
+            }
+        }
+        return;
     }
     constexpr int CHUNKS = KB_N * DP / 8;            // 16-byte chunks per operand tile
     constexpr int PER = (CHUNKS + 255) / 256;
@@ -353,15 +374,44 @@ __global__ __launch_bounds__(256) void k_knn_cand(const uint16_t *__restrict__ Q
         float th = __shfl(list_d[R], 63);
         int64_t row = q0 + R;
         if (row < M) {
-            int64_t orow = qmap(row);
-            cand[orow * KNN_CAND + lane] = list_i[R] == 0x7fffffff ? -1 : list_i[R];
-            if (lane == 0) thr_out[orow] = th;
+            if (cand_d) {
+                const int64_t o = ((int64_t)blockIdx.y * M + row) * KNN_CAND + lane;
+                cand[o] = list_i[R] == 0x7fffffff ? -1 : list_i[R];
+                cand_d[o] = list_d[R];
+            } else {
+                int64_t orow = qmap(row);
+                cand[orow * KNN_CAND + lane] = list_i[R] == 0x7fffffff ? -1 : list_i[R];
+                if (lane == 0) thr_out[orow] = th;
+            }
         }
     }
 #undef QMAPPED
 #undef QROW
 #define QMAPPED false
 #define QROW(q) (q)
+}
+
+// Per row (one wave): the 64 smallest of the rows' segment lists; output
+// through the row map (candidates and the 64th distance as threshold).
+__global__ __launch_bounds__(256) void k_knn_merge_seg(int64_t M, int nseg, const int32_t *__restrict__ qpos,
+                                                       const int32_t *__restrict__ si, const float *__restrict__ sd,
+                                                       int32_t *__restrict__ cand, float *__restrict__ thr)
+{
+    const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    if (r >= M) return;
+    float ld = INFINITY;
+    int li = 0x7fffffff;
+    for (int g = 0; g < nseg; ++g) {
+        const int64_t o = ((int64_t)g * M + r) * KNN_CAND;
+        ListEntry e = merge_list(ld, li, sd + o, si + o, KNN_CAND, lane);
+        ld = e.d;
+        li = e.i;
+    }
+    const int64_t orow = qpos ? (int64_t)qpos[r] : r;
+    cand[orow * KNN_CAND + lane] = (li == 0x7fffffff || li < 0) ? -1 : li;
+    const float th = __shfl(ld, 63);
+    if (lane == 0) thr[orow] = th;
 }
 
 // Generic variant for dp > 128: query fragments re-read from memory per tile,
@@ -707,34 +757,34 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
     const float tin = thr[row];          // the filter threshold: every point left out is above it
     float ld = INFINITY;
     int li = 0x7fffffff;
-    if (n > cap) {
-        if (lane == 0) {
-            int p = atomicAdd(bad_count, 1);
-            bad_rows[p] = (int32_t)row;
-        }
-    } else {
-        for (int c0 = 0; c0 < n; c0 += 64) {
-            ListEntry e = merge_list(ld, li, od + lrow * cap + c0, oi + lrow * cap + c0, min(64, n - c0),
-                                     lane);
-            ld = e.d;
-            li = e.i;
-        }
+    if (n > cap && lane == 0) {
+        int p = atomicAdd(bad_count, 1);
+        bad_rows[p] = (int32_t)row;
+    }
+    const int nk = min(n, cap);
+    for (int c0 = 0; c0 < nk; c0 += 64) {
+        ListEntry e = merge_list(ld, li, od + lrow * cap + c0, oi + lrow * cap + c0, min(64, nk - c0), lane);
+        ld = e.d;
+        li = e.i;
     }
     cand[row * KNN_CAND + lane] = li == 0x7fffffff ? -1 : li;
     // bound for the points outside the candidates: the 64th survivor, or the
-    // filter threshold when fewer than 64 points survived
+    // filter threshold when fewer than 64 points survived.  A row whose
+    // segment overflowed is swept again; the 64th of its stored survivors
+    // (real distances, so at least its 64th smallest), widened as the window
+    // threshold, starts that sweep.
     float th = __shfl(ld, 63);
-    if (lane == 0) thr[row] = n >= 64 ? th : tin;
+    if (lane == 0) thr[row] = n > cap ? th + fabsf(th) * 1e-5f + 1e-30f : (n >= 64 ? th : tin);
 }
 
 template <int KS>
 static void launch_cand(dim3 g, dim3 b, hipStream_t s, const uint16_t *Qh, const uint16_t *Ql,
                         const float *Qn, int64_t M, const uint16_t *Xh, const uint16_t *Xl,
                         const float *Xn, int64_t N, int ex, int sl, int win, const int32_t *qpos,
-                        int32_t *cand, float *thr)
+                        int32_t *cand, float *thr, float *cand_d = nullptr)
 {
     hipLaunchKernelGGL(k_knn_cand<KS>, g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, win, qpos, cand,
-                       thr);
+                       thr, cand_d);
 }
 
 template <int KS>
@@ -850,9 +900,25 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     }
     if (n_retry) *n_retry = nretry;
     if (nretry > 0) {
-        dim3 g((unsigned)((nretry + KB_M - 1) / KB_M));
-        KNN_DISPATCH(launch_cand, g, block, s, Qh, Ql, Qn, (int64_t)nretry, Xh, Xl, Xn, N, ex, sl, 0,
-                     (const int32_t *)(retry + 1), cand, thr);
+        // the overflowed rows sweep every point with lists; the point range is
+        // split in segments so that about 2048 workgroups share the sweep
+        const int rb = (int)((nretry + KB_M - 1) / KB_M);
+        const int nseg = (int)std::max<int64_t>(1, std::min<int64_t>({32, 2048 / rb, ntiles}));
+        if (nseg == 1) {
+            KNN_DISPATCH(launch_cand, dim3((unsigned)rb), block, s, Qh, Ql, Qn, (int64_t)nretry, Xh, Xl, Xn, N,
+                         ex, sl, 0, (const int32_t *)(retry + 1), cand, thr);
+        } else {
+            int32_t *si;
+            float *sd;
+            HIPC(hipMallocAsync((void **)&si, sizeof(int32_t) * nseg * nretry * KNN_CAND, s));
+            HIPC(hipMallocAsync((void **)&sd, sizeof(float) * nseg * nretry * KNN_CAND, s));
+            KNN_DISPATCH(launch_cand, dim3((unsigned)rb, (unsigned)nseg), block, s, Qh, Ql, Qn, (int64_t)nretry,
+                         Xh, Xl, Xn, N, ex, 0, 0, (const int32_t *)(retry + 1), si, thr, sd);
+            hipLaunchKernelGGL(k_knn_merge_seg, dim3((unsigned)((nretry + 3) / 4)), dim3(256), 0, s,
+                               (int64_t)nretry, nseg, (const int32_t *)(retry + 1), si, sd, cand, thr);
+            HIPC(hipFreeAsync(si, s));
+            HIPC(hipFreeAsync(sd, s));
+        }
         HIPC(hipGetLastError());
     }
     HIPC(hipFreeAsync(ocnt, s));
