@@ -550,7 +550,7 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
                                                        const float *__restrict__ Tin,
                                                        int cap, int32_t *__restrict__ ocnt,
                                                        float *__restrict__ od,
-                                                       int32_t *__restrict__ oi)
+                                                       int32_t *__restrict__ oi, int win_tiles)
 {
     constexpr int DP = KS * 16;
     constexpr int LDB = DP + 8;
@@ -591,8 +591,14 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     const uint32_t qbase = (uint32_t)q0 + 4u * (uint32_t)half;
     const int64_t ntiles_all = (N + KB_N - 1) / KB_N;
     const int64_t tself = ((row0 + (int64_t)blockIdx.x * KB_M) / KB_N) % ntiles_all;   // the block's own tile
-    const int64_t ntiles = SYM ? ntiles_all - tself : ntiles_all;
-    const int64_t t0 = tself;
+    int64_t ntiles = SYM ? ntiles_all - tself : ntiles_all;
+    int64_t t0 = tself;
+    if (!SYM && win_tiles > 0 && win_tiles < ntiles_all) {
+        // the win_tiles tiles centred on the block's rows (the window pass's range)
+        ntiles = win_tiles;
+        const int64_t c = (row0 + (int64_t)blockIdx.x * KB_M) / KB_N + (KB_M / KB_N) / 2 - win_tiles / 2;
+        t0 = c < 0 ? 0 : (c + win_tiles > ntiles_all ? ntiles_all - win_tiles : c);
+    }
     constexpr int CHUNKS = KB_N * DP / 8;
     constexpr int PER = (CHUNKS + 255) / 256;
     uint4 rh[1][PER], rl[1][PER];
@@ -664,21 +670,33 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
         if (__ballot(any)) {
             const uint32_t cA = (uint32_t)tbase + (uint32_t)l32, cB = cA + 32u;
             const uint32_t n32 = (uint32_t)N;
+            const uint32_t below = (1u << l32) - 1u;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
+                // the 32 lanes of a half-wave hold the same row: one counter
+                // update per row and half-wave, lanes write at their prefix
                 const uint32_t qrow = qbase + (uint32_t)(8 * (r / 4) + (r % 4));
                 const float dA = fmaf(-2.0f, c0[r], qn[r] + ny0);
                 const float dB = fmaf(-2.0f, c1[r], qn[r] + ny1);
-                if (dA <= thrv[r] && cA < n32 && !(excl && cA == qrow + (uint32_t)row0)) {
-                    uint32_t p = (uint32_t)atomicAdd(&ocnt[qrow], 1);
+                const bool pA = dA <= thrv[r] && cA < n32 && !(excl && cA == qrow + (uint32_t)row0);
+                const bool pB = dB <= thrv[r] && cB < n32 && !(excl && cB == qrow + (uint32_t)row0);
+                const uint64_t bA = __ballot(pA), bB = __ballot(pB);
+                const uint32_t hA = (uint32_t)(bA >> (32 * half)), hB = (uint32_t)(bB >> (32 * half));
+                if ((hA | hB) == 0u) continue;
+                const int lead = 32 * half + __ffs(hA | hB) - 1;
+                uint32_t p0 = 0;
+                if (lane == lead) p0 = (uint32_t)atomicAdd(&ocnt[qrow], __popc(hA) + __popc(hB));
+                p0 = (uint32_t)__shfl((int)p0, lead);
+                if (pA) {
+                    const uint32_t p = p0 + __popc(hA & below);
                     if (p < (uint32_t)cap) {
                         const size_t o = (size_t)qrow * (uint32_t)cap + p;
                         od[o] = dA;
                         oi[o] = (int32_t)cA;
                     }
                 }
-                if (dB <= thrv[r] && cB < n32 && !(excl && cB == qrow + (uint32_t)row0)) {
-                    uint32_t p = (uint32_t)atomicAdd(&ocnt[qrow], 1);
+                if (pB) {
+                    const uint32_t p = p0 + __popc(hA) + __popc(hB & below);
                     if (p < (uint32_t)cap) {
                         const size_t o = (size_t)qrow * (uint32_t)cap + p;
                         od[o] = dB;
@@ -791,14 +809,14 @@ template <int KS>
 static void launch_filter(dim3 g, dim3 b, hipStream_t s, const uint16_t *Qh, const uint16_t *Ql,
                           const float *Qn, int64_t M, const uint16_t *Xh, const uint16_t *Xl,
                           const float *Xn, int64_t N, int ex, int64_t row0, const float *T, int cap,
-                          int32_t *ocnt, float *od, int32_t *oi, bool sym)
+                          int32_t *ocnt, float *od, int32_t *oi, bool sym, int win = 0)
 {
     if (sym)
         hipLaunchKernelGGL((k_knn_filter<KS, true>), g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, row0, T, cap,
-                           ocnt, od, oi);
+                           ocnt, od, oi, 0);
     else
         hipLaunchKernelGGL((k_knn_filter<KS, false>), g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, row0, T,
-                           cap, ocnt, od, oi);
+                           cap, ocnt, od, oi, win);
 }
 
 __global__ void k_widen(float *__restrict__ T, int64_t M)
@@ -849,22 +867,40 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
         HIPC(hipGetLastError());
         return;
     }
-    // window pass: thr = 64th approximate distance among 4096 tree-order neighbours
-    KNN_DISPATCH(launch_cand, grid, block, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, WIN,
-                 (const int32_t *)nullptr, cand, thr);
-    hipLaunchKernelGGL(k_widen, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M);
     // the point set against itself with every row's segment in one buffer:
     // one triangular sweep (each unordered pair once); else row chunks
     const bool sym = exclude_self && Qh == Xh && M == N && (double)N * CAP * 8.0 <= 48.0 * (1ull << 30);
     const int64_t chunk = sym ? M : CHUNK;
     const int64_t mc = std::min<int64_t>(M, chunk);
-    int32_t *ocnt, *oi, *retry;
+    int32_t *ocnt, *oi, *retry, *wflag;
     float *od;
     HIPC(hipMallocAsync((void **)&ocnt, sizeof(int32_t) * mc, s));
     HIPC(hipMallocAsync((void **)&od, sizeof(float) * mc * CAP, s));
     HIPC(hipMallocAsync((void **)&oi, sizeof(int32_t) * mc * CAP, s));
     HIPC(hipMallocAsync((void **)&retry, sizeof(int32_t) * (M + 1), s));
+    HIPC(hipMallocAsync((void **)&wflag, sizeof(int32_t) * (M + 1), s));
     HIPC(hipMemsetAsync(retry, 0, sizeof(int32_t), s));
+    HIPC(hipMemsetAsync(wflag, 0, sizeof(int32_t), s));
+    // window threshold: thr = 64th approximate distance among the 4096
+    // tree-order neighbours of the row's block, in three steps with the same
+    // arithmetic: lists over the block's own two tiles bound it; the threshold
+    // filter over the window at that bound keeps every closer point (so at
+    // least those 64); their 64th is the exact window value (or a bound, when
+    // more than CAP survive)
+    KNN_DISPATCH(launch_cand, grid, block, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, 2,
+                 (const int32_t *)nullptr, cand, thr);
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M);
+    for (int64_t r0 = 0; r0 < M; r0 += chunk) {
+        const int64_t m = std::min<int64_t>(chunk, M - r0);
+        dim3 g((unsigned)((m + KB_M - 1) / KB_M));
+        HIPC(hipMemsetAsync(ocnt, 0, sizeof(int32_t) * m, s));
+        KNN_DISPATCH(launch_filter, g, block, s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, CAP, ocnt, od,
+                     oi, false, WIN);
+        hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, CAP, ocnt,
+                           od, oi, cand, thr, wflag + 1, wflag);
+        HIPC(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M);
     std::vector<hipEvent_t> ev;             // brackets of each filter launch (timing only)
     for (int64_t r0 = 0; r0 < M; r0 += chunk) {
         const int64_t m = std::min<int64_t>(chunk, M - r0);
@@ -925,6 +961,7 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     HIPC(hipFreeAsync(od, s));
     HIPC(hipFreeAsync(oi, s));
     HIPC(hipFreeAsync(retry, s));
+    HIPC(hipFreeAsync(wflag, s));
     (void)bad_rows;
     (void)bad_count;
 }
