@@ -33,11 +33,27 @@ inline int round_up(int x, int a) { return (x + a - 1) / a * a; }
 
 // ---------------------------------------------------------------- device helpers
 // Canonical squared distance: FP64, increasing k, no fused multiply-add.
+// Rows are 16-byte aligned (stride dp, a multiple of 16), so they are read
+// four coordinates at a time; the sum still runs over k in order.
 __device__ __forceinline__ double canon_sqdist(const float *a, const float *b, int d)
 {
 #pragma clang fp contract(off)
     double s = 0.0;
-    for (int k = 0; k < d; ++k) {
+    int k = 0;
+    for (; k + 4 <= d; k += 4) {
+        const float4 x = *reinterpret_cast<const float4 *>(a + k);
+        const float4 y = *reinterpret_cast<const float4 *>(b + k);
+        double t;
+        t = (double)x.x - (double)y.x;
+        s += t * t;
+        t = (double)x.y - (double)y.y;
+        s += t * t;
+        t = (double)x.z - (double)y.z;
+        s += t * t;
+        t = (double)x.w - (double)y.w;
+        s += t * t;
+    }
+    for (; k < d; ++k) {
         double t = (double)a[k] - (double)b[k];
         s += t * t;
     }
@@ -48,7 +64,20 @@ __device__ __forceinline__ double canon_sqdist_c(const float *a, const double *c
 {
 #pragma clang fp contract(off)
     double s = 0.0;
-    for (int k = 0; k < d; ++k) {
+    int k = 0;
+    for (; k + 4 <= d; k += 4) {
+        const float4 x = *reinterpret_cast<const float4 *>(a + k);
+        double t;
+        t = (double)x.x - c[k];
+        s += t * t;
+        t = (double)x.y - c[k + 1];
+        s += t * t;
+        t = (double)x.z - c[k + 2];
+        s += t * t;
+        t = (double)x.w - c[k + 3];
+        s += t * t;
+    }
+    for (; k < d; ++k) {
         double t = (double)a[k] - c[k];
         s += t * t;
     }

@@ -48,14 +48,21 @@ __global__ void k_block_sums(const float *__restrict__ X, int dp, int d,
     bool ok = i < s.n;
     const float *x = ok ? X + (int64_t)perm[s.lo + i] * dp : X;
     double *out = bsum + ((int64_t)q * maxblk + b) * d;
-    for (int k = 0; k < d; ++k) {
-        double v = ok ? (double)x[k] : 0.0;
+    for (int k0 = 0; k0 < d; k0 += 4) {           // four coordinates per load (rows padded to dp)
+        float4 x4 = {0.f, 0.f, 0.f, 0.f};
+        if (ok) x4 = *reinterpret_cast<const float4 *>(x + k0);
+        const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-            double w = __shfl_down(v, o);
-            v = v + w;
+        for (int j = 0; j < 4; ++j) {
+            if (k0 + j >= d) break;
+            double v = (double)xs[j];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                double w = __shfl_down(v, o);
+                v = v + w;
+            }
+            if (lane == 0) out[k0 + j] = v;
         }
-        if (lane == 0) out[k] = v;
     }
 }
 
@@ -138,7 +145,21 @@ __global__ void k_project(const float *__restrict__ X, int dp, int d, const int3
     const float *xl = X + (int64_t)L[q] * dp;
     const float *xr = X + (int64_t)Rr[q] * dp;
     double acc = 0.0;
-    for (int k = 0; k < d; ++k) {
+    int k = 0;
+    for (; k + 4 <= d; k += 4) {                  // rows are 16-byte aligned; k stays in order
+        const float4 x4 = *reinterpret_cast<const float4 *>(x + k);
+        const float4 l4 = *reinterpret_cast<const float4 *>(xl + k);
+        const float4 r4 = *reinterpret_cast<const float4 *>(xr + k);
+        const float xs[4] = {x4.x, x4.y, x4.z, x4.w}, ls[4] = {l4.x, l4.y, l4.z, l4.w};
+        const float rs[4] = {r4.x, r4.y, r4.z, r4.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double a = (double)xs[j] - (double)ls[j];
+            double b = (double)rs[j] - (double)ls[j];
+            acc += a * b;
+        }
+    }
+    for (; k < d; ++k) {
         double a = (double)x[k] - (double)xl[k];
         double b = (double)xr[k] - (double)xl[k];
         acc += a * b;
