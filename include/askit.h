@@ -119,6 +119,18 @@ askit_status askit_evaluate(askit_handle *h, float *U, int64_t ldu, void *stream
 askit_status askit_query(askit_handle *h, const float *Y, int64_t M, int64_t ldy, float *U,
                          int64_t ldu, void *stream);
 
+/*
+ * The kappa nearest sources of M new points Y (device, M x d FP32, row
+ * stride ldy): the neighbour search that askit_query runs for its targets
+ * (Sec. 3.1; Alg. 4 prunes with these lists).  idx (device, M x kappa int32,
+ * row stride kappa) receives original point ids and dist (device, M x kappa
+ * FP64, same layout) the squared Euclidean distances, each row in increasing
+ * (distance, id) order; the result is exact.  Needs no weights.  1 <= M;
+ * synchronises `stream`.  Outputs are owned by the caller.
+ */
+askit_status askit_query_neighbors(askit_handle *h, const float *Y, int64_t M, int64_t ldy, int32_t *idx,
+                                   double *dist, void *stream);
+
 void askit_destroy(askit_handle *h);
 
 /* Thread-local description of the last error on the calling thread ("" if none). */

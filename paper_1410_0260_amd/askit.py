@@ -62,7 +62,8 @@ class AskitError(RuntimeError):
 _lib = None
 
 EXPORTED = ["askit_params_default", "askit_setup", "askit_update_weights", "askit_evaluate",
-            "askit_query", "askit_destroy", "askit_last_error", "askit_get_info", "askit_export"]
+            "askit_query", "askit_query_neighbors", "askit_destroy", "askit_last_error", "askit_get_info",
+            "askit_export"]
 
 
 def lib():
@@ -78,6 +79,7 @@ def lib():
         L.askit_update_weights.argtypes = [P, P, i64, i32, P]
         L.askit_evaluate.argtypes = [P, P, i64, P]
         L.askit_query.argtypes = [P, P, i64, i64, P, i64, P]
+        L.askit_query_neighbors.argtypes = [P, P, i64, i64, P, P, P]
         L.askit_destroy.argtypes = [P]
         L.askit_destroy.restype = None
         L.askit_last_error.restype = C.c_char_p
@@ -152,6 +154,19 @@ class Handle:
         _check(lib().askit_query(self.ptr, C.c_void_p(Yd.data_ptr()), M, Yd.stride(0),
                                  C.c_void_p(U.data_ptr()), U.stride(0), _stream(torch)))
         return U
+
+    def query_neighbors(self, Y):
+        """(ids, squared distances) of the kappa nearest sources of each row of Y."""
+        import torch
+        kappa = self.info()["kappa"]
+        Yd = _dev_f32(torch, Y)
+        M = Yd.shape[0]
+        idx = torch.empty((M, kappa), device="cuda", dtype=torch.int32)
+        dist = torch.empty((M, kappa), device="cuda", dtype=torch.float64)
+        _check(lib().askit_query_neighbors(self.ptr, C.c_void_p(Yd.data_ptr()), M, Yd.stride(0),
+                                           C.c_void_p(idx.data_ptr()), C.c_void_p(dist.data_ptr()),
+                                           _stream(torch)))
+        return idx, dist
 
     def info(self) -> dict:
         i = Info()

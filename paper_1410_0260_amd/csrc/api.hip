@@ -104,6 +104,39 @@ void permute_weights(askit_handle *h, const float *W, int64_t ldw, WeightSet &ws
     HIPC(hipGetLastError());
 }
 
+// Exact kappa nearest sources of M new points (original ids and FP64 squared
+// distances, M x kappa each); Yp receives the packed points.  Temporaries come
+// from ta (freed by the caller's guard).
+static void query_knn(askit_handle *h, const float *Y, int64_t M, int64_t ldy, float *Yp, int32_t *qidx,
+                      double *qd, const std::function<void *(size_t)> &ta, hipStream_t s)
+{
+    const int dp = h->dp, kappa = h->kappa;
+    uint16_t *Yh = (uint16_t *)ta(sizeof(uint16_t) * M * dp);
+    uint16_t *Yl = (uint16_t *)ta(sizeof(uint16_t) * M * dp);
+    float *Yn = (float *)ta(sizeof(float) * M);
+    int32_t *flag = (int32_t *)ta(sizeof(int32_t) * (M + 1));
+    int32_t *cand = (int32_t *)ta(sizeof(int32_t) * M * KNN_CAND);
+    float *thr = (float *)ta(sizeof(float) * M);
+    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    pack_points(Y, M, h->d, ldy, dp, Yp, flag, s);
+    int32_t hflag = 0;
+    HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hflag) fail(ASKIT_ERR_INVALID_ARG, "Y holds a non-finite value");
+    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    split_bf16(Yp, M, dp, Yh, Yl, Yn, s);
+    knn_candidates(Yh, Yl, Yn, M, h->Xh, h->Xl, h->Xn, h->N, dp, false, false, cand, thr, flag + 1,
+                   flag, s, nullptr, nullptr, nullptr, &h->ksamp);
+    float *tb = (float *)ta(sizeof(float) * M);
+    knn_refine(Yp, M, h->Xt, h->N, h->d, dp, kappa, cand, thr, Yn, h->maxnorm, h->perm, nullptr, qidx,
+               qd, flag + 1, flag, tb, s);
+    int32_t nbad = 0;
+    HIPC(hipMemcpyAsync(&nbad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    knn_fallback(Yp, Yh, Yl, Yn, h->Xt, h->Xh, h->Xl, h->Xn, h->N, h->d, dp, kappa, false, flag + 1, nbad, tb,
+                 h->perm, nullptr, qidx, qd, s);
+}
+
 void query_points(askit_handle *h, const WeightSet &ws, const float *Y, int64_t M, int64_t ldy, float *U,
                   int64_t ldu, hipStream_t s)
 {
@@ -121,36 +154,13 @@ void query_points(askit_handle *h, const WeightSet &ws, const float *Y, int64_t 
         return p;
     };
     float *Yp = (float *)ta(sizeof(float) * M * dp);
-    uint16_t *Yh = (uint16_t *)ta(sizeof(uint16_t) * M * dp);
-    uint16_t *Yl = (uint16_t *)ta(sizeof(uint16_t) * M * dp);
-    float *Yn = (float *)ta(sizeof(float) * M);
-    int32_t *flag = (int32_t *)ta(sizeof(int32_t) * (M + 1));
-    int32_t *cand = (int32_t *)ta(sizeof(int32_t) * M * KNN_CAND);
-    float *thr = (float *)ta(sizeof(float) * M);
     int32_t *qidx = (int32_t *)ta(sizeof(int32_t) * M * kappa);
     double *qd = (double *)ta(sizeof(double) * M * kappa);
     int32_t *nb = (int32_t *)ta(sizeof(int32_t) * M * kappa);
     int32_t *nbs = (int32_t *)ta(sizeof(int32_t) * M * kappa);
     int32_t *order = (int32_t *)ta(sizeof(int32_t) * M);
     float *Ys = (float *)ta(sizeof(float) * M * dp);
-    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    pack_points(Y, M, h->d, ldy, dp, Yp, flag, s);
-    int32_t hflag = 0;
-    HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    if (hflag) fail(ASKIT_ERR_INVALID_ARG, "Y holds a non-finite value");
-    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    split_bf16(Yp, M, dp, Yh, Yl, Yn, s);
-    knn_candidates(Yh, Yl, Yn, M, h->Xh, h->Xl, h->Xn, h->N, dp, false, false, cand, thr, flag + 1,
-                   flag, s);
-    float *tb = (float *)ta(sizeof(float) * M);
-    knn_refine(Yp, M, h->Xt, h->N, h->d, dp, kappa, cand, thr, Yn, h->maxnorm, h->perm, nullptr, qidx,
-               qd, flag + 1, flag, tb, s);
-    int32_t nbad = 0;
-    HIPC(hipMemcpyAsync(&nbad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    knn_fallback(Yp, Yh, Yl, Yn, h->Xt, h->Xh, h->Xl, h->Xn, h->N, h->d, dp, kappa, false, flag + 1, nbad, tb,
-                 h->perm, nullptr, qidx, qd, s);
+    query_knn(h, Y, M, ldy, Yp, qidx, qd, ta, s);
     hipLaunchKernelGGL(k_map_pos, dim3((unsigned)((M * kappa + 255) / 256)), dim3(256), 0, s, qidx,
                        M * kappa, h->iperm, nb);
     HIPC(hipGetLastError());
@@ -398,6 +408,7 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
     HIPC(hipEventRecord(ev[1], s));
     // ---- exact neighbours, swept in tree order (each block starts at its own leaf)
     split_bf16(h->Xt, N, dp, h->Xh, h->Xl, h->Xn, s);
+    knn_build_sample(h.get(), s);
     float mx = max_norm(h->Xn, N, s);
     h->maxnorm = mx;
     {
@@ -527,6 +538,32 @@ askit_status askit_query(askit_handle *h, const float *Y, int64_t M, int64_t ldy
     if (h->ws.R < 1) fail(ASKIT_ERR_NOT_READY, "askit_update_weights has not been called");
     if (ldu < h->ws.R) fail(ASKIT_ERR_INVALID_ARG, "need ldu >= nrhs");
     query_points(h, h->ws, Y, M, ldy, U, ldu, (hipStream_t)stream);
+    API_END
+}
+
+askit_status askit_query_neighbors(askit_handle *h, const float *Y, int64_t M, int64_t ldy, int32_t *idx,
+                                   double *dist, void *stream)
+{
+    API_BEGIN
+    if (!h || !Y || !idx || !dist) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    if (M < 1 || M >= (1ll << 31)) fail(ASKIT_ERR_INVALID_ARG, "need 1 <= M < 2^31");
+    if (ldy < h->d) fail(ASKIT_ERR_INVALID_ARG, "need ldy >= d");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<void *> tmp;
+    struct Guard {
+        std::vector<void *> &t;
+        hipStream_t s;
+        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+    } guard{tmp, s};
+    auto ta = [&](size_t b) {
+        void *p;
+        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        tmp.push_back(p);
+        return p;
+    };
+    float *Yp = (float *)ta(sizeof(float) * M * h->dp);
+    query_knn(h, Y, M, ldy, Yp, idx, dist, ta, s);
+    HIPC(hipStreamSynchronize(s));
     API_END
 }
 

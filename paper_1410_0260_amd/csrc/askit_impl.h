@@ -132,6 +132,18 @@ struct PairLists {
     Chunk *chunks = nullptr;
 };
 
+// Strided samples of the tree-ordered points for neighbour searches of new
+// points: level j holds every (8^(L-j))-th position (bf16 hi / lo rows and
+// FP32 squared norms copied from the full set), so level 0 is the coarsest
+// and each level is a subset of the next.
+struct KnnSample {
+    static constexpr int MAXL = 10;
+    int levels = 0;
+    uint16_t *h[MAXL] = {}, *l[MAXL] = {};
+    float *n[MAXL] = {};
+    int64_t rows[MAXL] = {};
+};
+
 }  // namespace askit
 
 struct askit_handle {
@@ -186,6 +198,7 @@ struct askit_handle {
     uint64_t *sl_mask = nullptr;
     int64_t near_entries = 0, far_entries = 0;
     askit::PairLists pairs;       // the same pairs grouped by source node (evaluation work)
+    askit::KnnSample ksamp;       // query threshold samples (levels == 0: none)
 
     // diagnostics
     int64_t near_pairs = 0, far_pairs = 0, knn_uncertified = 0;
@@ -219,7 +232,11 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
                     const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int dp,
                     bool exclude_self, bool start_local, int32_t *cand, float *thr,
                     int32_t *bad_rows, int32_t *bad_count, hipStream_t s,
-                    float *t_filter_ms = nullptr, int *n_filter = nullptr, int *n_retry = nullptr);
+                    float *t_filter_ms = nullptr, int *n_filter = nullptr, int *n_retry = nullptr,
+                    const KnnSample *samp = nullptr);
+// Fills h->ksamp from the tree-ordered bf16 points when the point set is large
+// enough for the sampled query search (allocations owned by the handle).
+void knn_build_sample(askit_handle *h, hipStream_t s);
 void knn_refine(const float *Q, int64_t M, const float *X, int64_t N, int d, int dp, int kappa,
                 const int32_t *cand, const float *thr, const float *Qn, float maxnorm,
                 const int32_t *idmap, const int32_t *rowmap, int32_t *idx, double *dist,

@@ -599,6 +599,14 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
         const int64_t c = (row0 + (int64_t)blockIdx.x * KB_M) / KB_N + (KB_M / KB_N) / 2 - win_tiles / 2;
         t0 = c < 0 ? 0 : (c + win_tiles > ntiles_all ? ntiles_all - win_tiles : c);
     }
+    if (!SYM && gridDim.y > 1) {
+        // column segment blockIdx.y of gridDim.y contiguous tile ranges (the
+        // segments of a row append to the same output segment)
+        const int64_t per = (ntiles_all + gridDim.y - 1) / gridDim.y;
+        t0 = (int64_t)blockIdx.y * per;
+        ntiles = t0 < ntiles_all ? min(per, ntiles_all - t0) : 0;
+    }
+    if (ntiles <= 0) return;
     constexpr int CHUNKS = KB_N * DP / 8;
     constexpr int PER = (CHUNKS + 255) / 256;
     uint4 rh[1][PER], rl[1][PER];
@@ -819,6 +827,12 @@ static void launch_filter(dim3 g, dim3 b, hipStream_t s, const uint16_t *Qh, con
                            cap, ocnt, od, oi, win);
 }
 
+__global__ void k_fill_f32(float *__restrict__ p, int64_t n, float v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void k_widen(float *__restrict__ T, int64_t M)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -840,15 +854,58 @@ __global__ void k_widen(float *__restrict__ T, int64_t M)
     default: FN<8>(__VA_ARGS__); break;                                                            \
     }
 
+// List sweep of every point for rows [0, M) (through qpos when given): with
+// few row blocks the point range is split in segments so that about 2048
+// workgroups share the sweep, and the segment lists are merged per row.  With
+// seeded, thr holds each row's known bound on entry (segments only).
+template <int KS>
+static void list_sweep(hipStream_t s, const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int64_t M,
+                       const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int ex, int sl,
+                       const int32_t *qpos, bool seeded, int32_t *cand, float *thr)
+{
+    const int64_t ntiles = (N + KB_N - 1) / KB_N;
+    const int rb = (int)((M + KB_M - 1) / KB_M);
+    const int nseg = (int)std::max<int64_t>(1, std::min<int64_t>({32, 2048 / rb, ntiles / 16}));
+    if (nseg == 1) {
+        launch_cand<KS>(dim3((unsigned)rb), dim3(256), s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, 0, qpos, cand,
+                        thr);
+    } else {
+        int32_t *si;
+        float *sd;
+        HIPC(hipMallocAsync((void **)&si, sizeof(int32_t) * nseg * M * KNN_CAND, s));
+        HIPC(hipMallocAsync((void **)&sd, sizeof(float) * nseg * M * KNN_CAND, s));
+        if (!seeded) {
+            // unseeded: every row starts from +inf (the rows are the identity map)
+            hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M, INFINITY);
+        }
+        launch_cand<KS>(dim3((unsigned)rb, (unsigned)nseg), dim3(256), s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, 0, 0,
+                        qpos, si, thr, sd);
+        hipLaunchKernelGGL(k_knn_merge_seg, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, s, M, nseg, qpos, si, sd,
+                           cand, thr);
+        HIPC(hipFreeAsync(si, s));
+        HIPC(hipFreeAsync(sd, s));
+    }
+    HIPC(hipGetLastError());
+}
+
+// Column segments of a filter launch over rows [0, m): enough workgroups to
+// fill the chip when the row blocks alone do not.
+static int filter_segments(int64_t m, int64_t ntiles)
+{
+    const int64_t rb = (m + KB_M - 1) / KB_M;
+    return (int)std::max<int64_t>(1, std::min<int64_t>({64, 2048 / rb, ntiles / 16}));
+}
+
 void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int64_t M,
                     const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int dp,
                     bool exclude_self, bool start_local, int32_t *cand, float *thr,
                     int32_t *bad_rows, int32_t *bad_count, hipStream_t s, float *t_filter_ms,
-                    int *n_filter, int *n_retry)
+                    int *n_filter, int *n_retry, const KnnSample *samp)
 {
     if (t_filter_ms) *t_filter_ms = 0.f;
     if (n_filter) *n_filter = 0;
     if (n_retry) *n_retry = 0;
+    if (M <= 0) return;
     dim3 grid((unsigned)((M + KB_M - 1) / KB_M)), block(256);
     int ex = exclude_self ? 1 : 0, sl = start_local ? 1 : 0;
     const int64_t ntiles = (N + KB_N - 1) / KB_N;
@@ -861,10 +918,11 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     constexpr int WIN = 64;                 // window tiles (4096 points)
     constexpr int CAP = 1024;               // filter output per row
     constexpr int64_t CHUNK = 1 << 20;      // query rows per filter pass (bounds the buffers)
-    if (!start_local || ntiles <= 4 * WIN) {
-        KNN_DISPATCH(launch_cand, grid, block, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, 0,
-                     (const int32_t *)nullptr, cand, thr);
-        HIPC(hipGetLastError());
+    // new points against the set: thresholds from the strided samples
+    const bool sampled = !exclude_self && !start_local && samp && samp->levels > 0 && ntiles > 4 * WIN;
+    if (!sampled && (!start_local || ntiles <= 4 * WIN)) {
+        KNN_DISPATCH(list_sweep, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, (const int32_t *)nullptr, false, cand,
+                     thr);
         return;
     }
     // the point set against itself with every row's segment in one buffer:
@@ -881,30 +939,56 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     HIPC(hipMallocAsync((void **)&wflag, sizeof(int32_t) * (M + 1), s));
     HIPC(hipMemsetAsync(retry, 0, sizeof(int32_t), s));
     HIPC(hipMemsetAsync(wflag, 0, sizeof(int32_t), s));
-    // window threshold: thr = 64th approximate distance among the 4096
-    // tree-order neighbours of the row's block, in three steps with the same
-    // arithmetic: lists over the block's own two tiles bound it; the threshold
-    // filter over the window at that bound keeps every closer point (so at
-    // least those 64); their 64th is the exact window value (or a bound, when
-    // more than CAP survive)
-    KNN_DISPATCH(launch_cand, grid, block, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, 2,
-                 (const int32_t *)nullptr, cand, thr);
-    hipLaunchKernelGGL(k_widen, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M);
-    for (int64_t r0 = 0; r0 < M; r0 += chunk) {
-        const int64_t m = std::min<int64_t>(chunk, M - r0);
-        dim3 g((unsigned)((m + KB_M - 1) / KB_M));
-        HIPC(hipMemsetAsync(ocnt, 0, sizeof(int32_t) * m, s));
-        KNN_DISPATCH(launch_filter, g, block, s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, CAP, ocnt, od,
-                     oi, false, WIN);
-        hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, CAP, ocnt,
-                           od, oi, cand, thr, wflag + 1, wflag);
-        HIPC(hipGetLastError());
+    if (sampled) {
+        // thresholds refined level by level: every point of the coarsest
+        // sample (at most CAP) passes the filter at +inf; at each level the
+        // 64th smallest survivor bounds the row's 64th smallest distance over
+        // the whole set, and the next, 8 times denser, level (a superset)
+        // keeps at least those 64 at that bound -- about 512 points.  Each
+        // step only lowers a valid bound; the sample passes' candidate lists
+        // are scratch.
+        hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M, INFINITY);
+        for (int lv = 0; lv < samp->levels; ++lv) {
+            const int64_t nl = samp->rows[lv], ntl = (nl + KB_N - 1) / KB_N;
+            for (int64_t r0 = 0; r0 < M; r0 += chunk) {
+                const int64_t m = std::min<int64_t>(chunk, M - r0);
+                dim3 g((unsigned)((m + KB_M - 1) / KB_M), (unsigned)filter_segments(m, ntl));
+                HIPC(hipMemsetAsync(ocnt, 0, sizeof(int32_t) * m, s));
+                KNN_DISPATCH(launch_filter, g, block, s, Qh, Ql, Qn, m, samp->h[lv], samp->l[lv], samp->n[lv],
+                             nl, 0, r0, thr, CAP, ocnt, od, oi, false, 0);
+                hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, CAP,
+                                   ocnt, od, oi, cand, thr, wflag + 1, wflag);
+                HIPC(hipGetLastError());
+            }
+            if (lv + 1 < samp->levels)
+                hipLaunchKernelGGL(k_widen, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M);
+        }
+    } else {
+        // window threshold: thr = 64th approximate distance among the 4096
+        // tree-order neighbours of the row's block, in three steps with the
+        // same arithmetic: lists over the block's own two tiles bound it; the
+        // threshold filter over the window at that bound keeps every closer
+        // point (so at least those 64); their 64th is the exact window value
+        // (or a bound, when more than CAP survive)
+        KNN_DISPATCH(launch_cand, grid, block, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, 2,
+                     (const int32_t *)nullptr, cand, thr);
+        hipLaunchKernelGGL(k_widen, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M);
+        for (int64_t r0 = 0; r0 < M; r0 += chunk) {
+            const int64_t m = std::min<int64_t>(chunk, M - r0);
+            dim3 g((unsigned)((m + KB_M - 1) / KB_M));
+            HIPC(hipMemsetAsync(ocnt, 0, sizeof(int32_t) * m, s));
+            KNN_DISPATCH(launch_filter, g, block, s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, CAP, ocnt, od,
+                         oi, false, WIN);
+            hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, CAP, ocnt,
+                               od, oi, cand, thr, wflag + 1, wflag);
+            HIPC(hipGetLastError());
+        }
     }
     hipLaunchKernelGGL(k_widen, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M);
     std::vector<hipEvent_t> ev;             // brackets of each filter launch (timing only)
     for (int64_t r0 = 0; r0 < M; r0 += chunk) {
         const int64_t m = std::min<int64_t>(chunk, M - r0);
-        dim3 g((unsigned)((m + KB_M - 1) / KB_M));
+        dim3 g((unsigned)((m + KB_M - 1) / KB_M), (unsigned)(sym ? 1 : filter_segments(m, ntiles)));
         HIPC(hipMemsetAsync(ocnt, 0, sizeof(int32_t) * m, s));
         if (t_filter_ms) {
             ev.resize(ev.size() + 2);
@@ -919,7 +1003,8 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
                            od, oi, cand, thr, retry + 1, retry);
         HIPC(hipGetLastError());
     }
-    // rows whose segment overflowed: full list sweep on the compacted rows
+    // rows whose segment overflowed: full list sweep on the compacted rows,
+    // seeded with the bound the selection left
     int32_t nretry = 0;
     HIPC(hipMemcpyAsync(&nretry, retry, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
@@ -935,28 +1020,9 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
         if (n_filter) *n_filter = (int)(ev.size() / 2);
     }
     if (n_retry) *n_retry = nretry;
-    if (nretry > 0) {
-        // the overflowed rows sweep every point with lists; the point range is
-        // split in segments so that about 2048 workgroups share the sweep
-        const int rb = (int)((nretry + KB_M - 1) / KB_M);
-        const int nseg = (int)std::max<int64_t>(1, std::min<int64_t>({32, 2048 / rb, ntiles}));
-        if (nseg == 1) {
-            KNN_DISPATCH(launch_cand, dim3((unsigned)rb), block, s, Qh, Ql, Qn, (int64_t)nretry, Xh, Xl, Xn, N,
-                         ex, sl, 0, (const int32_t *)(retry + 1), cand, thr);
-        } else {
-            int32_t *si;
-            float *sd;
-            HIPC(hipMallocAsync((void **)&si, sizeof(int32_t) * nseg * nretry * KNN_CAND, s));
-            HIPC(hipMallocAsync((void **)&sd, sizeof(float) * nseg * nretry * KNN_CAND, s));
-            KNN_DISPATCH(launch_cand, dim3((unsigned)rb, (unsigned)nseg), block, s, Qh, Ql, Qn, (int64_t)nretry,
-                         Xh, Xl, Xn, N, ex, 0, 0, (const int32_t *)(retry + 1), si, thr, sd);
-            hipLaunchKernelGGL(k_knn_merge_seg, dim3((unsigned)((nretry + 3) / 4)), dim3(256), 0, s,
-                               (int64_t)nretry, nseg, (const int32_t *)(retry + 1), si, sd, cand, thr);
-            HIPC(hipFreeAsync(si, s));
-            HIPC(hipFreeAsync(sd, s));
-        }
-        HIPC(hipGetLastError());
-    }
+    if (nretry > 0)
+        KNN_DISPATCH(list_sweep, s, Qh, Ql, Qn, (int64_t)nretry, Xh, Xl, Xn, N, ex, sl,
+                     (const int32_t *)(retry + 1), true, cand, thr);
     HIPC(hipFreeAsync(ocnt, s));
     HIPC(hipFreeAsync(od, s));
     HIPC(hipFreeAsync(oi, s));
@@ -964,6 +1030,48 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     HIPC(hipFreeAsync(wflag, s));
     (void)bad_rows;
     (void)bad_count;
+}
+
+__global__ void k_stride_rows(const uint16_t *__restrict__ h, const uint16_t *__restrict__ l,
+                              const float *__restrict__ n, int dp, int stride, int64_t rows,
+                              uint16_t *__restrict__ oh, uint16_t *__restrict__ ol, float *__restrict__ on)
+{
+    const int cpr = dp / 8;                  // 16-byte chunks per row
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * cpr) return;
+    const int64_t r = i / cpr, c = i % cpr, src = r * stride;
+    *reinterpret_cast<uint4 *>(oh + r * dp + 8 * c) = *reinterpret_cast<const uint4 *>(h + src * dp + 8 * c);
+    *reinterpret_cast<uint4 *>(ol + r * dp + 8 * c) = *reinterpret_cast<const uint4 *>(l + src * dp + 8 * c);
+    if (c == 0) on[r] = n[src];
+}
+
+void knn_build_sample(askit_handle *h, hipStream_t s)
+{
+    h->ksamp = KnnSample{};
+    const int64_t N = h->N;
+    const int dp = h->dp;
+    constexpr int CAP = 1024;               // the filter output per row (see knn_candidates)
+    if (dp > 128 || (N + KB_N - 1) / KB_N <= 4 * 64) return;
+    // coarsest stride 8^L: the fewest levels whose coarsest sample fits CAP
+    int L = 1;
+    int64_t st = 8;
+    while ((N + st - 1) / st > CAP) {
+        st *= 8;
+        ++L;
+    }
+    if (L > KnnSample::MAXL) return;
+    for (int lv = 0; lv < L; ++lv, st /= 8) {
+        const int64_t rows = (N + st - 1) / st;              // positions st * r < N
+        h->ksamp.h[lv] = (uint16_t *)h->alloc(sizeof(uint16_t) * rows * dp, false);
+        h->ksamp.l[lv] = (uint16_t *)h->alloc(sizeof(uint16_t) * rows * dp, false);
+        h->ksamp.n[lv] = (float *)h->alloc(sizeof(float) * rows, false);
+        h->ksamp.rows[lv] = rows;
+        const int64_t nthr = rows * (dp / 8);
+        hipLaunchKernelGGL(k_stride_rows, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, h->Xh, h->Xl,
+                           h->Xn, dp, (int)st, rows, h->ksamp.h[lv], h->ksamp.l[lv], h->ksamp.n[lv]);
+        HIPC(hipGetLastError());
+    }
+    h->ksamp.levels = L;
 }
 
 // ---------------------------------------------------------------- refine

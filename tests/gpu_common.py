@@ -20,6 +20,8 @@ def run_both(X, W, wl_params, gpu_params, Y=None):
         Uq = h.query(torch.from_numpy(Y).cuda())
         torch.cuda.synchronize()
         g["Uq"] = Uq.cpu().numpy().astype(np.float64)
+        qi, qd = h.query_neighbors(torch.from_numpy(Y).cuda())
+        g["qidx"], g["qd"] = qi.cpu().numpy(), qd.cpu().numpy()
         st["query"] = O.query(st, Y)
     h.close()
     return st, g

@@ -3,7 +3,8 @@ launch configuration the benchmark times (same parameters, one RHS), on
 outputs the FP64 oracle can compute one by one:
 
   * the whole tree (permutation and every node) -- the oracle builds it in full;
-  * the kNN lists of sampled points (oracle exhaustive search per point);
+  * the kNN lists of sampled points (oracle exhaustive search per point), and
+    of 256 new points;
   * for a sampled leaf beta: its node list (Alg. 2, leaf rule), sampled rows
     (Eq. e:sk_targets), skeleton and P (Alg. 3), and its skeleton weights;
   * the interaction lists of sampled targets (Alg. 4 / Eq. e:prune);
@@ -60,6 +61,9 @@ def full():
     for r, o in enumerate(rows):
         keep = i1[r] != o
         kidx[r], kd[r] = i1[r][keep][:p.kappa], d1[r][keep][:p.kappa]
+    Yq = synth.queries(wl, 256, 77)
+    _log(f"[fullsize] oracle kNN of {len(Yq)} new points")
+    qidx_o, qd_o = O.knn(Yq, X, p.kappa, exclude_self=False)
     Wb = np.zeros((N, 1), np.float32)
     Wb[bpts, 0] = synth.weights(len(bpts), 1, 31)[:, 0]
 
@@ -69,9 +73,11 @@ def full():
     U = h.evaluate().cpu().numpy().astype(np.float64)[:, 0]
     torch.cuda.synchronize()
     g = h.structures()
+    qi, qd = h.query_neighbors(torch.from_numpy(Yq).cuda())
+    g["qidx"], g["qd"] = qi.cpu().numpy(), qd.cpu().numpy()
     h.close()
     return dict(wl=wl, p=p, X=X, N=N, nodes=nodes, perm=perm, iperm=iperm, beta=beta, sigma=sigma,
-                rows=rows, kidx=kidx, kd=kd, Wb=Wb, U=U, g=g)
+                rows=rows, kidx=kidx, kd=kd, Wb=Wb, U=U, g=g, qidx=qidx_o, qd=qd_o)
 
 
 def test_tree_full(full):
@@ -85,6 +91,12 @@ def test_knn_sampled(full):
     g, rows = full["g"], full["rows"]
     assert np.array_equal(g["knn_idx"][rows], full["kidx"])
     assert np.array_equal(g["knn_d"][rows], full["kd"])
+
+
+def test_query_knn(full):
+    """256 new points, through the sampled-threshold search at full size."""
+    assert np.array_equal(full["g"]["qidx"], full["qidx"])
+    assert np.array_equal(full["g"]["qd"], full["qd"])
 
 
 @pytest.fixture(scope="module")

@@ -175,6 +175,16 @@ def test_skeleton_weights(case):
             assert np.linalg.norm(g["Wsk"][a, :k] - ref) <= 1e-5 * max(1.0, np.linalg.norm(ref))
 
 
+def test_query_knn_bit_exact(case):
+    """Neighbours of the new points (the sampled-threshold search above 256
+    reference tiles) equal the oracle's exhaustive search, ids and FP64
+    distances."""
+    name, X, W, p, st, g = case
+    qi, qd, ev = st["query"]
+    assert np.array_equal(g["qidx"], qi)
+    assert np.array_equal(g["qd"], qd)
+
+
 def test_query_matches_oracle(case):
     name, X, W, p, st, g = case
     qi, qd, ev = st["query"]
