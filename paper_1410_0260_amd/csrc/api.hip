@@ -424,7 +424,7 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
         HIPC(hipEventRecord(k0, s));
         float fms = 0.f;
         knn_candidates(h->Xh, h->Xl, h->Xn, N, h->Xh, h->Xl, h->Xn, N, dp, true, true, cand, thr,
-                       bad + 1, bad, s, &fms, &h->knn_filter_launches, &h->knn_retry_rows);
+                       bad + 1, bad, s, &fms, &h->knn_filter_launches, &h->knn_retry_rows, &h->ksamp);
         h->t_knn_filter = fms;
         HIPC(hipEventRecord(k1, s));
         float *tb;

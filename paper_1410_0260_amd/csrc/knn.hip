@@ -765,7 +765,7 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
 
 // Per row (one wave): the 64 smallest (approximate distance, position) of the
 // filter's output, as candidates + the certificate threshold.  Rows whose
-// segment overflowed are listed for the retry sweep.
+// segment overflowed are listed for the retry sweep (when bad_count is given).
 __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int cap,
                                                     const int32_t *__restrict__ ocnt,
                                                     const float *__restrict__ od,
@@ -783,7 +783,7 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
     const float tin = thr[row];          // the filter threshold: every point left out is above it
     float ld = INFINITY;
     int li = 0x7fffffff;
-    if (n > cap && lane == 0) {
+    if (n > cap && lane == 0 && bad_count) {
         int p = atomicAdd(bad_count, 1);
         bad_rows[p] = (int32_t)row;
     }
@@ -896,6 +896,107 @@ static int filter_segments(int64_t m, int64_t ntiles)
     return (int)std::max<int64_t>(1, std::min<int64_t>({64, 2048 / rb, ntiles / 16}));
 }
 
+constexpr int KNN_WIN = 64;                 // window tiles (4096 points)
+constexpr int KNN_CAP = 1024;               // filter output per row
+constexpr int64_t KNN_CHUNK = 1 << 20;      // query rows per filter pass (bounds the buffers)
+
+// Filter output buffers of up to `rows` rows.
+struct FilterBufs {
+    int32_t *ocnt = nullptr, *oi = nullptr;
+    float *od = nullptr;
+};
+
+// Threshold filter of rows [0, M) against a reference set, in passes of
+// `chunk` rows, each followed by the selection (cand, thr of every row; rows
+// whose output overflowed appended to over[1..], count over[0], when over is
+// given).  win > 0: only the win tiles around each row block; sym: the
+// triangular sweep.  ev collects HIP events around each filter launch.
+static void filter_select(int dp, hipStream_t s, const uint16_t *Qh, const uint16_t *Ql, const float *Qn,
+                          int64_t M, const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int ex,
+                          int64_t chunk, float *thr, const FilterBufs &B, int32_t *cand, int32_t *over, bool sym,
+                          int win, std::vector<hipEvent_t> *ev)
+{
+    const int64_t ntl = (N + KB_N - 1) / KB_N;
+    for (int64_t r0 = 0; r0 < M; r0 += chunk) {
+        const int64_t m = std::min<int64_t>(chunk, M - r0);
+        dim3 g((unsigned)((m + KB_M - 1) / KB_M), (unsigned)((sym || win > 0) ? 1 : filter_segments(m, ntl)));
+        HIPC(hipMemsetAsync(B.ocnt, 0, sizeof(int32_t) * m, s));
+        if (ev) {
+            ev->resize(ev->size() + 2);
+            HIPC(hipEventCreate(&(*ev)[ev->size() - 2]));
+            HIPC(hipEventCreate(&ev->back()));
+            HIPC(hipEventRecord((*ev)[ev->size() - 2], s));
+        }
+        KNN_DISPATCH(launch_filter, g, dim3(256), s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, KNN_CAP, B.ocnt,
+                     B.od, B.oi, sym, win);
+        if (ev) HIPC(hipEventRecord(ev->back(), s));
+        hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, KNN_CAP, B.ocnt,
+                           B.od, B.oi, cand, thr, over ? over + 1 : nullptr, over);
+        HIPC(hipGetLastError());
+    }
+}
+
+static void widen(float *thr, int64_t M, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M);
+    HIPC(hipGetLastError());
+}
+
+// Thresholds from the nested strided samples for rows [0, M): every point of
+// the coarsest sample (at most KNN_CAP) passes the filter at +inf; at each
+// level the 64th smallest survivor bounds the row's 64th smallest distance
+// over the whole set (an upper bound: those 64 are real points), and the next,
+// 8 times denser, level (a superset) keeps at least those 64 at that bound --
+// about 512 points.  Each step only lowers a valid bound.  The sample passes'
+// candidate lists (in cand) are scratch; thr leaves widened.  No self
+// exclusion: a row that is itself a sample point may count itself.
+static void sample_thresholds(int dp, hipStream_t s, const uint16_t *Qh, const uint16_t *Ql, const float *Qn,
+                              int64_t M, const KnnSample &S, int64_t chunk, float *thr, const FilterBufs &B,
+                              int32_t *cand)
+{
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M, INFINITY);
+    for (int lv = 0; lv < S.levels; ++lv) {
+        filter_select(dp, s, Qh, Ql, Qn, M, S.h[lv], S.l[lv], S.n[lv], S.rows[lv], 0, chunk, thr, B, cand,
+                      nullptr, false, 0, nullptr);
+        widen(thr, M, s);
+    }
+}
+
+// Retry rows of the point set against itself (tree positions rows[0, n)),
+// filtered through compact copies: the compact candidates go back to their
+// rows with the row itself removed (the compact pass cannot exclude it; every
+// other point left out stays at or above the threshold, so the certificate
+// holds).  Rows that overflow again get an unseeded list sweep (thr = +inf:
+// the stored 64th may count the row itself).
+__global__ __launch_bounds__(256) void k_scatter_retry(int64_t n, const int32_t *__restrict__ rows,
+                                                       const int32_t *__restrict__ cc, const float *__restrict__ tc,
+                                                       const int32_t *__restrict__ ocnt, int cap,
+                                                       int32_t *__restrict__ cand, float *__restrict__ thr,
+                                                       int32_t *__restrict__ over_rows,
+                                                       int32_t *__restrict__ over_count)
+{
+    const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    if (i >= n) return;
+    const int64_t row = rows[i];
+    const int c = cc[i * KNN_CAND + lane];
+    cand[row * KNN_CAND + lane] = c == row ? -1 : c;
+    if (lane == 0) {
+        if (ocnt[i] > cap) {
+            over_rows[atomicAdd(over_count, 1)] = (int32_t)row;
+            thr[row] = INFINITY;
+        } else {
+            thr[row] = tc[i];
+        }
+    }
+}
+
+__global__ void k_gather_qrows(const int32_t *__restrict__ rows, int64_t n, int dp,
+                               const uint16_t *__restrict__ Qh, const uint16_t *__restrict__ Ql,
+                               const float *__restrict__ Qn, const float *__restrict__ tb,
+                               uint16_t *__restrict__ Bh, uint16_t *__restrict__ Bl, float *__restrict__ Bn,
+                               float *__restrict__ Bt);
+
 void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int64_t M,
                     const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int dp,
                     bool exclude_self, bool start_local, int32_t *cand, float *thr,
@@ -915,96 +1016,48 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
         HIPC(hipGetLastError());
         return;
     }
-    constexpr int WIN = 64;                 // window tiles (4096 points)
-    constexpr int CAP = 1024;               // filter output per row
-    constexpr int64_t CHUNK = 1 << 20;      // query rows per filter pass (bounds the buffers)
+    const bool have_samp = samp && samp->levels > 0 && ntiles > 4 * KNN_WIN;
     // new points against the set: thresholds from the strided samples
-    const bool sampled = !exclude_self && !start_local && samp && samp->levels > 0 && ntiles > 4 * WIN;
-    if (!sampled && (!start_local || ntiles <= 4 * WIN)) {
+    const bool sampled = !exclude_self && !start_local && have_samp;
+    if (!sampled && (!start_local || ntiles <= 4 * KNN_WIN)) {
         KNN_DISPATCH(list_sweep, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, (const int32_t *)nullptr, false, cand,
                      thr);
         return;
     }
     // the point set against itself with every row's segment in one buffer:
     // one triangular sweep (each unordered pair once); else row chunks
-    const bool sym = exclude_self && Qh == Xh && M == N && (double)N * CAP * 8.0 <= 48.0 * (1ull << 30);
-    const int64_t chunk = sym ? M : CHUNK;
+    const bool sym = exclude_self && Qh == Xh && M == N && (double)N * KNN_CAP * 8.0 <= 48.0 * (1ull << 30);
+    const int64_t chunk = sym ? M : KNN_CHUNK;
     const int64_t mc = std::min<int64_t>(M, chunk);
-    int32_t *ocnt, *oi, *retry, *wflag;
-    float *od;
-    HIPC(hipMallocAsync((void **)&ocnt, sizeof(int32_t) * mc, s));
-    HIPC(hipMallocAsync((void **)&od, sizeof(float) * mc * CAP, s));
-    HIPC(hipMallocAsync((void **)&oi, sizeof(int32_t) * mc * CAP, s));
+    FilterBufs B;
+    int32_t *retry, *over;
+    HIPC(hipMallocAsync((void **)&B.ocnt, sizeof(int32_t) * mc, s));
+    HIPC(hipMallocAsync((void **)&B.od, sizeof(float) * mc * KNN_CAP, s));
+    HIPC(hipMallocAsync((void **)&B.oi, sizeof(int32_t) * mc * KNN_CAP, s));
     HIPC(hipMallocAsync((void **)&retry, sizeof(int32_t) * (M + 1), s));
-    HIPC(hipMallocAsync((void **)&wflag, sizeof(int32_t) * (M + 1), s));
+    HIPC(hipMallocAsync((void **)&over, sizeof(int32_t) * (M + 1), s));
     HIPC(hipMemsetAsync(retry, 0, sizeof(int32_t), s));
-    HIPC(hipMemsetAsync(wflag, 0, sizeof(int32_t), s));
+    HIPC(hipMemsetAsync(over, 0, sizeof(int32_t), s));
     if (sampled) {
-        // thresholds refined level by level: every point of the coarsest
-        // sample (at most CAP) passes the filter at +inf; at each level the
-        // 64th smallest survivor bounds the row's 64th smallest distance over
-        // the whole set, and the next, 8 times denser, level (a superset)
-        // keeps at least those 64 at that bound -- about 512 points.  Each
-        // step only lowers a valid bound; the sample passes' candidate lists
-        // are scratch.
-        hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M, INFINITY);
-        for (int lv = 0; lv < samp->levels; ++lv) {
-            const int64_t nl = samp->rows[lv], ntl = (nl + KB_N - 1) / KB_N;
-            for (int64_t r0 = 0; r0 < M; r0 += chunk) {
-                const int64_t m = std::min<int64_t>(chunk, M - r0);
-                dim3 g((unsigned)((m + KB_M - 1) / KB_M), (unsigned)filter_segments(m, ntl));
-                HIPC(hipMemsetAsync(ocnt, 0, sizeof(int32_t) * m, s));
-                KNN_DISPATCH(launch_filter, g, block, s, Qh, Ql, Qn, m, samp->h[lv], samp->l[lv], samp->n[lv],
-                             nl, 0, r0, thr, CAP, ocnt, od, oi, false, 0);
-                hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, CAP,
-                                   ocnt, od, oi, cand, thr, wflag + 1, wflag);
-                HIPC(hipGetLastError());
-            }
-            if (lv + 1 < samp->levels)
-                hipLaunchKernelGGL(k_widen, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M);
-        }
+        sample_thresholds(dp, s, Qh, Ql, Qn, M, *samp, chunk, thr, B, cand);
     } else {
         // window threshold: thr = 64th approximate distance among the 4096
         // tree-order neighbours of the row's block, in three steps with the
-        // same arithmetic: lists over the block's own two tiles bound it; the
-        // threshold filter over the window at that bound keeps every closer
-        // point (so at least those 64); their 64th is the exact window value
-        // (or a bound, when more than CAP survive)
-        KNN_DISPATCH(launch_cand, grid, block, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, sl, 2,
-                     (const int32_t *)nullptr, cand, thr);
-        hipLaunchKernelGGL(k_widen, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M);
-        for (int64_t r0 = 0; r0 < M; r0 += chunk) {
-            const int64_t m = std::min<int64_t>(chunk, M - r0);
-            dim3 g((unsigned)((m + KB_M - 1) / KB_M));
-            HIPC(hipMemsetAsync(ocnt, 0, sizeof(int32_t) * m, s));
-            KNN_DISPATCH(launch_filter, g, block, s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, CAP, ocnt, od,
-                         oi, false, WIN);
-            hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, CAP, ocnt,
-                               od, oi, cand, thr, wflag + 1, wflag);
-            HIPC(hipGetLastError());
-        }
+        // same arithmetic: the 64th of the block's own two tiles (every point
+        // passes at +inf) bounds it; the threshold filter over the window at
+        // that bound keeps every closer point (so at least those 64); their
+        // 64th is the exact window value (or a bound, when more than the
+        // capacity survive)
+        hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M, INFINITY);
+        filter_select(dp, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, chunk, thr, B, cand, nullptr, false, 2, nullptr);
+        widen(thr, M, s);
+        filter_select(dp, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, chunk, thr, B, cand, nullptr, false, KNN_WIN,
+                      nullptr);
+        widen(thr, M, s);
     }
-    hipLaunchKernelGGL(k_widen, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M);
     std::vector<hipEvent_t> ev;             // brackets of each filter launch (timing only)
-    for (int64_t r0 = 0; r0 < M; r0 += chunk) {
-        const int64_t m = std::min<int64_t>(chunk, M - r0);
-        dim3 g((unsigned)((m + KB_M - 1) / KB_M), (unsigned)(sym ? 1 : filter_segments(m, ntiles)));
-        HIPC(hipMemsetAsync(ocnt, 0, sizeof(int32_t) * m, s));
-        if (t_filter_ms) {
-            ev.resize(ev.size() + 2);
-            HIPC(hipEventCreate(&ev[ev.size() - 2]));
-            HIPC(hipEventCreate(&ev.back()));
-            HIPC(hipEventRecord(ev[ev.size() - 2], s));
-        }
-        KNN_DISPATCH(launch_filter, g, block, s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, CAP, ocnt, od,
-                     oi, sym);
-        if (t_filter_ms) HIPC(hipEventRecord(ev.back(), s));
-        hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, CAP, ocnt,
-                           od, oi, cand, thr, retry + 1, retry);
-        HIPC(hipGetLastError());
-    }
-    // rows whose segment overflowed: full list sweep on the compacted rows,
-    // seeded with the bound the selection left
+    filter_select(dp, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, chunk, thr, B, cand, retry, sym, 0,
+                  t_filter_ms ? &ev : nullptr);
     int32_t nretry = 0;
     HIPC(hipMemcpyAsync(&nretry, retry, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
@@ -1020,14 +1073,48 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
         if (n_filter) *n_filter = (int)(ev.size() / 2);
     }
     if (n_retry) *n_retry = nretry;
-    if (nretry > 0)
-        KNN_DISPATCH(list_sweep, s, Qh, Ql, Qn, (int64_t)nretry, Xh, Xl, Xn, N, ex, sl,
-                     (const int32_t *)(retry + 1), true, cand, thr);
-    HIPC(hipFreeAsync(ocnt, s));
-    HIPC(hipFreeAsync(od, s));
-    HIPC(hipFreeAsync(oi, s));
+    // rows whose output overflowed (their window bound was far above their
+    // 64th distance)
+    const int32_t *list = retry + 1;
+    int32_t nlist = nretry;
+    if (nretry > 0 && nretry <= mc && exclude_self && have_samp && Qh == Xh) {
+        // the point set against itself: the sampled thresholds on compact
+        // copies of the rows, then the filter over all points (one pass: the
+        // rows fit the filter buffers)
+        const int64_t n = nretry;
+        uint16_t *Bh, *Bl;
+        float *Bn, *tc;
+        int32_t *cc;
+        HIPC(hipMallocAsync((void **)&Bh, sizeof(uint16_t) * n * dp, s));
+        HIPC(hipMallocAsync((void **)&Bl, sizeof(uint16_t) * n * dp, s));
+        HIPC(hipMallocAsync((void **)&Bn, sizeof(float) * n, s));
+        HIPC(hipMallocAsync((void **)&tc, sizeof(float) * n, s));
+        HIPC(hipMallocAsync((void **)&cc, sizeof(int32_t) * n * KNN_CAND, s));
+        hipLaunchKernelGGL(k_gather_qrows, dim3((unsigned)n), dim3(128), 0, s, list, n, dp, Qh, Ql, Qn, thr, Bh, Bl,
+                           Bn, tc);
+        sample_thresholds(dp, s, Bh, Bl, Bn, n, *samp, n, tc, B, cc);
+        filter_select(dp, s, Bh, Bl, Bn, n, Xh, Xl, Xn, N, 0, n, tc, B, cc, nullptr, false, 0, nullptr);
+        hipLaunchKernelGGL(k_scatter_retry, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, list, cc, tc,
+                           B.ocnt, KNN_CAP, cand, thr, over + 1, over);
+        HIPC(hipGetLastError());
+        HIPC(hipMemcpyAsync(&nlist, over, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        list = over + 1;
+        HIPC(hipFreeAsync(Bh, s));
+        HIPC(hipFreeAsync(Bl, s));
+        HIPC(hipFreeAsync(Bn, s));
+        HIPC(hipFreeAsync(tc, s));
+        HIPC(hipFreeAsync(cc, s));
+    }
+    // the rest: list sweep over every point on the compacted rows, seeded with
+    // the bound the selection left
+    if (nlist > 0)
+        KNN_DISPATCH(list_sweep, s, Qh, Ql, Qn, (int64_t)nlist, Xh, Xl, Xn, N, ex, sl, list, true, cand, thr);
+    HIPC(hipFreeAsync(B.ocnt, s));
+    HIPC(hipFreeAsync(B.od, s));
+    HIPC(hipFreeAsync(B.oi, s));
     HIPC(hipFreeAsync(retry, s));
-    HIPC(hipFreeAsync(wflag, s));
+    HIPC(hipFreeAsync(over, s));
     (void)bad_rows;
     (void)bad_count;
 }
@@ -1050,12 +1137,12 @@ void knn_build_sample(askit_handle *h, hipStream_t s)
     h->ksamp = KnnSample{};
     const int64_t N = h->N;
     const int dp = h->dp;
-    constexpr int CAP = 1024;               // the filter output per row (see knn_candidates)
-    if (dp > 128 || (N + KB_N - 1) / KB_N <= 4 * 64) return;
-    // coarsest stride 8^L: the fewest levels whose coarsest sample fits CAP
+    if (dp > 128 || (N + KB_N - 1) / KB_N <= 4 * KNN_WIN) return;
+    // coarsest stride 8^L: the fewest levels whose coarsest sample fits the
+    // filter output (every point of it passes the first filter)
     int L = 1;
     int64_t st = 8;
-    while ((N + st - 1) / st > CAP) {
+    while ((N + st - 1) / st > KNN_CAP) {
         st *= 8;
         ++L;
     }
