@@ -134,8 +134,12 @@ __device__ __forceinline__ double group16_sum(double v)
 }
 
 // One block per node.  Every wave works on 4 columns at a time, 16 lanes per
-// column, so each wave keeps 4 columns' loads in flight.
-template <int QT>
+// column, so each wave keeps 4 columns' loads in flight.  RM > 0 (rows <=
+// 16 RM): a lane keeps its slice of the column (rows t+1+l16, +16, ...) in
+// registers between the reflector's dot product and the update, so a pivot
+// step reads and writes every trailing element once; the operations and
+// their order are those of RM = 0 (slices re-read from memory).
+template <int QT, int RM>
 __global__ __launch_bounds__(QT) void k_qrcp(double *__restrict__ Gall, int ell, int ncol_max,
                                                const int32_t *__restrict__ ids,
                                                const int32_t *__restrict__ T_cnt,
@@ -229,12 +233,43 @@ __global__ __launch_bounds__(QT) void k_qrcp(double *__restrict__ Gall, int ell,
             const bool on = c < cols;
             double *gc = G + (int64_t)(on ? c : t) * ell;
             double s = 0.0;
+            double ns = 0.0;
+            if constexpr (RM > 0) {
+                double xr[RM];
+#pragma unroll
+                for (int j = 0; j < RM; ++j) {
+                    const int i = t + 1 + l16 + 16 * j;
+                    xr[j] = (on && i < rows) ? gc[i] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < RM; ++j) {
+                    const int i = t + 1 + l16 + 16 * j;
+                    if (on && i < rows) s += v[i] * xr[j];
+                }
+                s = group16_sum(s);
+                const double top = on ? gc[t] : 0.0;
+                const double f = beta * (s + top);
+#pragma unroll
+                for (int j = 0; j < RM; ++j) {
+                    const int i = t + 1 + l16 + 16 * j;
+                    if (on && i < rows) {
+                        double y = xr[j] - f * v[i];
+                        gc[i] = y;
+                        ns += y * y;
+                    }
+                }
+                ns = group16_sum(ns);
+                if (on && l16 == 0) {
+                    gc[t] = top - f;
+                    nrm2[c] = ns;
+                }
+                continue;
+            }
             if (on)
                 for (int i = t + 1 + l16; i < rows; i += 16) s += v[i] * gc[i];
             s = group16_sum(s);
             const double top = on ? gc[t] : 0.0;
             const double f = beta * (s + top);
-            double ns = 0.0;
             if (on)
                 for (int i = t + 1 + l16; i < rows; i += 16) {
                     double y = gc[i] - f * v[i];
@@ -458,8 +493,15 @@ void skeletonize(askit_handle *h, hipStream_t s)
             HIPC(hipEventRecord(q0, s));
             // 1024 threads per node: twice the columns in flight per pivot step
             // (the arithmetic per column is the same for any block size)
-            hipLaunchKernelGGL(k_qrcp<QR_T>, dim3((unsigned)nb), dim3(QR_T), 0, s, G, ell, ncm,
-                               d_ids, h->T_cnt, h->ncols, smax, h->prm.id_tol, h->colperm, h->skk, nb);
+            if (ell <= 16 * 8)
+                hipLaunchKernelGGL((k_qrcp<512, 8>), dim3((unsigned)nb), dim3(512), 0, s, G, ell, ncm, d_ids,
+                                   h->T_cnt, h->ncols, smax, h->prm.id_tol, h->colperm, h->skk, nb);
+            else if (ell <= 16 * 18)
+                hipLaunchKernelGGL((k_qrcp<512, 18>), dim3((unsigned)nb), dim3(512), 0, s, G, ell, ncm, d_ids,
+                                   h->T_cnt, h->ncols, smax, h->prm.id_tol, h->colperm, h->skk, nb);
+            else
+                hipLaunchKernelGGL((k_qrcp<QR_T, 0>), dim3((unsigned)nb), dim3(QR_T), 0, s, G, ell, ncm, d_ids,
+                                   h->T_cnt, h->ncols, smax, h->prm.id_tol, h->colperm, h->skk, nb);
             HIPC(hipEventRecord(q1, s));
             if (smax <= SR_L * SR_R)
                 hipLaunchKernelGGL(k_solve_reg, dim3((ncm + SR_C - 1) / SR_C, nb), dim3(256), 0, s, G, ell, ncm,
