@@ -155,7 +155,8 @@ typedef struct {
     int64_t knn_filter_launches;         /* ... and their number */
     int64_t eval_pairs;                  /* (target, source node) pairs of one evaluation */
     int64_t eval_chunks;                 /* evaluation work items (up to 64 targets of one source node) */
-    int64_t knn_retry_rows;              /* rows whose filter output overflowed (swept again with lists) */
+    int64_t knn_retry_rows;              /* rows whose filter output overflowed (filtered again at
+                                            sampled thresholds, then list sweeps if that overflows) */
 } askit_info;
 
 askit_status askit_get_info(const askit_handle *h, askit_info *out);
@@ -187,7 +188,9 @@ typedef enum {
     ASKIT_X_SLAB_NODE = 17,  /* int32[near_entries+far_entries]: node ids, near block first */
     ASKIT_X_SLAB_MASK = 18,  /* uint64[near_entries+far_entries]: row masks */
     ASKIT_X_SLAB_ROW0 = 19,  /* int32[num_slabs]: first tree position of each slab */
-    ASKIT_X_BANDWIDTH = 20   /* double[N]: per-source bandwidth, original order */
+    ASKIT_X_BANDWIDTH = 20,  /* double[N]: per-source bandwidth, original order */
+    ASKIT_X_KNN_RETRY = 21   /* int32[knn_retry_rows]: tree positions of the rows whose kNN
+                                filter output overflowed (any order) */
 } askit_export_item;
 
 /* Copies item `what` into host buffer `dst` of `cap` bytes; *bytes receives

@@ -24,6 +24,7 @@ ABI_VERSION = 1
 X_PERM, X_KNN_IDX, X_KNN_DIST, X_NODES, X_NLIST_POS, X_NLIST_KEY, X_NLIST_CNT = 1, 2, 3, 4, 5, 6, 7
 X_ROWS, X_ROWS_CNT, X_SKEL, X_SKEL_K, X_COLPERM, X_NCOLS, X_PROJ, X_SKEL_W = 8, 9, 10, 11, 12, 13, 14, 15
 X_SLAB_PTR, X_SLAB_NODE, X_SLAB_MASK, X_SLAB_ROW0, X_BANDWIDTH = 16, 17, 18, 19, 20
+X_KNN_RETRY = 21
 
 NODE_DTYPE = np.dtype([("lo", "<i4"), ("hi", "<i4"), ("level", "<i4"), ("parent", "<i4"),
                        ("left", "<i4"), ("right", "<i4"), ("path", "<i8")])
@@ -220,6 +221,7 @@ class Handle:
         out["slab_mask"] = self.export(X_SLAB_MASK, np.uint64)
         out["slab_row0"] = self.export(X_SLAB_ROW0, np.int32)
         out["hsrc"] = self.export(X_BANDWIDTH, np.float64)
+        out["knn_retry"] = self.export(X_KNN_RETRY, np.int32)
         if self.nrhs:
             out["Wsk"] = self.export(X_SKEL_W, np.float32).reshape(nn, smax, self.nrhs)
         return out

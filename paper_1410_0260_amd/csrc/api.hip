@@ -424,7 +424,8 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
         HIPC(hipEventRecord(k0, s));
         float fms = 0.f;
         knn_candidates(h->Xh, h->Xl, h->Xn, N, h->Xh, h->Xl, h->Xn, N, dp, true, true, cand, thr,
-                       bad + 1, bad, s, &fms, &h->knn_filter_launches, &h->knn_retry_rows, &h->ksamp);
+                       bad + 1, bad, s, &fms, &h->knn_filter_launches, &h->knn_retry_rows, &h->ksamp,
+                       &h->knn_retry_list);
         h->t_knn_filter = fms;
         HIPC(hipEventRecord(k1, s));
         float *tb;
@@ -656,6 +657,11 @@ askit_status askit_export(const askit_handle *h, int32_t what, void *dst, size_t
         host = true;
         break;
     case ASKIT_X_BANDWIDTH: src = h->hsrc; n = 8 * h->N; break;
+    case ASKIT_X_KNN_RETRY:
+        src = h->knn_retry_list.data();
+        n = 4 * h->knn_retry_list.size();
+        host = true;
+        break;
     default: fail(ASKIT_ERR_INVALID_ARG, "unknown export item");
     }
     if (bytes) *bytes = n;

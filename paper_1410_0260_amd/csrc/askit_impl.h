@@ -205,6 +205,7 @@ struct askit_handle {
     double t_knn = 0, t_tree = 0, t_lists = 0, t_skel = 0, t_inter = 0, t_update = 0;
     double t_knn_sweep = 0, t_qr = 0, t_knn_filter = 0;
     int knn_filter_launches = 0, knn_retry_rows = 0;
+    std::vector<int32_t> knn_retry_list;   // their tree positions
     hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr;
     bool up_pending = false;
 
@@ -233,7 +234,7 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
                     bool exclude_self, bool start_local, int32_t *cand, float *thr,
                     int32_t *bad_rows, int32_t *bad_count, hipStream_t s,
                     float *t_filter_ms = nullptr, int *n_filter = nullptr, int *n_retry = nullptr,
-                    const KnnSample *samp = nullptr);
+                    const KnnSample *samp = nullptr, std::vector<int32_t> *retry_rows = nullptr);
 // Fills h->ksamp from the tree-ordered bf16 points when the point set is large
 // enough for the sampled query search (allocations owned by the handle).
 void knn_build_sample(askit_handle *h, hipStream_t s);

@@ -1001,8 +1001,9 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
                     const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int dp,
                     bool exclude_self, bool start_local, int32_t *cand, float *thr,
                     int32_t *bad_rows, int32_t *bad_count, hipStream_t s, float *t_filter_ms,
-                    int *n_filter, int *n_retry, const KnnSample *samp)
+                    int *n_filter, int *n_retry, const KnnSample *samp, std::vector<int32_t> *retry_rows)
 {
+    if (retry_rows) retry_rows->clear();
     if (t_filter_ms) *t_filter_ms = 0.f;
     if (n_filter) *n_filter = 0;
     if (n_retry) *n_retry = 0;
@@ -1073,6 +1074,11 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
         if (n_filter) *n_filter = (int)(ev.size() / 2);
     }
     if (n_retry) *n_retry = nretry;
+    if (retry_rows && nretry > 0) {
+        retry_rows->resize(nretry);
+        HIPC(hipMemcpyAsync(retry_rows->data(), retry + 1, sizeof(int32_t) * nretry, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+    }
     // rows whose output overflowed (their window bound was far above their
     // 64th distance)
     const int32_t *list = retry + 1;

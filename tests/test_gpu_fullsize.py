@@ -53,19 +53,9 @@ def full():
     bpts = perm[nodes[beta]["lo"]:nodes[beta]["hi"]]
     spts = rng.choice(perm[nodes[sigma]["lo"]:nodes[sigma]["hi"]], 192, replace=False)
     rpts = rng.choice(N, 64, replace=False)
-    rows = np.unique(np.concatenate([bpts, spts, rpts])).astype(np.int64)
-    _log(f"[fullsize] oracle kNN of {len(rows)} points")
-    i1, d1 = O.knn(X[rows], X, p.kappa + 1, exclude_self=False)
-    kidx = np.empty((len(rows), p.kappa), np.int32)
-    kd = np.empty((len(rows), p.kappa))
-    for r, o in enumerate(rows):
-        keep = i1[r] != o
-        kidx[r], kd[r] = i1[r][keep][:p.kappa], d1[r][keep][:p.kappa]
-    Yq = synth.queries(wl, 256, 77)
-    _log(f"[fullsize] oracle kNN of {len(Yq)} new points")
-    qidx_o, qd_o = O.knn(Yq, X, p.kappa, exclude_self=False)
     Wb = np.zeros((N, 1), np.float32)
     Wb[bpts, 0] = synth.weights(len(bpts), 1, 31)[:, 0]
+    Yq = synth.queries(wl, 256, 77)
 
     _log("[fullsize] HIP setup + update + evaluate")
     h = A.setup(torch.from_numpy(X).cuda(), A.params_from_workload(wl))
@@ -76,8 +66,22 @@ def full():
     qi, qd = h.query_neighbors(torch.from_numpy(Yq).cuda())
     g["qidx"], g["qd"] = qi.cpu().numpy(), qd.cpu().numpy()
     h.close()
+    # rows whose filter output overflowed (the re-filtered path): up to 64 of them
+    retry_pos = g["knn_retry"]
+    pick = rng.choice(len(retry_pos), min(64, len(retry_pos)), replace=False) if len(retry_pos) else []
+    retry_ids = g["perm"][retry_pos[pick]].astype(np.int64) if len(retry_pos) else np.zeros(0, np.int64)
+    rows = np.unique(np.concatenate([bpts, spts, rpts, retry_ids])).astype(np.int64)
+    _log(f"[fullsize] oracle kNN of {len(rows)} points ({len(retry_ids)} of {len(retry_pos)} retried rows)")
+    i1, d1 = O.knn(X[rows], X, p.kappa + 1, exclude_self=False)
+    kidx = np.empty((len(rows), p.kappa), np.int32)
+    kd = np.empty((len(rows), p.kappa))
+    for r, o in enumerate(rows):
+        keep = i1[r] != o
+        kidx[r], kd[r] = i1[r][keep][:p.kappa], d1[r][keep][:p.kappa]
+    _log(f"[fullsize] oracle kNN of {len(Yq)} new points")
+    qidx_o, qd_o = O.knn(Yq, X, p.kappa, exclude_self=False)
     return dict(wl=wl, p=p, X=X, N=N, nodes=nodes, perm=perm, iperm=iperm, beta=beta, sigma=sigma,
-                rows=rows, kidx=kidx, kd=kd, Wb=Wb, U=U, g=g, qidx=qidx_o, qd=qd_o)
+                rows=rows, kidx=kidx, kd=kd, Wb=Wb, U=U, g=g, qidx=qidx_o, qd=qd_o, retry_ids=retry_ids)
 
 
 def test_tree_full(full):
@@ -91,6 +95,13 @@ def test_knn_sampled(full):
     g, rows = full["g"], full["rows"]
     assert np.array_equal(g["knn_idx"][rows], full["kidx"])
     assert np.array_equal(g["knn_d"][rows], full["kd"])
+
+
+def test_knn_retried_rows_covered(full):
+    """At this size some rows' window bound lets more than the filter's
+    capacity through; the sampled rows above include up to 64 of them."""
+    assert full["g"]["info"]["knn_retry_rows"] == len(full["g"]["knn_retry"]) > 0
+    assert np.isin(full["retry_ids"], full["rows"]).all() and len(full["retry_ids"]) > 0
 
 
 def test_query_knn(full):

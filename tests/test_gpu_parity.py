@@ -56,7 +56,8 @@ def case(request):
 
 def test_knn_bit_exact(case):
     name, X, W, p, st, g = case
-    print(f"[knn] {name}: rows not certified by the approximate pass: {g['info']['knn_uncertified_rows']}",
+    print(f"[knn] {name}: rows not certified by the approximate pass: {g['info']['knn_uncertified_rows']}, "
+          f"rows retried after a filter overflow: {g['info']['knn_retry_rows']}",
           flush=True)
     if name == "wide-fallback":
         assert g["info"]["knn_uncertified_rows"] > 0      # the fallback is exercised
