@@ -1153,11 +1153,20 @@ void knn_build_sample(askit_handle *h, hipStream_t s)
         ++L;
     }
     if (L > KnnSample::MAXL) return;
+    // one allocation for every level (rows of 2 dp bf16 values and one float)
+    int64_t total = 0;
+    for (int64_t t = st; t >= 8; t /= 8) total += (N + t - 1) / t;
+    char *base = (char *)h->alloc((size_t)total * (4 * dp + 4) + 256 * 3 * L, false);
+    auto take = [&](size_t b) {
+        char *p = base;
+        base += (b + 255) / 256 * 256;
+        return p;
+    };
     for (int lv = 0; lv < L; ++lv, st /= 8) {
         const int64_t rows = (N + st - 1) / st;              // positions st * r < N
-        h->ksamp.h[lv] = (uint16_t *)h->alloc(sizeof(uint16_t) * rows * dp, false);
-        h->ksamp.l[lv] = (uint16_t *)h->alloc(sizeof(uint16_t) * rows * dp, false);
-        h->ksamp.n[lv] = (float *)h->alloc(sizeof(float) * rows, false);
+        h->ksamp.h[lv] = (uint16_t *)take(sizeof(uint16_t) * rows * dp);
+        h->ksamp.l[lv] = (uint16_t *)take(sizeof(uint16_t) * rows * dp);
+        h->ksamp.n[lv] = (float *)take(sizeof(float) * rows);
         h->ksamp.rows[lv] = rows;
         const int64_t nthr = rows * (dp / 8);
         hipLaunchKernelGGL(k_stride_rows, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, h->Xh, h->Xl,
