@@ -766,6 +766,24 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
 // Per row (one wave): the 64 smallest (approximate distance, position) of the
 // filter's output, as candidates + the certificate threshold.  Rows whose
 // segment overflowed are listed for the retry sweep (when bad_count is given).
+// The 64th smallest distance is found by a radix selection on an
+// order-preserving image of the FP32 values (four 8-bit digits, a histogram
+// per wave in LDS); the candidates are every stored entry below it and, among
+// those equal to it, the ones with the smallest positions.  Candidates are
+// written in no particular order (the certificate re-sorts them exactly).
+constexpr int SEL_Q = 16;                  // stored entries per lane (cap <= 1024)
+
+__device__ __forceinline__ uint32_t f2key(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float key2f(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
 __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int cap,
                                                     const int32_t *__restrict__ ocnt,
                                                     const float *__restrict__ od,
@@ -775,32 +793,128 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
                                                     int32_t *__restrict__ bad_rows,
                                                     int32_t *__restrict__ bad_count)
 {
-    int64_t lrow = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
-    int lane = threadIdx.x % WAVE;
+    __shared__ int hist[4][256];
+    const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    int64_t lrow = (int64_t)blockIdx.x * 4 + wv;
     if (lrow >= M) return;
     const int64_t row = row0 + lrow;
     const int n = ocnt[lrow];
     const float tin = thr[row];          // the filter threshold: every point left out is above it
-    float ld = INFINITY;
-    int li = 0x7fffffff;
     if (n > cap && lane == 0 && bad_count) {
         int p = atomicAdd(bad_count, 1);
         bad_rows[p] = (int32_t)row;
     }
     const int nk = min(n, cap);
-    for (int c0 = 0; c0 < nk; c0 += 64) {
-        ListEntry e = merge_list(ld, li, od + lrow * cap + c0, oi + lrow * cap + c0, min(64, nk - c0), lane);
-        ld = e.d;
-        li = e.i;
+    const float *rd = od + lrow * cap;
+    const int32_t *ri = oi + lrow * cap;
+    int32_t *co = cand + row * KNN_CAND;
+    if (nk <= KNN_CAND) {
+        // every stored entry is a candidate
+        co[lane] = lane < nk ? ri[lane] : -1;
+        float m = -INFINITY;
+        if (nk == KNN_CAND) {
+            m = lane < nk ? rd[lane] : -INFINITY;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        }
+        if (lane == 0) thr[row] = n > cap ? m + fabsf(m) * 1e-5f + 1e-30f : (n >= KNN_CAND ? m : tin);
+        return;
     }
-    cand[row * KNN_CAND + lane] = li == 0x7fffffff ? -1 : li;
-    // bound for the points outside the candidates: the 64th survivor, or the
-    // filter threshold when fewer than 64 points survived.  A row whose
-    // segment overflowed is swept again; the 64th of its stored survivors
-    // (real distances, so at least its 64th smallest), widened as the window
-    // threshold, starts that sweep.
-    float th = __shfl(ld, 63);
-    if (lane == 0) thr[row] = n > cap ? th + fabsf(th) * 1e-5f + 1e-30f : (n >= 64 ? th : tin);
+    uint32_t key[SEL_Q];
+#pragma unroll
+    for (int q = 0; q < SEL_Q; ++q) {
+        const int e = lane + WAVE * q;
+        key[q] = e < nk ? f2key(rd[e]) : 0xffffffffu;
+    }
+    // the KNN_CAND-th smallest key, one 8-bit digit at a time
+    uint32_t prefix = 0, pmask = 0;
+    int kk = KNN_CAND;                   // rank sought among the keys matching prefix
+    int *hw = hist[wv];
+#pragma unroll 1
+    for (int shift = 24; shift >= 0; shift -= 8) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) hw[lane * 4 + u] = 0;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < SEL_Q; ++q)
+            if ((key[q] & pmask) == prefix) atomicAdd(&hw[(key[q] >> shift) & 255u], 1);
+        __builtin_amdgcn_wave_barrier();
+        int c[4], c4 = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = hw[lane * 4 + u];
+            c4 += c[u];
+        }
+        int inc = c4;                    // inclusive scan over lanes (bins in order)
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const int y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        const int ex = inc - c4;
+        const uint64_t hit = __ballot(ex < kk && inc >= kk);
+        const int L = __ffsll((long long)hit) - 1;
+        int bin = 0, below = ex;
+        if (lane == L) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (below + c[u] >= kk) { bin = lane * 4 + u; break; }
+                below += c[u];
+            }
+        }
+        bin = __shfl(bin, L);
+        below = __shfl(below, L);
+        kk -= below;
+        prefix |= (uint32_t)bin << shift;
+        pmask |= 255u << shift;
+        __builtin_amdgcn_wave_barrier();
+    }
+    const uint32_t K = prefix;           // kk of the keys equal to K complete the 64
+    // entries below K (64 - kk of them), then the kk equal ones with the smallest positions
+    int base = 0;
+#pragma unroll
+    for (int q = 0; q < SEL_Q; ++q) {
+        const bool pr = key[q] < K;
+        const uint64_t bm = __ballot(pr);
+        if (pr) co[base + __popcll(bm & ((1ull << lane) - 1ull))] = ri[lane + WAVE * q];
+        base += __popcll(bm);
+    }
+    int neq = 0;
+#pragma unroll
+    for (int q = 0; q < SEL_Q; ++q) neq += __popcll(__ballot(key[q] == K));
+    if (neq == kk) {
+#pragma unroll
+        for (int q = 0; q < SEL_Q; ++q) {
+            const bool pr = key[q] == K;
+            const uint64_t bm = __ballot(pr);
+            if (pr) co[base + __popcll(bm & ((1ull << lane) - 1ull))] = ri[lane + WAVE * q];
+            base += __popcll(bm);
+        }
+    } else {
+        // ties at the 64th distance: the kk smallest positions among them
+        int last = -1;
+        for (int take = 0; take < kk; ++take) {
+            int mi = 0x7fffffff;
+#pragma unroll
+            for (int q = 0; q < SEL_Q; ++q) {
+                const int e = lane + WAVE * q;
+                if (key[q] == K && e < nk) {
+                    const int p = ri[e];
+                    if (p > last && p < mi) mi = p;
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) mi = min(mi, __shfl_xor(mi, o));
+            if (lane == 0) co[base + take] = mi;
+            last = mi;
+        }
+    }
+    // bound for the points outside the candidates: the 64th survivor.  A row
+    // whose segment overflowed is swept again; the 64th of its stored
+    // survivors (real distances, so at least its 64th smallest), widened as
+    // the window threshold, starts that sweep.
+    const float th = key2f(K);
+    if (lane == 0) thr[row] = n > cap ? th + fabsf(th) * 1e-5f + 1e-30f : th;
 }
 
 template <int KS>

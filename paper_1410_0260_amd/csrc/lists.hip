@@ -339,55 +339,75 @@ __device__ __forceinline__ bool has_nb(const int32_t *nb, int n, int lo, int hi)
     return a < n && nb[a] < hi;
 }
 
-// mode 0: count entries per slab; mode 1: write them.
-__global__ __launch_bounds__(64) void k_interactions(const Node *__restrict__ nodes, int nn,
-                                                     const int32_t *__restrict__ leaf_of,
-                                                     const Slab *__restrict__ slabs,
-                                                     const int32_t *__restrict__ nbpos, int nnb,
-                                                     int mode, int32_t *__restrict__ cnt_near,
-                                                     int32_t *__restrict__ cnt_far,
-                                                     const int32_t *__restrict__ ptr, int64_t nslab,
-                                                     int32_t *__restrict__ out_node,
-                                                     uint64_t *__restrict__ out_mask)
+// mode 0: count entries per slab; mode 1: write them.  NW waves per slab:
+// wave 0 builds the rows' sorted neighbour lists and marks A (the union of
+// their ancestors); the node scan is split in NW contiguous word ranges (so
+// the output keeps node order), with the per-wave entry counts of mode 0
+// (cntw, prefix within the slab) placing each wave's entries in mode 1.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_interactions(const Node *__restrict__ nodes, int nn,
+                                                          const int32_t *__restrict__ leaf_of,
+                                                          const Slab *__restrict__ slabs,
+                                                          const int32_t *__restrict__ nbpos, int nnb,
+                                                          int mode, int32_t *__restrict__ cnt_near,
+                                                          int32_t *__restrict__ cnt_far,
+                                                          const int32_t *__restrict__ ptr, int64_t nslab,
+                                                          int32_t *__restrict__ out_node,
+                                                          uint64_t *__restrict__ out_mask,
+                                                          int32_t *__restrict__ cntw)
 {
     extern __shared__ uint32_t sh[];
+    __shared__ int nm[64];
+    __shared__ int wcnt[2 * NW];
     const int nwords = (nn + 31) / 32;
     uint32_t *U = sh;
     int32_t *nbs = reinterpret_cast<int32_t *>(sh + nwords);
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t sl = blockIdx.x;
     const Slab sb = slabs[sl];
     const bool valid = lane < sb.nrows;
-    for (int w = lane; w < nwords; w += 64) U[w] = 0;
+    for (int w = threadIdx.x; w < nwords; w += 64 * NW) U[w] = 0;
     int32_t *mine = nbs + lane * nnb;
-    int nmine = 0;
-    if (valid) {
-        const int32_t *src = nbpos + ((int64_t)sb.row0 + lane) * nnb;
-        for (int t = 0; t < nnb; ++t) {
-            int32_t v = src[t];
-            if (v < 0) continue;
-            int q = nmine++;
-            while (q > 0 && mine[q - 1] > v) {
-                mine[q] = mine[q - 1];
-                --q;
+    if (wv == 0) {
+        int nmine = 0;
+        if (valid) {
+            const int32_t *src = nbpos + ((int64_t)sb.row0 + lane) * nnb;
+            for (int t = 0; t < nnb; ++t) {
+                int32_t v = src[t];
+                if (v < 0) continue;
+                int q = nmine++;
+                while (q > 0 && mine[q - 1] > v) {
+                    mine[q] = mine[q - 1];
+                    --q;
+                }
+                mine[q] = v;
             }
-            mine[q] = v;
+        }
+        nm[lane] = nmine;
+    }
+    __syncthreads();
+    const int nmine = nm[lane];
+    if (wv == 0) {
+        for (int t = 0; t < nmine; ++t) {
+            int a = leaf_of[mine[t]];
+            while (a >= 0) {
+                uint32_t bit = 1u << (a & 31);
+                uint32_t old = atomicOr(&U[a >> 5], bit);
+                if (old & bit) break;
+                a = nodes[a].parent;
+            }
         }
     }
     __syncthreads();
-    for (int t = 0; t < nmine; ++t) {
-        int a = leaf_of[mine[t]];
-        while (a >= 0) {
-            uint32_t bit = 1u << (a & 31);
-            uint32_t old = atomicOr(&U[a >> 5], bit);
-            if (old & bit) break;
-            a = nodes[a].parent;
-        }
-    }
-    __syncthreads();
+    const int per = (nwords + NW - 1) / NW;
+    const int w0 = min(nwords, wv * per), w1 = min(nwords, w0 + per);
     int kn = 0, kf = 0;
-    int64_t on = mode ? ptr[sl] : 0, of = mode ? ptr[nslab + 1 + sl] : 0;
-    for (int w = 0; w < nwords; ++w) {
+    int64_t on = 0, of = 0;
+    if (mode) {
+        on = ptr[sl] + (NW > 1 ? cntw[(sl * NW + wv) * 2] : 0);
+        of = ptr[nslab + 1 + sl] + (NW > 1 ? cntw[(sl * NW + wv) * 2 + 1] : 0);
+    }
+    for (int w = w0; w < w1; ++w) {
         uint32_t bits = U[w];
         while (bits) {
             int b = __builtin_ctz(bits);
@@ -421,9 +441,25 @@ __global__ __launch_bounds__(64) void k_interactions(const Node *__restrict__ no
             }
         }
     }
-    if (!mode && lane == 0) {
-        cnt_near[sl] = kn;
-        cnt_far[sl] = kf;
+    if (!mode) {
+        if (lane == 0) {
+            wcnt[wv] = kn;
+            wcnt[NW + wv] = kf;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int an = 0, af = 0;
+            for (int u = 0; u < NW; ++u) {
+                if (NW > 1) {
+                    cntw[(sl * NW + u) * 2] = an;
+                    cntw[(sl * NW + u) * 2 + 1] = af;
+                }
+                an += wcnt[u];
+                af += wcnt[NW + u];
+            }
+            cnt_near[sl] = an;
+            cnt_far[sl] = af;
+        }
     }
 }
 
@@ -461,16 +497,24 @@ static void run_interactions(askit_handle *h, const Slab *d_slabs, int64_t nslab
 {
     int nn = (int)h->nodes.size();
     size_t shb = sizeof(uint32_t) * ((nn + 31) / 32) + sizeof(int32_t) * 64 * nnb;
-    if (shb > 160 * 1024) fail(ASKIT_ERR_UNSUPPORTED, "tree too large for the interaction kernel");
-    if (shb > 64 * 1024)
-        HIPC(hipFuncSetAttribute((const void *)k_interactions,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb));
-    int32_t *cnt;
+    if (shb > 150 * 1024) fail(ASKIT_ERR_UNSUPPORTED, "tree too large for the interaction kernel");
+    // few slabs (a batch of new points): four waves share each slab's node scan
+    const bool wide = nslab < 2048;
+    const void *kfn = wide ? (const void *)k_interactions<4> : (const void *)k_interactions<1>;
+    if (shb > 64 * 1024) HIPC(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb));
+    int32_t *cnt, *cntw = nullptr;
     HIPC(hipMallocAsync((void **)&cnt, sizeof(int32_t) * 2 * (nslab + 1), s));
-    hipLaunchKernelGGL(k_interactions, dim3((unsigned)nslab), dim3(64), shb, s, h->d_nodes, nn,
-                       h->leaf_of, d_slabs, nbpos, nnb, 0, cnt, cnt + nslab + 1,
-                       (const int32_t *)nullptr, nslab, (int32_t *)nullptr, (uint64_t *)nullptr);
-    HIPC(hipGetLastError());
+    if (wide) HIPC(hipMallocAsync((void **)&cntw, sizeof(int32_t) * 2 * 4 * std::max<int64_t>(nslab, 1), s));
+    auto launch = [&](int mode, int32_t *cn, int32_t *cf, const int32_t *pp, int32_t *on, uint64_t *om) {
+        if (wide)
+            hipLaunchKernelGGL(k_interactions<4>, dim3((unsigned)nslab), dim3(256), shb, s, h->d_nodes, nn,
+                               h->leaf_of, d_slabs, nbpos, nnb, mode, cn, cf, pp, nslab, on, om, cntw);
+        else
+            hipLaunchKernelGGL(k_interactions<1>, dim3((unsigned)nslab), dim3(64), shb, s, h->d_nodes, nn,
+                               h->leaf_of, d_slabs, nbpos, nnb, mode, cn, cf, pp, nslab, on, om, cntw);
+        HIPC(hipGetLastError());
+    };
+    launch(0, cnt, cnt + nslab + 1, nullptr, nullptr, nullptr);
     std::vector<int32_t> hc(2 * (nslab + 1));
     HIPC(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * 2 * (nslab + 1), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
@@ -502,11 +546,9 @@ static void run_interactions(askit_handle *h, const Slab *d_slabs, int64_t nslab
     node = (int32_t *)al(sizeof(int32_t) * std::max<int64_t>(acc, 1));
     mask = (uint64_t *)al(sizeof(uint64_t) * std::max<int64_t>(acc, 1));
     HIPC(hipMemcpyAsync(ptr, hp.data(), sizeof(int32_t) * hp.size(), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_interactions, dim3((unsigned)nslab), dim3(64), shb, s, h->d_nodes, nn,
-                       h->leaf_of, d_slabs, nbpos, nnb, 1, (int32_t *)nullptr, (int32_t *)nullptr,
-                       ptr, nslab, node, mask);
-    HIPC(hipGetLastError());
+    launch(1, nullptr, nullptr, ptr, node, mask);
     HIPC(hipFreeAsync(cnt, s));
+    if (cntw) HIPC(hipFreeAsync(cntw, s));
 }
 
 void build_interactions(askit_handle *h, hipStream_t s)
