@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 namespace askit {
 
@@ -289,6 +290,273 @@ __global__ __launch_bounds__(QT) void k_qrcp(double *__restrict__ Gall, int ell,
   }
 }
 
+// ---------------------------------------------------------------- gang QRCP
+// The same factorization with the node's columns held in registers across a
+// gang of W workgroups (co-resident by a cooperative launch): column c
+// belongs to workgroup c % W, whose 16-lane group (c / W) % 32 keeps it in
+// slot (c / W) / 32, lane l16 holding rows l16 + 16 r.  Per pivot step each
+// workgroup publishes, in device memory, its best column (largest residual
+// norm, ties to the lowest current position) with that column's rows t..,
+// and then a sequence number.  Every workgroup waits for the W sequence
+// numbers of the step, reads the W candidates, takes the best one as the
+// pivot, computes the same reflector from its rows and applies it to its
+// own columns.  Column swaps are bookkeeping only: every workgroup keeps
+// the same position <-> column maps.  At the end each column is written to
+// G at its final position, so the solve and finalize kernels read the same
+// layout as after k_qrcp.  Exchanged values are written and read with
+// device-coherent (agent-scope) atomic accesses; a wait lasts at most
+// `timeout` ticks of the constant-rate clock, past which the kernel sets
+// *err and every workgroup returns.  Candidates are double-buffered by step
+// parity: a workgroup overwrites a buffer only after every workgroup has
+// published the step that followed its use.
+constexpr int QG_T = 512;
+constexpr double QG_TIMEOUT_S = 10.0;                // wait limit
+
+struct GangSlot {
+    double v;
+    int32_t pos, col;
+    int32_t seq, pad;
+};
+
+__device__ __forceinline__ bool qg_better(double v1, int p1, double v2, int p2)
+{
+    return v1 > v2 || (v1 == v2 && p1 < p2);
+}
+
+template <int W, int RM, int CPG>
+__global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, int ell, int ncol_max,
+                                                     const int32_t *__restrict__ ids,
+                                                     const int32_t *__restrict__ T_cnt,
+                                                     const int32_t *__restrict__ ncols, int smax, double tau,
+                                                     int32_t *__restrict__ colperm, int32_t *__restrict__ kout,
+                                                     int nb, GangSlot *__restrict__ slots,
+                                                     double *__restrict__ sdata, int32_t *__restrict__ err,
+                                                     uint64_t timeout)
+{
+    constexpr int RMAX = 16 * RM;
+    __shared__ int piv[QR_MAXCOL];            // position -> column
+    __shared__ int posof[QR_MAXCOL];          // column -> position
+    __shared__ double cd[W][RMAX];            // the W candidates' rows
+    __shared__ double cv[W];
+    __shared__ int cp[W], cc[W];
+    __shared__ double rdv[QG_T / 64];
+    __shared__ int rdp[QG_T / 64], rdc[QG_T / 64];
+    __shared__ int s_lb, s_fail;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int grp = tid >> 4, l16 = tid & 15;
+    const int gang = blockIdx.x / W, w = blockIdx.x % W, ngang = gridDim.x / W;
+    int32_t gs = 0;                           // steps published by this gang
+    if (tid == 0) s_fail = 0;
+    for (int q = gang; q < nb; q += ngang) {
+        __syncthreads();
+        const int a = ids[q];
+        const int rows = T_cnt[a], cols = ncols[a];
+        double *G = Gall + (int64_t)q * ncol_max * ell;
+        for (int c = tid; c < cols; c += QG_T) {
+            piv[c] = c;
+            posof[c] = c;
+        }
+        double x[CPG][RM];
+        double nv[CPG];
+        bool act[CPG];
+#pragma unroll
+        for (int j = 0; j < CPG; ++j) {
+            const int c = w + W * (grp + 32 * j);
+            act[j] = c < cols;
+            double sq = 0.0;
+#pragma unroll
+            for (int r = 0; r < RM; ++r) {
+                const int i = l16 + 16 * r;
+                x[j][r] = (act[j] && i < rows) ? G[(int64_t)c * ell + i] : 0.0;
+                if (i < rows) sq += x[j][r] * x[j][r];
+            }
+            nv[j] = group16_sum(sq);
+        }
+        __syncthreads();
+        const double teff = tau > TAU_FLOOR ? tau : TAU_FLOOR;
+        const int kcap = min(smax, min(rows, cols));
+        int k = kcap;
+        double nrm0 = 0.0;
+        for (int t = 0; t < kcap; ++t) {
+            // this workgroup's best active column
+            double bv = -1.0;
+            int bp = 0x7fffffff, bc = -1;
+#pragma unroll
+            for (int j = 0; j < CPG; ++j) {
+                if (!act[j]) continue;
+                const int c = w + W * (grp + 32 * j);
+                const int pc = posof[c];
+                if (qg_better(nv[j], pc, bv, bp)) { bv = nv[j]; bp = pc; bc = c; }
+            }
+#pragma unroll
+            for (int o = 32; o >= 16; o >>= 1) {
+                const double ov = __shfl_xor(bv, o);
+                const int op = __shfl_xor(bp, o), oc = __shfl_xor(bc, o);
+                if (qg_better(ov, op, bv, bp)) { bv = ov; bp = op; bc = oc; }
+            }
+            if (lane == 0) { rdv[wv] = bv; rdp[wv] = bp; rdc[wv] = bc; }
+            __syncthreads();
+            ++gs;
+            const int par = gs & 1;
+            GangSlot *sl = slots + ((int64_t)gang * 2 + par) * W;
+            double *sd = sdata + ((int64_t)gang * 2 + par) * W * ell;
+            if (tid == 0) {
+                for (int u = 1; u < QG_T / 64; ++u)
+                    if (qg_better(rdv[u], rdp[u], bv, bp)) { bv = rdv[u]; bp = rdp[u]; bc = rdc[u]; }
+                __hip_atomic_store(&sl[w].v, bv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&sl[w].pos, bp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&sl[w].col, bc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_lb = bc;
+            }
+            __syncthreads();
+            {
+                const int lbc = s_lb;
+                if (lbc >= 0 && grp == (lbc / W) % 32) {
+                    const int jb = (lbc / W) / 32;
+                    double *dst = sd + (int64_t)w * ell;
+#pragma unroll
+                    for (int j = 0; j < CPG; ++j) {
+                        if (j != jb) continue;
+#pragma unroll
+                        for (int r = 0; r < RM; ++r) {
+                            const int i = l16 + 16 * r;
+                            if (i >= t && i < rows)
+                                __hip_atomic_store(&dst[i], x[j][r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                }
+            }
+            // every wave waits until its stores have completed (a block barrier
+            // alone only orders them for this workgroup); then the sequence number
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            if (tid == 0) __hip_atomic_store(&sl[w].seq, gs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // wait for the W candidates of this step
+            if (tid < W) {
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(&sl[tid].seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gs) {
+                    if (wall_clock64() - t0 > timeout) {
+                        atomicExch(err, 1);
+                        s_fail = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            __syncthreads();
+            if (s_fail) return;
+            // the headers and every candidate's rows t.. in one round of loads
+            // (a workgroup without a candidate left stale rows: not used)
+            if (tid < W) {
+                cv[tid] = __hip_atomic_load(&sl[tid].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                cp[tid] = __hip_atomic_load(&sl[tid].pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                cc[tid] = __hip_atomic_load(&sl[tid].col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            for (int e = tid; e < W * (rows - t); e += QG_T) {
+                const int u = e / (rows - t), i = t + e % (rows - t);
+                cd[u][i] = __hip_atomic_load(&sd[(int64_t)u * ell + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+            double gv = -1.0;
+            int gp = 0x7fffffff, pc = -1, pw = 0;
+#pragma unroll
+            for (int u = 0; u < W; ++u)
+                if (cc[u] >= 0 && qg_better(cv[u], cp[u], gv, gp)) { gv = cv[u]; gp = cp[u]; pc = cc[u]; pw = u; }
+            if (pc < 0) { k = t; break; }              // no active column with a finite norm
+            const double nrm = sqrt(gv);
+            if (t == 0) {
+                nrm0 = nrm;
+                if (!(nrm0 > 0.0)) { k = 0; break; }
+            } else if (nrm <= teff * nrm0) {
+                k = t;
+                break;
+            }
+            // swap positions t and posof[pc]
+            if (tid == 0) {
+                const int ct = piv[t], pp = posof[pc];
+                piv[t] = pc;
+                piv[pp] = ct;
+                posof[ct] = pp;
+                posof[pc] = t;
+            }
+            __syncthreads();
+            // the reflector, computed alike in every workgroup
+            const double *vs = cd[pw];
+            const double x0 = vs[t];
+            const double rtt = x0 >= 0.0 ? -nrm : nrm;
+            const double denom = x0 - rtt;
+            const double beta = (rtt - x0) / rtt;
+            const int rt = t / 16, lt = t % 16;
+            if (pw == w && grp == (pc / W) % 32) {
+                const int jp = (pc / W) / 32;
+#pragma unroll
+                for (int j = 0; j < CPG; ++j) {
+                    if (j != jp) continue;
+#pragma unroll
+                    for (int r = 0; r < RM; ++r) {
+                        const int i = l16 + 16 * r;
+                        if (i > t && i < rows) x[j][r] = 0.0;
+                        else if (i == t) x[j][r] = rtt;
+                    }
+                    act[j] = false;
+                }
+            }
+            double vr[RM];
+#pragma unroll
+            for (int r = 0; r < RM; ++r) {
+                const int i = l16 + 16 * r;
+                vr[r] = (i > t && i < rows) ? vs[i] / denom : 0.0;
+            }
+            const int src = (lane & ~15) | lt;
+#pragma unroll
+            for (int j = 0; j < CPG; ++j) {
+                if (!act[j]) continue;                 // group-uniform
+                double sdot = 0.0, top = 0.0;
+#pragma unroll
+                for (int r = 0; r < RM; ++r) {
+                    const int i = l16 + 16 * r;
+                    if (i > t && i < rows) sdot += vr[r] * x[j][r];
+                    if (r == rt) top = x[j][r];
+                }
+                sdot = group16_sum(sdot);
+                top = __shfl(top, src);
+                const double f = beta * (sdot + top);
+                double ns = 0.0;
+#pragma unroll
+                for (int r = 0; r < RM; ++r) {
+                    const int i = l16 + 16 * r;
+                    if (i > t && i < rows) {
+                        const double y = x[j][r] - f * vr[r];
+                        x[j][r] = y;
+                        ns += y * y;
+                    } else if (i == t) {
+                        x[j][r] = top - f;
+                    }
+                }
+                nv[j] = group16_sum(ns);
+            }
+        }
+        // every column to its final position
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CPG; ++j) {
+            const int c = w + W * (grp + 32 * j);
+            if (c < cols) {
+                const int pos = posof[c];
+#pragma unroll
+                for (int r = 0; r < RM; ++r) {
+                    const int i = l16 + 16 * r;
+                    if (i < rows) G[(int64_t)pos * ell + i] = x[j][r];
+                }
+            }
+        }
+        if (w == 0) {
+            for (int c = tid; c < cols; c += QG_T) colperm[(int64_t)a * ncol_max + c] = piv[c];
+            if (tid == 0) kout[a] = k;
+        }
+    }
+}
+
 // P = R11^{-1} R12 in place over R12 (FP64).  Block per (node, chunk of SV_C
 // columns of R12): the chunk is held in LDS and solved right-looking: for
 // t = k-1 .. 0, P[t] = R12'[t] / R_tt, then R12'[u] -= R_ut P[t] for u < t.
@@ -422,6 +690,55 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ Gal
     }
 }
 
+// Scratch of the gang factorization: per gang two rounds of W candidate
+// slots and candidate columns (ell rows each); one error flag.
+constexpr int QG_GMAX = 256;
+struct GangScratch {
+    GangSlot *slots = nullptr;
+    double *sdata = nullptr;
+    int32_t *err = nullptr;
+};
+
+__global__ void k_gang_reset(GangSlot *__restrict__ slots, int n, int32_t *__restrict__ err)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        slots[i].seq = 0;
+        slots[i].col = -1;
+    }
+    if (i == 0) *err = 0;
+}
+
+// Gang launches are serialized across host threads: each needs all of its
+// workgroups resident at once, which a cooperative launch guarantees for
+// one kernel at a time.
+static std::mutex g_gang_mu;
+
+template <int W, int RM, int CPG>
+static bool qr_gang_launch(double *G, int ell, int ncm, const int32_t *ids, const int32_t *T_cnt,
+                           const int32_t *ncols, int smax, double tau, int32_t *colperm, int32_t *kout, int nb,
+                           const GangScratch &gs, uint64_t timeout, hipStream_t s)
+{
+    int dev = 0, ncu = 0, per = 0;
+    HIPC(hipGetDevice(&dev));
+    HIPC(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_qrcp_gang<W, RM, CPG>, QG_T, 0));
+    const int ngang = std::min(nb, std::min(QG_GMAX, per * ncu / W));
+    if (ngang < 1) return false;
+    const int nslot = ngang * 2 * W;
+    hipLaunchKernelGGL(k_gang_reset, dim3((unsigned)((nslot + 255) / 256)), dim3(256), 0, s, gs.slots, nslot,
+                       gs.err);
+    HIPC(hipGetLastError());
+    GangSlot *slots = gs.slots;
+    double *sdata = gs.sdata;
+    int32_t *err = gs.err;
+    void *args[] = {&G, &ell, &ncm, (void *)&ids, (void *)&T_cnt, (void *)&ncols, &smax, &tau, &colperm,
+                    &kout, &nb, &slots, &sdata, &err, &timeout};
+    HIPC(hipLaunchCooperativeKernel((const void *)k_qrcp_gang<W, RM, CPG>, dim3((unsigned)(ngang * W)),
+                                    dim3(QG_T), args, 0, s));
+    return true;
+}
+
 void skeletonize(askit_handle *h, hipStream_t s)
 {
     const int nn = (int)h->nodes.size();
@@ -461,6 +778,23 @@ void skeletonize(askit_handle *h, hipStream_t s)
         HIPC(hipFuncSetAttribute((const void *)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)sv_lds));
     std::vector<int32_t> ids;
+    // gang factorization: needs cooperative launches, at most 512 columns
+    // (the registers of 4 x 32 x 4 slots) and 288 rows (18 per lane)
+    int coop = 0, clk_khz = 0;
+    {
+        int dev = 0;
+        HIPC(hipGetDevice(&dev));
+        HIPC(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        HIPC(hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev));
+    }
+    const bool use_gang = coop && clk_khz > 0 && ncm <= 512 && ell <= 16 * 18;
+    const uint64_t g_timeout = (uint64_t)((double)clk_khz * 1000.0 * QG_TIMEOUT_S);
+    GangScratch gsc;
+    if (use_gang) {
+        HIPC(hipMallocAsync((void **)&gsc.slots, sizeof(GangSlot) * QG_GMAX * 2 * 8, s));
+        HIPC(hipMallocAsync((void **)&gsc.sdata, sizeof(double) * QG_GMAX * 2 * 8 * ell, s));
+        HIPC(hipMallocAsync((void **)&gsc.err, sizeof(int32_t), s));
+    }
     hipEvent_t q0, q1;
     HIPC(hipEventCreate(&q0));
     HIPC(hipEventCreate(&q1));
@@ -491,9 +825,28 @@ void skeletonize(askit_handle *h, hipStream_t s)
                                        h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
             }
             HIPC(hipEventRecord(q0, s));
-            // 1024 threads per node: twice the columns in flight per pivot step
-            // (the arithmetic per column is the same for any block size)
-            if (ell <= 16 * 8)
+            // the node's columns in registers across a gang of workgroups
+            // (8 per node on the upper levels, 4 where the nodes fill the
+            // chip); else one workgroup per node streaming G
+            bool gang = false;
+            std::unique_lock<std::mutex> glk(g_gang_mu, std::defer_lock);
+            if (use_gang) {
+                glk.lock();
+                const double tau = h->prm.id_tol;
+                if (ell <= 16 * 8)
+                    gang = nb >= 64 ? qr_gang_launch<4, 8, 4>(G, ell, ncm, d_ids, h->T_cnt, h->ncols, smax, tau,
+                                                             h->colperm, h->skk, nb, gsc, g_timeout, s)
+                                    : qr_gang_launch<8, 8, 2>(G, ell, ncm, d_ids, h->T_cnt, h->ncols, smax, tau,
+                                                             h->colperm, h->skk, nb, gsc, g_timeout, s);
+                else
+                    gang = nb >= 64 ? qr_gang_launch<4, 18, 4>(G, ell, ncm, d_ids, h->T_cnt, h->ncols, smax, tau,
+                                                              h->colperm, h->skk, nb, gsc, g_timeout, s)
+                                    : qr_gang_launch<8, 18, 2>(G, ell, ncm, d_ids, h->T_cnt, h->ncols, smax, tau,
+                                                              h->colperm, h->skk, nb, gsc, g_timeout, s);
+                if (!gang) glk.unlock();
+            }
+            if (gang) {
+            } else if (ell <= 16 * 8)
                 hipLaunchKernelGGL((k_qrcp<512, 8>), dim3((unsigned)nb), dim3(512), 0, s, G, ell, ncm, d_ids,
                                    h->T_cnt, h->ncols, smax, h->prm.id_tol, h->colperm, h->skk, nb);
             else if (ell <= 16 * 18)
@@ -514,6 +867,12 @@ void skeletonize(askit_handle *h, hipStream_t s)
                                h->S, h->P, h->Xs, h->gs);
             HIPC(hipGetLastError());
             HIPC(hipStreamSynchronize(s));
+            if (gang) {
+                int32_t herr = 0;
+                HIPC(hipMemcpy(&herr, gsc.err, sizeof(int32_t), hipMemcpyDeviceToHost));
+                glk.unlock();
+                if (herr) fail(ASKIT_ERR_DEVICE, "QR gang exchange timed out (workgroups not co-resident)");
+            }
             float ms = 0.f;
             HIPC(hipEventElapsedTime(&ms, q0, q1));
             h->t_qr += ms;
@@ -523,6 +882,11 @@ void skeletonize(askit_handle *h, hipStream_t s)
     (void)hipEventDestroy(q1);
     HIPC(hipStreamSynchronize(s));
     HIPC(hipFreeAsync(G, s));
+    if (use_gang) {
+        HIPC(hipFreeAsync(gsc.slots, s));
+        HIPC(hipFreeAsync(gsc.sdata, s));
+        HIPC(hipFreeAsync(gsc.err, s));
+    }
     HIPC(hipFreeAsync(colpos, s));
     HIPC(hipFreeAsync(d_ids, s));
     if (hp_tmp) HIPC(hipFreeAsync(hp_tmp, s));
