@@ -825,12 +825,13 @@ void skeletonize(askit_handle *h, hipStream_t s)
                                        h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
             }
             HIPC(hipEventRecord(q0, s));
-            // the node's columns in registers across a gang of workgroups
-            // (8 per node on the upper levels, 4 where the nodes fill the
-            // chip); else one workgroup per node streaming G
+            // levels of at most 128 nodes: the node's columns in registers
+            // across a gang of workgroups (4 per node from 64 nodes on, else
+            // 8); larger levels keep one workgroup per node streaming G,
+            // which there costs about as much as the gang's per-step exchange
             bool gang = false;
             std::unique_lock<std::mutex> glk(g_gang_mu, std::defer_lock);
-            if (use_gang) {
+            if (use_gang && nb <= 128) {
                 glk.lock();
                 const double tau = h->prm.id_tol;
                 if (ell <= 16 * 8)
