@@ -364,6 +364,9 @@ def main():
     ap.add_argument("--serve-mem-gib", type=int, default=64)
     ap.add_argument("--serve-budget-s", type=float, default=20.0, help="GPU work per serving replay")
     ap.add_argument("--batched-rhs", type=int, default=1)
+    ap.add_argument("--query-points", default=None,
+                    help="new-point batch sizes timed through askit_query on the built handle "
+                         "(default 4096,32768 on the 2^20 x 64 workload, none elsewhere; '' for none)")
     ap.add_argument("--set", action="append", default=[], metavar="FIELD=VALUE",
                     help="change one workload parameter (e.g. h=0.5, smax=128); the line then names it")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"],
@@ -440,6 +443,21 @@ def main():
     ms_amort = (tb - ta) * 1e3 / args.evals
     info = h.info()
 
+    # new points (askit_query: their kNN, interaction lists and evaluation)
+    queries = []
+    qspec = args.query_points if args.query_points is not None else ("4096,32768" if args.workload == "fp32_1m" else "")
+    for mq in [int(v) for v in qspec.split(",") if v.strip()]:
+        Yq = torch.from_numpy(synth.queries(wl, mq, 991 + mq)).cuda()
+        h.query(Yq)
+        torch.cuda.synchronize()
+        tq0 = time.perf_counter()
+        for _ in range(3):
+            h.query(Yq)
+        torch.cuda.synchronize()
+        msq = (time.perf_counter() - tq0) * 1e3 / 3
+        queries.append({"points": mq, "ms": msq, "points_per_s": mq / (msq * 1e-3)})
+        log(f"[bench] query of {mq} new points: {msq:.1f} ms")
+
     # accuracy on sampled targets against an FP64 direct sum
     rng = np.random.default_rng(12345)
     nt = min(args.eps_targets, wl.N)
@@ -508,6 +526,7 @@ def main():
                                         "knn_uncertified_rows", "knn_retry_rows", "eval_pairs", "eval_chunks")},
         "roofline": roof,
         "roofline_eval": eval_roof,
+        "queries": queries,
     }
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
