@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <mutex>
 
 namespace askit {
@@ -787,7 +788,13 @@ void skeletonize(askit_handle *h, hipStream_t s)
         HIPC(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
         HIPC(hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev));
     }
-    const bool use_gang = coop && clk_khz > 0 && ncm <= 512 && ell <= 16 * 18;
+    // (by default large point sets only: gang launches are serialized
+    // across host threads, which would serialize the many small setups of a
+    // batch).  ASKIT_QR_GANG=1 uses it at any size, 0 never.
+    const char *genv = std::getenv("ASKIT_QR_GANG");
+    const int gmode = genv ? std::atoi(genv) : -1;
+    const bool use_gang = coop && clk_khz > 0 && ncm <= 512 && ell <= 16 * 18 && gmode != 0 &&
+                          (gmode == 1 || h->N >= (1 << 18));
     const uint64_t g_timeout = (uint64_t)((double)clk_khz * 1000.0 * QG_TIMEOUT_S);
     GangScratch gsc;
     if (use_gang) {

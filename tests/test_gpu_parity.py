@@ -275,3 +275,22 @@ def test_many_rhs_blocks(R):
         U1 = h.evaluate().cpu().numpy().astype(np.float64)
         assert rel(U1[:, 0], U[:, r]) < 1e-6
     h.close()
+
+
+@pytest.mark.parametrize("name", ["small-fp64", "filter-path"])
+def test_gang_qr_matches_oracle(name, monkeypatch):
+    """The pivoted QR by gangs of workgroups (used by default for large point
+    sets on levels of at most 128 nodes) forced at this size: skeletons,
+    projections and u against the oracle."""
+    monkeypatch.setenv("ASKIT_QR_GANG", "1")
+    N, d, q, comps, p = CASES[name]
+    X = synth.mixture_points(N, d, q, comps, 1e-3, 100 + N)
+    W = synth.weights(N, 2, N)
+    st, g = run_both(X, W, p, gparams(p))
+    nn = len(st["nodes"])
+    for a in range(1, nn):
+        k = st["sk"].k[a]
+        assert g["k"][a] == k, f"node {a}"
+        assert np.array_equal(g["S"][a, :k], st["sk"].S[a, :k]), f"node {a}"
+    for r in range(W.shape[1]):
+        assert rel(g["U"][:, r], st["ev"].U[:, r]) < U_TOL
