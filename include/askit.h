@@ -90,6 +90,11 @@ askit_status askit_params_default(askit_params *p);
  * Returns ASKIT_ERR_INVALID_ARG for N < 2, d < 1, kappa >= N, m < 1,
  * s_max < 1, l < s_max, h <= 0 with a fixed bandwidth, non-finite X, or a
  * zero variable bandwidth (duplicate points).  Synchronises `stream`.
+ * The pivoted QR of the upper tree levels runs on gangs of co-resident
+ * workgroups (a cooperative launch) for N >= 2^18; the environment variable
+ * ASKIT_QR_GANG=1 selects that form at any N and ASKIT_QR_GANG=0 never (the
+ * two forms take the same decisions with different summation orders).
+ * ASKIT_ERR_DEVICE if a gang's exchange does not complete within 10 s.
  */
 askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx,
                          const askit_params *p, void *stream, askit_handle **out);

@@ -84,6 +84,7 @@ def test_null_handle_calls():
     assert L.askit_update_weights(None, None, 1, 1, None) == A.ERR_INVALID_ARG
     assert L.askit_evaluate(None, None, 1, None) == A.ERR_INVALID_ARG
     assert L.askit_query(None, None, 1, 1, None, 1, None) == A.ERR_INVALID_ARG
+    assert L.askit_query_neighbors(None, None, 1, 1, None, None, None) == A.ERR_INVALID_ARG
     L.askit_destroy(None)
 
 
