@@ -73,8 +73,18 @@ __global__ void k_centroid(const double *__restrict__ bsum, const Split *__restr
     Split s = sp[q];
     int nb = (s.n + 63) / 64;
     for (int k = threadIdx.x; k < d; k += blockDim.x) {
+        const double *bs = bsum + (int64_t)q * maxblk * d + k;
         double acc = 0.0;
-        for (int b = 0; b < nb; ++b) acc += bsum[((int64_t)q * maxblk + b) * d + k];
+        int b = 0;
+        // sixteen loads in flight, added in block order
+        for (; b + 16 <= nb; b += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = bs[(int64_t)(b + u) * d];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc += v[u];
+        }
+        for (; b < nb; ++b) acc += bs[(int64_t)b * d];
         cen[(int64_t)q * d + k] = acc / (double)s.n;
     }
 }
