@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <exception>
 #include <new>
+#include <thread>
 
 using namespace askit;
 
@@ -211,6 +213,7 @@ askit_handle::~askit_handle()
 
 void *askit_handle::alloc(size_t bytes, bool zero)
 {
+    std::lock_guard<std::mutex> lk(alloc_mu);
     void *p = nullptr;
     HIPC(hipMalloc(&p, std::max<size_t>(bytes, 16)));
     allocs.push_back(p);
@@ -459,18 +462,60 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
                        N, h->gt);
     HIPC(hipGetLastError());
     HIPC(hipEventRecord(ev[2], s));
-    // ---- node lists and sampled rows
-    build_node_lists(h.get(), s);
-    sample_rows(h.get(), s);
-    HIPC(hipEventRecord(ev[3], s));
-    // ---- skeletons
-    skeletonize(h.get(), s);
-    HIPC(hipEventRecord(ev[4], s));
-    // ---- interaction lists, and the same pairs grouped by source node
-    build_interactions(h.get(), s);
-    build_pairs(h.get(), h->d_slabs, (int64_t)h->slabs.size(), N, h->sl_ptr, h->sl_node, h->sl_mask,
-                h->near_entries, h->far_entries, h->pairs,
-                [hp = h.get()](size_t b) { return hp->alloc(b, false); }, s);
+    // ---- interaction lists and the same pairs grouped by source node: they
+    // need the tree and the neighbours, not the skeletons, so a helper thread
+    // builds them on a second stream while this one builds node lists, sampled
+    // rows and skeletons
+    hipStream_t s2 = nullptr;
+    hipEvent_t ei[2] = {nullptr, nullptr};
+    HIPC(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    HIPC(hipEventCreate(&ei[0]));
+    HIPC(hipEventCreate(&ei[1]));
+    HIPC(hipStreamWaitEvent(s2, ev[2], 0));
+    std::exception_ptr ierr;
+    askit_handle *hp = h.get();
+    std::thread ith([&, hp]() {
+        try {
+            HIPC(hipSetDevice(hp->device));
+            HIPC(hipEventRecord(ei[0], s2));
+            build_interactions(hp, s2);
+            build_pairs(hp, hp->d_slabs, (int64_t)hp->slabs.size(), N, hp->sl_ptr, hp->sl_node, hp->sl_mask,
+                        hp->near_entries, hp->far_entries, hp->pairs,
+                        [hp](size_t b) { return hp->alloc(b, false); }, s2);
+            HIPC(hipEventRecord(ei[1], s2));
+            HIPC(hipStreamSynchronize(s2));
+        } catch (...) {
+            ierr = std::current_exception();
+        }
+    });
+    struct Join {
+        std::thread &t;
+        hipStream_t s2;
+        hipEvent_t *e;
+        ~Join()
+        {
+            if (t.joinable()) t.join();
+            (void)hipStreamSynchronize(s2);
+            (void)hipStreamDestroy(s2);
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    };
+    float ms_inter = 0.f;
+    {
+        Join jn{ith, s2, ei};
+        // ---- node lists and sampled rows
+        build_node_lists(h.get(), s);
+        sample_rows(h.get(), s);
+        HIPC(hipEventRecord(ev[3], s));
+        // ---- skeletons
+        skeletonize(h.get(), s);
+        HIPC(hipEventRecord(ev[4], s));
+        ith.join();
+        if (ierr) std::rethrow_exception(ierr);
+        HIPC(hipEventElapsedTime(&ms_inter, ei[0], ei[1]));
+    }
+    count_pairs(h.get(), s);
     HIPC(hipEventRecord(ev[5], s));
     HIPC(hipStreamSynchronize(s));
     prepare_upward(h.get());
@@ -481,7 +526,7 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
     HIPC(hipEventElapsedTime(&ms, ev[1], ev[2])); h->t_knn = ms;
     HIPC(hipEventElapsedTime(&ms, ev[2], ev[3])); h->t_lists = ms;
     HIPC(hipEventElapsedTime(&ms, ev[3], ev[4])); h->t_skel = ms;
-    HIPC(hipEventElapsedTime(&ms, ev[4], ev[5])); h->t_inter = ms;
+    h->t_inter = ms_inter;                 // on the second stream, overlapped with the above
     *out = h.release();
     API_END
 }

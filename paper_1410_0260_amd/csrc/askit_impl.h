@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -211,6 +212,7 @@ struct askit_handle {
 
     ~askit_handle();
     void *alloc(size_t bytes, bool zero = true);
+    std::mutex alloc_mu;               // alloc may be called from two host threads during setup
     hipStream_t astream = nullptr;     // stream that orders alloc's zero fill (the calling API's)
 };
 
@@ -261,6 +263,8 @@ void build_tree(askit_handle *h, hipStream_t s);
 void build_node_lists(askit_handle *h, hipStream_t s);
 void sample_rows(askit_handle *h, hipStream_t s);
 void build_interactions(askit_handle *h, hipStream_t s);
+// algorithmic (target, source) pair counts of one evaluation (needs the skeleton sizes)
+void count_pairs(askit_handle *h, hipStream_t s);
 // query lists: nb is M x kappa neighbour positions; slabs of consecutive queries
 void build_query_interactions(askit_handle *h, const int32_t *nb, int64_t M, Slab *&slabs,
                               int32_t *&ptr, int32_t *&node, uint64_t *&mask, int64_t &ne_near,

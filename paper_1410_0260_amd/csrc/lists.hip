@@ -564,6 +564,10 @@ void build_interactions(askit_handle *h, hipStream_t s)
     run_interactions(h, h->d_slabs, (int64_t)h->slabs.size(), nb, nnb, h->sl_ptr, h->sl_node,
                      h->sl_mask, h->near_entries, h->far_entries, owned, s, true);
     HIPC(hipFreeAsync(nb, s));
+}
+
+void count_pairs(askit_handle *h, hipStream_t s)
+{
     // algorithmic pair counts of one evaluation
     unsigned long long *pc;
     HIPC(hipMallocAsync((void **)&pc, 16, s));
