@@ -837,7 +837,7 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int q = 0; q < SEL_Q; ++q)
-            if ((key[q] & pmask) == prefix) atomicAdd(&hw[(key[q] >> shift) & 255u], 1);
+            if (lane + WAVE * q < nk && (key[q] & pmask) == prefix) atomicAdd(&hw[(key[q] >> shift) & 255u], 1);
         __builtin_amdgcn_wave_barrier();
         int c[4], c4 = 0;
 #pragma unroll
