@@ -521,6 +521,11 @@ def main():
                       ("t_knn_ms", "t_tree_ms", "t_lists_ms", "t_skel_ms", "t_inter_ms", "t_update_ms",
                        "t_knn_sweep_ms", "t_knn_filter_ms", "t_qr_ms")},
         "eps_vs_fp64_direct": {"per_rhs": eps, "targets_sampled": nt},
+        "accuracy_gate": {"target": 1e-3, "eps_max": max(eps), "met": bool(max(eps) <= 1e-3),
+                          "note": None if max(eps) <= 1e-3 else
+                          "the error of the approximation itself at this workload's h and s_max (the "
+                          "FP64 oracle of the same approximation has it too); a narrower kernel "
+                          "(--set h=...) or a larger s_max lowers it"},
         "counts": {k: info[k] for k in ("num_nodes", "num_leaves", "depth", "num_slabs", "near_entries",
                                         "far_entries", "near_pairs", "far_pairs",
                                         "knn_uncertified_rows", "knn_retry_rows", "eval_pairs", "eval_chunks")},
