@@ -345,7 +345,12 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
     __shared__ int s_lb, s_fail;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int grp = tid >> 4, l16 = tid & 15;
-    const int gang = blockIdx.x / W, w = blockIdx.x % W, ngang = gridDim.x / W;
+    // workgroups are dealt to the 8 XCDs round robin (id mod 8): the members
+    // of a gang are ids 8 apart, so a gang stays on one XCD, where its
+    // exchanges take about a fifth of the time they take across XCDs (the
+    // protocol itself does not depend on the placement)
+    const int ngang = gridDim.x / W;
+    const int gang = (int)(blockIdx.x / (8 * W)) * 8 + (int)(blockIdx.x % 8), w = (int)(blockIdx.x / 8) % W;
     int32_t gs = 0;                           // steps published by this gang
     if (tid == 0) s_fail = 0;
     for (int q = gang; q < nb; q += ngang) {
@@ -724,8 +729,10 @@ static bool qr_gang_launch(double *G, int ell, int ncm, const int32_t *ids, cons
     HIPC(hipGetDevice(&dev));
     HIPC(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_qrcp_gang<W, RM, CPG>, QG_T, 0));
-    const int ngang = std::min(nb, std::min(QG_GMAX, per * ncu / W));
-    if (ngang < 1) return false;
+    // a multiple of 8 gangs (one set per XCD); gangs past the last node idle
+    const int fit = std::min(QG_GMAX, per * ncu / W) / 8 * 8;
+    const int ngang = std::min(fit, (nb + 7) / 8 * 8);
+    if (ngang < 8) return false;
     const int nslot = ngang * 2 * W;
     hipLaunchKernelGGL(k_gang_reset, dim3((unsigned)((nslot + 255) / 256)), dim3(256), 0, s, gs.slots, nslot,
                        gs.err);
