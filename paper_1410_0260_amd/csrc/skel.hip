@@ -128,10 +128,33 @@ constexpr int QR_T = 1024;
 constexpr int QR_MAXCOL = 2048;
 constexpr int QR_MAXROW = 1024;
 
+// Lane l's value from lane l ^ o (o = 8, 4, 2, 1; the partner is always in
+// the same group of 16): xor 8 and 4 by a swizzle in the LDS crossbar, xor 2
+// and 1 by DPP quad permutes, so no LDS address round trip.
+template <int O>
+__device__ __forceinline__ double xor_lane(double v)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    if constexpr (O == 8 || O == 4) {
+        constexpr int pat = 0x1f | (O << 10);          // and 31, or 0, xor O
+        lo = __builtin_amdgcn_ds_swizzle(lo, pat);
+        hi = __builtin_amdgcn_ds_swizzle(hi, pat);
+    } else {
+        constexpr int ctrl = O == 2 ? 0x4e : 0xb1;     // quad_perm [2,3,0,1] / [1,0,3,2]
+        lo = __builtin_amdgcn_mov_dpp(lo, ctrl, 0xf, 0xf, false);
+        hi = __builtin_amdgcn_mov_dpp(hi, ctrl, 0xf, 0xf, false);
+    }
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over a group of 16 lanes by the xor butterfly: every lane of the group
+// ends with the same value.
 __device__ __forceinline__ double group16_sum(double v)
 {
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    v += xor_lane<8>(v);
+    v += xor_lane<4>(v);
+    v += xor_lane<2>(v);
+    v += xor_lane<1>(v);
     return v;
 }
 
@@ -338,6 +361,7 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
     __shared__ int piv[QR_MAXCOL];            // position -> column
     __shared__ int posof[QR_MAXCOL];          // column -> position
     __shared__ double cd[W][RMAX];            // the W candidates' rows
+    __shared__ double svr[RMAX];              // the reflector's rows below t
     __shared__ double cv[W];
     __shared__ int cp[W], cc[W];
     __shared__ double rdv[QG_T / 64];
@@ -507,12 +531,11 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
                     act[j] = false;
                 }
             }
+            for (int i = tid; i < RMAX; i += QG_T) svr[i] = (i > t && i < rows) ? vs[i] / denom : 0.0;
+            __syncthreads();
             double vr[RM];
 #pragma unroll
-            for (int r = 0; r < RM; ++r) {
-                const int i = l16 + 16 * r;
-                vr[r] = (i > t && i < rows) ? vs[i] / denom : 0.0;
-            }
+            for (int r = 0; r < RM; ++r) vr[r] = svr[l16 + 16 * r];
             const int src = (lane & ~15) | lt;
 #pragma unroll
             for (int j = 0; j < CPG; ++j) {
