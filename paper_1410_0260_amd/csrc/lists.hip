@@ -18,7 +18,7 @@ namespace askit {
 // the chunk that holds its smallest key.  An internal node reduces the
 // union of its children's stored lists (Alg. 2, second line).
 // ====================================================================
-constexpr int NL_CAP = 4096;
+constexpr int NL_CAP = 2048;                // 48 KiB of LDS: three workgroups per CU
 constexpr int NL_T = 256;
 
 struct NLShared {
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(NL_T) void k_internal_nlists(const Node *__restrict
 void build_node_lists(askit_handle *h, hipStream_t s)
 {
     if (h->ell > NL_CAP / 2 || h->kappa > NL_CAP / 2)
-        fail(ASKIT_ERR_UNSUPPORTED, "sample_rows and kappa must be at most 2048");
+        fail(ASKIT_ERR_UNSUPPORTED, "sample_rows and kappa must be at most 1024");
     int nn = (int)h->nodes.size();
     HIPC(hipMemsetAsync(h->nl_cnt, 0, sizeof(int32_t) * nn, s));
     if (h->depth == 0) return;
