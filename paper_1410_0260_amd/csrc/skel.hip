@@ -537,29 +537,40 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
 #pragma unroll
             for (int r = 0; r < RM; ++r) vr[r] = svr[l16 + 16 * r];
             const int src = (lane & ~15) | lt;
+            const bool lane_after = l16 > lt, lane_at = l16 == lt;
 #pragma unroll
             for (int j = 0; j < CPG; ++j) {
                 if (!act[j]) continue;                 // group-uniform
+                // vr is zero outside rows (t, rows): the dot product needs no
+                // row test
                 double sdot = 0.0, top = 0.0;
 #pragma unroll
                 for (int r = 0; r < RM; ++r) {
-                    const int i = l16 + 16 * r;
-                    if (i > t && i < rows) sdot += vr[r] * x[j][r];
+                    sdot += vr[r] * x[j][r];
                     if (r == rt) top = x[j][r];
                 }
                 sdot = group16_sum(sdot);
                 top = __shfl(top, src);
                 const double f = beta * (sdot + top);
                 double ns = 0.0;
+                // slices after rt change whole (their rows past `rows` hold
+                // zeros with zero reflector entries and stay zero), slice rt
+                // changes its rows > t and row t becomes R(t, c), slices
+                // before it keep their R rows: uniform tests per slice and
+                // one lane test, instead of a row test per element
 #pragma unroll
                 for (int r = 0; r < RM; ++r) {
-                    const int i = l16 + 16 * r;
-                    if (i > t && i < rows) {
-                        const double y = x[j][r] - f * vr[r];
+                    const double y = x[j][r] - f * vr[r];
+                    if (r > rt) {
                         x[j][r] = y;
                         ns += y * y;
-                    } else if (i == t) {
-                        x[j][r] = top - f;
+                    } else if (r == rt) {
+                        if (lane_after) {
+                            x[j][r] = y;
+                            ns += y * y;
+                        } else if (lane_at) {
+                            x[j][r] = top - f;
+                        }
                     }
                 }
                 nv[j] = group16_sum(ns);
@@ -862,13 +873,14 @@ void skeletonize(askit_handle *h, hipStream_t s)
                                        h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
             }
             HIPC(hipEventRecord(q0, s));
-            // levels of at most 128 nodes: the node's columns in registers
-            // across a gang of workgroups (4 per node from 64 nodes on, else
-            // 8); larger levels keep one workgroup per node streaming G,
-            // which there costs about as much as the gang's per-step exchange
+            // every level: the node's columns in registers across a gang of
+            // workgroups (4 per node from 64 nodes on, else 8), as many gangs
+            // as fit at once, each taking nodes in turn; one workgroup per
+            // node streaming G when the gang cannot run (no cooperative
+            // launch, more than 512 columns or 288 rows)
             bool gang = false;
             std::unique_lock<std::mutex> glk(g_gang_mu, std::defer_lock);
-            if (use_gang && nb <= 128) {
+            if (use_gang) {
                 glk.lock();
                 const double tau = h->prm.id_tol;
                 if (ell <= 16 * 8)
