@@ -366,7 +366,7 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
     __shared__ int cp[W], cc[W];
     __shared__ double rdv[QG_T / 64];
     __shared__ int rdp[QG_T / 64], rdc[QG_T / 64];
-    __shared__ int s_lb, s_fail;
+    __shared__ int s_fail;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int grp = tid >> 4, l16 = tid & 15;
     // workgroups are dealt to the 8 XCDs round robin (id mod 8): the members
@@ -430,17 +430,20 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
             const int par = gs & 1;
             GangSlot *sl = slots + ((int64_t)gang * 2 + par) * W;
             double *sd = sdata + ((int64_t)gang * 2 + par) * W * ell;
+            // every thread reduces the waves' candidates (same order, same
+            // result), so no barrier is needed before the rows are published
+            bv = rdv[0];
+            bp = rdp[0];
+            bc = rdc[0];
+            for (int u = 1; u < QG_T / 64; ++u)
+                if (qg_better(rdv[u], rdp[u], bv, bp)) { bv = rdv[u]; bp = rdp[u]; bc = rdc[u]; }
             if (tid == 0) {
-                for (int u = 1; u < QG_T / 64; ++u)
-                    if (qg_better(rdv[u], rdp[u], bv, bp)) { bv = rdv[u]; bp = rdp[u]; bc = rdc[u]; }
                 __hip_atomic_store(&sl[w].v, bv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&sl[w].pos, bp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&sl[w].col, bc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_lb = bc;
             }
-            __syncthreads();
             {
-                const int lbc = s_lb;
+                const int lbc = bc;
                 if (lbc >= 0 && grp == (lbc / W) % 32) {
                     const int jb = (lbc / W) / 32;
                     double *dst = sd + (int64_t)w * ell;
@@ -461,10 +464,12 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             __syncthreads();
             if (tid == 0) __hip_atomic_store(&sl[w].seq, gs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // wait for the W candidates of this step
-            if (tid < W) {
+            // every wave waits for the W candidates of this step itself (its
+            // lanes < W poll), then loads its share: the loads of a lane are
+            // issued only after its wave saw all W sequence numbers
+            if (lane < W) {
                 const uint64_t t0 = wall_clock64();
-                while (__hip_atomic_load(&sl[tid].seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gs) {
+                while (__hip_atomic_load(&sl[lane].seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gs) {
                     if (wall_clock64() - t0 > timeout) {
                         atomicExch(err, 1);
                         s_fail = 1;
@@ -473,8 +478,7 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
                     __builtin_amdgcn_s_sleep(1);
                 }
             }
-            __syncthreads();
-            if (s_fail) return;
+            __builtin_amdgcn_wave_barrier();
             // the headers and every candidate's rows t.. in one round of loads
             // (a workgroup without a candidate left stale rows: not used)
             if (tid < W) {
@@ -487,6 +491,7 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
                 cd[u][i] = __hip_atomic_load(&sd[(int64_t)u * ell + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             __syncthreads();
+            if (s_fail) return;
             double gv = -1.0;
             int gp = 0x7fffffff, pc = -1, pw = 0;
 #pragma unroll
@@ -501,7 +506,8 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
                 k = t;
                 break;
             }
-            // swap positions t and posof[pc]
+            // swap positions t and posof[pc] (read again only after the
+            // barrier that follows the reflector rows below)
             if (tid == 0) {
                 const int ct = piv[t], pp = posof[pc];
                 piv[t] = pc;
@@ -509,7 +515,6 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
                 posof[ct] = pp;
                 posof[pc] = t;
             }
-            __syncthreads();
             // the reflector, computed alike in every workgroup
             const double *vs = cd[pw];
             const double x0 = vs[t];
