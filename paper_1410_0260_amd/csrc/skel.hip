@@ -797,9 +797,10 @@ void skeletonize(askit_handle *h, hipStream_t s)
     if (h->depth == 0) return;
     int maxlev = 0;
     for (auto &lv : h->level_nodes) maxlev = std::max(maxlev, (int)lv.size());
-    // batch so that the FP64 blocks stay within ~2 GiB
+    // batch so that the FP64 blocks stay within ~4 GiB (one batch per level
+    // up to 3,800 nodes of 512 columns x 276 rows)
     const size_t per = (size_t)ncm * ell * sizeof(double);
-    int batch = (int)std::max<size_t>(1, std::min<size_t>(maxlev, (size_t)(2ull << 30) / per));
+    int batch = (int)std::max<size_t>(1, std::min<size_t>(maxlev, (size_t)(4ull << 30) / per));
     double *G;
     int32_t *colpos, *d_ids;
     HIPC(hipMallocAsync((void **)&G, per * batch, s));
