@@ -90,8 +90,9 @@ askit_status askit_params_default(askit_params *p);
  * Returns ASKIT_ERR_INVALID_ARG for N < 2, d < 1, kappa >= N, m < 1,
  * s_max < 1, l < s_max, h <= 0 with a fixed bandwidth, non-finite X, or a
  * zero variable bandwidth (duplicate points).  Synchronises `stream`.
- * The pivoted QR of the upper tree levels runs on gangs of co-resident
- * workgroups (a cooperative launch) for N >= 2^18; the environment variable
+ * The pivoted QR of every tree level runs on gangs of co-resident
+ * workgroups (a cooperative launch) for N >= 2^18 when l <= 288 and a node
+ * has at most 512 columns, else one workgroup per node; the environment variable
  * ASKIT_QR_GANG=1 selects that form at any N and ASKIT_QR_GANG=0 never (the
  * two forms take the same decisions with different summation orders).
  * ASKIT_ERR_DEVICE if a gang's exchange does not complete within 10 s.
