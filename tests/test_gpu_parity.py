@@ -280,8 +280,8 @@ def test_many_rhs_blocks(R):
 @pytest.mark.parametrize("name", ["small-fp64", "filter-path"])
 def test_gang_qr_matches_oracle(name, monkeypatch):
     """The pivoted QR by gangs of workgroups (used by default for large point
-    sets on levels of at most 128 nodes) forced at this size: skeletons,
-    projections and u against the oracle."""
+    sets on every tree level) forced at this size: skeletons, projections and
+    u against the oracle."""
     monkeypatch.setenv("ASKIT_QR_GANG", "1")
     N, d, q, comps, p = CASES[name]
     X = synth.mixture_points(N, d, q, comps, 1e-3, 100 + N)
@@ -294,3 +294,39 @@ def test_gang_qr_matches_oracle(name, monkeypatch):
         assert np.array_equal(g["S"][a, :k], st["sk"].S[a, :k]), f"node {a}"
     for r in range(W.shape[1]):
         assert rel(g["U"][:, r], st["ev"].U[:, r]) < U_TOL
+
+
+@pytest.mark.parametrize("name", ["small-fp64", "filter-path"])
+def test_gang_and_streaming_qr_agree(name, monkeypatch):
+    """Both forms of the pivoted QR (gangs holding a node's columns on chip,
+    and one workgroup per node streaming G) on the same input: the same ranks,
+    column orders and skeletons, and P equal up to FP32 rounding."""
+    import torch
+    from paper_1410_0260_amd import askit as A
+    N, d, q, comps, p = CASES[name]
+    X = synth.mixture_points(N, d, q, comps, 1e-3, 200 + N)
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("ASKIT_QR_GANG", mode)
+        h = A.setup(torch.from_numpy(X).cuda(), gparams(p))
+        out[mode] = h.structures()
+        h.close()
+    a, b = out["0"], out["1"]
+    assert np.array_equal(a["k"], b["k"])
+    assert np.array_equal(a["S"], b["S"])
+    nn = len(a["k"])
+    for n in range(1, nn):
+        m = a["ncols"][n]
+        assert np.array_equal(a["colperm"][n, :m], b["colperm"][n, :m]), f"node {n}"
+    # P slots are packed in node order, k x (n - k) used in each
+    nodes = a["nodes"]
+    off = 0
+    for n in range(1, nn):
+        n_a = int(nodes[n]["hi"] - nodes[n]["lo"])
+        ncap = n_a if nodes[n]["left"] < 0 else 2 * p.smax
+        kcap = min(p.smax, min(p.ell, N - n_a), ncap)
+        k, m = a["k"][n], a["ncols"][n]
+        pa = a["P"][off:off + k * (m - k)].astype(np.float64)
+        pb = b["P"][off:off + k * (m - k)].astype(np.float64)
+        assert np.linalg.norm(pa - pb) <= 1e-5 * max(1.0, np.linalg.norm(pa)), f"node {n}"
+        off += kcap * ncap
