@@ -429,7 +429,7 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
             ++gs;
             const int par = gs & 1;
             GangSlot *sl = slots + ((int64_t)gang * 2 + par) * W;
-            double *sd = sdata + ((int64_t)gang * 2 + par) * W * ell;
+            double *sd = sdata + ((int64_t)gang * 2 + par) * W * RMAX;   // RMAX rows per member
             // every thread reduces the waves' candidates (same order, same
             // result), so no barrier is needed before the rows are published
             bv = rdv[0];
@@ -446,16 +446,17 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
                 const int lbc = bc;
                 if (lbc >= 0 && grp == (lbc / W) % 32) {
                     const int jb = (lbc / W) / 32;
-                    double *dst = sd + (int64_t)w * ell;
+                    double *dst = sd + (int64_t)w * RMAX;
+                    // whole slices from the one holding row t (a uniform test;
+                    // rows < t and >= rows are written too and never read)
 #pragma unroll
                     for (int j = 0; j < CPG; ++j) {
                         if (j != jb) continue;
 #pragma unroll
-                        for (int r = 0; r < RM; ++r) {
-                            const int i = l16 + 16 * r;
-                            if (i >= t && i < rows)
-                                __hip_atomic_store(&dst[i], x[j][r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        }
+                        for (int r = 0; r < RM; ++r)
+                            if (r >= (t >> 4))
+                                __hip_atomic_store(&dst[l16 + 16 * r], x[j][r], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
             }
@@ -488,7 +489,7 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
             }
             for (int e = tid; e < W * (rows - t); e += QG_T) {
                 const int u = e / (rows - t), i = t + e % (rows - t);
-                cd[u][i] = __hip_atomic_load(&sd[(int64_t)u * ell + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                cd[u][i] = __hip_atomic_load(&sd[(int64_t)u * RMAX + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             __syncthreads();
             if (s_fail) return;
@@ -529,9 +530,12 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
                     if (j != jp) continue;
 #pragma unroll
                     for (int r = 0; r < RM; ++r) {
-                        const int i = l16 + 16 * r;
-                        if (i > t && i < rows) x[j][r] = 0.0;
-                        else if (i == t) x[j][r] = rtt;
+                        if (r > rt) {
+                            x[j][r] = 0.0;             // rows past `rows` hold zeros already
+                        } else if (r == rt) {
+                            if (l16 > lt) x[j][r] = 0.0;
+                            else if (l16 == lt) x[j][r] = rtt;
+                        }
                     }
                     act[j] = false;
                 }
@@ -846,7 +850,7 @@ void skeletonize(askit_handle *h, hipStream_t s)
     GangScratch gsc;
     if (use_gang) {
         HIPC(hipMallocAsync((void **)&gsc.slots, sizeof(GangSlot) * QG_GMAX * 2 * 8, s));
-        HIPC(hipMallocAsync((void **)&gsc.sdata, sizeof(double) * QG_GMAX * 2 * 8 * ell, s));
+        HIPC(hipMallocAsync((void **)&gsc.sdata, sizeof(double) * QG_GMAX * 2 * 8 * 16 * 18, s));
         HIPC(hipMallocAsync((void **)&gsc.err, sizeof(int32_t), s));
     }
     hipEvent_t q0, q1;
