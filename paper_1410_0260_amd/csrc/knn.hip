@@ -607,13 +607,15 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
         ntiles = t0 < ntiles_all ? min(per, ntiles_all - t0) : 0;
     }
     if (ntiles <= 0) return;
+    // tile counts fit 32 bits (N < 2^31 points)
+    const int nt32 = (int)ntiles, t032 = (int)t0, nta32 = (int)ntiles_all;
     constexpr int CHUNKS = KB_N * DP / 8;
     constexpr int PER = (CHUNKS + 255) / 256;
     uint4 rh[1][PER], rl[1][PER];
     float rn[1] = {0.0f};
-    auto tile_of = [&](int64_t t) {
-        int64_t tt = t0 + t;
-        return tt >= ntiles_all ? tt - ntiles_all : tt;
+    auto tile_of = [&](int t) -> int {
+        const int tt = t032 + t;
+        return tt >= nta32 ? tt - nta32 : tt;
     };
     KNN_TILE_IO();
     float rt = -INFINITY;
@@ -661,13 +663,13 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     mfma_tile(0, accA0, accA1);
     // iteration t: accumulators of tile t ready; MFMAs of tile t+1 read buffer
     // (t+1)%3; the points of tile t+2 are loaded and stored to buffer (t+2)%3
-    auto iter = [&](auto CUR, int64_t t, f32x16 &c0, f32x16 &c1, f32x16 &n0, f32x16 &n1) {
-        const int64_t tbase = tile_of(t) * KB_N;
-        if (t + 2 < ntiles) {
+    auto iter = [&](auto CUR, int t, f32x16 &c0, f32x16 &c1, f32x16 &n0, f32x16 &n1) {
+        const int tbase = tile_of(t) * KB_N;
+        if (t + 2 < nt32) {
             load_tile(0, tile_of(t + 2));
             load_thr(tile_of(t + 2));
         }
-        if (t + 1 < ntiles) mfma_tile((int)((t + 1) % 3), n0, n1);
+        if (t + 1 < nt32) mfma_tile((t + 1) % 3, n0, n1);
         // <= keeps the window's own 64 points (same arithmetic as the window pass)
         const float *nb = sBn + (t % 3) * KB_N;
         const float ny0 = nb[l32], ny1 = nb[32 + l32];
@@ -751,15 +753,15 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
                 }
             }
         }
-        if (t + 2 < ntiles) {
-            store_tile(0, (int)((t + 2) % 3));
-            store_thr((int)((t + 2) % 3));
+        if (t + 2 < nt32) {
+            store_tile(0, (t + 2) % 3);
+            store_thr((t + 2) % 3);
         }
         __syncthreads();
     };
-    for (int64_t t = 0; t < ntiles; t += 2) {
+    for (int t = 0; t < nt32; t += 2) {
         iter(std::integral_constant<int, 0>{}, t, accA0, accA1, accB0, accB1);
-        if (t + 1 < ntiles) iter(std::integral_constant<int, 1>{}, t + 1, accB0, accB1, accA0, accA1);
+        if (t + 1 < nt32) iter(std::integral_constant<int, 1>{}, t + 1, accB0, accB1, accA0, accA1);
     }
 }
 
