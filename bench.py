@@ -35,6 +35,7 @@ WORKLOADS = {
 }
 
 PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6, "hbm": 8000.0}   # TFLOP/s, GB/s
+BASELINE_METRIC = "kernel-sum targets\u00b7RHS/sec at 1e-3 rel err vs FP64; serving p50/p99 latency"
 
 
 # HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
@@ -104,13 +105,31 @@ def cpu_baseline(wl, X, W, budget_s=20.0):
     lvl = np.log2(max(2.0, N / wl.m)) / np.log2(max(2.0, Ns / wl.m))
     t_full = t_knn * scale_knn + t_rest * (N / Ns) * lvl
     return {"value": N * wl.R / t_full, "unit": "targets*RHS/s", "cores": threads, "kind": "oracle",
+            "host": cpu_info(),
             "sample": (f"full FP64 oracle pipeline on the first {Ns} points of the workload "
                        f"(kNN {t_knn:.2f} s, rest {t_rest:.2f} s), scaled to N={N}: kNN x (N/Ns)^2, "
                        f"rest x (N/Ns) x log(N/m)/log(Ns/m)"),
             "measured_value_at_sample": Ns * wl.R / (t_knn + t_rest)}
 
 
-def serve_bench(args, wl, A, torch):
+def serve_leg(args, A, torch):
+    """The serving form, bounded, inside the default run: the 2^22-point
+    resident setup, the Poisson stream's first requests at their offered
+    arrival times (about 6 s of GPU work), p50/p99 latency and throughput."""
+    import dataclasses
+    a2 = dataclasses.replace(args) if dataclasses.is_dataclass(args) else argparse.Namespace(**vars(args))
+    a2.serve_budget_s = min(args.serve_budget_s, 6.0)
+    full = serve_bench(a2, synth.serving_4m(), A, torch, stretched=False)
+    st = full["at_offered_rate"]
+    return {"workload": full["config"]["workload"], "requests": st["requests"], "p50_ms": st["p50_ms"],
+            "p99_ms": st["p99_ms"], "p50_weights_ms": st["p50_weights_ms"], "p99_weights_ms": st["p99_weights_ms"],
+            "p50_query_ms": st["p50_query_ms"], "p99_query_ms": st["p99_query_ms"],
+            "throughput_targets_rhs_per_s": st["throughput_targets_rhs_per_s"], "setup_s": full["setup_s"],
+            "offered_load_factor": full["offered"]["load_factor"], "capacity": full["capacity"],
+            "stream": full["config"]["stream"]}
+
+
+def serve_bench(args, wl, A, torch, stretched=True):
     """Serving form: a resident setup answers a Poisson stream of weight
     requests (R columns of new weights, u at all N points) and query requests
     (u at M new points for the resident weights), batched continuously.  The
@@ -202,7 +221,7 @@ def serve_bench(args, wl, A, torch):
         f"(offered load {offered_factor:.1f}x capacity)")
     at_rate = replay(head, [r["t"] for r in head])
     stretch = max(1.0, offered_factor / 0.7)
-    below = replay(head, [r["t"] * stretch for r in head])
+    below = replay(head, [r["t"] * stretch for r in head]) if stretched else None
     h.close()
     keep = ("requests", "completed", "failed", "deferred", "batches", "batched_requests", "p50_ms", "p99_ms",
             "mean_ms", "p50_weights_ms", "p99_weights_ms", "p50_query_ms", "p99_query_ms",
@@ -219,7 +238,7 @@ def serve_bench(args, wl, A, torch):
         "offered": {"requests": n, "arrival_span_s": span, "estimated_work_s": work,
                     "load_factor": offered_factor},
         "at_offered_rate": {k: at_rate[k] for k in keep},
-        "stretched_to_70pct_capacity": dict({k: below[k] for k in keep}, stretch=stretch),
+        "stretched_to_70pct_capacity": dict({k: below[k] for k in keep}, stretch=stretch) if below else None,
     }
 
 
@@ -349,52 +368,31 @@ def batched_cpu_baseline(wls, Xs, W, offsets, budget_s=20.0):
                        f"instances (N = {names}), per-point rate")}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fp32_1m", choices=list(WORKLOADS) + ["batched"])
-    ap.add_argument("--eps-targets", type=int, default=1000)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--evals", type=int, default=5, help="amortized update+evaluate repetitions")
-    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the request stream")
-    ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-workers", type=int, default=2)
-    ap.add_argument("--serve-mem-gib", type=int, default=64)
-    ap.add_argument("--serve-budget-s", type=float, default=20.0, help="GPU work per serving replay")
-    ap.add_argument("--batched-rhs", type=int, default=1)
-    ap.add_argument("--query-points", default=None,
-                    help="new-point batch sizes timed through askit_query on the built handle "
-                         "(default 4096,32768 on the 2^20 x 64 workload, none elsewhere; '' for none)")
-    ap.add_argument("--set", action="append", default=[], metavar="FIELD=VALUE",
-                    help="change one workload parameter (e.g. h=0.5, smax=128); the line then names it")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"],
-                    help="distance products: FP32, or bf16 hi/lo split products (precision form)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
-              "multi-GPU path", file=sys.stderr)
-        sys.exit(2)
-
+def direct_gpu_fp64(X, W, tg, h, chunk=65536):
+    """FP64 direct sum at the targets tg (Eq. e:problem) with plain torch
+    float64 on the device: the accuracy reference of the gate.  It is
+    independent of the library (torch's matmul and exp, no library kernel)."""
     import torch
-    from paper_1410_0260_amd import askit as A
+    Xd = torch.from_numpy(X).cuda().double()
+    T = Xd[torch.from_numpy(tg).cuda()]
+    Wd = torch.from_numpy(W).cuda().double()
+    tn = (T * T).sum(1)
+    U = torch.zeros((len(tg), W.shape[1]), dtype=torch.float64, device="cuda")
+    for a in range(0, X.shape[0], chunk):
+        S = Xd[a:a + chunk]
+        D = tn[:, None] + (S * S).sum(1)[None, :] - 2.0 * (T @ S.T)
+        D.clamp_(min=0.0)
+        U += torch.exp(-D / (2.0 * h * h)) @ Wd[a:a + chunk]
+    out = U.cpu().numpy()
+    del Xd, T, Wd, U
+    return out
 
-    if args.workload == "batched":
-        print(json.dumps(batched_bench(args, A, torch)))
-        return
-    wl = WORKLOADS[args.workload]()
-    if args.set:
-        import dataclasses
-        ch = {}
-        for kv in args.set:
-            k, v = kv.split("=", 1)
-            ch[k] = type(getattr(wl, k))(v)
-        wl = dataclasses.replace(wl, **ch)
-        wl = dataclasses.replace(wl, name=wl.name + " [" + ", ".join(args.set) + "]")
-    if args.workload == "serving_4m":
-        print(json.dumps(serve_bench(args, wl, A, torch)))
-        return
+
+def step_bench(wl, args, A, torch, steps, warmup, queries_spec="", eps_targets=10000):
+    """Whole hot path per step (setup + update_weights + evaluate) on one
+    workload; then the amortized per-weight part, the new-point queries, and
+    the error against the FP64 direct sum on sampled targets, with the
+    near-field part of u (the paper's eps_kappa)."""
     log(f"[bench] workload {wl.name}: generating inputs")
     X = synth.points(wl)
     W = synth.weights(wl.N, wl.R, wl.seed)
@@ -411,23 +409,21 @@ def main():
         torch.cuda.synchronize()
         return h
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         log(f"[bench] warmup step {i}")
         step().close()
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         h = step()
         infos.append(h.info())
-        if i < args.steps - 1:
+        if i < steps - 1:
             h.close()
         log(f"[bench] step {i} done")
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_step = (time.perf_counter() - t0) * 1e3 / steps
 
-    # amortized per-weight part on the last handle, and the evaluation kernel alone
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ta = time.perf_counter()
@@ -439,14 +435,11 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         ev_ms.append(ev0.elapsed_time(ev1))
-    tb = time.perf_counter()
-    ms_amort = (tb - ta) * 1e3 / args.evals
+    ms_amort = (time.perf_counter() - ta) * 1e3 / args.evals
     info = h.info()
 
-    # new points (askit_query: their kNN, interaction lists and evaluation)
     queries = []
-    qspec = args.query_points if args.query_points is not None else ("4096,32768" if args.workload == "fp32_1m" else "")
-    for mq in [int(v) for v in qspec.split(",") if v.strip()]:
+    for mq in [int(v) for v in queries_spec.split(",") if v.strip()]:
         Yq = torch.from_numpy(synth.queries(wl, mq, 991 + mq)).cuda()
         h.query(Yq)
         torch.cuda.synchronize()
@@ -455,87 +448,190 @@ def main():
             h.query(Yq)
         torch.cuda.synchronize()
         msq = (time.perf_counter() - tq0) * 1e3 / 3
-        queries.append({"points": mq, "ms": msq, "points_per_s": mq / (msq * 1e-3)})
+        queries.append({"points": mq, "ms": round(msq, 3), "points_per_s": mq / (msq * 1e-3)})
         log(f"[bench] query of {mq} new points: {msq:.1f} ms")
 
-    # accuracy on sampled targets against an FP64 direct sum
+    # error against the FP64 direct sum on sampled targets (Sec. 4: 10K targets)
+    Uf, Un = h.evaluate_parts()
+    torch.cuda.synchronize()
     rng = np.random.default_rng(12345)
-    nt = min(args.eps_targets, wl.N)
+    nt = min(eps_targets, wl.N)
     tgt = np.sort(rng.choice(wl.N, nt, replace=False))
-    Ug = U.cpu().numpy().astype(np.float64)[tgt]
-    hs = h.export(A.X_BANDWIDTH, np.float64)
-    if wl.bw_neighbor > 0:
-        raise SystemExit("variable-bandwidth workloads are benchmarked elsewhere")
-    Ud = direct_fp64(X[tgt], X, W, wl.h)
-    eps = [float(np.linalg.norm(Ug[:, r] - Ud[:, r]) / np.linalg.norm(Ud[:, r])) for r in range(wl.R)]
+    Ug = Uf.cpu().numpy().astype(np.float64)[tgt]
+    Ung = Un.cpu().numpy().astype(np.float64)[tgt]
     h.close()
+    if wl.bw_neighbor > 0:
+        raise SystemExit("variable-bandwidth workloads are benchmarked with --workload batched")
+    Ud = direct_gpu_fp64(X, W, tgt, wl.h)
+    eps = [float(np.linalg.norm(Ug[:, r] - Ud[:, r]) / np.linalg.norm(Ud[:, r])) for r in range(wl.R)]
+    eps_near = [float(np.linalg.norm(Ung[:, r] - Ud[:, r]) / np.linalg.norm(Ud[:, r])) for r in range(wl.R)]
+    offdiag = [float(np.linalg.norm(Ud[:, r] - W[tgt, r]) / np.linalg.norm(Ud[:, r])) for r in range(wl.R)]
+    return dict(X=X, W=W, ms_step=ms_step, ms_amort=ms_amort, ev_ms=ev_ms, infos=infos, info=info,
+                queries=queries, eps=eps, eps_near=eps_near, offdiag=offdiag, targets=nt)
 
-    # roofline of the dominant kernel: the kNN distance sweep (bf16 hi/lo MFMA):
-    # the filter kernel where the sweep runs as window + filter, else the
-    # candidate-list kernel over all rows (wide rows or small N)
+
+def roofline_of(wl, r):
+    """Dominant kernel: the kNN distance sweep on bf16 hi/lo MFMA.  The
+    symmetric sweep computes each unordered pair once: N^2 d algorithmic
+    flops per setup (N^2/2 pairs, 2d flops each), issued as 3 bf16 products
+    each (hi*hi, hi*lo, lo*hi), so the MFMA flops issued are 3 N^2 d.
+    frac = issued flops / time / bf16 dense peak, which equals algorithmic
+    flops / time / the emulated peak (bf16 peak / 3)."""
+    infos = r["infos"]
     launches = int(infos[-1]["knn_filter_launches"])
     if launches >= 1:
         sweep_ms = float(np.mean([i_["t_knn_filter_ms"] / i_["knn_filter_launches"] for i_ in infos]))
-        kname = "k_knn_filter (bf16 hi/lo split distance sweep, threshold filter)"
+        kname = "k_knn_filter (bf16 hi/lo split distance sweep, symmetric)"
+        alg = float(wl.N) * wl.N * wl.d / launches
     else:
         launches = 1
         sweep_ms = float(np.mean([i_["t_knn_sweep_ms"] for i_ in infos]))
-        kname = ("k_knn_cand_wide (bf16 hi/lo split distance sweep, top-64 lists)" if wl.d > 128
-                 else "k_knn_cand (bf16 hi/lo split distance sweep, top-64 lists)")
-    alg_flops = 2.0 * (wl.N / launches) * wl.N * wl.d        # every row against every point
-    achieved = alg_flops / (sweep_ms * 1e-3) / 1e12
-    roof = {"kernel": kname, "bound": "mfma",
-            "achieved": achieved, "peak": PEAK["bf16"], "unit": "TFLOP/s",
-            "frac": achieved / PEAK["bf16"], "traffic": traffic_of("k_knn_filter") if "filter" in kname else None,
-            "algorithmic_flops_per_launch": alg_flops, "avg_launch_ms": sweep_ms, "launches_per_step": launches,
-            "note": ("algorithmic flops 2 N^2 d per step; each algorithmic product costs 3 bf16 MFMA "
-                     "products (hi*hi, hi*lo, lo*hi)")}
+        kname = "k_knn_cand_wide (bf16 hi/lo split distance sweep)"
+        alg = 2.0 * float(wl.N) * wl.N * wl.d
+    issued = 3.0 * alg
+    t = sweep_ms * 1e-3
+    return {"kernel": kname, "bound": "mfma", "achieved": issued / t / 1e12, "peak": PEAK["bf16"],
+            "unit": "TFLOP/s", "frac": issued / t / 1e12 / PEAK["bf16"],
+            "traffic": traffic_of("k_knn_filter") if "filter" in kname else None,
+            "avg_launch_ms": sweep_ms, "launches_per_step": launches,
+            "algorithmic_flops_per_launch": alg, "mfma_flops_issued_per_launch": issued,
+            "algorithmic_vs_emulated_peak": {"achieved": alg / t / 1e12, "peak": PEAK["bf16"] / 3.0,
+                                             "frac": alg / t / 1e12 / (PEAK["bf16"] / 3.0)},
+            "note": ("flops issued = 3 N^2 d bf16 MFMA flops per setup (each unordered pair once, "
+                     "three products hi*hi, hi*lo, lo*hi) over the launch's HIP-event time")}
+
+
+def cpu_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="fp32_1m", choices=list(WORKLOADS) + ["batched"])
+    ap.add_argument("--eps-targets", type=int, default=10000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the bounded serving leg of the default run")
+    ap.add_argument("--no-listed", action="store_true",
+                    help="skip the run of the workload as listed (h = 1) beside the gated variant")
+    ap.add_argument("--evals", type=int, default=5, help="amortized update+evaluate repetitions")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the request stream")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-workers", type=int, default=2)
+    ap.add_argument("--serve-mem-gib", type=int, default=64)
+    ap.add_argument("--serve-budget-s", type=float, default=20.0, help="GPU work per serving replay")
+    ap.add_argument("--batched-rhs", type=int, default=1)
+    ap.add_argument("--query-points", default=None,
+                    help="new-point batch sizes timed through askit_query on the built handle "
+                         "(default 4096,32768 on the 2^20 x 64 workloads, none elsewhere; '' for none)")
+    ap.add_argument("--set", action="append", default=[], metavar="FIELD=VALUE",
+                    help="change one workload parameter (e.g. h=0.5, smax=128); the line then names it")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"],
+                    help="distance products: FP32, or bf16 hi/lo split products (precision form)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1410_0260_amd import askit as A
+
+    if args.workload == "batched":
+        print(json.dumps(batched_bench(args, A, torch)))
+        return
+    default_run = args.workload == "fp32_1m" and not args.set
+    wl = synth.fp32_1m_gate() if default_run else WORKLOADS[args.workload]()
+    if args.set:
+        import dataclasses
+        ch = {}
+        for kv in args.set:
+            k, v = kv.split("=", 1)
+            ch[k] = type(getattr(wl, k))(v)
+        wl = dataclasses.replace(wl, **ch)
+        wl = dataclasses.replace(wl, name=wl.name + " [" + ", ".join(args.set) + "]")
+    if args.workload == "serving_4m":
+        print(json.dumps(serve_bench(args, wl, A, torch)))
+        return
+    qspec = args.query_points if args.query_points is not None else (
+        "4096,32768" if args.workload == "fp32_1m" else "")
+    r = step_bench(wl, args, A, torch, args.steps, args.warmup, qspec, args.eps_targets)
+    info, infos = r["info"], r["infos"]
+    gate_met = bool(max(r["eps"]) <= 1e-3)
+    far_matters = bool(min(r["eps_near"]) >= 10.0 * max(r["eps"]))
     ev_pairs = info["near_pairs"] + info["far_pairs"]
-    ev_kernel_ms = float(np.median(ev_ms))
+    ev_kernel_ms = float(np.median(r["ev_ms"]))
     ev_flops = ev_pairs * (2.0 * wl.d + 3.0 + 2.0 * wl.R)
-    eval_roof = {"kernel": "k_eval (FP32 MFMA distance + exp + weight contraction)", "bound": "mfma",
+    eval_roof = {"kernel": "k_eval_chunks (FP32 MFMA distance + exp + weight contraction)", "bound": "mfma",
                  "achieved": ev_flops / (ev_kernel_ms * 1e-3) / 1e12, "peak": PEAK["fp32"],
                  "unit": "TFLOP/s", "avg_launch_ms": ev_kernel_ms, "algorithmic_pairs": ev_pairs}
     eval_roof["frac"] = eval_roof["achieved"] / eval_roof["peak"]
-
+    logN = np.log2(max(2.0, wl.N / wl.m))
     out = {
-        "metric": "kernel-sum targets*RHS/s (whole hot path: setup + skeleton weights + evaluation)",
-        "value": wl.N * wl.R / (ms_step * 1e-3),
+        "metric": BASELINE_METRIC if gate_met else BASELINE_METRIC + " [gate NOT met at this workload]",
+        "value": wl.N * wl.R / (r["ms_step"] * 1e-3),
         "unit": "targets*RHS/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "bf16x3 products, f32 accumulation",
         "data": "synthetic",
-        "config": {"workload": wl.name, "N": wl.N, "d": wl.d, "m": wl.m, "kappa": wl.kappa,
-                   "precision": args.precision,
-                   "s_max": wl.smax, "l": wl.ell_eff, "tau": wl.tau, "h": wl.h, "nrhs": wl.R,
+        "config": {"workload": wl.name, "N": wl.N, "d": wl.d, "m": wl.m, "kappa": wl.kappa, "s_max": wl.smax,
+                   "l": wl.ell_eff, "tau": wl.tau, "h": wl.h, "nrhs": wl.R, "precision": args.precision,
+                   "step": "askit_setup + askit_update_weights + askit_evaluate",
                    "parallelism": "single GPU"},
-        "amortized": {"value": wl.N * wl.R / (ms_amort * 1e-3), "ms_update_plus_evaluate": ms_amort,
+        "accuracy_gate": {"target": 1e-3, "eps": max(r["eps"]), "eps_near_only": min(r["eps_near"]),
+                          "met": gate_met, "far_field_carries_weight": far_matters,
+                          "targets_sampled": r["targets"],
+                          "reference": "FP64 direct sum (torch float64) at seeded sampled targets"},
+    }
+    roof = roofline_of(wl, r)
+    out["roofline"] = roof
+    if default_run and not args.no_listed:
+        lw = synth.fp32_1m()
+        lr = step_bench(lw, args, A, torch, min(args.steps, 3), 1, "", args.eps_targets)
+        out["listed_config"] = {
+            "workload": lw.name, "h": lw.h, "ms_per_step": lr["ms_step"],
+            "value": lw.N * lw.R / (lr["ms_step"] * 1e-3), "eps": max(lr["eps"]),
+            "eps_near_only": min(lr["eps_near"]), "gate_met": bool(max(lr["eps"]) <= 1e-3),
+            "amortized_value": lw.N * lw.R / (lr["ms_amort"] * 1e-3),
+            "note": ("the 2^20 x 64 workload at its listed h = 1: the approximation's own error at "
+                     "s <= 256 exceeds 1e-3 (the FP64 oracle of the same approximation has it too)")}
+        del lr
+    if default_run and not args.no_serving:
+        out["serving"] = serve_leg(args, A, torch)
+    out.update({
+        "amortized": {"value": wl.N * wl.R / (r["ms_amort"] * 1e-3), "ms_update_plus_evaluate": r["ms_amort"],
                       "ms_evaluate_kernel": ev_kernel_ms},
-        "phases_ms": {k: float(np.mean([i_[k] for i_ in infos])) for k in
+        "paper_counters": {"eps": r["eps"], "eps_kappa": r["eps_near"], "offdiag_share": r["offdiag"],
+                           "near_pct": 100.0 * info["near_lists"] / wl.N / wl.kappa,
+                           "far_pct": 100.0 * info["far_lists"] / wl.N / (wl.kappa * logN)},
+        "phases_ms": {k: round(float(np.mean([i_[k] for i_ in infos])), 3) for k in
                       ("t_knn_ms", "t_tree_ms", "t_lists_ms", "t_skel_ms", "t_inter_ms", "t_update_ms",
                        "t_knn_sweep_ms", "t_knn_filter_ms", "t_qr_ms")},
-        "eps_vs_fp64_direct": {"per_rhs": eps, "targets_sampled": nt},
-        "accuracy_gate": {"target": 1e-3, "eps_max": max(eps), "met": bool(max(eps) <= 1e-3),
-                          "note": None if max(eps) <= 1e-3 else
-                          "the error of the approximation itself at this workload's h and s_max (the "
-                          "FP64 oracle of the same approximation has it too); a narrower kernel "
-                          "(--set h=...) or a larger s_max lowers it"},
-        "counts": {k: info[k] for k in ("num_nodes", "num_leaves", "depth", "num_slabs", "near_entries",
-                                        "far_entries", "near_pairs", "far_pairs",
-                                        "knn_uncertified_rows", "knn_retry_rows", "eval_pairs", "eval_chunks")},
-        "roofline": roof,
         "roofline_eval": eval_roof,
-        "queries": queries,
-    }
+        "queries": r["queries"],
+        "counts": {k: info[k] for k in ("num_nodes", "num_leaves", "depth", "near_pairs", "far_pairs",
+                                        "knn_uncertified_rows", "knn_retry_rows", "eval_pairs", "eval_chunks")},
+    })
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(wl, X, W)
+        out["cpu_baseline"] = cpu_baseline(wl, r["X"], r["W"])
     print(json.dumps(out))
 
 

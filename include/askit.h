@@ -47,7 +47,8 @@ typedef enum {
     ASKIT_ERR_OUT_OF_MEMORY = 2, /* device allocation failed */
     ASKIT_ERR_DEVICE = 3,        /* no usable gfx950 device, or a HIP call failed */
     ASKIT_ERR_NOT_READY = 4,     /* evaluate before any update_weights */
-    ASKIT_ERR_UNSUPPORTED = 5    /* valid request outside the built limits */
+    ASKIT_ERR_UNSUPPORTED = 5,   /* valid request outside the built limits */
+    ASKIT_ERR_BUSY = 6           /* serving: the request queue is full; submit again later */
 } askit_status;
 
 typedef enum {
@@ -56,7 +57,7 @@ typedef enum {
                               on MFMA with FP32 accumulation */
 } askit_precision;
 
-/* Method parameters (Sec. 4 "Complexity and error", parameter list). */
+/* Method parameters (Sec. 3 "Complexity and error", parameter list). */
 typedef struct {
     uint32_t struct_size;   /* sizeof(askit_params) */
     uint32_t abi_version;   /* ASKIT_ABI_VERSION */
@@ -80,7 +81,7 @@ askit_status askit_params_default(askit_params *p);
 
 /*
  * Builds everything that does not depend on the weights (Alg. 5 lines 1-3):
- * exact kappa-nearest-neighbour lists, the median-split tree (Sec. 3.2), the
+ * exact kappa-nearest-neighbour lists, the median-split tree (Sec. 2.2), the
  * node neighbour lists (Alg. 2), sampled rows (Eq. e:sk_targets), the
  * skeletons and projections P_alpha (Alg. 3), and the interaction lists of
  * the downward pass (Eq. e:prune).
@@ -101,6 +102,22 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx,
                          const askit_params *p, void *stream, askit_handle **out);
 
 /*
+ * askit_setup with the neighbour lists N(X) given by the caller instead of
+ * the exact search: the paper's driver takes N(X) as an input (Alg. 5), and
+ * its neighbours come from an approximate search (Sec. 2.2, "computing
+ * nearest neighbors").  Every later step (tree, node lists, sampling,
+ * skeletons, pruning) is the one askit_setup runs, on these lists.
+ *   knn  device, N x kappa int32 original point ids, row stride ldk >= kappa;
+ *        row i holds kappa distinct ids other than i, in any order.  The
+ *        library computes their canonical FP64 squared distances and keeps
+ *        each row sorted by (distance, id); read only during the call.
+ * ASKIT_ERR_INVALID_ARG as askit_setup, and for an id out of [0, N), the
+ * row's own id, or a repeated id in a row.  Synchronises `stream`.
+ */
+askit_status askit_setup_with_knn(const float *X, int64_t N, int32_t d, int64_t ldx, const int32_t *knn,
+                                  int64_t ldk, const askit_params *p, void *stream, askit_handle **out);
+
+/*
  * Upward pass (Sec. 2.1, Alg. 3): computes the skeleton weights of every
  * node from W (device, N x nrhs FP32, original point order, row stride
  * ldw >= nrhs), 1 <= nrhs <= 64.  Enqueued on `stream`; W must stay valid
@@ -117,6 +134,17 @@ askit_status askit_update_weights(askit_handle *h, const float *W, int64_t ldw, 
 askit_status askit_evaluate(askit_handle *h, float *U, int64_t ldu, void *stream);
 
 /*
+ * askit_evaluate that also returns the near-field part of u: Unear (device,
+ * N x nrhs FP32, row stride ldun >= nrhs, original point order) receives the
+ * direct sums over each point's near leaves alone (Alg. 4, the leaf branch),
+ * whose error against the exact sum is the paper's eps_kappa (Sec. 4).  U is
+ * bit-identical to askit_evaluate's (the near sums are a prefix of the same
+ * summation).  Same conditions and errors as askit_evaluate.
+ */
+askit_status askit_evaluate_parts(askit_handle *h, float *U, int64_t ldu, float *Unear, int64_t ldun,
+                                  void *stream);
+
+/*
  * Evaluation at M new target points Y (device, M x d FP32, row stride ldy)
  * that are not sources (an extension of Alg. 4: a node is pruned for y when
  * it holds none of y's kappa nearest sources).  U (device, M x nrhs FP32,
@@ -128,7 +156,7 @@ askit_status askit_query(askit_handle *h, const float *Y, int64_t M, int64_t ldy
 /*
  * The kappa nearest sources of M new points Y (device, M x d FP32, row
  * stride ldy): the neighbour search that askit_query runs for its targets
- * (Sec. 3.1; Alg. 4 prunes with these lists).  idx (device, M x kappa int32,
+ * (Sec. 2.2; Alg. 4 prunes with these lists).  idx (device, M x kappa int32,
  * row stride kappa) receives original point ids and dist (device, M x kappa
  * FP64, same layout) the squared Euclidean distances, each row in increasing
  * (distance, id) order; the result is exact.  Needs no weights.  1 <= M;
@@ -163,6 +191,9 @@ typedef struct {
     int64_t eval_chunks;                 /* evaluation work items (up to 64 targets of one source node) */
     int64_t knn_retry_rows;              /* rows whose filter output overflowed (filtered again at
                                             sampled thresholds, then list sweeps if that overflows) */
+    int64_t near_lists;                  /* sum over points of |near(i)|: near leaves per point (Alg. 4) */
+    int64_t far_lists;                   /* sum over points of |far(i)|: pruned nodes per point; with
+                                            near_lists, the paper's near and far counters (Sec. 4) */
 } askit_info;
 
 askit_status askit_get_info(const askit_handle *h, askit_info *out);
@@ -209,7 +240,7 @@ askit_status askit_export(const askit_handle *h, int32_t what, void *dst, size_t
  * interaction lists stay in device memory) and answers two kinds of request
  * with continuous batching:
  *   - weights: u = K w at all N points for the request's own weights (the
- *     per-iteration cost that setup amortizes, Sec. 5);
+ *     per-iteration cost that setup amortizes, Sec. 4);
  *   - query:   u at M new points for the resident weights W0.
  * Requests are admitted against a device-memory budget; pending requests of
  * one kind are batched (weight columns side by side, query points stacked)
@@ -275,7 +306,7 @@ void askit_server_destroy(askit_server *s);
  * same parameters) behind one handle, for workloads of many small instances
  * where one launch per instance would leave the device idle.  The work per
  * weight vector (permutation, upward pass, evaluation: the per-iteration cost
- * of Sec. 5 that setup amortizes) runs as a few launches over all instances;
+ * of Sec. 4 that setup amortizes) runs as a few launches over all instances;
  * every instance's result is the one askit_setup/askit_update_weights/
  * askit_evaluate give for it alone (same kernels, same arithmetic).
  *

@@ -11,14 +11,14 @@
  * Kernel-Independent Treecode in High Dimensions" (arXiv 1410.0260).
  *
  *   or_direct       Eq. (e:problem): u_i = sum_j K(x_i, x_j) w_j, FP64.
- *   or_knn          kappa nearest neighbours by exhaustive search (Sec. 3.2,
+ *   or_knn          kappa nearest neighbours by exhaustive search (Sec. 2.2,
  *                   "Computing nearest neighbors"; exact search replaces the
  *                   randomized-tree search, ties broken by point id).
  *   or_bandwidth    per-source bandwidth h_j for the variable-bandwidth
- *                   Gaussian (Sec. 5, "variable bandwidth").
- *   or_tree         median-split binary tree (Sec. 3.2 tree rule, Fig. tree).
+ *                   Gaussian (Sec. 4, "variable bandwidth").
+ *   or_tree         median-split binary tree (Sec. 2.2 tree rule, Fig. tree).
  *   or_node_lists   BuildNeighbors (Alg. 2) with truncation to l by distance
- *                   to the node (Sec. 3.2, "Skeletonization of leaves").
+ *                   to the node (Sec. 2.2, "Skeletonization of leaves").
  *   or_sample_rows  sampled rows T_alpha (Eq. e:sk_targets).
  *   or_gauss_matrix K(T_alpha, C_alpha).
  *   or_id           interpolative decomposition by Householder QR with
@@ -144,7 +144,7 @@ int or_bandwidth(const double *dist, int64_t N, int kappa, int b, double *h)
 }
 
 /* ------------------------------------------------------------------ */
-/* Tree (Sec. 3.2).  Shape depends only on N and m: a node with n > m
+/* Tree (Sec. 2.2).  Shape depends only on N and m: a node with n > m
  * points has children of ceil(n/2) and floor(n/2) points.  Nodes are
  * numbered breadth first, left before right.                          */
 static int64_t count_nodes(int64_t n, int m)
@@ -264,7 +264,7 @@ int or_tree(const float *X, int64_t N, int d, int m, or_node *nodes, int64_t nn_
 }
 
 /* ------------------------------------------------------------------ */
-/* BuildNeighbors (Alg. 2) with truncation to l nearest (Sec. 3.2).
+/* BuildNeighbors (Alg. 2) with truncation to l nearest (Sec. 2.2).
  * Leaf: N_alpha = (union of N_i, i in alpha) minus alpha, key(j) = min
  * D(x_i, x_j).  Internal: union of the children's stored (truncated)
  * lists minus alpha, key = min of the children's keys.  Sorted by

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libaskit.so")
 
-OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_READY, ERR_UNSUPPORTED = range(6)
+OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_READY, ERR_UNSUPPORTED, ERR_BUSY = range(7)
 PREC_FP32, PREC_BF16X3 = 0, 1
 ABI_VERSION = 1
 
@@ -48,7 +48,8 @@ class Info(C.Structure):
                 ("t_inter_ms", C.c_double), ("t_update_ms", C.c_double),
                 ("t_knn_sweep_ms", C.c_double), ("t_qr_ms", C.c_double),
                 ("t_knn_filter_ms", C.c_double), ("knn_filter_launches", C.c_int64),
-                ("eval_pairs", C.c_int64), ("eval_chunks", C.c_int64), ("knn_retry_rows", C.c_int64)]
+                ("eval_pairs", C.c_int64), ("eval_chunks", C.c_int64), ("knn_retry_rows", C.c_int64),
+                ("near_lists", C.c_int64), ("far_lists", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -62,8 +63,8 @@ class AskitError(RuntimeError):
 
 _lib = None
 
-EXPORTED = ["askit_params_default", "askit_setup", "askit_update_weights", "askit_evaluate",
-            "askit_query", "askit_query_neighbors", "askit_destroy", "askit_last_error", "askit_get_info",
+EXPORTED = ["askit_params_default", "askit_setup", "askit_setup_with_knn", "askit_update_weights",
+            "askit_evaluate", "askit_evaluate_parts", "askit_query", "askit_query_neighbors", "askit_destroy", "askit_last_error", "askit_get_info",
             "askit_export"]
 
 
@@ -78,7 +79,9 @@ def lib():
         L.askit_params_default.argtypes = [C.POINTER(Params)]
         L.askit_setup.argtypes = [P, i64, i32, i64, C.POINTER(Params), P, C.POINTER(P)]
         L.askit_update_weights.argtypes = [P, P, i64, i32, P]
+        L.askit_setup_with_knn.argtypes = [P, i64, i32, i64, P, i64, C.POINTER(Params), P, C.POINTER(P)]
         L.askit_evaluate.argtypes = [P, P, i64, P]
+        L.askit_evaluate_parts.argtypes = [P, P, i64, P, i64, P]
         L.askit_query.argtypes = [P, P, i64, i64, P, i64, P]
         L.askit_query_neighbors.argtypes = [P, P, i64, i64, P, P, P]
         L.askit_destroy.argtypes = [P]
@@ -146,6 +149,15 @@ class Handle:
                                                      dtype=torch.float32)
         _check(lib().askit_evaluate(self.ptr, C.c_void_p(U.data_ptr()), U.stride(0), _stream(torch)))
         return U
+
+    def evaluate_parts(self):
+        """(u, near-field part of u) at every point."""
+        import torch
+        U = torch.empty((self.N, self.nrhs), device="cuda", dtype=torch.float32)
+        Un = torch.empty((self.N, self.nrhs), device="cuda", dtype=torch.float32)
+        _check(lib().askit_evaluate_parts(self.ptr, C.c_void_p(U.data_ptr()), U.stride(0),
+                                          C.c_void_p(Un.data_ptr()), Un.stride(0), _stream(torch)))
+        return U, Un
 
     def query(self, Y, out=None):
         import torch
@@ -235,6 +247,21 @@ def setup(X, params: Params) -> Handle:
     h = C.c_void_p()
     rc = lib().askit_setup(C.c_void_p(Xd.data_ptr()), N, d, Xd.stride(0), C.byref(params),
                            _stream(torch), C.byref(h))
+    _check(rc)
+    return Handle(h, N, d)
+
+
+def setup_with_knn(X, knn, params: Params) -> Handle:
+    """askit_setup with given neighbour lists (N x kappa original ids)."""
+    import torch
+    Xd = _dev_f32(torch, X)
+    N, d = Xd.shape
+    K = knn if torch.is_tensor(knn) else torch.from_numpy(np.ascontiguousarray(knn, dtype=np.int32))
+    K = K.to(device="cuda", dtype=torch.int32).contiguous()
+    assert K.shape[0] == N
+    h = C.c_void_p()
+    rc = lib().askit_setup_with_knn(C.c_void_p(Xd.data_ptr()), N, d, Xd.stride(0), C.c_void_p(K.data_ptr()),
+                                    K.stride(0), C.byref(params), _stream(torch), C.byref(h))
     _check(rc)
     return Handle(h, N, d)
 

@@ -88,6 +88,46 @@ __global__ void k_map_pos(const int32_t *__restrict__ ids, int64_t n, const int3
     if (i < n) out[i] = iperm[ids[i]];
 }
 
+// Neighbour lists given by the caller (ASKIT takes N(X) as an input, Alg. 5):
+// per row, validate the kappa ids (in range, not the row itself, distinct),
+// compute their canonical FP64 squared distances and store the row sorted by
+// (distance, id).  Xo holds the points in original order (stride dp).
+__global__ void k_knn_import(const int32_t *__restrict__ in, int64_t ldk, int64_t N, int kappa,
+                             const float *__restrict__ Xo, int dp, int d, int32_t *__restrict__ idx,
+                             double *__restrict__ dist, int32_t *__restrict__ bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int32_t li[64];
+    double ld[64];
+    bool ok = true;
+    for (int t = 0; t < kappa; ++t) {
+        const int32_t j = in[i * ldk + t];
+        if (j < 0 || j >= N || j == i) {
+            ok = false;
+            li[t] = 0;
+            ld[t] = 0.0;
+            continue;
+        }
+        const double D = canon_sqdist(Xo + i * dp, Xo + (int64_t)j * dp, d);
+        int q = t;
+        while (q > 0 && (ld[q - 1] > D || (ld[q - 1] == D && li[q - 1] > j))) {
+            ld[q] = ld[q - 1];
+            li[q] = li[q - 1];
+            --q;
+        }
+        ld[q] = D;
+        li[q] = j;
+    }
+    for (int t = 1; t < kappa && ok; ++t)
+        if (li[t] == li[t - 1]) ok = false;
+    if (!ok) atomicOr(bad, 1);
+    for (int t = 0; t < kappa; ++t) {
+        idx[i * kappa + t] = li[t];
+        dist[i * kappa + t] = ld[t];
+    }
+}
+
 void permute_rows(const float *W, int64_t ldw, const int32_t *gperm, int64_t rows, int R, float *Wt,
                   hipStream_t s)
 {
@@ -304,10 +344,13 @@ askit_status askit_params_default(askit_params *p)
 
 const char *askit_last_error(void) { return g_err.c_str(); }
 
-askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, const askit_params *p,
-                         void *stream, askit_handle **out)
+}  // extern "C"
+
+// Alg. 5 setup steps; knn_in (device, N x kappa original ids, row stride ldk)
+// replaces the exact neighbour search when given.
+static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const int32_t *knn_in, int64_t ldk,
+                       const askit_params *p, void *stream, askit_handle **out)
 {
-    API_BEGIN
     if (!out) fail(ASKIT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!p || !X) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
@@ -328,6 +371,7 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
     if (p->precision != ASKIT_PREC_FP32 && p->precision != ASKIT_PREC_BF16X3)
         fail(ASKIT_ERR_INVALID_ARG, "unknown precision");
     if (d > 1024) fail(ASKIT_ERR_UNSUPPORTED, "d above 1024 is not supported");
+    if (knn_in && ldk < p->kappa) fail(ASKIT_ERR_INVALID_ARG, "need ldk >= kappa");
     check_device();
     hipStream_t s = (hipStream_t)stream;
 
@@ -414,7 +458,16 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
     knn_build_sample(h.get(), s);
     float mx = max_norm(h->Xn, N, s);
     h->maxnorm = mx;
-    {
+    if (knn_in) {
+        HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+        hipLaunchKernelGGL(k_knn_import, dim3((unsigned)((N + 127) / 128)), dim3(128), 0, s, knn_in, ldk, N, kappa,
+                           h->Xo, dp, d, h->knn_idx, h->knn_d, flag);
+        HIPC(hipGetLastError());
+        HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        if (hflag)
+            fail(ASKIT_ERR_INVALID_ARG, "neighbour lists hold an id out of range, the row's own id or a repeated id");
+    } else {
         int32_t *cand, *bad;
         float *thr;
         HIPC(hipMallocAsync((void **)&cand, sizeof(int32_t) * N * KNN_CAND, s));
@@ -528,6 +581,24 @@ askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, cons
     HIPC(hipEventElapsedTime(&ms, ev[3], ev[4])); h->t_skel = ms;
     h->t_inter = ms_inter;                 // on the second stream, overlapped with the above
     *out = h.release();
+}
+
+extern "C" {
+
+askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx, const askit_params *p,
+                         void *stream, askit_handle **out)
+{
+    API_BEGIN
+    setup_impl(X, N, d, ldx, nullptr, 0, p, stream, out);
+    API_END
+}
+
+askit_status askit_setup_with_knn(const float *X, int64_t N, int32_t d, int64_t ldx, const int32_t *knn,
+                                  int64_t ldk, const askit_params *p, void *stream, askit_handle **out)
+{
+    API_BEGIN
+    if (!knn) fail(ASKIT_ERR_INVALID_ARG, "knn is NULL");
+    setup_impl(X, N, d, ldx, knn, ldk, p, stream, out);
     API_END
 }
 
@@ -571,6 +642,16 @@ askit_status askit_evaluate(askit_handle *h, float *U, int64_t ldu, void *stream
     if (h->ws.R < 1) fail(ASKIT_ERR_NOT_READY, "askit_update_weights has not been called");
     if (ldu < h->ws.R) fail(ASKIT_ERR_INVALID_ARG, "need ldu >= nrhs");
     evaluate(h, h->ws, h->Xt, h->pairs, h->perm, U, ldu, h->ws.part, (hipStream_t)stream);
+    API_END
+}
+
+askit_status askit_evaluate_parts(askit_handle *h, float *U, int64_t ldu, float *Unear, int64_t ldun, void *stream)
+{
+    API_BEGIN
+    if (!h || !U || !Unear) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    if (h->ws.R < 1) fail(ASKIT_ERR_NOT_READY, "askit_update_weights has not been called");
+    if (ldu < h->ws.R || ldun < h->ws.R) fail(ASKIT_ERR_INVALID_ARG, "need ldu >= nrhs and ldun >= nrhs");
+    evaluate(h, h->ws, h->Xt, h->pairs, h->perm, U, ldu, h->ws.part, (hipStream_t)stream, Unear, ldun);
     API_END
 }
 
@@ -662,6 +743,8 @@ askit_status askit_get_info(const askit_handle *h, askit_info *o)
     o->eval_chunks = h->pairs.nchunk;
     o->knn_retry_rows = h->knn_retry_rows;
     o->t_qr_ms = h->t_qr;
+    o->near_lists = h->pairs.near_lists;
+    o->far_lists = h->pairs.far_lists;
     API_END
 }
 

@@ -130,7 +130,9 @@ struct PairLists {
     int32_t *tpos = nullptr;   // target row of each pair
     int32_t *tslot = nullptr;  // partial-sum slot of each pair
     int32_t *sbase = nullptr;  // ntarget + 1: first slot of each target (slots of a target are contiguous)
+    int32_t *snear = nullptr;  // ntarget: first far slot of each target (its near slots come first)
     Chunk *chunks = nullptr;
+    int64_t near_lists = 0, far_lists = 0;   // sum over targets of |near(i)| and |far(i)|
 };
 
 // Strided samples of the tree-ordered points for neighbour searches of new
@@ -293,7 +295,8 @@ void build_pairs(const askit_handle *h, const Slab *d_slabs, int64_t nslab, int6
 // pair slot into part (>= npairs x R floats), then per-target sums into
 // U[outmap[i]] (identity when NULL).
 void evaluate(const askit_handle *h, const WeightSet &ws, const float *Y, const PairLists &L,
-              const int32_t *outmap, float *U, int64_t ldu, float *part, hipStream_t s);
+              const int32_t *outmap, float *U, int64_t ldu, float *part, hipStream_t s,
+              float *Unear = nullptr, int64_t ldun = 0);
 
 // ---------------------------------------------------------------- batched form
 // One entry per instance of a batch (device tables).  Weights of all

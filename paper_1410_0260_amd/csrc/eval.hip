@@ -314,17 +314,25 @@ __global__ __launch_bounds__(EV_T) void k_eval_chunks(ChunkParams p)
     }
 }
 
-// u[i, r] = sum of target i's slots, in slot order.
+// u[i, r] = sum of target i's slots, in slot order.  Its near slots come
+// first, so the running sum after them is the near-field part of u (the
+// direct sums over the near leaves alone), written to Unear when given.
 __global__ void k_sum_slots(const int32_t *__restrict__ sbase, int64_t ntarget, const float *__restrict__ part,
-                            int R, const int32_t *__restrict__ outmap, float *__restrict__ U, int64_t ldu)
+                            int R, const int32_t *__restrict__ outmap, float *__restrict__ U, int64_t ldu,
+                            const int32_t *__restrict__ snear, float *__restrict__ Unear, int64_t ldun)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = t / R;
     if (i >= ntarget) return;
     const int r = (int)(t - i * R);
-    float u = 0.0f;
-    for (int sl = sbase[i]; sl < sbase[i + 1]; ++sl) u += part[(int64_t)sl * R + r];
     const int64_t o = outmap ? outmap[i] : i;
+    float u = 0.0f;
+    int sl = sbase[i];
+    if (Unear) {
+        for (; sl < snear[i]; ++sl) u += part[(int64_t)sl * R + r];
+        Unear[o * ldun + r] = u;
+    }
+    for (; sl < sbase[i + 1]; ++sl) u += part[(int64_t)sl * R + r];
     U[o * ldu + r] = u;
 }
 
@@ -363,7 +371,8 @@ static void launch_passes(ChunkParams p, bool bf, int R, int64_t grid, int32_t *
 }
 
 void evaluate(const askit_handle *h, const WeightSet &ws, const float *Y, const PairLists &L,
-              const int32_t *outmap, float *U, int64_t ldu, float *part, hipStream_t s)
+              const int32_t *outmap, float *U, int64_t ldu, float *part, hipStream_t s, float *Unear,
+              int64_t ldun)
 {
     if (h->dp > 1024) fail(ASKIT_ERR_UNSUPPORTED, "dimension above 1024 is not supported");
     if (L.ntarget == 0) return;
@@ -390,7 +399,7 @@ void evaluate(const askit_handle *h, const WeightSet &ws, const float *Y, const 
     }
     const int64_t tot = L.ntarget * ws.R;
     hipLaunchKernelGGL(k_sum_slots, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L.sbase, L.ntarget, part,
-                       ws.R, outmap, U, ldu);
+                       ws.R, outmap, U, ldu, L.snear, Unear, ldun);
     HIPC(hipGetLastError());
 }
 
@@ -414,7 +423,7 @@ void evaluate_batch(const BatchEvalArgs &b, hipStream_t s)
     }
     const int64_t tot = b.rows * b.R;
     hipLaunchKernelGGL(k_sum_slots, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.sbase, b.rows, b.part,
-                       b.R, b.outrow, b.U, b.ldu);
+                       b.R, b.outrow, b.U, b.ldu, (const int32_t *)nullptr, (float *)nullptr, (int64_t)0);
     HIPC(hipGetLastError());
 }
 

@@ -68,7 +68,8 @@ __global__ __launch_bounds__(64) void k_pair_fill(const Slab *__restrict__ slabs
                                                   const uint64_t *__restrict__ mask,
                                                   const int32_t *__restrict__ off_e,
                                                   const int32_t *__restrict__ sbase,
-                                                  int32_t *__restrict__ tpos, int32_t *__restrict__ tslot)
+                                                  int32_t *__restrict__ tpos, int32_t *__restrict__ tslot,
+                                                  int32_t *__restrict__ snear)
 {
     const int64_t s = blockIdx.x;
     const int b = threadIdx.x;
@@ -88,6 +89,7 @@ __global__ __launch_bounds__(64) void k_pair_fill(const Slab *__restrict__ slabs
                 ++r;
             }
         }
+        if (part == 0) snear[sb.row0 + b] = base + r;
     }
 }
 
@@ -113,6 +115,7 @@ void build_pairs(const askit_handle *h, const Slab *d_slabs, int64_t nslab, int6
     int32_t *cnt = (int32_t *)ta(sizeof(int32_t) * nkey);
     HIPC(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nkey, s));
     L.sbase = (int32_t *)al(sizeof(int32_t) * (ntarget + 1));
+    L.snear = (int32_t *)al(sizeof(int32_t) * std::max<int64_t>(ntarget, 1));
     int32_t *cnt_t = (int32_t *)ta(sizeof(int32_t) * (ntarget + 1));
     HIPC(hipMemsetAsync(cnt_t, 0, sizeof(int32_t) * (ntarget + 1), s));
     if (nslab > 0)
@@ -153,7 +156,9 @@ void build_pairs(const askit_handle *h, const Slab *d_slabs, int64_t nslab, int6
     HIPC(hipStreamSynchronize(s));
     int64_t npairs = 0;
     std::vector<Chunk> chunks;
+    L.near_lists = L.far_lists = 0;
     for (int64_t k = 0; k < nkey; ++k) {
+        (k & 1 ? L.far_lists : L.near_lists) += hc[k];
         for (int64_t j = 0; j < hc[k]; j += 64)
             chunks.push_back(Chunk{(int32_t)(k >> 1), (int32_t)(k & 1), (int32_t)(npairs + j),
                                    (int32_t)std::min<int64_t>(64, hc[k] - j)});
@@ -169,7 +174,7 @@ void build_pairs(const askit_handle *h, const Slab *d_slabs, int64_t nslab, int6
         HIPC(hipMemcpyAsync(L.chunks, chunks.data(), sizeof(Chunk) * L.nchunk, hipMemcpyHostToDevice, s));
     if (nslab > 0 && npairs > 0)
         hipLaunchKernelGGL(k_pair_fill, dim3((unsigned)nslab), dim3(64), 0, s, d_slabs, nslab, ptr, mask, off_e,
-                           L.sbase, L.tpos, L.tslot);
+                           L.sbase, L.tpos, L.tslot, L.snear);
     HIPC(hipGetLastError());
     HIPC(hipStreamSynchronize(s));          // the chunk table's host copy is released on return
 }

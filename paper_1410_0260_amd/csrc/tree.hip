@@ -1,4 +1,4 @@
-// Median-split binary tree on the GPU (Sec. 3.2, Fig. "The tree").
+// Median-split binary tree on the GPU (Sec. 2.2, Fig. "The tree").
 //
 // A node with n > m points is split by: centre c (mean), x_l = the point
 // farthest from c, x_r = the point farthest from x_l, projection p_i =

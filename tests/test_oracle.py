@@ -3,7 +3,7 @@
 Each check is independent of the oracle's own code path: textbook
 definitions evaluated another way (numpy / scipy / pure Python sets),
 exact special cases in which ASKIT reduces to the direct sum, invariants
-the paper states (Sec. 4 bounds on near/far counts), and published test
+the paper states (Sec. 3 bounds on near/far counts), and published test
 vectors.  None of these tests needs a GPU.
 """
 import dataclasses as dc
@@ -82,7 +82,7 @@ def test_bandwidth_is_distance_to_bth_neighbour():
     assert np.allclose(h, np.sqrt(D[:, 16]), rtol=1e-12)   # column 0 is the point itself
 
 
-# ------------------------------------------------------------ tree (Sec. 3.2)
+# ------------------------------------------------------------ tree (Sec. 2.2)
 @pytest.mark.parametrize("N,m", [(1000, 32), (777, 50), (64, 64), (129, 64), (4096, 128)])
 def test_tree_invariants(N, m):
     X = small(N)
@@ -105,7 +105,7 @@ def test_tree_invariants(N, m):
         assert L["path"] == nd["path"] << 1 and R["path"] == (nd["path"] << 1) | 1
         assert L["level"] == nd["level"] + 1 and L["parent"] == a
         ids = perm[nd["lo"]:nd["hi"]]
-        # the split is a median split along the line (x_l, x_r) of Sec. 3.2
+        # the split is a median split along the line (x_l, x_r) of Sec. 2.2
         P = X64[ids]
         c = P.mean(0)
         l = ids[np.argmax(((P - c) ** 2).sum(1))]
@@ -324,7 +324,7 @@ def test_variable_bandwidth_exact_case():
 
 def test_partition_and_count_bounds():
     """Near leaves and pruned nodes of every target partition the sources
-    exactly once; |near| <= kappa + 1 and |far| <= (kappa + 1) * depth (Sec. 4)."""
+    exactly once; |near| <= kappa + 1 and |far| <= (kappa + 1) * depth (Sec. 3)."""
     N = 1500
     X = small(N)
     W = synth.weights(N, 1, 5)
