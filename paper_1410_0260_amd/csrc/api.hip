@@ -180,7 +180,7 @@ static void query_knn(askit_handle *h, const float *Y, int64_t M, int64_t ldy, f
 }
 
 void query_points(askit_handle *h, const WeightSet &ws, const float *Y, int64_t M, int64_t ldy, float *U,
-                  int64_t ldu, hipStream_t s)
+                  int64_t ldu, hipStream_t s, const std::vector<int64_t> *segs)
 {
     const int dp = h->dp, kappa = h->kappa;
     std::vector<void *> tmp;
@@ -206,15 +206,31 @@ void query_points(askit_handle *h, const WeightSet &ws, const float *Y, int64_t 
     hipLaunchKernelGGL(k_map_pos, dim3((unsigned)((M * kappa + 255) / 256)), dim3(256), 0, s, qidx,
                        M * kappa, h->iperm, nb);
     HIPC(hipGetLastError());
-    sort_queries(h, nb, M, order, nbs, tmp, s);
+    // requests of a served batch are kept apart: each sorts, forms slabs and
+    // chunks among its own points only, so its result is the one it gets alone
+    const int64_t nseg = segs ? (int64_t)segs->size() : 1;
+    int32_t *dseg = nullptr;
+    if (nseg > 1) {
+        if ((uint64_t)nseg * (uint64_t)h->nodes.size() >= (1ull << 32))
+            fail(ASKIT_ERR_UNSUPPORTED, "too many requests in one query batch");
+        std::vector<int32_t> hseg;
+        hseg.reserve(M);
+        for (int64_t sg = 0; sg < nseg; ++sg) hseg.insert(hseg.end(), (size_t)(*segs)[sg], (int32_t)sg);
+        if ((int64_t)hseg.size() != M) fail(ASKIT_ERR_INVALID_ARG, "query segments do not add up to the query count");
+        dseg = (int32_t *)ta(sizeof(int32_t) * M);
+        HIPC(hipMemcpyAsync(dseg, hseg.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, s));
+        HIPC(hipStreamSynchronize(s));         // hseg is released on return of this block
+    }
+    sort_queries(h, nb, M, order, nbs, tmp, s, dseg);
     gather_rows(Yp, order, M, dp, Ys, s);
     int32_t *ptr, *node;
     uint64_t *mask;
     Slab *qslabs;
-    int64_t nen, nef;
-    build_query_interactions(h, nbs, M, qslabs, ptr, node, mask, nen, nef, tmp, s);
+    int64_t nen, nef, nqslab = 0;
+    build_query_interactions(h, nbs, M, qslabs, ptr, node, mask, nen, nef, tmp, s, nseg > 1 ? segs : nullptr,
+                             nqslab);
     PairLists L;
-    build_pairs(h, qslabs, (M + SLAB - 1) / SLAB, M, ptr, node, mask, nen, nef, L, ta, s);
+    build_pairs(h, qslabs, nqslab, M, ptr, node, mask, nen, nef, L, ta, s, nseg);
     float *part = (float *)ta(sizeof(float) * std::max<int64_t>(L.npairs, 1) * ws.R);
     evaluate(h, ws, Ys, L, order, U, ldu, part, s);
     HIPC(hipStreamSynchronize(s));

@@ -268,15 +268,20 @@ void build_interactions(askit_handle *h, hipStream_t s);
 // algorithmic (target, source) pair counts of one evaluation (needs the skeleton sizes)
 void count_pairs(askit_handle *h, hipStream_t s);
 // query lists: nb is M x kappa neighbour positions; slabs of consecutive queries
+// query lists: nb is M x kappa neighbour positions (sorted queries); slabs of
+// consecutive queries that stay within one segment (segs: segment lengths,
+// NULL = one segment); nslab receives their number
 void build_query_interactions(askit_handle *h, const int32_t *nb, int64_t M, Slab *&slabs,
                               int32_t *&ptr, int32_t *&node, uint64_t *&mask, int64_t &ne_near,
-                              int64_t &ne_far, std::vector<void *> &tmp, hipStream_t s);
+                              int64_t &ne_far, std::vector<void *> &tmp, hipStream_t s,
+                              const std::vector<int64_t> *segs, int64_t &nslab);
 
 void gather_f64(const double *src, const int32_t *idx, int64_t n, double *dst, hipStream_t s);
 
-// queries sorted by (leaf of the nearest source, index): order[M], nb rows permuted
+// queries sorted by (segment, leaf of the nearest source, index): order[M],
+// nb rows permuted; seg (device, M) gives each query's segment (NULL: one)
 void sort_queries(askit_handle *h, const int32_t *nb, int64_t M, int32_t *order, int32_t *nb_sorted,
-                  std::vector<void *> &tmp, hipStream_t s);
+                  std::vector<void *> &tmp, hipStream_t s, const int32_t *seg = nullptr);
 
 // skel.hip
 void skeletonize(askit_handle *h, hipStream_t s);
@@ -288,9 +293,12 @@ void permute_weights(askit_handle *h, const float *W, int64_t ldw, WeightSet &ws
 // Pair lists of the targets described by slab lists (ptr: near offsets
 // [0..nslab], far offsets [nslab+1 .. 2 nslab + 1] into node/mask); `al`
 // allocates the outputs (persistent or temporary).
+// With nseg > 1 the slabs carry their segment in `pad`, and no chunk mixes
+// targets of two segments (a served request's result then does not depend on
+// the requests batched with it).
 void build_pairs(const askit_handle *h, const Slab *d_slabs, int64_t nslab, int64_t ntarget, const int32_t *ptr,
                  const int32_t *node, const uint64_t *mask, int64_t ne_near, int64_t ne_far, PairLists &L,
-                 const std::function<void *(size_t)> &al, hipStream_t s);
+                 const std::function<void *(size_t)> &al, hipStream_t s, int64_t nseg = 1);
 // u at the targets Y (rows of stride dp) for the weights ws: partial sums per
 // pair slot into part (>= npairs x R floats), then per-target sums into
 // U[outmap[i]] (identity when NULL).
@@ -341,8 +349,9 @@ void upward_batch(const UpInst *inst, const int2 *items, const std::vector<std::
 // Wt[t, r] = W[gperm[t], r] over all rows of a batch (gperm: original row of tree row t).
 void permute_rows(const float *W, int64_t ldw, const int32_t *gperm, int64_t rows, int R, float *Wt,
                   hipStream_t s);
-// queries at M new points against the weights ws (U: M x ws.R, row stride ldu)
+// queries at M new points against the weights ws (U: M x ws.R, row stride ldu);
+// segs: lengths of consecutive independent requests (NULL = one)
 void query_points(askit_handle *h, const WeightSet &ws, const float *Y, int64_t M, int64_t ldy,
-                  float *U, int64_t ldu, hipStream_t s);
+                  float *U, int64_t ldu, hipStream_t s, const std::vector<int64_t> *segs = nullptr);
 
 }  // namespace askit

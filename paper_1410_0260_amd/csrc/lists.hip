@@ -587,12 +587,20 @@ void count_pairs(askit_handle *h, hipStream_t s)
 
 // ---- query grouping: sort queries by (leaf of their nearest source, index) so
 // that a slab holds spatially close targets (denser masks, small centred norms).
+// Sort key of query i: (its segment, the leaf of its nearest source, i); a
+// segment is one request of a served batch (seg NULL: one segment).
 __global__ void k_qkeys(const int32_t *__restrict__ nb, int64_t M, int kappa,
-                        const int32_t *__restrict__ leaf_of, int64_t M2, uint64_t *__restrict__ key)
+                        const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ seg, int64_t nn,
+                        int64_t M2, uint64_t *__restrict__ key)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M2) return;
-    key[i] = i < M ? (((uint64_t)(uint32_t)leaf_of[nb[i * kappa]] << 32) | (uint64_t)i) : ~0ull;
+    if (i >= M) {
+        key[i] = ~0ull;
+        return;
+    }
+    const uint64_t hi = (uint64_t)(uint32_t)leaf_of[nb[i * kappa]] + (seg ? (uint64_t)seg[i] * (uint64_t)nn : 0ull);
+    key[i] = (hi << 32) | (uint64_t)i;
 }
 
 __global__ void k_bitonic_step(uint64_t *__restrict__ key, int64_t M2, int64_t j, int64_t k)
@@ -625,7 +633,7 @@ __global__ void k_gather_i32_rows(const int32_t *__restrict__ src, const int32_t
 }
 
 void sort_queries(askit_handle *h, const int32_t *nb, int64_t M, int32_t *order, int32_t *nb_sorted,
-                  std::vector<void *> &tmp, hipStream_t s)
+                  std::vector<void *> &tmp, hipStream_t s, const int32_t *seg)
 {
     int64_t M2 = 1;
     while (M2 < M) M2 <<= 1;
@@ -633,7 +641,7 @@ void sort_queries(askit_handle *h, const int32_t *nb, int64_t M, int32_t *order,
     HIPC(hipMallocAsync((void **)&key, sizeof(uint64_t) * M2, s));
     tmp.push_back(key);
     hipLaunchKernelGGL(k_qkeys, dim3((unsigned)((M2 + 255) / 256)), dim3(256), 0, s, nb, M, h->kappa,
-                       h->leaf_of, M2, key);
+                       h->leaf_of, seg, (int64_t)h->nodes.size(), M2, key);
     for (int64_t k = 2; k <= M2; k <<= 1)
         for (int64_t j = k >> 1; j > 0; j >>= 1)
             hipLaunchKernelGGL(k_bitonic_step, dim3((unsigned)((M2 / 2 + 255) / 256)), dim3(256), 0, s,
@@ -647,12 +655,22 @@ void sort_queries(askit_handle *h, const int32_t *nb, int64_t M, int32_t *order,
 
 void build_query_interactions(askit_handle *h, const int32_t *nb, int64_t M, Slab *&slabs,
                               int32_t *&ptr, int32_t *&node, uint64_t *&mask, int64_t &ne_near,
-                              int64_t &ne_far, std::vector<void *> &tmp, hipStream_t s)
+                              int64_t &ne_far, std::vector<void *> &tmp, hipStream_t s,
+                              const std::vector<int64_t> *segs, int64_t &nslab)
 {
-    int64_t nslab = (M + SLAB - 1) / SLAB;
-    std::vector<Slab> hs(nslab);
-    for (int64_t i = 0; i < nslab; ++i)
-        hs[i] = Slab{(int32_t)(i * SLAB), (int32_t)std::min<int64_t>(SLAB, M - i * SLAB), -1, 0};
+    // slabs of SLAB consecutive (sorted) queries that never cross a segment;
+    // each slab carries its segment in `pad`
+    std::vector<Slab> hs;
+    int64_t r0 = 0;
+    const int64_t nseg = segs ? (int64_t)segs->size() : 1;
+    for (int64_t sg = 0; sg < nseg; ++sg) {
+        const int64_t len = segs ? (*segs)[sg] : M;
+        for (int64_t i = 0; i < len; i += SLAB)
+            hs.push_back(Slab{(int32_t)(r0 + i), (int32_t)std::min<int64_t>(SLAB, len - i), -1, (int32_t)sg});
+        r0 += len;
+    }
+    if (r0 != M) fail(ASKIT_ERR_INVALID_ARG, "query segments do not add up to the query count");
+    nslab = (int64_t)hs.size();
     Slab *ds;
     HIPC(hipMallocAsync((void **)&ds, sizeof(Slab) * nslab, s));
     tmp.push_back(ds);

@@ -17,13 +17,23 @@
 
 namespace askit {
 
+// Segment of every list entry: the segment of its slab (`pad`).
+__global__ void k_entry_seg(const Slab *__restrict__ slabs, int64_t nslab, const int32_t *__restrict__ ptr,
+                            int32_t *__restrict__ eseg)
+{
+    const int64_t s = blockIdx.x;
+    const int32_t sg = slabs[s].pad;
+    for (int e = ptr[s] + threadIdx.x; e < ptr[s + 1]; e += blockDim.x) eseg[e] = sg;
+    for (int e = ptr[nslab + 1 + s] + threadIdx.x; e < ptr[nslab + 2 + s]; e += blockDim.x) eseg[e] = sg;
+}
+
 __global__ void k_pair_keys(const int32_t *__restrict__ node, const uint64_t *__restrict__ mask,
-                            int64_t ne_near, int64_t ne, uint32_t *__restrict__ key,
-                            int32_t *__restrict__ idx, int32_t *__restrict__ cnt)
+                            int64_t ne_near, int64_t ne, const int32_t *__restrict__ eseg, int64_t nn,
+                            uint32_t *__restrict__ key, int32_t *__restrict__ idx, int32_t *__restrict__ cnt)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
-    const uint32_t k = (uint32_t)node[e] * 2u + (e >= ne_near ? 1u : 0u);
+    const uint32_t k = (uint32_t)((eseg ? (int64_t)eseg[e] * nn : 0) + node[e]) * 2u + (e >= ne_near ? 1u : 0u);
     key[e] = k;
     idx[e] = (int32_t)e;
     atomicAdd(&cnt[k], __popcll(mask[e]));      // integer counts: order-independent
@@ -95,10 +105,12 @@ __global__ __launch_bounds__(64) void k_pair_fill(const Slab *__restrict__ slabs
 
 void build_pairs(const askit_handle *h, const Slab *d_slabs, int64_t nslab, int64_t ntarget, const int32_t *ptr,
                  const int32_t *node, const uint64_t *mask, int64_t ne_near, int64_t ne_far, PairLists &L,
-                 const std::function<void *(size_t)> &al, hipStream_t s)
+                 const std::function<void *(size_t)> &al, hipStream_t s, int64_t nseg)
 {
     const int64_t ne = ne_near + ne_far;
-    const int64_t nkey = 2 * (int64_t)h->nodes.size();
+    const int64_t nn = (int64_t)h->nodes.size();
+    if (nseg < 1 || nseg * 2 * nn >= (1ll << 31)) fail(ASKIT_ERR_UNSUPPORTED, "too many segments in one batch");
+    const int64_t nkey = 2 * nn * nseg;
     L.ntarget = ntarget;
     std::vector<void *> tmp;
     auto ta = [&](size_t b) {
@@ -133,7 +145,13 @@ void build_pairs(const askit_handle *h, const Slab *d_slabs, int64_t nslab, int6
         int32_t *idx = (int32_t *)ta(sizeof(int32_t) * ne), *idx_s = (int32_t *)ta(sizeof(int32_t) * ne);
         int32_t *pc = (int32_t *)ta(sizeof(int32_t) * ne), *off_s = (int32_t *)ta(sizeof(int32_t) * ne);
         const unsigned g = (unsigned)((ne + 255) / 256);
-        hipLaunchKernelGGL(k_pair_keys, dim3(g), dim3(256), 0, s, node, mask, ne_near, ne, key, idx, cnt);
+        int32_t *eseg = nullptr;
+        if (nseg > 1) {
+            eseg = (int32_t *)ta(sizeof(int32_t) * ne);
+            hipLaunchKernelGGL(k_entry_seg, dim3((unsigned)nslab), dim3(64), 0, s, d_slabs, nslab, ptr, eseg);
+            HIPC(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_pair_keys, dim3(g), dim3(256), 0, s, node, mask, ne_near, ne, eseg, nn, key, idx, cnt);
         HIPC(hipGetLastError());
         int bits = 1;
         while (((int64_t)1 << bits) < nkey) ++bits;
@@ -160,7 +178,7 @@ void build_pairs(const askit_handle *h, const Slab *d_slabs, int64_t nslab, int6
     for (int64_t k = 0; k < nkey; ++k) {
         (k & 1 ? L.far_lists : L.near_lists) += hc[k];
         for (int64_t j = 0; j < hc[k]; j += 64)
-            chunks.push_back(Chunk{(int32_t)(k >> 1), (int32_t)(k & 1), (int32_t)(npairs + j),
+            chunks.push_back(Chunk{(int32_t)((k >> 1) % nn), (int32_t)(k & 1), (int32_t)(npairs + j),
                                    (int32_t)std::min<int64_t>(64, hc[k] - j)});
         npairs += hc[k];
     }

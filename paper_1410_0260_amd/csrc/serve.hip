@@ -160,7 +160,9 @@ void askit_server::run_batch(std::vector<Request> &b, hipStream_t s)
                                   sizeof(float) * d, r.rows, hipMemcpyDeviceToDevice, s));
             off += r.rows;
         }
-        query_points(h, ws0, Yb, M, d, Ub, R0, s);
+        std::vector<int64_t> segs;
+        for (auto &r : b) segs.push_back(r.rows);
+        query_points(h, ws0, Yb, M, d, Ub, R0, s, &segs);
         off = 0;
         for (auto &r : b) {
             HIPC(hipMemcpy2DAsync(r.out, sizeof(float) * r.ld_out, Ub + off * R0, sizeof(float) * R0,

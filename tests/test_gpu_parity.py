@@ -38,6 +38,9 @@ CASES = {
     # error bound, which grows with the squared norms, exceeds the neighbour
     # gaps, so rows go through the filtered fallback
     "wide-fallback": (5000, 600, 5, 6, O.Params(m=128, kappa=16, smax=32, ell=52, tau=1e-5, h=2.0, seed=13)),
+    # l above half the outside pool: most nodes draw their rows by the
+    # shuffled-pool branch of the sampler (pool <= 2r)
+    "small-pool": (300, 5, 3, 3, O.Params(m=32, kappa=8, smax=64, ell=160, tau=1e-6, h=0.9, seed=17)),
 }
 SPREAD = {"wide-fallback": 30.0}
 
@@ -89,6 +92,13 @@ def test_node_lists_bit_exact(case):
 
 def test_sampled_rows_bit_exact(case):
     name, X, W, p, st, g = case
+    if name == "small-pool":
+        N = len(X)
+        nd = st["nodes"]
+        fy = sum(1 for a in range(1, len(nd))
+                 if (lambda n, c: 0 < min(p.ell - c, N - n - c) < N - n - c <= 2 * min(p.ell - c, N - n - c))(
+                     int(nd[a]["hi"] - nd[a]["lo"]), int(st["nl_cnt"][a])))
+        assert fy >= 20
     assert np.array_equal(g["T_cnt"], st["T_cnt"])
     for a in range(len(st["nodes"])):
         c = st["T_cnt"][a]

@@ -1,7 +1,7 @@
 """Serving form: requests that arrive while others are on the GPU are batched
 and admitted by memory; every result equals the same request run alone
-(weight columns to FP32 rounding of identical arithmetic, queries within the
-FP32 parity tolerance)."""
+(query values bit for bit, weight columns to FP32 rounding), and matches the
+FP64 oracle within the parity tolerance."""
 import numpy as np
 import pytest
 
@@ -16,35 +16,62 @@ def _setup(N=12000, d=16):
     import torch
     from paper_1410_0260_amd import askit as A
     X = synth.mixture_points(N, d, 4, 5, 1e-3, 77)
-    p = A.default_params(leaf_size=128, kappa=16, max_skeleton=48, sample_rows=68, id_tol=1e-5,
-                         bandwidth=1.0, seed=3)
+    q = P_SERVE
+    p = A.default_params(leaf_size=q.m, kappa=q.kappa, max_skeleton=q.smax, sample_rows=q.ell, id_tol=q.tau,
+                         bandwidth=q.h, seed=q.seed)
     h = A.setup(torch.from_numpy(X).cuda(), p)
     return A, h, X
+
+
+P_SERVE = O.Params(m=128, kappa=16, smax=48, ell=68, tau=1e-5, h=1.0, seed=3)
+
+
+def _requests(N, d, count, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        if rng.random() < 0.5:
+            reqs.append(("w", synth.weights(N, int(rng.integers(1, 9)), 1000 + 37 * seed + i)))
+        else:
+            M = int(rng.integers(1, 700))
+            reqs.append(("q", synth.mixture_points(M, d, 4, 5, 1e-3, 2000 + 37 * seed + i, basis_seed=77)))
+    return reqs
+
+
+def _alone(h, reqs, W0):
+    import torch
+    out = []
+    for kind, a in reqs:
+        if kind == "w":
+            h.update_weights(torch.from_numpy(a).cuda())
+            out.append(h.evaluate().cpu().numpy().astype(np.float64))
+        else:
+            h.update_weights(torch.from_numpy(W0).cuda())
+            out.append(h.query(torch.from_numpy(a).cuda()).cpu().numpy().astype(np.float64))
+    torch.cuda.synchronize()
+    return out
+
+
+def _check_same(reqs, alone, outs):
+    # a query request is sorted, cut into slabs and chunks among its own points
+    # only, so its values are bit-identical alone and in a mix; a weight
+    # request's columns are contracted in a pass of as many columns as the
+    # batch holds (vector units or MFMA), equal to FP32 rounding
+    for (kind, _), a, b in zip(reqs, alone, outs):
+        if kind == "q":
+            assert np.array_equal(a, b)
+        else:
+            for r in range(a.shape[1]):
+                assert rel(b[:, r], a[:, r]) < 1e-6
 
 
 def test_serving_mix_equals_alone():
     import torch
     A, h, X = _setup()
     N, d = X.shape
-    rng = np.random.default_rng(5)
     W0 = synth.weights(N, 2, 900)
-    reqs = []
-    for i in range(24):
-        if rng.random() < 0.5:
-            reqs.append(("w", synth.weights(N, int(rng.integers(1, 9)), 1000 + i)))
-        else:
-            M = int(rng.integers(1, 700))
-            reqs.append(("q", synth.mixture_points(M, d, 4, 5, 1e-3, 2000 + i, basis_seed=77)))
-    # alone, through the plain API
-    alone = []
-    for kind, a in reqs:
-        if kind == "w":
-            h.update_weights(torch.from_numpy(a).cuda())
-            alone.append(h.evaluate().cpu().numpy().astype(np.float64))
-        else:
-            h.update_weights(torch.from_numpy(W0).cuda())
-            alone.append(h.query(torch.from_numpy(a).cuda()).cpu().numpy().astype(np.float64))
-    torch.cuda.synchronize()
+    reqs = _requests(N, d, 24, 5)
+    alone = _alone(h, reqs, W0)
     # in a mix: all submitted at once, 3 workers, batches of up to 16 columns / 1500 points
     srv = A.Server(h, torch.from_numpy(W0).cuda(),
                    A.server_config(workers=3, max_batch_rhs=16, max_batch_queries=1500))
@@ -57,14 +84,75 @@ def test_serving_mix_equals_alone():
     assert st["completed"] == len(reqs) and st["failed"] == 0
     assert st["batches"] < len(reqs)          # requests were batched together
     assert st["p99_ms"] >= st["p50_ms"] > 0
-    # weight requests use the handle's own work lists: the same arithmetic alone
-    # and in a mix.  A query's pairs ride in chunks with the batch's other
-    # queries, and the chunk's first target centres the distance computation,
-    # so its value agrees to the FP32 rounding of that cancellation (a few ulps
-    # of |x - c|^2 + |y - c|^2 in r^2, relative 1e-4 at most here).
-    for (kind, _), a, b in zip(reqs, alone, outs):
-        for r in range(a.shape[1]):
-            assert rel(b[:, r], a[:, r]) < (1e-6 if kind == "w" else 1e-4)
+    _check_same(reqs, alone, outs)
+
+
+def test_serving_poisson_arrivals():
+    """Requests submitted on a seeded Poisson schedule while earlier batches
+    are still on the device: each result equals the request run alone."""
+    import time
+    import torch
+    A, h, X = _setup()
+    N, d = X.shape
+    W0 = synth.weights(N, 2, 901)
+    reqs = _requests(N, d, 30, 6)
+    alone = _alone(h, reqs, W0)
+    inputs = [torch.from_numpy(a).cuda() for _, a in reqs]
+    torch.cuda.synchronize()
+    gaps = np.random.default_rng(66).exponential(0.004, len(reqs))
+    srv = A.Server(h, torch.from_numpy(W0).cuda(),
+                   A.server_config(workers=2, max_batch_rhs=16, max_batch_queries=1500))
+    tickets, busy_at_submit = [], 0
+    for (kind, _), x, gap in zip(reqs, inputs, gaps):
+        time.sleep(float(gap))
+        busy_at_submit += int(any(srv.poll(t) == 0 for t in tickets))
+        tickets.append(srv.submit_weights(x) if kind == "w" else srv.submit_query(x))
+    outs = [srv.wait(t, 120.0).cpu().numpy().astype(np.float64) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    h.close()
+    print(f"[serving] {busy_at_submit} of {len(reqs)} requests arrived while others were pending; {st}")
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert busy_at_submit >= len(reqs) // 3
+    _check_same(reqs, alone, outs)
+
+
+def test_served_results_match_oracle():
+    """Served weight and query requests against the FP64 oracle's Alg. 4 for
+    the same weights (u at 1500 sampled points; queries at all their points)."""
+    import torch
+    A, h, X = _setup()
+    N, d = X.shape
+    W0 = synth.weights(N, 2, 902)
+    reqs = _requests(N, d, 10, 7)
+    srv = A.Server(h, torch.from_numpy(W0).cuda(),
+                   A.server_config(workers=2, max_batch_rhs=16, max_batch_queries=1500))
+    tickets = [srv.submit_weights(torch.from_numpy(a).cuda()) if k == "w"
+               else srv.submit_query(torch.from_numpy(a).cuda()) for k, a in reqs]
+    outs = [srv.wait(t, 120.0).cpu().numpy().astype(np.float64) for t in tickets]
+    srv.close()
+    h.close()
+    st = O.setup(X, P_SERVE)
+    tg = np.sort(np.random.default_rng(8).choice(N, 1500, replace=False))
+    nb = O.self_neighbours(st, tg)
+
+    def oracle_u(W, targets_Y=None):
+        Wsk = O.upward(st["nodes"], W[st["perm"]].astype(np.float64), st["sk"], P_SERVE.smax)
+        if targets_Y is None:
+            return O.evaluate(X[tg], nb, X, st["perm"], st["nodes"], None, P_SERVE.h, W, st["sk"], Wsk,
+                              P_SERVE.smax, record=False).U
+        sq = dict(st, W=W, Wsk=Wsk)
+        return O.query(sq, targets_Y, record=False)[2].U
+
+    for (kind, a), b in zip(reqs, outs):
+        if kind == "w":
+            ref, got = oracle_u(a), b[tg]
+        else:
+            ref, got = oracle_u(W0, a), b
+        for r in range(ref.shape[1]):
+            e = rel(got[:, r], ref[:, r])
+            print(f"[serving vs oracle] {kind} column {r}: {e:.2e}", flush=True)
+            assert e < 1e-5
 
 
 def test_serving_memory_admission():

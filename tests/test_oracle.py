@@ -227,6 +227,71 @@ def test_sampler_uniform_chi2():
     assert scipy.stats.chisquare(obs).pvalue > 1e-4
 
 
+def _two_node_case(N, lo, hi, nl, ell):
+    """A root and one node alpha = [lo, hi) with the neighbour list nl (tree
+    positions): enough for the sampler, which reads only alpha's range, level,
+    path and list (Eq. e:sk_targets)."""
+    nodes = np.zeros(2, dtype=O.NODE_DTYPE)
+    nodes[0] = (0, N, 0, -1, 1, 1, 0)
+    nodes[1] = (lo, hi, 3, 0, -1, -1, 5)
+    nl_pos = np.full((2, ell), -1, np.int32)
+    nl_cnt = np.zeros(2, np.int32)
+    nl_pos[1, :len(nl)] = nl
+    nl_cnt[1] = len(nl)
+    return nodes, nl_pos, nl_cnt
+
+
+def test_sampler_small_pool_branch_uniform():
+    """Pool of at most 2r positions (the shuffled-pool branch): r distinct
+    positions, none in alpha or N_alpha; every pool position is included with
+    probability r / pool, and the first draw is uniform over the pool -- the
+    distribution of uniform sampling without replacement (Eq. e:sk_targets)."""
+    N, lo, hi, ell = 60, 20, 40, 25
+    nl = [3, 47, 11, 58, 41]
+    nodes, nl_pos, nl_cnt = _two_node_case(N, lo, hi, nl, ell)
+    c = len(nl)
+    r = ell - c
+    pool = [p for p in range(N) if not (lo <= p < hi) and p not in nl]
+    assert r < len(pool) <= 2 * r          # the branch under test
+    incl = dict.fromkeys(pool, 0)
+    first = dict.fromkeys(pool, 0)
+    trials = 4000
+    for s in range(trials):
+        T, Tc = O.sample_rows(nodes, N, nl_pos, nl_cnt, ell, seed=77 + 1009 * s)
+        t = T[1, :Tc[1]]
+        assert Tc[1] == ell
+        assert (t[:c] == nl).all()
+        drawn = t[c:].tolist()
+        assert len(set(drawn)) == r and set(drawn) <= set(pool)
+        for p in drawn:
+            incl[p] += 1
+        first[drawn[0]] += 1
+    obs = np.array(list(incl.values()), float)
+    assert abs(obs.mean() / trials - r / len(pool)) < 1e-12
+    # inclusion counts: each position Binomial(trials, r/pool); chi-square on (in, out)
+    pexp = r / len(pool)
+    chi = float((((obs - trials * pexp) ** 2) / (trials * pexp * (1 - pexp))).sum())
+    assert scipy.stats.chi2.sf(chi, len(pool) - 1) > 1e-4
+    assert scipy.stats.chisquare(np.array(list(first.values()), float)).pvalue > 1e-4
+
+
+def test_sampler_rejection_branch_uniform_first_draw():
+    """Pool larger than 2r (draw and reject): the first draw is uniform over
+    positions outside alpha and N_alpha, and repeated draws never repeat."""
+    N, lo, hi, ell = 90, 30, 50, 12
+    nl = [7, 88, 52]
+    nodes, nl_pos, nl_cnt = _two_node_case(N, lo, hi, nl, ell)
+    pool = [p for p in range(N) if not (lo <= p < hi) and p not in nl]
+    assert len(pool) > 2 * (ell - len(nl))
+    first = dict.fromkeys(pool, 0)
+    for s in range(5000):
+        T, Tc = O.sample_rows(nodes, N, nl_pos, nl_cnt, ell, seed=3 + 7919 * s)
+        drawn = T[1, len(nl):Tc[1]].tolist()
+        assert len(set(drawn)) == len(drawn) == ell - len(nl) and set(drawn) <= set(pool)
+        first[drawn[0]] += 1
+    assert scipy.stats.chisquare(np.array(list(first.values()), float)).pvalue > 1e-4
+
+
 # ------------------------------------------------------------ ID (Sec. 2.1)
 def test_qrcp_matches_lapack_geqp3():
     rng = np.random.default_rng(0)
