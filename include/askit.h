@@ -154,6 +154,29 @@ askit_status askit_query(askit_handle *h, const float *Y, int64_t M, int64_t ldy
                          int64_t ldu, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): u = K w for
+ * the weights W in one call -- the work of askit_update_weights followed by
+ * askit_evaluate, with the same kernels and the same results -- without any
+ * allocation.  Its working buffers (W in tree order, the skeleton weights and
+ * one partial sum per (target, source node) pair and column) live in a fixed
+ * device array of ASKIT_NOALLOC_SCRATCH_BYTES, one per GPU, held by the
+ * library until the process ends.
+ *   W  device, N x nrhs FP32, original point order, row stride ldw >= nrhs;
+ *   U  device, N x nrhs FP32, row stride ldu >= nrhs; both owned by the caller.
+ * 1 <= nrhs <= 64.  ASKIT_ERR_UNSUPPORTED when the working buffers,
+ * 4 (N + num_nodes s_max + eval_pairs) nrhs bytes (each part rounded up to
+ * 256 bytes), exceed the array.  Only enqueues work on `stream` (no host
+ * synchronisation).  The handle's own weights (askit_update_weights) are left
+ * unchanged.  Every call on one GPU shares that GPU's array: calls that overlap
+ * on one device (two streams, two host threads) race and must be serialized by
+ * the caller.
+ */
+#define ASKIT_NOALLOC_SCRATCH_BYTES (256ull << 20)
+askit_status askit_evaluate_weights_noalloc(askit_handle *h, const float *W, int64_t ldw, int32_t nrhs,
+                                            float *U, int64_t ldu, void *stream);
+
+/*
  * The kappa nearest sources of M new points Y (device, M x d FP32, row
  * stride ldy): the neighbour search that askit_query runs for its targets
  * (Sec. 2.2; Alg. 4 prunes with these lists).  idx (device, M x kappa int32,

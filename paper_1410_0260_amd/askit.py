@@ -64,7 +64,7 @@ class AskitError(RuntimeError):
 _lib = None
 
 EXPORTED = ["askit_params_default", "askit_setup", "askit_setup_with_knn", "askit_update_weights",
-            "askit_evaluate", "askit_evaluate_parts", "askit_query", "askit_query_neighbors", "askit_destroy", "askit_last_error", "askit_get_info",
+            "askit_evaluate", "askit_evaluate_parts", "askit_evaluate_weights_noalloc", "askit_query", "askit_query_neighbors", "askit_destroy", "askit_last_error", "askit_get_info",
             "askit_export"]
 
 
@@ -82,6 +82,7 @@ def lib():
         L.askit_setup_with_knn.argtypes = [P, i64, i32, i64, P, i64, C.POINTER(Params), P, C.POINTER(P)]
         L.askit_evaluate.argtypes = [P, P, i64, P]
         L.askit_evaluate_parts.argtypes = [P, P, i64, P, i64, P]
+        L.askit_evaluate_weights_noalloc.argtypes = [P, P, i64, i32, P, i64, P]
         L.askit_query.argtypes = [P, P, i64, i64, P, i64, P]
         L.askit_query_neighbors.argtypes = [P, P, i64, i64, P, P, P]
         L.askit_destroy.argtypes = [P]
@@ -158,6 +159,17 @@ class Handle:
         _check(lib().askit_evaluate_parts(self.ptr, C.c_void_p(U.data_ptr()), U.stride(0),
                                           C.c_void_p(Un.data_ptr()), Un.stride(0), _stream(torch)))
         return U, Un
+
+    def evaluate_weights_noalloc(self, W, out=None):
+        """u = K w for W through the entry point that allocates nothing."""
+        import torch
+        Wd = _dev_f32(torch, W)
+        assert Wd.shape[0] == self.N
+        U = out if out is not None else torch.empty((self.N, Wd.shape[1]), device="cuda", dtype=torch.float32)
+        _check(lib().askit_evaluate_weights_noalloc(self.ptr, C.c_void_p(Wd.data_ptr()), Wd.stride(0),
+                                                    Wd.shape[1], C.c_void_p(U.data_ptr()), U.stride(0),
+                                                    _stream(torch)))
+        return U
 
     def query(self, Y, out=None):
         import torch

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libaskit.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "points.hip", "knn.hip", "tree.hip", "lists.hip", "skel.hip", "eval.hip",
-           "serve.hip", "batch.hip", "pairs.hip"]
+           "serve.hip", "batch.hip", "pairs.hip", "noalloc.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature",
          "-Xclang", "-packed-fp32-ops", "-Wno-unused-result", "-Wno-unused-value",
          "-I" + os.path.join(HERE, "..", "include")]
