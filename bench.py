@@ -514,12 +514,94 @@ def cpu_info():
     return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
 
 
+def hit_rate(torch, approx, exact, chunk=65536):
+    """Fraction of the exact neighbour pairs (i, j) that the approximate lists hold."""
+    hits = 0
+    for a in range(0, exact.shape[0], chunk):
+        x = torch.from_numpy(np.ascontiguousarray(approx[a:a + chunk])).cuda()
+        e = torch.from_numpy(np.ascontiguousarray(exact[a:a + chunk])).cuda()
+        hits += int((e[:, :, None] == x[:, None, :]).any(2).sum())
+    return hits / exact.size
+
+
+def approx_knn_bench(args, A, torch):
+    """The paper's exact-vs-approximate neighbour experiment (runs 10-15 of
+    Table t:results0) on the GPU: a 4-D standard normal point set of 2^20
+    points, m = 64, fixed rank s in {4, 32} (tau = 0, l = s + 20), h = 0.113
+    (the paper's 0.16 in exp(-r^2/h^2)), kappa = 64 (the paper's 2m = 128 is
+    above this library's limit); neighbour lists exact, or from the greedy
+    random-projection-tree search with few and with more rounds.  Per run: hit
+    rate against the exact lists, eps and eps_kappa on 10K targets, near and
+    far percentages, and the times T_kappa (neighbours), T_S (the rest of the
+    setup) and T_E (skeleton weights + evaluation)."""
+    import dataclasses
+    N = 1 << 20
+    wl0 = synth.Workload("4-D standard normal N=1048576 m=64", N=N, d=4, q=4, n_comp=1, noise_var=0.0, h=0.113,
+                         m=64, kappa=64, smax=4, ell=24, tau=0.0, R=1, seed=10, spread=0.0)
+    X = synth.points(wl0)
+    W = synth.weights(N, 1, wl0.seed)
+    Xd, Wd = torch.from_numpy(X).cuda(), torch.from_numpy(W).cuda()
+    rng = np.random.default_rng(1010)
+    tg = np.sort(rng.choice(N, min(args.eps_targets, N), replace=False))
+    Ud = direct_gpu_fp64(X, W, tg, wl0.h)[:, 0]
+    leaf = 256
+    exact_idx = None
+    runs = []
+    for mode, rounds in (("exact", 0), ("rp-tree", 1), ("rp-tree", 4)):
+        for smax in (4, 32):
+            wl = dataclasses.replace(wl0, smax=smax, ell=smax + 20)
+            prm = A.params_from_workload(wl)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "exact":
+                h = A.setup(Xd, prm)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                inf = h.info()
+                t_kappa = inf["t_knn_ms"] * 1e-3
+                t_s = (t1 - t0) - t_kappa
+                if exact_idx is None:
+                    exact_idx = h.export(A.X_KNN_IDX, np.int32).reshape(N, wl.kappa)
+                ki = exact_idx
+            else:
+                gi, gd = A.knn_rptree(Xd, wl.kappa, leaf, rounds, 77)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                h = A.setup_with_knn(Xd, gi, prm)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                t_kappa, t_s = t1 - t0, t2 - t1
+                ki = gi.cpu().numpy()
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            h.update_weights(Wd)
+            U, Un = h.evaluate_parts()
+            torch.cuda.synchronize()
+            t_e = time.perf_counter() - t3
+            inf = h.info()
+            h.close()
+            u, un = U.cpu().numpy()[tg, 0].astype(np.float64), Un.cpu().numpy()[tg, 0].astype(np.float64)
+            hit = hit_rate(torch, ki, exact_idx) if mode != "exact" else 1.0
+            runs.append({"knn": mode, "rounds": rounds, "leaf": leaf if rounds else None, "s": smax,
+                         "hit_rate": hit, "eps": float(np.linalg.norm(u - Ud) / np.linalg.norm(Ud)),
+                         "eps_kappa": float(np.linalg.norm(un - Ud) / np.linalg.norm(Ud)),
+                         "near_pct": 100.0 * inf["near_lists"] / N / wl.kappa,
+                         "far_pct": 100.0 * inf["far_lists"] / N / (wl.kappa * np.log2(N / wl.m)),
+                         "T_kappa_s": t_kappa, "T_S_s": t_s, "T_E_s": t_e})
+            log(f"[approx-knn] {runs[-1]}")
+    return {"metric": "exact vs approximate neighbours (runs 10-15 analogue): hit rate, eps, pruning, times",
+            "value": None, "unit": None, "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": wl0.name, "N": N, "d": 4, "m": 64, "kappa": 64, "h": wl0.h, "tau": 0.0,
+                       "eps_targets": len(tg)},
+            "runs": runs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fp32_1m", choices=list(WORKLOADS) + ["batched"])
+    ap.add_argument("--workload", default="fp32_1m", choices=list(WORKLOADS) + ["batched", "approx_knn"])
     ap.add_argument("--eps-targets", type=int, default=10000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the bounded serving leg of the default run")
@@ -550,6 +632,9 @@ def main():
 
     if args.workload == "batched":
         print(json.dumps(batched_bench(args, A, torch)))
+        return
+    if args.workload == "approx_knn":
+        print(json.dumps(approx_knn_bench(args, A, torch)))
         return
     default_run = args.workload == "fp32_1m" and not args.set
     wl = synth.fp32_1m_gate() if default_run else WORKLOADS[args.workload]()

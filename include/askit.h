@@ -118,6 +118,31 @@ askit_status askit_setup_with_knn(const float *X, int64_t N, int32_t d, int64_t 
                                   int64_t ldk, const askit_params *p, void *stream, askit_handle **out);
 
 /*
+ * Approximate kappa nearest neighbours by the paper's greedy search with
+ * random projection trees (Sec. 2.2, "computing nearest neighbors"): each of
+ * `iterations` rounds builds a tree that splits every node with more than
+ * leaf_size points at the median of its points' projections on a random
+ * direction (the ceil(n/2) smallest (projection, position) go left), gives
+ * each point the other points of its leaf as candidates (exhaustive search,
+ * canonical FP64 squared distances), keeps each point's kappa best
+ * (distance, id) pairs seen in all rounds, and discards the tree.  Directions
+ * have +-1 coordinates from a SplitMix64 stream keyed by (seed, round, node),
+ * so the result is reproducible bit for bit.  The lists feed
+ * askit_setup_with_knn.
+ *   X     device, N x d FP32, row stride ldx >= d; read only during the call.
+ *   idx   device, N x kappa int32 (row stride kappa): original ids, each row in
+ *         increasing (distance, id) order; dist: device N x kappa FP64, the
+ *         squared distances.  Both owned by the caller.
+ * 1 <= kappa <= 64, kappa < N; 1 <= iterations <= 2046; every leaf of the
+ * tree shape (split at ceil(n/2) until at most leaf_size points) must hold
+ * more than kappa points (ASKIT_ERR_INVALID_ARG otherwise).  Synchronises
+ * `stream`.
+ */
+askit_status askit_knn_rptree(const float *X, int64_t N, int32_t d, int64_t ldx, int32_t kappa,
+                              int32_t leaf_size, int32_t iterations, uint64_t seed, int32_t *idx,
+                              double *dist, void *stream);
+
+/*
  * Upward pass (Sec. 2.1, Alg. 3): computes the skeleton weights of every
  * node from W (device, N x nrhs FP32, original point order, row stride
  * ldw >= nrhs), 1 <= nrhs <= 64.  Enqueued on `stream`; W must stay valid

@@ -14,6 +14,8 @@
  *   or_knn          kappa nearest neighbours by exhaustive search (Sec. 2.2,
  *                   "Computing nearest neighbors"; exact search replaces the
  *                   randomized-tree search, ties broken by point id).
+ *   or_rpknn        the paper's approximate search: iterated random
+ *                   projection trees, exhaustive search in each leaf.
  *   or_bandwidth    per-source bandwidth h_j for the variable-bandwidth
  *                   Gaussian (Sec. 4, "variable bandwidth").
  *   or_tree         median-split binary tree (Sec. 2.2 tree rule, Fig. tree).
@@ -420,6 +422,98 @@ int or_sample_rows(const or_node *nodes, int64_t nn, int64_t N, const int32_t *n
     }
     free(pool);
     return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Approximate neighbours (Sec. 2.2, "Computing nearest neighbors"): greedy
+ * search with random projection trees.  One round: build a tree over all
+ * points whose nodes split at the median of the projections on a random
+ * direction, give every point the other points of its leaf as candidates
+ * (exhaustive search), keep its kappa best (D, id) pairs over all rounds so
+ * far, discard the tree.
+ *
+ * Readings: a node with n > leaf points splits into ceil(n/2) (smallest
+ * (projection, id)) and floor(n/2), each child in increasing id (the rule of
+ * the ASKIT tree, with the random direction in place of (x_l, x_r)); the
+ * direction has coordinates +1 or -1 (Achlioptas-type random projection),
+ * coordinate k being -1 when bit (k mod 64) of output floor(k / 64) of the
+ * SplitMix64 stream with base seed XOR (key * golden) is set, key =
+ * ((round + 1) << 53) XOR (level << 48) XOR path; the projection
+ * sum_k sign_k x_k is summed in FP64 in increasing k.                    */
+typedef struct { int32_t lo, n, level; int64_t path; } rp_node;
+
+static void rp_merge(int32_t *li, double *ld, int kappa, int32_t j, double D)
+{
+    if (!nn_less(D, j, ld[kappa - 1], li[kappa - 1])) return;
+    for (int t = 0; t < kappa; ++t)
+        if (li[t] == j) return;               /* already a candidate (same D) */
+    int p = kappa - 1;
+    while (p > 0 && nn_less(D, j, ld[p - 1], li[p - 1])) {
+        ld[p] = ld[p - 1];
+        li[p] = li[p - 1];
+        --p;
+    }
+    ld[p] = D;
+    li[p] = j;
+}
+
+int or_rpknn(const float *X, int64_t N, int d, int kappa, int leaf, int rounds, uint64_t seed,
+             int32_t *idx, double *dist)
+{
+    if (N < 2 || d < 1 || kappa < 1 || kappa >= N || leaf < 2 || rounds < 1) return OR_EINVAL;
+    int64_t nn = count_nodes(N, leaf);
+    rp_node *nodes = (rp_node *)malloc(sizeof(rp_node) * (size_t)nn);
+    int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    proj_t *pr = (proj_t *)malloc(sizeof(proj_t) * (size_t)N);
+    if (!nodes || !ids || !pr) { free(nodes); free(ids); free(pr); return OR_ENOMEM; }
+    for (int64_t t = 0; t < N * kappa; ++t) { idx[t] = -1; dist[t] = INFINITY; }
+    int rc = OR_OK;
+    for (int r = 0; r < rounds && rc == OR_OK; ++r) {
+        for (int64_t i = 0; i < N; ++i) ids[i] = (int32_t)i;
+        nodes[0] = (rp_node){0, (int32_t)N, 0, 0};
+        int64_t next = 1;
+        for (int64_t a = 0; a < next; ++a) {      /* breadth first */
+            rp_node nd = nodes[a];
+            if (nd.n <= leaf) {                    /* leaf: exhaustive search */
+                if (nd.n - 1 < kappa) { rc = OR_EINVAL; break; }
+                for (int32_t u = 0; u < nd.n; ++u) {
+                    int32_t i = ids[nd.lo + u];
+                    for (int32_t v = 0; v < nd.n; ++v) {
+                        if (v == u) continue;
+                        int32_t j = ids[nd.lo + v];
+                        rp_merge(idx + (int64_t)i * kappa, dist + (int64_t)i * kappa, kappa, j,
+                                 sqdist(X + (int64_t)i * d, X + (int64_t)j * d, d));
+                    }
+                }
+                continue;
+            }
+            uint64_t key = ((uint64_t)(r + 1) << 53) ^ ((uint64_t)nd.level << 48) ^ (uint64_t)nd.path;
+            uint64_t base = seed ^ (key * SM64_GOLDEN);
+            for (int32_t u = 0; u < nd.n; ++u) {
+                const float *x = X + (int64_t)ids[nd.lo + u] * d;
+                double s = 0.0;
+                uint64_t z = 0;
+                for (int k = 0; k < d; ++k) {
+                    if (k % 64 == 0) z = or_splitmix64(base, (uint64_t)(k / 64));
+                    if ((z >> (k % 64)) & 1) s -= (double)x[k];
+                    else s += (double)x[k];
+                }
+                pr[u].p = s;
+                pr[u].id = ids[nd.lo + u];
+            }
+            qsort(pr, (size_t)nd.n, sizeof(proj_t), cmp_proj);
+            int32_t nl = (nd.n + 1) / 2;
+            for (int32_t u = 0; u < nd.n; ++u) ids[nd.lo + u] = pr[u].id;
+            qsort(ids + nd.lo, (size_t)nl, sizeof(int32_t), cmp_i32);
+            qsort(ids + nd.lo + nl, (size_t)(nd.n - nl), sizeof(int32_t), cmp_i32);
+            nodes[next++] = (rp_node){nd.lo, nl, nd.level + 1, nd.path << 1};
+            nodes[next++] = (rp_node){nd.lo + nl, nd.n - nl, nd.level + 1, (nd.path << 1) | 1};
+        }
+    }
+    free(nodes);
+    free(ids);
+    free(pr);
+    return rc;
 }
 
 /* ------------------------------------------------------------------ */

@@ -38,6 +38,7 @@ def lib():
         L.or_direct.argtypes = [P, i64, P, i64, i32, P, i32, P, f64, P]
         L.or_knn.argtypes = [P, i64, P, i64, i32, i32, i32, P, P]
         L.or_bandwidth.argtypes = [P, i64, i32, i32, P]
+        L.or_rpknn.argtypes = [P, i64, i32, i32, i32, i32, u64, P, P]
         L.or_tree_count.argtypes = [i64, i32]
         L.or_tree_count.restype = i64
         L.or_tree.argtypes = [P, i64, i32, i32, P, i64, P]
@@ -52,7 +53,7 @@ def lib():
         L.or_upward.argtypes = [P, i64, P, i32, i32, P, P, i32, P, P, P]
         L.or_evaluate.argtypes = [P, i64, P, i32, P, i32, P, P, P, f64, P, i32, P, P, i32, P,
                                   P, P, P, P, i32, P, P, i32]
-        for f in ("or_direct", "or_knn", "or_bandwidth", "or_tree", "or_node_lists",
+        for f in ("or_direct", "or_knn", "or_rpknn", "or_bandwidth", "or_tree", "or_node_lists",
                   "or_sample_rows", "or_gauss_matrix", "or_id", "or_skeletonize", "or_upward",
                   "or_evaluate"):
             getattr(L, f).restype = i32
@@ -92,6 +93,17 @@ def knn(Q, X, kappa, exclude_self):
     dist = np.empty((Q.shape[0], kappa), dtype=np.float64)
     _check(lib().or_knn(_p(Q), Q.shape[0], _p(X), X.shape[0], X.shape[1], kappa,
                         1 if exclude_self else 0, _p(idx), _p(dist)), "knn")
+    return idx, dist
+
+
+def rpknn(X, kappa, leaf, rounds, seed):
+    """Approximate kappa nearest neighbours by iterated random projection trees."""
+    X = _f32(X)
+    N = X.shape[0]
+    idx = np.empty((N, kappa), dtype=np.int32)
+    dist = np.empty((N, kappa), dtype=np.float64)
+    _check(lib().or_rpknn(_p(X), N, X.shape[1], kappa, leaf, rounds, C.c_uint64(seed & (2**64 - 1)),
+                          _p(idx), _p(dist)), "rpknn")
     return idx, dist
 
 

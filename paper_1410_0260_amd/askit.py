@@ -64,7 +64,8 @@ class AskitError(RuntimeError):
 _lib = None
 
 EXPORTED = ["askit_params_default", "askit_setup", "askit_setup_with_knn", "askit_update_weights",
-            "askit_evaluate", "askit_evaluate_parts", "askit_evaluate_weights_noalloc", "askit_query", "askit_query_neighbors", "askit_destroy", "askit_last_error", "askit_get_info",
+            "askit_evaluate", "askit_evaluate_parts", "askit_evaluate_weights_noalloc", "askit_knn_rptree",
+            "askit_query", "askit_query_neighbors", "askit_destroy", "askit_last_error", "askit_get_info",
             "askit_export"]
 
 
@@ -83,6 +84,7 @@ def lib():
         L.askit_evaluate.argtypes = [P, P, i64, P]
         L.askit_evaluate_parts.argtypes = [P, P, i64, P, i64, P]
         L.askit_evaluate_weights_noalloc.argtypes = [P, P, i64, i32, P, i64, P]
+        L.askit_knn_rptree.argtypes = [P, i64, i32, i64, i32, i32, i32, C.c_uint64, P, P, P]
         L.askit_query.argtypes = [P, P, i64, i64, P, i64, P]
         L.askit_query_neighbors.argtypes = [P, P, i64, i64, P, P, P]
         L.askit_destroy.argtypes = [P]
@@ -261,6 +263,20 @@ def setup(X, params: Params) -> Handle:
                            _stream(torch), C.byref(h))
     _check(rc)
     return Handle(h, N, d)
+
+
+def knn_rptree(X, kappa, leaf_size, iterations, seed=0):
+    """Approximate neighbour lists by iterated random projection trees:
+    (ids N x kappa int32, squared distances N x kappa float64), device tensors."""
+    import torch
+    Xd = _dev_f32(torch, X)
+    N, d = Xd.shape
+    idx = torch.empty((N, kappa), device="cuda", dtype=torch.int32)
+    dist = torch.empty((N, kappa), device="cuda", dtype=torch.float64)
+    _check(lib().askit_knn_rptree(C.c_void_p(Xd.data_ptr()), N, d, Xd.stride(0), kappa, leaf_size, iterations,
+                                  C.c_uint64(seed & (2**64 - 1)), C.c_void_p(idx.data_ptr()),
+                                  C.c_void_p(dist.data_ptr()), _stream(torch)))
+    return idx, dist
 
 
 def setup_with_knn(X, knn, params: Params) -> Handle:

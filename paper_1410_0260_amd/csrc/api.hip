@@ -661,6 +661,43 @@ askit_status askit_evaluate(askit_handle *h, float *U, int64_t ldu, void *stream
     API_END
 }
 
+askit_status askit_knn_rptree(const float *X, int64_t N, int32_t d, int64_t ldx, int32_t kappa, int32_t leaf_size,
+                              int32_t iterations, uint64_t seed, int32_t *idx, double *dist, void *stream)
+{
+    API_BEGIN
+    if (!X || !idx || !dist) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    if (N < 2 || N >= (1ll << 31)) fail(ASKIT_ERR_INVALID_ARG, "N must be in [2, 2^31)");
+    if (d < 1 || ldx < d) fail(ASKIT_ERR_INVALID_ARG, "need d >= 1 and ldx >= d");
+    if (kappa < 1 || kappa >= N) fail(ASKIT_ERR_INVALID_ARG, "need 1 <= kappa < N");
+    if (kappa > 64) fail(ASKIT_ERR_UNSUPPORTED, "kappa above 64 is not supported");
+    if (d > 1024) fail(ASKIT_ERR_UNSUPPORTED, "d above 1024 is not supported");
+    if (iterations < 1 || iterations > 2046) fail(ASKIT_ERR_INVALID_ARG, "need 1 <= iterations <= 2046");
+    if (leaf_size < 2) fail(ASKIT_ERR_INVALID_ARG, "need leaf_size >= 2");
+    check_device();
+    hipStream_t s = (hipStream_t)stream;
+    const int dp = round_up(d, 16);
+    std::vector<void *> tmp;
+    struct Guard {
+        std::vector<void *> &t;
+        hipStream_t s;
+        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+    } guard{tmp, s};
+    float *Xo;
+    int32_t *flag;
+    HIPC(hipMallocAsync((void **)&Xo, sizeof(float) * N * dp, s));
+    tmp.push_back(Xo);
+    HIPC(hipMallocAsync((void **)&flag, 16, s));
+    tmp.push_back(flag);
+    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    pack_points(X, N, d, ldx, dp, Xo, flag, s);
+    int32_t hflag = 0;
+    HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hflag) fail(ASKIT_ERR_INVALID_ARG, "X holds a non-finite value");
+    rp_knn(Xo, N, d, dp, kappa, leaf_size, iterations, seed, idx, dist, s);
+    API_END
+}
+
 askit_status askit_evaluate_parts(askit_handle *h, float *U, int64_t ldu, float *Unear, int64_t ldun, void *stream)
 {
     API_BEGIN

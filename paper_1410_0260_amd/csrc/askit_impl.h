@@ -260,6 +260,10 @@ float max_norm(const float *nrm, int64_t N, hipStream_t s);
 
 // tree.hip
 void build_tree(askit_handle *h, hipStream_t s);
+// approximate kappa nearest neighbours by iterated random projection trees
+// (Xo: N x dp points, original order); idx/dist: N x kappa, sorted by (distance, id)
+void rp_knn(const float *Xo, int64_t N, int d, int dp, int kappa, int leaf, int iters, uint64_t seed,
+            int32_t *idx, double *dist, hipStream_t s);
 
 // lists.hip
 void build_node_lists(askit_handle *h, hipStream_t s);

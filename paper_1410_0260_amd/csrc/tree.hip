@@ -332,6 +332,30 @@ __global__ void k_invert(const int32_t *__restrict__ p, int64_t n, int32_t *__re
     if (i < n) ip[p[i]] = (int32_t)i;
 }
 
+// Median split of every node of a level by its keys: the ceil(n/2) smallest
+// (key, position) go left, each side keeps the parent's order (radix select of
+// the median key in 8 passes of 8 bits, then a stable partition).  perm is
+// updated in place through pout; sel must hold (0, ceil(n/2) - 1) per split and
+// hist must be zero.
+static void median_split(const uint64_t *key, const Split *d_sp, int nsp, int maxn, Sel *sel, uint32_t *hist,
+                         PartCnt *pc, int32_t *perm, int32_t *pout, int64_t N, hipStream_t s)
+{
+    const int nchunk = (maxn + 255) / 256;
+    const int hchunk = (maxn + 1023) / 1024;
+    for (int pass = 0; pass < 8; ++pass) {
+        int shift = 56 - 8 * pass;
+        hipLaunchKernelGGL(k_radix_hist, dim3(hchunk, nsp), dim3(256), 0, s, key, d_sp, sel, shift, hist);
+        hipLaunchKernelGGL(k_radix_pick, dim3((nsp + 63) / 64), dim3(64), 0, s, hist, sel, nsp, shift);
+    }
+    hipLaunchKernelGGL(k_part_count, dim3(nchunk, nsp), dim3(256), 0, s, key, d_sp, sel, nchunk, pc);
+    hipLaunchKernelGGL(k_part_scan, dim3((nsp + 63) / 64), dim3(64), 0, s, pc, d_sp, nsp, nchunk);
+    HIPC(hipMemcpyAsync(pout, perm, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_part_scatter, dim3(nchunk, nsp), dim3(256), 0, s, key, perm, d_sp, sel, nchunk, pc,
+                       pout);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(perm, pout, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
+}
+
 void build_tree(askit_handle *h, hipStream_t s)
 {
     const int64_t N = h->N;
@@ -400,26 +424,206 @@ void build_tree(askit_handle *h, hipStream_t s)
         hipLaunchKernelGGL(k_far_final, dim3(nsp), dim3(64), 0, s, part, d_sp, nchunk, Rr);
         hipLaunchKernelGGL(k_project, dim3(nchunk, nsp), dim3(256), 0, s, h->Xo, dp, d, h->perm, d_sp,
                            L, Rr, key);
-        int hchunk = (maxn + 1023) / 1024;
-        for (int pass = 0; pass < 8; ++pass) {
-            int shift = 56 - 8 * pass;
-            hipLaunchKernelGGL(k_radix_hist, dim3(hchunk, nsp), dim3(256), 0, s, key, d_sp, sel, shift,
-                               hist);
-            hipLaunchKernelGGL(k_radix_pick, dim3((nsp + 63) / 64), dim3(64), 0, s, hist, sel, nsp,
-                               shift);
-        }
-        hipLaunchKernelGGL(k_part_count, dim3(nchunk, nsp), dim3(256), 0, s, key, d_sp, sel, nchunk,
-                           pc);
-        hipLaunchKernelGGL(k_part_scan, dim3((nsp + 63) / 64), dim3(64), 0, s, pc, d_sp, nsp, nchunk);
-        HIPC(hipMemcpyAsync(pout, h->perm, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
-        hipLaunchKernelGGL(k_part_scatter, dim3(nchunk, nsp), dim3(256), 0, s, key, h->perm, d_sp, sel,
-                           nchunk, pc, pout);
-        HIPC(hipGetLastError());
-        HIPC(hipMemcpyAsync(h->perm, pout, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
+        median_split(key, d_sp, nsp, maxn, sel, hist, pc, h->perm, pout, N, s);
     }
     hipLaunchKernelGGL(k_invert, dim3(nb), dim3(256), 0, s, h->perm, N, h->iperm);
     HIPC(hipGetLastError());
     for (void *p : tmp) HIPC(hipFreeAsync(p, s));
+}
+
+
+// ---------------------------------------------------------------- approximate neighbours
+// Greedy search with random projection trees (Sec. 2.2, "Computing nearest
+// neighbors"): each iteration builds a tree whose nodes split at the median of
+// the points' projections on a random direction, gives every point the
+// candidates of its leaf by exhaustive search, keeps each point's kappa best
+// (distance, id) pairs seen so far, and discards the tree.
+//
+// Direction of a node: coordinate k has sign -1 when bit (k mod 64) of output
+// floor(k / 64) of a SplitMix64 stream (Steele, Lea, Flood 2014) is set, +1
+// otherwise.  The stream state starts at seed XOR (key * golden), key =
+// ((iteration + 1) << 53) XOR (level << 48) XOR path; output t =
+// mix(state + (t + 1) * golden).  The projection sum_k sign_k x_k is added in
+// FP64 in increasing k, so the splits (median by (projection, position), as
+// the tree rule) are reproducible bit for bit.
+namespace {
+
+constexpr uint64_t RP_GOLDEN = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ uint64_t rp_out(uint64_t base, uint64_t t)
+{
+    uint64_t z = base + (t + 1) * RP_GOLDEN;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+__global__ void k_rp_project(const float *__restrict__ X, int dp, int d, const int32_t *__restrict__ perm,
+                             const Split *__restrict__ sp, const uint64_t *__restrict__ sbase,
+                             uint64_t *__restrict__ key)
+{
+#pragma clang fp contract(off)
+    const int c = blockIdx.x, q = blockIdx.y;
+    const Split s = sp[q];
+    const int i = c * 256 + threadIdx.x;
+    if (i >= s.n) return;
+    const float *x = X + (int64_t)perm[s.lo + i] * dp;
+    const uint64_t base = sbase[q];
+    double acc = 0.0;
+    uint64_t z = 0;
+    for (int k = 0; k < d; ++k) {
+        if ((k & 63) == 0) z = rp_out(base, (uint64_t)(k >> 6));
+        const double v = (double)x[k];
+        acc = ((z >> (k & 63)) & 1ull) ? acc - v : acc + v;
+    }
+    key[s.lo + i] = dkey(acc);
+}
+
+__global__ void k_rp_init(int32_t *__restrict__ idx, double *__restrict__ dist, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    idx[t] = -1;
+    dist[t] = __longlong_as_double(0x7ff0000000000000ll);   // +inf: empty slot
+}
+
+// One workgroup per leaf; each thread merges the other points of the leaf
+// into one point's list (canonical FP64 distances, order (distance, id)).
+__global__ __launch_bounds__(256) void k_rp_leaf_search(const float *__restrict__ X, int dp, int d,
+                                                        const int32_t *__restrict__ perm,
+                                                        const Split *__restrict__ leaves, int kappa,
+                                                        int32_t *__restrict__ idx, double *__restrict__ dist)
+{
+    const Split lf = leaves[blockIdx.x];
+    for (int ii = threadIdx.x; ii < lf.n; ii += blockDim.x) {
+        const int32_t i = perm[lf.lo + ii];
+        int32_t li[64];
+        double ld[64];
+        for (int t = 0; t < kappa; ++t) {
+            li[t] = idx[(int64_t)i * kappa + t];
+            ld[t] = dist[(int64_t)i * kappa + t];
+        }
+        const float *xi = X + (int64_t)i * dp;
+        for (int jj = 0; jj < lf.n; ++jj) {
+            if (jj == ii) continue;
+            const int32_t j = perm[lf.lo + jj];
+            const double D = canon_sqdist(xi, X + (int64_t)j * dp, d);
+            const double wd = ld[kappa - 1];
+            if (!(D < wd || (D == wd && j < li[kappa - 1]))) continue;
+            bool dup = false;
+            for (int t = 0; t < kappa; ++t) dup |= li[t] == j;
+            if (dup) continue;
+            int q = kappa - 1;
+            while (q > 0 && (ld[q - 1] > D || (ld[q - 1] == D && li[q - 1] > j))) {
+                ld[q] = ld[q - 1];
+                li[q] = li[q - 1];
+                --q;
+            }
+            ld[q] = D;
+            li[q] = j;
+        }
+        for (int t = 0; t < kappa; ++t) {
+            idx[(int64_t)i * kappa + t] = li[t];
+            dist[(int64_t)i * kappa + t] = ld[t];
+        }
+    }
+}
+
+void rp_knn(const float *Xo, int64_t N, int d, int dp, int kappa, int leaf, int iters, uint64_t seed,
+            int32_t *idx, double *dist, hipStream_t s)
+{
+    // tree shape (depends on N and the leaf size only), breadth first
+    struct RpNode {
+        int32_t lo, n, level;
+        int64_t path;
+    };
+    std::vector<RpNode> nodes{RpNode{0, (int32_t)N, 0, 0}};
+    for (size_t a = 0; a < nodes.size(); ++a) {
+        const RpNode nd = nodes[a];
+        if (nd.n <= leaf) continue;
+        const int32_t nl = (nd.n + 1) / 2;
+        nodes.push_back(RpNode{nd.lo, nl, nd.level + 1, nd.path << 1});
+        nodes.push_back(RpNode{nd.lo + nl, nd.n - nl, nd.level + 1, (nd.path << 1) | 1});
+    }
+    int depth = 0, minleaf = (int)N;
+    for (auto &nd : nodes) depth = std::max(depth, (int)nd.level);
+    std::vector<std::vector<int>> lev(depth + 1);
+    std::vector<Split> hleaves;
+    for (size_t a = 0; a < nodes.size(); ++a) {
+        lev[nodes[a].level].push_back((int)a);
+        if (nodes[a].n <= leaf) {
+            hleaves.push_back(Split{nodes[a].lo, nodes[a].n});
+            minleaf = std::min(minleaf, (int)nodes[a].n);
+        }
+    }
+    if (minleaf - 1 < kappa)
+        fail(ASKIT_ERR_INVALID_ARG, "leaf size too small: every leaf must hold more than kappa points");
+    std::vector<void *> tmp;
+    struct Guard {
+        std::vector<void *> &t;
+        hipStream_t s;
+        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+    } guard{tmp, s};
+    auto ta = [&](size_t b) {
+        void *p;
+        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        tmp.push_back(p);
+        return p;
+    };
+    int64_t maxsp = 1;
+    for (auto &l : lev) maxsp = std::max<int64_t>(maxsp, (int64_t)l.size());
+    int64_t chunk_total = (N + 255) / 256 + 2 * maxsp;
+    int32_t *perm = (int32_t *)ta(sizeof(int32_t) * N);
+    int32_t *pout = (int32_t *)ta(sizeof(int32_t) * N);
+    uint64_t *key = (uint64_t *)ta(sizeof(uint64_t) * N);
+    Split *d_sp = (Split *)ta(sizeof(Split) * maxsp);
+    uint64_t *d_base = (uint64_t *)ta(sizeof(uint64_t) * maxsp);
+    Sel *sel = (Sel *)ta(sizeof(Sel) * maxsp);
+    uint32_t *hist = (uint32_t *)ta(sizeof(uint32_t) * 256 * maxsp);
+    PartCnt *pc = (PartCnt *)ta(sizeof(PartCnt) * chunk_total);
+    Split *d_leaves = (Split *)ta(sizeof(Split) * hleaves.size());
+    HIPC(hipMemsetAsync(hist, 0, sizeof(uint32_t) * 256 * maxsp, s));
+    HIPC(hipMemcpyAsync(d_leaves, hleaves.data(), sizeof(Split) * hleaves.size(), hipMemcpyHostToDevice, s));
+    const int64_t tot = N * kappa;
+    hipLaunchKernelGGL(k_rp_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, idx, dist, tot);
+    HIPC(hipGetLastError());
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    std::vector<Split> hsp;
+    std::vector<Sel> hsel;
+    std::vector<uint64_t> hbase;
+    for (int it = 0; it < iters; ++it) {
+        hipLaunchKernelGGL(k_iota, dim3(nb), dim3(256), 0, s, perm, N);
+        for (int l = 0; l <= depth; ++l) {
+            hsp.clear();
+            hsel.clear();
+            hbase.clear();
+            int maxn = 0;
+            for (int a : lev[l]) {
+                const RpNode &nd = nodes[a];
+                if (nd.n <= leaf) continue;
+                hsp.push_back(Split{nd.lo, nd.n});
+                hsel.push_back(Sel{0ull, (int64_t)((nd.n + 1) / 2 - 1)});
+                const uint64_t k = ((uint64_t)(it + 1) << 53) ^ ((uint64_t)nd.level << 48) ^ (uint64_t)nd.path;
+                hbase.push_back(seed ^ (k * RP_GOLDEN));
+                maxn = std::max(maxn, (int)nd.n);
+            }
+            const int nsp = (int)hsp.size();
+            if (nsp == 0) continue;
+            HIPC(hipMemcpyAsync(d_sp, hsp.data(), sizeof(Split) * nsp, hipMemcpyHostToDevice, s));
+            HIPC(hipMemcpyAsync(sel, hsel.data(), sizeof(Sel) * nsp, hipMemcpyHostToDevice, s));
+            HIPC(hipMemcpyAsync(d_base, hbase.data(), sizeof(uint64_t) * nsp, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_rp_project, dim3((maxn + 255) / 256, nsp), dim3(256), 0, s, Xo, dp, d, perm, d_sp,
+                               d_base, key);
+            median_split(key, d_sp, nsp, maxn, sel, hist, pc, perm, pout, N, s);
+            HIPC(hipStreamSynchronize(s));   // the host split tables are reused by the next level
+        }
+        hipLaunchKernelGGL(k_rp_leaf_search, dim3((unsigned)hleaves.size()), dim3(256), 0, s, Xo, dp, d, perm,
+                           d_leaves, kappa, idx, dist);
+        HIPC(hipGetLastError());
+    }
+    HIPC(hipStreamSynchronize(s));
 }
 
 }  // namespace askit

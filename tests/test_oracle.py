@@ -73,6 +73,55 @@ def test_knn_ties_break_by_index():
     assert (dist[:, :2] == 0).all()
 
 
+# ------------------------------------------------ approximate neighbours (Sec. 2.2)
+def test_rpknn_single_leaf_is_exact_search():
+    """With every point in one leaf the search is exhaustive: the exact lists."""
+    X = small(500)
+    ei, ed = O.knn(X, X, 7, exclude_self=True)
+    ri, rd = O.rpknn(X, 7, 500, 2, seed=3)
+    assert np.array_equal(ri, ei) and np.array_equal(rd, ed)
+
+
+def test_rpknn_lists_valid_and_improving():
+    """Each list holds kappa distinct other points with their exact squared
+    distances (sequential sum), sorted by (distance, id); more rounds only
+    add candidates, so every row's j-th distance never grows; the hit rate
+    against the exact lists approaches 1."""
+    X = synth.mixture_points(2000, 6, 3, 3, 1e-3, 12)
+    kappa = 8
+    ei, _ = O.knn(X, X, kappa, exclude_self=True)
+    prev, hits = None, []
+    for rounds in (1, 2, 4, 12):
+        ri, rd = O.rpknn(X, kappa, 48, rounds, seed=99)
+        for i in range(0, len(X), 97):
+            assert len(set(ri[i].tolist())) == kappa and i not in ri[i]
+            for t in range(kappa):
+                diff = X[i].astype(np.float64) - X[ri[i, t]].astype(np.float64)
+                assert rd[i, t] == np.cumsum(diff * diff)[-1]
+            assert all((rd[i, t], ri[i, t]) < (rd[i, t + 1], ri[i, t + 1]) for t in range(kappa - 1))
+        if prev is not None:
+            assert (rd <= prev).all()
+        prev = rd
+        hits.append(np.mean([len(set(ri[i]) & set(ei[i])) for i in range(len(X))]) / kappa)
+    assert hits == sorted(hits) and hits[0] < 0.9 and hits[-1] > 0.98
+
+
+def test_rpknn_one_dimension_leaves_are_runs():
+    """In 1-D every direction is +-1, so each split cuts the node's sorted
+    values into a lower and an upper half and every leaf is a run of
+    consecutive values: a point's candidates lie within leaf-size ranks."""
+    N, leaf, kappa = 1000, 40, 12
+    X = np.random.default_rng(4).permutation(np.arange(N, dtype=np.float32))[:, None] * 0.37
+    ri, _ = O.rpknn(X, kappa, leaf, 1, seed=5)
+    rank = np.empty(N, np.int64)
+    rank[np.argsort(X[:, 0])] = np.arange(N)
+    span = np.array([rank[np.append(ri[i], i)].max() - rank[np.append(ri[i], i)].min() for i in range(N)])
+    assert span.max() < leaf
+    ri2, _ = O.rpknn(X, kappa, leaf, 1, seed=6)
+    ri3, _ = O.rpknn(X, kappa, leaf, 1, seed=5)
+    assert np.array_equal(ri, ri3) and not np.array_equal(ri, ri2)
+
+
 def test_bandwidth_is_distance_to_bth_neighbour():
     X = small(200)
     idx, dist = O.knn(X, X, 16, exclude_self=True)
