@@ -596,12 +596,95 @@ def approx_knn_bench(args, A, torch):
             "runs": runs}
 
 
+def trends_bench(args, A, torch):
+    """The paper's fixed-rank mode and the convergence trends of runs 1-9 of
+    Table t:results0: a 4-D standard normal point set of 100,000 points; for
+    h in {0.148, 0.707, 3.54} (the paper's 0.21, 1 and 5 in exp(-r^2/h^2)), the
+    three (m, s) pairs (64, 4), (64, 32) and (256, 128) with fixed rank s at
+    every node (tau = 0, l = s + 20), kappa = 64 (the paper's 2m is above this
+    library's limit for m = 64 and 256).  Per run: eps and eps_kappa on 10K
+    targets against the FP64 direct sum, near/far percentages, T_S and T_E;
+    per h: whether eps falls along the three pairs, as in the paper."""
+    import dataclasses
+    N = 100000
+    wl0 = synth.Workload("4-D standard normal N=100000", N=N, d=4, q=4, n_comp=1, noise_var=0.0, h=1.0,
+                         m=64, kappa=64, smax=4, ell=24, tau=0.0, R=1, seed=20, spread=0.0)
+    X = synth.points(wl0)
+    W = synth.weights(N, 1, wl0.seed)
+    Xd, Wd = torch.from_numpy(X).cuda(), torch.from_numpy(W).cuda()
+    tg = np.sort(np.random.default_rng(2020).choice(N, min(args.eps_targets, N), replace=False))
+    runs, trends = [], {}
+    for h in (0.148, 0.707, 3.54):
+        Ud = direct_gpu_fp64(X, W, tg, h)[:, 0]
+        eps_h = []
+        for m, smax in ((64, 4), (64, 32), (256, 128)):
+            wl = dataclasses.replace(wl0, h=h, m=m, smax=smax, ell=smax + 20)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hd = A.setup(Xd, A.params_from_workload(wl))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            hd.update_weights(Wd)
+            U, Un = hd.evaluate_parts()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            inf = hd.info()
+            k = hd.export(A.X_SKEL_K, np.int32)
+            hd.close()
+            u, un = U.cpu().numpy()[tg, 0].astype(np.float64), Un.cpu().numpy()[tg, 0].astype(np.float64)
+            e = float(np.linalg.norm(u - Ud) / np.linalg.norm(Ud))
+            eps_h.append(e)
+            runs.append({"h": h, "m": m, "s": smax, "eps": e,
+                         "eps_kappa": float(np.linalg.norm(un - Ud) / np.linalg.norm(Ud)),
+                         "rank_s_at_nodes": float(np.mean(k[1:] == smax)),
+                         "near_pct": 100.0 * inf["near_lists"] / N / wl.kappa,
+                         "far_pct": 100.0 * inf["far_lists"] / N / (wl.kappa * np.log2(N / m)),
+                         "T_kappa_s": inf["t_knn_ms"] * 1e-3, "T_S_s": (t1 - t0) - inf["t_knn_ms"] * 1e-3,
+                         "T_E_s": t2 - t1})
+            log(f"[trends] {runs[-1]}")
+        trends[str(h)] = {"eps": eps_h, "falls": bool(eps_h[0] >= eps_h[1] >= eps_h[2])}
+    return {"metric": "fixed-rank ASKIT, runs 1-9 analogue: eps against m and s at three bandwidths",
+            "value": None, "unit": None, "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": wl0.name, "kappa": 64, "tau": 0.0, "eps_targets": len(tg)},
+            "trends": trends, "runs": runs}
+
+
+def prune_table_bench(args, A, torch):
+    """Table t:prune: average percentage of tree nodes visited per target under
+    distance pruning (R) and neighbour pruning (kappa), for the curve, Gaussian
+    and hypersphere point sets in 2, 4, 32 and 256 dimensions, N = 65,536,
+    m = 64; kappa = 64 (the paper's 128 is above this library's limit)."""
+    N, m, kappa = 65536, 64, 64
+    gens = {"curve": synth.curve_points, "gaussian": synth.gaussian_points, "hypersphere": synth.sphere_points}
+    rows = {}
+    for kind, gen in gens.items():
+        for d in (2, 4, 32, 256):
+            if kind == "hypersphere" and d < 4:
+                continue
+            X = gen(N, d, 100 + d)
+            prm = A.default_params(leaf_size=m, kappa=kappa, max_skeleton=16, sample_rows=36, id_tol=1e-3,
+                                   bandwidth=1.0, seed=1)
+            t0 = time.perf_counter()
+            h = A.setup(torch.from_numpy(X).cuda(), prm)
+            vk, vd = h.pruning_visits()
+            torch.cuda.synchronize()
+            nn = h.info()["num_nodes"]
+            h.close()
+            rows[f"{kind} {d}D"] = {"R_pct": 100.0 * float(vd.double().mean()) / nn,
+                                    "kappa_pct": 100.0 * float(vk.double().mean()) / nn,
+                                    "seconds": time.perf_counter() - t0}
+            log(f"[prune] {kind} {d}D: {rows[f'{kind} {d}D']}")
+    return {"metric": "Table t:prune: % of tree nodes visited per target, distance vs neighbour pruning",
+            "value": None, "unit": "%", "n_gpus": 1, "data": "synthetic",
+            "config": {"N": N, "m": m, "kappa": kappa}, "table": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fp32_1m", choices=list(WORKLOADS) + ["batched", "approx_knn"])
+    ap.add_argument("--workload", default="fp32_1m", choices=list(WORKLOADS) + ["batched", "approx_knn", "trends_4d", "prune_table"])
     ap.add_argument("--eps-targets", type=int, default=10000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the bounded serving leg of the default run")
@@ -635,6 +718,12 @@ def main():
         return
     if args.workload == "approx_knn":
         print(json.dumps(approx_knn_bench(args, A, torch)))
+        return
+    if args.workload == "trends_4d":
+        print(json.dumps(trends_bench(args, A, torch)))
+        return
+    if args.workload == "prune_table":
+        print(json.dumps(prune_table_bench(args, A, torch)))
         return
     default_run = args.workload == "fp32_1m" and not args.set
     wl = synth.fp32_1m_gate() if default_run else WORKLOADS[args.workload]()

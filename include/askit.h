@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define ASKIT_ABI_VERSION 1u
+#define ASKIT_ABI_VERSION 2u
 
 typedef enum {
     ASKIT_OK = 0,
@@ -71,6 +71,11 @@ typedef struct {
                                bw_neighbor-th nearest neighbour (1-based, <= kappa) */
     int32_t precision;      /* askit_precision */
     uint64_t seed;          /* sampler stream (SplitMix64) seed */
+    int32_t prune_levels;   /* level restriction (Sec. 3, the error discussion): > 0 lets only the
+                               prune_levels deepest tree levels be pruned; a target's traversal
+                               goes on below any node above them, and a leaf it reaches there is
+                               summed directly.  0 (default): every level may be pruned */
+    int32_t reserved;       /* 0 */
 } askit_params;
 
 typedef struct askit_handle askit_handle;
@@ -245,6 +250,19 @@ typedef struct {
 } askit_info;
 
 askit_status askit_get_info(const askit_handle *h, askit_info *out);
+
+/*
+ * Pruning diagnostic (Table t:prune): for every point as a target, the number
+ * of tree nodes the traversal of Alg. 4 visits (a visited node that is pruned
+ * or is a leaf ends its branch; otherwise both children are visited) under
+ * the neighbour rule of Eq. (e:prune), into visits_kappa, and under distance
+ * pruning -- prune a node when the target lies outside the ball centred at the
+ * centroid of the node's points that holds all of them, tested on squared
+ * distances in FP64 -- into visits_dist.  Both device, N int32, original
+ * point order, owned by the caller.  Synchronises `stream`.
+ */
+askit_status askit_pruning_visits(const askit_handle *h, int32_t *visits_kappa, int32_t *visits_dist,
+                                  void *stream);
 
 /* Node record, breadth-first numbering (root = 0, left before right). */
 typedef struct {

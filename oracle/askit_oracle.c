@@ -730,12 +730,17 @@ int or_upward(const or_node *nodes, int64_t nn, const double *Wtree, int R, int 
  * its kappa neighbours; for a new query point, its kappa neighbours.
  * Prune(alpha) holds when no neighbour position lies in [lo, hi).
  * The traversal visits the left child before the right.  Near leaves and
- * pruned nodes are recorded per target (node ids, visit order).        */
+ * pruned nodes are recorded per target (node ids, visit order).
+ * Level restriction (Sec. 3, controlling the growth of the error term:
+ * start the evaluation at a fixed distance from the leaves): with
+ * min_level > 0 a node above that level is never pruned -- the traversal
+ * goes on into its children, and a leaf reached above it is summed directly
+ * (a near leaf although it holds no neighbour).                         */
 typedef struct {
     const float *X; int d; const int32_t *perm; const or_node *nodes;
     const double *hsrc; double h; const float *W; int R;
     const int32_t *S; const int32_t *kout; int smax; const double *Wsk;
-    const float *y; const int32_t *nb; int nnb;
+    const float *y; const int32_t *nb; int nnb; int minlev;
     double *u, *unear;
     int32_t *near_ids; int32_t near_n; int near_cap;
     int32_t *far_ids; int32_t far_n; int far_cap;
@@ -754,7 +759,7 @@ static int node_has_neighbour(const ev_ctx *e, const or_node *nd)
 static void eval_rec(ev_ctx *e, int32_t a)
 {
     const or_node *nd = &e->nodes[a];
-    if (!node_has_neighbour(e, nd)) {                  /* pruned: skeleton */
+    if (!node_has_neighbour(e, nd) && nd->level >= e->minlev) {   /* pruned: skeleton */
         for (int t = 0; t < e->kout[a]; ++t) {
             int32_t o = e->perm[e->S[(int64_t)a * e->smax + t]];
             double kv = kernel_value(sqdist(e->y, e->X + (int64_t)o * e->d, e->d),
@@ -788,13 +793,13 @@ int or_evaluate(const float *Y, int64_t M, const int32_t *nb, int nnb, const flo
                 const int32_t *perm, const or_node *nodes, const double *hsrc, double h,
                 const float *W, int R, const int32_t *S, const int32_t *kout, int smax,
                 const double *Wsk, double *U, double *Unear, int32_t *near_ids, int32_t *near_cnt,
-                int near_cap, int32_t *far_ids, int32_t *far_cnt, int far_cap)
+                int near_cap, int32_t *far_ids, int32_t *far_cnt, int far_cap, int min_level)
 {
     int overflow = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(| : overflow)
     for (int64_t i = 0; i < M; ++i) {
         ev_ctx e = {X, d, perm, nodes, hsrc, h, W, R, S, kout, smax, Wsk,
-                    Y + i * d, nb + i * nnb, nnb, U + i * R, Unear ? Unear + i * R : NULL,
+                    Y + i * d, nb + i * nnb, nnb, min_level, U + i * R, Unear ? Unear + i * R : NULL,
                     near_ids ? near_ids + i * near_cap : NULL, 0, near_ids ? near_cap : 0,
                     far_ids ? far_ids + i * far_cap : NULL, 0, far_ids ? far_cap : 0, 0};
         for (int r = 0; r < R; ++r) {
@@ -807,4 +812,74 @@ int or_evaluate(const float *Y, int64_t M, const int32_t *nb, int nnb, const flo
         if (e.overflow && (near_ids || far_ids)) overflow = 1;
     }
     return overflow ? OR_ENOMEM : OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Pruning diagnostic (Table t:prune): nodes visited by the traversal of
+ * Alg. 4 for each target, under the neighbour rule of Eq. (e:prune) and under
+ * the distance rule the paper compares it with: prune alpha when
+ * |x - c_alpha| > R_alpha, c_alpha the centroid of the node's points and
+ * R_alpha the largest distance from c_alpha to them.  A call on alpha counts
+ * as one visit; a pruned node or a leaf ends the branch, otherwise both
+ * children are visited.
+ * Readings: the distance rule compares squared distances, D(x, c) > R^2,
+ * with R^2 = max D(x_j, c) over the node's points; c is the tree's centroid
+ * (the blocked summation of the tree rule over the node's points in
+ * increasing id); no extra scaling of R.  Targets are the points
+ * themselves; nb holds each target's own position and its neighbours'. */
+static int64_t visits_kappa(const or_node *nodes, const int32_t *nb, int nnb)
+{
+    int32_t stk[128];
+    int top = 0;
+    int64_t v = 0;
+    stk[top++] = 0;
+    while (top > 0) {
+        const or_node *nd = &nodes[stk[--top]];
+        ++v;
+        int has = 0;
+        for (int q = 0; q < nnb && !has; ++q) has = nb[q] >= nd->lo && nb[q] < nd->hi;
+        if (!has || nd->left < 0) continue;
+        stk[top++] = nd->right;
+        stk[top++] = nd->left;
+    }
+    return v;
+}
+
+static int64_t visits_ball(const or_node *nodes, const float *x, int d, const double *cen, const double *r2)
+{
+    int32_t stk[128];
+    int top = 0;
+    int64_t v = 0;
+    stk[top++] = 0;
+    while (top > 0) {
+        int32_t a = stk[--top];
+        const or_node *nd = &nodes[a];
+        ++v;
+        if (sqdist_d(x, cen + (int64_t)a * d, d) > r2[a] || nd->left < 0) continue;
+        stk[top++] = nd->right;
+        stk[top++] = nd->left;
+    }
+    return v;
+}
+
+int or_prune_visits(const float *X, int64_t N, int d, const int32_t *perm, const or_node *nodes, int64_t nn,
+                    const int32_t *nb, int nnb, int32_t *vk, int32_t *vd, double *cen, double *r2)
+{
+    for (int64_t a = 0; a < nn; ++a) {
+        const or_node *nd = &nodes[a];
+        int64_t n = (int64_t)nd->hi - nd->lo;
+        centroid(X, d, perm + nd->lo, n, cen + a * d);
+        double m = 0.0;
+        for (int64_t p = nd->lo; p < nd->hi; ++p) {
+            double D = sqdist_d(X + (int64_t)perm[p] * d, cen + a * d, d);
+            if (D > m) m = D;
+        }
+        r2[a] = m;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        vk[i] = (int32_t)visits_kappa(nodes, nb + i * nnb, nnb);
+        vd[i] = (int32_t)visits_ball(nodes, X + i * d, d, cen, r2);
+    }
+    return OR_OK;
 }

@@ -39,6 +39,7 @@ def lib():
         L.or_knn.argtypes = [P, i64, P, i64, i32, i32, i32, P, P]
         L.or_bandwidth.argtypes = [P, i64, i32, i32, P]
         L.or_rpknn.argtypes = [P, i64, i32, i32, i32, i32, u64, P, P]
+        L.or_prune_visits.argtypes = [P, i64, i32, P, P, i64, P, i32, P, P, P, P]
         L.or_tree_count.argtypes = [i64, i32]
         L.or_tree_count.restype = i64
         L.or_tree.argtypes = [P, i64, i32, i32, P, i64, P]
@@ -52,8 +53,8 @@ def lib():
                                      P, P, P, P, P, P, P]
         L.or_upward.argtypes = [P, i64, P, i32, i32, P, P, i32, P, P, P]
         L.or_evaluate.argtypes = [P, i64, P, i32, P, i32, P, P, P, f64, P, i32, P, P, i32, P,
-                                  P, P, P, P, i32, P, P, i32]
-        for f in ("or_direct", "or_knn", "or_rpknn", "or_bandwidth", "or_tree", "or_node_lists",
+                                  P, P, P, P, i32, P, P, i32, i32]
+        for f in ("or_direct", "or_knn", "or_rpknn", "or_prune_visits", "or_bandwidth", "or_tree", "or_node_lists",
                   "or_sample_rows", "or_gauss_matrix", "or_id", "or_skeletonize", "or_upward",
                   "or_evaluate"):
             getattr(L, f).restype = i32
@@ -249,7 +250,15 @@ class EvalResult:
     far: list             # per target: pruned node ids (visit order)
 
 
-def evaluate(Y, nb, X, perm, nodes, hsrc, h, W, sk: Skeletons, Wsk, smax, record=True):
+def min_prune_level(nodes, prune_levels):
+    """First level whose nodes may be pruned: 0 (every level) when
+    prune_levels is 0, else the prune_levels deepest levels only."""
+    if prune_levels <= 0:
+        return 0
+    return max(1, int(nodes["level"].max()) - prune_levels + 1)
+
+
+def evaluate(Y, nb, X, perm, nodes, hsrc, h, W, sk: Skeletons, Wsk, smax, record=True, min_level=0):
     Y, X = _f32(Y), _f32(X)
     W = _f32(W if W.ndim == 2 else W[:, None])
     nb = np.ascontiguousarray(nb, dtype=np.int32)
@@ -258,8 +267,8 @@ def evaluate(Y, nb, X, perm, nodes, hsrc, h, W, sk: Skeletons, Wsk, smax, record
     U = np.zeros((M, R))
     Un = np.zeros((M, R))
     depth = int(nodes["level"].max()) + 1
-    near_cap = nnb + 1
-    far_cap = (nnb + 1) * depth + 1
+    near_cap = nnb + 1 if min_level == 0 else int((nodes["left"] < 0).sum())
+    far_cap = (nnb + 1) * depth + 1 if min_level == 0 else len(nodes)
     nids = np.zeros((M, near_cap), np.int32) if record else None
     fids = np.zeros((M, far_cap), np.int32) if record else None
     ncnt = np.zeros(M, np.int32)
@@ -270,10 +279,27 @@ def evaluate(Y, nb, X, perm, nodes, hsrc, h, W, sk: Skeletons, Wsk, smax, record
                              _p(W), R, _p(sk.S), _p(sk.k), smax,
                              _p(np.ascontiguousarray(Wsk, np.float64)), _p(U), _p(Un),
                              _p(nids), _p(ncnt), near_cap if record else 0,
-                             _p(fids), _p(fcnt), far_cap if record else 0), "evaluate")
+                             _p(fids), _p(fcnt), far_cap if record else 0, int(min_level)), "evaluate")
     near = [nids[i, :ncnt[i]].copy() for i in range(M)] if record else None
     far = [fids[i, :fcnt[i]].copy() for i in range(M)] if record else None
     return EvalResult(U, Un, near, far)
+
+
+def prune_visits(X, perm, nodes, nb):
+    """Per target (point i, original order; nb row i = position of i and of its
+    neighbours): nodes visited by Alg. 4 under neighbour pruning and under
+    distance pruning (Table t:prune), with the node centroids and squared radii."""
+    X = _f32(X)
+    N, d = X.shape
+    nn = len(nodes)
+    nb = np.ascontiguousarray(nb, dtype=np.int32)
+    vk = np.zeros(N, np.int32)
+    vd = np.zeros(N, np.int32)
+    cen = np.zeros((nn, d))
+    r2 = np.zeros(nn)
+    _check(lib().or_prune_visits(_p(X), N, d, _p(np.ascontiguousarray(perm, np.int32)), _p(nodes), nn, _p(nb),
+                                 nb.shape[1], _p(vk), _p(vd), _p(cen), _p(r2)), "prune_visits")
+    return vk, vd, cen, r2
 
 
 # ---------------------------------------------------------------- driver
@@ -287,10 +313,11 @@ class Params:
     h: float               # fixed bandwidth (ignored when bw_neighbor > 0)
     bw_neighbor: int = 0
     seed: int = 0
+    prune_levels: int = 0  # > 0: only the prune_levels deepest levels may be pruned
 
     @staticmethod
     def from_workload(w):
-        return Params(w.m, w.kappa, w.smax, w.ell_eff, w.tau, w.h, w.bw_neighbor, w.seed)
+        return Params(w.m, w.kappa, w.smax, w.ell_eff, w.tau, w.h, w.bw_neighbor, w.seed, w.prune_levels)
 
 
 def setup(X, p: Params, knn_lists=None):
@@ -331,7 +358,7 @@ def run_askit(X, W, p: Params, targets=None, record=True, knn_lists=None):
     tgt = np.arange(st["N"]) if targets is None else np.asarray(targets)
     nb = self_neighbours(st, tgt)
     ev = evaluate(st["X"][tgt], nb, st["X"], st["perm"], st["nodes"], st["hsrc"], p.h, W,
-                  st["sk"], Wsk, p.smax, record=record)
+                  st["sk"], Wsk, p.smax, record=record, min_level=min_prune_level(st["nodes"], p.prune_levels))
     st.update(W=W, Wsk=Wsk, targets=tgt, ev=ev)
     return st
 
@@ -343,5 +370,6 @@ def query(st, Y, record=True):
     qi, qd = knn(Y, st["X"], st["p"].kappa, exclude_self=False)
     nb = st["iperm"][qi].astype(np.int32)
     ev = evaluate(Y, nb, st["X"], st["perm"], st["nodes"], st["hsrc"], st["p"].h, st["W"],
-                  st["sk"], st["Wsk"], st["p"].smax, record=record)
+                  st["sk"], st["Wsk"], st["p"].smax, record=record,
+                  min_level=min_prune_level(st["nodes"], st["p"].prune_levels))
     return qi, qd, ev

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libaskit.so")
 
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_READY, ERR_UNSUPPORTED, ERR_BUSY = range(7)
 PREC_FP32, PREC_BF16X3 = 0, 1
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 X_PERM, X_KNN_IDX, X_KNN_DIST, X_NODES, X_NLIST_POS, X_NLIST_KEY, X_NLIST_CNT = 1, 2, 3, 4, 5, 6, 7
 X_ROWS, X_ROWS_CNT, X_SKEL, X_SKEL_K, X_COLPERM, X_NCOLS, X_PROJ, X_SKEL_W = 8, 9, 10, 11, 12, 13, 14, 15
@@ -34,7 +34,8 @@ class Params(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("abi_version", C.c_uint32),
                 ("leaf_size", C.c_int32), ("kappa", C.c_int32), ("max_skeleton", C.c_int32),
                 ("sample_rows", C.c_int32), ("id_tol", C.c_double), ("bandwidth", C.c_double),
-                ("bw_neighbor", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64)]
+                ("bw_neighbor", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64),
+                ("prune_levels", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -65,7 +66,7 @@ _lib = None
 
 EXPORTED = ["askit_params_default", "askit_setup", "askit_setup_with_knn", "askit_update_weights",
             "askit_evaluate", "askit_evaluate_parts", "askit_evaluate_weights_noalloc", "askit_knn_rptree",
-            "askit_query", "askit_query_neighbors", "askit_destroy", "askit_last_error", "askit_get_info",
+            "askit_pruning_visits", "askit_query", "askit_query_neighbors", "askit_destroy", "askit_last_error", "askit_get_info",
             "askit_export"]
 
 
@@ -85,6 +86,7 @@ def lib():
         L.askit_evaluate_parts.argtypes = [P, P, i64, P, i64, P]
         L.askit_evaluate_weights_noalloc.argtypes = [P, P, i64, i32, P, i64, P]
         L.askit_knn_rptree.argtypes = [P, i64, i32, i64, i32, i32, i32, C.c_uint64, P, P, P]
+        L.askit_pruning_visits.argtypes = [P, P, P, P]
         L.askit_query.argtypes = [P, P, i64, i64, P, i64, P]
         L.askit_query_neighbors.argtypes = [P, P, i64, i64, P, P, P]
         L.askit_destroy.argtypes = [P]
@@ -115,7 +117,8 @@ def default_params(**kw) -> Params:
 def params_from_workload(w, precision=PREC_FP32) -> Params:
     return default_params(leaf_size=w.m, kappa=w.kappa, max_skeleton=w.smax, sample_rows=w.ell_eff,
                           id_tol=w.tau, bandwidth=w.h if w.h > 0 else 1.0,
-                          bw_neighbor=w.bw_neighbor, precision=precision, seed=w.seed)
+                          bw_neighbor=w.bw_neighbor, precision=precision, seed=w.seed,
+                          prune_levels=w.prune_levels)
 
 
 def _stream(torch):
@@ -194,6 +197,15 @@ class Handle:
                                            C.c_void_p(idx.data_ptr()), C.c_void_p(dist.data_ptr()),
                                            _stream(torch)))
         return idx, dist
+
+    def pruning_visits(self):
+        """(nodes visited per point under neighbour pruning, under distance pruning)."""
+        import torch
+        vk = torch.empty(self.N, device="cuda", dtype=torch.int32)
+        vd = torch.empty(self.N, device="cuda", dtype=torch.int32)
+        _check(lib().askit_pruning_visits(self.ptr, C.c_void_p(vk.data_ptr()), C.c_void_p(vd.data_ptr()),
+                                          _stream(torch)))
+        return vk, vd
 
     def info(self) -> dict:
         i = Info()

@@ -387,6 +387,7 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
     if (p->precision != ASKIT_PREC_FP32 && p->precision != ASKIT_PREC_BF16X3)
         fail(ASKIT_ERR_INVALID_ARG, "unknown precision");
     if (d > 1024) fail(ASKIT_ERR_UNSUPPORTED, "d above 1024 is not supported");
+    if (p->prune_levels < 0) fail(ASKIT_ERR_INVALID_ARG, "need prune_levels >= 0");
     if (knn_in && ldk < p->kappa) fail(ASKIT_ERR_INVALID_ARG, "need ldk >= kappa");
     check_device();
     hipStream_t s = (hipStream_t)stream;
@@ -405,6 +406,7 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
     h->ell = ell;
     h->varh = p->bw_neighbor > 0;
     make_shape(h.get());
+    h->minlev = p->prune_levels > 0 ? std::max(1, h->depth - p->prune_levels + 1) : 0;
     const int64_t nn = (int64_t)h->nodes.size();
     const int dp = h->dp, kappa = h->kappa;
 
@@ -752,6 +754,14 @@ void askit_destroy(askit_handle *h)
     if (!h) return;
     (void)hipDeviceSynchronize();
     delete h;
+}
+
+askit_status askit_pruning_visits(const askit_handle *h, int32_t *visits_kappa, int32_t *visits_dist, void *stream)
+{
+    API_BEGIN
+    if (!h || !visits_kappa || !visits_dist) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
+    prune_visits(h, visits_kappa, visits_dist, (hipStream_t)stream);
+    API_END
 }
 
 askit_status askit_get_info(const askit_handle *h, askit_info *o)

@@ -155,6 +155,7 @@ struct askit_handle {
     int d = 0, dp = 0;                 // dp: coordinate stride (d rounded up to 16)
     askit_params prm{};
     int kappa = 0, m = 0, smax = 0, ell = 0, ncol_max = 0;
+    int minlev = 0;                    // first level whose nodes may be pruned (level restriction)
     bool varh = false;
     float maxnorm = 0.0f;              // largest FP32 squared norm of the points
     int device = 0;
@@ -260,6 +261,8 @@ float max_norm(const float *nrm, int64_t N, hipStream_t s);
 
 // tree.hip
 void build_tree(askit_handle *h, hipStream_t s);
+// nodes visited per target (original order) under neighbour and distance pruning
+void prune_visits(const askit_handle *h, int32_t *vk, int32_t *vd, hipStream_t s);
 // approximate kappa nearest neighbours by iterated random projection trees
 // (Xo: N x dp points, original order); idx/dist: N x kappa, sorted by (distance, id)
 void rp_knn(const float *Xo, int64_t N, int d, int dp, int kappa, int leaf, int iters, uint64_t seed,

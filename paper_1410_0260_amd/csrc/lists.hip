@@ -354,7 +354,7 @@ __global__ __launch_bounds__(64 * NW) void k_interactions(const Node *__restrict
                                                           const int32_t *__restrict__ ptr, int64_t nslab,
                                                           int32_t *__restrict__ out_node,
                                                           uint64_t *__restrict__ out_mask,
-                                                          int32_t *__restrict__ cntw)
+                                                          int32_t *__restrict__ cntw, int minlev)
 {
     extern __shared__ uint32_t sh[];
     __shared__ int nm[64];
@@ -430,12 +430,42 @@ __global__ __launch_bounds__(64 * NW) void k_interactions(const Node *__restrict
                     Node cn = nodes[ch[c]];
                     bool f = in_a && !has_nb(mine, nmine, cn.lo, cn.hi);
                     uint64_t m = __ballot(f);
-                    if (m) {
+                    if (!m) continue;
+                    if (cn.level >= minlev) {
                         if (mode && lane == 0) {
                             out_node[of + kf] = ch[c];
                             out_mask[of + kf] = m;
                         }
                         ++kf;
+                        continue;
+                    }
+                    // level restriction: a node above the first prunable level
+                    // is not pruned; its subtree holds no neighbour of the rows
+                    // in m, so they take its descendants on that level as far
+                    // nodes and its leaves above that level as near leaves
+                    // (depth first, left before right; uniform in the wave)
+                    int stk[64];
+                    int top = 0;
+                    stk[top++] = ch[c];
+                    while (top > 0) {
+                        const int b = stk[--top];
+                        const Node bn = nodes[b];
+                        if (bn.level >= minlev) {
+                            if (mode && lane == 0) {
+                                out_node[of + kf] = b;
+                                out_mask[of + kf] = m;
+                            }
+                            ++kf;
+                        } else if (bn.left < 0) {
+                            if (mode && lane == 0) {
+                                out_node[on + kn] = b;
+                                out_mask[on + kn] = m;
+                            }
+                            ++kn;
+                        } else {
+                            stk[top++] = bn.right;
+                            stk[top++] = bn.left;
+                        }
                     }
                 }
             }
@@ -508,10 +538,12 @@ static void run_interactions(askit_handle *h, const Slab *d_slabs, int64_t nslab
     auto launch = [&](int mode, int32_t *cn, int32_t *cf, const int32_t *pp, int32_t *on, uint64_t *om) {
         if (wide)
             hipLaunchKernelGGL(k_interactions<4>, dim3((unsigned)nslab), dim3(256), shb, s, h->d_nodes, nn,
-                               h->leaf_of, d_slabs, nbpos, nnb, mode, cn, cf, pp, nslab, on, om, cntw);
+                               h->leaf_of, d_slabs, nbpos, nnb, mode, cn, cf, pp, nslab, on, om, cntw,
+                               h->minlev);
         else
             hipLaunchKernelGGL(k_interactions<1>, dim3((unsigned)nslab), dim3(64), shb, s, h->d_nodes, nn,
-                               h->leaf_of, d_slabs, nbpos, nnb, mode, cn, cf, pp, nslab, on, om, cntw);
+                               h->leaf_of, d_slabs, nbpos, nnb, mode, cn, cf, pp, nslab, on, om, cntw,
+                               h->minlev);
         HIPC(hipGetLastError());
     };
     launch(0, cnt, cnt + nslab + 1, nullptr, nullptr, nullptr);

@@ -432,6 +432,135 @@ void build_tree(askit_handle *h, hipStream_t s)
 }
 
 
+// ---------------------------------------------------------------- pruning diagnostic
+// Nodes visited by the traversal of Alg. 4 per target under the neighbour rule
+// (Eq. e:prune) and under distance pruning (prune alpha when the target lies
+// outside the ball around the node's centroid that holds all its points), the
+// comparison of Table t:prune.  Centroids use the tree's blocked summation
+// over each node's points (increasing id); the ball test compares squared
+// distances, D(x, c) > R^2, with R^2 = max D(x_j, c) over the node.
+__global__ __launch_bounds__(256) void k_node_r2(const float *__restrict__ X, int dp, int d,
+                                                 const int32_t *__restrict__ perm, const Split *__restrict__ sp,
+                                                 const int32_t *__restrict__ ids, const double *__restrict__ cen,
+                                                 double *__restrict__ r2)
+{
+    __shared__ double sm[256];
+    const int q = blockIdx.x;
+    const Split s = sp[q];
+    const int a = ids[q];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < s.n; i += 256)
+        m = fmax(m, canon_sqdist_c(X + (int64_t)perm[s.lo + i] * dp, cen + (int64_t)q * d, d));
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) r2[a] = sm[0];
+}
+
+__global__ void k_scatter_cen(const double *__restrict__ cen_q, const int32_t *__restrict__ ids, int nq, int d,
+                              double *__restrict__ cen)
+{
+    const int q = blockIdx.x;
+    if (q >= nq) return;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) cen[(int64_t)ids[q] * d + k] = cen_q[(int64_t)q * d + k];
+}
+
+__global__ __launch_bounds__(128) void k_prune_visits(const float *__restrict__ X, int dp, int d, int64_t N,
+                                                      const Node *__restrict__ nodes, const int32_t *__restrict__ iperm,
+                                                      const int32_t *__restrict__ knn_idx, int kappa,
+                                                      const double *__restrict__ cen, const double *__restrict__ r2,
+                                                      int32_t *__restrict__ vk, int32_t *__restrict__ vd)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int32_t nb[65];
+    nb[0] = iperm[i];
+    for (int t = 0; t < kappa; ++t) nb[1 + t] = iperm[knn_idx[i * kappa + t]];
+    const int nnb = kappa + 1;
+    const float *x = X + i * dp;
+    int32_t stk[128];
+    for (int rule = 0; rule < 2; ++rule) {
+        int top = 0, v = 0;
+        stk[top++] = 0;
+        while (top > 0) {
+            const int a = stk[--top];
+            const Node nd = nodes[a];
+            ++v;
+            bool prune;
+            if (rule == 0) {
+                bool has = false;
+                for (int q = 0; q < nnb; ++q) has |= nb[q] >= nd.lo && nb[q] < nd.hi;
+                prune = !has;
+            } else {
+                prune = canon_sqdist_c(x, cen + (int64_t)a * d, d) > r2[a];
+            }
+            if (prune || nd.left < 0) continue;
+            stk[top++] = nd.right;
+            stk[top++] = nd.left;
+        }
+        (rule == 0 ? vk : vd)[i] = v;
+    }
+}
+
+void prune_visits(const askit_handle *h, int32_t *vk, int32_t *vd, hipStream_t s)
+{
+    const int d = h->d, dp = h->dp;
+    const int64_t nn = (int64_t)h->nodes.size();
+    std::vector<void *> tmp;
+    struct Guard {
+        std::vector<void *> &t;
+        hipStream_t s;
+        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+    } guard{tmp, s};
+    auto ta = [&](size_t b) {
+        void *p;
+        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        tmp.push_back(p);
+        return p;
+    };
+    int64_t maxq = 1;
+    for (auto &lv : h->level_nodes) maxq = std::max<int64_t>(maxq, (int64_t)lv.size());
+    const int64_t blk_total = (h->N + 63) / 64 + 2 * maxq;
+    Split *d_sp = (Split *)ta(sizeof(Split) * maxq);
+    int32_t *d_ids = (int32_t *)ta(sizeof(int32_t) * maxq);
+    double *bsum = (double *)ta(sizeof(double) * blk_total * d + 64);
+    double *cen_q = (double *)ta(sizeof(double) * maxq * d);
+    double *cen = (double *)ta(sizeof(double) * nn * d);
+    double *r2 = (double *)ta(sizeof(double) * nn);
+    std::vector<Split> hsp;
+    std::vector<int32_t> hids;
+    for (const auto &lv : h->level_nodes) {
+        hsp.clear();
+        hids.clear();
+        int maxn = 0;
+        for (int a : lv) {
+            const Node &nd = h->nodes[a];
+            hsp.push_back(Split{nd.lo, nd.hi - nd.lo});
+            hids.push_back(a);
+            maxn = std::max(maxn, nd.hi - nd.lo);
+        }
+        const int nq = (int)hsp.size();
+        if (nq == 0) continue;
+        HIPC(hipMemcpyAsync(d_sp, hsp.data(), sizeof(Split) * nq, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(d_ids, hids.data(), sizeof(int32_t) * nq, hipMemcpyHostToDevice, s));
+        const int maxblk = (maxn + 63) / 64;
+        hipLaunchKernelGGL(k_block_sums, dim3(maxblk, nq), dim3(64), 0, s, h->Xo, dp, d, h->perm, d_sp, maxblk, bsum);
+        hipLaunchKernelGGL(k_centroid, dim3(nq), dim3(std::min(256, round_up(d, 64))), 0, s, bsum, d_sp, maxblk, d,
+                           cen_q);
+        hipLaunchKernelGGL(k_node_r2, dim3(nq), dim3(256), 0, s, h->Xo, dp, d, h->perm, d_sp, d_ids, cen_q, r2);
+        hipLaunchKernelGGL(k_scatter_cen, dim3(nq), dim3(64), 0, s, cen_q, d_ids, nq, d, cen);
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize(s));          // host tables are reused by the next level
+    }
+    hipLaunchKernelGGL(k_prune_visits, dim3((unsigned)((h->N + 127) / 128)), dim3(128), 0, s, h->Xo, dp, d, h->N,
+                       h->d_nodes, h->iperm, h->knn_idx, h->kappa, cen, r2, vk, vd);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(s));
+}
+
 // ---------------------------------------------------------------- approximate neighbours
 // Greedy search with random projection trees (Sec. 2.2, "Computing nearest
 // neighbors"): each iteration builds a tree whose nodes split at the median of

@@ -40,6 +40,7 @@ class Workload:
     seed: int
     bw_neighbor: int = 0   # variable bandwidth: h_j = distance to this neighbour (1-based)
     spread: float = 3.0    # component means ~ spread * N(0, I_q)
+    prune_levels: int = 0  # > 0: only the prune_levels deepest tree levels may be pruned
     extra: dict = field(default_factory=dict)
 
     @property
@@ -75,6 +76,38 @@ def mixture_points(N: int, d: int, q: int, n_comp: int, noise_var: float, seed: 
         b = min(N, a + chunk)
         X[a:b] = (z[a:b] @ Qm.T + sd * g.standard_normal((b - a, d))).astype(np.float32)
     return X
+
+
+# ---------------------------------------------------------------------------
+# Point sets of the pruning comparison (Table t:prune).
+# ---------------------------------------------------------------------------
+
+def curve_points(N: int, d: int, seed: int) -> np.ndarray:
+    """The paper's curve: x_i = f(i pi t), t uniform in [0, 1], i = 1..d, f = cos
+    for odd i and sin for even i (intrinsic dimension one)."""
+    t = np.random.default_rng(seed).random(N)
+    i = np.arange(1, d + 1)
+    arg = np.pi * t[:, None] * i[None, :]
+    return np.where(i % 2 == 1, np.cos(arg), np.sin(arg)).astype(np.float32)
+
+
+def gaussian_points(N: int, d: int, seed: int) -> np.ndarray:
+    """Standard normal points in d dimensions (intrinsic dimension d)."""
+    return np.random.default_rng(seed).standard_normal((N, d)).astype(np.float32)
+
+
+def sphere_points(N: int, d: int, seed: int) -> np.ndarray:
+    """Points uniform on the unit sphere S^4 of a random 5-dim subspace
+    (intrinsic dimension four) for d >= 5; for d = 4, uniform on S^3."""
+    g = np.random.default_rng(seed)
+    k = 5 if d >= 5 else d
+    z = g.standard_normal((N, k))
+    z /= np.linalg.norm(z, axis=1, keepdims=True)
+    if k == d:
+        return z.astype(np.float32)
+    Q, Rm = np.linalg.qr(g.standard_normal((d, k)))
+    Q = Q * np.sign(np.diag(Rm))[None, :]
+    return (z @ Q.T).astype(np.float32)
 
 
 def weights(N: int, R: int, seed: int) -> np.ndarray:

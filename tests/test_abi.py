@@ -29,9 +29,9 @@ def test_header_symbols_exported():
 def test_params_struct_layout():
     A = _lib()
     p = A.default_params()
-    assert p.struct_size == C.sizeof(A.Params) == 56
+    assert p.struct_size == C.sizeof(A.Params) == 64
     assert p.abi_version == A.ABI_VERSION
-    assert p.leaf_size == 128 and p.kappa == 16 and p.max_skeleton == 64
+    assert p.leaf_size == 128 and p.kappa == 16 and p.max_skeleton == 64 and p.prune_levels == 0
 
 
 def _setup(A, N=100, d=3, ldx=3, **kw):
@@ -54,6 +54,7 @@ def _setup(A, N=100, d=3, ldx=3, **kw):
     (dict(bw_neighbor=17), "bw_neighbor <= kappa"),
     (dict(id_tol=-1.0), "id_tol"),
     (dict(precision=7), "unknown precision"),
+    (dict(prune_levels=-1), "prune_levels >= 0"),
 ])
 def test_invalid_arguments(kw, msg):
     A = _lib()

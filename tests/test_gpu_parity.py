@@ -22,7 +22,8 @@ def gparams(p: O.Params, precision=0):
     from paper_1410_0260_amd import askit as A
     return A.default_params(leaf_size=p.m, kappa=p.kappa, max_skeleton=p.smax, sample_rows=p.ell,
                             id_tol=p.tau, bandwidth=p.h if p.h > 0 else 1.0,
-                            bw_neighbor=p.bw_neighbor, precision=precision, seed=p.seed)
+                            bw_neighbor=p.bw_neighbor, precision=precision, seed=p.seed,
+                            prune_levels=p.prune_levels)
 
 
 CASES = {
@@ -41,6 +42,11 @@ CASES = {
     # l above half the outside pool: most nodes draw their rows by the
     # shuffled-pool branch of the sampler (pool <= 2r)
     "small-pool": (300, 5, 3, 3, O.Params(m=32, kappa=8, smax=64, ell=160, tau=1e-6, h=0.9, seed=17)),
+    # the paper's fixed-rank mode: tau = 0, rank s at every node
+    "fixed-rank": (3000, 6, 4, 3, O.Params(m=64, kappa=16, smax=16, ell=36, tau=0.0, h=0.6, seed=29)),
+    # level restriction: only the two deepest levels may be pruned
+    "level-restricted": (5000, 10, 4, 5, O.Params(m=64, kappa=12, smax=32, ell=52, tau=1e-6, h=0.8, seed=23,
+                                                 prune_levels=2)),
 }
 SPREAD = {"wide-fallback": 30.0}
 
@@ -119,6 +125,23 @@ def test_skeletons(case):
             ties += 1
     assert ties == 0
     assert np.array_equal(g["ncols"], sk.ncols)
+
+
+def test_fixed_rank_mode(case):
+    """tau = 0 keeps rank s at a node (the paper fixes s, Sec. 3) unless the
+    sampled block has fewer rows or columns, or is numerically rank deficient
+    (a pivot |R_tt| at rounding level, 64 eps |R_00|): then the oracle stops at
+    the same rank (the skeleton test compares every node)."""
+    name, X, W, p, st, g = case
+    if name != "fixed-rank":
+        pytest.skip("fixed-rank case only")
+    nn = len(st["nodes"])
+    cap = np.array([min(p.smax, st["T_cnt"][a], st["sk"].ncols[a]) for a in range(1, nn)])
+    k = g["k"][1:]
+    assert np.array_equal(k, st["sk"].k[1:]) and (k <= cap).all()
+    full = float((k == cap).mean())
+    print(f"[fixed-rank] nodes at rank min(s, rows, cols): {full:.3f}", flush=True)
+    assert full >= 0.8
 
 
 def test_projection_close(case):

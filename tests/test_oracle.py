@@ -456,6 +456,103 @@ def test_partition_and_count_bounds():
         assert all(nodes[a]["left"] < 0 for a in st["ev"].near[i])
 
 
+# ------------------------------------------- level restriction (Sec. 3, error discussion)
+def test_level_restriction_partition_and_levels():
+    """With only the L deepest levels prunable, every target's near leaves and
+    pruned nodes still partition the sources exactly once, every pruned node
+    lies on a prunable level, and each target visits at least as many nodes
+    as with a looser restriction (a node above the limit is replaced by its
+    descendants).  L >= depth is no restriction at all."""
+    N = 1500
+    X = small(N)
+    W = synth.weights(N, 1, 5)
+    base = O.run_askit(X, W, base_params())
+    nodes = base["nodes"]
+    depth = int(nodes["level"].max())
+    prev = None
+    for L in (depth, 3, 2, 1):
+        st = O.run_askit(X, W, base_params(prune_levels=L))
+        minlev = O.min_prune_level(nodes, L)
+        assert minlev == max(1, depth - L + 1)
+        counts = []
+        for i in range(0, N, 7):
+            cover = np.zeros(N, int)
+            for a in list(st["ev"].near[i]) + list(st["ev"].far[i]):
+                cover[nodes[a]["lo"]:nodes[a]["hi"]] += 1
+            assert (cover == 1).all()
+            assert all(nodes[a]["level"] >= minlev for a in st["ev"].far[i])
+            assert all(nodes[a]["left"] < 0 for a in st["ev"].near[i])
+            counts.append(len(st["ev"].near[i]) + len(st["ev"].far[i]))
+        counts = np.array(counts)
+        if L == depth:
+            assert np.array_equal(st["ev"].U, base["ev"].U)
+        if prev is not None:
+            assert (counts >= prev).all() and (counts > prev).any()
+        prev = counts
+
+
+def test_level_restriction_exact_skeletons_reproduce_direct():
+    """Exact IDs (every outside point sampled, tau = 0): the restricted
+    evaluation is the direct sum as well, through leaves summed above the
+    limit and skeletons below it."""
+    X = small(162)
+    W = synth.weights(162, 1, 4)
+    # 162 points, m = 40: leaves of 40 on level 2 and of 20-21 on level 3
+    e, st = _eps(X, W, base_params(m=40, kappa=3, ell=162, smax=162, tau=0.0, prune_levels=1))
+    assert e < 1e-11
+    nodes = st["nodes"]
+    assert {int(nodes[a]["level"]) for a in range(len(nodes)) if nodes[a]["left"] < 0} == {2, 3}
+    nb = O.self_neighbours(st, np.arange(162))
+
+    def holds_none(i, a):
+        return not ((nb[i] >= nodes[a]["lo"]) & (nb[i] < nodes[a]["hi"])).any()
+
+    # leaves that hold no neighbour of the target, summed directly above the limit
+    assert sum(holds_none(i, a) for i in range(162) for a in st["ev"].near[i]) > 0
+
+
+# ------------------------------------------------ pruning comparison (Table t:prune)
+@pytest.mark.parametrize("kind,d", [("curve", 2), ("gaussian", 4), ("sphere", 32)])
+def test_prune_visits_against_set_definitions(kind, d):
+    """Visits under neighbour pruning = 1 + 2 x (internal nodes holding the
+    target or one of its neighbours); under distance pruning a node is visited
+    iff no proper ancestor has the target outside its ball, which is counted
+    here over all nodes at once.  Centroids are the node means, radii the
+    largest distances."""
+    N, m, kappa = 1500, 32, 12
+    X = {"curve": synth.curve_points, "gaussian": synth.gaussian_points, "sphere": synth.sphere_points}[kind](
+        N, d, 3)
+    idx, dist = O.knn(X, X, kappa, exclude_self=True)
+    nodes, perm = O.tree(X, m)
+    iperm = np.empty(N, np.int32)
+    iperm[perm] = np.arange(N, dtype=np.int32)
+    nb = np.concatenate([iperm[:, None], iperm[idx]], axis=1)
+    vk, vd, cen, r2 = O.prune_visits(X, perm, nodes, nb)
+    X64 = X.astype(np.float64)
+    internal = np.nonzero(nodes["left"] >= 0)[0]
+    holds = np.zeros((N, len(nodes)), bool)
+    for a in range(len(nodes)):
+        lo, hi = nodes[a]["lo"], nodes[a]["hi"]
+        pts = X64[perm[lo:hi]]
+        assert np.allclose(cen[a], pts.mean(0), rtol=1e-12, atol=1e-12)
+        Dn = np.cumsum((pts - cen[a]) ** 2, axis=1)[:, -1]
+        assert r2[a] == Dn.max()
+        holds[:, a] = ((nb >= lo) & (nb < hi)).any(1)
+    assert np.array_equal(vk, 1 + 2 * holds[:, internal].sum(1))
+    inside = np.empty((N, len(nodes)), bool)
+    for a in range(len(nodes)):
+        inside[:, a] = np.cumsum((X64 - cen[a]) ** 2, axis=1)[:, -1] <= r2[a]
+    visited = np.zeros((N, len(nodes)), bool)
+    visited[:, 0] = True
+    for a in range(1, len(nodes)):                  # parents have smaller ids
+        par = nodes[a]["parent"]
+        visited[:, a] = visited[:, par] & inside[:, par]
+    assert np.array_equal(vd, visited.sum(1))
+    depth_leaf = nodes["level"][[np.nonzero((nodes["left"] < 0) & (nodes["lo"] <= iperm[i]) &
+                                            (iperm[i] < nodes["hi"]))[0][0] for i in range(N)]]
+    assert (vd >= 1 + 2 * depth_leaf).all()        # a node never prunes a point of its own
+
+
 def test_error_falls_as_id_tolerance_tightens():
     w = synth.small_fp64()
     X = synth.points(w)[:2048]
