@@ -801,7 +801,8 @@ def main():
         "roofline_eval": eval_roof,
         "queries": r["queries"],
         "counts": {k: info[k] for k in ("num_nodes", "num_leaves", "depth", "near_pairs", "far_pairs",
-                                        "knn_uncertified_rows", "knn_retry_rows", "eval_pairs", "eval_chunks")},
+                                        "knn_uncertified_rows", "knn_retry_rows", "eval_pairs", "eval_chunks",
+                                        "knn_tiles_swept")},
     })
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")

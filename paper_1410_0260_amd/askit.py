@@ -50,7 +50,7 @@ class Info(C.Structure):
                 ("t_knn_sweep_ms", C.c_double), ("t_qr_ms", C.c_double),
                 ("t_knn_filter_ms", C.c_double), ("knn_filter_launches", C.c_int64),
                 ("eval_pairs", C.c_int64), ("eval_chunks", C.c_int64), ("knn_retry_rows", C.c_int64),
-                ("near_lists", C.c_int64), ("far_lists", C.c_int64)]
+                ("near_lists", C.c_int64), ("far_lists", C.c_int64), ("knn_tiles_swept", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -3,6 +3,7 @@
 #include "askit_impl.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -495,16 +496,42 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
         hipEvent_t k0, k1;
         HIPC(hipEventCreate(&k0));
         HIPC(hipEventCreate(&k1));
+        // the search sweeps the points in a finer order than the tree's (leaves
+        // split on into cells of at most 64 points): compact tiles, so far
+        // (row block, tile) pairs are skipped; results are ids and exact
+        // distances, independent of the order
+        const bool fine = h->depth > 0 && N > 64 * 64 && !std::getenv("ASKIT_KNN_TREE_ORDER");
+        int32_t *perm_f = h->perm;
+        float *Xt_f = h->Xt, *Xn_f = h->Xn;
+        uint16_t *Xh_f = h->Xh, *Xl_f = h->Xl;
+        if (fine) {
+            HIPC(hipMallocAsync((void **)&perm_f, sizeof(int32_t) * N, s));
+            HIPC(hipMallocAsync((void **)&Xt_f, sizeof(float) * N * dp, s));
+            HIPC(hipMallocAsync((void **)&Xn_f, sizeof(float) * N, s));
+            HIPC(hipMallocAsync((void **)&Xh_f, sizeof(uint16_t) * N * dp, s));
+            HIPC(hipMallocAsync((void **)&Xl_f, sizeof(uint16_t) * N * dp, s));
+            build_fine_order(h.get(), 64, perm_f, s);
+            gather_rows(h->Xo, perm_f, N, dp, Xt_f, s);
+            split_bf16(Xt_f, N, dp, Xh_f, Xl_f, Xn_f, s);
+        }
         HIPC(hipEventRecord(k0, s));
         float fms = 0.f;
-        knn_candidates(h->Xh, h->Xl, h->Xn, N, h->Xh, h->Xl, h->Xn, N, dp, true, true, cand, thr,
+        knn_candidates(Xh_f, Xl_f, Xn_f, N, Xh_f, Xl_f, Xn_f, N, dp, true, true, cand, thr,
                        bad + 1, bad, s, &fms, &h->knn_filter_launches, &h->knn_retry_rows, &h->ksamp,
-                       &h->knn_retry_list);
+                       &h->knn_retry_list, Xt_f, d, &h->knn_tiles_swept);
         h->t_knn_filter = fms;
         HIPC(hipEventRecord(k1, s));
+        if (fine && !h->knn_retry_list.empty()) {
+            // retried rows are reported as tree positions
+            std::vector<int32_t> pf(N), ip(N);
+            HIPC(hipMemcpyAsync(pf.data(), perm_f, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
+            HIPC(hipMemcpyAsync(ip.data(), h->iperm, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            for (int32_t &r : h->knn_retry_list) r = ip[pf[r]];
+        }
         float *tb;
         HIPC(hipMallocAsync((void **)&tb, sizeof(float) * N, s));
-        knn_refine(h->Xt, N, h->Xt, N, d, dp, kappa, cand, thr, h->Xn, mx, h->perm, h->perm,
+        knn_refine(Xt_f, N, Xt_f, N, d, dp, kappa, cand, thr, Xn_f, mx, perm_f, perm_f,
                    h->knn_idx, h->knn_d, bad + 1, bad, tb, s);
         int32_t nbad = 0;
         HIPC(hipMemcpyAsync(&nbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -515,9 +542,16 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
         h->t_knn_sweep = kms;
         (void)hipEventDestroy(k0);
         (void)hipEventDestroy(k1);
-        knn_fallback(h->Xt, h->Xh, h->Xl, h->Xn, h->Xt, h->Xh, h->Xl, h->Xn, N, d, dp, kappa, true, bad + 1, nbad,
-                     tb, h->perm, h->perm, h->knn_idx, h->knn_d, s);
+        knn_fallback(Xt_f, Xh_f, Xl_f, Xn_f, Xt_f, Xh_f, Xl_f, Xn_f, N, d, dp, kappa, true, bad + 1, nbad,
+                     tb, perm_f, perm_f, h->knn_idx, h->knn_d, s);
         HIPC(hipFreeAsync(tb, s));
+        if (fine) {
+            HIPC(hipFreeAsync(perm_f, s));
+            HIPC(hipFreeAsync(Xt_f, s));
+            HIPC(hipFreeAsync(Xn_f, s));
+            HIPC(hipFreeAsync(Xh_f, s));
+            HIPC(hipFreeAsync(Xl_f, s));
+        }
         HIPC(hipFreeAsync(cand, s));
         HIPC(hipFreeAsync(thr, s));
         HIPC(hipFreeAsync(bad, s));
@@ -806,6 +840,7 @@ askit_status askit_get_info(const askit_handle *h, askit_info *o)
     o->eval_chunks = h->pairs.nchunk;
     o->knn_retry_rows = h->knn_retry_rows;
     o->t_qr_ms = h->t_qr;
+    o->knn_tiles_swept = h->knn_tiles_swept;
     o->near_lists = h->pairs.near_lists;
     o->far_lists = h->pairs.far_lists;
     API_END

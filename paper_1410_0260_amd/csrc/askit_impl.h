@@ -209,6 +209,7 @@ struct askit_handle {
     double t_knn = 0, t_tree = 0, t_lists = 0, t_skel = 0, t_inter = 0, t_update = 0;
     double t_knn_sweep = 0, t_qr = 0, t_knn_filter = 0;
     int knn_filter_launches = 0, knn_retry_rows = 0;
+    int64_t knn_tiles_swept = -1;      // (row block, tile) pairs of the symmetric sweep; -1: no skipping
     std::vector<int32_t> knn_retry_list;   // their tree positions
     hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr;
     bool up_pending = false;
@@ -239,7 +240,8 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
                     bool exclude_self, bool start_local, int32_t *cand, float *thr,
                     int32_t *bad_rows, int32_t *bad_count, hipStream_t s,
                     float *t_filter_ms = nullptr, int *n_filter = nullptr, int *n_retry = nullptr,
-                    const KnnSample *samp = nullptr, std::vector<int32_t> *retry_rows = nullptr);
+                    const KnnSample *samp = nullptr, std::vector<int32_t> *retry_rows = nullptr,
+                    const float *Xf = nullptr, int d = 0, int64_t *tiles_swept = nullptr);
 // Fills h->ksamp from the tree-ordered bf16 points when the point set is large
 // enough for the sampled query search (allocations owned by the handle).
 void knn_build_sample(askit_handle *h, hipStream_t s);
@@ -261,6 +263,9 @@ float max_norm(const float *nrm, int64_t N, hipStream_t s);
 
 // tree.hip
 void build_tree(askit_handle *h, hipStream_t s);
+// refinement of the tree order (leaves split on until cells of <= mfine points)
+// used as the sweep order of the neighbour search
+void build_fine_order(const askit_handle *h, int mfine, int32_t *perm_f, hipStream_t s);
 // nodes visited per target (original order) under neighbour and distance pruning
 void prune_visits(const askit_handle *h, int32_t *vk, int32_t *vd, hipStream_t s);
 // approximate kappa nearest neighbours by iterated random projection trees

@@ -15,6 +15,7 @@
 #include "askit_impl.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 namespace askit {
@@ -550,7 +551,9 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
                                                        const float *__restrict__ Tin,
                                                        int cap, int32_t *__restrict__ ocnt,
                                                        float *__restrict__ od,
-                                                       int32_t *__restrict__ oi, int win_tiles)
+                                                       int32_t *__restrict__ oi, int win_tiles,
+                                                       const int32_t *__restrict__ tlist,
+                                                       const int64_t *__restrict__ toff)
 {
     constexpr int DP = KS * 16;
     constexpr int LDB = DP + 8;
@@ -559,6 +562,7 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     __shared__ __attribute__((aligned(16))) uint16_t sBl[3 * TB];
     __shared__ float sBn[3 * KB_N];
     __shared__ float sBt[SYM ? 3 * KB_N : 1];       // SYM: thresholds of the tile's points
+    __shared__ int sTile[3];                          // tile held by each buffer
 
     const int tid = threadIdx.x, lane = tid % WAVE;
     const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
@@ -606,6 +610,13 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
         t0 = (int64_t)blockIdx.y * per;
         ntiles = t0 < ntiles_all ? min(per, ntiles_all - t0) : 0;
     }
+    // SYM with tile lists: only the tiles that may hold a survivor (the block's
+    // own two first), in increasing order
+    const int32_t *tl = nullptr;
+    if (SYM && tlist) {
+        tl = tlist + toff[blockIdx.x];
+        ntiles = toff[blockIdx.x + 1] - toff[blockIdx.x];
+    }
     if (ntiles <= 0) return;
     // tile counts fit 32 bits (N < 2^31 points)
     const int nt32 = (int)ntiles, t032 = (int)t0, nta32 = (int)ntiles_all;
@@ -614,6 +625,9 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     uint4 rh[1][PER], rl[1][PER];
     float rn[1] = {0.0f};
     auto tile_of = [&](int t) -> int {
+        if constexpr (SYM) {
+            if (tl) return tl[t];
+        }
         const int tt = t032 + t;
         return tt >= nta32 ? tt - nta32 : tt;
     };
@@ -648,15 +662,19 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], bh1, acc1, 0, 0, 0);
         }
     };
-    load_tile(0, tile_of(0));
-    load_thr(tile_of(0));
+    int tnext = tile_of(0);                 // tile of the next load (kept in a register)
+    load_tile(0, tnext);
+    load_thr(tnext);
     store_tile(0, 0);
     store_thr(0);
+    if (tid == 0) sTile[0] = tnext;
     if (ntiles > 1) {
-        load_tile(0, tile_of(1));
-        load_thr(tile_of(1));
+        tnext = tile_of(1);
+        load_tile(0, tnext);
+        load_thr(tnext);
         store_tile(0, 1);
         store_thr(1);
+        if (tid == 0) sTile[1] = tnext;
     }
     __syncthreads();
     f32x16 accA0, accA1, accB0, accB1;
@@ -664,10 +682,11 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     // iteration t: accumulators of tile t ready; MFMAs of tile t+1 read buffer
     // (t+1)%3; the points of tile t+2 are loaded and stored to buffer (t+2)%3
     auto iter = [&](auto CUR, int t, f32x16 &c0, f32x16 &c1, f32x16 &n0, f32x16 &n1) {
-        const int tbase = tile_of(t) * KB_N;
+        const int tbase = sTile[t % 3] * KB_N;
         if (t + 2 < nt32) {
-            load_tile(0, tile_of(t + 2));
-            load_thr(tile_of(t + 2));
+            tnext = tile_of(t + 2);
+            load_tile(0, tnext);
+            load_thr(tnext);
         }
         if (t + 1 < nt32) mfma_tile((t + 1) % 3, n0, n1);
         // <= keeps the window's own 64 points (same arithmetic as the window pass)
@@ -756,6 +775,7 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
         if (t + 2 < nt32) {
             store_tile(0, (t + 2) % 3);
             store_thr((t + 2) % 3);
+            if (tid == 0) sTile[(t + 2) % 3] = tnext;
         }
         __syncthreads();
     };
@@ -933,14 +953,15 @@ template <int KS>
 static void launch_filter(dim3 g, dim3 b, hipStream_t s, const uint16_t *Qh, const uint16_t *Ql,
                           const float *Qn, int64_t M, const uint16_t *Xh, const uint16_t *Xl,
                           const float *Xn, int64_t N, int ex, int64_t row0, const float *T, int cap,
-                          int32_t *ocnt, float *od, int32_t *oi, bool sym, int win = 0)
+                          int32_t *ocnt, float *od, int32_t *oi, bool sym, int win = 0,
+                          const int32_t *tlist = nullptr, const int64_t *toff = nullptr)
 {
     if (sym)
         hipLaunchKernelGGL((k_knn_filter<KS, true>), g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, row0, T, cap,
-                           ocnt, od, oi, 0);
+                           ocnt, od, oi, 0, tlist, toff);
     else
         hipLaunchKernelGGL((k_knn_filter<KS, false>), g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, row0, T,
-                           cap, ocnt, od, oi, win);
+                           cap, ocnt, od, oi, win, (const int32_t *)nullptr, (const int64_t *)nullptr);
 }
 
 __global__ void k_fill_f32(float *__restrict__ p, int64_t n, float v)
@@ -1030,7 +1051,8 @@ struct FilterBufs {
 static void filter_select(int dp, hipStream_t s, const uint16_t *Qh, const uint16_t *Ql, const float *Qn,
                           int64_t M, const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int ex,
                           int64_t chunk, float *thr, const FilterBufs &B, int32_t *cand, int32_t *over, bool sym,
-                          int win, std::vector<hipEvent_t> *ev)
+                          int win, std::vector<hipEvent_t> *ev, const int32_t *tlist = nullptr,
+                          const int64_t *toff = nullptr)
 {
     const int64_t ntl = (N + KB_N - 1) / KB_N;
     for (int64_t r0 = 0; r0 < M; r0 += chunk) {
@@ -1044,7 +1066,7 @@ static void filter_select(int dp, hipStream_t s, const uint16_t *Qh, const uint1
             HIPC(hipEventRecord((*ev)[ev->size() - 2], s));
         }
         KNN_DISPATCH(launch_filter, g, dim3(256), s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, KNN_CAP, B.ocnt,
-                     B.od, B.oi, sym, win);
+                     B.od, B.oi, sym, win, tlist, toff);
         if (ev) HIPC(hipEventRecord(ev->back(), s));
         hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, KNN_CAP, B.ocnt,
                            B.od, B.oi, cand, thr, over ? over + 1 : nullptr, over);
@@ -1113,13 +1135,189 @@ __global__ void k_gather_qrows(const int32_t *__restrict__ rows, int64_t n, int 
                                uint16_t *__restrict__ Bh, uint16_t *__restrict__ Bl, float *__restrict__ Bn,
                                float *__restrict__ Bt);
 
+// ---------------------------------------------------------------- tile skipping
+// In the symmetric sweep a (row block, tile) pair can be skipped when no pair
+// of its points can pass either threshold test: with c and r a centre and a
+// radius of each 64-point tile (every point within r of c), every distance
+// between a row of tile a and a point of tile b is at least
+// L = |c_a - c_b| - r_a - r_b, and an approximate squared distance differs
+// from the exact one by at most E = g (|q|^2 + |x|^2) (the certificate's
+// bound).  The pair is skipped when L > 0 and L^2 exceeds (the largest
+// threshold of the block's rows and of the tile's points + the largest E) by
+// a relative margin of 1e-6 -- then no survivor is lost and the filter output
+// is exactly the full sweep's.  Centres are FP32 copies of the FP64 means;
+// radii are FP64 distances to those copies, enlarged by 1e-9 relative, and
+// centre distances are shrunk by 1e-9 relative.  ASKIT_KNN_NO_SKIP=1 in the
+// environment sweeps every pair (the same output, for comparison).
+struct TileGeom {
+    double r;        // radius around c
+    float tmax;      // largest row threshold of the tile's points
+    float nmax;      // largest FP32 squared norm of the tile's points
+};
+
+__global__ __launch_bounds__(64) void k_tile_geom(const float *__restrict__ Xf, int dp, int d, int64_t N,
+                                                  const float *__restrict__ thr, const float *__restrict__ Xn,
+                                                  float *__restrict__ cen, TileGeom *__restrict__ geo)
+{
+    const int64_t t = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t p = t * KB_N + lane;
+    const bool ok = p < N;
+    const int n = (int)min<int64_t>(KB_N, N - t * KB_N);
+    for (int k = 0; k < d; ++k) {
+        double v = ok ? (double)Xf[p * dp + k] : 0.0;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) cen[t * dp + k] = (float)(v / (double)n);
+    }
+    __syncthreads();
+    double r2 = 0.0;
+    float tm = -INFINITY, nm = 0.0f;
+    if (ok) {
+        for (int k = 0; k < d; ++k) {
+            const double u = (double)Xf[p * dp + k] - (double)cen[t * dp + k];
+            r2 += u * u;
+        }
+        tm = thr[p];
+        nm = Xn[p];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        r2 = fmax(r2, __shfl_xor(r2, o));
+        tm = fmaxf(tm, __shfl_xor(tm, o));
+        nm = fmaxf(nm, __shfl_xor(nm, o));
+    }
+    if (lane == 0) geo[t] = TileGeom{sqrt(r2) * (1.0 + 1e-9) + 1e-30, tm, nm};
+}
+
+// One workgroup per row block b (tiles 2b and 2b+1): bit t - 2b of the block's
+// mask is set for every tile t >= 2b that must be swept; cnt[b] = set bits.
+__global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen, const TileGeom *__restrict__ geo,
+                                                   int dp, int d, int64_t ntiles, double g,
+                                                   const int64_t *__restrict__ moff, uint64_t *__restrict__ mask,
+                                                   int64_t *__restrict__ cnt)
+{
+    __shared__ float ca[2][1024];
+    __shared__ int wsum[4];
+    const int64_t b = blockIdx.x, t0 = 2 * b;
+    const int nown = (int)min<int64_t>(2, ntiles - t0);
+    for (int k = threadIdx.x; k < d; k += 256) {
+        ca[0][k] = cen[t0 * dp + k];
+        ca[1][k] = nown > 1 ? cen[(t0 + 1) * dp + k] : ca[0][k];
+    }
+    __syncthreads();
+    const TileGeom ga = geo[t0], gb = nown > 1 ? geo[t0 + 1] : geo[t0];
+    const float tB = fmaxf(ga.tmax, gb.tmax), nB = fmaxf(ga.nmax, gb.nmax);
+    int64_t total = 0;
+    for (int64_t base = t0; base < ntiles; base += 256) {
+        const int64_t t = base + threadIdx.x;
+        bool keep = false;
+        if (t < ntiles) {
+            if (t < t0 + nown) {
+                keep = true;
+            } else {
+                const TileGeom gt = geo[t];
+                double s0 = 0.0, s1 = 0.0;
+                const float *ct = cen + t * dp;
+                for (int k = 0; k < d; ++k) {
+                    const double c = (double)ct[k];
+                    const double u0 = (double)ca[0][k] - c, u1 = (double)ca[1][k] - c;
+                    s0 += u0 * u0;
+                    s1 += u1 * u1;
+                }
+                // centre distances shrunk by 1e-9 relative: the FP64 rounding of
+                // the sums is far below that
+                const double L = fmin(sqrt(s0) * (1.0 - 1e-9) - ga.r, sqrt(s1) * (1.0 - 1e-9) - gb.r) - gt.r;
+                const double bound = ((double)fmaxf(tB, gt.tmax) + g * ((double)nB + (double)gt.nmax)) * (1.0 + 1e-6);
+                keep = !(L > 0.0 && L * L > bound);
+            }
+        }
+        const uint64_t bits = __ballot(keep);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        if (lane == 0) {
+            const int64_t w = (base - t0) / 64 + wv;
+            if (t0 + 64 * w < ntiles) mask[moff[b] + w] = bits;
+            wsum[wv] = __popcll(bits);
+        }
+        __syncthreads();
+        total += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt[b] = total;
+}
+
+// Expands each block's mask into its list of tiles (increasing order).
+__global__ __launch_bounds__(64) void k_tile_list(const uint64_t *__restrict__ mask, const int64_t *__restrict__ moff,
+                                                  int64_t ntiles, const int64_t *__restrict__ toff,
+                                                  int32_t *__restrict__ tlist)
+{
+    const int64_t b = blockIdx.x, t0 = 2 * b;
+    const int64_t nw = (ntiles - t0 + 63) / 64;
+    int64_t o = toff[b];
+    const int lane = threadIdx.x;
+    for (int64_t w = 0; w < nw; ++w) {
+        const uint64_t bits = mask[moff[b] + w];
+        if ((bits >> lane) & 1ull) tlist[o + __popcll(bits & ((1ull << lane) - 1ull))] = (int32_t)(t0 + 64 * w + lane);
+        o += __popcll(bits);
+    }
+}
+
+// Builds the tile lists of the symmetric sweep (tree-ordered FP32 points Xf,
+// stride dp; thr the rows' thresholds).  Returns false (no lists) when the
+// blocks are not aligned with the tiles.  Allocations go to tmp.
+static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const float *thr, const float *Xn,
+                             int32_t *&tlist, int64_t *&toff, int64_t &kept, std::vector<void *> &tmp,
+                             hipStream_t s)
+{
+    static_assert(KB_M == 2 * KB_N, "a row block is two tiles");
+    if (!Xf || d > 1024) return false;
+    const int64_t ntiles = (N + KB_N - 1) / KB_N, nblk = (N + KB_M - 1) / KB_M;
+    auto ta = [&](size_t b) {
+        void *p;
+        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        tmp.push_back(p);
+        return p;
+    };
+    std::vector<int64_t> hmoff(nblk + 1);
+    int64_t words = 0;
+    for (int64_t b = 0; b < nblk; ++b) {
+        hmoff[b] = words;
+        words += (ntiles - 2 * b + 63) / 64;
+    }
+    hmoff[nblk] = words;
+    float *cen = (float *)ta(sizeof(float) * ntiles * dp);
+    TileGeom *geo = (TileGeom *)ta(sizeof(TileGeom) * ntiles);
+    int64_t *moff = (int64_t *)ta(sizeof(int64_t) * (nblk + 1));
+    uint64_t *mask = (uint64_t *)ta(sizeof(uint64_t) * words);
+    int64_t *cnt = (int64_t *)ta(sizeof(int64_t) * nblk);
+    toff = (int64_t *)ta(sizeof(int64_t) * (nblk + 1));
+    HIPC(hipMemcpyAsync(moff, hmoff.data(), sizeof(int64_t) * (nblk + 1), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_tile_geom, dim3((unsigned)ntiles), dim3(64), 0, s, Xf, dp, d, N, thr, Xn, cen, geo);
+    const double g = 2.0 * (3.1 * ldexp(1.0, -16) + (4.0 * dp + 8.0) * ldexp(1.0, -24));
+    hipLaunchKernelGGL(k_tile_mask, dim3((unsigned)nblk), dim3(256), 0, s, cen, geo, dp, d, ntiles, g, moff, mask,
+                       cnt);
+    HIPC(hipGetLastError());
+    std::vector<int64_t> hc(nblk), ho(nblk + 1);
+    HIPC(hipMemcpyAsync(hc.data(), cnt, sizeof(int64_t) * nblk, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    ho[0] = 0;
+    for (int64_t b = 0; b < nblk; ++b) ho[b + 1] = ho[b] + hc[b];
+    kept = ho[nblk];
+    tlist = (int32_t *)ta(sizeof(int32_t) * std::max<int64_t>(kept, 1));
+    HIPC(hipMemcpyAsync(toff, ho.data(), sizeof(int64_t) * (nblk + 1), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_tile_list, dim3((unsigned)nblk), dim3(64), 0, s, mask, moff, ntiles, toff, tlist);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(s));          // the host tables are released on return
+    return true;
+}
+
 void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int64_t M,
                     const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int dp,
                     bool exclude_self, bool start_local, int32_t *cand, float *thr,
                     int32_t *bad_rows, int32_t *bad_count, hipStream_t s, float *t_filter_ms,
-                    int *n_filter, int *n_retry, const KnnSample *samp, std::vector<int32_t> *retry_rows)
+                    int *n_filter, int *n_retry, const KnnSample *samp, std::vector<int32_t> *retry_rows,
+                    const float *Xf, int d, int64_t *tiles_swept)
 {
     if (retry_rows) retry_rows->clear();
+    if (tiles_swept) *tiles_swept = -1;
     if (t_filter_ms) *t_filter_ms = 0.f;
     if (n_filter) *n_filter = 0;
     if (n_retry) *n_retry = 0;
@@ -1172,9 +1370,21 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
                       nullptr);
         widen(thr, M, s);
     }
+    // symmetric sweep: only the (row block, tile) pairs whose bounding balls
+    // come within the thresholds
+    std::vector<void *> ttmp;
+    int32_t *tlist = nullptr;
+    int64_t *toff = nullptr, kept = 0;
+    if (sym && !std::getenv("ASKIT_KNN_NO_SKIP") &&
+        build_tile_lists(Xf, dp, d, N, thr, Xn, tlist, toff, kept, ttmp, s)) {
+        if (tiles_swept) *tiles_swept = kept;
+    } else {
+        tlist = nullptr;
+        toff = nullptr;
+    }
     std::vector<hipEvent_t> ev;             // brackets of each filter launch (timing only)
     filter_select(dp, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, chunk, thr, B, cand, retry, sym, 0,
-                  t_filter_ms ? &ev : nullptr);
+                  t_filter_ms ? &ev : nullptr, tlist, toff);
     int32_t nretry = 0;
     HIPC(hipMemcpyAsync(&nretry, retry, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
@@ -1237,6 +1447,7 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     HIPC(hipFreeAsync(B.oi, s));
     HIPC(hipFreeAsync(retry, s));
     HIPC(hipFreeAsync(over, s));
+    for (void *p : ttmp) HIPC(hipFreeAsync(p, s));
     (void)bad_rows;
     (void)bad_count;
 }

@@ -460,10 +460,19 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
                     }
                 }
             }
-            // every wave waits until its stores have completed (a block barrier
-            // alone only orders them for this workgroup); then the sequence number
+            // Publication order.  The members of a gang run on one XCD and
+            // exchange through agent-scope atomics, which bypass the
+            // non-coherent caches.  Every wave waits until its stores are
+            // complete (vmcnt reaches 0: acknowledged by the memory system),
+            // the block barrier orders that before thread 0's store of the
+            // sequence number; the signal fences stop the compiler from moving
+            // the stores across.  (Agent-scope release/acquire fences give the
+            // same order through a write-back of the L2 and a cache invalidate
+            // per pivot step; measured, they made the QR 2.5x slower.)
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             __syncthreads();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
             if (tid == 0) __hip_atomic_store(&sl[w].seq, gs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             // every wave waits for the W candidates of this step itself (its
             // lanes < W poll), then loads its share: the loads of a lane are
@@ -480,6 +489,10 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
                 }
             }
             __builtin_amdgcn_wave_barrier();
+            // the loads below are issued after the poll in program order (the
+            // hardware issues a wave's loads in order; the fence keeps the
+            // compiler from hoisting them above the loop)
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
             // the headers and every candidate's rows t.. in one round of loads
             // (a workgroup without a candidate left stale rows: not used)
             if (tid < W) {

@@ -356,22 +356,22 @@ static void median_split(const uint64_t *key, const Split *d_sp, int nsp, int ma
     HIPC(hipMemcpyAsync(perm, pout, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
 }
 
-void build_tree(askit_handle *h, hipStream_t s)
+// Splits every node of each level (host split tables, one vector per level,
+// top-down) by the tree rule, permuting perm in place.
+static void run_split_levels(const askit_handle *h, int32_t *perm, const std::vector<std::vector<Split>> &levels,
+                             hipStream_t s)
 {
     const int64_t N = h->N;
     const int d = h->d, dp = h->dp;
-    unsigned nb = (unsigned)((N + 255) / 256);
-    hipLaunchKernelGGL(k_iota, dim3(nb), dim3(256), 0, s, h->perm, N);
-    HIPC(hipGetLastError());
-    if (h->depth == 0) {
-        hipLaunchKernelGGL(k_invert, dim3(nb), dim3(256), 0, s, h->perm, N, h->iperm);
-        return;
-    }
-    // scratch sized for the root level (largest node, one split)
     int64_t maxsp = 1;
-    for (auto &lv : h->level_nodes) maxsp = std::max<int64_t>(maxsp, (int64_t)lv.size());
+    for (auto &lv : levels) maxsp = std::max<int64_t>(maxsp, (int64_t)lv.size());
     int64_t blk_total = (N + 63) / 64 + 2 * maxsp;       // 64-point blocks over one level
     std::vector<void *> tmp;
+    struct Guard {
+        std::vector<void *> &t;
+        hipStream_t s;
+        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+    } guard{tmp, s};
     auto talloc = [&](size_t b) {
         void *p;
         HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
@@ -392,45 +392,82 @@ void build_tree(askit_handle *h, hipStream_t s)
     int32_t *pout = (int32_t *)talloc(sizeof(int32_t) * N);
     HIPC(hipMemsetAsync(hist, 0, sizeof(uint32_t) * 256 * maxsp, s));
 
-    std::vector<Split> hsp;
     std::vector<Sel> hsel;
-    for (int lev = 0; lev < (int)h->level_nodes.size(); ++lev) {
-        hsp.clear();
+    for (const auto &hsp : levels) {
+        const int nsp = (int)hsp.size();
+        if (nsp == 0) continue;
         hsel.clear();
         int maxn = 0;
-        for (int a : h->level_nodes[lev]) {
-            const Node &nd = h->nodes[a];
-            if (nd.left < 0) continue;
-            int n = nd.hi - nd.lo;
-            hsp.push_back(Split{nd.lo, n});
-            hsel.push_back(Sel{0ull, (int64_t)((n + 1) / 2 - 1)});
-            maxn = std::max(maxn, n);
+        for (const Split &sp : hsp) {
+            hsel.push_back(Sel{0ull, (int64_t)((sp.n + 1) / 2 - 1)});
+            maxn = std::max(maxn, (int)sp.n);
         }
-        int nsp = (int)hsp.size();
-        if (nsp == 0) continue;
         HIPC(hipMemcpyAsync(d_sp, hsp.data(), sizeof(Split) * nsp, hipMemcpyHostToDevice, s));
         HIPC(hipMemcpyAsync(sel, hsel.data(), sizeof(Sel) * nsp, hipMemcpyHostToDevice, s));
         int maxblk = (maxn + 63) / 64;
         int nchunk = (maxn + 255) / 256;
-        hipLaunchKernelGGL(k_block_sums, dim3(maxblk, nsp), dim3(64), 0, s, h->Xo, dp, d, h->perm,
-                           d_sp, maxblk, bsum);
-        hipLaunchKernelGGL(k_centroid, dim3(nsp), dim3(std::min(256, round_up(d, 64))), 0, s, bsum,
-                           d_sp, maxblk, d, cen);
-        hipLaunchKernelGGL(k_far_partial, dim3(nchunk, nsp), dim3(256), 0, s, h->Xo, dp, d, h->perm,
-                           d_sp, cen, (const int32_t *)nullptr, 0, nchunk, part);
+        hipLaunchKernelGGL(k_block_sums, dim3(maxblk, nsp), dim3(64), 0, s, h->Xo, dp, d, perm, d_sp, maxblk,
+                           bsum);
+        hipLaunchKernelGGL(k_centroid, dim3(nsp), dim3(std::min(256, round_up(d, 64))), 0, s, bsum, d_sp, maxblk,
+                           d, cen);
+        hipLaunchKernelGGL(k_far_partial, dim3(nchunk, nsp), dim3(256), 0, s, h->Xo, dp, d, perm, d_sp, cen,
+                           (const int32_t *)nullptr, 0, nchunk, part);
         hipLaunchKernelGGL(k_far_final, dim3(nsp), dim3(64), 0, s, part, d_sp, nchunk, L);
-        hipLaunchKernelGGL(k_far_partial, dim3(nchunk, nsp), dim3(256), 0, s, h->Xo, dp, d, h->perm,
-                           d_sp, cen, L, 1, nchunk, part);
+        hipLaunchKernelGGL(k_far_partial, dim3(nchunk, nsp), dim3(256), 0, s, h->Xo, dp, d, perm, d_sp, cen, L, 1,
+                           nchunk, part);
         hipLaunchKernelGGL(k_far_final, dim3(nsp), dim3(64), 0, s, part, d_sp, nchunk, Rr);
-        hipLaunchKernelGGL(k_project, dim3(nchunk, nsp), dim3(256), 0, s, h->Xo, dp, d, h->perm, d_sp,
-                           L, Rr, key);
-        median_split(key, d_sp, nsp, maxn, sel, hist, pc, h->perm, pout, N, s);
+        hipLaunchKernelGGL(k_project, dim3(nchunk, nsp), dim3(256), 0, s, h->Xo, dp, d, perm, d_sp, L, Rr, key);
+        median_split(key, d_sp, nsp, maxn, sel, hist, pc, perm, pout, N, s);
+        HIPC(hipStreamSynchronize(s));          // the host tables are reused by the next level
     }
-    hipLaunchKernelGGL(k_invert, dim3(nb), dim3(256), 0, s, h->perm, N, h->iperm);
-    HIPC(hipGetLastError());
-    for (void *p : tmp) HIPC(hipFreeAsync(p, s));
 }
 
+void build_tree(askit_handle *h, hipStream_t s)
+{
+    const int64_t N = h->N;
+    unsigned nb = (unsigned)((N + 255) / 256);
+    hipLaunchKernelGGL(k_iota, dim3(nb), dim3(256), 0, s, h->perm, N);
+    HIPC(hipGetLastError());
+    std::vector<std::vector<Split>> levels;
+    for (const auto &lv : h->level_nodes) {
+        levels.emplace_back();
+        for (int a : lv) {
+            const Node &nd = h->nodes[a];
+            if (nd.left >= 0) levels.back().push_back(Split{nd.lo, nd.hi - nd.lo});
+        }
+    }
+    run_split_levels(h, h->perm, levels, s);
+    hipLaunchKernelGGL(k_invert, dim3(nb), dim3(256), 0, s, h->perm, N, h->iperm);
+    HIPC(hipGetLastError());
+}
+
+// Finer order of the points for the neighbour search: the tree's leaves split
+// further by the same rule until every cell holds at most mfine points.  It
+// refines the tree order (each leaf keeps its range), so cells of consecutive
+// positions are spatially compact: the sweep's tiles and row blocks then have
+// small bounding balls and far pairs of them are skipped.  Only the search
+// uses it (its results are point ids and exact distances).
+void build_fine_order(const askit_handle *h, int mfine, int32_t *perm_f, hipStream_t s)
+{
+    HIPC(hipMemcpyAsync(perm_f, h->perm, sizeof(int32_t) * h->N, hipMemcpyDeviceToDevice, s));
+    std::vector<std::vector<Split>> levels;
+    std::vector<Split> cur;
+    for (int a : h->leaves) {
+        const Node &nd = h->nodes[a];
+        if (nd.hi - nd.lo > mfine) cur.push_back(Split{nd.lo, nd.hi - nd.lo});
+    }
+    while (!cur.empty()) {
+        levels.push_back(cur);
+        std::vector<Split> nxt;
+        for (const Split &sp : cur) {
+            const int32_t nl = (sp.n + 1) / 2;
+            if (nl > mfine) nxt.push_back(Split{sp.lo, nl});
+            if (sp.n - nl > mfine) nxt.push_back(Split{sp.lo + nl, sp.n - nl});
+        }
+        cur.swap(nxt);
+    }
+    run_split_levels(h, perm_f, levels, s);
+}
 
 // ---------------------------------------------------------------- pruning diagnostic
 // Nodes visited by the traversal of Alg. 4 per target under the neighbour rule
