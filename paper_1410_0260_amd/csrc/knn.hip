@@ -624,13 +624,16 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     constexpr int PER = (CHUNKS + 255) / 256;
     uint4 rh[1][PER], rl[1][PER];
     float rn[1] = {0.0f};
+    // entry of list position t: the tile, and in bits 27-30 the waves that
+    // sweep it (all four without lists)
     auto tile_of = [&](int t) -> int {
         if constexpr (SYM) {
             if (tl) return tl[t];
         }
         const int tt = t032 + t;
-        return tt >= nta32 ? tt - nta32 : tt;
+        return (tt >= nta32 ? tt - nta32 : tt) | (15 << 27);
     };
+    auto wave_on = [&](int ent) -> bool { return (ent >> (27 + wv)) & 1; };
     KNN_TILE_IO();
     float rt = -INFINITY;
     auto load_thr = [&](int64_t tt) {
@@ -662,40 +665,50 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], bh1, acc1, 0, 0, 0);
         }
     };
-    int tnext = tile_of(0);                 // tile of the next load (kept in a register)
-    load_tile(0, tnext);
-    load_thr(tnext);
+    int tnext = tile_of(0);                 // entry of the next load (kept in a register)
+    load_tile(0, tnext & 0x7ffffff);
+    load_thr(tnext & 0x7ffffff);
     store_tile(0, 0);
     store_thr(0);
     if (tid == 0) sTile[0] = tnext;
     if (ntiles > 1) {
         tnext = tile_of(1);
-        load_tile(0, tnext);
-        load_thr(tnext);
+        load_tile(0, tnext & 0x7ffffff);
+        load_thr(tnext & 0x7ffffff);
         store_tile(0, 1);
         store_thr(1);
         if (tid == 0) sTile[1] = tnext;
     }
     __syncthreads();
     f32x16 accA0, accA1, accB0, accB1;
-    mfma_tile(0, accA0, accA1);
+    if (wave_on(sTile[0])) mfma_tile(0, accA0, accA1);
     // iteration t: accumulators of tile t ready; MFMAs of tile t+1 read buffer
     // (t+1)%3; the points of tile t+2 are loaded and stored to buffer (t+2)%3
     auto iter = [&](auto CUR, int t, f32x16 &c0, f32x16 &c1, f32x16 &n0, f32x16 &n1) {
-        const int tbase = sTile[t % 3] * KB_N;
+        const int ent = sTile[t % 3];
+        const int tbase = (ent & 0x7ffffff) * KB_N;
+        const bool on = wave_on(ent);
         if (t + 2 < nt32) {
             tnext = tile_of(t + 2);
-            load_tile(0, tnext);
-            load_thr(tnext);
+            load_tile(0, tnext & 0x7ffffff);
+            load_thr(tnext & 0x7ffffff);
         }
-        if (t + 1 < nt32) mfma_tile((t + 1) % 3, n0, n1);
+        if (t + 1 < nt32 && wave_on(sTile[(t + 1) % 3])) mfma_tile((t + 1) % 3, n0, n1);
         // <= keeps the window's own 64 points (same arithmetic as the window pass)
         const float *nb = sBn + (t % 3) * KB_N;
         const float ny0 = nb[l32], ny1 = nb[32 + l32];
-        bool any = false;
+        // the 32 distances of the lane, computed once for both tests
+        float dv[32];
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-            any |= (fmaf(-2.0f, c0[r], qn[r] + ny0) <= thrv[r]) | (fmaf(-2.0f, c1[r], qn[r] + ny1) <= thrv[r]);
+        for (int r = 0; r < 16; ++r) {
+            dv[r] = fmaf(-2.0f, c0[r], qn[r] + ny0);
+            dv[16 + r] = fmaf(-2.0f, c1[r], qn[r] + ny1);
+        }
+        bool any = false;
+        if (on) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) any |= (dv[r] <= thrv[r]) | (dv[16 + r] <= thrv[r]);
+        }
         if (__ballot(any)) {
             const uint32_t cA = (uint32_t)tbase + (uint32_t)l32, cB = cA + 32u;
             const uint32_t n32 = (uint32_t)N;
@@ -705,8 +718,8 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
                 // the 32 lanes of a half-wave hold the same row: one counter
                 // update per row and half-wave, lanes write at their prefix
                 const uint32_t qrow = qbase + (uint32_t)(8 * (r / 4) + (r % 4));
-                const float dA = fmaf(-2.0f, c0[r], qn[r] + ny0);
-                const float dB = fmaf(-2.0f, c1[r], qn[r] + ny1);
+                const float dA = dv[r];
+                const float dB = dv[16 + r];
                 const bool pA = dA <= thrv[r] && cA < n32 && !(excl && cA == qrow + (uint32_t)row0);
                 const bool pB = dB <= thrv[r] && cB < n32 && !(excl && cB == qrow + (uint32_t)row0);
                 const uint64_t bA = __ballot(pA), bB = __ballot(pB);
@@ -736,13 +749,12 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
         }
         if constexpr (SYM) {
             // tiles after the block's own two: offer each distance to the tile's point too
-            if (t >= 2) {
+            if (t >= 2 && on) {
                 const float *tb = sBt + (t % 3) * KB_N;
                 const float tA = tb[l32], tB = tb[32 + l32];
                 bool anyc = false;
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    anyc |= (fmaf(-2.0f, c0[r], qn[r] + ny0) <= tA) | (fmaf(-2.0f, c1[r], qn[r] + ny1) <= tB);
+                for (int r = 0; r < 16; ++r) anyc |= (dv[r] <= tA) | (dv[16 + r] <= tB);
                 if (__ballot(anyc)) {
                     const uint32_t cA = (uint32_t)tbase + (uint32_t)l32, cB = cA + 32u;
                     const uint32_t m32 = (uint32_t)M;
@@ -750,8 +762,8 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
                     for (int r = 0; r < 16; ++r) {
                         const uint32_t qrow = qbase + (uint32_t)(8 * (r / 4) + (r % 4));
                         if (qrow >= m32) continue;
-                        const float dA = fmaf(-2.0f, c0[r], qn[r] + ny0);
-                        const float dB = fmaf(-2.0f, c1[r], qn[r] + ny1);
+                        const float dA = dv[r];
+                        const float dB = dv[16 + r];
                         if (dA <= tA) {
                             uint32_t p = (uint32_t)atomicAdd(&ocnt[cA], 1);
                             if (p < (uint32_t)cap) {
@@ -1136,34 +1148,42 @@ __global__ void k_gather_qrows(const int32_t *__restrict__ rows, int64_t n, int 
                                float *__restrict__ Bt);
 
 // ---------------------------------------------------------------- tile skipping
-// In the symmetric sweep a (row block, tile) pair can be skipped when no pair
+// In the symmetric sweep a (row group, tile) pair can be skipped when no pair
 // of its points can pass either threshold test: with c and r a centre and a
-// radius of each 64-point tile (every point within r of c), every distance
-// between a row of tile a and a point of tile b is at least
+// radius of a set of points (every point within r of c), every distance
+// between a row of group a and a point of tile b is at least
 // L = |c_a - c_b| - r_a - r_b, and an approximate squared distance differs
 // from the exact one by at most E = g (|q|^2 + |x|^2) (the certificate's
 // bound).  The pair is skipped when L > 0 and L^2 exceeds (the largest
-// threshold of the block's rows and of the tile's points + the largest E) by
+// threshold of the group's rows and of the tile's points + the largest E) by
 // a relative margin of 1e-6 -- then no survivor is lost and the filter output
-// is exactly the full sweep's.  Centres are FP32 copies of the FP64 means;
-// radii are FP64 distances to those copies, enlarged by 1e-9 relative, and
-// centre distances are shrunk by 1e-9 relative.  ASKIT_KNN_NO_SKIP=1 in the
-// environment sweeps every pair (the same output, for comparison).
+// is exactly the full sweep's.  Row groups are the 32 rows of one wave; a
+// block's tile list keeps the tiles that any of its four waves needs, with a
+// 4-bit mask of those waves in bits 27-30 of the entry.  Centres are FP32
+// copies of the FP64 means; radii are FP64 distances to those copies,
+// enlarged by 1e-9 relative, and centre distances are shrunk by 1e-9
+// relative.  ASKIT_KNN_NO_SKIP=1 in the environment sweeps every pair (the
+// same output, for comparison).
+constexpr int TL_TILE_BITS = 27;
+constexpr int32_t TL_TILE_MASK = (1 << TL_TILE_BITS) - 1;
+
 struct TileGeom {
     double r;        // radius around c
-    float tmax;      // largest row threshold of the tile's points
-    float nmax;      // largest FP32 squared norm of the tile's points
+    float tmax;      // largest row threshold of the points
+    float nmax;      // largest FP32 squared norm of the points
 };
 
+// Geometry of consecutive groups of G points (G <= 64), one wave per group.
+template <int G>
 __global__ __launch_bounds__(64) void k_tile_geom(const float *__restrict__ Xf, int dp, int d, int64_t N,
                                                   const float *__restrict__ thr, const float *__restrict__ Xn,
                                                   float *__restrict__ cen, TileGeom *__restrict__ geo)
 {
     const int64_t t = blockIdx.x;
     const int lane = threadIdx.x;
-    const int64_t p = t * KB_N + lane;
-    const bool ok = p < N;
-    const int n = (int)min<int64_t>(KB_N, N - t * KB_N);
+    const int64_t p = t * G + lane;
+    const bool ok = lane < G && p < N;
+    const int n = (int)min<int64_t>(G, N - t * G);
     for (int k = 0; k < d; ++k) {
         double v = ok ? (double)Xf[p * dp + k] : 0.0;
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -1188,55 +1208,62 @@ __global__ __launch_bounds__(64) void k_tile_geom(const float *__restrict__ Xf, 
     if (lane == 0) geo[t] = TileGeom{sqrt(r2) * (1.0 + 1e-9) + 1e-30, tm, nm};
 }
 
-// One workgroup per row block b (tiles 2b and 2b+1): bit t - 2b of the block's
-// mask is set for every tile t >= 2b that must be swept; cnt[b] = set bits.
-__global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen, const TileGeom *__restrict__ geo,
-                                                   int dp, int d, int64_t ntiles, double g,
-                                                   const int64_t *__restrict__ moff, uint64_t *__restrict__ mask,
-                                                   int64_t *__restrict__ cnt)
+// One workgroup per row block b (row groups 4b..4b+3, tiles 2b and 2b+1):
+// for every tile t >= 2b, bit (t - 2b) of the block's mask word w (w = the
+// wave) is set when that wave must sweep it; cnt[b] = tiles any wave needs.
+__global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen_g, const TileGeom *__restrict__ geo_g,
+                                                   int64_t ngroups, const float *__restrict__ cen_t,
+                                                   const TileGeom *__restrict__ geo_t, int dp, int d,
+                                                   int64_t ntiles, double g, const int64_t *__restrict__ moff,
+                                                   uint64_t *__restrict__ mask, int64_t *__restrict__ cnt)
 {
-    __shared__ float ca[2][1024];
+    __shared__ float ca[4][1024];
     __shared__ int wsum[4];
-    const int64_t b = blockIdx.x, t0 = 2 * b;
+    const int64_t b = blockIdx.x, t0 = 2 * b, g0 = 4 * b;
     const int nown = (int)min<int64_t>(2, ntiles - t0);
-    for (int k = threadIdx.x; k < d; k += 256) {
-        ca[0][k] = cen[t0 * dp + k];
-        ca[1][k] = nown > 1 ? cen[(t0 + 1) * dp + k] : ca[0][k];
-    }
+    const int ng = (int)min<int64_t>(4, ngroups - g0);
+    for (int k = threadIdx.x; k < d; k += 256)
+        for (int w = 0; w < 4; ++w) ca[w][k] = cen_g[(g0 + min(w, ng - 1)) * dp + k];
     __syncthreads();
-    const TileGeom ga = geo[t0], gb = nown > 1 ? geo[t0 + 1] : geo[t0];
-    const float tB = fmaxf(ga.tmax, gb.tmax), nB = fmaxf(ga.nmax, gb.nmax);
+    TileGeom gw[4];
+    for (int w = 0; w < 4; ++w) gw[w] = geo_g[g0 + min(w, ng - 1)];
     int64_t total = 0;
     for (int64_t base = t0; base < ntiles; base += 256) {
         const int64_t t = base + threadIdx.x;
-        bool keep = false;
+        bool keep[4] = {false, false, false, false};
         if (t < ntiles) {
             if (t < t0 + nown) {
-                keep = true;
+                for (int w = 0; w < 4; ++w) keep[w] = w < ng;
             } else {
-                const TileGeom gt = geo[t];
-                double s0 = 0.0, s1 = 0.0;
-                const float *ct = cen + t * dp;
+                const TileGeom gt = geo_t[t];
+                double sw[4] = {0.0, 0.0, 0.0, 0.0};
+                const float *ct = cen_t + t * dp;
                 for (int k = 0; k < d; ++k) {
                     const double c = (double)ct[k];
-                    const double u0 = (double)ca[0][k] - c, u1 = (double)ca[1][k] - c;
-                    s0 += u0 * u0;
-                    s1 += u1 * u1;
+                    for (int w = 0; w < 4; ++w) {
+                        const double u = (double)ca[w][k] - c;
+                        sw[w] += u * u;
+                    }
                 }
-                // centre distances shrunk by 1e-9 relative: the FP64 rounding of
-                // the sums is far below that
-                const double L = fmin(sqrt(s0) * (1.0 - 1e-9) - ga.r, sqrt(s1) * (1.0 - 1e-9) - gb.r) - gt.r;
-                const double bound = ((double)fmaxf(tB, gt.tmax) + g * ((double)nB + (double)gt.nmax)) * (1.0 + 1e-6);
-                keep = !(L > 0.0 && L * L > bound);
+                for (int w = 0; w < ng; ++w) {
+                    // centre distances shrunk by 1e-9 relative: the FP64 rounding
+                    // of the sums is far below that
+                    const double L = sqrt(sw[w]) * (1.0 - 1e-9) - gw[w].r - gt.r;
+                    const double bound = ((double)fmaxf(gw[w].tmax, gt.tmax) +
+                                          g * ((double)gw[w].nmax + (double)gt.nmax)) * (1.0 + 1e-6);
+                    keep[w] = !(L > 0.0 && L * L > bound);
+                }
             }
         }
-        const uint64_t bits = __ballot(keep);
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        if (lane == 0) {
-            const int64_t w = (base - t0) / 64 + wv;
-            if (t0 + 64 * w < ntiles) mask[moff[b] + w] = bits;
-            wsum[wv] = __popcll(bits);
+        uint64_t any = 0;
+        for (int w = 0; w < 4; ++w) {
+            const uint64_t bits = __ballot(keep[w]);
+            any |= bits;
+            const int64_t wd = (base - t0) / 64 + wv;
+            if (lane == 0 && t0 + 64 * wd < ntiles) mask[(moff[b] + wd) * 4 + w] = bits;
         }
+        if (lane == 0) wsum[wv] = __popcll(any);
         __syncthreads();
         total += wsum[0] + wsum[1] + wsum[2] + wsum[3];
         __syncthreads();
@@ -1244,7 +1271,8 @@ __global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen
     if (threadIdx.x == 0) cnt[b] = total;
 }
 
-// Expands each block's mask into its list of tiles (increasing order).
+// Expands each block's masks into its list of entries (increasing tile
+// order): tile | (wave mask << 27).
 __global__ __launch_bounds__(64) void k_tile_list(const uint64_t *__restrict__ mask, const int64_t *__restrict__ moff,
                                                   int64_t ntiles, const int64_t *__restrict__ toff,
                                                   int32_t *__restrict__ tlist)
@@ -1254,22 +1282,27 @@ __global__ __launch_bounds__(64) void k_tile_list(const uint64_t *__restrict__ m
     int64_t o = toff[b];
     const int lane = threadIdx.x;
     for (int64_t w = 0; w < nw; ++w) {
-        const uint64_t bits = mask[moff[b] + w];
-        if ((bits >> lane) & 1ull) tlist[o + __popcll(bits & ((1ull << lane) - 1ull))] = (int32_t)(t0 + 64 * w + lane);
-        o += __popcll(bits);
+        const uint64_t *m = mask + (moff[b] + w) * 4;
+        const uint64_t m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3], any = m0 | m1 | m2 | m3;
+        if ((any >> lane) & 1ull) {
+            const int32_t nib = (int32_t)(((m0 >> lane) & 1ull) | (((m1 >> lane) & 1ull) << 1) |
+                                          (((m2 >> lane) & 1ull) << 2) | (((m3 >> lane) & 1ull) << 3));
+            tlist[o + __popcll(any & ((1ull << lane) - 1ull))] = (int32_t)(t0 + 64 * w + lane) | (nib << TL_TILE_BITS);
+        }
+        o += __popcll(any);
     }
 }
 
-// Builds the tile lists of the symmetric sweep (tree-ordered FP32 points Xf,
-// stride dp; thr the rows' thresholds).  Returns false (no lists) when the
-// blocks are not aligned with the tiles.  Allocations go to tmp.
+// Builds the tile lists of the symmetric sweep (FP32 points Xf in sweep
+// order, stride dp; thr the rows' thresholds).  Returns false (no lists) when
+// they do not apply.  Allocations go to tmp.
 static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const float *thr, const float *Xn,
                              int32_t *&tlist, int64_t *&toff, int64_t &kept, std::vector<void *> &tmp,
                              hipStream_t s)
 {
-    static_assert(KB_M == 2 * KB_N, "a row block is two tiles");
-    if (!Xf || d > 1024) return false;
-    const int64_t ntiles = (N + KB_N - 1) / KB_N, nblk = (N + KB_M - 1) / KB_M;
+    static_assert(KB_M == 2 * KB_N && KB_M == 4 * 32, "a row block is two tiles and four waves of 32 rows");
+    const int64_t ntiles = (N + KB_N - 1) / KB_N, nblk = (N + KB_M - 1) / KB_M, ngroups = (N + 31) / 32;
+    if (!Xf || d > 1024 || ntiles > TL_TILE_MASK) return false;
     auto ta = [&](size_t b) {
         void *p;
         HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
@@ -1283,17 +1316,21 @@ static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const fl
         words += (ntiles - 2 * b + 63) / 64;
     }
     hmoff[nblk] = words;
-    float *cen = (float *)ta(sizeof(float) * ntiles * dp);
-    TileGeom *geo = (TileGeom *)ta(sizeof(TileGeom) * ntiles);
+    float *cen_t = (float *)ta(sizeof(float) * ntiles * dp);
+    TileGeom *geo_t = (TileGeom *)ta(sizeof(TileGeom) * ntiles);
+    float *cen_g = (float *)ta(sizeof(float) * ngroups * dp);
+    TileGeom *geo_g = (TileGeom *)ta(sizeof(TileGeom) * ngroups);
     int64_t *moff = (int64_t *)ta(sizeof(int64_t) * (nblk + 1));
-    uint64_t *mask = (uint64_t *)ta(sizeof(uint64_t) * words);
+    uint64_t *mask = (uint64_t *)ta(sizeof(uint64_t) * words * 4);
     int64_t *cnt = (int64_t *)ta(sizeof(int64_t) * nblk);
     toff = (int64_t *)ta(sizeof(int64_t) * (nblk + 1));
     HIPC(hipMemcpyAsync(moff, hmoff.data(), sizeof(int64_t) * (nblk + 1), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_tile_geom, dim3((unsigned)ntiles), dim3(64), 0, s, Xf, dp, d, N, thr, Xn, cen, geo);
+    hipLaunchKernelGGL(k_tile_geom<64>, dim3((unsigned)ntiles), dim3(64), 0, s, Xf, dp, d, N, thr, Xn, cen_t, geo_t);
+    hipLaunchKernelGGL(k_tile_geom<32>, dim3((unsigned)ngroups), dim3(64), 0, s, Xf, dp, d, N, thr, Xn, cen_g,
+                       geo_g);
     const double g = 2.0 * (3.1 * ldexp(1.0, -16) + (4.0 * dp + 8.0) * ldexp(1.0, -24));
-    hipLaunchKernelGGL(k_tile_mask, dim3((unsigned)nblk), dim3(256), 0, s, cen, geo, dp, d, ntiles, g, moff, mask,
-                       cnt);
+    hipLaunchKernelGGL(k_tile_mask, dim3((unsigned)nblk), dim3(256), 0, s, cen_g, geo_g, ngroups, cen_t, geo_t, dp, d,
+                       ntiles, g, moff, mask, cnt);
     HIPC(hipGetLastError());
     std::vector<int64_t> hc(nblk), ho(nblk + 1);
     HIPC(hipMemcpyAsync(hc.data(), cnt, sizeof(int64_t) * nblk, hipMemcpyDeviceToHost, s));
