@@ -126,7 +126,8 @@ def serve_leg(args, A, torch):
             "p50_query_ms": st["p50_query_ms"], "p99_query_ms": st["p99_query_ms"],
             "throughput_targets_rhs_per_s": st["throughput_targets_rhs_per_s"], "setup_s": full["setup_s"],
             "offered_load_factor": full["offered"]["load_factor"], "capacity": full["capacity"],
-            "stream": full["config"]["stream"]}
+            "stream": full["config"]["stream"], "weight_passes": args.serve_passes,
+            "joined_mid_cycle": st["joined_mid_cycle"]}
 
 
 def serve_bench(args, wl, A, torch, stretched=True):
@@ -159,7 +160,7 @@ def serve_bench(args, wl, A, torch, stretched=True):
         return torch.from_numpy(synth.queries(wl, r["M"], r["seed"])).cuda()
 
     cfg = A.server_config(workers=args.serve_workers, max_batch_rhs=64, max_batch_queries=16384,
-                          mem_budget=args.serve_mem_gib << 30)
+                          mem_budget=args.serve_mem_gib << 30, weight_passes=args.serve_passes)
 
     def replay(rs, times):
         srv = A.Server(h, W0, cfg)
@@ -225,13 +226,14 @@ def serve_bench(args, wl, A, torch, stretched=True):
     h.close()
     keep = ("requests", "completed", "failed", "deferred", "batches", "batched_requests", "p50_ms", "p99_ms",
             "mean_ms", "p50_weights_ms", "p99_weights_ms", "p50_query_ms", "p99_query_ms",
-            "throughput_targets_rhs_per_s", "busy_s", "peak_mem")
+            "throughput_targets_rhs_per_s", "busy_s", "peak_mem", "joined_mid_cycle")
     return {
         "metric": "serving targets*RHS/s and p50/p99 latency (resident setup, continuous batching)",
         "value": at_rate["throughput_targets_rhs_per_s"], "unit": "targets*RHS/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "N": N, "d": d, "stream": f"Poisson {args.serve_rate} req/s, seed 55",
-                   "workers": args.serve_workers, "mem_budget_gib": args.serve_mem_gib},
+                   "workers": args.serve_workers, "mem_budget_gib": args.serve_mem_gib,
+                   "weight_passes": args.serve_passes},
         "setup_s": t_setup,
         "capacity": {"s_per_weight_column": sec_per_col, "s_per_query_point": sec_per_q,
                      "weight_columns_per_s": 1.0 / sec_per_col, "query_points_per_s": 1.0 / sec_per_q},
@@ -703,6 +705,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-workers", type=int, default=2)
     ap.add_argument("--serve-mem-gib", type=int, default=64)
+    ap.add_argument("--serve-passes", type=int, default=4,
+                    help="weight requests: 0 = whole batches on the workers, K > 0 = cyclic column pool, "
+                         "K passes per cycle")
     ap.add_argument("--serve-budget-s", type=float, default=20.0, help="GPU work per serving replay")
     ap.add_argument("--batched-rhs", type=int, default=1)
     ap.add_argument("--query-points", default=None,

@@ -316,8 +316,19 @@ askit_status askit_export(const askit_handle *h, int32_t what, void *dst, size_t
  * one kind are batched (weight columns side by side, query points stacked)
  * and run by `workers` threads, each on its own stream, so batches overlap on
  * the device.  Results are independent of the batch a request rides in: a
- * weight request's columns are bit-identical to running it alone, a query's
- * values agree to FP32 rounding (its slab of targets may differ).
+ * query's values are bit-identical to running it alone (its points are
+ * sorted, cut into slabs and chunked among themselves only), a weight
+ * request's columns agree to FP32 rounding (the contraction runs as wide as
+ * the batch's columns).
+ *
+ * Cyclic weights (weight_passes = K > 0): weight requests go to one column
+ * engine with a resident pool of max_batch_rhs columns instead of the
+ * workers.  The evaluation's source-node chunks are cut into K ranges of
+ * about equal pair counts, evaluated round robin, one range per pass, for
+ * every column in flight; waiting requests are admitted into free columns
+ * between passes (their upward pass runs then) and a request finishes after
+ * K passes, whichever range it started at.  The pool (weights_bytes for
+ * max_batch_rhs columns) is charged to mem_budget for the server's lifetime.
  * ------------------------------------------------------------------------- */
 typedef struct askit_server askit_server;
 
@@ -327,20 +338,28 @@ typedef struct {
     int32_t max_batch_rhs;      /* weight columns per batch, 1..64 */
     int32_t max_batch_queries;  /* query points per batch, >= 1 */
     uint64_t mem_budget;        /* device bytes for in-flight requests (0: 8 GiB) */
+    int32_t weight_passes;      /* 0: weight requests batched whole by the workers;
+                                   K in 1..4096: cyclic weights, K passes per cycle */
+    int32_t max_pending;        /* queued requests beyond which submit returns
+                                   ASKIT_ERR_BUSY (0: no limit) */
 } askit_server_config;
 
 typedef struct {
     int64_t submitted, completed, failed;
     int64_t deferred;           /* requests that reached the queue head and waited for memory */
-    int64_t batches, batched_requests;
+    int64_t batches, batched_requests;   /* cyclic weights: passes that admitted
+                                            requests, and the requests admitted */
     double p50_ms, p99_ms, mean_ms;                 /* submit -> result ready, all requests */
     double p50_weights_ms, p99_weights_ms, p50_query_ms, p99_query_ms;
     double targets_rhs;         /* sum over completed requests of targets x RHS */
     double busy_s;              /* wall time from first submit to last completion */
     uint64_t peak_mem;          /* largest admitted total */
+    int64_t joined_mid_cycle;   /* cyclic weights: requests admitted while other
+                                   columns were part way through their cycle */
 } askit_serving_stats;
 
-/* Fills *c with defaults: 2 workers, 64 columns, 65536 points, 8 GiB. */
+/* Fills *c with defaults: 2 workers, 64 columns, 65536 points, 8 GiB, whole
+ * weight batches (weight_passes 0), no queue limit. */
 askit_status askit_server_config_default(askit_server_config *c);
 
 /* Creates a server over a set-up handle (the handle must outlive the server
@@ -354,7 +373,9 @@ askit_status askit_server_create(askit_handle *h, const float *W0, int64_t ldw0,
  * stride ldu) out.  Both must stay valid until the request completes, and W
  * must already hold its values (work that writes it has finished): the
  * server reads it on its own streams, unordered with the caller's.
- * ASKIT_ERR_OUT_OF_MEMORY if the request alone exceeds the budget. */
+ * ASKIT_ERR_OUT_OF_MEMORY if the request alone exceeds the budget (batch
+ * mode; in cyclic mode the pool is charged at creation), ASKIT_ERR_BUSY if
+ * max_pending requests are already queued (both kinds count). */
 askit_status askit_server_submit_weights(askit_server *s, const float *W, int64_t ldw, int32_t nrhs,
                                          float *U, int64_t ldu, uint64_t *ticket);
 

@@ -309,7 +309,8 @@ def setup_with_knn(X, knn, params: Params) -> Handle:
 # ----------------------------------------------------------------- serving
 class ServerConfig(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("workers", C.c_int32), ("max_batch_rhs", C.c_int32),
-                ("max_batch_queries", C.c_int32), ("mem_budget", C.c_uint64)]
+                ("max_batch_queries", C.c_int32), ("mem_budget", C.c_uint64), ("weight_passes", C.c_int32),
+                ("max_pending", C.c_int32)]
 
 
 class ServerStats(C.Structure):
@@ -318,7 +319,8 @@ class ServerStats(C.Structure):
                 ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
                 ("p50_weights_ms", C.c_double), ("p99_weights_ms", C.c_double),
                 ("p50_query_ms", C.c_double), ("p99_query_ms", C.c_double),
-                ("targets_rhs", C.c_double), ("busy_s", C.c_double), ("peak_mem", C.c_uint64)]
+                ("targets_rhs", C.c_double), ("busy_s", C.c_double), ("peak_mem", C.c_uint64),
+                ("joined_mid_cycle", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -147,6 +147,25 @@ void permute_weights(askit_handle *h, const float *W, int64_t ldw, WeightSet &ws
     HIPC(hipGetLastError());
 }
 
+__global__ void k_permute_w_cols(const float *__restrict__ W, int64_t ldw, const int32_t *__restrict__ perm,
+                                 int64_t N, int rb, float *__restrict__ Wt, int ldt, int c0)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t p = t / rb;
+    if (p >= N) return;
+    int r = (int)(t - p * rb);
+    Wt[p * ldt + c0 + r] = W[(int64_t)perm[p] * ldw + r];
+}
+
+void permute_weight_cols(askit_handle *h, const float *W, int64_t ldw, int rb, float *Wt, int ldt, int c0,
+                         hipStream_t s)
+{
+    int64_t tot = h->N * rb;
+    hipLaunchKernelGGL(k_permute_w_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, W, ldw, h->perm,
+                       h->N, rb, Wt, ldt, c0);
+    HIPC(hipGetLastError());
+}
+
 // Exact kappa nearest sources of M new points (original ids and FP64 squared
 // distances, M x kappa each); Yp receives the packed points.  Temporaries come
 // from ta (freed by the caller's guard).

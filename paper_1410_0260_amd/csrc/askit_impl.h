@@ -297,9 +297,13 @@ void sort_queries(askit_handle *h, const int32_t *nb, int64_t M, int32_t *order,
 
 // skel.hip
 void skeletonize(askit_handle *h, hipStream_t s);
-void upward(askit_handle *h, const WeightSet &ws, hipStream_t s);   // no host sync
+// columns [r0, r1) of ws (r1 < 0: all); no host sync
+void upward(askit_handle *h, const WeightSet &ws, hipStream_t s, int r0 = 0, int r1 = -1);
 void prepare_upward(askit_handle *h);                                  // once, after setup
 void permute_weights(askit_handle *h, const float *W, int64_t ldw, WeightSet &ws, hipStream_t s);
+// W (N x rb, original order) into columns [c0, c0 + rb) of Wt (tree order, row stride ldt)
+void permute_weight_cols(askit_handle *h, const float *W, int64_t ldw, int rb, float *Wt, int ldt, int c0,
+                         hipStream_t s);
 
 // eval.hip
 // Pair lists of the targets described by slab lists (ptr: near offsets
@@ -317,6 +321,15 @@ void build_pairs(const askit_handle *h, const Slab *d_slabs, int64_t nslab, int6
 void evaluate(const askit_handle *h, const WeightSet &ws, const float *Y, const PairLists &L,
               const int32_t *outmap, float *U, int64_t ldu, float *part, hipStream_t s,
               float *Unear = nullptr, int64_t ldun = 0);
+
+// The evaluation's chunks [ch0, ch1) for the weight columns [c0, c1) of ws
+// (row stride ws.R): their pair slots of part (row stride ws.R).
+void evaluate_chunk_range(const askit_handle *h, const WeightSet &ws, const PairLists &L, int64_t ch0, int64_t ch1,
+                          int c0, int c1, float *part, hipStream_t s);
+// Per-target sums of the slot columns [c0, c0 + rb) of part (row stride R) into
+// U[outmap[i]] columns [0, rb).
+void sum_slot_cols(const askit_handle *h, const PairLists &L, const float *part, int R, int c0, int rb,
+                   const int32_t *outmap, float *U, int64_t ldu, hipStream_t s);
 
 // ---------------------------------------------------------------- batched form
 // One entry per instance of a batch (device tables).  Weights of all

@@ -317,23 +317,25 @@ __global__ __launch_bounds__(EV_T) void k_eval_chunks(ChunkParams p)
 // u[i, r] = sum of target i's slots, in slot order.  Its near slots come
 // first, so the running sum after them is the near-field part of u (the
 // direct sums over the near leaves alone), written to Unear when given.
+// Columns [r0, r0 + rb) of part (row stride R) into U's columns [0, rb).
 __global__ void k_sum_slots(const int32_t *__restrict__ sbase, int64_t ntarget, const float *__restrict__ part,
                             int R, const int32_t *__restrict__ outmap, float *__restrict__ U, int64_t ldu,
-                            const int32_t *__restrict__ snear, float *__restrict__ Unear, int64_t ldun)
+                            const int32_t *__restrict__ snear, float *__restrict__ Unear, int64_t ldun, int r0,
+                            int rb)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t i = t / R;
+    const int64_t i = t / rb;
     if (i >= ntarget) return;
-    const int r = (int)(t - i * R);
+    const int j = (int)(t - i * rb), r = r0 + j;
     const int64_t o = outmap ? outmap[i] : i;
     float u = 0.0f;
     int sl = sbase[i];
     if (Unear) {
         for (; sl < snear[i]; ++sl) u += part[(int64_t)sl * R + r];
-        Unear[o * ldun + r] = u;
+        Unear[o * ldun + j] = u;
     }
     for (; sl < sbase[i + 1]; ++sl) u += part[(int64_t)sl * R + r];
-    U[o * ldu + r] = u;
+    U[o * ldu + j] = u;
 }
 
 __global__ void k_zero_i32(int32_t *__restrict__ p, int n)
@@ -343,10 +345,10 @@ __global__ void k_zero_i32(int32_t *__restrict__ p, int n)
 }
 
 template <bool MULTI>
-static void launch_passes(ChunkParams p, bool bf, int R, int64_t grid, int32_t *queue, hipStream_t s)
+static void launch_passes(ChunkParams p, bool bf, int R, int64_t grid, int32_t *queue, hipStream_t s, int c0 = 0)
 {
-    // passes of 64, 32, 4 or 1 columns
-    for (int r0 = 0; r0 < R;) {
+    // passes of 64, 32, 4 or 1 columns over columns [c0, R)
+    for (int r0 = c0; r0 < R;) {
         const int left = R - r0;
         const int cm = left > 32 ? 64 : left > 4 ? 32 : left > 1 ? 4 : 1;
         p.r0 = r0;
@@ -399,7 +401,43 @@ void evaluate(const askit_handle *h, const WeightSet &ws, const float *Y, const 
     }
     const int64_t tot = L.ntarget * ws.R;
     hipLaunchKernelGGL(k_sum_slots, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L.sbase, L.ntarget, part,
-                       ws.R, outmap, U, ldu, L.snear, Unear, ldun);
+                       ws.R, outmap, U, ldu, L.snear, Unear, ldun, 0, ws.R);
+    HIPC(hipGetLastError());
+}
+
+void evaluate_chunk_range(const askit_handle *h, const WeightSet &ws, const PairLists &L, int64_t ch0, int64_t ch1,
+                          int c0, int c1, float *part, hipStream_t s)
+{
+    if (h->dp > 1024) fail(ASKIT_ERR_UNSUPPORTED, "dimension above 1024 is not supported");
+    ch1 = std::min(ch1, L.nchunk);
+    if (ch1 <= ch0 || c1 <= c0) return;
+    ChunkParams p{};
+    p.chunks = L.chunks + ch0;
+    p.nchunk = ch1 - ch0;
+    p.tpos = L.tpos;
+    p.tslot = L.tslot;
+    p.nodes = h->d_nodes;
+    p.Y = h->Xt;
+    p.Xt = h->Xt;
+    p.gt = h->gt;
+    p.Xs = h->Xs;
+    p.gs = h->gs;
+    p.skk = h->skk;
+    p.smax = h->smax;
+    p.dp = h->dp;
+    p.Wt = ws.Wt;
+    p.Wsk = ws.Wsk;
+    p.part = part;
+    p.R = ws.R;
+    launch_passes<false>(p, h->prm.precision == ASKIT_PREC_BF16X3, c1, ch1 - ch0, nullptr, s, c0);
+}
+
+void sum_slot_cols(const askit_handle *h, const PairLists &L, const float *part, int R, int c0, int rb,
+                   const int32_t *outmap, float *U, int64_t ldu, hipStream_t s)
+{
+    const int64_t tot = L.ntarget * rb;
+    hipLaunchKernelGGL(k_sum_slots, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L.sbase, L.ntarget, part,
+                       R, outmap, U, ldu, (const int32_t *)nullptr, (float *)nullptr, (int64_t)0, c0, rb);
     HIPC(hipGetLastError());
 }
 
@@ -423,7 +461,7 @@ void evaluate_batch(const BatchEvalArgs &b, hipStream_t s)
     }
     const int64_t tot = b.rows * b.R;
     hipLaunchKernelGGL(k_sum_slots, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.sbase, b.rows, b.part,
-                       b.R, b.outrow, b.U, b.ldu, (const int32_t *)nullptr, (float *)nullptr, (int64_t)0);
+                       b.R, b.outrow, b.U, b.ldu, (const int32_t *)nullptr, (float *)nullptr, (int64_t)0, 0, b.R);
     HIPC(hipGetLastError());
 }
 

@@ -11,6 +11,20 @@
 // evaluation once for all of them and scatters the columns back; a query
 // batch stacks the points, runs one query evaluation against the resident
 // weights and scatters the rows back.
+//
+// Cyclic weights (weight_passes = K > 0): weight requests bypass the workers
+// and go to one column engine that owns a resident pool of max_batch_rhs
+// weight columns.  The evaluation's chunk list is cut into K ranges of about
+// equal pair counts; the engine sweeps them round robin, one range per pass,
+// over every column in flight.  Between passes it admits waiting requests
+// into free columns (permutation to tree order and the upward pass for those
+// columns only) and retires the columns that have now seen all K ranges
+// (their per-target slot sums go straight to the request's output).  A
+// request admitted mid-sweep therefore starts at whichever range comes next
+// and finishes one full cycle later.  Every pair slot is written by exactly
+// one pass and the slot sums run in a fixed order, so a request's result
+// equals evaluating it alone up to the rounding of the contraction width (the
+// run of live columns it rides in).
 #include "askit_impl.h"
 
 #include <algorithm>
@@ -53,6 +67,13 @@ struct Done {
     std::string err;
 };
 
+// A weight request holding pool columns [c0, c0 + r.cols).
+struct Slot {
+    Request r;
+    int c0;
+    int passes_left;
+};
+
 }  // namespace
 
 struct askit_server {
@@ -68,11 +89,17 @@ struct askit_server {
     bool stopping = false;
     uint64_t next_id = 1;
     uint64_t mem_used = 0, peak_mem = 0;
-    int64_t submitted = 0, completed = 0, failed = 0, deferred = 0, batches = 0, batched = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, deferred = 0, batches = 0, batched = 0, joined = 0;
     double targets_rhs = 0.0;
     std::vector<double> lat_all, lat_w, lat_q;
     bool any_submit = false;
     clk::time_point t_first, t_last;
+    // cyclic weights
+    std::deque<Request> wpending;         // weight requests waiting for pool columns
+    WeightSet pool;                       // pool.R = max_batch_rhs columns; pool.part: the slots
+    std::vector<int64_t> range_end;       // K + 1 chunk indices: pass p evaluates [range_end[p], range_end[p+1])
+    std::thread engine;
+    uint64_t pool_bytes = 0;
 
     uint64_t weights_bytes(int32_t R) const
     {
@@ -88,6 +115,8 @@ struct askit_server {
     }
     void worker_loop(int wid);
     void run_batch(std::vector<Request> &b, hipStream_t s);
+    void engine_loop();
+    void finish(const std::vector<Request> &rs, int32_t state, const std::string &err);
 };
 
 static double percentile(std::vector<double> v, double q)
@@ -235,26 +264,139 @@ void askit_server::worker_loop(int wid)
                 err = "internal error";
             }
         }
-        const auto t_end = clk::now();
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            for (auto &r : batch) {
-                mem_used -= r.bytes;
-                double ms = std::chrono::duration<double, std::milli>(t_end - r.t_submit).count();
-                done[r.id] = Done{state, ms, err};
-                if (state == 1) {
-                    ++completed;
-                    lat_all.push_back(ms);
-                    (r.query ? lat_q : lat_w).push_back(ms);
-                    targets_rhs += r.query ? (double)r.rows * ws0.R : (double)h->N * r.cols;
-                } else {
-                    ++failed;
-                }
+        finish(batch, state, err);
+    }
+    if (s) (void)hipStreamDestroy(s);
+}
+
+// Records the outcome of finished requests and releases their memory.
+void askit_server::finish(const std::vector<Request> &rs, int32_t state, const std::string &err)
+{
+    if (rs.empty()) return;
+    const auto t_end = clk::now();
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &r : rs) {
+            mem_used -= r.bytes;
+            double ms = std::chrono::duration<double, std::milli>(t_end - r.t_submit).count();
+            done[r.id] = Done{state, ms, err};
+            if (state == 1) {
+                ++completed;
+                lat_all.push_back(ms);
+                (r.query ? lat_q : lat_w).push_back(ms);
+                targets_rhs += r.query ? (double)r.rows * ws0.R : (double)h->N * r.cols;
+            } else {
+                ++failed;
             }
-            t_last = t_end;
         }
-        cv_done.notify_all();
-        cv_work.notify_all();
+        t_last = t_end;
+    }
+    cv_done.notify_all();
+    cv_work.notify_all();
+}
+
+void askit_server::engine_loop()
+{
+    hipStream_t s = nullptr;
+    if (hipSetDevice(h->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+        s = nullptr;
+    const int C = pool.R, K = (int)range_end.size() - 1;
+    std::vector<char> used(C, 0);
+    std::vector<Slot> live;
+    int64_t pass = 0;
+    auto fits = [&](int n) {
+        for (int c0 = 0; c0 + n <= C; ++c0) {
+            int c = c0;
+            while (c < c0 + n && !used[c]) ++c;
+            if (c == c0 + n) return c0;
+            c0 = c;   // the loop's ++ moves past the used column
+        }
+        return -1;
+    };
+    for (;;) {
+        std::vector<Slot> admitted;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            for (;;) {
+                // oldest first; a request that does not fit blocks those behind it
+                while (!wpending.empty()) {
+                    Request &head = wpending.front();
+                    const int c0 = fits(head.cols);
+                    if (c0 < 0) {
+                        if (!head.waited) {
+                            head.waited = true;
+                            ++deferred;
+                        }
+                        break;
+                    }
+                    for (int c = c0; c < c0 + head.cols; ++c) used[c] = 1;
+                    admitted.push_back(Slot{head, c0, K});
+                    wpending.pop_front();
+                }
+                if (!admitted.empty() || !live.empty()) break;
+                if (stopping && wpending.empty()) break;
+                cv_work.wait(lk);
+            }
+            if (admitted.empty() && live.empty()) break;
+            if (!admitted.empty()) {
+                ++batches;
+                batched += (int64_t)admitted.size();
+                if (!live.empty()) joined += (int64_t)admitted.size();
+            }
+        }
+        std::vector<Request> ok, bad;
+        std::string err;
+        try {
+            if (!s) fail(ASKIT_ERR_DEVICE, "engine stream creation failed");
+            for (auto &a : admitted) {
+                permute_weight_cols(h, a.r.in, a.r.ld_in, a.r.cols, pool.Wt, C, a.c0, s);
+                upward(h, pool, s, a.c0, a.c0 + a.r.cols);
+                live.push_back(a);
+            }
+            admitted.clear();
+            // this pass's range over every maximal run of live columns
+            std::vector<char> on(C, 0);
+            for (auto &l : live)
+                for (int c = l.c0; c < l.c0 + l.r.cols; ++c) on[c] = 1;
+            const int rg = (int)(pass % K);
+            for (int c = 0; c < C;) {
+                if (!on[c]) { ++c; continue; }
+                int e = c;
+                while (e < C && on[e]) ++e;
+                evaluate_chunk_range(h, pool, h->pairs, range_end[rg], range_end[rg + 1], c, e, pool.part, s);
+                c = e;
+            }
+            ++pass;
+            std::vector<Slot> keep;
+            for (auto &l : live) {
+                if (--l.passes_left > 0) {
+                    keep.push_back(l);
+                    continue;
+                }
+                sum_slot_cols(h, h->pairs, pool.part, C, l.c0, l.r.cols, h->perm, l.r.out, l.r.ld_out, s);
+                ok.push_back(l.r);
+                for (int c = l.c0; c < l.c0 + l.r.cols; ++c) used[c] = 0;
+            }
+            HIPC(hipStreamSynchronize(s));
+            live.swap(keep);
+        } catch (const Error &e) {
+            err = e.msg;
+        } catch (...) {
+            err = "internal error";
+        }
+        if (!err.empty()) {
+            // every request in flight fails; the pool starts over empty
+            if (s) (void)hipStreamSynchronize(s);
+            for (auto &a : admitted) bad.push_back(a.r);
+            for (auto &l : live) bad.push_back(l.r);
+            bad.insert(bad.end(), ok.begin(), ok.end());
+            ok.clear();
+            live.clear();
+            std::fill(used.begin(), used.end(), 0);
+        }
+        finish(ok, 1, "");
+        finish(bad, -1, err);
     }
     if (s) (void)hipStreamDestroy(s);
 }
@@ -287,6 +429,8 @@ askit_status askit_server_config_default(askit_server_config *c)
     c->max_batch_rhs = 64;
     c->max_batch_queries = 65536;
     c->mem_budget = 8ull << 30;
+    c->weight_passes = 0;
+    c->max_pending = 0;
     return ASKIT_OK;
 }
 
@@ -302,6 +446,9 @@ askit_status askit_server_create(askit_handle *h, const float *W0, int64_t ldw0,
     if (cfg->max_batch_rhs < 1 || cfg->max_batch_rhs > MAX_RHS)
         fail(ASKIT_ERR_INVALID_ARG, "need 1 <= max_batch_rhs <= 64");
     if (cfg->max_batch_queries < 1) fail(ASKIT_ERR_INVALID_ARG, "need max_batch_queries >= 1");
+    if (cfg->weight_passes < 0 || cfg->weight_passes > 4096)
+        fail(ASKIT_ERR_INVALID_ARG, "need 0 <= weight_passes <= 4096");
+    if (cfg->max_pending < 0) fail(ASKIT_ERR_INVALID_ARG, "need max_pending >= 0");
     if (nrhs0 < 1 || nrhs0 > MAX_RHS || ldw0 < nrhs0) fail(ASKIT_ERR_INVALID_ARG, "bad resident weights");
     std::unique_ptr<askit_server> sv(new askit_server());
     sv->h = h;
@@ -317,9 +464,42 @@ askit_status askit_server_create(askit_handle *h, const float *W0, int64_t ldw0,
     HIPC(hipMemset(sv->ws0.Wsk, 0, sizeof(float) * nn * h->smax * nrhs0));
     permute_weights(h, W0, ldw0, sv->ws0, nullptr);
     upward(h, sv->ws0, nullptr);
+    if (sv->cfg.weight_passes > 0) {
+        // the column pool stays allocated for the server's lifetime and is
+        // charged to the budget up front
+        const int C = sv->cfg.max_batch_rhs;
+        sv->pool_bytes = sv->weights_bytes(C);
+        if (sv->pool_bytes > sv->cfg.mem_budget)
+            fail(ASKIT_ERR_OUT_OF_MEMORY, "the weight column pool exceeds the server memory budget");
+        sv->pool.R = C;
+        HIPC(hipMalloc((void **)&sv->pool.Wt, sizeof(float) * h->N * C));
+        sv->own.push_back(sv->pool.Wt);
+        HIPC(hipMalloc((void **)&sv->pool.Wsk, sizeof(float) * nn * h->smax * C));
+        sv->own.push_back(sv->pool.Wsk);
+        HIPC(hipMemset(sv->pool.Wsk, 0, sizeof(float) * nn * h->smax * C));
+        HIPC(hipMalloc((void **)&sv->pool.part, sizeof(float) * std::max<int64_t>(h->pairs.npairs, 1) * C));
+        sv->own.push_back(sv->pool.part);
+        sv->mem_used = sv->peak_mem = sv->pool_bytes;
+        // K ranges of the chunk list with about npairs / K pairs each
+        const int K = sv->cfg.weight_passes;
+        const int64_t nc = h->pairs.nchunk;
+        std::vector<Chunk> ch((size_t)nc);
+        if (nc > 0) HIPC(hipMemcpy(ch.data(), h->pairs.chunks, sizeof(Chunk) * nc, hipMemcpyDeviceToHost));
+        int64_t tot = 0;
+        for (auto &c : ch) tot += c.count;
+        sv->range_end.assign(K + 1, nc);
+        sv->range_end[0] = 0;
+        int64_t acc = 0, i = 0;
+        for (int k = 1; k < K; ++k) {
+            const int64_t goal = (tot * k + K - 1) / K;
+            while (i < nc && acc < goal) acc += ch[(size_t)i++].count;
+            sv->range_end[k] = i;
+        }
+    }
     HIPC(hipDeviceSynchronize());
     for (int w = 0; w < sv->cfg.workers; ++w)
         sv->workers.emplace_back([p = sv.get(), w] { p->worker_loop(w); });
+    if (sv->cfg.weight_passes > 0) sv->engine = std::thread([p = sv.get()] { p->engine_loop(); });
     *out = sv.release();
     API_END
 }
@@ -329,6 +509,9 @@ static askit_status submit(askit_server *s, Request r, uint64_t *ticket)
     if (r.bytes > s->cfg.mem_budget) fail(ASKIT_ERR_OUT_OF_MEMORY, "request exceeds the server memory budget");
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) fail(ASKIT_ERR_INVALID_ARG, "server is stopping");
+    const bool cyclic = !r.query && s->cfg.weight_passes > 0;
+    if (s->cfg.max_pending > 0 && (int64_t)(s->pending.size() + s->wpending.size()) >= s->cfg.max_pending)
+        fail(ASKIT_ERR_BUSY, "the server's queue is full; submit again later");
     r.id = s->next_id++;
     r.t_submit = clk::now();
     if (!s->any_submit) {
@@ -337,8 +520,13 @@ static askit_status submit(askit_server *s, Request r, uint64_t *ticket)
     }
     ++s->submitted;
     *ticket = r.id;
-    s->pending.push_back(r);
-    s->cv_work.notify_one();
+    if (cyclic) {
+        s->wpending.push_back(r);
+        s->cv_work.notify_all();   // the engine shares the condition with the workers
+    } else {
+        s->pending.push_back(r);
+        s->cv_work.notify_one();
+    }
     return ASKIT_OK;
 }
 
@@ -357,7 +545,7 @@ askit_status askit_server_submit_weights(askit_server *s, const float *W, int64_
     r.cols = nrhs;
     r.out = U;
     r.ld_out = ldu;
-    r.bytes = s->weights_bytes(nrhs);
+    r.bytes = s->cfg.weight_passes > 0 ? 0 : s->weights_bytes(nrhs);   // cyclic: the pool is charged already
     return submit(s, r, ticket);
     API_END
 }
@@ -437,6 +625,7 @@ askit_status askit_server_stats(askit_server *s, askit_serving_stats *o)
     o->targets_rhs = s->targets_rhs;
     o->busy_s = s->any_submit ? std::chrono::duration<double>(s->t_last - s->t_first).count() : 0.0;
     o->peak_mem = s->peak_mem;
+    o->joined_mid_cycle = s->joined;
     API_END
 }
 
@@ -449,6 +638,7 @@ void askit_server_destroy(askit_server *s)
     }
     s->cv_work.notify_all();
     for (auto &t : s->workers) t.join();
+    if (s->engine.joinable()) s->engine.join();
     for (void *p : s->own) (void)hipFree(p);
     delete s;
 }

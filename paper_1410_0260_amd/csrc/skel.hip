@@ -976,7 +976,7 @@ __global__ __launch_bounds__(64) void k_upward(const Node *__restrict__ nodes,
                                                const int64_t *__restrict__ pslot,
                                                const float *__restrict__ P, int smax,
                                                const float *__restrict__ Wt, int R,
-                                               float *__restrict__ Wsk)
+                                               float *__restrict__ Wsk, int r0, int r1)
 {
     const int a = ids[blockIdx.x], t = blockIdx.y, lane = threadIdx.x;
     const int k = skk[a];
@@ -991,7 +991,7 @@ __global__ __launch_bounds__(64) void k_upward(const Node *__restrict__ nodes,
         return c < kl ? Wsk[((int64_t)nd.left * smax + c) * R + r]
                       : Wsk[((int64_t)nd.right * smax + (c - kl)) * R + r];
     };
-    for (int r = 0; r < R; ++r) {
+    for (int r = r0; r < r1; ++r) {
         float acc = 0.0f;
         for (int c = lane; c < nr; c += 64) acc = fmaf(Pt[c], wc(pv[k + c], r), acc);
 #pragma unroll
@@ -1013,13 +1013,14 @@ void prepare_upward(askit_handle *h)
         HIPC(hipMemcpy(h->up_ids, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice));
 }
 
-void upward(askit_handle *h, const WeightSet &ws, hipStream_t s)
+void upward(askit_handle *h, const WeightSet &ws, hipStream_t s, int r0, int r1)
 {
+    if (r1 < 0) r1 = ws.R;
     for (auto &sg : h->up_seg) {
         if (sg.second == 0) continue;
         hipLaunchKernelGGL(k_upward, dim3(sg.second, h->smax), dim3(64), 0, s, h->d_nodes,
                            h->up_ids + sg.first, h->skk, h->ncols, h->colperm, h->ncol_max, h->d_pslot,
-                           h->P, h->smax, ws.Wt, ws.R, ws.Wsk);
+                           h->P, h->smax, ws.Wt, ws.R, ws.Wsk, r0, r1);
         HIPC(hipGetLastError());
     }
 }

@@ -93,6 +93,7 @@ def test_server_argument_checks():
     A = _lib()
     c = A.server_config()
     assert c.workers == 2 and c.max_batch_rhs == 64 and c.mem_budget == 8 << 30
+    assert c.weight_passes == 0 and c.max_pending == 0 and C.sizeof(c) == c.struct_size == 32
     L = A._server_lib()
     out = C.c_void_p()
     assert L.askit_server_create(None, None, 1, 1, C.byref(c), C.byref(out)) == A.ERR_INVALID_ARG

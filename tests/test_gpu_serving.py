@@ -183,3 +183,92 @@ def test_serving_memory_admission():
     srv.close()
     h.close()
     assert all(o.shape == (N, 2) for o in outs)
+
+
+@pytest.mark.parametrize("passes", [1, 5])
+def test_cyclic_weights_poisson(passes):
+    """Cyclic weights: weight requests arriving on a Poisson schedule join the
+    column pool between passes of the round-robin evaluation while earlier
+    requests are part way through their cycle; queries are served beside
+    them by the workers.  Every result equals the request run alone."""
+    import time
+    import torch
+    A, h, X = _setup()
+    N, d = X.shape
+    W0 = synth.weights(N, 2, 903)
+    reqs = _requests(N, d, 30, 9)
+    alone = _alone(h, reqs, W0)
+    inputs = [torch.from_numpy(a).cuda() for _, a in reqs]
+    torch.cuda.synchronize()
+    gaps = np.random.default_rng(67).exponential(0.001, len(reqs))
+    gaps[:8] = 0.0                 # a burst first: later requests join while the first are in flight
+    srv = A.Server(h, torch.from_numpy(W0).cuda(),
+                   A.server_config(workers=2, max_batch_rhs=16, max_batch_queries=1500, weight_passes=passes))
+    tickets = []
+    for (kind, _), x, gap in zip(reqs, inputs, gaps):
+        time.sleep(float(gap))
+        tickets.append(srv.submit_weights(x) if kind == "w" else srv.submit_query(x))
+    outs = [srv.wait(t, 120.0).cpu().numpy().astype(np.float64) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    h.close()
+    nw = sum(k == "w" for k, _ in reqs)
+    print(f"[serving cyclic K={passes}] {st['joined_mid_cycle']} of {nw} weight requests joined mid-cycle; {st}")
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    if passes > 1:
+        assert st["joined_mid_cycle"] > 0
+    _check_same(reqs, alone, outs)
+
+
+def test_cyclic_weights_match_oracle():
+    """Weight requests served in cyclic mode (7 passes, an 8-column pool so
+    that requests wait for columns) against the FP64 oracle at 1500 sampled
+    points."""
+    import torch
+    A, h, X = _setup()
+    N = X.shape[0]
+    W0 = synth.weights(N, 1, 904)
+    Ws = [synth.weights(N, c, 3000 + i) for i, c in enumerate([3, 5, 1, 8, 2, 4])]
+    srv = A.Server(h, torch.from_numpy(W0).cuda(), A.server_config(workers=1, max_batch_rhs=8, weight_passes=7))
+    tickets = [srv.submit_weights(torch.from_numpy(w).cuda()) for w in Ws]
+    outs = [srv.wait(t, 120.0).cpu().numpy().astype(np.float64) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    h.close()
+    assert st["completed"] == len(Ws) and st["deferred"] > 0
+    so = O.setup(X, P_SERVE)
+    tg = np.sort(np.random.default_rng(10).choice(N, 1500, replace=False))
+    nb = O.self_neighbours(so, tg)
+    for W, U in zip(Ws, outs):
+        Wsk = O.upward(so["nodes"], W[so["perm"]].astype(np.float64), so["sk"], P_SERVE.smax)
+        ref = O.evaluate(X[tg], nb, X, so["perm"], so["nodes"], None, P_SERVE.h, W, so["sk"], Wsk, P_SERVE.smax,
+                         record=False).U
+        for r in range(W.shape[1]):
+            e = rel(U[tg, r], ref[:, r])
+            print(f"[cyclic vs oracle] column {r} of {W.shape[1]}: {e:.2e}", flush=True)
+            assert e < 1e-5
+
+
+def test_server_queue_limit():
+    """max_pending bounds the queue: a burst beyond it is refused with
+    ASKIT_ERR_BUSY and every accepted request still completes."""
+    import torch
+    A, h, X = _setup()
+    N = X.shape[0]
+    W0 = synth.weights(N, 1, 905)
+    srv = A.Server(h, torch.from_numpy(W0).cuda(),
+                   A.server_config(workers=1, max_batch_rhs=4, weight_passes=3, max_pending=2))
+    Ws = [torch.from_numpy(synth.weights(N, 4, 4000 + i)).cuda() for i in range(40)]
+    torch.cuda.synchronize()
+    tickets, busy = [], 0
+    for w in Ws:
+        try:
+            tickets.append(srv.submit_weights(w))
+        except A.AskitError as e:
+            assert e.code == A.ERR_BUSY
+            busy += 1
+    states = [srv.wait(t, 120.0) is not None for t in tickets]
+    st = srv.stats()
+    srv.close()
+    h.close()
+    assert busy > 0 and all(states) and st["completed"] == len(tickets) and st["failed"] == 0
