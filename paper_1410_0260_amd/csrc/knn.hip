@@ -540,6 +540,21 @@ __global__ __launch_bounds__(256) void k_knn_cand_wide(const uint16_t *__restric
 // may keep fewer than 64 of the window's points (their distances can come
 // from the transposed product, rounded differently); the selection and its
 // certificate allow both.
+// Row block of workgroup i (of n) for the listed symmetric sweep.  Workgroups
+// are dealt to the 8 XCDs round robin (id mod 8); here the j-th workgroup of
+// an XCD takes row block j within runs of 64 consecutive blocks per XCD, so
+// the blocks resident on one XCD at a time are neighbours in the sweep order,
+// whose tile lists overlap: the tiles they stream are shared in that XCD's
+// L2.  A bijection on [0, n) (the last partial round keeps the identity).
+__device__ __forceinline__ int64_t xcd_run_block(int64_t i, int64_t n)
+{
+    constexpr int64_t XCD = 8, RUN = 64;
+    const int64_t full = n / (XCD * RUN) * (XCD * RUN);
+    if (i >= full) return i;
+    const int64_t x = i % XCD, j = i / XCD;
+    return ((j / RUN) * XCD + x) * RUN + j % RUN;
+}
+
 template <int KS, bool SYM>
 __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restrict__ Qh,
                                                        const uint16_t *__restrict__ Ql,
@@ -567,7 +582,8 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     const int tid = threadIdx.x, lane = tid % WAVE;
     const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const int half = lane >> 5, l32 = lane & 31;
-    const int64_t q0 = (int64_t)blockIdx.x * KB_M + wv * 32;     // local row (output segments)
+    const int64_t bx = (SYM && tlist) ? xcd_run_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t q0 = bx * KB_M + wv * 32;     // local row (output segments)
 
     bf16x8 ah[KS], al[KS];
     {
@@ -594,7 +610,7 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     // 32-bit row indices (M < 2^31) keep the survivor path's state small
     const uint32_t qbase = (uint32_t)q0 + 4u * (uint32_t)half;
     const int64_t ntiles_all = (N + KB_N - 1) / KB_N;
-    const int64_t tself = ((row0 + (int64_t)blockIdx.x * KB_M) / KB_N) % ntiles_all;   // the block's own tile
+    const int64_t tself = ((row0 + bx * KB_M) / KB_N) % ntiles_all;   // the block's own tile
     int64_t ntiles = SYM ? ntiles_all - tself : ntiles_all;
     int64_t t0 = tself;
     if (!SYM && win_tiles > 0 && win_tiles < ntiles_all) {
@@ -614,8 +630,8 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     // own two first), in increasing order
     const int32_t *tl = nullptr;
     if (SYM && tlist) {
-        tl = tlist + toff[blockIdx.x];
-        ntiles = toff[blockIdx.x + 1] - toff[blockIdx.x];
+        tl = tlist + toff[bx];
+        ntiles = toff[bx + 1] - toff[bx];
     }
     if (ntiles <= 0) return;
     // tile counts fit 32 bits (N < 2^31 points)
@@ -626,9 +642,24 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     float rn[1] = {0.0f};
     // entry of list position t: the tile, and in bits 27-30 the waves that
     // sweep it (all four without lists)
+    // with lists: 64 entries per register (one per lane), the next 64 loaded
+    // a full chunk ahead; entries are read with a uniform lane index, so the
+    // next tile's address never waits on a list load
+    int lcur = 0, lnxt = 0;
+    if (SYM && tl) {
+        lcur = lane < nt32 ? tl[lane] : 0;
+        lnxt = 64 + lane < nt32 ? tl[64 + lane] : 0;
+    }
     auto tile_of = [&](int t) -> int {
         if constexpr (SYM) {
-            if (tl) return tl[t];
+            if (tl) {
+                // positions are asked for in order 0, 1, 2, ...
+                if ((t & 63) == 0 && t > 0) {
+                    lcur = lnxt;
+                    lnxt = t + 64 + lane < nt32 ? tl[t + 64 + lane] : 0;
+                }
+                return __builtin_amdgcn_readlane(lcur, t & 63);
+            }
         }
         const int tt = t032 + t;
         return (tt >= nta32 ? tt - nta32 : tt) | (15 << 27);
@@ -713,11 +744,16 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
             const uint32_t cA = (uint32_t)tbase + (uint32_t)l32, cB = cA + 32u;
             const uint32_t n32 = (uint32_t)N;
             const uint32_t below = (1u << l32) - 1u;
+            // an opaque copy of the rows' base: otherwise the compiler hoists
+            // the 16 rows' 64-bit segment offsets out of the sweep loop, spills
+            // them, and every append waits on a scratch reload
+            uint32_t qb = qbase;
+            asm volatile("" : "+v"(qb));
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 // the 32 lanes of a half-wave hold the same row: one counter
                 // update per row and half-wave, lanes write at their prefix
-                const uint32_t qrow = qbase + (uint32_t)(8 * (r / 4) + (r % 4));
+                const uint32_t qrow = qb + (uint32_t)(8 * (r / 4) + (r % 4));
                 const float dA = dv[r];
                 const float dB = dv[16 + r];
                 const bool pA = dA <= thrv[r] && cA < n32 && !(excl && cA == qrow + (uint32_t)row0);
