@@ -26,5 +26,26 @@ def build(force: bool = True) -> str:
     return OUT
 
 
+ASAN_OUT = os.path.join(HERE, "liboracle_asan.so")
+
+
+def build_asan(force: bool = True) -> str:
+    """The same source under AddressSanitizer and UndefinedBehaviorSanitizer
+    (`liboracle_asan.so`): loaded instead of `liboracle.so` when
+    ASKIT_ORACLE_ASAN=1, by a process that preloads the ASan runtime."""
+    if not force and os.path.exists(ASAN_OUT) and os.path.getmtime(ASAN_OUT) >= os.path.getmtime(SRC):
+        return ASAN_OUT
+    tmp = ASAN_OUT + f".tmp{os.getpid()}"
+    cmd = ["gcc", "-O1", "-g", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-Wall", "-Wno-unknown-pragmas", SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, ASAN_OUT)
+    return ASAN_OUT
+
+
 if __name__ == "__main__":
-    print(build(force="--lazy" not in sys.argv))
+    if "--asan" in sys.argv:
+        print(build_asan(force="--lazy" not in sys.argv))
+    else:
+        print(build(force="--lazy" not in sys.argv))

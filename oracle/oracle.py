@@ -30,7 +30,10 @@ NODE_DTYPE = np.dtype([("lo", "<i4"), ("hi", "<i4"), ("level", "<i4"), ("parent"
 def lib():
     global _lib
     if _lib is None:
-        path = _build.build(force=False)
+        # ASKIT_ORACLE_ASAN=1: the sanitizer build (the process must preload
+        # the ASan runtime)
+        asan = os.environ.get("ASKIT_ORACLE_ASAN") == "1"
+        path = _build.build_asan(force=False) if asan else _build.build(force=False)
         L = C.CDLL(path)
         P = C.c_void_p
         i64, i32, f64, u64 = C.c_int64, C.c_int, C.c_double, C.c_uint64
