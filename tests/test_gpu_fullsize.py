@@ -229,3 +229,87 @@ def test_u_beta_weights(full, targets):
     assert is_near.sum() >= 256 and is_far.sum() >= 8
     for sel in (is_near, is_far):
         assert np.linalg.norm(Ug[sel] - Uo[sel]) <= U_TOL * np.linalg.norm(Uo[sel])
+
+
+# ---------------------------------------------------------------------------
+# Against the full FP64 oracle run of this workload (tests/golden/, written by
+# tests/golden/make_fullsize_golden.py, which calls only the oracle): u and its
+# near-field part at 10,000 seeded targets, their interaction lists, ~200
+# nodes' skeletons on every level, and P, column order and skeleton weights of
+# 8 nodes.
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "fullsize_fp32_1m_h1.npz")
+
+
+@pytest.fixture(scope="module")
+def gold():
+    import torch
+    from paper_1410_0260_amd import askit as A
+    z = dict(np.load(GOLDEN))
+    wl = synth.fp32_1m()
+    assert float(z["h"]) == wl.h
+    X = synth.points(wl)
+    W = synth.weights(wl.N, wl.R, wl.seed)
+    _log("\n[fullsize-oracle] HIP setup + update + evaluate with the workload's weights")
+    h = A.setup(torch.from_numpy(X).cuda(), A.params_from_workload(wl))
+    h.update_weights(torch.from_numpy(W).cuda())
+    U, Un = h.evaluate_parts()
+    torch.cuda.synchronize()
+    g = h.structures()
+    h.close()
+    g["U"] = U.cpu().numpy().astype(np.float64)[:, 0]
+    g["Un"] = Un.cpu().numpy().astype(np.float64)[:, 0]
+    return wl, z, g
+
+
+def test_fullsize_oracle_u(gold):
+    wl, z, g = gold
+    tg = z["targets"]
+    e = float(np.linalg.norm(g["U"][tg] - z["u"]) / np.linalg.norm(z["u"]))
+    en = float(np.linalg.norm(g["Un"][tg] - z["u_near"]) / np.linalg.norm(z["u_near"]))
+    eps_gpu = float(np.linalg.norm(g["U"][tg] - z["u_direct"]) / np.linalg.norm(z["u_direct"]))
+    _log(f"[fullsize-oracle] u vs oracle {e:.2e}, near part {en:.2e}; eps vs FP64 direct: GPU {eps_gpu:.4f}, "
+         f"oracle {float(z['eps']):.4f}")
+    assert e < U_TOL and en < U_TOL
+    assert abs(eps_gpu - float(z["eps"])) <= 1e-4 * float(z["eps"]) + 1e-6
+
+
+def test_fullsize_oracle_lists(gold):
+    wl, z, g = gold
+    N = wl.N
+    iperm = np.empty(N, np.int64)
+    iperm[g["perm"]] = np.arange(N)
+    for r, o in enumerate(z["targets"]):
+        near, far = _gpu_lists(g, int(iperm[o]))
+        for ids, c, s1, s2 in ((near, "near_cnt", "near_s1", "near_s2"), (far, "far_cnt", "far_s1", "far_s2")):
+            a = np.array(ids, np.int64)
+            assert (len(a), int(a.sum()), int((a * a).sum())) == (int(z[c][r]), int(z[s1][r]), int(z[s2][r])), \
+                f"target {o}"
+
+
+def test_fullsize_oracle_nodes(gold):
+    wl, z, g = gold
+    ties = 0
+    for r, a in enumerate(z["nodes"]):
+        k = int(z["k"][r])
+        same = g["k"][a] == k and np.array_equal(g["S"][a, :k], z["S"][r, :k])
+        if not same:
+            assert min(z["piv_margin"][r], z["rank_margin"][r]) < 1e-10, f"node {a}"
+            ties += 1
+    assert ties == 0
+
+
+def test_fullsize_oracle_projections(gold):
+    wl, z, g = gold
+    p = O.Params.from_workload(wl)
+    V = np.random.default_rng(20141003).standard_normal((int(g["info"]["ncol_max"]), z["p_sketch"].shape[2]))
+    for r, a in enumerate(z["p_nodes"]):
+        k, n = int(g["k"][a]), int(z["p_ncols"][r])
+        assert g["ncols"][a] == n and np.array_equal(g["colperm"][a, :n], z["p_colperm"][r, :n]), f"node {a}"
+        off = _pslot_offset(g["nodes"], a, p, wl.N)
+        Pg = g["P"][off:off + k * (n - k)].reshape(k, n - k).astype(np.float64)
+        sk = Pg @ V[:n - k]
+        ref = z["p_sketch"][r, :k]
+        assert np.linalg.norm(sk - ref) <= 1e-5 * max(1.0, np.linalg.norm(ref)), f"node {a}"
+        assert abs(np.linalg.norm(Pg) - z["p_fro"][r]) <= 1e-5 * max(1.0, z["p_fro"][r]), f"node {a}"
+        w = z["wsk"][r, :k]
+        assert np.linalg.norm(g["Wsk"][a, :k, 0] - w) <= 1e-5 * max(1.0, np.linalg.norm(w)), f"node {a}"
