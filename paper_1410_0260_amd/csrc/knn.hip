@@ -540,21 +540,6 @@ __global__ __launch_bounds__(256) void k_knn_cand_wide(const uint16_t *__restric
 // may keep fewer than 64 of the window's points (their distances can come
 // from the transposed product, rounded differently); the selection and its
 // certificate allow both.
-// Row block of workgroup i (of n) for the listed symmetric sweep.  Workgroups
-// are dealt to the 8 XCDs round robin (id mod 8); here the j-th workgroup of
-// an XCD takes row block j within runs of 64 consecutive blocks per XCD, so
-// the blocks resident on one XCD at a time are neighbours in the sweep order,
-// whose tile lists overlap: the tiles they stream are shared in that XCD's
-// L2.  A bijection on [0, n) (the last partial round keeps the identity).
-__device__ __forceinline__ int64_t xcd_run_block(int64_t i, int64_t n)
-{
-    constexpr int64_t XCD = 8, RUN = 64;
-    const int64_t full = n / (XCD * RUN) * (XCD * RUN);
-    if (i >= full) return i;
-    const int64_t x = i % XCD, j = i / XCD;
-    return ((j / RUN) * XCD + x) * RUN + j % RUN;
-}
-
 template <int KS, bool SYM>
 __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restrict__ Qh,
                                                        const uint16_t *__restrict__ Ql,
@@ -568,7 +553,8 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
                                                        float *__restrict__ od,
                                                        int32_t *__restrict__ oi, int win_tiles,
                                                        const int32_t *__restrict__ tlist,
-                                                       const int64_t *__restrict__ toff)
+                                                       const int64_t *__restrict__ toff,
+                                                       const int4 *__restrict__ items)
 {
     constexpr int DP = KS * 16;
     constexpr int LDB = DP + 8;
@@ -582,7 +568,10 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     const int tid = threadIdx.x, lane = tid % WAVE;
     const int wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const int half = lane >> 5, l32 = lane & 31;
-    const int64_t bx = (SYM && tlist) ? xcd_run_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    // listed sweep: workgroup i takes the piece items[i] = (row block, first
+    // list position, tile count) of a block's tile list
+    const int4 item = (SYM && tlist) ? items[blockIdx.x] : int4{(int)blockIdx.x, 0, 0, 0};
+    const int64_t bx = item.x;
     const int64_t q0 = bx * KB_M + wv * 32;     // local row (output segments)
 
     bf16x8 ah[KS], al[KS];
@@ -627,11 +616,11 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
         ntiles = t0 < ntiles_all ? min(per, ntiles_all - t0) : 0;
     }
     // SYM with tile lists: only the tiles that may hold a survivor (the block's
-    // own two first), in increasing order
+    // own two first), in increasing order; this workgroup's piece of them
     const int32_t *tl = nullptr;
     if (SYM && tlist) {
-        tl = tlist + toff[bx];
-        ntiles = toff[bx + 1] - toff[bx];
+        tl = tlist + toff[bx] + item.y;
+        ntiles = item.z;
     }
     if (ntiles <= 0) return;
     // tile counts fit 32 bits (N < 2^31 points)
@@ -785,7 +774,7 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
         }
         if constexpr (SYM) {
             // tiles after the block's own two: offer each distance to the tile's point too
-            if (t >= 2 && on) {
+            if ((ent & 0x7ffffff) >= tself + 2 && on) {
                 const float *tb = sBt + (t % 3) * KB_N;
                 const float tA = tb[l32], tB = tb[32 + l32];
                 bool anyc = false;
@@ -1002,14 +991,16 @@ static void launch_filter(dim3 g, dim3 b, hipStream_t s, const uint16_t *Qh, con
                           const float *Qn, int64_t M, const uint16_t *Xh, const uint16_t *Xl,
                           const float *Xn, int64_t N, int ex, int64_t row0, const float *T, int cap,
                           int32_t *ocnt, float *od, int32_t *oi, bool sym, int win = 0,
-                          const int32_t *tlist = nullptr, const int64_t *toff = nullptr)
+                          const int32_t *tlist = nullptr, const int64_t *toff = nullptr,
+                          const int4 *items = nullptr)
 {
     if (sym)
         hipLaunchKernelGGL((k_knn_filter<KS, true>), g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, row0, T, cap,
-                           ocnt, od, oi, 0, tlist, toff);
+                           ocnt, od, oi, 0, tlist, toff, items);
     else
         hipLaunchKernelGGL((k_knn_filter<KS, false>), g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, row0, T,
-                           cap, ocnt, od, oi, win, (const int32_t *)nullptr, (const int64_t *)nullptr);
+                           cap, ocnt, od, oi, win, (const int32_t *)nullptr, (const int64_t *)nullptr,
+                           (const int4 *)nullptr);
 }
 
 __global__ void k_fill_f32(float *__restrict__ p, int64_t n, float v)
@@ -1100,12 +1091,13 @@ static void filter_select(int dp, hipStream_t s, const uint16_t *Qh, const uint1
                           int64_t M, const uint16_t *Xh, const uint16_t *Xl, const float *Xn, int64_t N, int ex,
                           int64_t chunk, float *thr, const FilterBufs &B, int32_t *cand, int32_t *over, bool sym,
                           int win, std::vector<hipEvent_t> *ev, const int32_t *tlist = nullptr,
-                          const int64_t *toff = nullptr)
+                          const int64_t *toff = nullptr, const int4 *items = nullptr, int64_t nitems = 0)
 {
     const int64_t ntl = (N + KB_N - 1) / KB_N;
     for (int64_t r0 = 0; r0 < M; r0 += chunk) {
         const int64_t m = std::min<int64_t>(chunk, M - r0);
         dim3 g((unsigned)((m + KB_M - 1) / KB_M), (unsigned)((sym || win > 0) ? 1 : filter_segments(m, ntl)));
+        if (sym && tlist) g = dim3((unsigned)nitems);      // one workgroup per list piece
         HIPC(hipMemsetAsync(B.ocnt, 0, sizeof(int32_t) * m, s));
         if (ev) {
             ev->resize(ev->size() + 2);
@@ -1114,7 +1106,7 @@ static void filter_select(int dp, hipStream_t s, const uint16_t *Qh, const uint1
             HIPC(hipEventRecord((*ev)[ev->size() - 2], s));
         }
         KNN_DISPATCH(launch_filter, g, dim3(256), s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, KNN_CAP, B.ocnt,
-                     B.od, B.oi, sym, win, tlist, toff);
+                     B.od, B.oi, sym, win, tlist, toff, items);
         if (ev) HIPC(hipEventRecord(ev->back(), s));
         hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, KNN_CAP, B.ocnt,
                            B.od, B.oi, cand, thr, over ? over + 1 : nullptr, over);
@@ -1201,6 +1193,7 @@ __global__ void k_gather_qrows(const int32_t *__restrict__ rows, int64_t n, int 
 // relative.  ASKIT_KNN_NO_SKIP=1 in the environment sweeps every pair (the
 // same output, for comparison).
 constexpr int TL_TILE_BITS = 27;
+constexpr int64_t KNN_PIECE = 2048;         // tiles per work item of the listed sweep
 constexpr int32_t TL_TILE_MASK = (1 << TL_TILE_BITS) - 1;
 
 struct TileGeom {
@@ -1333,8 +1326,8 @@ __global__ __launch_bounds__(64) void k_tile_list(const uint64_t *__restrict__ m
 // order, stride dp; thr the rows' thresholds).  Returns false (no lists) when
 // they do not apply.  Allocations go to tmp.
 static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const float *thr, const float *Xn,
-                             int32_t *&tlist, int64_t *&toff, int64_t &kept, std::vector<void *> &tmp,
-                             hipStream_t s)
+                             int32_t *&tlist, int64_t *&toff, int64_t &kept, int4 *&items, int64_t &nitems,
+                             std::vector<void *> &tmp, hipStream_t s)
 {
     static_assert(KB_M == 2 * KB_N && KB_M == 4 * 32, "a row block is two tiles and four waves of 32 rows");
     const int64_t ntiles = (N + KB_N - 1) / KB_N, nblk = (N + KB_M - 1) / KB_M, ngroups = (N + 31) / 32;
@@ -1374,6 +1367,24 @@ static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const fl
     ho[0] = 0;
     for (int64_t b = 0; b < nblk; ++b) ho[b + 1] = ho[b] + hc[b];
     kept = ho[nblk];
+    // Work items: the lists vary by more than 10x between row blocks (dense
+    // regions keep many tiles), so each list is cut into pieces of at most
+    // KNN_PIECE tiles and the pieces are launched longest first: the
+    // workgroups that start last are the short ones, and no single list sets
+    // the sweep's length.
+    std::vector<int4> hi;
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int64_t c = hc[b];
+        const int64_t np = (c + KNN_PIECE - 1) / KNN_PIECE;
+        for (int64_t q = 0; q < np; ++q) {
+            const int64_t a0 = c * q / np, a1 = c * (q + 1) / np;
+            hi.push_back(int4{(int)b, (int)a0, (int)(a1 - a0), 0});
+        }
+    }
+    std::stable_sort(hi.begin(), hi.end(), [](const int4 &x, const int4 &y) { return x.z > y.z; });
+    nitems = (int64_t)hi.size();
+    items = (int4 *)ta(sizeof(int4) * std::max<int64_t>(nitems, 1));
+    if (nitems > 0) HIPC(hipMemcpyAsync(items, hi.data(), sizeof(int4) * nitems, hipMemcpyHostToDevice, s));
     tlist = (int32_t *)ta(sizeof(int32_t) * std::max<int64_t>(kept, 1));
     HIPC(hipMemcpyAsync(toff, ho.data(), sizeof(int64_t) * (nblk + 1), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_tile_list, dim3((unsigned)nblk), dim3(64), 0, s, mask, moff, ntiles, toff, tlist);
@@ -1447,17 +1458,19 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     // come within the thresholds
     std::vector<void *> ttmp;
     int32_t *tlist = nullptr;
-    int64_t *toff = nullptr, kept = 0;
+    int64_t *toff = nullptr, kept = 0, nitems = 0;
+    int4 *items = nullptr;
     if (sym && !std::getenv("ASKIT_KNN_NO_SKIP") &&
-        build_tile_lists(Xf, dp, d, N, thr, Xn, tlist, toff, kept, ttmp, s)) {
+        build_tile_lists(Xf, dp, d, N, thr, Xn, tlist, toff, kept, items, nitems, ttmp, s)) {
         if (tiles_swept) *tiles_swept = kept;
     } else {
         tlist = nullptr;
         toff = nullptr;
+        items = nullptr;
     }
     std::vector<hipEvent_t> ev;             // brackets of each filter launch (timing only)
     filter_select(dp, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, chunk, thr, B, cand, retry, sym, 0,
-                  t_filter_ms ? &ev : nullptr, tlist, toff);
+                  t_filter_ms ? &ev : nullptr, tlist, toff, items, nitems);
     int32_t nretry = 0;
     HIPC(hipMemcpyAsync(&nretry, retry, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
