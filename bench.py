@@ -329,7 +329,10 @@ def batched_bench(args, A, torch):
         "plain_path": {"ms_per_step": res["plain"], "value": b.rows * R / (res["plain"] * 1e-3)},
         "batched_equals_plain": same,
         "setup_s": t_setup,
-        "tuner": {"launch_blocks": inf["launch_blocks"], "candidate_ms": inf["candidate_ms"]},
+        "tuner": {"launch_blocks": inf["launch_blocks"], "launch_plan": ["wide", "narrow"][inf["launch_plan"]],
+                  "candidate_ms": {"wide": inf["candidate_ms"][:4], "narrow": inf["candidate_ms"][4:]},
+                  "candidates": "per plan: one workgroup per slab; persistent 2, 4, 8 per CU",
+                  "bucket": f"d<={max(w.d for w in wls)}, m={w0.m}, s={w0.smax}, R={R}"},
         "roofline_eval": {"kernel": "k_eval (batched)", "bound": "mfma", "achieved": achieved,
                           "peak": PEAK["fp32"], "unit": "TFLOP/s", "frac": achieved / PEAK["fp32"],
                           "avg_launch_ms": ev_kernel_ms},

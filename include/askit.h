@@ -414,7 +414,11 @@ typedef struct {
     double t_setup_ms;
     int32_t tuned;              /* 1 once a launch shape is chosen for nrhs */
     int32_t launch_blocks;      /* chosen shape: 0 = one workgroup per slab, else persistent grid size */
-    double candidate_ms[4];     /* evaluation time of: one workgroup per slab; persistent 2, 4, 8 per CU */
+    int32_t launch_plan;        /* chosen column tiles: 0 wide (64 or 32 columns per MFMA pass, 4 or 1
+                                   per vector pass), 1 narrow (32 per MFMA pass, 1 per vector pass) */
+    int32_t reserved;
+    double candidate_ms[8];     /* evaluation time of plan 0, then plan 1, each with: one workgroup
+                                   per slab; persistent 2, 4, 8 per CU */
     int32_t graphs;             /* cached graphs of askit_batch_run */
 } askit_batch_info;
 
@@ -430,12 +434,15 @@ askit_status askit_batch_update_weights(askit_batch *b, const float *W, int64_t 
                                         void *stream);
 
 /* u of every instance into U (device, rows as above).  Uses the launch shape
- * the tuner chose for nrhs, else one workgroup per slab. */
+ * the tuner chose for nrhs, else one workgroup per slab with wide tiles. */
 askit_status askit_batch_evaluate(askit_batch *b, float *U, int64_t ldu, void *stream);
 
 /* update_weights + evaluate as one HIP graph, replayed on `stream`.  The first
- * call for an nrhs times the evaluation's launch shapes (eagerly, on
- * `stream`) and keeps the fastest; the graph is captured once per (W, ldw,
+ * call for an nrhs in a problem class -- the bucket (largest padded d, leaf
+ * size m, s_max, nrhs, precision) -- times the evaluation's 8 launch shapes
+ * (2 column-tile plans x 4 grid forms, eagerly, on `stream`) and keeps the
+ * fastest for every later batch of that bucket in the process; every shape
+ * gives bit-identical results.  The graph is captured once per (W, ldw,
  * nrhs, U, ldu) and replayed afterwards, so later calls must pass buffers
  * that are still allocated (new values in the same buffers are fine). */
 askit_status askit_batch_run(askit_batch *b, const float *W, int64_t ldw, int32_t nrhs, float *U, int64_t ldu,
@@ -443,8 +450,9 @@ askit_status askit_batch_run(askit_batch *b, const float *W, int64_t ldw, int32_
 
 /* Fixes the evaluation's launch shape for nrhs instead of timing them:
  * blocks = 0 for one workgroup per slab, else the persistent grid size
- * (1 .. 64 x compute units).  Graphs captured before keep their shape. */
-askit_status askit_batch_set_launch(askit_batch *b, int32_t nrhs, int32_t blocks);
+ * (1 .. 64 x compute units); plan 0 (wide) or 1 (narrow) column tiles.
+ * Graphs captured before keep their shape. */
+askit_status askit_batch_set_launch(askit_batch *b, int32_t nrhs, int32_t blocks, int32_t plan);
 
 askit_status askit_batch_get_info(const askit_batch *b, askit_batch_info *out);
 

@@ -447,8 +447,8 @@ class BatchInfo(C.Structure):
     _fields_ = [("count", C.c_int32), ("nrhs", C.c_int32), ("total_points", C.c_int64),
                 ("total_chunks", C.c_int64), ("near_entries", C.c_int64), ("far_entries", C.c_int64),
                 ("near_pairs", C.c_int64), ("far_pairs", C.c_int64), ("t_setup_ms", C.c_double),
-                ("tuned", C.c_int32), ("launch_blocks", C.c_int32), ("candidate_ms", C.c_double * 4),
-                ("graphs", C.c_int32)]
+                ("tuned", C.c_int32), ("launch_blocks", C.c_int32), ("launch_plan", C.c_int32),
+                ("reserved", C.c_int32), ("candidate_ms", C.c_double * 8), ("graphs", C.c_int32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -471,7 +471,7 @@ def _batch_lib():
         L.askit_batch_evaluate.argtypes = [P, P, i64, P]
         L.askit_batch_run.argtypes = [P, P, i64, i32, P, i64, P]
         L.askit_batch_get_info.argtypes = [P, C.POINTER(BatchInfo)]
-        L.askit_batch_set_launch.argtypes = [P, i32, i32]
+        L.askit_batch_set_launch.argtypes = [P, i32, i32, i32]
         L.askit_batch_instance.argtypes = [P, i32]
         L.askit_batch_instance.restype = P
         L.askit_batch_destroy.argtypes = [P]
@@ -530,8 +530,8 @@ class Batch:
         self.nrhs = W.shape[1]
         return out
 
-    def set_launch(self, nrhs, blocks):
-        _check(_batch_lib().askit_batch_set_launch(self.ptr, nrhs, blocks))
+    def set_launch(self, nrhs, blocks, plan=0):
+        _check(_batch_lib().askit_batch_set_launch(self.ptr, nrhs, blocks, plan))
 
     def info(self) -> dict:
         i = BatchInfo()

@@ -366,6 +366,7 @@ struct BatchEvalArgs {
     bool bf;
     int persistent;            // 0: one workgroup per chunk; else the persistent grid size
     int32_t *queue;            // persistent: work counter (cleared by a kernel before the launch)
+    int plan;                  // column passes: 0 wide (64/32 MFMA, 4/1 vector), 1 narrow (32 MFMA, 1 vector)
 };
 void evaluate_batch(const BatchEvalArgs &b, hipStream_t s);
 // One launch per level (deepest first): items are (instance, node) pairs.

@@ -9,8 +9,10 @@
 // evaluation launch over the slabs of every instance, reading each slab's
 // instance tables from a device array.  The evaluation runs either as one
 // workgroup per slab or as a persistent grid that takes
-// slabs from a work queue in decreasing cost order; a small autotuner times
-// these launch shapes once per right-hand-side count and keeps the fastest.
+// slabs from a work queue in decreasing cost order, with wide or narrow
+// column tiles (the weight columns a pass contracts); an autotuner times the
+// launch shapes once per problem class -- the bucket (d, m, s, R) -- and keeps
+// the fastest.
 // askit_batch_run captures the whole weights -> u sequence in a HIP graph
 // (kernels only: the queue counters are cleared by a kernel) and replays it.
 #include "askit_impl.h"
@@ -33,8 +35,10 @@ extern thread_local std::string g_err;
 namespace {
 
 constexpr int MAX_PASSES = (MAX_RHS + 7) / 8;     // RHS passes of the evaluation (8 columns each)
-constexpr int NUM_CAND = 4;                       // launch shapes tried by the tuner
-constexpr int CAND_BLOCKS_PER_CU[NUM_CAND] = {0, 2, 4, 8};   // 0: one workgroup per slab
+constexpr int NUM_GRID = 4;                       // grid forms tried by the tuner
+constexpr int CAND_BLOCKS_PER_CU[NUM_GRID] = {0, 2, 4, 8};   // 0: one workgroup per slab
+constexpr int NUM_PLAN = 2;                       // column-tile plans (wide, narrow)
+constexpr int NUM_CAND = NUM_GRID * NUM_PLAN;     // launch shapes, plan-major
 
 struct GraphEntry {
     const float *W;
@@ -42,14 +46,19 @@ struct GraphEntry {
     int R;
     float *U;
     int64_t ldu;
-    int blocks;
+    int blocks, plan;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
 
+struct Launch {
+    int blocks = -1;     // -1: not tuned; 0: one workgroup per slab; else the persistent grid
+    int plan = 0;
+};
+
 // Launch shapes already chosen in this process, by problem class.
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, std::vector<double>>> g_tune_cache;
+std::map<std::string, std::pair<Launch, std::vector<double>>> g_tune_cache;
 
 }  // namespace
 
@@ -74,7 +83,7 @@ struct askit_batch {
     float *Wt = nullptr, *Wsk = nullptr, *part = nullptr;
     int wcap = 0, R = 0;
 
-    int blocks_for_R[MAX_RHS + 1] = {};      // -1: not tuned
+    Launch launch_for_R[MAX_RHS + 1];
     std::vector<double> cand_ms[MAX_RHS + 1];
     std::string tune_key_base;
 
@@ -107,7 +116,7 @@ struct askit_batch {
         if (part) (void)hipFree(part);
         for (auto *h : inst) askit_destroy(h);
     }
-    BatchEvalArgs eval_args(float *U, int64_t ldu, int blocks) const
+    BatchEvalArgs eval_args(float *U, int64_t ldu, Launch l) const
     {
         BatchEvalArgs a{};
         a.inst = d_einst;
@@ -125,7 +134,8 @@ struct askit_batch {
         a.ldu = ldu;
         a.R = R;
         a.bf = prm.precision == ASKIT_PREC_BF16X3;
-        a.persistent = blocks;
+        a.persistent = l.blocks > 0 ? l.blocks : 0;
+        a.plan = l.plan;
         a.queue = d_queue;
         return a;
     }
@@ -185,6 +195,8 @@ static void ensure_weights(askit_batch *b, int R, hipStream_t s)
 
 // Times every launch shape of the evaluation for the current R (the weights
 // must be in place) and keeps the fastest; all shapes give identical results.
+// The choice is kept for the problem class (bucket) and reused by later
+// batches of the same class.
 static void autotune(askit_batch *b, float *U, int64_t ldu, hipStream_t s)
 {
     const int R = b->R;
@@ -193,7 +205,7 @@ static void autotune(askit_batch *b, float *U, int64_t ldu, hipStream_t s)
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            b->blocks_for_R[R] = it->second.first;
+            b->launch_for_R[R] = it->second.first;
             b->cand_ms[R] = it->second.second;
             return;
         }
@@ -203,9 +215,14 @@ static void autotune(askit_batch *b, float *U, int64_t ldu, hipStream_t s)
     HIPC(hipEventCreate(&e1));
     std::vector<double> ms(NUM_CAND, 0.0);
     int best = 0;
+    auto cand = [&](int c) {
+        Launch l;
+        l.plan = c / NUM_GRID;
+        l.blocks = CAND_BLOCKS_PER_CU[c % NUM_GRID] * b->num_cu;
+        return l;
+    };
     for (int c = 0; c < NUM_CAND; ++c) {
-        const int blocks = CAND_BLOCKS_PER_CU[c] * b->num_cu;
-        const BatchEvalArgs a = b->eval_args(U, ldu, blocks);
+        const BatchEvalArgs a = b->eval_args(U, ldu, cand(c));
         evaluate_batch(a, s);                        // warm-up
         std::vector<float> t;
         for (int rep = 0; rep < 3; ++rep) {
@@ -223,10 +240,10 @@ static void autotune(askit_batch *b, float *U, int64_t ldu, hipStream_t s)
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    b->blocks_for_R[R] = CAND_BLOCKS_PER_CU[best] * b->num_cu;
+    b->launch_for_R[R] = cand(best);
     b->cand_ms[R] = ms;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {b->blocks_for_R[R], ms};
+    g_tune_cache[key] = {b->launch_for_R[R], ms};
 }
 
 extern "C" {
@@ -373,14 +390,12 @@ askit_status askit_batch_setup(int32_t count, const float *const *X, const int64
         HIPC(hipMemcpy(b->d_chunks, chunks.data(), sizeof(Chunk) * b->nchunk, hipMemcpyHostToDevice));
     HIPC(hipMemcpy(b->d_outrow, outrow.data(), sizeof(int32_t) * b->rows, hipMemcpyHostToDevice));
     HIPC(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
-    for (int r = 0; r <= MAX_RHS; ++r) b->blocks_for_R[r] = -1;
-    // problem class of the tuner: points, slabs, list entries (rounded to powers of two), d, s, precision
-    auto lg = [](int64_t v) { int k = 0; while ((int64_t)1 << k < v) ++k; return k; };
+    // problem class of the tuner: the bucket (largest padded dimension, leaf
+    // size, skeleton bound; R is appended per tuning) and the precision form
     int maxdp = 0;
     for (auto *h : b->inst) maxdp = std::max(maxdp, h->dp);
-    b->tune_key_base = "n" + std::to_string(lg(b->rows)) + "s" + std::to_string(lg(b->nchunk)) + "e" +
-                       std::to_string(lg(b->ne + b->fe)) + "d" + std::to_string(maxdp) + "k" + std::to_string(smax) +
-                       "p" + std::to_string((int)p->precision) + "c" + std::to_string(count);
+    b->tune_key_base = "d" + std::to_string(maxdp) + "m" + std::to_string(p->leaf_size) + "s" +
+                       std::to_string(smax) + "p" + std::to_string((int)p->precision);
     HIPC(hipDeviceSynchronize());
     b->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = b.release();
@@ -405,8 +420,7 @@ askit_status askit_batch_evaluate(askit_batch *b, float *U, int64_t ldu, void *s
     if (!b || !U) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
     if (b->R < 1) fail(ASKIT_ERR_NOT_READY, "askit_batch_update_weights has not been called");
     if (ldu < b->R) fail(ASKIT_ERR_INVALID_ARG, "need ldu >= nrhs");
-    const int blocks = b->blocks_for_R[b->R];
-    evaluate_batch(b->eval_args(U, ldu, blocks > 0 ? blocks : 0), (hipStream_t)stream);
+    evaluate_batch(b->eval_args(U, ldu, b->launch_for_R[b->R]), (hipStream_t)stream);
     API_END
 }
 
@@ -419,14 +433,16 @@ askit_status askit_batch_run(askit_batch *b, const float *W, int64_t ldw, int32_
     if (ldw < nrhs || ldu < nrhs) fail(ASKIT_ERR_INVALID_ARG, "need ldw, ldu >= nrhs");
     hipStream_t s = (hipStream_t)stream;
     ensure_weights(b, nrhs, s);
-    if (b->blocks_for_R[nrhs] < 0) {
+    if (b->launch_for_R[nrhs].blocks < 0) {
         b->update(W, ldw, s);
         autotune(b, U, ldu, s);
     }
-    const int blocks = b->blocks_for_R[nrhs];
+    const Launch ln = b->launch_for_R[nrhs];
     GraphEntry *ge = nullptr;
     for (auto &g : b->graphs)
-        if (g.W == W && g.ldw == ldw && g.R == nrhs && g.U == U && g.ldu == ldu && g.blocks == blocks) ge = &g;
+        if (g.W == W && g.ldw == ldw && g.R == nrhs && g.U == U && g.ldu == ldu && g.blocks == ln.blocks &&
+            g.plan == ln.plan)
+            ge = &g;
     if (!ge) {
         if (b->graphs.size() >= 8) {
             HIPC(hipStreamSynchronize(s));
@@ -434,11 +450,11 @@ askit_status askit_batch_run(askit_batch *b, const float *W, int64_t ldw, int32_
             (void)hipGraphDestroy(b->graphs.front().graph);
             b->graphs.erase(b->graphs.begin());
         }
-        GraphEntry g{W, ldw, nrhs, U, ldu, blocks, nullptr, nullptr};
+        GraphEntry g{W, ldw, nrhs, U, ldu, ln.blocks, ln.plan, nullptr, nullptr};
         HIPC(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
         try {
             b->update(W, ldw, b->cap);
-            evaluate_batch(b->eval_args(U, ldu, blocks), b->cap);
+            evaluate_batch(b->eval_args(U, ldu, ln), b->cap);
         } catch (...) {
             hipGraph_t junk = nullptr;
             (void)hipStreamEndCapture(b->cap, &junk);
@@ -454,13 +470,15 @@ askit_status askit_batch_run(askit_batch *b, const float *W, int64_t ldw, int32_
     API_END
 }
 
-askit_status askit_batch_set_launch(askit_batch *b, int32_t nrhs, int32_t blocks)
+askit_status askit_batch_set_launch(askit_batch *b, int32_t nrhs, int32_t blocks, int32_t plan)
 {
     API_BEGIN
     if (!b) fail(ASKIT_ERR_INVALID_ARG, "NULL argument");
     if (nrhs < 1 || nrhs > MAX_RHS) fail(ASKIT_ERR_INVALID_ARG, "need 1 <= nrhs <= 64");
     if (blocks < 0 || blocks > 64 * b->num_cu) fail(ASKIT_ERR_INVALID_ARG, "need 0 <= blocks <= 64 x CUs");
-    b->blocks_for_R[nrhs] = blocks;
+    if (plan < 0 || plan >= NUM_PLAN) fail(ASKIT_ERR_INVALID_ARG, "need plan 0 (wide) or 1 (narrow)");
+    b->launch_for_R[nrhs].blocks = blocks;
+    b->launch_for_R[nrhs].plan = plan;
     b->cand_ms[nrhs].clear();
     API_END
 }
@@ -480,8 +498,9 @@ askit_status askit_batch_get_info(const askit_batch *b, askit_batch_info *o)
     o->far_pairs = b->far_pairs;
     o->t_setup_ms = b->t_setup_ms;
     const int R = b->R;
-    o->tuned = R > 0 && b->blocks_for_R[R] >= 0;
-    o->launch_blocks = o->tuned ? b->blocks_for_R[R] : 0;
+    o->tuned = R > 0 && b->launch_for_R[R].blocks >= 0;
+    o->launch_blocks = o->tuned ? b->launch_for_R[R].blocks : 0;
+    o->launch_plan = o->tuned ? b->launch_for_R[R].plan : 0;
     for (int c = 0; c < NUM_CAND && o->tuned && c < (int)b->cand_ms[R].size(); ++c) o->candidate_ms[c] = b->cand_ms[R][c];
     o->graphs = (int32_t)b->graphs.size();
     API_END

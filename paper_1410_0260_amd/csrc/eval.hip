@@ -345,12 +345,16 @@ __global__ void k_zero_i32(int32_t *__restrict__ p, int n)
 }
 
 template <bool MULTI>
-static void launch_passes(ChunkParams p, bool bf, int R, int64_t grid, int32_t *queue, hipStream_t s, int c0 = 0)
+static void launch_passes(ChunkParams p, bool bf, int R, int64_t grid, int32_t *queue, hipStream_t s, int c0 = 0,
+                          int plan = 0)
 {
-    // passes of 64, 32, 4 or 1 columns over columns [c0, R)
+    // passes over columns [c0, R): plan 0 (wide) of 64, 32, 4 or 1 columns,
+    // plan 1 (narrow) of 32 or 1.  A column sees the same arithmetic in
+    // either (MFMA for a remainder above 4 columns, the vector units below;
+    // the 32 and 64 forms, and the 1 and 4 forms, treat each column alike)
     for (int r0 = c0; r0 < R;) {
         const int left = R - r0;
-        const int cm = left > 32 ? 64 : left > 4 ? 32 : left > 1 ? 4 : 1;
+        const int cm = plan == 1 ? (left > 4 ? 32 : 1) : (left > 32 ? 64 : left > 4 ? 32 : left > 1 ? 4 : 1);
         p.r0 = r0;
         p.rb = std::min(cm, left);
         p.queue = queue;
@@ -457,7 +461,7 @@ void evaluate_batch(const BatchEvalArgs &b, hipStream_t s)
         p.part = b.part;
         p.R = b.R;
         const int64_t grid = p.persistent ? std::min<int64_t>(b.persistent, b.nchunk) : b.nchunk;
-        launch_passes<true>(p, b.bf, b.R, grid, b.queue, s);
+        launch_passes<true>(p, b.bf, b.R, grid, b.queue, s, 0, b.plan);
     }
     const int64_t tot = b.rows * b.R;
     hipLaunchKernelGGL(k_sum_slots, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, b.sbase, b.rows, b.part,

@@ -114,4 +114,6 @@ def test_batch_argument_checks():
     assert L.askit_batch_update_weights(None, None, 1, 1, None) == A.ERR_INVALID_ARG
     assert L.askit_batch_run(None, None, 1, 1, None, 1, None) == A.ERR_INVALID_ARG
     assert L.askit_batch_instance(None, 0) is None
+    assert L.askit_batch_set_launch(None, 1, 0, 0) == A.ERR_INVALID_ARG
+    assert C.sizeof(A.BatchInfo) == 152
     L.askit_batch_destroy(None)

@@ -45,18 +45,23 @@ def _alone(A, Xs, W, offsets):
     return out
 
 
-@pytest.mark.parametrize("R", [1, 3, 9])
+@pytest.mark.parametrize("R", [1, 3, 9, 40])
 def test_every_launch_shape_equals_alone(batch, R):
+    """Every grid form and column-tile plan (wide: 64/32-column MFMA passes
+    and 4/1-column vector passes; narrow: 32 and 1) gives each instance's
+    u bit for bit as set up and evaluated alone."""
     import torch
     A, b, Xs = batch
     W = synth.weights(b.rows, R, 77 + R)
     alone = _alone(A, Xs, W, b.offsets)
     b.update_weights(torch.from_numpy(W).cuda())
-    for blocks in (0, 256, 1024, 3):
-        b.set_launch(R, blocks)
-        U = b.evaluate().cpu().numpy()
-        for i in range(len(Xs)):
-            assert np.array_equal(U[b.offsets[i]:b.offsets[i + 1]], alone[i]), f"blocks {blocks} instance {i}"
+    for plan in (0, 1):
+        for blocks in (0, 256, 1024, 3):
+            b.set_launch(R, blocks, plan)
+            U = b.evaluate().cpu().numpy()
+            for i in range(len(Xs)):
+                assert np.array_equal(U[b.offsets[i]:b.offsets[i + 1]], alone[i]), \
+                    f"plan {plan} blocks {blocks} instance {i}"
 
 
 def test_matches_oracle(batch):
@@ -100,4 +105,5 @@ def test_graph_replays_equal_eager(batch):
     inf = b.info()
     assert inf["tuned"] == 1 and inf["graphs"] == 1
     assert inf["launch_blocks"] in (0, 2 * 256, 4 * 256, 8 * 256) or inf["launch_blocks"] % 256 == 0
+    assert inf["launch_plan"] in (0, 1)
     assert all(t > 0 for t in inf["candidate_ms"])
