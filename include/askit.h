@@ -412,6 +412,8 @@ typedef struct {
     int64_t total_points, total_chunks;   /* chunks: evaluation work items of up to 64 targets */
     int64_t near_entries, far_entries, near_pairs, far_pairs;
     double t_setup_ms;
+    double t_skel_ms;           /* of which the fused skeletonization of all instances (the
+                                   instances' own t_skel_ms read 0) */
     int32_t tuned;              /* 1 once a launch shape is chosen for nrhs */
     int32_t launch_blocks;      /* chosen shape: 0 = one workgroup per slab, else persistent grid size */
     int32_t launch_plan;        /* chosen column tiles: 0 wide (64 or 32 columns per MFMA pass, 4 or 1
@@ -424,8 +426,11 @@ typedef struct {
 
 /* Sets up `count` instances: X[i] (device, N[i] x d[i], row stride ldx[i])
  * with the parameters *p.  Synchronises `stream` (the point sets must be
- * written), then builds the instances several at a time on worker streams;
- * the point sets are copied.  Errors name the failing instance. */
+ * written), then builds the instances up to their skeletons several at a
+ * time on worker streams, and the skeletons of all instances in one fused
+ * pass over the tree levels on `stream` (every kernel of Alg. 3 launched once
+ * per level for the nodes of every instance); the point sets are copied.
+ * Errors name the failing instance. */
 askit_status askit_batch_setup(int32_t count, const float *const *X, const int64_t *N, const int32_t *d,
                                const int64_t *ldx, const askit_params *p, void *stream, askit_batch **out);
 

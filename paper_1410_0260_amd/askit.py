@@ -447,7 +447,7 @@ class BatchInfo(C.Structure):
     _fields_ = [("count", C.c_int32), ("nrhs", C.c_int32), ("total_points", C.c_int64),
                 ("total_chunks", C.c_int64), ("near_entries", C.c_int64), ("far_entries", C.c_int64),
                 ("near_pairs", C.c_int64), ("far_pairs", C.c_int64), ("t_setup_ms", C.c_double),
-                ("tuned", C.c_int32), ("launch_blocks", C.c_int32), ("launch_plan", C.c_int32),
+                ("t_skel_ms", C.c_double), ("tuned", C.c_int32), ("launch_blocks", C.c_int32), ("launch_plan", C.c_int32),
                 ("reserved", C.c_int32), ("candidate_ms", C.c_double * 8), ("graphs", C.c_int32)]
 
     def as_dict(self):

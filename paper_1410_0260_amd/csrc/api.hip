@@ -384,8 +384,10 @@ const char *askit_last_error(void) { return g_err.c_str(); }
 
 // Alg. 5 setup steps; knn_in (device, N x kappa original ids, row stride ldk)
 // replaces the exact neighbour search when given.
+// defer_skel: stop before the skeletons (the fused skeletonization of a batch
+// runs them for many handles at once; finish_deferred completes the setup).
 static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const int32_t *knn_in, int64_t ldk,
-                       const askit_params *p, void *stream, askit_handle **out)
+                       const askit_params *p, void *stream, askit_handle **out, bool defer_skel = false)
 {
     if (!out) fail(ASKIT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -633,13 +635,13 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
         sample_rows(h.get(), s);
         HIPC(hipEventRecord(ev[3], s));
         // ---- skeletons
-        skeletonize(h.get(), s);
+        if (!defer_skel) skeletonize(h.get(), s);
         HIPC(hipEventRecord(ev[4], s));
         ith.join();
         if (ierr) std::rethrow_exception(ierr);
         HIPC(hipEventElapsedTime(&ms_inter, ei[0], ei[1]));
     }
-    count_pairs(h.get(), s);
+    if (!defer_skel) count_pairs(h.get(), s);
     HIPC(hipEventRecord(ev[5], s));
     HIPC(hipStreamSynchronize(s));
     prepare_upward(h.get());
@@ -651,8 +653,27 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
     HIPC(hipEventElapsedTime(&ms, ev[2], ev[3])); h->t_lists = ms;
     HIPC(hipEventElapsedTime(&ms, ev[3], ev[4])); h->t_skel = ms;
     h->t_inter = ms_inter;                 // on the second stream, overlapped with the above
+    h->skel_pending = defer_skel;
     *out = h.release();
 }
+
+namespace askit {
+
+askit_handle *setup_deferred(const float *X, int64_t N, int32_t d, int64_t ldx, const askit_params *p,
+                             hipStream_t s)
+{
+    askit_handle *h = nullptr;
+    setup_impl(X, N, d, ldx, nullptr, 0, p, s, &h, true);
+    return h;
+}
+
+void finish_deferred(askit_handle *h, hipStream_t s)
+{
+    count_pairs(h, s);
+    h->skel_pending = false;
+}
+
+}  // namespace askit
 
 extern "C" {
 

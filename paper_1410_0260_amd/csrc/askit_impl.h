@@ -218,6 +218,7 @@ struct askit_handle {
     void *alloc(size_t bytes, bool zero = true);
     std::mutex alloc_mu;               // alloc may be called from two host threads during setup
     hipStream_t astream = nullptr;     // stream that orders alloc's zero fill (the calling API's)
+    bool skel_pending = false;         // set up without skeletons (a batch's fused pass completes it)
 };
 
 namespace askit {
@@ -297,6 +298,29 @@ void sort_queries(askit_handle *h, const int32_t *nb, int64_t M, int32_t *order,
 
 // skel.hip
 void skeletonize(askit_handle *h, hipStream_t s);
+// The skeletons of several handles (same ell, s_max and tolerance) in one
+// pass over the tree levels: each kernel launched once per level for the
+// nodes of every handle.
+void skeletonize_multi(const std::vector<askit_handle *> &hs, hipStream_t s);
+// askit_setup up to (not including) the skeletons; finish_deferred completes
+// a handle after its skeletons are built.  Throws Error.
+askit_handle *setup_deferred(const float *X, int64_t N, int32_t d, int64_t ldx, const askit_params *p,
+                             hipStream_t s);
+void finish_deferred(askit_handle *h, hipStream_t s);
+
+// A handle's arrays as the skeletonization kernels read them (one entry per
+// handle; work items are (entry, node) pairs).
+struct SkelInst {
+    const Node *nodes;
+    const float *Xt, *gt;
+    const int32_t *T, *T_cnt;
+    int32_t *S, *skk, *ncols, *colperm;
+    const int64_t *pslot;
+    float *P, *Xs, *gs;
+    const double *hpos;        // per tree position bandwidth (variable h), else NULL
+    double h;                  // the fixed bandwidth
+    int dp, d, ncol_max;       // ncol_max: the handle's column bound (row stride of colperm)
+};
 // columns [r0, r1) of ws (r1 < 0: all); no host sync
 void upward(askit_handle *h, const WeightSet &ws, hipStream_t s, int r0 = 0, int r1 = -1);
 void prepare_upward(askit_handle *h);                                  // once, after setup

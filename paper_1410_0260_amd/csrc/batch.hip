@@ -1,8 +1,12 @@
 // Batched form: many independent problems (uneven sizes and dimensions)
 // behind one handle.
 //
-// Setup runs the single-problem setup of every instance, several at a time
-// on worker threads with their own streams.  The per-weight-vector work of
+// Setup runs the single-problem setup of every instance up to the skeletons,
+// several at a time on worker threads with their own streams; then one fused
+// skeletonization builds the IDs of every instance, level by level, each
+// kernel launched once per level over the nodes of all instances (the small
+// instances' per-node factorizations fill the device together instead of a
+// few at a time).  The per-weight-vector work of
 // all instances is then fused: one permutation launch over all rows, one
 // upward launch per tree level across every instance (deepest level first,
 // so each instance still sees its children before its parents), and one
@@ -19,6 +23,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -70,7 +75,7 @@ struct askit_batch {
     int smax = 0;
     int64_t rows = 0, wsk_slots = 0, npairs = 0, nchunk = 0, ne = 0, fe = 0;
     int64_t near_pairs = 0, far_pairs = 0;
-    double t_setup_ms = 0.0;
+    double t_setup_ms = 0.0, t_skel_ms = 0.0;
     std::vector<void *> own;
 
     EvalInst *d_einst = nullptr;
@@ -290,24 +295,44 @@ askit_status askit_batch_setup(int32_t count, const float *const *X, const int64
             for (;;) {
                 const int32_t i = next++;
                 if (i >= count) break;
-                askit_handle *h = nullptr;
-                askit_status rc = askit_setup(X[i], N[i], d[i], ldx[i], p, ws, &h);
+                askit_status rc = ASKIT_OK;
+                std::string msg;
+                try {
+                    if (!X[i]) fail(ASKIT_ERR_INVALID_ARG, "NULL point set");
+                    b->inst[i] = setup_deferred(X[i], N[i], d[i], ldx[i], p, ws);
+                } catch (const Error &e) {
+                    rc = e.code;
+                    msg = e.msg;
+                } catch (const std::bad_alloc &) {
+                    rc = ASKIT_ERR_OUT_OF_MEMORY;
+                    msg = "host allocation failed";
+                } catch (...) {
+                    rc = ASKIT_ERR_DEVICE;
+                    msg = "internal error";
+                }
                 if (rc != ASKIT_OK) {
                     std::lock_guard<std::mutex> lk(emu);
                     if (first_code == ASKIT_OK) {
                         first_code = rc;
-                        first_msg = "instance " + std::to_string(i) + ": " + askit_last_error();
+                        first_msg = "instance " + std::to_string(i) + ": " + msg;
                     }
                     next = count;
                     break;
                 }
-                b->inst[i] = h;
             }
             (void)hipStreamSynchronize(ws);
             (void)hipStreamDestroy(ws);
         });
     for (auto &t : th) t.join();
     if (first_code != ASKIT_OK) fail(first_code, first_msg);
+    // the fused skeletonization of all instances, then each setup's last step
+    {
+        const auto ts = std::chrono::steady_clock::now();
+        skeletonize_multi(b->inst, s);
+        for (auto *h : b->inst) finish_deferred(h, s);
+        HIPC(hipStreamSynchronize(s));
+        b->t_skel_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ts).count();
+    }
 
     // host tables: instance offsets of rows, skeleton-weight slots and pairs
     const int smax = b->inst[0]->smax;
@@ -497,6 +522,7 @@ askit_status askit_batch_get_info(const askit_batch *b, askit_batch_info *o)
     o->near_pairs = b->near_pairs;
     o->far_pairs = b->far_pairs;
     o->t_setup_ms = b->t_setup_ms;
+    o->t_skel_ms = b->t_skel_ms;
     const int R = b->R;
     o->tuned = R > 0 && b->launch_for_R[R].blocks >= 0;
     o->launch_blocks = o->tuned ? b->launch_for_R[R].blocks : 0;

@@ -22,12 +22,16 @@ namespace askit {
 
 constexpr double TAU_FLOOR = 64.0 * 2.220446049250313e-16;
 
-__global__ void k_cols(const Node *__restrict__ nodes, const int32_t *__restrict__ ids, int smax,
-                       int ncol_max, const int32_t *__restrict__ S, const int32_t *__restrict__ skk,
-                       int32_t *__restrict__ colpos, int32_t *__restrict__ ncols)
+__global__ void k_cols(const SkelInst *__restrict__ inst, const int2 *__restrict__ items, int smax, int ncol_max,
+                       int32_t *__restrict__ colpos)
 {
-    int q = blockIdx.x, a = ids[q];
-    Node nd = nodes[a];
+    const int q = blockIdx.x;
+    const int2 it = items[q];
+    const SkelInst &I = inst[it.x];
+    const int a = it.y;
+    const int32_t *S = I.S, *skk = I.skk;
+    int32_t *ncols = I.ncols;
+    Node nd = I.nodes[a];
     int32_t *cp = colpos + (int64_t)q * ncol_max;
     int n;
     if (nd.left < 0) {
@@ -56,18 +60,22 @@ constexpr int FG_MAXROW = 1024;
 
 // PP: (row, column) pairs per thread, >= rows * FG_C / FG_T
 template <int PP>
-__global__ __launch_bounds__(FG_T) void k_form_G(const float *__restrict__ Xt, int dp, int d,
-                                                 const int32_t *__restrict__ ids,
-                                                 const int32_t *__restrict__ T,
-                                                 const int32_t *__restrict__ T_cnt, int ell,
-                                                 const int32_t *__restrict__ colpos,
-                                                 const int32_t *__restrict__ ncols, int ncol_max,
-                                                 const double *__restrict__ hpos, double h,
+__global__ __launch_bounds__(FG_T) void k_form_G(const SkelInst *__restrict__ inst,
+                                                 const int2 *__restrict__ items, int ell,
+                                                 const int32_t *__restrict__ colpos, int ncol_max,
                                                  double *__restrict__ G)
 {
 #pragma clang fp contract(off)
     extern __shared__ float fsm[];
-    const int q = blockIdx.y, a = ids[q];
+    const int q = blockIdx.y;
+    const int2 it = items[q];
+    const SkelInst &I = inst[it.x];
+    const int a = it.y;
+    const float *Xt = I.Xt;
+    const int dp = I.dp, d = I.d;
+    const int32_t *T = I.T, *T_cnt = I.T_cnt, *ncols = I.ncols;
+    const double *hpos = I.hpos;
+    const double h = I.h;
     const int c0 = blockIdx.x * FG_C;
     const int nc = min(FG_C, ncols[a] - c0);
     if (nc <= 0) return;
@@ -166,11 +174,8 @@ __device__ __forceinline__ double group16_sum(double v)
 // their order are those of RM = 0 (slices re-read from memory).
 template <int QT, int RM>
 __global__ __launch_bounds__(QT) void k_qrcp(double *__restrict__ Gall, int ell, int ncol_max,
-                                               const int32_t *__restrict__ ids,
-                                               const int32_t *__restrict__ T_cnt,
-                                               const int32_t *__restrict__ ncols, int smax,
-                                               double tau, int32_t *__restrict__ colperm,
-                                               int32_t *__restrict__ kout, int nb)
+                                               const SkelInst *__restrict__ inst,
+                                               const int2 *__restrict__ items, int smax, double tau, int nb)
 {
     __shared__ double nrm2[QR_MAXCOL];
     __shared__ int piv[QR_MAXCOL];
@@ -185,8 +190,10 @@ __global__ __launch_bounds__(QT) void k_qrcp(double *__restrict__ Gall, int ell,
   // a smaller grid would bound the factorizations in flight)
   for (int q = blockIdx.x; q < nb; q += gridDim.x) {
     __syncthreads();                           // the previous node is done with the shared arrays
-    const int a = ids[q];
-    const int rows = T_cnt[a], cols = ncols[a];
+    const int2 it = items[q];
+    const SkelInst &I = inst[it.x];
+    const int a = it.y;
+    const int rows = I.T_cnt[a], cols = I.ncols[a];
     double *G = Gall + (int64_t)q * ncol_max * ell;
     for (int c = tid; c < cols; c += QT) piv[c] = c;
     for (int cb = 0; cb < cols; cb += CG) {
@@ -309,8 +316,8 @@ __global__ __launch_bounds__(QT) void k_qrcp(double *__restrict__ Gall, int ell,
         }
         __syncthreads();
     }
-    for (int c = tid; c < cols; c += QT) colperm[(int64_t)a * ncol_max + c] = piv[c];
-    if (tid == 0) kout[a] = k;
+    for (int c = tid; c < cols; c += QT) I.colperm[(int64_t)a * I.ncol_max + c] = piv[c];
+    if (tid == 0) I.skk[a] = k;
   }
 }
 
@@ -349,10 +356,8 @@ __device__ __forceinline__ bool qg_better(double v1, int p1, double v2, int p2)
 
 template <int W, int RM, int CPG>
 __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, int ell, int ncol_max,
-                                                     const int32_t *__restrict__ ids,
-                                                     const int32_t *__restrict__ T_cnt,
-                                                     const int32_t *__restrict__ ncols, int smax, double tau,
-                                                     int32_t *__restrict__ colperm, int32_t *__restrict__ kout,
+                                                     const SkelInst *__restrict__ inst,
+                                                     const int2 *__restrict__ items, int smax, double tau,
                                                      int nb, GangSlot *__restrict__ slots,
                                                      double *__restrict__ sdata, int32_t *__restrict__ err,
                                                      uint64_t timeout)
@@ -379,8 +384,10 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
     if (tid == 0) s_fail = 0;
     for (int q = gang; q < nb; q += ngang) {
         __syncthreads();
-        const int a = ids[q];
-        const int rows = T_cnt[a], cols = ncols[a];
+        const int2 it = items[q];
+        const SkelInst &I = inst[it.x];
+        const int a = it.y;
+        const int rows = I.T_cnt[a], cols = I.ncols[a];
         double *G = Gall + (int64_t)q * ncol_max * ell;
         for (int c = tid; c < cols; c += QG_T) {
             piv[c] = c;
@@ -613,8 +620,8 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
             }
         }
         if (w == 0) {
-            for (int c = tid; c < cols; c += QG_T) colperm[(int64_t)a * ncol_max + c] = piv[c];
-            if (tid == 0) kout[a] = k;
+            for (int c = tid; c < cols; c += QG_T) I.colperm[(int64_t)a * I.ncol_max + c] = piv[c];
+            if (tid == 0) I.skk[a] = k;
         }
     }
 }
@@ -626,13 +633,14 @@ constexpr int SV_T = 256;
 constexpr int SV_C = 16;
 
 __global__ __launch_bounds__(SV_T) void k_solve(double *__restrict__ Gall, int ell, int ncol_max,
-                                                const int32_t *__restrict__ ids,
-                                                const int32_t *__restrict__ ncols,
-                                                const int32_t *__restrict__ skk)
+                                                const SkelInst *__restrict__ inst,
+                                                const int2 *__restrict__ items)
 {
     extern __shared__ double sP[];             // k x SV_C
-    const int q = blockIdx.y, a = ids[q];
-    const int k = skk[a], n = ncols[a];
+    const int q = blockIdx.y;
+    const int2 it = items[q];
+    const int a = it.y;
+    const int k = inst[it.x].skk[a], n = inst[it.x].ncols[a];
     const int c0 = blockIdx.x * SV_C;
     const int cw = min(SV_C, n - k - c0);
     if (cw <= 0 || k == 0) return;
@@ -672,13 +680,14 @@ constexpr int SR_R = 32;      // rows per lane (k <= 256)
 constexpr int SR_C = 32;      // columns per block
 
 __global__ __launch_bounds__(256) void k_solve_reg(double *__restrict__ Gall, int ell, int ncol_max,
-                                                   const int32_t *__restrict__ ids,
-                                                   const int32_t *__restrict__ ncols,
-                                                   const int32_t *__restrict__ skk)
+                                                   const SkelInst *__restrict__ inst,
+                                                   const int2 *__restrict__ items)
 {
     __shared__ double sR[SR_L * SR_L * SR_R];       // 8 columns of R, rows 0 .. 255
-    const int q = blockIdx.y, a = ids[q];
-    const int k = skk[a], m = ncols[a] - k;
+    const int q = blockIdx.y;
+    const int2 it = items[q];
+    const int a = it.y;
+    const int k = inst[it.x].skk[a], m = inst[it.x].ncols[a] - k;
     const int c0 = blockIdx.x * SR_C;
     if (k == 0 || c0 >= m) return;
     const int tid = threadIdx.x, lane = tid % 64;
@@ -720,21 +729,21 @@ __global__ __launch_bounds__(256) void k_solve_reg(double *__restrict__ Gall, in
 }
 
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ Gall, int ell,
-                                                  int ncol_max, const int32_t *__restrict__ ids,
-                                                  const int32_t *__restrict__ colpos,
-                                                  const int32_t *__restrict__ ncols,
-                                                  const int32_t *__restrict__ skk,
-                                                  const int32_t *__restrict__ colperm, int smax,
-                                                  const int64_t *__restrict__ pslot,
-                                                  const float *__restrict__ Xt, int dp,
-                                                  const float *__restrict__ gt,
-                                                  int32_t *__restrict__ S, float *__restrict__ P,
-                                                  float *__restrict__ Xs, float *__restrict__ gs)
+                                                  int ncol_max, const SkelInst *__restrict__ inst,
+                                                  const int2 *__restrict__ items,
+                                                  const int32_t *__restrict__ colpos, int smax)
 {
-    const int q = blockIdx.x, a = ids[q];
-    const int k = skk[a], n = ncols[a], nr = n - k;
+    const int q = blockIdx.x;
+    const int2 it = items[q];
+    const SkelInst &I = inst[it.x];
+    const int a = it.y;
+    const int dp = I.dp;
+    const float *Xt = I.Xt, *gt = I.gt;
+    int32_t *S = I.S;
+    float *Xs = I.Xs, *gs = I.gs;
+    const int k = I.skk[a], n = I.ncols[a], nr = n - k;
     const double *G = Gall + (int64_t)q * ncol_max * ell;
-    const int32_t *pv = colperm + (int64_t)a * ncol_max;
+    const int32_t *pv = I.colperm + (int64_t)a * I.ncol_max;
     const int32_t *cp = colpos + (int64_t)q * ncol_max;
     for (int t = threadIdx.x; t < k; t += blockDim.x) {
         int32_t pos = cp[pv[t]];
@@ -745,7 +754,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ Gal
         int t = e / dp, j = e % dp;
         Xs[((int64_t)a * smax + t) * dp + j] = Xt[(int64_t)cp[pv[t]] * dp + j];
     }
-    float *Pa = P + pslot[a];
+    float *Pa = I.P + I.pslot[a];
     for (int e = threadIdx.x; e < k * nr; e += blockDim.x) {
         int t = e / nr, c = e % nr;
         Pa[e] = (float)G[(int64_t)(k + c) * ell + t];
@@ -777,9 +786,8 @@ __global__ void k_gang_reset(GangSlot *__restrict__ slots, int n, int32_t *__res
 static std::mutex g_gang_mu;
 
 template <int W, int RM, int CPG>
-static bool qr_gang_launch(double *G, int ell, int ncm, const int32_t *ids, const int32_t *T_cnt,
-                           const int32_t *ncols, int smax, double tau, int32_t *colperm, int32_t *kout, int nb,
-                           const GangScratch &gs, uint64_t timeout, hipStream_t s)
+static bool qr_gang_launch(double *G, int ell, int ncm, const SkelInst *inst, const int2 *items, int smax,
+                           double tau, int nb, const GangScratch &gs, uint64_t timeout, hipStream_t s)
 {
     int dev = 0, ncu = 0, per = 0;
     HIPC(hipGetDevice(&dev));
@@ -796,8 +804,7 @@ static bool qr_gang_launch(double *G, int ell, int ncm, const int32_t *ids, cons
     GangSlot *slots = gs.slots;
     double *sdata = gs.sdata;
     int32_t *err = gs.err;
-    void *args[] = {&G, &ell, &ncm, (void *)&ids, (void *)&T_cnt, (void *)&ncols, &smax, &tau, &colperm,
-                    &kout, &nb, &slots, &sdata, &err, &timeout};
+    void *args[] = {&G, &ell, &ncm, (void *)&inst, (void *)&items, &smax, &tau, &nb, &slots, &sdata, &err, &timeout};
     HIPC(hipLaunchCooperativeKernel((const void *)k_qrcp_gang<W, RM, CPG>, dim3((unsigned)(ngang * W)),
                                     dim3(QG_T), args, 0, s));
     return true;
@@ -805,32 +812,99 @@ static bool qr_gang_launch(double *G, int ell, int ncm, const int32_t *ids, cons
 
 void skeletonize(askit_handle *h, hipStream_t s)
 {
-    const int nn = (int)h->nodes.size();
-    const int ell = h->ell, ncm = h->ncol_max, smax = h->smax;
+    std::vector<askit_handle *> one{h};
+    skeletonize_multi(one, s);
+}
+
+// The ID of every node of every given handle (Alg. 3 with the sampled rows of
+// Eq. e:sk_targets), level by level from the deepest: one launch of each
+// kernel per level (in batches that bound the FP64 blocks) over the nodes of
+// that level in all handles, each node reading its handle's arrays from an
+// instance table.  The handles share ell, s_max and the ID tolerance.  Every
+// node sees the same operations as when its handle is skeletonized alone.
+void skeletonize_multi(const std::vector<askit_handle *> &hs, hipStream_t s)
+{
+    if (hs.empty()) return;
+    const askit_handle *h0 = hs[0];
+    const int ell = h0->ell, smax = h0->smax;
+    const double tau = h0->prm.id_tol;
+    int ncm = 0, maxdepth = 0;
+    for (auto *h : hs) {
+        if (h->ell != ell || h->smax != smax || h->prm.id_tol != tau)
+            fail(ASKIT_ERR_INVALID_ARG, "fused skeletonization needs one ell, s_max and tolerance");
+        ncm = std::max(ncm, h->ncol_max);
+        maxdepth = std::max(maxdepth, h->depth);
+    }
     if (ncm > QR_MAXCOL || ell > QR_MAXROW || ell > FG_MAXROW)
         fail(ASKIT_ERR_UNSUPPORTED, "ID block larger than 1024 rows x 2048 columns");
-    HIPC(hipMemsetAsync(h->skk, 0, sizeof(int32_t) * nn, s));
-    HIPC(hipMemsetAsync(h->ncols, 0, sizeof(int32_t) * nn, s));
-    if (h->depth == 0) return;
-    int maxlev = 0;
-    for (auto &lv : h->level_nodes) maxlev = std::max(maxlev, (int)lv.size());
+    for (auto *h : hs) {
+        HIPC(hipMemsetAsync(h->skk, 0, sizeof(int32_t) * h->nodes.size(), s));
+        HIPC(hipMemsetAsync(h->ncols, 0, sizeof(int32_t) * h->nodes.size(), s));
+        h->t_qr = 0;
+    }
+    if (maxdepth == 0) return;
+    std::vector<void *> tmp;
+    struct Free {
+        std::vector<void *> &t;
+        hipStream_t s;
+        ~Free()
+        {
+            (void)hipStreamSynchronize(s);
+            for (void *p : t) (void)hipFreeAsync(p, s);
+        }
+    } fr{tmp, s};
+    auto ta = [&](size_t b) {
+        void *p;
+        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        tmp.push_back(p);
+        return p;
+    };
+    // the instance table
+    std::vector<SkelInst> hin(hs.size());
+    for (size_t i = 0; i < hs.size(); ++i) {
+        askit_handle *h = hs[i];
+        SkelInst &I = hin[i];
+        I.nodes = h->d_nodes;
+        I.Xt = h->Xt;
+        I.gt = h->gt;
+        I.T = h->T;
+        I.T_cnt = h->T_cnt;
+        I.S = h->S;
+        I.skk = h->skk;
+        I.ncols = h->ncols;
+        I.colperm = h->colperm;
+        I.pslot = h->d_pslot;
+        I.P = h->P;
+        I.Xs = h->Xs;
+        I.gs = h->gs;
+        I.h = h->prm.bandwidth;
+        I.hpos = nullptr;
+        I.dp = h->dp;
+        I.d = h->d;
+        I.ncol_max = h->ncol_max;
+        if (h->varh) {
+            // per tree position bandwidth (FP64) from the per-id array
+            double *hp = (double *)ta(sizeof(double) * h->N);
+            gather_f64(h->hsrc, h->perm, h->N, hp, s);
+            I.hpos = hp;
+        }
+    }
+    SkelInst *d_inst = (SkelInst *)ta(sizeof(SkelInst) * hs.size());
+    HIPC(hipMemcpyAsync(d_inst, hin.data(), sizeof(SkelInst) * hs.size(), hipMemcpyHostToDevice, s));
     // batch so that the FP64 blocks stay within ~4 GiB (one batch per level
     // up to 3,800 nodes of 512 columns x 276 rows)
-    const size_t per = (size_t)ncm * ell * sizeof(double);
-    int batch = (int)std::max<size_t>(1, std::min<size_t>(maxlev, (size_t)(4ull << 30) / per));
-    double *G;
-    int32_t *colpos, *d_ids;
-    HIPC(hipMallocAsync((void **)&G, per * batch, s));
-    HIPC(hipMallocAsync((void **)&colpos, sizeof(int32_t) * (size_t)ncm * batch, s));
-    HIPC(hipMallocAsync((void **)&d_ids, sizeof(int32_t) * nn, s));
-    const double *hpos = nullptr;
-    double *hp_tmp = nullptr;
-    if (h->varh) {
-        // per tree position bandwidth (FP64) from the per-id array
-        HIPC(hipMallocAsync((void **)&hp_tmp, sizeof(double) * h->N, s));
-        gather_f64(h->hsrc, h->perm, h->N, hp_tmp, s);
-        hpos = hp_tmp;
+    int64_t maxlev = 0;
+    for (int lev = 1; lev <= maxdepth; ++lev) {
+        int64_t c = 0;
+        for (auto *h : hs)
+            if (lev <= h->depth) c += (int64_t)h->level_nodes[lev].size();
+        maxlev = std::max(maxlev, c);
     }
+    const size_t per = (size_t)ncm * ell * sizeof(double);
+    const int batch = (int)std::max<size_t>(1, std::min<size_t>((size_t)maxlev, (size_t)(4ull << 30) / per));
+    double *G = (double *)ta(per * batch);
+    int32_t *colpos = (int32_t *)ta(sizeof(int32_t) * (size_t)ncm * batch);
+    int2 *d_items = (int2 *)ta(sizeof(int2) * batch);
     const size_t fg_lds = sizeof(float) * ((size_t)ell * FG_LT + (size_t)FG_C * FG_K);
     const size_t sv_lds = sizeof(double) * (size_t)std::min(smax, ell) * SV_C;
     if (fg_lds > 64 * 1024) {
@@ -842,7 +916,6 @@ void skeletonize(askit_handle *h, hipStream_t s)
     if (sv_lds > 64 * 1024)
         HIPC(hipFuncSetAttribute((const void *)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)sv_lds));
-    std::vector<int32_t> ids;
     // gang factorization: needs cooperative launches, at most 512 columns
     // (the registers of 4 x 32 x 4 slots) and 288 rows (18 per lane)
     int coop = 0, clk_khz = 0;
@@ -852,48 +925,61 @@ void skeletonize(askit_handle *h, hipStream_t s)
         HIPC(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
         HIPC(hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev));
     }
-    // (by default large point sets only: gang launches are serialized
-    // across host threads, which would serialize the many small setups of a
-    // batch).  ASKIT_QR_GANG=1 uses it at any size, 0 never.
+    // (by default the nodes of large point sets only, as each handle alone
+    // would: a node takes the same form of the QR alone and fused).
+    // ASKIT_QR_GANG=1 uses it at any size, 0 never.
     const char *genv = std::getenv("ASKIT_QR_GANG");
     const int gmode = genv ? std::atoi(genv) : -1;
-    const bool use_gang = coop && clk_khz > 0 && ncm <= 512 && ell <= 16 * 18 && gmode != 0 &&
-                          (gmode == 1 || h->N >= (1 << 18));
+    const bool can_gang = coop && clk_khz > 0 && ncm <= 512 && ell <= 16 * 18 && gmode != 0;
+    auto gang_node = [&](const askit_handle *h) { return can_gang && (gmode == 1 || h->N >= (1 << 18)); };
+    bool use_gang = false;
+    for (auto *h : hs) use_gang = use_gang || gang_node(h);
     const uint64_t g_timeout = (uint64_t)((double)clk_khz * 1000.0 * QG_TIMEOUT_S);
     GangScratch gsc;
     if (use_gang) {
-        HIPC(hipMallocAsync((void **)&gsc.slots, sizeof(GangSlot) * QG_GMAX * 2 * 8, s));
-        HIPC(hipMallocAsync((void **)&gsc.sdata, sizeof(double) * QG_GMAX * 2 * 8 * 16 * 18, s));
-        HIPC(hipMallocAsync((void **)&gsc.err, sizeof(int32_t), s));
+        gsc.slots = (GangSlot *)ta(sizeof(GangSlot) * QG_GMAX * 2 * 8);
+        gsc.sdata = (double *)ta(sizeof(double) * QG_GMAX * 2 * 8 * 16 * 18);
+        gsc.err = (int32_t *)ta(sizeof(int32_t));
     }
     hipEvent_t q0, q1;
     HIPC(hipEventCreate(&q0));
     HIPC(hipEventCreate(&q1));
-    h->t_qr = 0;
-    for (int lev = h->depth; lev >= 1; --lev) {
-        const auto &lv = h->level_nodes[lev];
-        for (size_t b0 = 0; b0 < lv.size(); b0 += batch) {
-            ids.assign(lv.begin() + b0, lv.begin() + std::min(lv.size(), b0 + batch));
-            int nb = (int)ids.size();
-            HIPC(hipStreamSynchronize(s));
-            HIPC(hipMemcpyAsync(d_ids, ids.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_cols, dim3(nb), dim3(256), 0, s, h->d_nodes, d_ids, smax, ncm, h->S,
-                               h->skk, colpos, h->ncols);
+    struct EvFree {
+        hipEvent_t a, b;
+        ~EvFree()
+        {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } evf{q0, q1};
+    double t_qr = 0.0;
+    std::vector<int2> items;
+    for (int lev = maxdepth; lev >= 1; --lev) {
+        // the level's nodes, those that take the gang form first
+        std::vector<int2> all;
+        for (int pass = 0; pass < 2; ++pass)
+            for (size_t i = 0; i < hs.size(); ++i)
+                if (lev <= hs[i]->depth && gang_node(hs[i]) == (pass == 0))
+                    for (int a : hs[i]->level_nodes[lev]) all.push_back(int2{(int)i, a});
+        for (size_t b0 = 0; b0 < all.size(); b0 += batch) {
+            items.assign(all.begin() + b0, all.begin() + std::min(all.size(), b0 + batch));
+            const int nb = (int)items.size();
+            int ng = 0;                             // items [0, ng) take the gang form
+            while (ng < nb && gang_node(hs[items[ng].x])) ++ng;
+            HIPC(hipStreamSynchronize(s));          // the previous batch is done with d_items
+            HIPC(hipMemcpyAsync(d_items, items.data(), sizeof(int2) * nb, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_cols, dim3(nb), dim3(256), 0, s, d_inst, d_items, smax, ncm, colpos);
             {
                 dim3 gg((ncm + FG_C - 1) / FG_C, nb), gb(FG_T);
                 const int pp = (ell * FG_C + FG_T - 1) / FG_T;
                 if (pp <= 4)
-                    hipLaunchKernelGGL(k_form_G<4>, gg, gb, fg_lds, s, h->Xt, h->dp, h->d, d_ids, h->T,
-                                       h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
+                    hipLaunchKernelGGL(k_form_G<4>, gg, gb, fg_lds, s, d_inst, d_items, ell, colpos, ncm, G);
                 else if (pp <= 8)
-                    hipLaunchKernelGGL(k_form_G<8>, gg, gb, fg_lds, s, h->Xt, h->dp, h->d, d_ids, h->T,
-                                       h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
+                    hipLaunchKernelGGL(k_form_G<8>, gg, gb, fg_lds, s, d_inst, d_items, ell, colpos, ncm, G);
                 else if (pp <= 16)
-                    hipLaunchKernelGGL(k_form_G<16>, gg, gb, fg_lds, s, h->Xt, h->dp, h->d, d_ids, h->T,
-                                       h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
+                    hipLaunchKernelGGL(k_form_G<16>, gg, gb, fg_lds, s, d_inst, d_items, ell, colpos, ncm, G);
                 else
-                    hipLaunchKernelGGL(k_form_G<32>, gg, gb, fg_lds, s, h->Xt, h->dp, h->d, d_ids, h->T,
-                                       h->T_cnt, ell, colpos, h->ncols, ncm, hpos, h->prm.bandwidth, G);
+                    hipLaunchKernelGGL(k_form_G<32>, gg, gb, fg_lds, s, d_inst, d_items, ell, colpos, ncm, G);
             }
             HIPC(hipEventRecord(q0, s));
             // every level: the node's columns in registers across a gang of
@@ -903,41 +989,42 @@ void skeletonize(askit_handle *h, hipStream_t s)
             // launch, more than 512 columns or 288 rows)
             bool gang = false;
             std::unique_lock<std::mutex> glk(g_gang_mu, std::defer_lock);
-            if (use_gang) {
+            if (use_gang && ng > 0) {
                 glk.lock();
-                const double tau = h->prm.id_tol;
                 if (ell <= 16 * 8)
-                    gang = nb >= 64 ? qr_gang_launch<4, 8, 4>(G, ell, ncm, d_ids, h->T_cnt, h->ncols, smax, tau,
-                                                             h->colperm, h->skk, nb, gsc, g_timeout, s)
-                                    : qr_gang_launch<8, 8, 2>(G, ell, ncm, d_ids, h->T_cnt, h->ncols, smax, tau,
-                                                             h->colperm, h->skk, nb, gsc, g_timeout, s);
+                    gang = ng >= 64 ? qr_gang_launch<4, 8, 4>(G, ell, ncm, d_inst, d_items, smax, tau, ng, gsc,
+                                                             g_timeout, s)
+                                    : qr_gang_launch<8, 8, 2>(G, ell, ncm, d_inst, d_items, smax, tau, ng, gsc,
+                                                             g_timeout, s);
                 else
-                    gang = nb >= 64 ? qr_gang_launch<4, 18, 4>(G, ell, ncm, d_ids, h->T_cnt, h->ncols, smax, tau,
-                                                              h->colperm, h->skk, nb, gsc, g_timeout, s)
-                                    : qr_gang_launch<8, 18, 2>(G, ell, ncm, d_ids, h->T_cnt, h->ncols, smax, tau,
-                                                              h->colperm, h->skk, nb, gsc, g_timeout, s);
+                    gang = ng >= 64 ? qr_gang_launch<4, 18, 4>(G, ell, ncm, d_inst, d_items, smax, tau, ng, gsc,
+                                                              g_timeout, s)
+                                    : qr_gang_launch<8, 18, 2>(G, ell, ncm, d_inst, d_items, smax, tau, ng, gsc,
+                                                              g_timeout, s);
                 if (!gang) glk.unlock();
             }
-            if (gang) {
+            // the rest (all items when the gang did not run), streaming G
+            const int q0i = gang ? ng : 0, nrest = nb - q0i;
+            double *Gr = G + (int64_t)q0i * ncm * ell;
+            const int2 *ir = d_items + q0i;
+            if (nrest == 0) {
             } else if (ell <= 16 * 8)
-                hipLaunchKernelGGL((k_qrcp<512, 8>), dim3((unsigned)nb), dim3(512), 0, s, G, ell, ncm, d_ids,
-                                   h->T_cnt, h->ncols, smax, h->prm.id_tol, h->colperm, h->skk, nb);
+                hipLaunchKernelGGL((k_qrcp<512, 8>), dim3((unsigned)nrest), dim3(512), 0, s, Gr, ell, ncm, d_inst,
+                                   ir, smax, tau, nrest);
             else if (ell <= 16 * 18)
-                hipLaunchKernelGGL((k_qrcp<512, 18>), dim3((unsigned)nb), dim3(512), 0, s, G, ell, ncm, d_ids,
-                                   h->T_cnt, h->ncols, smax, h->prm.id_tol, h->colperm, h->skk, nb);
+                hipLaunchKernelGGL((k_qrcp<512, 18>), dim3((unsigned)nrest), dim3(512), 0, s, Gr, ell, ncm,
+                                   d_inst, ir, smax, tau, nrest);
             else
-                hipLaunchKernelGGL((k_qrcp<QR_T, 0>), dim3((unsigned)nb), dim3(QR_T), 0, s, G, ell, ncm, d_ids,
-                                   h->T_cnt, h->ncols, smax, h->prm.id_tol, h->colperm, h->skk, nb);
+                hipLaunchKernelGGL((k_qrcp<QR_T, 0>), dim3((unsigned)nrest), dim3(QR_T), 0, s, Gr, ell, ncm,
+                                   d_inst, ir, smax, tau, nrest);
             HIPC(hipEventRecord(q1, s));
             if (smax <= SR_L * SR_R)
                 hipLaunchKernelGGL(k_solve_reg, dim3((ncm + SR_C - 1) / SR_C, nb), dim3(256), 0, s, G, ell, ncm,
-                                   d_ids, h->ncols, h->skk);
+                                   d_inst, d_items);
             else
                 hipLaunchKernelGGL(k_solve, dim3((ncm + SV_C - 1) / SV_C, nb), dim3(SV_T), sv_lds, s, G, ell,
-                               ncm, d_ids, h->ncols, h->skk);
-            hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(256), 0, s, G, ell, ncm, d_ids, colpos,
-                               h->ncols, h->skk, h->colperm, smax, h->d_pslot, h->Xt, h->dp, h->gt,
-                               h->S, h->P, h->Xs, h->gs);
+                                   ncm, d_inst, d_items);
+            hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(256), 0, s, G, ell, ncm, d_inst, d_items, colpos, smax);
             HIPC(hipGetLastError());
             HIPC(hipStreamSynchronize(s));
             if (gang) {
@@ -948,21 +1035,11 @@ void skeletonize(askit_handle *h, hipStream_t s)
             }
             float ms = 0.f;
             HIPC(hipEventElapsedTime(&ms, q0, q1));
-            h->t_qr += ms;
+            t_qr += ms;
         }
     }
-    (void)hipEventDestroy(q0);
-    (void)hipEventDestroy(q1);
     HIPC(hipStreamSynchronize(s));
-    HIPC(hipFreeAsync(G, s));
-    if (use_gang) {
-        HIPC(hipFreeAsync(gsc.slots, s));
-        HIPC(hipFreeAsync(gsc.sdata, s));
-        HIPC(hipFreeAsync(gsc.err, s));
-    }
-    HIPC(hipFreeAsync(colpos, s));
-    HIPC(hipFreeAsync(d_ids, s));
-    if (hp_tmp) HIPC(hipFreeAsync(hp_tmp, s));
+    for (auto *h : hs) h->t_qr = t_qr;
 }
 
 // ---------------------------------------------------------------- upward pass

@@ -115,5 +115,5 @@ def test_batch_argument_checks():
     assert L.askit_batch_run(None, None, 1, 1, None, 1, None) == A.ERR_INVALID_ARG
     assert L.askit_batch_instance(None, 0) is None
     assert L.askit_batch_set_launch(None, 1, 0, 0) == A.ERR_INVALID_ARG
-    assert C.sizeof(A.BatchInfo) == 152
+    assert C.sizeof(A.BatchInfo) == 160
     L.askit_batch_destroy(None)
