@@ -329,6 +329,7 @@ def batched_bench(args, A, torch):
         "plain_path": {"ms_per_step": res["plain"], "value": b.rows * R / (res["plain"] * 1e-3)},
         "batched_equals_plain": same,
         "setup_s": t_setup,
+        "setup_fused_skeletons_s": inf["t_skel_ms"] * 1e-3,
         "tuner": {"launch_blocks": inf["launch_blocks"], "launch_plan": ["wide", "narrow"][inf["launch_plan"]],
                   "candidate_ms": {"wide": inf["candidate_ms"][:4], "narrow": inf["candidate_ms"][4:]},
                   "candidates": "per plan: one workgroup per slab; persistent 2, 4, 8 per CU",
