@@ -43,8 +43,8 @@ BASELINE_METRIC = "kernel-sum targets\u00b7RHS/sec at 1e-3 rel err vs FP64; serv
 # for a plain copy of known size.  The figure holds for the kernel source it
 # was taken on: a different hash of that file reports null.
 TRAFFIC = {
-    "k_knn_filter": {"bytes_per_launch": 1.00401e12, "source": "paper_1410_0260_amd/csrc/knn.hip",
-                     "sha": "0c116dffa8254785"},
+    "k_knn_filter": {"bytes_per_launch": 2.05001e+11, "source": "paper_1410_0260_amd/csrc/knn.hip",
+                     "sha": "84b6fed5201d55d5"},
 }
 
 
@@ -492,8 +492,8 @@ def roofline_of(wl, r):
         sweep_ms = float(np.mean([i_["t_knn_filter_ms"] / i_["knn_filter_launches"] for i_ in infos]))
         kname = "k_knn_filter (bf16 hi/lo split distance sweep, symmetric)"
         alg = float(wl.N) * wl.N * wl.d / launches               # every unordered pair once
-        # pairs computed: the kept (128-row block, 64-point tile) pairs, 2 dp flops each
-        pairs = kept * 128.0 * 64.0 if kept >= 0 else float(wl.N) * wl.N / 2.0
+        # pairs computed: the kept (32-row wave group, 64-point tile) products, 2 dp flops each
+        pairs = kept * 32.0 * 64.0 if kept >= 0 else float(wl.N) * wl.N / 2.0
         issued = 3.0 * pairs * 2.0 * dp
     else:
         launches = 1
@@ -506,13 +506,14 @@ def roofline_of(wl, r):
             "unit": "TFLOP/s", "frac": issued / t / 1e12 / PEAK["bf16"],
             "traffic": traffic_of("k_knn_filter") if "filter" in kname else None,
             "avg_launch_ms": sweep_ms, "launches_per_step": launches,
-            "mfma_flops_issued_per_launch": issued, "tile_pairs_swept": kept,
+            "mfma_flops_issued_per_launch": issued, "wave_tiles_swept": kept,
             "all_pairs": {"algorithmic_flops": alg, "effective_tflops": alg / t / 1e12,
                           "note": "N^2 d (every unordered pair once, 2d flops each) over the same time: the "
                                   "rate of an exhaustive sweep that would take as long"},
             "note": ("achieved = bf16 MFMA flops issued (3 products hi*hi, hi*lo, lo*hi of 2 dp flops per "
-                     "computed pair; pairs = 128 x 64 per swept (row block, tile) pair after bounding-ball "
-                     "skipping) over the launch's HIP-event time")}
+                     "computed pair; pairs = 32 x 64 per swept (wave row group, tile) product after "
+                     "bounding-ball skipping, the count the MFMA instruction counter confirms) over the "
+                     "launch's HIP-event time")}
 
 
 def cpu_info():

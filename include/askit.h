@@ -247,9 +247,9 @@ typedef struct {
     int64_t near_lists;                  /* sum over points of |near(i)|: near leaves per point (Alg. 4) */
     int64_t far_lists;                   /* sum over points of |far(i)|: pruned nodes per point; with
                                             near_lists, the paper's near and far counters (Sec. 4) */
-    int64_t knn_tiles_swept;             /* last setup: (128-row block, 64-point tile) pairs the
-                                            symmetric kNN sweep computed after skipping the pairs whose
-                                            bounding balls are farther apart than the thresholds
+    int64_t knn_tiles_swept;             /* last setup: (32-row wave group, 64-point tile) products
+                                            the symmetric kNN sweep computed after skipping the pairs
+                                            whose bounding balls are farther apart than the thresholds
                                             (-1: no skipping) */
 } askit_info;
 

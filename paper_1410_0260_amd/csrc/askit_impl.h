@@ -209,7 +209,7 @@ struct askit_handle {
     double t_knn = 0, t_tree = 0, t_lists = 0, t_skel = 0, t_inter = 0, t_update = 0;
     double t_knn_sweep = 0, t_qr = 0, t_knn_filter = 0;
     int knn_filter_launches = 0, knn_retry_rows = 0;
-    int64_t knn_tiles_swept = -1;      // (row block, tile) pairs of the symmetric sweep; -1: no skipping
+    int64_t knn_tiles_swept = -1;      // (wave, tile) sweeps of the symmetric sweep; -1: no skipping
     std::vector<int32_t> knn_retry_list;   // their tree positions
     hipEvent_t ev_up0 = nullptr, ev_up1 = nullptr;
     bool up_pending = false;

@@ -1239,15 +1239,17 @@ __global__ __launch_bounds__(64) void k_tile_geom(const float *__restrict__ Xf, 
 
 // One workgroup per row block b (row groups 4b..4b+3, tiles 2b and 2b+1):
 // for every tile t >= 2b, bit (t - 2b) of the block's mask word w (w = the
-// wave) is set when that wave must sweep it; cnt[b] = tiles any wave needs.
+// wave) is set when that wave must sweep it; cnt[b] = tiles any wave needs,
+// wcnt[b] = (wave, tile) sweeps.
 __global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen_g, const TileGeom *__restrict__ geo_g,
                                                    int64_t ngroups, const float *__restrict__ cen_t,
                                                    const TileGeom *__restrict__ geo_t, int dp, int d,
                                                    int64_t ntiles, double g, const int64_t *__restrict__ moff,
-                                                   uint64_t *__restrict__ mask, int64_t *__restrict__ cnt)
+                                                   uint64_t *__restrict__ mask, int64_t *__restrict__ cnt,
+                                                   int64_t *__restrict__ wcnt)
 {
     __shared__ float ca[4][1024];
-    __shared__ int wsum[4];
+    __shared__ int wsum[4], wwsum[4];
     const int64_t b = blockIdx.x, t0 = 2 * b, g0 = 4 * b;
     const int nown = (int)min<int64_t>(2, ntiles - t0);
     const int ng = (int)min<int64_t>(4, ngroups - g0);
@@ -1256,7 +1258,7 @@ __global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen
     __syncthreads();
     TileGeom gw[4];
     for (int w = 0; w < 4; ++w) gw[w] = geo_g[g0 + min(w, ng - 1)];
-    int64_t total = 0;
+    int64_t total = 0, wtotal = 0;
     for (int64_t base = t0; base < ntiles; base += 256) {
         const int64_t t = base + threadIdx.x;
         bool keep[4] = {false, false, false, false};
@@ -1286,18 +1288,27 @@ __global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen
         }
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         uint64_t any = 0;
+        int nw = 0;
         for (int w = 0; w < 4; ++w) {
             const uint64_t bits = __ballot(keep[w]);
             any |= bits;
+            nw += __popcll(bits);
             const int64_t wd = (base - t0) / 64 + wv;
             if (lane == 0 && t0 + 64 * wd < ntiles) mask[(moff[b] + wd) * 4 + w] = bits;
         }
-        if (lane == 0) wsum[wv] = __popcll(any);
+        if (lane == 0) {
+            wsum[wv] = __popcll(any);
+            wwsum[wv] = nw;
+        }
         __syncthreads();
         total += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        wtotal += wwsum[0] + wwsum[1] + wwsum[2] + wwsum[3];
         __syncthreads();
     }
-    if (threadIdx.x == 0) cnt[b] = total;
+    if (threadIdx.x == 0) {
+        cnt[b] = total;
+        wcnt[b] = wtotal;
+    }
 }
 
 // Expands each block's masks into its list of entries (increasing tile
@@ -1326,8 +1337,8 @@ __global__ __launch_bounds__(64) void k_tile_list(const uint64_t *__restrict__ m
 // order, stride dp; thr the rows' thresholds).  Returns false (no lists) when
 // they do not apply.  Allocations go to tmp.
 static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const float *thr, const float *Xn,
-                             int32_t *&tlist, int64_t *&toff, int64_t &kept, int4 *&items, int64_t &nitems,
-                             std::vector<void *> &tmp, hipStream_t s)
+                             int32_t *&tlist, int64_t *&toff, int64_t &kept, int64_t &kept_waves, int4 *&items,
+                             int64_t &nitems, std::vector<void *> &tmp, hipStream_t s)
 {
     static_assert(KB_M == 2 * KB_N && KB_M == 4 * 32, "a row block is two tiles and four waves of 32 rows");
     const int64_t ntiles = (N + KB_N - 1) / KB_N, nblk = (N + KB_M - 1) / KB_M, ngroups = (N + 31) / 32;
@@ -1352,6 +1363,7 @@ static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const fl
     int64_t *moff = (int64_t *)ta(sizeof(int64_t) * (nblk + 1));
     uint64_t *mask = (uint64_t *)ta(sizeof(uint64_t) * words * 4);
     int64_t *cnt = (int64_t *)ta(sizeof(int64_t) * nblk);
+    int64_t *wcnt = (int64_t *)ta(sizeof(int64_t) * nblk);
     toff = (int64_t *)ta(sizeof(int64_t) * (nblk + 1));
     HIPC(hipMemcpyAsync(moff, hmoff.data(), sizeof(int64_t) * (nblk + 1), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_tile_geom<64>, dim3((unsigned)ntiles), dim3(64), 0, s, Xf, dp, d, N, thr, Xn, cen_t, geo_t);
@@ -1359,11 +1371,14 @@ static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const fl
                        geo_g);
     const double g = 2.0 * (3.1 * ldexp(1.0, -16) + (4.0 * dp + 8.0) * ldexp(1.0, -24));
     hipLaunchKernelGGL(k_tile_mask, dim3((unsigned)nblk), dim3(256), 0, s, cen_g, geo_g, ngroups, cen_t, geo_t, dp, d,
-                       ntiles, g, moff, mask, cnt);
+                       ntiles, g, moff, mask, cnt, wcnt);
     HIPC(hipGetLastError());
-    std::vector<int64_t> hc(nblk), ho(nblk + 1);
+    std::vector<int64_t> hc(nblk), ho(nblk + 1), hw(nblk);
     HIPC(hipMemcpyAsync(hc.data(), cnt, sizeof(int64_t) * nblk, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(hw.data(), wcnt, sizeof(int64_t) * nblk, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
+    kept_waves = 0;
+    for (int64_t b = 0; b < nblk; ++b) kept_waves += hw[b];
     ho[0] = 0;
     for (int64_t b = 0; b < nblk; ++b) ho[b + 1] = ho[b] + hc[b];
     kept = ho[nblk];
@@ -1458,11 +1473,11 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     // come within the thresholds
     std::vector<void *> ttmp;
     int32_t *tlist = nullptr;
-    int64_t *toff = nullptr, kept = 0, nitems = 0;
+    int64_t *toff = nullptr, kept = 0, kept_waves = 0, nitems = 0;
     int4 *items = nullptr;
     if (sym && !std::getenv("ASKIT_KNN_NO_SKIP") &&
-        build_tile_lists(Xf, dp, d, N, thr, Xn, tlist, toff, kept, items, nitems, ttmp, s)) {
-        if (tiles_swept) *tiles_swept = kept;
+        build_tile_lists(Xf, dp, d, N, thr, Xn, tlist, toff, kept, kept_waves, items, nitems, ttmp, s)) {
+        if (tiles_swept) *tiles_swept = kept_waves;
     } else {
         tlist = nullptr;
         toff = nullptr;
