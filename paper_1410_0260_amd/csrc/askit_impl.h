@@ -298,6 +298,8 @@ void sort_queries(askit_handle *h, const int32_t *nb, int64_t M, int32_t *order,
 
 // skel.hip
 void skeletonize(askit_handle *h, hipStream_t s);
+// Ascending bitonic sort of n2 (a power of two) 64-bit keys in place.
+void sort_u64_pow2(uint64_t *key, int64_t n2, hipStream_t s);
 // The skeletons of several handles (same ell, s_max and tolerance) in one
 // pass over the tree levels: each kernel launched once per level for the
 // nodes of every handle.

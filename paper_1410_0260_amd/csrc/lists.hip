@@ -664,6 +664,15 @@ __global__ void k_gather_i32_rows(const int32_t *__restrict__ src, const int32_t
     dst[t] = src[(int64_t)idx[row] * w + (t - row * w)];
 }
 
+void sort_u64_pow2(uint64_t *key, int64_t n2, hipStream_t s)
+{
+    for (int64_t k = 2; k <= n2; k <<= 1)
+        for (int64_t j = k >> 1; j > 0; j >>= 1)
+            hipLaunchKernelGGL(k_bitonic_step, dim3((unsigned)((n2 / 2 + 255) / 256)), dim3(256), 0, s, key, n2, j,
+                               k);
+    HIPC(hipGetLastError());
+}
+
 void sort_queries(askit_handle *h, const int32_t *nb, int64_t M, int32_t *order, int32_t *nb_sorted,
                   std::vector<void *> &tmp, hipStream_t s, const int32_t *seg)
 {
@@ -674,10 +683,7 @@ void sort_queries(askit_handle *h, const int32_t *nb, int64_t M, int32_t *order,
     tmp.push_back(key);
     hipLaunchKernelGGL(k_qkeys, dim3((unsigned)((M2 + 255) / 256)), dim3(256), 0, s, nb, M, h->kappa,
                        h->leaf_of, seg, (int64_t)h->nodes.size(), M2, key);
-    for (int64_t k = 2; k <= M2; k <<= 1)
-        for (int64_t j = k >> 1; j > 0; j >>= 1)
-            hipLaunchKernelGGL(k_bitonic_step, dim3((unsigned)((M2 / 2 + 255) / 256)), dim3(256), 0, s,
-                               key, M2, j, k);
+    sort_u64_pow2(key, M2, s);
     hipLaunchKernelGGL(k_qorder, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, key, M, order);
     int64_t tot = M * h->kappa;
     hipLaunchKernelGGL(k_gather_i32_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nb,

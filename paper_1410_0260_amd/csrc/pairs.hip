@@ -13,9 +13,81 @@
 // in which chunks run.
 #include "askit_impl.h"
 
-#include <hipcub/hipcub.hpp>
-
 namespace askit {
+
+// ---- exclusive prefix sums of int32 counts (out[i] = in[0] + ... + in[i-1]):
+// blocks of 1024 values scanned in registers and across waves, the block
+// totals scanned the same way (recursively), then added back.
+constexpr int SC_T = 256, SC_E = 4;
+
+__global__ __launch_bounds__(SC_T) void k_scan_block(const int32_t *__restrict__ in, int64_t n,
+                                                     int32_t *__restrict__ out, int32_t *__restrict__ bsum)
+{
+    __shared__ int32_t wsum[SC_T / 64];
+    const int64_t b0 = (int64_t)blockIdx.x * SC_T * SC_E;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int32_t v[SC_E];
+    int32_t tsum = 0;
+#pragma unroll
+    for (int u = 0; u < SC_E; ++u) {
+        const int64_t i = b0 + (int64_t)tid * SC_E + u;
+        v[u] = i < n ? in[i] : 0;
+        tsum += v[u];
+    }
+    int32_t x = tsum;                        // inclusive prefix over the wave's threads
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int32_t run = x - tsum;
+    for (int w = 0; w < wv; ++w) run += wsum[w];
+#pragma unroll
+    for (int u = 0; u < SC_E; ++u) {
+        const int64_t i = b0 + (int64_t)tid * SC_E + u;
+        if (i < n) out[i] = run;
+        run += v[u];
+    }
+    if (tid == SC_T - 1) bsum[blockIdx.x] = run;
+}
+
+__global__ void k_scan_add(int32_t *__restrict__ out, int64_t n, const int32_t *__restrict__ boff)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += boff[i / (SC_T * SC_E)];
+}
+
+static void exclusive_scan(const int32_t *in, int32_t *out, int64_t n, const std::function<void *(size_t)> &ta,
+                           hipStream_t s)
+{
+    if (n <= 0) return;
+    const int64_t per = SC_T * SC_E, nb = (n + per - 1) / per;
+    int32_t *bsum = (int32_t *)ta(sizeof(int32_t) * nb);
+    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(SC_T), 0, s, in, n, out, bsum);
+    HIPC(hipGetLastError());
+    if (nb > 1) {
+        int32_t *boff = (int32_t *)ta(sizeof(int32_t) * nb);
+        exclusive_scan(bsum, boff, nb, ta, s);
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, boff);
+        HIPC(hipGetLastError());
+    }
+}
+
+// sort keys: (source key << 32) | entry; entries past ne are padding
+__global__ void k_pair_sortkeys(const uint32_t *__restrict__ key, int64_t ne, int64_t n2, uint64_t *__restrict__ k64)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n2) return;
+    k64[e] = e < ne ? (((uint64_t)key[e] << 32) | (uint64_t)e) : ~0ull;
+}
+
+__global__ void k_pair_sorted_idx(const uint64_t *__restrict__ k64, int64_t ne, int32_t *__restrict__ idx_s)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ne) idx_s[i] = (int32_t)(k64[i] & 0xffffffffull);
+}
 
 // Segment of every list entry: the segment of its slab (`pad`).
 __global__ void k_entry_seg(const Slab *__restrict__ slabs, int64_t nslab, const int32_t *__restrict__ ptr,
@@ -29,13 +101,12 @@ __global__ void k_entry_seg(const Slab *__restrict__ slabs, int64_t nslab, const
 
 __global__ void k_pair_keys(const int32_t *__restrict__ node, const uint64_t *__restrict__ mask,
                             int64_t ne_near, int64_t ne, const int32_t *__restrict__ eseg, int64_t nn,
-                            uint32_t *__restrict__ key, int32_t *__restrict__ idx, int32_t *__restrict__ cnt)
+                            uint32_t *__restrict__ key, int32_t *__restrict__ cnt)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     const uint32_t k = (uint32_t)((eseg ? (int64_t)eseg[e] * nn : 0) + node[e]) * 2u + (e >= ne_near ? 1u : 0u);
     key[e] = k;
-    idx[e] = (int32_t)e;
     atomicAdd(&cnt[k], __popcll(mask[e]));      // integer counts: order-independent
 }
 
@@ -134,15 +205,12 @@ void build_pairs(const askit_handle *h, const Slab *d_slabs, int64_t nslab, int6
         hipLaunchKernelGGL(k_target_counts, dim3((unsigned)nslab), dim3(64), 0, s, d_slabs, nslab, ptr, mask,
                            cnt_t);
     HIPC(hipGetLastError());
-    size_t tb = 0;
-    HIPC(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt_t, L.sbase, (int)(ntarget + 1), s));
-    void *tstore = ta(tb);
-    HIPC(hipcub::DeviceScan::ExclusiveSum(tstore, tb, cnt_t, L.sbase, (int)(ntarget + 1), s));
+    exclusive_scan(cnt_t, L.sbase, ntarget + 1, ta, s);
 
     int32_t *off_e = (int32_t *)ta(sizeof(int32_t) * std::max<int64_t>(ne, 1));
     if (ne > 0) {
-        uint32_t *key = (uint32_t *)ta(sizeof(uint32_t) * ne), *key_s = (uint32_t *)ta(sizeof(uint32_t) * ne);
-        int32_t *idx = (int32_t *)ta(sizeof(int32_t) * ne), *idx_s = (int32_t *)ta(sizeof(int32_t) * ne);
+        uint32_t *key = (uint32_t *)ta(sizeof(uint32_t) * ne);
+        int32_t *idx_s = (int32_t *)ta(sizeof(int32_t) * ne);
         int32_t *pc = (int32_t *)ta(sizeof(int32_t) * ne), *off_s = (int32_t *)ta(sizeof(int32_t) * ne);
         const unsigned g = (unsigned)((ne + 255) / 256);
         int32_t *eseg = nullptr;
@@ -151,20 +219,18 @@ void build_pairs(const askit_handle *h, const Slab *d_slabs, int64_t nslab, int6
             hipLaunchKernelGGL(k_entry_seg, dim3((unsigned)nslab), dim3(64), 0, s, d_slabs, nslab, ptr, eseg);
             HIPC(hipGetLastError());
         }
-        hipLaunchKernelGGL(k_pair_keys, dim3(g), dim3(256), 0, s, node, mask, ne_near, ne, eseg, nn, key, idx, cnt);
+        hipLaunchKernelGGL(k_pair_keys, dim3(g), dim3(256), 0, s, node, mask, ne_near, ne, eseg, nn, key, cnt);
         HIPC(hipGetLastError());
-        int bits = 1;
-        while (((int64_t)1 << bits) < nkey) ++bits;
-        size_t sb = 0;
-        HIPC(hipcub::DeviceRadixSort::SortPairs(nullptr, sb, key, key_s, idx, idx_s, (int)ne, 0, bits, s));
-        void *sstore = ta(sb);
-        // LSD radix sort is stable: the entries of one source stay in list order
-        HIPC(hipcub::DeviceRadixSort::SortPairs(sstore, sb, key, key_s, idx, idx_s, (int)ne, 0, bits, s));
+        // entries by (source key, list position): the entry index in the low
+        // bits keeps the entries of one source in list order
+        int64_t n2 = 1;
+        while (n2 < ne) n2 <<= 1;
+        uint64_t *k64 = (uint64_t *)ta(sizeof(uint64_t) * n2);
+        hipLaunchKernelGGL(k_pair_sortkeys, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, key, ne, n2, k64);
+        sort_u64_pow2(k64, n2, s);
+        hipLaunchKernelGGL(k_pair_sorted_idx, dim3(g), dim3(256), 0, s, k64, ne, idx_s);
         hipLaunchKernelGGL(k_sorted_popc, dim3(g), dim3(256), 0, s, idx_s, mask, ne, pc);
-        size_t eb = 0;
-        HIPC(hipcub::DeviceScan::ExclusiveSum(nullptr, eb, pc, off_s, (int)ne, s));
-        void *estore = ta(eb);
-        HIPC(hipcub::DeviceScan::ExclusiveSum(estore, eb, pc, off_s, (int)ne, s));
+        exclusive_scan(pc, off_s, ne, ta, s);
         hipLaunchKernelGGL(k_scatter_off, dim3(g), dim3(256), 0, s, idx_s, off_s, ne, off_e);
         HIPC(hipGetLastError());
     }
