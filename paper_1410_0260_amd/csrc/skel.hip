@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <mutex>
 
@@ -354,13 +355,17 @@ __device__ __forceinline__ bool qg_better(double v1, int p1, double v2, int p2)
     return v1 > v2 || (v1 == v2 && p1 < p2);
 }
 
-template <int W, int RM, int CPG>
+// TIMING: each workgroup adds the clock cycles of its pivot steps' phases to
+// tacc (local argmax, publication, wait for the other members, candidate
+// loads, reflector, update of the held columns; then the step count), for
+// the ASKIT_QR_TIMING diagnostic.
+template <int W, int RM, int CPG, bool TIMING>
 __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, int ell, int ncol_max,
                                                      const SkelInst *__restrict__ inst,
                                                      const int2 *__restrict__ items, int smax, double tau,
                                                      int nb, GangSlot *__restrict__ slots,
                                                      double *__restrict__ sdata, int32_t *__restrict__ err,
-                                                     uint64_t timeout)
+                                                     uint64_t timeout, unsigned long long *__restrict__ tacc)
 {
     constexpr int RMAX = 16 * RM;
     __shared__ int piv[QR_MAXCOL];            // position -> column
@@ -381,6 +386,7 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
     const int ngang = gridDim.x / W;
     const int gang = (int)(blockIdx.x / (8 * W)) * 8 + (int)(blockIdx.x % 8), w = (int)(blockIdx.x / 8) % W;
     int32_t gs = 0;                           // steps published by this gang
+    unsigned long long tph[7] = {0, 0, 0, 0, 0, 0, 0};
     if (tid == 0) s_fail = 0;
     for (int q = gang; q < nb; q += ngang) {
         __syncthreads();
@@ -415,6 +421,8 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
         int k = kcap;
         double nrm0 = 0.0;
         for (int t = 0; t < kcap; ++t) {
+            unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
+            if constexpr (TIMING) c0 = clock64();
             // this workgroup's best active column
             double bv = -1.0;
             int bp = 0x7fffffff, bc = -1;
@@ -433,6 +441,7 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
             }
             if (lane == 0) { rdv[wv] = bv; rdp[wv] = bp; rdc[wv] = bc; }
             __syncthreads();
+            if constexpr (TIMING) c1 = clock64();
             ++gs;
             const int par = gs & 1;
             GangSlot *sl = slots + ((int64_t)gang * 2 + par) * W;
@@ -481,6 +490,7 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
             __syncthreads();
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
             if (tid == 0) __hip_atomic_store(&sl[w].seq, gs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if constexpr (TIMING) c2 = clock64();
             // every wave waits for the W candidates of this step itself (its
             // lanes < W poll), then loads its share: the loads of a lane are
             // issued only after its wave saw all W sequence numbers
@@ -496,6 +506,7 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
                 }
             }
             __builtin_amdgcn_wave_barrier();
+            if constexpr (TIMING) c3 = clock64();
             // the loads below are issued after the poll in program order (the
             // hardware issues a wave's loads in order; the fence keeps the
             // compiler from hoisting them above the loop)
@@ -513,6 +524,7 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
             }
             __syncthreads();
             if (s_fail) return;
+            if constexpr (TIMING) c4 = clock64();
             double gv = -1.0;
             int gp = 0x7fffffff, pc = -1, pw = 0;
 #pragma unroll
@@ -565,6 +577,7 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
             double vr[RM];
 #pragma unroll
             for (int r = 0; r < RM; ++r) vr[r] = svr[l16 + 16 * r];
+            if constexpr (TIMING) c5 = clock64();
             const int src = (lane & ~15) | lt;
             const bool lane_after = l16 > lt, lane_at = l16 == lt;
 #pragma unroll
@@ -604,6 +617,16 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
                 }
                 nv[j] = group16_sum(ns);
             }
+            if constexpr (TIMING) {
+                const unsigned long long c6 = clock64();
+                tph[0] += c1 - c0;
+                tph[1] += c2 - c1;
+                tph[2] += c3 - c2;
+                tph[3] += c4 - c3;
+                tph[4] += c5 - c4;
+                tph[5] += c6 - c5;
+                tph[6] += 1;
+            }
         }
         // every column to its final position
         __syncthreads();
@@ -623,6 +646,10 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
             for (int c = tid; c < cols; c += QG_T) I.colperm[(int64_t)a * I.ncol_max + c] = piv[c];
             if (tid == 0) I.skk[a] = k;
         }
+    }
+    if constexpr (TIMING) {
+        if (tid == 0)
+            for (int i = 0; i < 7; ++i) atomicAdd(&tacc[i], tph[i]);
     }
 }
 
@@ -768,6 +795,7 @@ struct GangScratch {
     GangSlot *slots = nullptr;
     double *sdata = nullptr;
     int32_t *err = nullptr;
+    unsigned long long *tacc = nullptr;     // ASKIT_QR_TIMING: phase cycle sums, else NULL
 };
 
 __global__ void k_gang_reset(GangSlot *__restrict__ slots, int n, int32_t *__restrict__ err)
@@ -785,14 +813,14 @@ __global__ void k_gang_reset(GangSlot *__restrict__ slots, int n, int32_t *__res
 // one kernel at a time.
 static std::mutex g_gang_mu;
 
-template <int W, int RM, int CPG>
-static bool qr_gang_launch(double *G, int ell, int ncm, const SkelInst *inst, const int2 *items, int smax,
-                           double tau, int nb, const GangScratch &gs, uint64_t timeout, hipStream_t s)
+template <int W, int RM, int CPG, bool TIMING>
+static bool qr_gang_launch1(double *G, int ell, int ncm, const SkelInst *inst, const int2 *items, int smax,
+                            double tau, int nb, const GangScratch &gs, uint64_t timeout, hipStream_t s)
 {
     int dev = 0, ncu = 0, per = 0;
     HIPC(hipGetDevice(&dev));
     HIPC(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_qrcp_gang<W, RM, CPG>, QG_T, 0));
+    HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_qrcp_gang<W, RM, CPG, TIMING>, QG_T, 0));
     // a multiple of 8 gangs (one set per XCD); gangs past the last node idle
     const int fit = std::min(QG_GMAX, per * ncu / W) / 8 * 8;
     const int ngang = std::min(fit, (nb + 7) / 8 * 8);
@@ -804,10 +832,20 @@ static bool qr_gang_launch(double *G, int ell, int ncm, const SkelInst *inst, co
     GangSlot *slots = gs.slots;
     double *sdata = gs.sdata;
     int32_t *err = gs.err;
-    void *args[] = {&G, &ell, &ncm, (void *)&inst, (void *)&items, &smax, &tau, &nb, &slots, &sdata, &err, &timeout};
-    HIPC(hipLaunchCooperativeKernel((const void *)k_qrcp_gang<W, RM, CPG>, dim3((unsigned)(ngang * W)),
+    unsigned long long *tacc = gs.tacc;
+    void *args[] = {&G, &ell, &ncm, (void *)&inst, (void *)&items, &smax, &tau, &nb, &slots, &sdata, &err, &timeout,
+                    &tacc};
+    HIPC(hipLaunchCooperativeKernel((const void *)k_qrcp_gang<W, RM, CPG, TIMING>, dim3((unsigned)(ngang * W)),
                                     dim3(QG_T), args, 0, s));
     return true;
+}
+
+template <int W, int RM, int CPG>
+static bool qr_gang_launch(double *G, int ell, int ncm, const SkelInst *inst, const int2 *items, int smax,
+                           double tau, int nb, const GangScratch &gs, uint64_t timeout, hipStream_t s)
+{
+    return gs.tacc ? qr_gang_launch1<W, RM, CPG, true>(G, ell, ncm, inst, items, smax, tau, nb, gs, timeout, s)
+                   : qr_gang_launch1<W, RM, CPG, false>(G, ell, ncm, inst, items, smax, tau, nb, gs, timeout, s);
 }
 
 void skeletonize(askit_handle *h, hipStream_t s)
@@ -940,6 +978,10 @@ void skeletonize_multi(const std::vector<askit_handle *> &hs, hipStream_t s)
         gsc.slots = (GangSlot *)ta(sizeof(GangSlot) * QG_GMAX * 2 * 8);
         gsc.sdata = (double *)ta(sizeof(double) * QG_GMAX * 2 * 8 * 16 * 18);
         gsc.err = (int32_t *)ta(sizeof(int32_t));
+        // ASKIT_QR_TIMING=1: per gang launch, the mean clock cycles of a pivot
+        // step's phases on stderr (a diagnostic; off by default)
+        const char *tenv = std::getenv("ASKIT_QR_TIMING");
+        if (tenv && std::atoi(tenv) == 1) gsc.tacc = (unsigned long long *)ta(sizeof(unsigned long long) * 8);
     }
     hipEvent_t q0, q1;
     HIPC(hipEventCreate(&q0));
@@ -991,6 +1033,7 @@ void skeletonize_multi(const std::vector<askit_handle *> &hs, hipStream_t s)
             std::unique_lock<std::mutex> glk(g_gang_mu, std::defer_lock);
             if (use_gang && ng > 0) {
                 glk.lock();
+                if (gsc.tacc) HIPC(hipMemsetAsync(gsc.tacc, 0, sizeof(unsigned long long) * 8, s));
                 if (ell <= 16 * 8)
                     gang = ng >= 64 ? qr_gang_launch<4, 8, 4>(G, ell, ncm, d_inst, d_items, smax, tau, ng, gsc,
                                                              g_timeout, s)
@@ -1032,6 +1075,16 @@ void skeletonize_multi(const std::vector<askit_handle *> &hs, hipStream_t s)
                 HIPC(hipMemcpy(&herr, gsc.err, sizeof(int32_t), hipMemcpyDeviceToHost));
                 glk.unlock();
                 if (herr) fail(ASKIT_ERR_DEVICE, "QR gang exchange timed out (workgroups not co-resident)");
+                if (gsc.tacc) {
+                    unsigned long long tc[8];
+                    HIPC(hipMemcpy(tc, gsc.tacc, sizeof(tc), hipMemcpyDeviceToHost));
+                    const double st = tc[6] ? (double)tc[6] : 1.0;
+                    std::fprintf(stderr,
+                                 "[askit qr timing] level %d: %d nodes, %llu workgroup pivot steps; cycles per step: "
+                                 "argmax %.0f, publish %.0f, wait %.0f, load %.0f, reflector %.0f, update %.0f\n",
+                                 lev, ng, tc[6], tc[0] / st, tc[1] / st, tc[2] / st, tc[3] / st, tc[4] / st,
+                                 tc[5] / st);
+                }
             }
             float ms = 0.f;
             HIPC(hipEventElapsedTime(&ms, q0, q1));
