@@ -54,6 +54,14 @@ __global__ void k_bandwidth(const double *__restrict__ knn_d, int64_t N, int kap
 }
 
 // g = -log2(e) / (2 h^2) per tree position (FP32 exponent factor of exp2).
+// list[i] <- ip[p[list[i]]] (a row of one order as a position of another)
+__global__ void k_map_rows(int32_t *__restrict__ list, int64_t n, const int32_t *__restrict__ p,
+                           const int32_t *__restrict__ ip)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) list[i] = ip[p[list[i]]];
+}
+
 __global__ void k_gfactor(const double *__restrict__ hs, const int32_t *__restrict__ perm, int64_t N,
                           float *__restrict__ g)
 {
@@ -543,12 +551,17 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
         h->t_knn_filter = fms;
         HIPC(hipEventRecord(k1, s));
         if (fine && !h->knn_retry_list.empty()) {
-            // retried rows are reported as tree positions
-            std::vector<int32_t> pf(N), ip(N);
-            HIPC(hipMemcpyAsync(pf.data(), perm_f, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
-            HIPC(hipMemcpyAsync(ip.data(), h->iperm, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
+            // retried rows are reported as tree positions: iperm[perm_f[r]]
+            const int64_t nr = (int64_t)h->knn_retry_list.size();
+            int32_t *dl;
+            HIPC(hipMallocAsync((void **)&dl, sizeof(int32_t) * nr, s));
+            HIPC(hipMemcpyAsync(dl, h->knn_retry_list.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_map_rows, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, dl, nr, perm_f,
+                               h->iperm);
+            HIPC(hipGetLastError());
+            HIPC(hipMemcpyAsync(h->knn_retry_list.data(), dl, sizeof(int32_t) * nr, hipMemcpyDeviceToHost, s));
+            HIPC(hipFreeAsync(dl, s));
             HIPC(hipStreamSynchronize(s));
-            for (int32_t &r : h->knn_retry_list) r = ip[pf[r]];
         }
         float *tb;
         HIPC(hipMallocAsync((void **)&tb, sizeof(float) * N, s));

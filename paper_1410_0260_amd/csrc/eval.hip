@@ -190,9 +190,29 @@ __global__ __launch_bounds__(EV_T) void k_eval_chunks(ChunkParams p)
             load_chunk(sS, sSh, sSl, srow, c * EV_KC, sSn, c > 0);
             if (c == 0) {
                 if (tid < 64) sSg[tid] = tid < nsrc ? g[s0 + tid] : 0.0f;
-                for (int e = tid; e < 64 * CM; e += EV_T) {
-                    const int r = e / CM, j = e % CM;
-                    sW[e] = (r < nsrc && j < p.rb) ? w[(int64_t)(s0 + r) * p.R + p.r0 + j] : 0.0f;
+                if constexpr (64 * CM >= EV_T) {
+                    // unconditional loads (indices clamped to the tile's first
+                    // entry), all in flight, then masked
+                    constexpr int NW = 64 * CM / EV_T;
+                    float wv_[NW];
+#pragma unroll
+                    for (int u = 0; u < NW; ++u) {
+                        const int e = tid + EV_T * u, r = e / CM, j = e % CM;
+                        const bool in = r < nsrc && j < p.rb;
+                        wv_[u] = w[in ? (int64_t)(s0 + r) * p.R + p.r0 + j : (int64_t)s0 * p.R + p.r0];
+                    }
+#pragma unroll
+                    for (int u = 0; u < NW; ++u) asm volatile("" : "+v"(wv_[u]));
+#pragma unroll
+                    for (int u = 0; u < NW; ++u) {
+                        const int e = tid + EV_T * u, r = e / CM, j = e % CM;
+                        sW[e] = (r < nsrc && j < p.rb) ? wv_[u] : 0.0f;
+                    }
+                } else {
+                    for (int e = tid; e < 64 * CM; e += EV_T) {
+                        const int r = e / CM, j = e % CM;
+                        sW[e] = (r < nsrc && j < p.rb) ? w[(int64_t)(s0 + r) * p.R + p.r0 + j] : 0.0f;
+                    }
                 }
             }
             __syncthreads();

@@ -879,12 +879,19 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
         if (lane == 0) thr[row] = n > cap ? m + fabsf(m) * 1e-5f + 1e-30f : (n >= KNN_CAND ? m : tin);
         return;
     }
+    // keys and ids of the stored entries; the loads are unconditional (index
+    // clamped to the last entry) so that all of them are in flight at once
+    // the stored distances, loaded unconditionally (index clamped to the last
+    // entry) and pinned by an empty asm so that the loads are not sunk into
+    // per-entry branches: all of them are in flight at once
+    float kv[SEL_Q];
+#pragma unroll
+    for (int q = 0; q < SEL_Q; ++q) kv[q] = rd[min(lane + WAVE * q, nk - 1)];
+#pragma unroll
+    for (int q = 0; q < SEL_Q; ++q) asm volatile("" : "+v"(kv[q]));
     uint32_t key[SEL_Q];
 #pragma unroll
-    for (int q = 0; q < SEL_Q; ++q) {
-        const int e = lane + WAVE * q;
-        key[q] = e < nk ? f2key(rd[e]) : 0xffffffffu;
-    }
+    for (int q = 0; q < SEL_Q; ++q) key[q] = lane + WAVE * q < nk ? f2key(kv[q]) : 0xffffffffu;
     // the KNN_CAND-th smallest key, one 8-bit digit at a time
     uint32_t prefix = 0, pmask = 0;
     int kk = KNN_CAND;                   // rank sought among the keys matching prefix
@@ -929,15 +936,19 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
         __builtin_amdgcn_wave_barrier();
     }
     const uint32_t K = prefix;           // kk of the keys equal to K complete the 64
-    // entries below K (64 - kk of them), then the kk equal ones with the smallest positions
+    // the winners' entry positions go to a per-wave list in LDS (the
+    // histogram's space), then each lane loads one id: entries below K (64 -
+    // kk of them), then the kk equal ones with the smallest positions
+    int *slot = hw;
     int base = 0;
 #pragma unroll
     for (int q = 0; q < SEL_Q; ++q) {
         const bool pr = key[q] < K;
         const uint64_t bm = __ballot(pr);
-        if (pr) co[base + __popcll(bm & ((1ull << lane) - 1ull))] = ri[lane + WAVE * q];
+        if (pr) slot[base + __popcll(bm & ((1ull << lane) - 1ull))] = lane + WAVE * q;
         base += __popcll(bm);
     }
+    int nslot = base;
     int neq = 0;
 #pragma unroll
     for (int q = 0; q < SEL_Q; ++q) neq += __popcll(__ballot(key[q] == K));
@@ -946,11 +957,12 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
         for (int q = 0; q < SEL_Q; ++q) {
             const bool pr = key[q] == K;
             const uint64_t bm = __ballot(pr);
-            if (pr) co[base + __popcll(bm & ((1ull << lane) - 1ull))] = ri[lane + WAVE * q];
+            if (pr) slot[base + __popcll(bm & ((1ull << lane) - 1ull))] = lane + WAVE * q;
             base += __popcll(bm);
         }
+        nslot = base;
     } else {
-        // ties at the 64th distance: the kk smallest positions among them
+        // ties at the 64th distance: the kk smallest ids among them
         int last = -1;
         for (int take = 0; take < kk; ++take) {
             int mi = 0x7fffffff;
@@ -968,6 +980,8 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
             last = mi;
         }
     }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < nslot) co[lane] = ri[slot[lane]];
     // bound for the points outside the candidates: the 64th survivor.  A row
     // whose segment overflowed is swept again; the 64th of its stored
     // survivors (real distances, so at least its 64th smallest), widened as

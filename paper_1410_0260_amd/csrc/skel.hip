@@ -84,19 +84,38 @@ __global__ __launch_bounds__(FG_T) void k_form_G(const SkelInst *__restrict__ in
     float *sT = fsm;                           // rows x FG_LT
     float *sC = fsm + (size_t)rows * FG_LT;    // FG_C x FG_K
     const int npair = rows * nc;
+    // the node's sampled-row ids and the block's column ids, read once
+    __shared__ int32_t sTid[FG_MAXROW], sCid[FG_C];
+    for (int t = threadIdx.x; t < rows; t += FG_T) sTid[t] = T[(int64_t)a * ell + t];
+    if (threadIdx.x < FG_C)
+        sCid[threadIdx.x] = colpos[(int64_t)q * ncol_max + c0 + min((int)threadIdx.x, nc - 1)];
     double acc[PP];
 #pragma unroll
     for (int u = 0; u < PP; ++u) acc[u] = 0.0;
+    const int ne = rows * FG_K;
     for (int k0 = 0; k0 < d; k0 += FG_K) {
         const int kk = min(FG_K, d - k0);
         __syncthreads();
-        for (int e = threadIdx.x; e < rows * FG_K; e += FG_T) {
-            int t = e / FG_K, j = e % FG_K;
-            sT[t * FG_LT + j] = j < kk ? Xt[(int64_t)T[(int64_t)a * ell + t] * dp + k0 + j] : 0.0f;
+        // coordinates k0 .. k0 + FG_K of the rows and columns, eight loads in
+        // flight per thread (indices clamped in bounds; entries past kk are
+        // never read)
+        for (int e0 = threadIdx.x; e0 < ne; e0 += FG_T * 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = min(e0 + FG_T * u, ne - 1);
+                const int t = e / FG_K, j = e % FG_K;
+                v[u] = Xt[(int64_t)sTid[t] * dp + min(k0 + j, dp - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + FG_T * u;
+                if (e < ne) sT[(e / FG_K) * FG_LT + e % FG_K] = v[u];
+            }
         }
         for (int e = threadIdx.x; e < nc * FG_K; e += FG_T) {
-            int c = e / FG_K, j = e % FG_K;
-            sC[e] = j < kk ? Xt[(int64_t)colpos[(int64_t)q * ncol_max + c0 + c] * dp + k0 + j] : 0.0f;
+            const int c = e / FG_K, j = e % FG_K;
+            sC[e] = Xt[(int64_t)sCid[c] * dp + min(k0 + j, dp - 1)];
         }
         __syncthreads();
 #pragma unroll
@@ -119,8 +138,7 @@ __global__ __launch_bounds__(FG_T) void k_form_G(const SkelInst *__restrict__ in
         const int pi = threadIdx.x + FG_T * u;
         if (pi < npair) {
             const int t = pi % rows, c = pi / rows;
-            const int32_t cpos = colpos[(int64_t)q * ncol_max + c0 + c];
-            const double hc = hpos ? hpos[cpos] : h;
+            const double hc = hpos ? hpos[sCid[c]] : h;
             G[((int64_t)q * ncol_max + c0 + c) * ell + t] = exp(-acc[u] / (2.0 * hc * hc));
         }
     }
@@ -722,19 +740,32 @@ __global__ __launch_bounds__(256) void k_solve_reg(double *__restrict__ Gall, in
     const bool cok = c0 + col < m;
     double *G = Gall + (int64_t)q * ncol_max * ell;
     double *pc = G + (int64_t)(k + c0 + (cok ? col : 0)) * ell;
+    // loads are unconditional (indices clamped inside the block) so that they
+    // are all in flight at once; entries outside R are replaced by zeros
     double P[SR_R];
 #pragma unroll
     for (int i = 0; i < SR_R; ++i) {
         const int u = SR_L * i + j;
-        P[i] = (cok && u < k) ? pc[u] : 0.0;
+        const double v = pc[min(u, ell - 1)];
+        P[i] = (cok && u < k) ? v : 0.0;
     }
 #pragma clang loop unroll(full)
     for (int ib = SR_R - 1; ib >= 0; --ib) {
         if (SR_L * ib >= k) continue;
         __syncthreads();
-        for (int e = tid; e < SR_L * SR_L * SR_R; e += 256) {
+        static_assert((SR_L * SR_L * SR_R) % 256 == 0, "the staging loop covers the block exactly");
+        double v[SR_L * SR_L * SR_R / 256];
+#pragma unroll
+        for (int r = 0; r < SR_L * SR_L * SR_R / 256; ++r) {
+            const int e = tid + 256 * r;
             const int cc = e / (SR_L * SR_R), u = e % (SR_L * SR_R), t = SR_L * ib + cc;
-            sR[e] = (t < k && u <= t) ? G[(int64_t)t * ell + u] : 0.0;
+            v[r] = G[(int64_t)min(t, k - 1) * ell + min(u, ell - 1)];
+        }
+#pragma unroll
+        for (int r = 0; r < SR_L * SR_L * SR_R / 256; ++r) {
+            const int e = tid + 256 * r;
+            const int cc = e / (SR_L * SR_R), u = e % (SR_L * SR_R), t = SR_L * ib + cc;
+            sR[e] = (t < k && u <= t) ? v[r] : 0.0;
         }
         __syncthreads();
         for (int jj = SR_L - 1; jj >= 0; --jj) {
@@ -1098,6 +1129,55 @@ void skeletonize_multi(const std::vector<askit_handle *> &hs, hipStream_t s)
 // ---------------------------------------------------------------- upward pass
 // w~_alpha[t] = Wc[piv t] + sum_c P[t][c] Wc[piv k+c]; Wc = W(X_alpha) at a
 // leaf, [w~_left; w~_right] at an internal node.  One wave per (node, t).
+// Skeleton weights of row t of node a, columns [r0, r1): w~_t = w(S_t) +
+// sum_c P_tc w(R_c) (Alg. 3, the far field by skeletonization).  Each
+// column's sum runs over c = lane, lane + 64, ... as an fma chain per lane,
+// then a xor butterfly across the wave (every lane ends with the same total);
+// the columns are taken RT at a time so that their weight loads are in flight
+// together.  A column's arithmetic does not depend on RT, on the column range
+// or on the number of columns.
+template <int RT>
+__device__ __forceinline__ void upward_row(const Node &nd, int a, int t, int k, int nr, int kl,
+                                           const int32_t *__restrict__ pv, const float *__restrict__ Pt,
+                                           const float *__restrict__ Wt, float *__restrict__ Wsk, int smax, int R,
+                                           int r0, int r1)
+{
+    const int lane = threadIdx.x;
+    // row of column c of the node's block: its own points at a leaf, else the
+    // children's skeleton rows (left first)
+    auto wrow = [&](int c) -> const float * {
+        if (nd.left < 0) return Wt + (int64_t)(nd.lo + c) * R;
+        return c < kl ? Wsk + ((int64_t)nd.left * smax + c) * R
+                      : Wsk + ((int64_t)nd.right * smax + (c - kl)) * R;
+    };
+    const float *w0 = wrow(pv[t]);
+    for (int rt = r0; rt < r1; rt += RT) {
+        float acc[RT];
+#pragma unroll
+        for (int j = 0; j < RT; ++j) acc[j] = 0.0f;
+#pragma unroll 2
+        for (int c = lane; c < nr; c += 64) {
+            const float pc = Pt[c];
+            const float *wr = wrow(pv[k + c]);
+            float wv[RT];
+#pragma unroll
+            for (int j = 0; j < RT; ++j) wv[j] = wr[min(rt + j, r1 - 1)];   // clamped: unconditional loads
+#pragma unroll
+            for (int j = 0; j < RT; ++j) acc[j] = fmaf(pc, wv[j], acc[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < RT; ++j) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) acc[j] += __shfl_xor(acc[j], o);
+        }
+        float v = acc[0];
+#pragma unroll
+        for (int j = 1; j < RT; ++j) v = lane == j ? acc[j] : v;
+        if (lane < RT && rt + lane < r1) Wsk[((int64_t)a * smax + t) * R + rt + lane] = w0[rt + lane] + v;
+    }
+}
+
+template <int RT>
 __global__ __launch_bounds__(64) void k_upward(const Node *__restrict__ nodes,
                                                const int32_t *__restrict__ ids,
                                                const int32_t *__restrict__ skk,
@@ -1108,27 +1188,111 @@ __global__ __launch_bounds__(64) void k_upward(const Node *__restrict__ nodes,
                                                const float *__restrict__ Wt, int R,
                                                float *__restrict__ Wsk, int r0, int r1)
 {
-    const int a = ids[blockIdx.x], t = blockIdx.y, lane = threadIdx.x;
+    const int a = ids[blockIdx.x], t = blockIdx.y;
     const int k = skk[a];
     if (t >= k) return;
     const Node nd = nodes[a];
-    const int n = ncols[a], nr = n - k;
-    const int32_t *pv = colperm + (int64_t)a * ncol_max;
-    const float *Pt = P + pslot[a] + (int64_t)t * nr;
+    const int nr = ncols[a] - k;
     const int kl = nd.left >= 0 ? skk[nd.left] : 0;
-    auto wc = [&](int c, int r) -> float {
-        if (nd.left < 0) return Wt[(int64_t)(nd.lo + c) * R + r];
-        return c < kl ? Wsk[((int64_t)nd.left * smax + c) * R + r]
-                      : Wsk[((int64_t)nd.right * smax + (c - kl)) * R + r];
+    upward_row<RT>(nd, a, t, k, nr, kl, colperm + (int64_t)a * ncol_max, P + pslot[a] + (int64_t)t * nr, Wt, Wsk,
+                   smax, R, r0, r1);
+}
+
+// The same rows of skeleton weights for many columns: one workgroup per
+// (node, UP_TT skeleton rows).  For each tile of RT columns the node's
+// non-skeleton weight rows are staged in LDS once, then the four waves take
+// the skeleton rows in turn.  Every column's arithmetic is that of
+// upward_row (fma chain over c = lane, lane + 64, ..., xor butterfly,
+// w(S_t) added last), so both forms give the same bits.
+constexpr int UP_TT = 64;
+
+template <int RT>
+__device__ __forceinline__ void upward_block(const Node &nd, int a, int k, int nr, int kl,
+                                             const int32_t *__restrict__ pv, const float *__restrict__ Pa,
+                                             const float *__restrict__ Wt, float *__restrict__ Wsk, int smax,
+                                             int R, int r0, int r1, int t0, int32_t *sPv, float *sW)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    auto wrow = [&](int c) -> const float * {
+        if (nd.left < 0) return Wt + (int64_t)(nd.lo + c) * R;
+        return c < kl ? Wsk + ((int64_t)nd.left * smax + c) * R
+                      : Wsk + ((int64_t)nd.right * smax + (c - kl)) * R;
     };
-    for (int r = r0; r < r1; ++r) {
-        float acc = 0.0f;
-        for (int c = lane; c < nr; c += 64) acc = fmaf(Pt[c], wc(pv[k + c], r), acc);
+    for (int c = tid; c < nr; c += 256) sPv[c] = pv[k + c];
+    const int tn = min(UP_TT, k - t0);
+    const int ne = nr * RT;
+    for (int rt = r0; rt < r1; rt += RT) {
+        __syncthreads();
+        // rows c of the block, columns rt .. rt + RT (clamped: unconditional loads, four in flight)
+        for (int e0 = tid; e0 < ne; e0 += 256 * 4) {
+            float v[4];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) Wsk[((int64_t)a * smax + t) * R + r] = wc(pv[t], r) + acc;
+            for (int u = 0; u < 4; ++u) {
+                const int e = min(e0 + 256 * u, ne - 1);
+                v[u] = wrow(sPv[e / RT])[min(rt + e % RT, r1 - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + 256 * u;
+                if (e < ne) sW[(e / RT) * (RT + 1) + e % RT] = v[u];
+            }
+        }
+        __syncthreads();
+        for (int tt = wv; tt < tn; tt += 4) {
+            const int t = t0 + tt;
+            const float *Pt = Pa + (int64_t)t * nr;
+            float acc[RT];
+#pragma unroll
+            for (int j = 0; j < RT; ++j) acc[j] = 0.0f;
+#pragma unroll 2
+            for (int c = lane; c < nr; c += 64) {
+                const float pc = Pt[c];
+                const float *wr = sW + c * (RT + 1);
+#pragma unroll
+                for (int j = 0; j < RT; ++j) acc[j] = fmaf(pc, wr[j], acc[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < RT; ++j) {
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) acc[j] += __shfl_xor(acc[j], o);
+            }
+            float v = acc[0];
+#pragma unroll
+            for (int j = 1; j < RT; ++j) v = lane == j ? acc[j] : v;
+            if (lane < RT && rt + lane < r1)
+                Wsk[((int64_t)a * smax + t) * R + rt + lane] = wrow(pv[t])[rt + lane] + v;
+        }
     }
 }
+
+template <int RT>
+__global__ __launch_bounds__(256) void k_upward_blk(const Node *__restrict__ nodes,
+                                                    const int32_t *__restrict__ ids,
+                                                    const int32_t *__restrict__ skk,
+                                                    const int32_t *__restrict__ ncols,
+                                                    const int32_t *__restrict__ colperm, int ncol_max,
+                                                    const int64_t *__restrict__ pslot,
+                                                    const float *__restrict__ P, int smax,
+                                                    const float *__restrict__ Wt, int R,
+                                                    float *__restrict__ Wsk, int r0, int r1)
+{
+    extern __shared__ float usm[];
+    const int a = ids[blockIdx.x], t0 = blockIdx.y * UP_TT;
+    const int k = skk[a];
+    if (t0 >= k) return;
+    const Node nd = nodes[a];
+    const int nr = ncols[a] - k;
+    const int kl = nd.left >= 0 ? skk[nd.left] : 0;
+    upward_block<RT>(nd, a, k, nr, kl, colperm + (int64_t)a * ncol_max, P + pslot[a], Wt, Wsk, smax, R, r0, r1,
+                     t0, (int32_t *)usm, usm + ncol_max);
+}
+
+// columns per tile of the upward pass for a range of nc columns
+static int upward_tile(int nc) { return nc >= 16 ? 16 : (nc >= 4 ? 4 : 1); }
+
+// LDS of the block form for RT columns and blocks of up to ncol_max columns
+static size_t upward_lds(int RT, int ncol_max) { return sizeof(float) * (size_t)ncol_max * (RT + 2); }
+constexpr size_t UP_LDS_MAX = 64 * 1024;
 
 void prepare_upward(askit_handle *h)
 {
@@ -1148,15 +1312,34 @@ void upward(askit_handle *h, const WeightSet &ws, hipStream_t s, int r0, int r1)
     if (r1 < 0) r1 = ws.R;
     for (auto &sg : h->up_seg) {
         if (sg.second == 0) continue;
-        hipLaunchKernelGGL(k_upward, dim3(sg.second, h->smax), dim3(64), 0, s, h->d_nodes,
-                           h->up_ids + sg.first, h->skk, h->ncols, h->colperm, h->ncol_max, h->d_pslot,
-                           h->P, h->smax, ws.Wt, ws.R, ws.Wsk, r0, r1);
+        const int rt = upward_tile(r1 - r0);
+        const size_t lds = upward_lds(rt, h->ncol_max);
+        const dim3 gb(sg.second, (h->smax + UP_TT - 1) / UP_TT), bb(256);
+        const dim3 g(sg.second, h->smax), b(64);
+        if (rt == 16 && lds <= UP_LDS_MAX)
+            hipLaunchKernelGGL(k_upward_blk<16>, gb, bb, lds, s, h->d_nodes, h->up_ids + sg.first, h->skk,
+                               h->ncols, h->colperm, h->ncol_max, h->d_pslot, h->P, h->smax, ws.Wt, ws.R, ws.Wsk,
+                               r0, r1);
+        else if (rt == 4 && lds <= UP_LDS_MAX)
+            hipLaunchKernelGGL(k_upward_blk<4>, gb, bb, lds, s, h->d_nodes, h->up_ids + sg.first, h->skk,
+                               h->ncols, h->colperm, h->ncol_max, h->d_pslot, h->P, h->smax, ws.Wt, ws.R, ws.Wsk,
+                               r0, r1);
+        else if (rt == 16)
+            hipLaunchKernelGGL(k_upward<16>, g, b, 0, s, h->d_nodes, h->up_ids + sg.first, h->skk, h->ncols,
+                               h->colperm, h->ncol_max, h->d_pslot, h->P, h->smax, ws.Wt, ws.R, ws.Wsk, r0, r1);
+        else if (rt == 4)
+            hipLaunchKernelGGL(k_upward<4>, g, b, 0, s, h->d_nodes, h->up_ids + sg.first, h->skk, h->ncols,
+                               h->colperm, h->ncol_max, h->d_pslot, h->P, h->smax, ws.Wt, ws.R, ws.Wsk, r0, r1);
+        else
+            hipLaunchKernelGGL(k_upward<1>, g, b, 0, s, h->d_nodes, h->up_ids + sg.first, h->skk, h->ncols,
+                               h->colperm, h->ncol_max, h->d_pslot, h->P, h->smax, ws.Wt, ws.R, ws.Wsk, r0, r1);
         HIPC(hipGetLastError());
     }
 }
 
 // Batched upward pass: the same computation as k_upward, one wave per
 // ((instance, node), t) with the instance's tables and weight offsets.
+template <int RT>
 __global__ __launch_bounds__(64) void k_upward_multi(const UpInst *__restrict__ inst,
                                                      const int2 *__restrict__ items, int R,
                                                      const float *__restrict__ Wt_all,
@@ -1164,29 +1347,14 @@ __global__ __launch_bounds__(64) void k_upward_multi(const UpInst *__restrict__ 
 {
     const int2 it = items[blockIdx.x];
     const UpInst &I = inst[it.x];
-    const int a = it.y, t = blockIdx.y, lane = threadIdx.x;
+    const int a = it.y, t = blockIdx.y;
     const int k = I.skk[a];
     if (t >= k) return;
-    const int smax = I.smax;
-    const float *Wt = Wt_all + I.wt_off * R;
-    float *Wsk = Wsk_all + I.wsk_off * R;
     const Node nd = I.nodes[a];
-    const int n = I.ncols[a], nr = n - k;
-    const int32_t *pv = I.colperm + (int64_t)a * I.ncol_max;
-    const float *Pt = I.P + I.pslot[a] + (int64_t)t * nr;
+    const int nr = I.ncols[a] - k;
     const int kl = nd.left >= 0 ? I.skk[nd.left] : 0;
-    auto wc = [&](int c, int r) -> float {
-        if (nd.left < 0) return Wt[(int64_t)(nd.lo + c) * R + r];
-        return c < kl ? Wsk[((int64_t)nd.left * smax + c) * R + r]
-                      : Wsk[((int64_t)nd.right * smax + (c - kl)) * R + r];
-    };
-    for (int r = 0; r < R; ++r) {
-        float acc = 0.0f;
-        for (int c = lane; c < nr; c += 64) acc = fmaf(Pt[c], wc(pv[k + c], r), acc);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) Wsk[((int64_t)a * smax + t) * R + r] = wc(pv[t], r) + acc;
-    }
+    upward_row<RT>(nd, a, t, k, nr, kl, I.colperm + (int64_t)a * I.ncol_max, I.P + I.pslot[a] + (int64_t)t * nr,
+                   Wt_all + I.wt_off * R, Wsk_all + I.wsk_off * R, I.smax, R, 0, R);
 }
 
 void upward_batch(const UpInst *inst, const int2 *items, const std::vector<std::pair<int64_t, int64_t>> &levels,
@@ -1194,8 +1362,17 @@ void upward_batch(const UpInst *inst, const int2 *items, const std::vector<std::
 {
     for (const auto &lv : levels) {
         if (lv.second == 0) continue;
-        hipLaunchKernelGGL(k_upward_multi, dim3((unsigned)lv.second, (unsigned)smax), dim3(64), 0, s, inst,
-                           items + lv.first, R, Wt, Wsk);
+        const dim3 g((unsigned)lv.second, (unsigned)smax), b(64);
+        switch (upward_tile(R)) {
+        case 16:
+            hipLaunchKernelGGL(k_upward_multi<16>, g, b, 0, s, inst, items + lv.first, R, Wt, Wsk);
+            break;
+        case 4:
+            hipLaunchKernelGGL(k_upward_multi<4>, g, b, 0, s, inst, items + lv.first, R, Wt, Wsk);
+            break;
+        default:
+            hipLaunchKernelGGL(k_upward_multi<1>, g, b, 0, s, inst, items + lv.first, R, Wt, Wsk);
+        }
         HIPC(hipGetLastError());
     }
 }

@@ -37,32 +37,42 @@ __device__ __forceinline__ bool better(double d1, int i1, double d2, int i2)
     return d1 > d2 || (d1 == d2 && i1 < i2);
 }
 
-__global__ void k_block_sums(const float *__restrict__ X, int dp, int d,
-                             const int32_t *__restrict__ perm, const Split *__restrict__ sp,
-                             int maxblk, double *__restrict__ bsum)
+// Coordinate sums of each 64-point block of a split (points in the split's
+// order, those past its end counting as zero): lane k holds coordinate k of
+// the block's points (one coalesced row load per point) and reduces them by
+// pairwise halving, v_i + v_(i+o) for o = 32, 16, ..., 1, in registers.
+__global__ __launch_bounds__(64) void k_block_sums(const float *__restrict__ X, int dp, int d,
+                                                   const int32_t *__restrict__ perm,
+                                                   const Split *__restrict__ sp, int maxblk,
+                                                   double *__restrict__ bsum)
 {
-    int b = blockIdx.x, q = blockIdx.y, lane = threadIdx.x;
-    Split s = sp[q];
+    const int b = blockIdx.x, q = blockIdx.y, lane = threadIdx.x;
+    const Split s = sp[q];
     if (b * 64 >= s.n) return;
-    int i = b * 64 + lane;
-    bool ok = i < s.n;
-    const float *x = ok ? X + (int64_t)perm[s.lo + i] * dp : X;
+    const int np = min(64, s.n - b * 64);
+    // rows past the end read a valid row and count as zero
+    const int myid = perm[s.lo + b * 64 + (lane < np ? lane : 0)];
     double *out = bsum + ((int64_t)q * maxblk + b) * d;
-    for (int k0 = 0; k0 < d; k0 += 4) {           // four coordinates per load (rows padded to dp)
-        float4 x4 = {0.f, 0.f, 0.f, 0.f};
-        if (ok) x4 = *reinterpret_cast<const float4 *>(x + k0);
-        const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
+    for (int k0 = 0; k0 < d; k0 += 64) {
+        const int k = k0 + lane;
+        const bool kin = k < d;
+        // unconditional loads (the index clamped inside the padded row) keep
+        // all 64 in flight; lanes past d are masked afterwards
+        const int kc = min(k, dp - 1);
+        float x[64];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (k0 + j >= d) break;
-            double v = (double)xs[j];
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                double w = __shfl_down(v, o);
-                v = v + w;
-            }
-            if (lane == 0) out[k0 + j] = v;
+        for (int i = 0; i < 64; ++i) {
+            const int id = __builtin_amdgcn_readlane(myid, i);
+            x[i] = X[(int64_t)id * dp + kc];
         }
+        double v[64];
+#pragma unroll
+        for (int i = 0; i < 64; ++i) v[i] = (i < np && kin) ? (double)x[i] : 0.0;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+            for (int i = 0; i < o; ++i) v[i] = v[i] + v[i + o];
+        if (kin) out[k] = v[0];
     }
 }
 
@@ -89,45 +99,76 @@ __global__ void k_centroid(const double *__restrict__ bsum, const Split *__restr
     }
 }
 
-// mode 0: D(x, centre); mode 1: D(x, x_ref[q]) (reference given as point id)
-__global__ __launch_bounds__(256) void k_far_partial(const float *__restrict__ X, int dp, int d,
-                                                     const int32_t *__restrict__ perm,
-                                                     const Split *__restrict__ sp,
-                                                     const double *__restrict__ cen,
-                                                     const int32_t *__restrict__ ref, int mode,
-                                                     int nchunk, BestD *__restrict__ part)
+// Rows of 64 points staged through LDS: lane k loads coordinate k of each
+// point (one coalesced row per instruction), so that lane i can then read
+// point i's coordinates in increasing k.  Row stride 65 words: the transposed
+// reads fall in distinct banks.
+constexpr int TR_PAD = 65;
+
+__device__ __forceinline__ void stage_rows(const float *__restrict__ X, int dp, int myid, int k0,
+                                           float *rows)
 {
-    __shared__ double sd[256];
-    __shared__ int si[256];
-    int c = blockIdx.x, q = blockIdx.y, tid = threadIdx.x;
-    Split s = sp[q];
-    int i = c * 256 + tid;
-    double D = -1.0;
-    int id = 0x7fffffff;
-    if (i < s.n) {
-        id = perm[s.lo + i];
-        const float *x = X + (int64_t)id * dp;
-        D = mode == 0 ? canon_sqdist_c(x, cen + (int64_t)q * d, d)
-                      : canon_sqdist(x, X + (int64_t)ref[q] * dp, d);
+    const int lane = threadIdx.x;
+    // unconditional loads (index clamped inside the padded row: all 64 in
+    // flight); coordinates past d are never read back
+    const int kc = min(k0 + lane, dp - 1);
+    float x[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+        const int id = __builtin_amdgcn_readlane(myid, i);
+        x[i] = X[(int64_t)id * dp + kc];
     }
-    sd[tid] = D;
-    si[tid] = id;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o && better(sd[tid + o], si[tid + o], sd[tid], si[tid])) {
-            sd[tid] = sd[tid + o];
-            si[tid] = si[tid + o];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) rows[i * TR_PAD + lane] = x[i];
+}
+
+// Farthest point of each split from a reference, per 64-point chunk: the
+// largest canonical distance D (ties to the smaller id).  mode 0: D(x, the
+// split's centre) (FP64 centre); mode 1: D(x, x_ref[q]).
+__global__ __launch_bounds__(64) void k_far_partial(const float *__restrict__ X, int dp, int d,
+                                                    const int32_t *__restrict__ perm,
+                                                    const Split *__restrict__ sp,
+                                                    const double *__restrict__ cen,
+                                                    const int32_t *__restrict__ ref, int mode,
+                                                    int nchunk, BestD *__restrict__ part)
+{
+#pragma clang fp contract(off)
+    __shared__ float rows[64 * TR_PAD];
+    __shared__ double rv[64];
+    const int c = blockIdx.x, q = blockIdx.y, lane = threadIdx.x;
+    const Split s = sp[q];
+    if (c * 64 >= s.n) return;
+    const int np = min(64, s.n - c * 64);
+    const int myid = perm[s.lo + c * 64 + (lane < np ? lane : 0)];
+    const float *xr = mode == 0 ? nullptr : X + (int64_t)ref[q] * dp;
+    double D = 0.0;
+    for (int k0 = 0; k0 < d; k0 += 64) {
+        const int k = k0 + lane;
+        rv[lane] = k < d ? (mode == 0 ? cen[(int64_t)q * d + k] : (double)xr[k]) : 0.0;
+        stage_rows(X, dp, myid, k0, rows);
+        __syncthreads();
+        const int kn = min(64, d - k0);
+        for (int j = 0; j < kn; ++j) {
+            const double t = (double)rows[lane * TR_PAD + j] - rv[j];
+            D += t * t;
         }
         __syncthreads();
     }
-    if (tid == 0) part[(int64_t)q * nchunk + c] = BestD{sd[0], si[0], 0};
+    double bd = lane < np ? D : -1.0;
+    int bi = lane < np ? myid : 0x7fffffff;
+    for (int o = 32; o > 0; o >>= 1) {
+        const double od = __shfl_xor(bd, o);
+        const int oi = __shfl_xor(bi, o);
+        if (better(od, oi, bd, bi)) { bd = od; bi = oi; }
+    }
+    if (lane == 0) part[(int64_t)q * nchunk + c] = BestD{bd, bi, 0};
 }
 
 __global__ void k_far_final(const BestD *__restrict__ part, const Split *__restrict__ sp, int nchunk,
                             int32_t *__restrict__ out)
 {
     int q = blockIdx.x, lane = threadIdx.x;
-    int nc = (sp[q].n + 255) / 256;
+    int nc = (sp[q].n + 63) / 64;
     double bd = -1.0;
     int bi = 0x7fffffff;
     for (int c = lane; c < nc; c += 64) {
@@ -142,39 +183,40 @@ __global__ void k_far_final(const BestD *__restrict__ part, const Split *__restr
     if (lane == 0) out[q] = bi;
 }
 
-__global__ void k_project(const float *__restrict__ X, int dp, int d, const int32_t *__restrict__ perm,
-                          const Split *__restrict__ sp, const int32_t *__restrict__ L,
-                          const int32_t *__restrict__ Rr, uint64_t *__restrict__ key)
+// Split key of every point: p = (x - x_l) . (x_r - x_l) in FP64, k increasing,
+// per 64-point chunk (rows staged as above).
+__global__ __launch_bounds__(64) void k_project(const float *__restrict__ X, int dp, int d,
+                                                const int32_t *__restrict__ perm,
+                                                const Split *__restrict__ sp, const int32_t *__restrict__ L,
+                                                const int32_t *__restrict__ Rr, uint64_t *__restrict__ key)
 {
 #pragma clang fp contract(off)
-    int c = blockIdx.x, q = blockIdx.y;
-    Split s = sp[q];
-    int i = c * 256 + threadIdx.x;
-    if (i >= s.n) return;
-    const float *x = X + (int64_t)perm[s.lo + i] * dp;
+    __shared__ float rows[64 * TR_PAD];
+    __shared__ double lv[64], bv[64];
+    const int c = blockIdx.x, q = blockIdx.y, lane = threadIdx.x;
+    const Split s = sp[q];
+    if (c * 64 >= s.n) return;
+    const int np = min(64, s.n - c * 64);
+    const int myid = perm[s.lo + c * 64 + (lane < np ? lane : 0)];
     const float *xl = X + (int64_t)L[q] * dp;
     const float *xr = X + (int64_t)Rr[q] * dp;
     double acc = 0.0;
-    int k = 0;
-    for (; k + 4 <= d; k += 4) {                  // rows are 16-byte aligned; k stays in order
-        const float4 x4 = *reinterpret_cast<const float4 *>(x + k);
-        const float4 l4 = *reinterpret_cast<const float4 *>(xl + k);
-        const float4 r4 = *reinterpret_cast<const float4 *>(xr + k);
-        const float xs[4] = {x4.x, x4.y, x4.z, x4.w}, ls[4] = {l4.x, l4.y, l4.z, l4.w};
-        const float rs[4] = {r4.x, r4.y, r4.z, r4.w};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            double a = (double)xs[j] - (double)ls[j];
-            double b = (double)rs[j] - (double)ls[j];
-            acc += a * b;
+    for (int k0 = 0; k0 < d; k0 += 64) {
+        const int k = k0 + lane;
+        if (k < d) {
+            lv[lane] = (double)xl[k];
+            bv[lane] = (double)xr[k] - (double)xl[k];
         }
+        stage_rows(X, dp, myid, k0, rows);
+        __syncthreads();
+        const int kn = min(64, d - k0);
+        for (int j = 0; j < kn; ++j) {
+            const double a = (double)rows[lane * TR_PAD + j] - lv[j];
+            acc += a * bv[j];
+        }
+        __syncthreads();
     }
-    for (; k < d; ++k) {
-        double a = (double)x[k] - (double)xl[k];
-        double b = (double)xr[k] - (double)xl[k];
-        acc += a * b;
-    }
-    key[s.lo + i] = dkey(acc);
+    if (lane < np) key[s.lo + c * 64 + lane] = dkey(acc);
 }
 
 // Radix select state per split: prefix of the pivot key, remaining rank.
@@ -203,23 +245,42 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t *__restrict__
     if (lh[tid]) atomicAdd(&hist[q * 256 + tid], lh[tid]);
 }
 
-__global__ void k_radix_pick(uint32_t *__restrict__ hist, Sel *__restrict__ sel, int nsp, int shift)
+// The digit of each split's median key, one wave per split: the 256 bins'
+// counts, an exclusive prefix across the wave, and the first bin whose
+// cumulative count passes the remaining rank; the histogram is cleared.
+__global__ __launch_bounds__(64) void k_radix_pick(uint32_t *__restrict__ hist, Sel *__restrict__ sel, int nsp,
+                                                   int shift)
 {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.x, lane = threadIdx.x;
     if (q >= nsp) return;
-    Sel st = sel[q];
-    int64_t cum = 0;
-    for (int dg = 0; dg < 256; ++dg) {
-        int64_t c = hist[q * 256 + dg];
-        if (cum + c > st.krem) {
-            st.prefix |= (uint64_t)dg << shift;
-            st.krem -= cum;
-            break;
-        }
-        cum += c;
+    uint4 *hq = reinterpret_cast<uint4 *>(hist + (int64_t)q * 256);
+    const uint4 c4 = hq[lane];                    // bins 4 lane .. 4 lane + 3
+    const uint32_t cs[4] = {c4.x, c4.y, c4.z, c4.w};
+    const uint32_t tot = cs[0] + cs[1] + cs[2] + cs[3];
+    uint32_t inc = tot;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(inc, o);
+        if (lane >= o) inc += v;
     }
-    for (int dg = 0; dg < 256; ++dg) hist[q * 256 + dg] = 0;
-    sel[q] = st;
+    Sel st = sel[q];
+    int64_t cum = (int64_t)(inc - tot);
+    int dg = -1;
+    int below = 0;
+    for (int j = 0; j < 4; ++j) {
+        if (dg < 0 && cum + cs[j] > st.krem) {
+            dg = 4 * lane + j;
+            below = (int)cum;
+        }
+        cum += cs[j];
+    }
+    const unsigned long long hit = __ballot(dg >= 0);
+    if (hit) {
+        const int src = __ffsll(hit) - 1;
+        st.prefix |= (uint64_t)__shfl(dg, src) << shift;
+        st.krem -= __shfl(below, src);
+    }
+    hq[lane] = make_uint4(0u, 0u, 0u, 0u);
+    if (lane == 0) sel[q] = st;
 }
 
 struct PartCnt {
@@ -272,18 +333,30 @@ __global__ __launch_bounds__(256) void k_part_count(const uint64_t *__restrict__
     if (tid == 0) cnt[(int64_t)q * nchunk + c] = PartCnt{tl, te};
 }
 
-__global__ void k_part_scan(PartCnt *__restrict__ cnt, const Split *__restrict__ sp, int nsp,
-                            int nchunk)
+// Exclusive prefix of the chunks' (less, equal) counts of each split, one
+// wave per split, 64 chunks at a time.
+__global__ __launch_bounds__(64) void k_part_scan(PartCnt *__restrict__ cnt, const Split *__restrict__ sp, int nsp,
+                                                  int nchunk)
 {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.x, lane = threadIdx.x;
     if (q >= nsp) return;
-    int nc = (sp[q].n + 255) / 256;
+    const int nc = (sp[q].n + 255) / 256;
+    PartCnt *cq = cnt + (int64_t)q * nchunk;
     int al = 0, ae = 0;
-    for (int c = 0; c < nc; ++c) {
-        PartCnt v = cnt[(int64_t)q * nchunk + c];
-        cnt[(int64_t)q * nchunk + c] = PartCnt{al, ae};
-        al += v.less;
-        ae += v.eq;
+    for (int c0 = 0; c0 < nc; c0 += 64) {
+        const int c = c0 + lane;
+        const PartCnt v = c < nc ? cq[c] : PartCnt{0, 0};
+        int il = v.less, ie = v.eq;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int a = __shfl_up(il, o), b = __shfl_up(ie, o);
+            if (lane >= o) {
+                il += a;
+                ie += b;
+            }
+        }
+        if (c < nc) cq[c] = PartCnt{al + il - v.less, ae + ie - v.eq};
+        al += __shfl(il, 63);
+        ae += __shfl(ie, 63);
     }
 }
 
@@ -345,10 +418,10 @@ static void median_split(const uint64_t *key, const Split *d_sp, int nsp, int ma
     for (int pass = 0; pass < 8; ++pass) {
         int shift = 56 - 8 * pass;
         hipLaunchKernelGGL(k_radix_hist, dim3(hchunk, nsp), dim3(256), 0, s, key, d_sp, sel, shift, hist);
-        hipLaunchKernelGGL(k_radix_pick, dim3((nsp + 63) / 64), dim3(64), 0, s, hist, sel, nsp, shift);
+        hipLaunchKernelGGL(k_radix_pick, dim3(nsp), dim3(64), 0, s, hist, sel, nsp, shift);
     }
     hipLaunchKernelGGL(k_part_count, dim3(nchunk, nsp), dim3(256), 0, s, key, d_sp, sel, nchunk, pc);
-    hipLaunchKernelGGL(k_part_scan, dim3((nsp + 63) / 64), dim3(64), 0, s, pc, d_sp, nsp, nchunk);
+    hipLaunchKernelGGL(k_part_scan, dim3(nsp), dim3(64), 0, s, pc, d_sp, nsp, nchunk);
     HIPC(hipMemcpyAsync(pout, perm, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_part_scatter, dim3(nchunk, nsp), dim3(256), 0, s, key, perm, d_sp, sel, nchunk, pc,
                        pout);
@@ -357,15 +430,34 @@ static void median_split(const uint64_t *key, const Split *d_sp, int nsp, int ma
 }
 
 // Splits every node of each level (host split tables, one vector per level,
-// top-down) by the tree rule, permuting perm in place.
+// top-down) by the tree rule, permuting perm in place.  Every level's table
+// is uploaded once; the levels then run back to back on the stream.
 static void run_split_levels(const askit_handle *h, int32_t *perm, const std::vector<std::vector<Split>> &levels,
                              hipStream_t s)
 {
     const int64_t N = h->N;
     const int d = h->d, dp = h->dp;
-    int64_t maxsp = 1;
-    for (auto &lv : levels) maxsp = std::max<int64_t>(maxsp, (int64_t)lv.size());
-    int64_t blk_total = (N + 63) / 64 + 2 * maxsp;       // 64-point blocks over one level
+    std::vector<Split> all_sp;
+    std::vector<Sel> all_sel;
+    std::vector<size_t> off;
+    std::vector<int> lmaxn;
+    int64_t maxsp = 1, blk_total = 1, part_total = 1, pc_total = 1;
+    for (const auto &lv : levels) {
+        off.push_back(all_sp.size());
+        int maxn = 0;
+        for (const Split &sp : lv) {
+            all_sp.push_back(sp);
+            all_sel.push_back(Sel{0ull, (int64_t)((sp.n + 1) / 2 - 1)});
+            maxn = std::max(maxn, (int)sp.n);
+        }
+        lmaxn.push_back(maxn);
+        const int64_t nsp = (int64_t)lv.size();
+        maxsp = std::max(maxsp, nsp);
+        blk_total = std::max(blk_total, nsp * ((maxn + 63) / 64));
+        part_total = std::max(part_total, nsp * ((maxn + 63) / 64));
+        pc_total = std::max(pc_total, nsp * ((maxn + 255) / 256));
+    }
+    if (all_sp.empty()) return;
     std::vector<void *> tmp;
     struct Guard {
         std::vector<void *> &t;
@@ -378,47 +470,42 @@ static void run_split_levels(const askit_handle *h, int32_t *perm, const std::ve
         tmp.push_back(p);
         return p;
     };
-    Split *d_sp = (Split *)talloc(sizeof(Split) * maxsp);
+    Split *d_sp = (Split *)talloc(sizeof(Split) * all_sp.size());
+    Sel *sel = (Sel *)talloc(sizeof(Sel) * all_sel.size());
     double *bsum = (double *)talloc(sizeof(double) * blk_total * d + 64);
     double *cen = (double *)talloc(sizeof(double) * maxsp * d);
-    int64_t chunk_total = (N + 255) / 256 + 2 * maxsp;
-    BestD *part = (BestD *)talloc(sizeof(BestD) * chunk_total);
+    BestD *part = (BestD *)talloc(sizeof(BestD) * part_total);
     int32_t *L = (int32_t *)talloc(sizeof(int32_t) * maxsp);
     int32_t *Rr = (int32_t *)talloc(sizeof(int32_t) * maxsp);
     uint64_t *key = (uint64_t *)talloc(sizeof(uint64_t) * N);
-    Sel *sel = (Sel *)talloc(sizeof(Sel) * maxsp);
     uint32_t *hist = (uint32_t *)talloc(sizeof(uint32_t) * 256 * maxsp);
-    PartCnt *pc = (PartCnt *)talloc(sizeof(PartCnt) * chunk_total);
+    PartCnt *pc = (PartCnt *)talloc(sizeof(PartCnt) * pc_total);
     int32_t *pout = (int32_t *)talloc(sizeof(int32_t) * N);
     HIPC(hipMemsetAsync(hist, 0, sizeof(uint32_t) * 256 * maxsp, s));
+    HIPC(hipMemcpyAsync(d_sp, all_sp.data(), sizeof(Split) * all_sp.size(), hipMemcpyHostToDevice, s));
+    HIPC(hipMemcpyAsync(sel, all_sel.data(), sizeof(Sel) * all_sel.size(), hipMemcpyHostToDevice, s));
+    HIPC(hipStreamSynchronize(s));              // the host tables are released on return
 
-    std::vector<Sel> hsel;
-    for (const auto &hsp : levels) {
-        const int nsp = (int)hsp.size();
+    for (size_t l = 0; l < levels.size(); ++l) {
+        const int nsp = (int)levels[l].size();
         if (nsp == 0) continue;
-        hsel.clear();
-        int maxn = 0;
-        for (const Split &sp : hsp) {
-            hsel.push_back(Sel{0ull, (int64_t)((sp.n + 1) / 2 - 1)});
-            maxn = std::max(maxn, (int)sp.n);
-        }
-        HIPC(hipMemcpyAsync(d_sp, hsp.data(), sizeof(Split) * nsp, hipMemcpyHostToDevice, s));
-        HIPC(hipMemcpyAsync(sel, hsel.data(), sizeof(Sel) * nsp, hipMemcpyHostToDevice, s));
-        int maxblk = (maxn + 63) / 64;
-        int nchunk = (maxn + 255) / 256;
-        hipLaunchKernelGGL(k_block_sums, dim3(maxblk, nsp), dim3(64), 0, s, h->Xo, dp, d, perm, d_sp, maxblk,
+        const Split *lsp = d_sp + off[l];
+        Sel *lsel = sel + off[l];
+        const int maxn = lmaxn[l];
+        const int maxblk = (maxn + 63) / 64;
+        const int nch = (maxn + 63) / 64;
+        hipLaunchKernelGGL(k_block_sums, dim3(maxblk, nsp), dim3(64), 0, s, h->Xo, dp, d, perm, lsp, maxblk,
                            bsum);
-        hipLaunchKernelGGL(k_centroid, dim3(nsp), dim3(std::min(256, round_up(d, 64))), 0, s, bsum, d_sp, maxblk,
+        hipLaunchKernelGGL(k_centroid, dim3(nsp), dim3(std::min(256, round_up(d, 64))), 0, s, bsum, lsp, maxblk,
                            d, cen);
-        hipLaunchKernelGGL(k_far_partial, dim3(nchunk, nsp), dim3(256), 0, s, h->Xo, dp, d, perm, d_sp, cen,
-                           (const int32_t *)nullptr, 0, nchunk, part);
-        hipLaunchKernelGGL(k_far_final, dim3(nsp), dim3(64), 0, s, part, d_sp, nchunk, L);
-        hipLaunchKernelGGL(k_far_partial, dim3(nchunk, nsp), dim3(256), 0, s, h->Xo, dp, d, perm, d_sp, cen, L, 1,
-                           nchunk, part);
-        hipLaunchKernelGGL(k_far_final, dim3(nsp), dim3(64), 0, s, part, d_sp, nchunk, Rr);
-        hipLaunchKernelGGL(k_project, dim3(nchunk, nsp), dim3(256), 0, s, h->Xo, dp, d, perm, d_sp, L, Rr, key);
-        median_split(key, d_sp, nsp, maxn, sel, hist, pc, perm, pout, N, s);
-        HIPC(hipStreamSynchronize(s));          // the host tables are reused by the next level
+        hipLaunchKernelGGL(k_far_partial, dim3(nch, nsp), dim3(64), 0, s, h->Xo, dp, d, perm, lsp, cen,
+                           (const int32_t *)nullptr, 0, nch, part);
+        hipLaunchKernelGGL(k_far_final, dim3(nsp), dim3(64), 0, s, part, lsp, nch, L);
+        hipLaunchKernelGGL(k_far_partial, dim3(nch, nsp), dim3(64), 0, s, h->Xo, dp, d, perm, lsp, cen, L, 1,
+                           nch, part);
+        hipLaunchKernelGGL(k_far_final, dim3(nsp), dim3(64), 0, s, part, lsp, nch, Rr);
+        hipLaunchKernelGGL(k_project, dim3(nch, nsp), dim3(64), 0, s, h->Xo, dp, d, perm, lsp, L, Rr, key);
+        median_split(key, lsp, nsp, maxn, lsel, hist, pc, perm, pout, N, s);
     }
 }
 
