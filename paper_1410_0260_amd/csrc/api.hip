@@ -196,7 +196,7 @@ static void query_knn(askit_handle *h, const float *Y, int64_t M, int64_t ldy, f
     HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
     split_bf16(Yp, M, dp, Yh, Yl, Yn, s);
     knn_candidates(Yh, Yl, Yn, M, h->Xh, h->Xl, h->Xn, h->N, dp, false, false, cand, thr, flag + 1,
-                   flag, s, nullptr, nullptr, nullptr, &h->ksamp);
+                   flag, s, nullptr, nullptr, nullptr, &h->ksamp, nullptr, nullptr, 0, nullptr, knn_nsel(kappa));
     float *tb = (float *)ta(sizeof(float) * M);
     knn_refine(Yp, M, h->Xt, h->N, h->d, dp, kappa, cand, thr, Yn, h->maxnorm, h->perm, nullptr, qidx,
                qd, flag + 1, flag, tb, s);
@@ -547,7 +547,7 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
         float fms = 0.f;
         knn_candidates(Xh_f, Xl_f, Xn_f, N, Xh_f, Xl_f, Xn_f, N, dp, true, true, cand, thr,
                        bad + 1, bad, s, &fms, &h->knn_filter_launches, &h->knn_retry_rows, &h->ksamp,
-                       &h->knn_retry_list, Xt_f, d, &h->knn_tiles_swept);
+                       &h->knn_retry_list, Xt_f, d, &h->knn_tiles_swept, knn_nsel(kappa));
         h->t_knn_filter = fms;
         HIPC(hipEventRecord(k1, s));
         if (fine && !h->knn_retry_list.empty()) {

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <functional>
 #include <mutex>
@@ -242,7 +243,13 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
                     int32_t *bad_rows, int32_t *bad_count, hipStream_t s,
                     float *t_filter_ms = nullptr, int *n_filter = nullptr, int *n_retry = nullptr,
                     const KnnSample *samp = nullptr, std::vector<int32_t> *retry_rows = nullptr,
-                    const float *Xf = nullptr, int d = 0, int64_t *tiles_swept = nullptr);
+                    const float *Xf = nullptr, int d = 0, int64_t *tiles_swept = nullptr,
+                    int nsel = KNN_CAND);
+// Candidates the threshold filter keeps per row for kappa neighbours: enough
+// above kappa that the FP64 certificate (the kappa-th exact distance below the
+// nsel-th approximate one, less the error bound) holds for most rows, and no
+// more, since the threshold sets how many points survive the filter.
+inline int knn_nsel(int kappa) { return std::min(KNN_CAND, kappa + std::max(16, kappa / 2)); }
 // Fills h->ksamp from the tree-ordered bf16 points when the point set is large
 // enough for the sampled query search (allocations owned by the handle).
 void knn_build_sample(askit_handle *h, hipStream_t s);

@@ -7,10 +7,14 @@
 //      the dot product as bf16 hi/lo split products (hi*hi + hi*lo + lo*hi)
 //      on MFMA 32x32x16 with FP32 accumulation; each query row keeps its 64
 //      smallest approximate distances in a wave-wide sorted list.
-//   2. k_knn_refine: exact FP64 distances of the 64 candidates, sorted by
+//   2. k_knn_refine: exact FP64 distances of the candidates, sorted by
 //      (D, j); the row is certified when the kappa-th exact distance is
-//      below (64th approximate distance - E), E a bound on the
-//      approximation error, so no point outside the candidates can enter.
+//      below (the threshold - E), E a bound on the approximation error and
+//      every point outside the candidates at or above the threshold in
+//      approximate distance, so none of them can enter.
+//   The threshold filter (k_knn_filter + k_knn_select) keeps nsel <= 64
+//   candidates per row (knn_nsel: a margin above kappa) with the nsel-th
+//   approximate distance as threshold; the list sweeps keep 64.
 //   3. k_knn_exact: full FP64 scan for the rows that are not certified.
 #include "askit_impl.h"
 
@@ -822,10 +826,10 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     }
 }
 
-// Per row (one wave): the 64 smallest (approximate distance, position) of the
-// filter's output, as candidates + the certificate threshold.  Rows whose
+// Per row (one wave): the nsel smallest (approximate distance, position) of
+// the filter's output, as candidates + the certificate threshold.  Rows whose
 // segment overflowed are listed for the retry sweep (when bad_count is given).
-// The 64th smallest distance is found by a radix selection on an
+// The nsel-th smallest distance is found by a radix selection on an
 // order-preserving image of the FP32 values (four 8-bit digits, a histogram
 // per wave in LDS); the candidates are every stored entry below it and, among
 // those equal to it, the ones with the smallest positions.  Candidates are
@@ -843,7 +847,7 @@ __device__ __forceinline__ float key2f(uint32_t k)
     return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
-__global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int cap,
+__global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int cap, int nsel,
                                                     const int32_t *__restrict__ ocnt,
                                                     const float *__restrict__ od,
                                                     const int32_t *__restrict__ oi,
@@ -867,16 +871,16 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
     const float *rd = od + lrow * cap;
     const int32_t *ri = oi + lrow * cap;
     int32_t *co = cand + row * KNN_CAND;
-    if (nk <= KNN_CAND) {
+    if (nk <= nsel) {
         // every stored entry is a candidate
         co[lane] = lane < nk ? ri[lane] : -1;
         float m = -INFINITY;
-        if (nk == KNN_CAND) {
+        if (nk == nsel) {
             m = lane < nk ? rd[lane] : -INFINITY;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
         }
-        if (lane == 0) thr[row] = n > cap ? m + fabsf(m) * 1e-5f + 1e-30f : (n >= KNN_CAND ? m : tin);
+        if (lane == 0) thr[row] = n > cap ? m + fabsf(m) * 1e-5f + 1e-30f : (n >= nsel ? m : tin);
         return;
     }
     // keys and ids of the stored entries; the loads are unconditional (index
@@ -892,9 +896,9 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
     uint32_t key[SEL_Q];
 #pragma unroll
     for (int q = 0; q < SEL_Q; ++q) key[q] = lane + WAVE * q < nk ? f2key(kv[q]) : 0xffffffffu;
-    // the KNN_CAND-th smallest key, one 8-bit digit at a time
+    // the nsel-th smallest key, one 8-bit digit at a time
     uint32_t prefix = 0, pmask = 0;
-    int kk = KNN_CAND;                   // rank sought among the keys matching prefix
+    int kk = nsel;                       // rank sought among the keys matching prefix
     int *hw = hist[wv];
 #pragma unroll 1
     for (int shift = 24; shift >= 0; shift -= 8) {
@@ -935,10 +939,11 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
         pmask |= 255u << shift;
         __builtin_amdgcn_wave_barrier();
     }
-    const uint32_t K = prefix;           // kk of the keys equal to K complete the 64
+    const uint32_t K = prefix;           // kk of the keys equal to K complete the nsel
     // the winners' entry positions go to a per-wave list in LDS (the
-    // histogram's space), then each lane loads one id: entries below K (64 -
-    // kk of them), then the kk equal ones with the smallest positions
+    // histogram's space), then each lane loads one id: entries below K (nsel
+    // - kk of them), then the kk equal ones with the smallest positions;
+    // lanes from nsel on hold no candidate
     int *slot = hw;
     int base = 0;
 #pragma unroll
@@ -982,9 +987,10 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
     }
     __builtin_amdgcn_wave_barrier();
     if (lane < nslot) co[lane] = ri[slot[lane]];
-    // bound for the points outside the candidates: the 64th survivor.  A row
-    // whose segment overflowed is swept again; the 64th of its stored
-    // survivors (real distances, so at least its 64th smallest), widened as
+    else if (lane >= nsel) co[lane] = -1;
+    // bound for the points outside the candidates: the nsel-th survivor.  A
+    // row whose segment overflowed is swept again; the nsel-th of its stored
+    // survivors (real distances, so at least its nsel-th smallest), widened as
     // the window threshold, starts that sweep.
     const float th = key2f(K);
     if (lane == 0) thr[row] = n > cap ? th + fabsf(th) * 1e-5f + 1e-30f : th;
@@ -1094,6 +1100,7 @@ constexpr int64_t KNN_CHUNK = 1 << 20;      // query rows per filter pass (bound
 struct FilterBufs {
     int32_t *ocnt = nullptr, *oi = nullptr;
     float *od = nullptr;
+    int nsel = KNN_CAND;                      // candidates the selection keeps per row
 };
 
 // Threshold filter of rows [0, M) against a reference set, in passes of
@@ -1122,8 +1129,8 @@ static void filter_select(int dp, hipStream_t s, const uint16_t *Qh, const uint1
         KNN_DISPATCH(launch_filter, g, dim3(256), s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, KNN_CAP, B.ocnt,
                      B.od, B.oi, sym, win, tlist, toff, items);
         if (ev) HIPC(hipEventRecord(ev->back(), s));
-        hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, KNN_CAP, B.ocnt,
-                           B.od, B.oi, cand, thr, over ? over + 1 : nullptr, over);
+        hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, KNN_CAP, B.nsel,
+                           B.ocnt, B.od, B.oi, cand, thr, over ? over + 1 : nullptr, over);
         HIPC(hipGetLastError());
     }
 }
@@ -1136,10 +1143,10 @@ static void widen(float *thr, int64_t M, hipStream_t s)
 
 // Thresholds from the nested strided samples for rows [0, M): every point of
 // the coarsest sample (at most KNN_CAP) passes the filter at +inf; at each
-// level the 64th smallest survivor bounds the row's 64th smallest distance
-// over the whole set (an upper bound: those 64 are real points), and the next,
-// 8 times denser, level (a superset) keeps at least those 64 at that bound --
-// about 512 points.  Each step only lowers a valid bound.  The sample passes'
+// level the nsel-th smallest survivor bounds the row's nsel-th smallest
+// distance over the whole set (an upper bound: those are real points), and the
+// next, 8 times denser, level (a superset) keeps at least those nsel at that
+// bound -- about 8 nsel points.  Each step only lowers a valid bound.  The sample passes'
 // candidate lists (in cand) are scratch; thr leaves widened.  No self
 // exclusion: a row that is itself a sample point may count itself.
 static void sample_thresholds(int dp, hipStream_t s, const uint16_t *Qh, const uint16_t *Ql, const float *Qn,
@@ -1427,7 +1434,7 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
                     bool exclude_self, bool start_local, int32_t *cand, float *thr,
                     int32_t *bad_rows, int32_t *bad_count, hipStream_t s, float *t_filter_ms,
                     int *n_filter, int *n_retry, const KnnSample *samp, std::vector<int32_t> *retry_rows,
-                    const float *Xf, int d, int64_t *tiles_swept)
+                    const float *Xf, int d, int64_t *tiles_swept, int nsel)
 {
     if (retry_rows) retry_rows->clear();
     if (tiles_swept) *tiles_swept = -1;
@@ -1458,6 +1465,7 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     const int64_t chunk = sym ? M : KNN_CHUNK;
     const int64_t mc = std::min<int64_t>(M, chunk);
     FilterBufs B;
+    B.nsel = std::max(1, std::min(nsel, KNN_CAND));
     int32_t *retry, *over;
     HIPC(hipMallocAsync((void **)&B.ocnt, sizeof(int32_t) * mc, s));
     HIPC(hipMallocAsync((void **)&B.od, sizeof(float) * mc * KNN_CAP, s));
@@ -1469,13 +1477,13 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     if (sampled) {
         sample_thresholds(dp, s, Qh, Ql, Qn, M, *samp, chunk, thr, B, cand);
     } else {
-        // window threshold: thr = 64th approximate distance among the 4096
+        // window threshold: thr = nsel-th approximate distance among the 4096
         // tree-order neighbours of the row's block, in three steps with the
-        // same arithmetic: the 64th of the block's own two tiles (every point
-        // passes at +inf) bounds it; the threshold filter over the window at
-        // that bound keeps every closer point (so at least those 64); their
-        // 64th is the exact window value (or a bound, when more than the
-        // capacity survive)
+        // same arithmetic: the nsel-th of the block's own two tiles (every
+        // point passes at +inf) bounds it; the threshold filter over the
+        // window at that bound keeps every closer point (so at least those
+        // nsel); their nsel-th is the exact window value (or a bound, when
+        // more than the capacity survive)
         hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M, INFINITY);
         filter_select(dp, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, chunk, thr, B, cand, nullptr, false, 2, nullptr);
         widen(thr, M, s);
@@ -1991,6 +1999,9 @@ void knn_fallback(const float *Q, const uint16_t *Qh, const uint16_t *Ql, const 
         hipLaunchKernelGGL(k_knn_filter_wide, g, block, 0, s, Bh, Bl, Bn, n, Xh, Xl, Xn, N, dp, Bt, FCAP, ocnt,
                            od, oi);
     } else {
+        // few rows: the points are split into column segments, one workgroup
+        // each, appending to the rows' common outputs
+        g.y = (unsigned)filter_segments(n, (N + KB_N - 1) / KB_N);
         KNN_DISPATCH(launch_filter, g, block, s, Bh, Bl, Bn, n, Xh, Xl, Xn, N, 0, 0, Bt, FCAP, ocnt, od, oi,
                      false);
     }
