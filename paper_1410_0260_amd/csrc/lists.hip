@@ -127,25 +127,41 @@ __global__ __launch_bounds__(NL_T) void k_leaf_nlists(const Node *__restrict__ n
     const int a = leaves[blockIdx.x];
     const Node nd = nodes[a];
     const int chunk = max(1, (NL_CAP - ell) / kappa);
+    // Once the reduced list holds ell entries its ell-th (key, position) bounds
+    // the final ell-th from above (more entries only lower a position's key or
+    // add positions), so entries at or above it are dropped when read; the
+    // buffer is reduced only when the next chunk might not fit, and at the end.
+    uint64_t tk = ~0ull;
+    int32_t tp = 0x7fffffff;
     int cur = 0;
+    if (threadIdx.x == 0) S.cnt = 0;
+    __syncthreads();
     for (int c0 = nd.lo; c0 < nd.hi; c0 += chunk) {
-        int c1 = min(nd.hi, c0 + chunk);
-        if (threadIdx.x == 0) S.cnt = cur;
-        __syncthreads();
-        int tot = (c1 - c0) * kappa;
+        const int c1 = min(nd.hi, c0 + chunk);
+        const int tot = (c1 - c0) * kappa;
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-            int i = c0 + e / kappa, t = e % kappa;
-            int64_t o = perm[i];
-            int pj = iperm[knn_idx[o * kappa + t]];
+            const int i = c0 + e / kappa, t = e % kappa;
+            const int64_t o = perm[i];
+            const int pj = iperm[knn_idx[o * kappa + t]];
             if (pj >= nd.lo && pj < nd.hi) continue;
-            int slot = atomicAdd(&S.cnt, 1);
+            const uint64_t key = (uint64_t)__double_as_longlong(knn_d[o * kappa + t]);
+            if (!lt_kp(key, pj, tk, tp)) continue;
+            const int slot = atomicAdd(&S.cnt, 1);
             S.p[0][slot] = pj;
-            S.k[0][slot] = (uint64_t)__double_as_longlong(knn_d[o * kappa + t]);
+            S.k[0][slot] = key;
         }
         __syncthreads();
-        int n = S.cnt;
+        const int n = S.cnt;
         __syncthreads();
-        cur = reduce_list(S, n, ell);
+        if (c1 >= nd.hi || n + chunk * kappa > NL_CAP) {
+            cur = reduce_list(S, n, ell);
+            if (cur == ell) {
+                tk = S.k[0][ell - 1];
+                tp = S.p[0][ell - 1];
+            }
+            if (threadIdx.x == 0) S.cnt = cur;
+            __syncthreads();
+        }
     }
     for (int t = threadIdx.x; t < cur; t += blockDim.x) {
         nl_pos[(int64_t)a * ell + t] = S.p[0][t];
