@@ -605,54 +605,83 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
     // need the tree and the neighbours, not the skeletons, so a helper thread
     // builds them on a second stream while this one builds node lists, sampled
     // rows and skeletons
-    hipStream_t s2 = nullptr;
-    hipEvent_t ei[2] = {nullptr, nullptr};
-    HIPC(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
-    HIPC(hipEventCreate(&ei[0]));
-    HIPC(hipEventCreate(&ei[1]));
-    HIPC(hipStreamWaitEvent(s2, ev[2], 0));
-    std::exception_ptr ierr;
-    askit_handle *hp = h.get();
-    std::thread ith([&, hp]() {
-        try {
-            HIPC(hipSetDevice(hp->device));
-            HIPC(hipEventRecord(ei[0], s2));
-            build_interactions(hp, s2);
-            build_pairs(hp, hp->d_slabs, (int64_t)hp->slabs.size(), N, hp->sl_ptr, hp->sl_node, hp->sl_mask,
-                        hp->near_entries, hp->far_entries, hp->pairs,
-                        [hp](size_t b) { return hp->alloc(b, false); }, s2);
-            HIPC(hipEventRecord(ei[1], s2));
-            HIPC(hipStreamSynchronize(s2));
-        } catch (...) {
-            ierr = std::current_exception();
-        }
-    });
-    struct Join {
-        std::thread &t;
-        hipStream_t s2;
-        hipEvent_t *e;
-        ~Join()
-        {
-            if (t.joinable()) t.join();
-            (void)hipStreamSynchronize(s2);
-            (void)hipStreamDestroy(s2);
-            (void)hipEventDestroy(e[0]);
-            (void)hipEventDestroy(e[1]);
-        }
-    };
     float ms_inter = 0.f;
-    {
-        Join jn{ith, s2, ei};
-        // ---- node lists and sampled rows
+    if (defer_skel) {
+        // a setup whose skeletons are built later (the batched form): the
+        // lists follow on the same stream (no helper stream and thread per
+        // instance; the instances' setups overlap each other instead)
+        hipEvent_t ei[2] = {nullptr, nullptr};
+        HIPC(hipEventCreate(&ei[0]));
+        HIPC(hipEventCreate(&ei[1]));
+        struct EvFree {
+            hipEvent_t *e;
+            ~EvFree()
+            {
+                (void)hipEventDestroy(e[0]);
+                (void)hipEventDestroy(e[1]);
+            }
+        } evf{ei};
         build_node_lists(h.get(), s);
         sample_rows(h.get(), s);
         HIPC(hipEventRecord(ev[3], s));
-        // ---- skeletons
-        if (!defer_skel) skeletonize(h.get(), s);
         HIPC(hipEventRecord(ev[4], s));
-        ith.join();
-        if (ierr) std::rethrow_exception(ierr);
+        askit_handle *hp = h.get();
+        HIPC(hipEventRecord(ei[0], s));
+        build_interactions(hp, s);
+        build_pairs(hp, hp->d_slabs, (int64_t)hp->slabs.size(), N, hp->sl_ptr, hp->sl_node, hp->sl_mask,
+                    hp->near_entries, hp->far_entries, hp->pairs, [hp](size_t b) { return hp->alloc(b, false); }, s);
+        HIPC(hipEventRecord(ei[1], s));
+        HIPC(hipStreamSynchronize(s));
         HIPC(hipEventElapsedTime(&ms_inter, ei[0], ei[1]));
+    } else {
+        hipStream_t s2 = nullptr;
+        hipEvent_t ei[2] = {nullptr, nullptr};
+        HIPC(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        HIPC(hipEventCreate(&ei[0]));
+        HIPC(hipEventCreate(&ei[1]));
+        HIPC(hipStreamWaitEvent(s2, ev[2], 0));
+        std::exception_ptr ierr;
+        askit_handle *hp = h.get();
+        std::thread ith([&, hp]() {
+            try {
+                HIPC(hipSetDevice(hp->device));
+                HIPC(hipEventRecord(ei[0], s2));
+                build_interactions(hp, s2);
+                build_pairs(hp, hp->d_slabs, (int64_t)hp->slabs.size(), N, hp->sl_ptr, hp->sl_node, hp->sl_mask,
+                            hp->near_entries, hp->far_entries, hp->pairs,
+                            [hp](size_t b) { return hp->alloc(b, false); }, s2);
+                HIPC(hipEventRecord(ei[1], s2));
+                HIPC(hipStreamSynchronize(s2));
+            } catch (...) {
+                ierr = std::current_exception();
+            }
+        });
+        struct Join {
+            std::thread &t;
+            hipStream_t s2;
+            hipEvent_t *e;
+            ~Join()
+            {
+                if (t.joinable()) t.join();
+                (void)hipStreamSynchronize(s2);
+                (void)hipStreamDestroy(s2);
+                (void)hipEventDestroy(e[0]);
+                (void)hipEventDestroy(e[1]);
+            }
+        };
+        {
+            Join jn{ith, s2, ei};
+            // ---- node lists and sampled rows
+            build_node_lists(h.get(), s);
+            sample_rows(h.get(), s);
+            HIPC(hipEventRecord(ev[3], s));
+            // ---- skeletons
+            if (!defer_skel) skeletonize(h.get(), s);
+            HIPC(hipEventRecord(ev[4], s));
+            ith.join();
+            if (ierr) std::rethrow_exception(ierr);
+            HIPC(hipEventElapsedTime(&ms_inter, ei[0], ei[1]));
+        }
     }
     if (!defer_skel) count_pairs(h.get(), s);
     HIPC(hipEventRecord(ev[5], s));

@@ -279,7 +279,7 @@ askit_status askit_batch_setup(int32_t count, const float *const *X, const int64
     std::mutex emu;
     askit_status first_code = ASKIT_OK;
     std::string first_msg;
-    const int nthreads = std::min<int>(count, 8);
+    const int nthreads = std::min<int>(count, 16);
     std::vector<std::thread> th;
     for (int w = 0; w < nthreads; ++w)
         th.emplace_back([&, dev = b->device] {
