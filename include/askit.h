@@ -102,6 +102,13 @@ askit_status askit_params_default(askit_params *p);
  * ASKIT_QR_GANG=1 selects that form at any N and ASKIT_QR_GANG=0 never (the
  * two forms take the same decisions with different summation orders).
  * ASKIT_ERR_DEVICE if a gang's exchange does not complete within 10 s.
+ * Working memory: a setup takes its temporary buffers (neighbour-search
+ * outputs, tile lists, the ID's G blocks, ...) from a per-device arena that
+ * the library keeps for the process.  It grows, after a setup that needed
+ * more, to that setup's total, up to 16 GiB (11.3 GiB at 2^20 x 64),
+ * and is never returned while the process runs.  One setup at a time uses
+ * it; concurrent setups and what does not fit use stream-ordered
+ * allocations as usual.
  */
 askit_status askit_setup(const float *X, int64_t N, int32_t d, int64_t ldx,
                          const askit_params *p, void *stream, askit_handle **out);

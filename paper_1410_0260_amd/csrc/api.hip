@@ -16,6 +16,81 @@ using namespace askit;
 
 namespace askit {
 
+// ---------------------------------------------------------------- working-memory arena
+namespace {
+struct ArenaState {
+    std::mutex mu;                 // held by the setup using the arena
+    char *base = nullptr;
+    size_t cap = 0;
+};
+ArenaState g_arena[64];
+thread_local ArenaScope *tl_scope = nullptr;
+constexpr size_t ARENA_ALIGN = 256;
+}  // namespace
+
+ArenaScope::ArenaScope(hipStream_t s) : stream(s)
+{
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || tl_scope) return;
+    if (!g_arena[dev].mu.try_lock()) return;
+    held = true;
+    base = g_arena[dev].base;
+    cap = g_arena[dev].cap;
+    tl_scope = this;
+}
+
+ArenaScope::~ArenaScope()
+{
+    if (!held) return;
+    tl_scope = nullptr;
+    // the setup's kernels are done with the arena before the next one takes
+    // it (its stream is already idle on success; after an error it is waited
+    // for here)
+    (void)hipStreamSynchronize(stream);
+    ArenaState &A = g_arena[dev];
+    const size_t want = std::min(ARENA_CAP, need);
+    if (want > A.cap) {
+        // grow for the next setup to what this one asked for
+        if (A.base) (void)hipFree(A.base);
+        A.base = nullptr;
+        A.cap = 0;
+        void *nb = nullptr;
+        if (hipMalloc(&nb, want) == hipSuccess) {
+            A.base = (char *)nb;
+            A.cap = want;
+        } else {
+            (void)hipGetLastError();           // no arena: later setups allocate as before
+        }
+    }
+    A.mu.unlock();
+}
+
+hipError_t ws_alloc(void **p, size_t bytes, hipStream_t s)
+{
+    ArenaScope *u = tl_scope;
+    if (u) {
+        const size_t b = (std::max<size_t>(bytes, 1) + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN;
+        u->need += b;
+        if (u->base && u->off + b <= u->cap) {
+            *p = u->base + u->off;
+            u->off += b;
+            return hipSuccess;
+        }
+    }
+    return hipMallocAsync(p, bytes, s);
+}
+
+hipError_t ws_free(void *p, hipStream_t s)
+{
+    int dev = 0;
+    if (p && hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
+        // arena buffers are released with their scope (the range is only
+        // read here while the scope's thread holds the arena)
+        const ArenaScope *u = tl_scope;
+        if (u && u->base && (const char *)p >= u->base && (const char *)p < u->base + u->cap) return hipSuccess;
+    }
+    return hipFreeAsync(p, s);
+}
+
 thread_local std::string g_err;
 
 void fail(askit_status code, const std::string &msg) { throw Error{code, msg}; }
@@ -215,11 +290,11 @@ void query_points(askit_handle *h, const WeightSet &ws, const float *Y, int64_t 
     struct Guard {
         std::vector<void *> &t;
         hipStream_t s;
-        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+        ~Guard() { for (void *p : t) (void)ws_free(p, s); }
     } guard{tmp, s};
     auto ta = [&](size_t b) {
         void *p;
-        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        HIPC(ws_alloc(&p, std::max<size_t>(b, 16), s));
         tmp.push_back(p);
         return p;
     };
@@ -421,6 +496,7 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
     if (knn_in && ldk < p->kappa) fail(ASKIT_ERR_INVALID_ARG, "need ldk >= kappa");
     check_device();
     hipStream_t s = (hipStream_t)stream;
+    ArenaScope arena(s);               // this setup's working buffers (released on return)
 
     std::unique_ptr<askit_handle> h(new askit_handle());
     h->astream = s;
@@ -491,14 +567,14 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
     gather_rows(h->Xo, h->perm, N, dp, h->Xt, s);
     {
         int32_t *dl;
-        HIPC(hipMallocAsync((void **)&dl, sizeof(int32_t) * h->leaves.size(), s));
+        HIPC(ws_alloc((void **)&dl, sizeof(int32_t) * h->leaves.size(), s));
         HIPC(hipMemcpyAsync(dl, h->leaves.data(), sizeof(int32_t) * h->leaves.size(),
                             hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_leaf_of, dim3((unsigned)h->leaves.size()), dim3(256), 0, s, h->d_nodes, dl,
                            (int)h->leaves.size(), h->leaf_of);
         HIPC(hipGetLastError());
         HIPC(hipStreamSynchronize(s));
-        HIPC(hipFreeAsync(dl, s));
+        HIPC(ws_free(dl, s));
     }
     HIPC(hipEventRecord(ev[1], s));
     // ---- exact neighbours, swept in tree order (each block starts at its own leaf)
@@ -518,9 +594,9 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
     } else {
         int32_t *cand, *bad;
         float *thr;
-        HIPC(hipMallocAsync((void **)&cand, sizeof(int32_t) * N * KNN_CAND, s));
-        HIPC(hipMallocAsync((void **)&thr, sizeof(float) * N, s));
-        HIPC(hipMallocAsync((void **)&bad, sizeof(int32_t) * (N + 1), s));
+        HIPC(ws_alloc((void **)&cand, sizeof(int32_t) * N * KNN_CAND, s));
+        HIPC(ws_alloc((void **)&thr, sizeof(float) * N, s));
+        HIPC(ws_alloc((void **)&bad, sizeof(int32_t) * (N + 1), s));
         HIPC(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
         hipEvent_t k0, k1;
         HIPC(hipEventCreate(&k0));
@@ -534,11 +610,11 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
         float *Xt_f = h->Xt, *Xn_f = h->Xn;
         uint16_t *Xh_f = h->Xh, *Xl_f = h->Xl;
         if (fine) {
-            HIPC(hipMallocAsync((void **)&perm_f, sizeof(int32_t) * N, s));
-            HIPC(hipMallocAsync((void **)&Xt_f, sizeof(float) * N * dp, s));
-            HIPC(hipMallocAsync((void **)&Xn_f, sizeof(float) * N, s));
-            HIPC(hipMallocAsync((void **)&Xh_f, sizeof(uint16_t) * N * dp, s));
-            HIPC(hipMallocAsync((void **)&Xl_f, sizeof(uint16_t) * N * dp, s));
+            HIPC(ws_alloc((void **)&perm_f, sizeof(int32_t) * N, s));
+            HIPC(ws_alloc((void **)&Xt_f, sizeof(float) * N * dp, s));
+            HIPC(ws_alloc((void **)&Xn_f, sizeof(float) * N, s));
+            HIPC(ws_alloc((void **)&Xh_f, sizeof(uint16_t) * N * dp, s));
+            HIPC(ws_alloc((void **)&Xl_f, sizeof(uint16_t) * N * dp, s));
             build_fine_order(h.get(), 64, perm_f, s);
             gather_rows(h->Xo, perm_f, N, dp, Xt_f, s);
             split_bf16(Xt_f, N, dp, Xh_f, Xl_f, Xn_f, s);
@@ -554,17 +630,17 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
             // retried rows are reported as tree positions: iperm[perm_f[r]]
             const int64_t nr = (int64_t)h->knn_retry_list.size();
             int32_t *dl;
-            HIPC(hipMallocAsync((void **)&dl, sizeof(int32_t) * nr, s));
+            HIPC(ws_alloc((void **)&dl, sizeof(int32_t) * nr, s));
             HIPC(hipMemcpyAsync(dl, h->knn_retry_list.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_map_rows, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, dl, nr, perm_f,
                                h->iperm);
             HIPC(hipGetLastError());
             HIPC(hipMemcpyAsync(h->knn_retry_list.data(), dl, sizeof(int32_t) * nr, hipMemcpyDeviceToHost, s));
-            HIPC(hipFreeAsync(dl, s));
+            HIPC(ws_free(dl, s));
             HIPC(hipStreamSynchronize(s));
         }
         float *tb;
-        HIPC(hipMallocAsync((void **)&tb, sizeof(float) * N, s));
+        HIPC(ws_alloc((void **)&tb, sizeof(float) * N, s));
         knn_refine(Xt_f, N, Xt_f, N, d, dp, kappa, cand, thr, Xn_f, mx, perm_f, perm_f,
                    h->knn_idx, h->knn_d, bad + 1, bad, tb, s);
         int32_t nbad = 0;
@@ -578,17 +654,17 @@ static void setup_impl(const float *X, int64_t N, int32_t d, int64_t ldx, const 
         (void)hipEventDestroy(k1);
         knn_fallback(Xt_f, Xh_f, Xl_f, Xn_f, Xt_f, Xh_f, Xl_f, Xn_f, N, d, dp, kappa, true, bad + 1, nbad,
                      tb, perm_f, perm_f, h->knn_idx, h->knn_d, s);
-        HIPC(hipFreeAsync(tb, s));
+        HIPC(ws_free(tb, s));
         if (fine) {
-            HIPC(hipFreeAsync(perm_f, s));
-            HIPC(hipFreeAsync(Xt_f, s));
-            HIPC(hipFreeAsync(Xn_f, s));
-            HIPC(hipFreeAsync(Xh_f, s));
-            HIPC(hipFreeAsync(Xl_f, s));
+            HIPC(ws_free(perm_f, s));
+            HIPC(ws_free(Xt_f, s));
+            HIPC(ws_free(Xn_f, s));
+            HIPC(ws_free(Xh_f, s));
+            HIPC(ws_free(Xl_f, s));
         }
-        HIPC(hipFreeAsync(cand, s));
-        HIPC(hipFreeAsync(thr, s));
-        HIPC(hipFreeAsync(bad, s));
+        HIPC(ws_free(cand, s));
+        HIPC(ws_free(thr, s));
+        HIPC(ws_free(bad, s));
     }
     HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
     hipLaunchKernelGGL(k_bandwidth, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, h->knn_d, N,
@@ -798,13 +874,13 @@ askit_status askit_knn_rptree(const float *X, int64_t N, int32_t d, int64_t ldx,
     struct Guard {
         std::vector<void *> &t;
         hipStream_t s;
-        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+        ~Guard() { for (void *p : t) (void)ws_free(p, s); }
     } guard{tmp, s};
     float *Xo;
     int32_t *flag;
-    HIPC(hipMallocAsync((void **)&Xo, sizeof(float) * N * dp, s));
+    HIPC(ws_alloc((void **)&Xo, sizeof(float) * N * dp, s));
     tmp.push_back(Xo);
-    HIPC(hipMallocAsync((void **)&flag, 16, s));
+    HIPC(ws_alloc((void **)&flag, 16, s));
     tmp.push_back(flag);
     HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
     pack_points(X, N, d, ldx, dp, Xo, flag, s);
@@ -851,11 +927,11 @@ askit_status askit_query_neighbors(askit_handle *h, const float *Y, int64_t M, i
     struct Guard {
         std::vector<void *> &t;
         hipStream_t s;
-        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+        ~Guard() { for (void *p : t) (void)ws_free(p, s); }
     } guard{tmp, s};
     auto ta = [&](size_t b) {
         void *p;
-        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        HIPC(ws_alloc(&p, std::max<size_t>(b, 16), s));
         tmp.push_back(p);
         return p;
     };

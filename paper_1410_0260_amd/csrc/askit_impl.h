@@ -25,6 +25,34 @@ struct Error {
 void hip_check(hipError_t e, const char *what);
 #define HIPC(x) ::askit::hip_check((x), #x)
 
+// ---------------------------------------------------------------- working memory
+// Stream-ordered working buffers.  Inside an ArenaScope (a setup holding the
+// device's working-memory arena) ws_alloc bumps an offset in the arena and
+// ws_free of an arena buffer does nothing; the scope resets the arena when it
+// ends.  Elsewhere, and for what does not fit, they are hipMallocAsync and
+// hipFreeAsync.  The arena is one allocation per device that grows (up to
+// ARENA_CAP) to what the largest setup asked for and is kept for the
+// process; one setup at a time holds it (the others allocate as usual).
+constexpr size_t ARENA_CAP = 16ull << 30;
+hipError_t ws_alloc(void **p, size_t bytes, hipStream_t s);
+hipError_t ws_free(void *p, hipStream_t s);
+template <typename T>
+inline hipError_t ws_alloc(T **p, size_t bytes, hipStream_t s)
+{
+    return ws_alloc(reinterpret_cast<void **>(p), bytes, s);
+}
+struct ArenaScope {
+    explicit ArenaScope(hipStream_t s);
+    ~ArenaScope();
+    ArenaScope(const ArenaScope &) = delete;
+    ArenaScope &operator=(const ArenaScope &) = delete;
+    hipStream_t stream;
+    int dev = -1;
+    bool held = false;
+    char *base = nullptr;
+    size_t cap = 0, off = 0, need = 0;
+};
+
 // ---------------------------------------------------------------- sizes
 constexpr int WAVE = 64;
 constexpr int SLAB = 64;           // target rows per evaluation work item (one bit per row)

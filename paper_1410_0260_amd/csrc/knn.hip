@@ -1068,8 +1068,8 @@ static void list_sweep(hipStream_t s, const uint16_t *Qh, const uint16_t *Ql, co
     } else {
         int32_t *si;
         float *sd;
-        HIPC(hipMallocAsync((void **)&si, sizeof(int32_t) * nseg * M * KNN_CAND, s));
-        HIPC(hipMallocAsync((void **)&sd, sizeof(float) * nseg * M * KNN_CAND, s));
+        HIPC(ws_alloc((void **)&si, sizeof(int32_t) * nseg * M * KNN_CAND, s));
+        HIPC(ws_alloc((void **)&sd, sizeof(float) * nseg * M * KNN_CAND, s));
         if (!seeded) {
             // unseeded: every row starts from +inf (the rows are the identity map)
             hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M, INFINITY);
@@ -1078,8 +1078,8 @@ static void list_sweep(hipStream_t s, const uint16_t *Qh, const uint16_t *Ql, co
                         qpos, si, thr, sd);
         hipLaunchKernelGGL(k_knn_merge_seg, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, s, M, nseg, qpos, si, sd,
                            cand, thr);
-        HIPC(hipFreeAsync(si, s));
-        HIPC(hipFreeAsync(sd, s));
+        HIPC(ws_free(si, s));
+        HIPC(ws_free(sd, s));
     }
     HIPC(hipGetLastError());
 }
@@ -1366,7 +1366,7 @@ static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const fl
     if (!Xf || d > 1024 || ntiles > TL_TILE_MASK) return false;
     auto ta = [&](size_t b) {
         void *p;
-        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        HIPC(ws_alloc(&p, std::max<size_t>(b, 16), s));
         tmp.push_back(p);
         return p;
     };
@@ -1467,11 +1467,11 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     FilterBufs B;
     B.nsel = std::max(1, std::min(nsel, KNN_CAND));
     int32_t *retry, *over;
-    HIPC(hipMallocAsync((void **)&B.ocnt, sizeof(int32_t) * mc, s));
-    HIPC(hipMallocAsync((void **)&B.od, sizeof(float) * mc * KNN_CAP, s));
-    HIPC(hipMallocAsync((void **)&B.oi, sizeof(int32_t) * mc * KNN_CAP, s));
-    HIPC(hipMallocAsync((void **)&retry, sizeof(int32_t) * (M + 1), s));
-    HIPC(hipMallocAsync((void **)&over, sizeof(int32_t) * (M + 1), s));
+    HIPC(ws_alloc((void **)&B.ocnt, sizeof(int32_t) * mc, s));
+    HIPC(ws_alloc((void **)&B.od, sizeof(float) * mc * KNN_CAP, s));
+    HIPC(ws_alloc((void **)&B.oi, sizeof(int32_t) * mc * KNN_CAP, s));
+    HIPC(ws_alloc((void **)&retry, sizeof(int32_t) * (M + 1), s));
+    HIPC(ws_alloc((void **)&over, sizeof(int32_t) * (M + 1), s));
     HIPC(hipMemsetAsync(retry, 0, sizeof(int32_t), s));
     HIPC(hipMemsetAsync(over, 0, sizeof(int32_t), s));
     if (sampled) {
@@ -1540,11 +1540,11 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
         uint16_t *Bh, *Bl;
         float *Bn, *tc;
         int32_t *cc;
-        HIPC(hipMallocAsync((void **)&Bh, sizeof(uint16_t) * n * dp, s));
-        HIPC(hipMallocAsync((void **)&Bl, sizeof(uint16_t) * n * dp, s));
-        HIPC(hipMallocAsync((void **)&Bn, sizeof(float) * n, s));
-        HIPC(hipMallocAsync((void **)&tc, sizeof(float) * n, s));
-        HIPC(hipMallocAsync((void **)&cc, sizeof(int32_t) * n * KNN_CAND, s));
+        HIPC(ws_alloc((void **)&Bh, sizeof(uint16_t) * n * dp, s));
+        HIPC(ws_alloc((void **)&Bl, sizeof(uint16_t) * n * dp, s));
+        HIPC(ws_alloc((void **)&Bn, sizeof(float) * n, s));
+        HIPC(ws_alloc((void **)&tc, sizeof(float) * n, s));
+        HIPC(ws_alloc((void **)&cc, sizeof(int32_t) * n * KNN_CAND, s));
         hipLaunchKernelGGL(k_gather_qrows, dim3((unsigned)n), dim3(128), 0, s, list, n, dp, Qh, Ql, Qn, thr, Bh, Bl,
                            Bn, tc);
         sample_thresholds(dp, s, Bh, Bl, Bn, n, *samp, n, tc, B, cc);
@@ -1555,22 +1555,22 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
         HIPC(hipMemcpyAsync(&nlist, over, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
         list = over + 1;
-        HIPC(hipFreeAsync(Bh, s));
-        HIPC(hipFreeAsync(Bl, s));
-        HIPC(hipFreeAsync(Bn, s));
-        HIPC(hipFreeAsync(tc, s));
-        HIPC(hipFreeAsync(cc, s));
+        HIPC(ws_free(Bh, s));
+        HIPC(ws_free(Bl, s));
+        HIPC(ws_free(Bn, s));
+        HIPC(ws_free(tc, s));
+        HIPC(ws_free(cc, s));
     }
     // the rest: list sweep over every point on the compacted rows, seeded with
     // the bound the selection left
     if (nlist > 0)
         KNN_DISPATCH(list_sweep, s, Qh, Ql, Qn, (int64_t)nlist, Xh, Xl, Xn, N, ex, sl, list, true, cand, thr);
-    HIPC(hipFreeAsync(B.ocnt, s));
-    HIPC(hipFreeAsync(B.od, s));
-    HIPC(hipFreeAsync(B.oi, s));
-    HIPC(hipFreeAsync(retry, s));
-    HIPC(hipFreeAsync(over, s));
-    for (void *p : ttmp) HIPC(hipFreeAsync(p, s));
+    HIPC(ws_free(B.ocnt, s));
+    HIPC(ws_free(B.od, s));
+    HIPC(ws_free(B.oi, s));
+    HIPC(ws_free(retry, s));
+    HIPC(ws_free(over, s));
+    for (void *p : ttmp) HIPC(ws_free(p, s));
     (void)bad_rows;
     (void)bad_count;
 }
@@ -1979,7 +1979,7 @@ void knn_fallback(const float *Q, const uint16_t *Qh, const uint16_t *Ql, const 
     std::vector<void *> tmp;
     auto ta = [&](size_t b) {
         void *p;
-        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        HIPC(ws_alloc(&p, std::max<size_t>(b, 16), s));
         tmp.push_back(p);
         return p;
     };
@@ -2013,7 +2013,7 @@ void knn_fallback(const float *Q, const uint16_t *Qh, const uint16_t *Ql, const 
     HIPC(hipMemcpyAsync(&nover, over, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     knn_exact_rows(Q, X, N, d, dp, kappa, exclude_self, over + 1, nover, idmap, rowmap, idx, dist, s);
-    for (void *p : tmp) HIPC(hipFreeAsync(p, s));
+    for (void *p : tmp) HIPC(ws_free(p, s));
 }
 
 }  // namespace askit

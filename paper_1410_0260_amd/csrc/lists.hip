@@ -212,7 +212,7 @@ void build_node_lists(askit_handle *h, hipStream_t s)
     if (h->depth == 0) return;
     std::vector<int32_t> lv(h->leaves.begin(), h->leaves.end());
     int32_t *d_ids;
-    HIPC(hipMallocAsync((void **)&d_ids, sizeof(int32_t) * nn, s));
+    HIPC(ws_alloc((void **)&d_ids, sizeof(int32_t) * nn, s));
     HIPC(hipMemcpyAsync(d_ids, lv.data(), sizeof(int32_t) * lv.size(), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_leaf_nlists, dim3((unsigned)lv.size()), dim3(NL_T), 0, s, h->d_nodes, d_ids,
                        h->perm, h->iperm, h->knn_idx, h->knn_d, h->kappa, h->ell, h->nl_pos,
@@ -232,7 +232,7 @@ void build_node_lists(askit_handle *h, hipStream_t s)
         HIPC(hipGetLastError());
     }
     HIPC(hipStreamSynchronize(s));
-    HIPC(hipFreeAsync(d_ids, s));
+    HIPC(ws_free(d_ids, s));
 }
 
 // ====================================================================
@@ -549,8 +549,8 @@ static void run_interactions(askit_handle *h, const Slab *d_slabs, int64_t nslab
     const void *kfn = wide ? (const void *)k_interactions<4> : (const void *)k_interactions<1>;
     if (shb > 64 * 1024) HIPC(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb));
     int32_t *cnt, *cntw = nullptr;
-    HIPC(hipMallocAsync((void **)&cnt, sizeof(int32_t) * 2 * (nslab + 1), s));
-    if (wide) HIPC(hipMallocAsync((void **)&cntw, sizeof(int32_t) * 2 * 4 * std::max<int64_t>(nslab, 1), s));
+    HIPC(ws_alloc((void **)&cnt, sizeof(int32_t) * 2 * (nslab + 1), s));
+    if (wide) HIPC(ws_alloc((void **)&cntw, sizeof(int32_t) * 2 * 4 * std::max<int64_t>(nslab, 1), s));
     auto launch = [&](int mode, int32_t *cn, int32_t *cf, const int32_t *pp, int32_t *on, uint64_t *om) {
         if (wide)
             hipLaunchKernelGGL(k_interactions<4>, dim3((unsigned)nslab), dim3(256), shb, s, h->d_nodes, nn,
@@ -585,7 +585,7 @@ static void run_interactions(askit_handle *h, const Slab *d_slabs, int64_t nslab
         void *p;
         if (persistent) p = h->alloc(b, false);
         else {
-            HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+            HIPC(ws_alloc(&p, std::max<size_t>(b, 16), s));
             owned.push_back(p);
         }
         return p;
@@ -595,8 +595,8 @@ static void run_interactions(askit_handle *h, const Slab *d_slabs, int64_t nslab
     mask = (uint64_t *)al(sizeof(uint64_t) * std::max<int64_t>(acc, 1));
     HIPC(hipMemcpyAsync(ptr, hp.data(), sizeof(int32_t) * hp.size(), hipMemcpyHostToDevice, s));
     launch(1, nullptr, nullptr, ptr, node, mask);
-    HIPC(hipFreeAsync(cnt, s));
-    if (cntw) HIPC(hipFreeAsync(cntw, s));
+    HIPC(ws_free(cnt, s));
+    if (cntw) HIPC(ws_free(cntw, s));
 }
 
 void build_interactions(askit_handle *h, hipStream_t s)
@@ -604,21 +604,21 @@ void build_interactions(askit_handle *h, hipStream_t s)
     const int64_t N = h->N;
     const int nnb = h->kappa + 1;
     int32_t *nb;
-    HIPC(hipMallocAsync((void **)&nb, sizeof(int32_t) * N * nnb, s));
+    HIPC(ws_alloc((void **)&nb, sizeof(int32_t) * N * nnb, s));
     hipLaunchKernelGGL(k_nbpos_self, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, h->perm,
                        h->iperm, h->knn_idx, N, h->kappa, nb);
     HIPC(hipGetLastError());
     std::vector<void *> owned;
     run_interactions(h, h->d_slabs, (int64_t)h->slabs.size(), nb, nnb, h->sl_ptr, h->sl_node,
                      h->sl_mask, h->near_entries, h->far_entries, owned, s, true);
-    HIPC(hipFreeAsync(nb, s));
+    HIPC(ws_free(nb, s));
 }
 
 void count_pairs(askit_handle *h, hipStream_t s)
 {
     // algorithmic pair counts of one evaluation
     unsigned long long *pc;
-    HIPC(hipMallocAsync((void **)&pc, 16, s));
+    HIPC(ws_alloc((void **)&pc, 16, s));
     HIPC(hipMemsetAsync(pc, 0, 16, s));
     int64_t ne = h->near_entries + h->far_entries;
     if (ne > 0)
@@ -627,7 +627,7 @@ void count_pairs(askit_handle *h, hipStream_t s)
     unsigned long long hpc[2];
     HIPC(hipMemcpyAsync(hpc, pc, 16, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    HIPC(hipFree(pc));
+    HIPC(ws_free(pc, s));
     h->near_pairs = (int64_t)hpc[0];
     h->far_pairs = (int64_t)hpc[1];
 }
@@ -695,7 +695,7 @@ void sort_queries(askit_handle *h, const int32_t *nb, int64_t M, int32_t *order,
     int64_t M2 = 1;
     while (M2 < M) M2 <<= 1;
     uint64_t *key;
-    HIPC(hipMallocAsync((void **)&key, sizeof(uint64_t) * M2, s));
+    HIPC(ws_alloc((void **)&key, sizeof(uint64_t) * M2, s));
     tmp.push_back(key);
     hipLaunchKernelGGL(k_qkeys, dim3((unsigned)((M2 + 255) / 256)), dim3(256), 0, s, nb, M, h->kappa,
                        h->leaf_of, seg, (int64_t)h->nodes.size(), M2, key);
@@ -726,7 +726,7 @@ void build_query_interactions(askit_handle *h, const int32_t *nb, int64_t M, Sla
     if (r0 != M) fail(ASKIT_ERR_INVALID_ARG, "query segments do not add up to the query count");
     nslab = (int64_t)hs.size();
     Slab *ds;
-    HIPC(hipMallocAsync((void **)&ds, sizeof(Slab) * nslab, s));
+    HIPC(ws_alloc((void **)&ds, sizeof(Slab) * nslab, s));
     tmp.push_back(ds);
     HIPC(hipMemcpyAsync(ds, hs.data(), sizeof(Slab) * nslab, hipMemcpyHostToDevice, s));
     slabs = ds;

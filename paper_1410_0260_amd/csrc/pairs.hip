@@ -186,14 +186,14 @@ void build_pairs(const askit_handle *h, const Slab *d_slabs, int64_t nslab, int6
     std::vector<void *> tmp;
     auto ta = [&](size_t b) {
         void *p;
-        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        HIPC(ws_alloc(&p, std::max<size_t>(b, 16), s));
         tmp.push_back(p);
         return p;
     };
     struct Guard {
         std::vector<void *> &t;
         hipStream_t s;
-        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+        ~Guard() { for (void *p : t) (void)ws_free(p, s); }
     } guard{tmp, s};
     int32_t *cnt = (int32_t *)ta(sizeof(int32_t) * nkey);
     HIPC(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nkey, s));

@@ -130,14 +130,14 @@ __global__ void k_max_norm(const float *__restrict__ v, int64_t n, unsigned *out
 float max_norm(const float *nrm, int64_t N, hipStream_t s)
 {
     unsigned *d;
-    HIPC(hipMallocAsync((void **)&d, sizeof(unsigned), s));
+    HIPC(ws_alloc((void **)&d, sizeof(unsigned), s));
     HIPC(hipMemsetAsync(d, 0, sizeof(unsigned), s));
     hipLaunchKernelGGL(k_max_norm, dim3(256), dim3(256), 0, s, nrm, N, d);
     HIPC(hipGetLastError());
     unsigned hbits = 0;
     HIPC(hipMemcpyAsync(&hbits, d, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    HIPC(hipFreeAsync(d, s));
+    HIPC(ws_free(d, s));
     float f;
     std::memcpy(&f, &hbits, 4);
     return f;

@@ -919,12 +919,12 @@ void skeletonize_multi(const std::vector<askit_handle *> &hs, hipStream_t s)
         ~Free()
         {
             (void)hipStreamSynchronize(s);
-            for (void *p : t) (void)hipFreeAsync(p, s);
+            for (void *p : t) (void)ws_free(p, s);
         }
     } fr{tmp, s};
     auto ta = [&](size_t b) {
         void *p;
-        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        HIPC(ws_alloc(&p, std::max<size_t>(b, 16), s));
         tmp.push_back(p);
         return p;
     };

@@ -462,11 +462,11 @@ static void run_split_levels(const askit_handle *h, int32_t *perm, const std::ve
     struct Guard {
         std::vector<void *> &t;
         hipStream_t s;
-        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+        ~Guard() { for (void *p : t) (void)ws_free(p, s); }
     } guard{tmp, s};
     auto talloc = [&](size_t b) {
         void *p;
-        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        HIPC(ws_alloc(&p, std::max<size_t>(b, 16), s));
         tmp.push_back(p);
         return p;
     };
@@ -637,11 +637,11 @@ void prune_visits(const askit_handle *h, int32_t *vk, int32_t *vd, hipStream_t s
     struct Guard {
         std::vector<void *> &t;
         hipStream_t s;
-        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+        ~Guard() { for (void *p : t) (void)ws_free(p, s); }
     } guard{tmp, s};
     auto ta = [&](size_t b) {
         void *p;
-        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        HIPC(ws_alloc(&p, std::max<size_t>(b, 16), s));
         tmp.push_back(p);
         return p;
     };
@@ -817,11 +817,11 @@ void rp_knn(const float *Xo, int64_t N, int d, int dp, int kappa, int leaf, int 
     struct Guard {
         std::vector<void *> &t;
         hipStream_t s;
-        ~Guard() { for (void *p : t) (void)hipFreeAsync(p, s); }
+        ~Guard() { for (void *p : t) (void)ws_free(p, s); }
     } guard{tmp, s};
     auto ta = [&](size_t b) {
         void *p;
-        HIPC(hipMallocAsync(&p, std::max<size_t>(b, 16), s));
+        HIPC(ws_alloc(&p, std::max<size_t>(b, 16), s));
         tmp.push_back(p);
         return p;
     };

@@ -363,3 +363,30 @@ def test_gang_and_streaming_qr_agree(name, monkeypatch):
         pb = b["P"][off:off + k * (m - k)].astype(np.float64)
         assert np.linalg.norm(pa - pb) <= 1e-5 * max(1.0, np.linalg.norm(pa)), f"node {n}"
         off += kcap * ncap
+
+
+def test_repeated_setups_identical():
+    """The same setup three times in one process (the first may run before
+    the library's working-memory arena exists, the later ones take their
+    buffers from it): every structure and u bit for bit the same."""
+    import torch
+    from paper_1410_0260_amd import askit as A
+    N, d = 30000, 24
+    X = synth.mixture_points(N, d, 6, 5, 1e-3, 71)
+    W = synth.weights(N, 2, 71)
+    p = O.Params(m=128, kappa=16, smax=48, ell=68, tau=1e-6, h=0.9, seed=5)
+    Xd, Wd = torch.from_numpy(X).cuda(), torch.from_numpy(W).cuda()
+    runs = []
+    for _ in range(3):
+        h = A.setup(Xd, gparams(p))
+        h.update_weights(Wd)
+        U = h.evaluate().cpu().numpy()
+        g = h.structures()
+        h.close()
+        runs.append((U, g))
+    U0, g0 = runs[0]
+    for U, g in runs[1:]:
+        assert np.array_equal(U, U0)
+        for k in ("perm", "knn_idx", "knn_d", "nl_pos", "nl_key", "T", "S", "k", "colperm", "P",
+                  "slab_ptr", "slab_node", "slab_mask", "Wsk"):
+            assert np.array_equal(g[k], g0[k]), k
