@@ -1229,26 +1229,48 @@ __global__ __launch_bounds__(64) void k_tile_geom(const float *__restrict__ Xf, 
                                                   const float *__restrict__ thr, const float *__restrict__ Xn,
                                                   float *__restrict__ cen, TileGeom *__restrict__ geo)
 {
+#pragma clang fp contract(off)
+    // per 64 coordinates: the group's rows with one coalesced row load per
+    // point (lane = coordinate); the centre is their FP64 sum in point order
+    // over n, rounded to FP32; the rows then pass through LDS so that each
+    // lane (point) forms its squared distance to that FP32 centre in FP64
+    __shared__ float rows[G * 65];
+    __shared__ float cs[64];
     const int64_t t = blockIdx.x;
     const int lane = threadIdx.x;
-    const int64_t p = t * G + lane;
-    const bool ok = lane < G && p < N;
-    const int n = (int)min<int64_t>(G, N - t * G);
-    for (int k = 0; k < d; ++k) {
-        double v = ok ? (double)Xf[p * dp + k] : 0.0;
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (lane == 0) cen[t * dp + k] = (float)(v / (double)n);
-    }
-    __syncthreads();
+    const int64_t p0 = t * G;
+    const int n = (int)min<int64_t>(G, N - p0);
     double r2 = 0.0;
-    float tm = -INFINITY, nm = 0.0f;
-    if (ok) {
-        for (int k = 0; k < d; ++k) {
-            const double u = (double)Xf[p * dp + k] - (double)cen[t * dp + k];
-            r2 += u * u;
+    for (int k0 = 0; k0 < d; k0 += 64) {
+        const int kc = min(k0 + lane, dp - 1);
+        float x[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) x[i] = Xf[(p0 + min(i, n - 1)) * dp + kc];
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < G; ++i)
+            if (i < n) v += (double)x[i];
+        const float c = (float)(v / (double)n);
+        if (k0 + lane < d) cen[t * dp + k0 + lane] = c;
+        cs[lane] = c;
+#pragma unroll
+        for (int i = 0; i < G; ++i) rows[i * 65 + lane] = x[i];
+        __syncthreads();
+        if (lane < n) {
+            const int kn = min(64, d - k0);
+            for (int j = 0; j < kn; ++j) {
+                const double u = (double)rows[lane * 65 + j] - (double)cs[j];
+                r2 += u * u;
+            }
         }
-        tm = thr[p];
-        nm = Xn[p];
+        __syncthreads();
+    }
+    float tm = -INFINITY, nm = 0.0f;
+    if (lane < n) {
+        tm = thr[p0 + lane];
+        nm = Xn[p0 + lane];
+    } else {
+        r2 = 0.0;
     }
     for (int o = 32; o > 0; o >>= 1) {
         r2 = fmax(r2, __shfl_xor(r2, o));
@@ -1269,7 +1291,7 @@ __global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen
                                                    uint64_t *__restrict__ mask, int64_t *__restrict__ cnt,
                                                    int64_t *__restrict__ wcnt)
 {
-    __shared__ float ca[4][1024];
+    __shared__ __attribute__((aligned(16))) float ca[4][1024];
     __shared__ int wsum[4], wwsum[4];
     const int64_t b = blockIdx.x, t0 = 2 * b, g0 = 4 * b;
     const int nown = (int)min<int64_t>(2, ntiles - t0);
@@ -1278,6 +1300,7 @@ __global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen
         for (int w = 0; w < 4; ++w) ca[w][k] = cen_g[(g0 + min(w, ng - 1)) * dp + k];
     __syncthreads();
     TileGeom gw[4];
+#pragma unroll
     for (int w = 0; w < 4; ++w) gw[w] = geo_g[g0 + min(w, ng - 1)];
     int64_t total = 0, wtotal = 0;
     for (int64_t base = t0; base < ntiles; base += 256) {
@@ -1288,19 +1311,39 @@ __global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen
                 for (int w = 0; w < 4; ++w) keep[w] = w < ng;
             } else {
                 const TileGeom gt = geo_t[t];
-                double sw[4] = {0.0, 0.0, 0.0, 0.0};
+                // squared centre distances in FP32, four coordinates per load
+                // (rows are 16-byte aligned); the test shrinks them by a
+                // relative 1e-5, above the FP32 rounding bound (d + 2) 2^-24
+                // for d <= 128
+                float sw[4] = {0.0f, 0.0f, 0.0f, 0.0f};
                 const float *ct = cen_t + t * dp;
-                for (int k = 0; k < d; ++k) {
-                    const double c = (double)ct[k];
+                int k = 0;
+                for (; k + 4 <= d; k += 4) {
+                    const float4 c = *reinterpret_cast<const float4 *>(ct + k);
+#pragma unroll
                     for (int w = 0; w < 4; ++w) {
-                        const double u = (double)ca[w][k] - c;
-                        sw[w] += u * u;
+                        const float4 q = *reinterpret_cast<const float4 *>(&ca[w][k]);
+                        float u = q.x - c.x;
+                        sw[w] = fmaf(u, u, sw[w]);
+                        u = q.y - c.y;
+                        sw[w] = fmaf(u, u, sw[w]);
+                        u = q.z - c.z;
+                        sw[w] = fmaf(u, u, sw[w]);
+                        u = q.w - c.w;
+                        sw[w] = fmaf(u, u, sw[w]);
                     }
                 }
-                for (int w = 0; w < ng; ++w) {
-                    // centre distances shrunk by 1e-9 relative: the FP64 rounding
-                    // of the sums is far below that
-                    const double L = sqrt(sw[w]) * (1.0 - 1e-9) - gw[w].r - gt.r;
+                for (; k < d; ++k) {
+                    const float c = ct[k];
+                    for (int w = 0; w < 4; ++w) {
+                        const float u = ca[w][k] - c;
+                        sw[w] = fmaf(u, u, sw[w]);
+                    }
+                }
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    if (w >= ng) break;
+                    const double L = sqrt((double)sw[w]) * (1.0 - 1e-5) - gw[w].r - gt.r;
                     const double bound = ((double)fmaxf(gw[w].tmax, gt.tmax) +
                                           g * ((double)gw[w].nmax + (double)gt.nmax)) * (1.0 + 1e-6);
                     keep[w] = !(L > 0.0 && L * L > bound);
@@ -1363,7 +1406,7 @@ static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const fl
 {
     static_assert(KB_M == 2 * KB_N && KB_M == 4 * 32, "a row block is two tiles and four waves of 32 rows");
     const int64_t ntiles = (N + KB_N - 1) / KB_N, nblk = (N + KB_M - 1) / KB_M, ngroups = (N + 31) / 32;
-    if (!Xf || d > 1024 || ntiles > TL_TILE_MASK) return false;
+    if (!Xf || d > 128 || ntiles > TL_TILE_MASK) return false;
     auto ta = [&](size_t b) {
         void *p;
         HIPC(ws_alloc(&p, std::max<size_t>(b, 16), s));
