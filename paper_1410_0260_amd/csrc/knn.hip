@@ -1679,6 +1679,40 @@ __device__ __forceinline__ bool lt_di(double d1, int i1, double d2, int i2)
 // positions), sorted by (D, point id) with id = idmap[position]; the kappa
 // first are written as point ids to output row rowmap[row] (identity when
 // NULL); certificate against the approximate threshold.
+// D(a, b) = sum_k (a_k - b_k)^2 in FP64, k increasing, no fused multiply-add
+// (the canonical distance), for rows padded to dp (a multiple of 16): 64
+// coordinates are loaded at a time, unconditionally (indices kept inside the
+// padded row), before the chain runs over them.
+__device__ __forceinline__ double canon_sqdist_rows(const float *__restrict__ a, const float *__restrict__ b, int d,
+                                                    int dp)
+{
+#pragma clang fp contract(off)
+    double s = 0.0;
+    for (int k0 = 0; k0 < d; k0 += 64) {
+        float4 xa[16], xb[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int k = min(k0 + 4 * i, dp - 4);
+            xa[i] = *reinterpret_cast<const float4 *>(a + k);
+            xb[i] = *reinterpret_cast<const float4 *>(b + k);
+        }
+        const int kn = min(64, d - k0);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const float pa[4] = {xa[i].x, xa[i].y, xa[i].z, xa[i].w};
+            const float pb[4] = {xb[i].x, xb[i].y, xb[i].z, xb[i].w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (4 * i + u < kn) {
+                    const double t = (double)pa[u] - (double)pb[u];
+                    s += t * t;
+                }
+            }
+        }
+    }
+    return s;
+}
+
 __global__ __launch_bounds__(256) void k_knn_refine(const float *__restrict__ Q, int64_t M,
                                                     const float *__restrict__ X, int64_t N, int d,
                                                     int dp, int kappa,
@@ -1697,9 +1731,13 @@ __global__ __launch_bounds__(256) void k_knn_refine(const float *__restrict__ Q,
     int lane = threadIdx.x % WAVE;
     if (row >= M) return;
     int j = cand[row * KNN_CAND + lane];
+    const bool valid = j >= 0 && j < N;
+    // canonical distance of every lane's candidate (empty slots read row 0
+    // and are dropped), 64 coordinates of loads in flight at a time
+    const double Dc = canon_sqdist_rows(Q + row * dp, X + (int64_t)(valid ? j : 0) * dp, d, dp);
     double D = INFINITY;
-    if (j >= 0 && j < N) {
-        D = canon_sqdist(Q + row * dp, X + (int64_t)j * dp, d);
+    if (valid) {
+        D = Dc;
         j = idmap[j];
     } else {
         j = 0x7fffffff;
