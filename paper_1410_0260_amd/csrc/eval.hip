@@ -255,7 +255,9 @@ __global__ __launch_bounds__(EV_T) void k_eval_chunks(ChunkParams p)
                 r2 = (float)fmax((double)sSn[sr] + (double)tn - 2.0 * (double)acc[r], 0.0);
             else
                 r2 = fmaxf(sSn[sr] + tn - 2.0f * acc[r], 0.0f);
-            kv[r] = exp2f(sSg[sr] * r2);
+            // the hardware 2^x (v_exp_f32): the exponent is <= 0 and values
+            // below 2^-126 (flushed) are far below any sum's rounding
+            kv[r] = __builtin_amdgcn_exp2f(sSg[sr] * r2);
         }
         if constexpr (MC) {
             // U^T (columns x targets) += W^T (columns x sources) K (sources x targets), two sources per step
