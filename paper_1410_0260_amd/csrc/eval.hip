@@ -133,7 +133,10 @@ __global__ __launch_bounds__(EV_T) void k_eval_chunks(ChunkParams p)
 
     // one 64 x EV_KC chunk of (centred) rows into LDS; rows given by `row(r)`
     // (negative: padding); per-row partial squared norms into nrm
-    auto load_chunk = [&](float *dst, uint16_t *dh, uint16_t *dl, auto row_ptr, int k0, float *nrm, bool accum) {
+    // (get(u, rp, kk) gives the row's coordinates kk..kk+3: a load, or a
+    // register filled ahead of time)
+    auto put_chunk = [&](float *dst, uint16_t *dh, uint16_t *dl, auto row_ptr, int k0, float *nrm, bool accum,
+                         auto get) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             int idx = tid + EV_T * u;
@@ -142,7 +145,7 @@ __global__ __launch_bounds__(EV_T) void k_eval_chunks(ChunkParams p)
             int kk = k0 + qd;
             const float *rp = row_ptr(row);
             if (rp && kk < dp) {
-                float4 x = *reinterpret_cast<const float4 *>(rp + kk);
+                float4 x = get(u, rp, kk);
                 v.x = x.x - sC[kk];
                 v.y = x.y - sC[kk + 1];
                 v.z = x.z - sC[kk + 2];
@@ -165,6 +168,10 @@ __global__ __launch_bounds__(EV_T) void k_eval_chunks(ChunkParams p)
             }
         }
     };
+    auto load_chunk = [&](float *dst, uint16_t *dh, uint16_t *dl, auto row_ptr, int k0, float *nrm, bool accum) {
+        put_chunk(dst, dh, dl, row_ptr, k0, nrm, accum,
+                  [](int, const float *rp, int kk) { return *reinterpret_cast<const float4 *>(rp + kk); });
+    };
     auto trow = [&](int r) -> const float * { return sRow[r] >= 0 ? Y + (int64_t)sRow[r] * dp : nullptr; };
 
     // target norms (all dimension chunks); the target chunk stays resident when dp <= EV_KC
@@ -180,12 +187,48 @@ __global__ __launch_bounds__(EV_T) void k_eval_chunks(ChunkParams p)
 #pragma unroll
     for (int j = 0; j < (MC ? 1 : CM); ++j) vacc[j] = 0.0f;
 
+    // one dimension chunk (dp <= 64): the next source block's rows, factors
+    // and weights are loaded into registers while the current one is on the
+    // MFMA (indices kept valid for rows past the node's end; those values
+    // are not used)
+    const bool pf = nchunk == 1;
+    constexpr int NWP = 64 * CM >= EV_T ? 64 * CM / EV_T : 1;
+    float4 px[4];
+    float pg = 0.0f, pw[NWP];
+    auto fetch = [&](int s1) {
+        const int n1 = min(64, ns - s1);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = tid + EV_T * u, row = idx >> 4, qd = (idx & 15) * 4;
+            px[u] = *reinterpret_cast<const float4 *>(src + (int64_t)(s1 + (row < n1 ? row : 0)) * dp +
+                                                       (qd < dp ? qd : 0));
+        }
+        pg = g[s1 + (tid < n1 ? tid : 0)];
+#pragma unroll
+        for (int u = 0; u < NWP; ++u) {
+            const int e = tid + EV_T * u, r = e / CM, j = e % CM;
+            const bool in = e < 64 * CM && r < n1 && j < p.rb;
+            pw[u] = w[in ? (int64_t)(s1 + r) * p.R + p.r0 + j : (int64_t)s1 * p.R + p.r0];
+        }
+    };
+    if (pf) fetch(0);
     for (int s0 = 0; s0 < ns; s0 += 64) {
         const int nsrc = min(64, ns - s0);
         auto srow = [&](int r) -> const float * { return r < nsrc ? src + (int64_t)(s0 + r) * dp : nullptr; };
         f32x16 acc = {};
         for (int c = 0; c < nchunk; ++c) {
             __syncthreads();
+            if (pf) {
+                put_chunk(sS, sSh, sSl, srow, 0, sSn, false, [&](int u, const float *, int) { return px[u]; });
+                if (tid < 64) sSg[tid] = tid < nsrc ? pg : 0.0f;
+#pragma unroll
+                for (int u = 0; u < NWP; ++u) {
+                    const int e = tid + EV_T * u, r = e / CM, j = e % CM;
+                    if (e < 64 * CM) sW[e] = (r < nsrc && j < p.rb) ? pw[u] : 0.0f;
+                }
+                __syncthreads();
+                if (s0 + 64 < ns) fetch(s0 + 64);
+            } else {
             if (nchunk > 1) load_chunk(sT, sTh, sTl, trow, c * EV_KC, nullptr, false);
             load_chunk(sS, sSh, sSl, srow, c * EV_KC, sSn, c > 0);
             if (c == 0) {
@@ -216,6 +259,7 @@ __global__ __launch_bounds__(EV_T) void k_eval_chunks(ChunkParams p)
                 }
             }
             __syncthreads();
+            }
             const int kc = min(EV_KC, dp - c * EV_KC);
             if constexpr (BF) {
                 const uint16_t *ph = sSh + (sq + l32) * EV_LH + 8 * half;
