@@ -1522,13 +1522,13 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     } else {
         // window threshold: thr = nsel-th approximate distance among the 4096
         // tree-order neighbours of the row's block, in three steps with the
-        // same arithmetic: the nsel-th of the block's own two tiles (every
-        // point passes at +inf) bounds it; the threshold filter over the
-        // window at that bound keeps every closer point (so at least those
-        // nsel); their nsel-th is the exact window value (or a bound, when
-        // more than the capacity survive)
+        // same arithmetic: the nsel-th of the 4 tiles around the block's rows
+        // (its own two and one on each side; every point passes at +inf)
+        // bounds it; the threshold filter over the window at that bound keeps
+        // every closer point (so at least those nsel); their nsel-th is the
+        // exact window value (or a bound, when more than the capacity survive)
         hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M, INFINITY);
-        filter_select(dp, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, chunk, thr, B, cand, nullptr, false, 2, nullptr);
+        filter_select(dp, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, chunk, thr, B, cand, nullptr, false, 4, nullptr);
         widen(thr, M, s);
         filter_select(dp, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, chunk, thr, B, cand, nullptr, false, KNN_WIN,
                       nullptr);
