@@ -554,8 +554,7 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
                                                        int excl, int64_t row0,
                                                        const float *__restrict__ Tin,
                                                        int cap, int32_t *__restrict__ ocnt,
-                                                       float *__restrict__ od,
-                                                       int32_t *__restrict__ oi, int win_tiles,
+                                                       uint2 *__restrict__ oe, int win_tiles,
                                                        const int32_t *__restrict__ tlist,
                                                        const int64_t *__restrict__ toff,
                                                        const int4 *__restrict__ items)
@@ -761,17 +760,13 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
                 if (pA) {
                     const uint32_t p = p0 + __popc(hA & below);
                     if (p < (uint32_t)cap) {
-                        const size_t o = (size_t)qrow * (uint32_t)cap + p;
-                        od[o] = dA;
-                        oi[o] = (int32_t)cA;
+                        oe[(size_t)qrow * (uint32_t)cap + p] = make_uint2(__float_as_uint(dA), cA);
                     }
                 }
                 if (pB) {
                     const uint32_t p = p0 + __popc(hA) + __popc(hB & below);
                     if (p < (uint32_t)cap) {
-                        const size_t o = (size_t)qrow * (uint32_t)cap + p;
-                        od[o] = dB;
-                        oi[o] = (int32_t)cB;
+                        oe[(size_t)qrow * (uint32_t)cap + p] = make_uint2(__float_as_uint(dB), cB);
                     }
                 }
             }
@@ -796,17 +791,13 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
                         if (dA <= tA) {
                             uint32_t p = (uint32_t)atomicAdd(&ocnt[cA], 1);
                             if (p < (uint32_t)cap) {
-                                const size_t o = (size_t)cA * (uint32_t)cap + p;
-                                od[o] = dA;
-                                oi[o] = (int32_t)qrow;
+                                oe[(size_t)cA * (uint32_t)cap + p] = make_uint2(__float_as_uint(dA), qrow);
                             }
                         }
                         if (dB <= tB) {
                             uint32_t p = (uint32_t)atomicAdd(&ocnt[cB], 1);
                             if (p < (uint32_t)cap) {
-                                const size_t o = (size_t)cB * (uint32_t)cap + p;
-                                od[o] = dB;
-                                oi[o] = (int32_t)qrow;
+                                oe[(size_t)cB * (uint32_t)cap + p] = make_uint2(__float_as_uint(dB), qrow);
                             }
                         }
                     }
@@ -849,8 +840,7 @@ __device__ __forceinline__ float key2f(uint32_t k)
 
 __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int cap, int nsel,
                                                     const int32_t *__restrict__ ocnt,
-                                                    const float *__restrict__ od,
-                                                    const int32_t *__restrict__ oi,
+                                                    const uint2 *__restrict__ oe,
                                                     int32_t *__restrict__ cand,
                                                     float *__restrict__ thr,
                                                     int32_t *__restrict__ bad_rows,
@@ -868,15 +858,14 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
         bad_rows[p] = (int32_t)row;
     }
     const int nk = min(n, cap);
-    const float *rd = od + lrow * cap;
-    const int32_t *ri = oi + lrow * cap;
+    const uint2 *re = oe + lrow * cap;          // (distance bits, id) per stored entry
     int32_t *co = cand + row * KNN_CAND;
     if (nk <= nsel) {
         // every stored entry is a candidate
-        co[lane] = lane < nk ? ri[lane] : -1;
+        co[lane] = lane < nk ? (int32_t)re[lane].y : -1;
         float m = -INFINITY;
         if (nk == nsel) {
-            m = lane < nk ? rd[lane] : -INFINITY;
+            m = lane < nk ? __uint_as_float(re[lane].x) : -INFINITY;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
         }
@@ -890,7 +879,7 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
     // per-entry branches: all of them are in flight at once
     float kv[SEL_Q];
 #pragma unroll
-    for (int q = 0; q < SEL_Q; ++q) kv[q] = rd[min(lane + WAVE * q, nk - 1)];
+    for (int q = 0; q < SEL_Q; ++q) kv[q] = __uint_as_float(re[min(lane + WAVE * q, nk - 1)].x);
 #pragma unroll
     for (int q = 0; q < SEL_Q; ++q) asm volatile("" : "+v"(kv[q]));
     uint32_t key[SEL_Q];
@@ -975,7 +964,7 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
             for (int q = 0; q < SEL_Q; ++q) {
                 const int e = lane + WAVE * q;
                 if (key[q] == K && e < nk) {
-                    const int p = ri[e];
+                    const int p = (int)re[e].y;
                     if (p > last && p < mi) mi = p;
                 }
             }
@@ -986,7 +975,7 @@ __global__ __launch_bounds__(256) void k_knn_select(int64_t M, int64_t row0, int
         }
     }
     __builtin_amdgcn_wave_barrier();
-    if (lane < nslot) co[lane] = ri[slot[lane]];
+    if (lane < nslot) co[lane] = (int32_t)re[slot[lane]].y;
     else if (lane >= nsel) co[lane] = -1;
     // bound for the points outside the candidates: the nsel-th survivor.  A
     // row whose segment overflowed is swept again; the nsel-th of its stored
@@ -1010,16 +999,16 @@ template <int KS>
 static void launch_filter(dim3 g, dim3 b, hipStream_t s, const uint16_t *Qh, const uint16_t *Ql,
                           const float *Qn, int64_t M, const uint16_t *Xh, const uint16_t *Xl,
                           const float *Xn, int64_t N, int ex, int64_t row0, const float *T, int cap,
-                          int32_t *ocnt, float *od, int32_t *oi, bool sym, int win = 0,
+                          int32_t *ocnt, uint2 *oe, bool sym, int win = 0,
                           const int32_t *tlist = nullptr, const int64_t *toff = nullptr,
                           const int4 *items = nullptr)
 {
     if (sym)
         hipLaunchKernelGGL((k_knn_filter<KS, true>), g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, row0, T, cap,
-                           ocnt, od, oi, 0, tlist, toff, items);
+                           ocnt, oe, 0, tlist, toff, items);
     else
         hipLaunchKernelGGL((k_knn_filter<KS, false>), g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, row0, T,
-                           cap, ocnt, od, oi, win, (const int32_t *)nullptr, (const int64_t *)nullptr,
+                           cap, ocnt, oe, win, (const int32_t *)nullptr, (const int64_t *)nullptr,
                            (const int4 *)nullptr);
 }
 
@@ -1098,8 +1087,8 @@ constexpr int64_t KNN_CHUNK = 1 << 20;      // query rows per filter pass (bound
 
 // Filter output buffers of up to `rows` rows.
 struct FilterBufs {
-    int32_t *ocnt = nullptr, *oi = nullptr;
-    float *od = nullptr;
+    int32_t *ocnt = nullptr;
+    uint2 *oe = nullptr;                      // (distance bits, id) per slot, KNN_CAP slots per row
     int nsel = KNN_CAND;                      // candidates the selection keeps per row
 };
 
@@ -1127,10 +1116,10 @@ static void filter_select(int dp, hipStream_t s, const uint16_t *Qh, const uint1
             HIPC(hipEventRecord((*ev)[ev->size() - 2], s));
         }
         KNN_DISPATCH(launch_filter, g, dim3(256), s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, KNN_CAP, B.ocnt,
-                     B.od, B.oi, sym, win, tlist, toff, items);
+                     B.oe, sym, win, tlist, toff, items);
         if (ev) HIPC(hipEventRecord(ev->back(), s));
         hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, KNN_CAP, B.nsel,
-                           B.ocnt, B.od, B.oi, cand, thr, over ? over + 1 : nullptr, over);
+                           B.ocnt, B.oe, cand, thr, over ? over + 1 : nullptr, over);
         HIPC(hipGetLastError());
     }
 }
@@ -1511,8 +1500,7 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     B.nsel = std::max(1, std::min(nsel, KNN_CAND));
     int32_t *retry, *over;
     HIPC(ws_alloc((void **)&B.ocnt, sizeof(int32_t) * mc, s));
-    HIPC(ws_alloc((void **)&B.od, sizeof(float) * mc * KNN_CAP, s));
-    HIPC(ws_alloc((void **)&B.oi, sizeof(int32_t) * mc * KNN_CAP, s));
+    HIPC(ws_alloc((void **)&B.oe, sizeof(uint2) * mc * KNN_CAP, s));
     HIPC(ws_alloc((void **)&retry, sizeof(int32_t) * (M + 1), s));
     HIPC(ws_alloc((void **)&over, sizeof(int32_t) * (M + 1), s));
     HIPC(hipMemsetAsync(retry, 0, sizeof(int32_t), s));
@@ -1609,8 +1597,7 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     if (nlist > 0)
         KNN_DISPATCH(list_sweep, s, Qh, Ql, Qn, (int64_t)nlist, Xh, Xl, Xn, N, ex, sl, list, true, cand, thr);
     HIPC(ws_free(B.ocnt, s));
-    HIPC(ws_free(B.od, s));
-    HIPC(ws_free(B.oi, s));
+    HIPC(ws_free(B.oe, s));
     HIPC(ws_free(retry, s));
     HIPC(ws_free(over, s));
     for (void *p : ttmp) HIPC(ws_free(p, s));
@@ -1879,8 +1866,7 @@ __global__ __launch_bounds__(256) void k_knn_filter_wide(const uint16_t *__restr
                                                          const uint16_t *__restrict__ Xl,
                                                          const float *__restrict__ Xn, int64_t N, int dp,
                                                          const float *__restrict__ Tin, int cap,
-                                                         int32_t *__restrict__ ocnt, float *__restrict__ od,
-                                                         int32_t *__restrict__ oi)
+                                                         int32_t *__restrict__ ocnt, uint2 *__restrict__ oe)
 {
     constexpr int KC = 128;
     constexpr int LDB = KC + 8;
@@ -1947,17 +1933,11 @@ __global__ __launch_bounds__(256) void k_knn_filter_wide(const uint16_t *__restr
             const float dB = fmaf(-2.0f, acc1[r], qn[r] + ny1);
             if (dA <= thrv[r] && cA < N) {
                 int p = atomicAdd(&ocnt[qrow], 1);
-                if (p < cap) {
-                    od[qrow * cap + p] = dA;
-                    oi[qrow * cap + p] = (int32_t)cA;
-                }
+                if (p < cap) oe[qrow * cap + p] = make_uint2(__float_as_uint(dA), (uint32_t)cA);
             }
             if (dB <= thrv[r] && cB < N) {
                 int p = atomicAdd(&ocnt[qrow], 1);
-                if (p < cap) {
-                    od[qrow * cap + p] = dB;
-                    oi[qrow * cap + p] = (int32_t)cB;
-                }
+                if (p < cap) oe[qrow * cap + p] = make_uint2(__float_as_uint(dB), (uint32_t)cB);
             }
         }
     }
@@ -1989,7 +1969,7 @@ __global__ __launch_bounds__(256) void k_knn_rerank(const int32_t *__restrict__ 
                                                     const float *__restrict__ Q, const float *__restrict__ X,
                                                     int d, int dp, int kappa, int excl, int cap,
                                                     const int32_t *__restrict__ ocnt,
-                                                    const int32_t *__restrict__ oi,
+                                                    const uint2 *__restrict__ oe,
                                                     const int32_t *__restrict__ idmap,
                                                     const int32_t *__restrict__ rowmap,
                                                     int32_t *__restrict__ idx, double *__restrict__ dist,
@@ -2011,7 +1991,7 @@ __global__ __launch_bounds__(256) void k_knn_rerank(const int32_t *__restrict__ 
         double D = INFINITY;
         int j = 0x7fffffff;
         if (c0 + lane < cnt) {
-            const int pos = oi[i * cap + c0 + lane];
+            const int pos = (int)oe[i * cap + c0 + lane].y;
             if (!(excl && pos == row)) {
                 D = canon_sqdist(Q + row * dp, X + (int64_t)pos * dp, d);
                 j = idmap ? idmap[pos] : pos;
@@ -2068,8 +2048,7 @@ void knn_fallback(const float *Q, const uint16_t *Qh, const uint16_t *Ql, const 
     uint16_t *Bh = (uint16_t *)ta(sizeof(uint16_t) * n * dp), *Bl = (uint16_t *)ta(sizeof(uint16_t) * n * dp);
     float *Bn = (float *)ta(sizeof(float) * n), *Bt = (float *)ta(sizeof(float) * n);
     int32_t *ocnt = (int32_t *)ta(sizeof(int32_t) * n);
-    float *od = (float *)ta(sizeof(float) * n * FCAP);
-    int32_t *oi = (int32_t *)ta(sizeof(int32_t) * n * FCAP);
+    uint2 *oe = (uint2 *)ta(sizeof(uint2) * n * FCAP);
     int32_t *over = (int32_t *)ta(sizeof(int32_t) * (n + 1));
     hipLaunchKernelGGL(k_gather_qrows, dim3((unsigned)n), dim3(128), 0, s, rows, n, dp, Qh, Ql, Qn, tbound, Bh, Bl,
                        Bn, Bt);
@@ -2078,17 +2057,17 @@ void knn_fallback(const float *Q, const uint16_t *Qh, const uint16_t *Ql, const 
     dim3 g((unsigned)((n + KB_M - 1) / KB_M)), block(256);
     if (dp > 128) {
         hipLaunchKernelGGL(k_knn_filter_wide, g, block, 0, s, Bh, Bl, Bn, n, Xh, Xl, Xn, N, dp, Bt, FCAP, ocnt,
-                           od, oi);
+                           oe);
     } else {
         // few rows: the points are split into column segments, one workgroup
         // each, appending to the rows' common outputs
         g.y = (unsigned)filter_segments(n, (N + KB_N - 1) / KB_N);
-        KNN_DISPATCH(launch_filter, g, block, s, Bh, Bl, Bn, n, Xh, Xl, Xn, N, 0, 0, Bt, FCAP, ocnt, od, oi,
+        KNN_DISPATCH(launch_filter, g, block, s, Bh, Bl, Bn, n, Xh, Xl, Xn, N, 0, 0, Bt, FCAP, ocnt, oe,
                      false);
     }
     HIPC(hipGetLastError());
     hipLaunchKernelGGL(k_knn_rerank, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, rows, n, Q, X, d, dp, kappa,
-                       exclude_self ? 1 : 0, FCAP, ocnt, oi, idmap, rowmap, idx, dist, over + 1, over);
+                       exclude_self ? 1 : 0, FCAP, ocnt, oe, idmap, rowmap, idx, dist, over + 1, over);
     HIPC(hipGetLastError());
     int32_t nover = 0;
     HIPC(hipMemcpyAsync(&nover, over, sizeof(int32_t), hipMemcpyDeviceToHost, s));
