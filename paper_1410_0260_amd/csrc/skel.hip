@@ -48,98 +48,94 @@ __global__ void k_cols(const SkelInst *__restrict__ inst, const int2 *__restrict
 }
 
 // G[q][c][t] = exp(-D(x_T[t], x_C[c]) / (2 h_c^2)), FP64.  Block per (node,
-// chunk of FG_C columns): the sampled-row points and the chunk's column points
-// are staged in LDS FG_K dimensions at a time; every thread keeps the partial
-// canonical distances of its (row, column) pairs and adds the dimensions in
-// increasing order, so D is the same sequential FP64 sum as everywhere else.
-constexpr int FG_T = 256;
+// chunk of FG_C columns), one thread per sampled row t (blockDim = ell rounded
+// up to whole waves): the thread holds FG_K coordinates of its row in
+// registers, the chunk's columns are staged in LDS as FP64 (every lane reads
+// the same column entry: a broadcast), and each of the thread's FG_C partial
+// distances adds the dimensions in increasing order, so D is the same
+// sequential FP64 sum as everywhere else (subtract, square, add; no fused
+// multiply-add).
 constexpr int FG_C = 8;           // columns per block
-constexpr int FG_K = 32;          // dimensions per LDS stage
-constexpr int FG_LT = FG_K + 1;   // LDS row stride of the sampled rows: lanes read different rows at
-                                  // the same offset, and an odd stride puts them in different banks
+constexpr int FG_K = 16;          // dimensions per stage
 constexpr int FG_MAXROW = 1024;
 
-// PP: (row, column) pairs per thread, >= rows * FG_C / FG_T
-template <int PP>
-__global__ __launch_bounds__(FG_T) void k_form_G(const SkelInst *__restrict__ inst,
-                                                 const int2 *__restrict__ items, int ell,
-                                                 const int32_t *__restrict__ colpos, int ncol_max,
-                                                 double *__restrict__ G)
+__global__ __launch_bounds__(FG_MAXROW) void k_form_G(const SkelInst *__restrict__ inst,
+                                                      const int2 *__restrict__ items, int ell,
+                                                      const int32_t *__restrict__ colpos, int ncol_max,
+                                                      double *__restrict__ G)
 {
 #pragma clang fp contract(off)
-    extern __shared__ float fsm[];
+    __shared__ __attribute__((aligned(16))) double sC[FG_K][FG_C];    // [dimension][column]
+    __shared__ int32_t sCid[FG_C];
     const int q = blockIdx.y;
     const int2 it = items[q];
     const SkelInst &I = inst[it.x];
     const int a = it.y;
     const float *Xt = I.Xt;
     const int dp = I.dp, d = I.d;
-    const int32_t *T = I.T, *T_cnt = I.T_cnt, *ncols = I.ncols;
     const double *hpos = I.hpos;
     const double h = I.h;
     const int c0 = blockIdx.x * FG_C;
-    const int nc = min(FG_C, ncols[a] - c0);
-    if (nc <= 0) return;
-    const int rows = T_cnt[a];
-    float *sT = fsm;                           // rows x FG_LT
-    float *sC = fsm + (size_t)rows * FG_LT;    // FG_C x FG_K
-    const int npair = rows * nc;
-    // the node's sampled-row ids and the block's column ids, read once
-    __shared__ int32_t sTid[FG_MAXROW], sCid[FG_C];
-    for (int t = threadIdx.x; t < rows; t += FG_T) sTid[t] = T[(int64_t)a * ell + t];
-    if (threadIdx.x < FG_C)
-        sCid[threadIdx.x] = colpos[(int64_t)q * ncol_max + c0 + min((int)threadIdx.x, nc - 1)];
-    double acc[PP];
+    const int nc = min(FG_C, I.ncols[a] - c0);
+    const int rows = I.T_cnt[a];
+    if (nc <= 0 || rows <= 0) return;
+    const int t = threadIdx.x;
+    if (t < FG_C) sCid[t] = colpos[(int64_t)q * ncol_max + c0 + min(t, nc - 1)];
+    // rows past `rows` repeat the last one and write nothing
+    const float *xr = Xt + (int64_t)I.T[(int64_t)a * ell + min(t, rows - 1)] * dp;
+    double acc[FG_C];
 #pragma unroll
-    for (int u = 0; u < PP; ++u) acc[u] = 0.0;
-    const int ne = rows * FG_K;
+    for (int c = 0; c < FG_C; ++c) acc[c] = 0.0;
     for (int k0 = 0; k0 < d; k0 += FG_K) {
         const int kk = min(FG_K, d - k0);
-        __syncthreads();
-        // coordinates k0 .. k0 + FG_K of the rows and columns, eight loads in
-        // flight per thread (indices clamped in bounds; entries past kk are
-        // never read)
-        for (int e0 = threadIdx.x; e0 < ne; e0 += FG_T * 8) {
-            float v[8];
+        // a whole stage: the row's coordinates first (their loads overlap the
+        // staging); rows are 16-byte aligned (dp is a multiple of 16)
+        float xv[FG_K];
+        if (kk == FG_K) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = min(e0 + FG_T * u, ne - 1);
-                const int t = e / FG_K, j = e % FG_K;
-                v[u] = Xt[(int64_t)sTid[t] * dp + min(k0 + j, dp - 1)];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + FG_T * u;
-                if (e < ne) sT[(e / FG_K) * FG_LT + e % FG_K] = v[u];
+            for (int j = 0; j < FG_K; j += 4) {
+                const float4 v = *reinterpret_cast<const float4 *>(xr + k0 + j);
+                xv[j] = v.x;
+                xv[j + 1] = v.y;
+                xv[j + 2] = v.z;
+                xv[j + 3] = v.w;
             }
         }
-        for (int e = threadIdx.x; e < nc * FG_K; e += FG_T) {
-            const int c = e / FG_K, j = e % FG_K;
-            sC[e] = Xt[(int64_t)sCid[c] * dp + min(k0 + j, dp - 1)];
+        __syncthreads();                       // sCid written; the previous stage's reads done
+        for (int e = t; e < FG_K * FG_C; e += blockDim.x) {
+            const int j = e / FG_C, c = e % FG_C;
+            sC[j][c] = (double)Xt[(int64_t)sCid[c] * dp + min(k0 + j, dp - 1)];
         }
         __syncthreads();
+        if (kk == FG_K) {
 #pragma unroll
-        for (int u = 0; u < PP; ++u) {
-            const int pi = threadIdx.x + FG_T * u;
-            if (pi < npair) {
-                const int t = pi % rows, c = pi / rows;
-                const float *x = sT + t * FG_LT, *y = sC + c * FG_K;
-                double s = acc[u];
-                for (int j = 0; j < kk; ++j) {
-                    double df = (double)x[j] - (double)y[j];
-                    s += df * df;
+            for (int j = 0; j < FG_K; ++j) {
+                const double xd = (double)xv[j];
+#pragma unroll
+                for (int c = 0; c < FG_C; ++c) {
+                    const double df = xd - sC[j][c];
+                    acc[c] = acc[c] + df * df;
                 }
-                acc[u] = s;
+            }
+        } else {
+            // the last, partial stage (k0 + j < d <= dp)
+#pragma unroll 1
+            for (int j = 0; j < kk; ++j) {
+                const double xd = (double)xr[k0 + j];
+#pragma unroll
+                for (int c = 0; c < FG_C; ++c) {
+                    const double df = xd - sC[j][c];
+                    acc[c] = acc[c] + df * df;
+                }
             }
         }
     }
+    if (t < rows) {
 #pragma unroll
-    for (int u = 0; u < PP; ++u) {
-        const int pi = threadIdx.x + FG_T * u;
-        if (pi < npair) {
-            const int t = pi % rows, c = pi / rows;
+        for (int c = 0; c < FG_C; ++c) {
+            if (c >= nc) break;
             const double hc = hpos ? hpos[sCid[c]] : h;
-            G[((int64_t)q * ncol_max + c0 + c) * ell + t] = exp(-acc[u] / (2.0 * hc * hc));
+            G[((int64_t)q * ncol_max + c0 + c) * ell + t] = exp(-acc[c] / (2.0 * hc * hc));
         }
     }
 }
@@ -974,14 +970,7 @@ void skeletonize_multi(const std::vector<askit_handle *> &hs, hipStream_t s)
     double *G = (double *)ta(per * batch);
     int32_t *colpos = (int32_t *)ta(sizeof(int32_t) * (size_t)ncm * batch);
     int2 *d_items = (int2 *)ta(sizeof(int2) * batch);
-    const size_t fg_lds = sizeof(float) * ((size_t)ell * FG_LT + (size_t)FG_C * FG_K);
     const size_t sv_lds = sizeof(double) * (size_t)std::min(smax, ell) * SV_C;
-    if (fg_lds > 64 * 1024) {
-        HIPC(hipFuncSetAttribute((const void *)k_form_G<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)fg_lds));
-        HIPC(hipFuncSetAttribute((const void *)k_form_G<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)fg_lds));
-    }
     if (sv_lds > 64 * 1024)
         HIPC(hipFuncSetAttribute((const void *)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)sv_lds));
@@ -1043,16 +1032,9 @@ void skeletonize_multi(const std::vector<askit_handle *> &hs, hipStream_t s)
             HIPC(hipMemcpyAsync(d_items, items.data(), sizeof(int2) * nb, hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_cols, dim3(nb), dim3(256), 0, s, d_inst, d_items, smax, ncm, colpos);
             {
-                dim3 gg((ncm + FG_C - 1) / FG_C, nb), gb(FG_T);
-                const int pp = (ell * FG_C + FG_T - 1) / FG_T;
-                if (pp <= 4)
-                    hipLaunchKernelGGL(k_form_G<4>, gg, gb, fg_lds, s, d_inst, d_items, ell, colpos, ncm, G);
-                else if (pp <= 8)
-                    hipLaunchKernelGGL(k_form_G<8>, gg, gb, fg_lds, s, d_inst, d_items, ell, colpos, ncm, G);
-                else if (pp <= 16)
-                    hipLaunchKernelGGL(k_form_G<16>, gg, gb, fg_lds, s, d_inst, d_items, ell, colpos, ncm, G);
-                else
-                    hipLaunchKernelGGL(k_form_G<32>, gg, gb, fg_lds, s, d_inst, d_items, ell, colpos, ncm, G);
+                dim3 gg((ncm + FG_C - 1) / FG_C, nb), gb((ell + 63) / 64 * 64);
+                hipLaunchKernelGGL(k_form_G, gg, gb, 0, s, d_inst, d_items, ell, colpos, ncm, G);
+                HIPC(hipGetLastError());
             }
             HIPC(hipEventRecord(q0, s));
             // every level: the node's columns in registers across a gang of
