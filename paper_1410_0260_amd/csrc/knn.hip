@@ -573,7 +573,7 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     const int half = lane >> 5, l32 = lane & 31;
     // listed sweep: workgroup i takes the piece items[i] = (row block, first
     // list position, tile count) of a block's tile list
-    const int4 item = (SYM && tlist) ? items[blockIdx.x] : int4{(int)blockIdx.x, 0, 0, 0};
+    const int4 item = tlist ? items[blockIdx.x] : int4{(int)blockIdx.x, 0, 0, 0};
     const int64_t bx = item.x;
     const int64_t q0 = bx * KB_M + wv * 32;     // local row (output segments)
 
@@ -618,10 +618,10 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
         t0 = (int64_t)blockIdx.y * per;
         ntiles = t0 < ntiles_all ? min(per, ntiles_all - t0) : 0;
     }
-    // SYM with tile lists: only the tiles that may hold a survivor (the block's
+    // tile lists: only the tiles that may hold a survivor (SYM: the block's
     // own two first), in increasing order; this workgroup's piece of them
     const int32_t *tl = nullptr;
-    if (SYM && tlist) {
+    if (tlist) {
         tl = tlist + toff[bx] + item.y;
         ntiles = item.z;
     }
@@ -638,20 +638,18 @@ __global__ __launch_bounds__(256, 2) void k_knn_filter(const uint16_t *__restric
     // a full chunk ahead; entries are read with a uniform lane index, so the
     // next tile's address never waits on a list load
     int lcur = 0, lnxt = 0;
-    if (SYM && tl) {
+    if (tl) {
         lcur = lane < nt32 ? tl[lane] : 0;
         lnxt = 64 + lane < nt32 ? tl[64 + lane] : 0;
     }
     auto tile_of = [&](int t) -> int {
-        if constexpr (SYM) {
-            if (tl) {
-                // positions are asked for in order 0, 1, 2, ...
-                if ((t & 63) == 0 && t > 0) {
-                    lcur = lnxt;
-                    lnxt = t + 64 + lane < nt32 ? tl[t + 64 + lane] : 0;
-                }
-                return __builtin_amdgcn_readlane(lcur, t & 63);
+        if (tl) {
+            // positions are asked for in order 0, 1, 2, ...
+            if ((t & 63) == 0 && t > 0) {
+                lcur = lnxt;
+                lnxt = t + 64 + lane < nt32 ? tl[t + 64 + lane] : 0;
             }
+            return __builtin_amdgcn_readlane(lcur, t & 63);
         }
         const int tt = t032 + t;
         return (tt >= nta32 ? tt - nta32 : tt) | (15 << 27);
@@ -1008,8 +1006,7 @@ static void launch_filter(dim3 g, dim3 b, hipStream_t s, const uint16_t *Qh, con
                            ocnt, oe, 0, tlist, toff, items);
     else
         hipLaunchKernelGGL((k_knn_filter<KS, false>), g, b, 0, s, Qh, Ql, Qn, M, Xh, Xl, Xn, N, ex, row0, T,
-                           cap, ocnt, oe, win, (const int32_t *)nullptr, (const int64_t *)nullptr,
-                           (const int4 *)nullptr);
+                           cap, ocnt, oe, win, tlist, toff, items);
 }
 
 __global__ void k_fill_f32(float *__restrict__ p, int64_t n, float v)
@@ -1107,7 +1104,7 @@ static void filter_select(int dp, hipStream_t s, const uint16_t *Qh, const uint1
     for (int64_t r0 = 0; r0 < M; r0 += chunk) {
         const int64_t m = std::min<int64_t>(chunk, M - r0);
         dim3 g((unsigned)((m + KB_M - 1) / KB_M), (unsigned)((sym || win > 0) ? 1 : filter_segments(m, ntl)));
-        if (sym && tlist) g = dim3((unsigned)nitems);      // one workgroup per list piece
+        if (tlist) g = dim3((unsigned)nitems);             // one workgroup per list piece
         HIPC(hipMemsetAsync(B.ocnt, 0, sizeof(int32_t) * m, s));
         if (ev) {
             ev->resize(ev->size() + 2);
@@ -1115,8 +1112,9 @@ static void filter_select(int dp, hipStream_t s, const uint16_t *Qh, const uint1
             HIPC(hipEventCreate(&ev->back()));
             HIPC(hipEventRecord((*ev)[ev->size() - 2], s));
         }
-        KNN_DISPATCH(launch_filter, g, dim3(256), s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, KNN_CAP, B.ocnt,
-                     B.oe, sym, win, tlist, toff, items);
+        if (!tlist || nitems > 0)
+            KNN_DISPATCH(launch_filter, g, dim3(256), s, Qh, Ql, Qn, m, Xh, Xl, Xn, N, ex, r0, thr, KNN_CAP, B.ocnt,
+                         B.oe, sym, win, tlist, toff, items);
         if (ev) HIPC(hipEventRecord(ev->back(), s));
         hipLaunchKernelGGL(k_knn_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, r0, KNN_CAP, B.nsel,
                            B.ocnt, B.oe, cand, thr, over ? over + 1 : nullptr, over);
@@ -1135,14 +1133,17 @@ static void widen(float *thr, int64_t M, hipStream_t s)
 // level the nsel-th smallest survivor bounds the row's nsel-th smallest
 // distance over the whole set (an upper bound: those are real points), and the
 // next, 8 times denser, level (a superset) keeps at least those nsel at that
-// bound -- about 8 nsel points.  Each step only lowers a valid bound.  The sample passes'
-// candidate lists (in cand) are scratch; thr leaves widened.  No self
-// exclusion: a row that is itself a sample point may count itself.
+// bound -- about 8 nsel points.  Each step only lowers a valid bound (a row
+// with fewer than nsel survivors keeps its threshold).  seeded: thr already
+// holds valid bounds to start from, else every row starts at +inf.  The
+// sample passes' candidate lists (in cand) are scratch; thr leaves widened.
+// No self exclusion: a row that is itself a sample point may count itself.
 static void sample_thresholds(int dp, hipStream_t s, const uint16_t *Qh, const uint16_t *Ql, const float *Qn,
                               int64_t M, const KnnSample &S, int64_t chunk, float *thr, const FilterBufs &B,
-                              int32_t *cand)
+                              int32_t *cand, bool seeded = false)
 {
-    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M, INFINITY);
+    if (!seeded)
+        hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, thr, M, INFINITY);
     for (int lv = 0; lv < S.levels; ++lv) {
         filter_select(dp, s, Qh, Ql, Qn, M, S.h[lv], S.l[lv], S.n[lv], S.rows[lv], 0, chunk, thr, B, cand,
                       nullptr, false, 0, nullptr);
@@ -1256,7 +1257,7 @@ __global__ __launch_bounds__(64) void k_tile_geom(const float *__restrict__ Xf, 
     }
     float tm = -INFINITY, nm = 0.0f;
     if (lane < n) {
-        tm = thr[p0 + lane];
+        tm = thr ? thr[p0 + lane] : -INFINITY;
         nm = Xn[p0 + lane];
     } else {
         r2 = 0.0;
@@ -1269,21 +1270,24 @@ __global__ __launch_bounds__(64) void k_tile_geom(const float *__restrict__ Xf, 
     if (lane == 0) geo[t] = TileGeom{sqrt(r2) * (1.0 + 1e-9) + 1e-30, tm, nm};
 }
 
-// One workgroup per row block b (row groups 4b..4b+3, tiles 2b and 2b+1):
-// for every tile t >= 2b, bit (t - 2b) of the block's mask word w (w = the
-// wave) is set when that wave must sweep it; cnt[b] = tiles any wave needs,
-// wcnt[b] = (wave, tile) sweeps.
+// One workgroup per row block b (row groups 4b..4b+3): for every tile
+// t >= t0 (sym: t0 = 2b, the block's own two tiles, always kept; else 0),
+// bit (t - t0) of the block's mask word w (w = the wave) is set when that
+// wave must sweep it; cnt[b] = tiles any wave needs, wcnt[b] = (wave, tile)
+// sweeps.  Without sym the tiles' own thresholds play no part (only the rows
+// take survivors).
 __global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen_g, const TileGeom *__restrict__ geo_g,
                                                    int64_t ngroups, const float *__restrict__ cen_t,
                                                    const TileGeom *__restrict__ geo_t, int dp, int d,
-                                                   int64_t ntiles, double g, const int64_t *__restrict__ moff,
+                                                   int64_t ntiles, double g, int sym,
+                                                   const int64_t *__restrict__ moff,
                                                    uint64_t *__restrict__ mask, int64_t *__restrict__ cnt,
                                                    int64_t *__restrict__ wcnt)
 {
     __shared__ __attribute__((aligned(16))) float ca[4][1024];
     __shared__ int wsum[4], wwsum[4];
-    const int64_t b = blockIdx.x, t0 = 2 * b, g0 = 4 * b;
-    const int nown = (int)min<int64_t>(2, ntiles - t0);
+    const int64_t b = blockIdx.x, t0 = sym ? 2 * b : 0, g0 = 4 * b;
+    const int nown = sym ? (int)min<int64_t>(2, ntiles - t0) : 0;
     const int ng = (int)min<int64_t>(4, ngroups - g0);
     for (int k = threadIdx.x; k < d; k += 256)
         for (int w = 0; w < 4; ++w) ca[w][k] = cen_g[(g0 + min(w, ng - 1)) * dp + k];
@@ -1333,7 +1337,7 @@ __global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen
                 for (int w = 0; w < 4; ++w) {
                     if (w >= ng) break;
                     const double L = sqrt((double)sw[w]) * (1.0 - 1e-5) - gw[w].r - gt.r;
-                    const double bound = ((double)fmaxf(gw[w].tmax, gt.tmax) +
+                    const double bound = ((double)(sym ? fmaxf(gw[w].tmax, gt.tmax) : gw[w].tmax) +
                                           g * ((double)gw[w].nmax + (double)gt.nmax)) * (1.0 + 1e-6);
                     keep[w] = !(L > 0.0 && L * L > bound);
                 }
@@ -1367,10 +1371,10 @@ __global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen
 // Expands each block's masks into its list of entries (increasing tile
 // order): tile | (wave mask << 27).
 __global__ __launch_bounds__(64) void k_tile_list(const uint64_t *__restrict__ mask, const int64_t *__restrict__ moff,
-                                                  int64_t ntiles, const int64_t *__restrict__ toff,
+                                                  int64_t ntiles, int sym, const int64_t *__restrict__ toff,
                                                   int32_t *__restrict__ tlist)
 {
-    const int64_t b = blockIdx.x, t0 = 2 * b;
+    const int64_t b = blockIdx.x, t0 = sym ? 2 * b : 0;
     const int64_t nw = (ntiles - t0 + 63) / 64;
     int64_t o = toff[b];
     const int lane = threadIdx.x;
@@ -1386,16 +1390,19 @@ __global__ __launch_bounds__(64) void k_tile_list(const uint64_t *__restrict__ m
     }
 }
 
-// Builds the tile lists of the symmetric sweep (FP32 points Xf in sweep
-// order, stride dp; thr the rows' thresholds).  Returns false (no lists) when
-// they do not apply.  Allocations go to tmp.
-static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const float *thr, const float *Xn,
+// Builds the tile lists of a sweep of M rows (FP32 coordinates Xr, stride
+// dp, thresholds thr_r, FP32 norms Xn_r) over N points (Xp, thr_p, Xn_p):
+// sym, the symmetric sweep of the point set against itself (rows = points),
+// or the rows against every tile.  Returns false (no lists) when they do not
+// apply.  Allocations go to tmp.
+static bool build_tile_lists(const float *Xr, const float *thr_r, const float *Xn_r, int64_t M, const float *Xp,
+                             const float *thr_p, const float *Xn_p, int64_t N, int dp, int d, bool sym,
                              int32_t *&tlist, int64_t *&toff, int64_t &kept, int64_t &kept_waves, int4 *&items,
                              int64_t &nitems, std::vector<void *> &tmp, hipStream_t s)
 {
     static_assert(KB_M == 2 * KB_N && KB_M == 4 * 32, "a row block is two tiles and four waves of 32 rows");
-    const int64_t ntiles = (N + KB_N - 1) / KB_N, nblk = (N + KB_M - 1) / KB_M, ngroups = (N + 31) / 32;
-    if (!Xf || d > 128 || ntiles > TL_TILE_MASK) return false;
+    const int64_t ntiles = (N + KB_N - 1) / KB_N, nblk = (M + KB_M - 1) / KB_M, ngroups = (M + 31) / 32;
+    if (!Xr || !Xp || M <= 0 || d > 128 || ntiles > TL_TILE_MASK) return false;
     auto ta = [&](size_t b) {
         void *p;
         HIPC(ws_alloc(&p, std::max<size_t>(b, 16), s));
@@ -1406,7 +1413,7 @@ static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const fl
     int64_t words = 0;
     for (int64_t b = 0; b < nblk; ++b) {
         hmoff[b] = words;
-        words += (ntiles - 2 * b + 63) / 64;
+        words += (ntiles - (sym ? 2 * b : 0) + 63) / 64;
     }
     hmoff[nblk] = words;
     float *cen_t = (float *)ta(sizeof(float) * ntiles * dp);
@@ -1419,12 +1426,13 @@ static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const fl
     int64_t *wcnt = (int64_t *)ta(sizeof(int64_t) * nblk);
     toff = (int64_t *)ta(sizeof(int64_t) * (nblk + 1));
     HIPC(hipMemcpyAsync(moff, hmoff.data(), sizeof(int64_t) * (nblk + 1), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_tile_geom<64>, dim3((unsigned)ntiles), dim3(64), 0, s, Xf, dp, d, N, thr, Xn, cen_t, geo_t);
-    hipLaunchKernelGGL(k_tile_geom<32>, dim3((unsigned)ngroups), dim3(64), 0, s, Xf, dp, d, N, thr, Xn, cen_g,
+    hipLaunchKernelGGL(k_tile_geom<64>, dim3((unsigned)ntiles), dim3(64), 0, s, Xp, dp, d, N, thr_p, Xn_p, cen_t,
+                       geo_t);
+    hipLaunchKernelGGL(k_tile_geom<32>, dim3((unsigned)ngroups), dim3(64), 0, s, Xr, dp, d, M, thr_r, Xn_r, cen_g,
                        geo_g);
     const double g = 2.0 * (3.1 * ldexp(1.0, -16) + (4.0 * dp + 8.0) * ldexp(1.0, -24));
     hipLaunchKernelGGL(k_tile_mask, dim3((unsigned)nblk), dim3(256), 0, s, cen_g, geo_g, ngroups, cen_t, geo_t, dp, d,
-                       ntiles, g, moff, mask, cnt, wcnt);
+                       ntiles, g, sym ? 1 : 0, moff, mask, cnt, wcnt);
     HIPC(hipGetLastError());
     std::vector<int64_t> hc(nblk), ho(nblk + 1), hw(nblk);
     HIPC(hipMemcpyAsync(hc.data(), cnt, sizeof(int64_t) * nblk, hipMemcpyDeviceToHost, s));
@@ -1439,11 +1447,13 @@ static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const fl
     // regions keep many tiles), so each list is cut into pieces of at most
     // KNN_PIECE tiles and the pieces are launched longest first: the
     // workgroups that start last are the short ones, and no single list sets
-    // the sweep's length.
+    // the sweep's length.  A sweep of few rows takes shorter pieces (about
+    // 2048 of them in all), so that it still fills the device.
+    const int64_t piece = sym ? KNN_PIECE : std::max<int64_t>(64, std::min<int64_t>(KNN_PIECE, kept / 2048 + 1));
     std::vector<int4> hi;
     for (int64_t b = 0; b < nblk; ++b) {
         const int64_t c = hc[b];
-        const int64_t np = (c + KNN_PIECE - 1) / KNN_PIECE;
+        const int64_t np = (c + piece - 1) / piece;
         for (int64_t q = 0; q < np; ++q) {
             const int64_t a0 = c * q / np, a1 = c * (q + 1) / np;
             hi.push_back(int4{(int)b, (int)a0, (int)(a1 - a0), 0});
@@ -1455,7 +1465,8 @@ static bool build_tile_lists(const float *Xf, int dp, int d, int64_t N, const fl
     if (nitems > 0) HIPC(hipMemcpyAsync(items, hi.data(), sizeof(int4) * nitems, hipMemcpyHostToDevice, s));
     tlist = (int32_t *)ta(sizeof(int32_t) * std::max<int64_t>(kept, 1));
     HIPC(hipMemcpyAsync(toff, ho.data(), sizeof(int64_t) * (nblk + 1), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_tile_list, dim3((unsigned)nblk), dim3(64), 0, s, mask, moff, ntiles, toff, tlist);
+    hipLaunchKernelGGL(k_tile_list, dim3((unsigned)nblk), dim3(64), 0, s, mask, moff, ntiles, sym ? 1 : 0, toff,
+                       tlist);
     HIPC(hipGetLastError());
     HIPC(hipStreamSynchronize(s));          // the host tables are released on return
     return true;
@@ -1529,7 +1540,8 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
     int64_t *toff = nullptr, kept = 0, kept_waves = 0, nitems = 0;
     int4 *items = nullptr;
     if (sym && !std::getenv("ASKIT_KNN_NO_SKIP") &&
-        build_tile_lists(Xf, dp, d, N, thr, Xn, tlist, toff, kept, kept_waves, items, nitems, ttmp, s)) {
+        build_tile_lists(Xf, thr, Xn, N, Xf, thr, Xn, N, dp, d, true, tlist, toff, kept, kept_waves, items, nitems,
+                         ttmp, s)) {
         if (tiles_swept) *tiles_swept = kept_waves;
     } else {
         tlist = nullptr;
@@ -1576,10 +1588,38 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
         HIPC(ws_alloc((void **)&Bn, sizeof(float) * n, s));
         HIPC(ws_alloc((void **)&tc, sizeof(float) * n, s));
         HIPC(ws_alloc((void **)&cc, sizeof(int32_t) * n * KNN_CAND, s));
+        // the rows in sweep (tree) order, so that the 32 rows of a wave lie
+        // close together and their bounding balls skip most tiles
+        {
+            std::vector<int32_t> hl(n);
+            HIPC(hipMemcpyAsync(hl.data(), retry + 1, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            std::sort(hl.begin(), hl.end());
+            HIPC(hipMemcpyAsync(retry + 1, hl.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+            HIPC(hipStreamSynchronize(s));
+        }
         hipLaunchKernelGGL(k_gather_qrows, dim3((unsigned)n), dim3(128), 0, s, list, n, dp, Qh, Ql, Qn, thr, Bh, Bl,
                            Bn, tc);
-        sample_thresholds(dp, s, Bh, Bl, Bn, n, *samp, n, tc, B, cc);
-        filter_select(dp, s, Bh, Bl, Bn, n, Xh, Xl, Xn, N, 0, n, tc, B, cc, nullptr, false, 0, nullptr);
+        // seeded with the bound the selection left (the nsel-th of the
+        // row's stored survivors, real points, widened)
+        sample_thresholds(dp, s, Bh, Bl, Bn, n, *samp, n, tc, B, cc, true);
+        // the filter over every point, only on the tiles the rows' sampled
+        // thresholds can reach (the same survivors as the full sweep)
+        std::vector<void *> rtmp;
+        int32_t *rl = nullptr;
+        int64_t *ro = nullptr, rkept = 0, rkw = 0, rni = 0;
+        int4 *ri = nullptr;
+        bool rlists = false;
+        if (Xf && !std::getenv("ASKIT_KNN_NO_SKIP")) {
+            float *Bf;
+            HIPC(ws_alloc((void **)&Bf, sizeof(float) * n * dp, s));
+            rtmp.push_back(Bf);
+            gather_rows(Xf, list, n, dp, Bf, s);
+            rlists = build_tile_lists(Bf, tc, Bn, n, Xf, nullptr, Xn, N, dp, d, false, rl, ro, rkept, rkw, ri, rni,
+                                      rtmp, s);
+        }
+        filter_select(dp, s, Bh, Bl, Bn, n, Xh, Xl, Xn, N, 0, n, tc, B, cc, nullptr, false, 0, nullptr,
+                      rlists ? rl : nullptr, rlists ? ro : nullptr, rlists ? ri : nullptr, rni);
         hipLaunchKernelGGL(k_scatter_retry, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, list, cc, tc,
                            B.ocnt, KNN_CAP, cand, thr, over + 1, over);
         HIPC(hipGetLastError());
@@ -1591,6 +1631,7 @@ void knn_candidates(const uint16_t *Qh, const uint16_t *Ql, const float *Qn, int
         HIPC(ws_free(Bn, s));
         HIPC(ws_free(tc, s));
         HIPC(ws_free(cc, s));
+        for (void *q : rtmp) HIPC(ws_free(q, s));
     }
     // the rest: list sweep over every point on the compacted rows, seeded with
     // the bound the selection left
