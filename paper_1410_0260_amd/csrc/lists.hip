@@ -306,15 +306,31 @@ __global__ __launch_bounds__(64) void k_sample(const Node *__restrict__ nodes, i
             }
         __syncthreads();
     } else if (r > 0) {
+        // 64 draws at a time, draw t0 + i in lane i.  One at a time, a draw is
+        // rejected exactly when its position is already listed; within a
+        // batch that is: listed before the batch, or equal to an earlier draw
+        // of the batch (which was either taken or itself rejected as listed).
+        // The accepted draws, appended in draw order up to the r-th, are
+        // therefore those of the one-at-a-time loop.
         int g = 0;
-        for (uint64_t t = 0; g < r; ++t) {
-            uint64_t z = sm64(base, t);
-            int64_t v = (int64_t)(z % (uint64_t)(N - na));
-            int32_t pos = (int32_t)(v < nd.lo ? v : v + na);
-            if (wave_member(sT, c + g, pos, lane)) continue;
-            if (lane == 0) sT[c + g] = pos;
+        for (uint64_t t0 = 0; g < r; t0 += 64) {
+            const uint64_t z = sm64(base, t0 + (uint64_t)lane);
+            const int64_t v = (int64_t)(z % (uint64_t)(N - na));
+            const int32_t pos = (int32_t)(v < nd.lo ? v : v + na);
+            const int n0 = c + g;
+            bool dup = false;
+            for (int i = 0; i < n0; ++i) dup |= sT[i] == pos;
+            for (int j = 0; j < 63; ++j) {
+                const int32_t pj = __shfl(pos, j);        // every lane takes part
+                dup |= j < lane && pj == pos;
+            }
+            const uint64_t ok = __ballot(!dup);
+            const int before = __popcll(ok & ((1ull << lane) - 1ull));
+            const int take = (int)min<int64_t>((int64_t)__popcll(ok), r - g);
             __syncthreads();
-            ++g;
+            if (!dup && before < take) sT[n0 + before] = pos;
+            g += take;
+            __syncthreads();
         }
     }
     const int tot = c + (int)max((int64_t)0, r);
