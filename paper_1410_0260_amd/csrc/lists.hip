@@ -18,12 +18,16 @@ namespace askit {
 // the chunk that holds its smallest key.  An internal node reduces the
 // union of its children's stored lists (Alg. 2, second line).
 // ====================================================================
-constexpr int NL_CAP = 2048;                // 48 KiB of LDS: three workgroups per CU
+// CAP entries of LDS buffer per workgroup: 1024 (24 KiB, six workgroups per
+// CU) when a chunk of neighbours plus a kept list (l + kappa) and the union
+// of two children's lists (2 l) fit, else 2048 (48 KiB).
+constexpr int NL_CAP = 2048;                // largest buffer
 constexpr int NL_T = 256;
 
+template <int CAP>
 struct NLShared {
-    uint64_t k[2][NL_CAP];
-    int32_t p[2][NL_CAP];
+    uint64_t k[2][CAP];
+    int32_t p[2][CAP];
     int32_t cnt;
     int32_t wsum[NL_T / 64];
 };
@@ -59,7 +63,8 @@ __device__ void bitonic_lds(uint64_t *k, int32_t *p, int n2)
 }
 
 // Entries in buffer 0 [0, n); result (<= ell) in buffer 0 [0, return).
-__device__ int reduce_list(NLShared &S, int n, int ell)
+template <int CAP>
+__device__ int reduce_list(NLShared<CAP> &S, int n, int ell)
 {
     int n2 = 1;
     while (n2 < n) n2 <<= 1;
@@ -113,6 +118,7 @@ __device__ int reduce_list(NLShared &S, int n, int ell)
     return keep;
 }
 
+template <int CAP>
 __global__ __launch_bounds__(NL_T) void k_leaf_nlists(const Node *__restrict__ nodes,
                                                       const int32_t *__restrict__ leaves,
                                                       const int32_t *__restrict__ perm,
@@ -123,10 +129,10 @@ __global__ __launch_bounds__(NL_T) void k_leaf_nlists(const Node *__restrict__ n
                                                       double *__restrict__ nl_key,
                                                       int32_t *__restrict__ nl_cnt)
 {
-    __shared__ NLShared S;
+    __shared__ NLShared<CAP> S;
     const int a = leaves[blockIdx.x];
     const Node nd = nodes[a];
-    const int chunk = max(1, (NL_CAP - ell) / kappa);
+    const int chunk = max(1, (CAP - ell) / kappa);
     // Once the reduced list holds ell entries its ell-th (key, position) bounds
     // the final ell-th from above (more entries only lower a position's key or
     // add positions), so entries at or above it are dropped when read; the
@@ -153,7 +159,7 @@ __global__ __launch_bounds__(NL_T) void k_leaf_nlists(const Node *__restrict__ n
         __syncthreads();
         const int n = S.cnt;
         __syncthreads();
-        if (c1 >= nd.hi || n + chunk * kappa > NL_CAP) {
+        if (c1 >= nd.hi || n + chunk * kappa > CAP) {
             cur = reduce_list(S, n, ell);
             if (cur == ell) {
                 tk = S.k[0][ell - 1];
@@ -170,13 +176,14 @@ __global__ __launch_bounds__(NL_T) void k_leaf_nlists(const Node *__restrict__ n
     if (threadIdx.x == 0) nl_cnt[a] = cur;
 }
 
+template <int CAP>
 __global__ __launch_bounds__(NL_T) void k_internal_nlists(const Node *__restrict__ nodes,
                                                           const int32_t *__restrict__ ids, int ell,
                                                           int32_t *__restrict__ nl_pos,
                                                           double *__restrict__ nl_key,
                                                           int32_t *__restrict__ nl_cnt)
 {
-    __shared__ NLShared S;
+    __shared__ NLShared<CAP> S;
     const int a = ids[blockIdx.x];
     const Node nd = nodes[a];
     if (threadIdx.x == 0) S.cnt = 0;
@@ -214,9 +221,15 @@ void build_node_lists(askit_handle *h, hipStream_t s)
     int32_t *d_ids;
     HIPC(ws_alloc((void **)&d_ids, sizeof(int32_t) * nn, s));
     HIPC(hipMemcpyAsync(d_ids, lv.data(), sizeof(int32_t) * lv.size(), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_leaf_nlists, dim3((unsigned)lv.size()), dim3(NL_T), 0, s, h->d_nodes, d_ids,
-                       h->perm, h->iperm, h->knn_idx, h->knn_d, h->kappa, h->ell, h->nl_pos,
-                       h->nl_key, h->nl_cnt);
+    const bool small = h->ell + h->kappa <= NL_CAP / 2 && 2 * h->ell <= NL_CAP / 2;
+    if (small)
+        hipLaunchKernelGGL(k_leaf_nlists<NL_CAP / 2>, dim3((unsigned)lv.size()), dim3(NL_T), 0, s, h->d_nodes, d_ids,
+                           h->perm, h->iperm, h->knn_idx, h->knn_d, h->kappa, h->ell, h->nl_pos, h->nl_key,
+                           h->nl_cnt);
+    else
+        hipLaunchKernelGGL(k_leaf_nlists<NL_CAP>, dim3((unsigned)lv.size()), dim3(NL_T), 0, s, h->d_nodes, d_ids,
+                           h->perm, h->iperm, h->knn_idx, h->knn_d, h->kappa, h->ell, h->nl_pos, h->nl_key,
+                           h->nl_cnt);
     HIPC(hipGetLastError());
     // internal nodes bottom-up, root excluded (its list is empty by definition)
     std::vector<int32_t> ids;
@@ -227,8 +240,12 @@ void build_node_lists(askit_handle *h, hipStream_t s)
         if (ids.empty()) continue;
         HIPC(hipStreamSynchronize(s));   // d_ids is reused on the host side
         HIPC(hipMemcpyAsync(d_ids, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_internal_nlists, dim3((unsigned)ids.size()), dim3(NL_T), 0, s,
-                           h->d_nodes, d_ids, h->ell, h->nl_pos, h->nl_key, h->nl_cnt);
+        if (small)
+            hipLaunchKernelGGL(k_internal_nlists<NL_CAP / 2>, dim3((unsigned)ids.size()), dim3(NL_T), 0, s,
+                               h->d_nodes, d_ids, h->ell, h->nl_pos, h->nl_key, h->nl_cnt);
+        else
+            hipLaunchKernelGGL(k_internal_nlists<NL_CAP>, dim3((unsigned)ids.size()), dim3(NL_T), 0, s,
+                               h->d_nodes, d_ids, h->ell, h->nl_pos, h->nl_key, h->nl_cnt);
         HIPC(hipGetLastError());
     }
     HIPC(hipStreamSynchronize(s));

@@ -44,6 +44,8 @@ CASES = {
     "small-pool": (300, 5, 3, 3, O.Params(m=32, kappa=8, smax=64, ell=160, tau=1e-6, h=0.9, seed=17)),
     # the paper's fixed-rank mode: tau = 0, rank s at every node
     "fixed-rank": (3000, 6, 4, 3, O.Params(m=64, kappa=16, smax=16, ell=36, tau=0.0, h=0.6, seed=29)),
+    # l above 512: the node lists take the 2048-entry buffer form
+    "long-lists": (3000, 6, 3, 3, O.Params(m=64, kappa=16, smax=32, ell=560, tau=1e-6, h=0.8, seed=31)),
     # level restriction: only the two deepest levels may be pruned
     "level-restricted": (5000, 10, 4, 5, O.Params(m=64, kappa=12, smax=32, ell=52, tau=1e-6, h=0.8, seed=23,
                                                  prune_levels=2)),
