@@ -745,25 +745,34 @@ __global__ __launch_bounds__(256) void k_solve_reg(double *__restrict__ Gall, in
         const double v = pc[min(u, ell - 1)];
         P[i] = (cok && u < k) ? v : 0.0;
     }
-#pragma clang loop unroll(full)
-    for (int ib = SR_R - 1; ib >= 0; --ib) {
-        if (SR_L * ib >= k) continue;
-        __syncthreads();
-        static_assert((SR_L * SR_L * SR_R) % 256 == 0, "the staging loop covers the block exactly");
-        double v[SR_L * SR_L * SR_R / 256];
+    // R's columns 8 ib .. 8 ib + 7: loaded into registers one group ahead
+    // (their loads are in flight while the previous group is solved), then
+    // stored to LDS
+    static_assert((SR_L * SR_L * SR_R) % 256 == 0, "the staging loop covers the block exactly");
+    constexpr int SV = SR_L * SR_L * SR_R / 256;
+    auto load_group = [&](int ib, double (&v)[SV]) {
 #pragma unroll
-        for (int r = 0; r < SR_L * SR_L * SR_R / 256; ++r) {
+        for (int r = 0; r < SV; ++r) {
             const int e = tid + 256 * r;
             const int cc = e / (SR_L * SR_R), u = e % (SR_L * SR_R), t = SR_L * ib + cc;
             v[r] = G[(int64_t)min(t, k - 1) * ell + min(u, ell - 1)];
         }
+    };
+    const int ibt = (k - 1) / SR_L;              // the last group holding a column of R11
+    double v[SV];
+    load_group(ibt, v);
+#pragma clang loop unroll(full)
+    for (int ib = SR_R - 1; ib >= 0; --ib) {
+        if (ib > ibt) continue;
+        __syncthreads();
 #pragma unroll
-        for (int r = 0; r < SR_L * SR_L * SR_R / 256; ++r) {
+        for (int r = 0; r < SV; ++r) {
             const int e = tid + 256 * r;
             const int cc = e / (SR_L * SR_R), u = e % (SR_L * SR_R), t = SR_L * ib + cc;
             sR[e] = (t < k && u <= t) ? v[r] : 0.0;
         }
         __syncthreads();
+        if (ib > 0) load_group(ib - 1, v);
         for (int jj = SR_L - 1; jj >= 0; --jj) {
             const int t = SR_L * ib + jj;
             if (t >= k) continue;
