@@ -817,11 +817,32 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ Gal
         int t = e / dp, j = e % dp;
         Xs[((int64_t)a * smax + t) * dp + j] = Xt[(int64_t)cp[pv[t]] * dp + j];
     }
+    // P (row t, column c) = R12 solution (G column k + c, row t) in FP32,
+    // through 64 x 64 tiles in LDS: reads run down G's columns and writes
+    // along P's rows (both contiguous); loads are unconditional (indices
+    // clamped inside the block) so that all of a tile's are in flight at once
+    __shared__ float tP[64][65];
     float *Pa = I.P + I.pslot[a];
-    for (int e = threadIdx.x; e < k * nr; e += blockDim.x) {
-        int t = e / nr, c = e % nr;
-        Pa[e] = (float)G[(int64_t)(k + c) * ell + t];
-    }
+    const int l64 = threadIdx.x & 63, w4 = threadIdx.x >> 6;
+    for (int t0 = 0; t0 < k; t0 += 64)
+        for (int c0 = 0; c0 < nr; c0 += 64) {
+            const int tr = min(t0 + l64, k - 1);
+            float v[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int c = min(c0 + w4 + 4 * i, nr - 1);
+                v[i] = (float)G[(int64_t)(k + c) * ell + tr];
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) tP[w4 + 4 * i][l64] = v[i];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int t = t0 + w4 + 4 * i, c = c0 + l64;
+                if (t < k && c < nr) Pa[(int64_t)t * nr + c] = tP[l64][w4 + 4 * i];
+            }
+            __syncthreads();
+        }
 }
 
 // Scratch of the gang factorization: per gang two rounds of W candidate
