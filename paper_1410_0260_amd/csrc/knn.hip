@@ -1270,101 +1270,135 @@ __global__ __launch_bounds__(64) void k_tile_geom(const float *__restrict__ Xf, 
     if (lane == 0) geo[t] = TileGeom{sqrt(r2) * (1.0 + 1e-9) + 1e-30, tm, nm};
 }
 
-// One workgroup per row block b (row groups 4b..4b+3): for every tile
-// t >= t0 (sym: t0 = 2b, the block's own two tiles, always kept; else 0),
-// bit (t - t0) of the block's mask word w (w = the wave) is set when that
-// wave must sweep it; cnt[b] = tiles any wave needs, wcnt[b] = (wave, tile)
-// sweeps.  Without sym the tiles' own thresholds play no part (only the rows
-// take survivors).
+// Row blocks b = TM_B q .. TM_B q + TM_B - 1 per workgroup q (row groups 4b ..
+// 4b + 3 each), so that each tile's centre read serves 4 TM_B groups.  A
+// block's mask words cover the tiles from tA(b) on (sym: 2b rounded down to a
+// multiple of 64, the same for the TM_B blocks of a workgroup; else 0): bit
+// (t - tA) of word w (w = the wave) is set when that wave must sweep tile t.
+// sym: tiles before the block's own two are never set, its own two always
+// are.  cnt[b] += tiles any wave needs, wcnt[b] += (wave, tile) sweeps (both
+// start at zero).  The tiles are split in ranges of `span` (a multiple of
+// 256) over gridDim.y, so that a sweep of few rows still fills the device.
+// Without sym the tiles' own thresholds play no part (only the rows take
+// survivors).
+constexpr int TM_B = 4;
+static_assert(64 % (2 * TM_B) == 0, "the blocks of a workgroup share their first mask word");
+
+__device__ __forceinline__ int64_t tile_mask_base(int64_t b, int sym) { return sym ? (2 * b) & ~(int64_t)63 : 0; }
+
 __global__ __launch_bounds__(256) void k_tile_mask(const float *__restrict__ cen_g, const TileGeom *__restrict__ geo_g,
-                                                   int64_t ngroups, const float *__restrict__ cen_t,
+                                                   int64_t ngroups, int64_t nblk, const float *__restrict__ cen_t,
                                                    const TileGeom *__restrict__ geo_t, int dp, int d,
-                                                   int64_t ntiles, double g, int sym,
+                                                   int64_t ntiles, double g, int sym, int64_t span,
                                                    const int64_t *__restrict__ moff,
                                                    uint64_t *__restrict__ mask, int64_t *__restrict__ cnt,
                                                    int64_t *__restrict__ wcnt)
 {
-    __shared__ __attribute__((aligned(16))) float ca[4][1024];
-    __shared__ int wsum[4], wwsum[4];
-    const int64_t b = blockIdx.x, t0 = sym ? 2 * b : 0, g0 = 4 * b;
-    const int nown = sym ? (int)min<int64_t>(2, ntiles - t0) : 0;
-    const int ng = (int)min<int64_t>(4, ngroups - g0);
-    for (int k = threadIdx.x; k < d; k += 256)
-        for (int w = 0; w < 4; ++w) ca[w][k] = cen_g[(g0 + min(w, ng - 1)) * dp + k];
+    constexpr int NG = 4 * TM_B;
+    __shared__ __attribute__((aligned(16))) float ca[NG][128];
+    __shared__ TileGeom sg[NG];
+    __shared__ int wsum[TM_B][4], wwsum[TM_B][4];
+    const int64_t b0 = (int64_t)blockIdx.x * TM_B, g0 = 4 * b0;
+    const int nb = (int)min<int64_t>(TM_B, nblk - b0);
+    const int ng = (int)min<int64_t>(NG, ngroups - g0);
+    const int64_t tA = tile_mask_base(b0, sym);
+    for (int e = threadIdx.x; e < NG * d; e += 256) {
+        const int w = e / d, k = e % d;
+        ca[w][k] = cen_g[(g0 + min(w, ng - 1)) * dp + k];
+    }
+    if (threadIdx.x < NG) sg[threadIdx.x] = geo_g[g0 + min((int)threadIdx.x, ng - 1)];
     __syncthreads();
-    TileGeom gw[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t total[TM_B], wtotal[TM_B];
 #pragma unroll
-    for (int w = 0; w < 4; ++w) gw[w] = geo_g[g0 + min(w, ng - 1)];
-    int64_t total = 0, wtotal = 0;
-    for (int64_t base = t0; base < ntiles; base += 256) {
+    for (int i = 0; i < TM_B; ++i) total[i] = wtotal[i] = 0;
+    const int64_t tbeg = tA + (int64_t)blockIdx.y * span, tend = min(ntiles, tbeg + span);
+    for (int64_t base = tbeg; base < tend; base += 256) {
         const int64_t t = base + threadIdx.x;
-        bool keep[4] = {false, false, false, false};
-        if (t < ntiles) {
-            if (t < t0 + nown) {
-                for (int w = 0; w < 4; ++w) keep[w] = w < ng;
-            } else {
-                const TileGeom gt = geo_t[t];
-                // squared centre distances in FP32, four coordinates per load
-                // (rows are 16-byte aligned); the test shrinks them by a
-                // relative 1e-5, above the FP32 rounding bound (d + 2) 2^-24
-                // for d <= 128
-                float sw[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                const float *ct = cen_t + t * dp;
-                int k = 0;
-                for (; k + 4 <= d; k += 4) {
-                    const float4 c = *reinterpret_cast<const float4 *>(ct + k);
+        // squared centre distances to the NG groups in FP32, four coordinates
+        // per load (rows are 16-byte aligned), each group's sum in coordinate
+        // order
+        float sw[NG];
 #pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        const float4 q = *reinterpret_cast<const float4 *>(&ca[w][k]);
-                        float u = q.x - c.x;
-                        sw[w] = fmaf(u, u, sw[w]);
-                        u = q.y - c.y;
-                        sw[w] = fmaf(u, u, sw[w]);
-                        u = q.z - c.z;
-                        sw[w] = fmaf(u, u, sw[w]);
-                        u = q.w - c.w;
-                        sw[w] = fmaf(u, u, sw[w]);
-                    }
-                }
-                for (; k < d; ++k) {
-                    const float c = ct[k];
-                    for (int w = 0; w < 4; ++w) {
-                        const float u = ca[w][k] - c;
-                        sw[w] = fmaf(u, u, sw[w]);
-                    }
-                }
+        for (int w = 0; w < NG; ++w) sw[w] = 0.0f;
+        const TileGeom gt = geo_t[min(t, ntiles - 1)];
+        const float *ct = cen_t + min(t, ntiles - 1) * dp;
+        int k = 0;
+        for (; k + 4 <= d; k += 4) {
+            const float4 c = *reinterpret_cast<const float4 *>(ct + k);
 #pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    if (w >= ng) break;
-                    const double L = sqrt((double)sw[w]) * (1.0 - 1e-5) - gw[w].r - gt.r;
-                    const double bound = ((double)(sym ? fmaxf(gw[w].tmax, gt.tmax) : gw[w].tmax) +
-                                          g * ((double)gw[w].nmax + (double)gt.nmax)) * (1.0 + 1e-6);
-                    keep[w] = !(L > 0.0 && L * L > bound);
-                }
+            for (int w = 0; w < NG; ++w) {
+                const float4 q = *reinterpret_cast<const float4 *>(&ca[w][k]);
+                float u = q.x - c.x;
+                sw[w] = fmaf(u, u, sw[w]);
+                u = q.y - c.y;
+                sw[w] = fmaf(u, u, sw[w]);
+                u = q.z - c.z;
+                sw[w] = fmaf(u, u, sw[w]);
+                u = q.w - c.w;
+                sw[w] = fmaf(u, u, sw[w]);
             }
         }
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        uint64_t any = 0;
-        int nw = 0;
-        for (int w = 0; w < 4; ++w) {
-            const uint64_t bits = __ballot(keep[w]);
-            any |= bits;
-            nw += __popcll(bits);
-            const int64_t wd = (base - t0) / 64 + wv;
-            if (lane == 0 && t0 + 64 * wd < ntiles) mask[(moff[b] + wd) * 4 + w] = bits;
+        for (; k < d; ++k) {
+            const float c = ct[k];
+#pragma unroll
+            for (int w = 0; w < NG; ++w) {
+                const float u = ca[w][k] - c;
+                sw[w] = fmaf(u, u, sw[w]);
+            }
         }
-        if (lane == 0) {
-            wsum[wv] = __popcll(any);
-            wwsum[wv] = nw;
+        const int64_t wd = (base - tA) / 64 + wv;
+#pragma unroll
+        for (int i = 0; i < TM_B; ++i) {
+            const int64_t b = b0 + i;
+            const int64_t t0 = sym ? 2 * b : 0;
+            const int nown = sym ? (int)min<int64_t>(2, ntiles - t0) : 0;
+            const int ngb = (int)min<int64_t>(4, ngroups - 4 * b);
+            uint64_t any = 0;
+            int nw = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int gi = 4 * i + w;
+                bool keep = false;
+                if (i < nb && w < ngb && t < ntiles && t >= t0) {
+                    if (t < t0 + nown) {
+                        keep = true;
+                    } else {
+                        // the test shrinks the centre distance by a relative
+                        // 1e-5, above the FP32 rounding bound (d + 2) 2^-24
+                        // for d <= 128
+                        const TileGeom gr = sg[gi];
+                        const double L = sqrt((double)sw[gi]) * (1.0 - 1e-5) - gr.r - gt.r;
+                        const double bound = ((double)(sym ? fmaxf(gr.tmax, gt.tmax) : gr.tmax) +
+                                              g * ((double)gr.nmax + (double)gt.nmax)) * (1.0 + 1e-6);
+                        keep = !(L > 0.0 && L * L > bound);
+                    }
+                }
+                const uint64_t bits = __ballot(keep);
+                any |= bits;
+                nw += __popcll(bits);
+                if (i < nb && lane == 0 && tA + 64 * wd < ntiles) mask[(moff[b] + wd) * 4 + w] = bits;
+            }
+            if (lane == 0) {
+                wsum[i][wv] = __popcll(any);
+                wwsum[i][wv] = nw;
+            }
         }
         __syncthreads();
-        total += wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        wtotal += wwsum[0] + wwsum[1] + wwsum[2] + wwsum[3];
+#pragma unroll
+        for (int i = 0; i < TM_B; ++i) {
+            total[i] += wsum[i][0] + wsum[i][1] + wsum[i][2] + wsum[i][3];
+            wtotal[i] += wwsum[i][0] + wwsum[i][1] + wwsum[i][2] + wwsum[i][3];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        cnt[b] = total;
-        wcnt[b] = wtotal;
+    if (threadIdx.x < nb) {
+#pragma unroll
+        for (int i = 0; i < TM_B; ++i)
+            if (i == (int)threadIdx.x) {
+                atomicAdd((unsigned long long *)&cnt[b0 + i], (unsigned long long)total[i]);
+                atomicAdd((unsigned long long *)&wcnt[b0 + i], (unsigned long long)wtotal[i]);
+            }
     }
 }
 
@@ -1374,7 +1408,7 @@ __global__ __launch_bounds__(64) void k_tile_list(const uint64_t *__restrict__ m
                                                   int64_t ntiles, int sym, const int64_t *__restrict__ toff,
                                                   int32_t *__restrict__ tlist)
 {
-    const int64_t b = blockIdx.x, t0 = sym ? 2 * b : 0;
+    const int64_t b = blockIdx.x, t0 = tile_mask_base(b, sym);
     const int64_t nw = (ntiles - t0 + 63) / 64;
     int64_t o = toff[b];
     const int lane = threadIdx.x;
@@ -1413,7 +1447,7 @@ static bool build_tile_lists(const float *Xr, const float *thr_r, const float *X
     int64_t words = 0;
     for (int64_t b = 0; b < nblk; ++b) {
         hmoff[b] = words;
-        words += (ntiles - (sym ? 2 * b : 0) + 63) / 64;
+        words += (ntiles - (sym ? (2 * b) & ~(int64_t)63 : 0) + 63) / 64;
     }
     hmoff[nblk] = words;
     float *cen_t = (float *)ta(sizeof(float) * ntiles * dp);
@@ -1431,8 +1465,14 @@ static bool build_tile_lists(const float *Xr, const float *thr_r, const float *X
     hipLaunchKernelGGL(k_tile_geom<32>, dim3((unsigned)ngroups), dim3(64), 0, s, Xr, dp, d, M, thr_r, Xn_r, cen_g,
                        geo_g);
     const double g = 2.0 * (3.1 * ldexp(1.0, -16) + (4.0 * dp + 8.0) * ldexp(1.0, -24));
-    hipLaunchKernelGGL(k_tile_mask, dim3((unsigned)nblk), dim3(256), 0, s, cen_g, geo_g, ngroups, cen_t, geo_t, dp, d,
-                       ntiles, g, sym ? 1 : 0, moff, mask, cnt, wcnt);
+    // about 1024 workgroups or more: few row blocks split the tiles
+    const int64_t nwg = (nblk + TM_B - 1) / TM_B, nchunk = (ntiles + 255) / 256;
+    const int64_t nsplit = sym ? 1 : std::max<int64_t>(1, std::min<int64_t>(nchunk, 1024 / nwg));
+    const int64_t span = (nchunk + nsplit - 1) / nsplit * 256;
+    HIPC(hipMemsetAsync(cnt, 0, sizeof(int64_t) * nblk, s));
+    HIPC(hipMemsetAsync(wcnt, 0, sizeof(int64_t) * nblk, s));
+    hipLaunchKernelGGL(k_tile_mask, dim3((unsigned)nwg, (unsigned)nsplit), dim3(256), 0, s, cen_g, geo_g, ngroups,
+                       nblk, cen_t, geo_t, dp, d, ntiles, g, sym ? 1 : 0, span, moff, mask, cnt, wcnt);
     HIPC(hipGetLastError());
     std::vector<int64_t> hc(nblk), ho(nblk + 1), hw(nblk);
     HIPC(hipMemcpyAsync(hc.data(), cnt, sizeof(int64_t) * nblk, hipMemcpyDeviceToHost, s));
