@@ -48,21 +48,22 @@ __global__ void k_cols(const SkelInst *__restrict__ inst, const int2 *__restrict
 }
 
 // G[q][c][t] = exp(-D(x_T[t], x_C[c]) / (2 h_c^2)), FP64.  Block per (node,
-// chunk of FG_C columns), one thread per sampled row t (blockDim = ell rounded
-// up to whole waves): the thread holds FG_K coordinates of its row in
-// registers, the chunk's columns are staged in LDS as FP64 (every lane reads
-// the same column entry: a broadcast), and each of the thread's FG_C partial
-// distances adds the dimensions in increasing order, so D is the same
-// sequential FP64 sum as everywhere else (subtract, square, add; no fused
-// multiply-add).
+// chunk of FG_C columns), FG_R sampled rows per thread (rows t and t +
+// blockDim; blockDim = ell / FG_R rounded up to whole waves): the thread holds
+// FG_K coordinates of its rows in registers, the chunk's columns are staged
+// in LDS as FP64 (every lane reads the same column entry: a broadcast, used
+// for FG_R rows), and each of the thread's partial distances adds the
+// dimensions in increasing order, so D is the same sequential FP64 sum as
+// everywhere else (subtract, square, add; no fused multiply-add).
 constexpr int FG_C = 8;           // columns per block
 constexpr int FG_K = 16;          // dimensions per stage
+constexpr int FG_R = 2;           // sampled rows per thread
 constexpr int FG_MAXROW = 1024;
 
-__global__ __launch_bounds__(FG_MAXROW) void k_form_G(const SkelInst *__restrict__ inst,
-                                                      const int2 *__restrict__ items, int ell,
-                                                      const int32_t *__restrict__ colpos, int ncol_max,
-                                                      double *__restrict__ G)
+__global__ __launch_bounds__(FG_MAXROW / FG_R) void k_form_G(const SkelInst *__restrict__ inst,
+                                                             const int2 *__restrict__ items, int ell,
+                                                             const int32_t *__restrict__ colpos, int ncol_max,
+                                                             double *__restrict__ G)
 {
 #pragma clang fp contract(off)
     __shared__ __attribute__((aligned(16))) double sC[FG_K][FG_C];    // [dimension][column]
@@ -79,30 +80,36 @@ __global__ __launch_bounds__(FG_MAXROW) void k_form_G(const SkelInst *__restrict
     const int nc = min(FG_C, I.ncols[a] - c0);
     const int rows = I.T_cnt[a];
     if (nc <= 0 || rows <= 0) return;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, nt = blockDim.x;
     if (t < FG_C) sCid[t] = colpos[(int64_t)q * ncol_max + c0 + min(t, nc - 1)];
     // rows past `rows` repeat the last one and write nothing
-    const float *xr = Xt + (int64_t)I.T[(int64_t)a * ell + min(t, rows - 1)] * dp;
-    double acc[FG_C];
+    const float *xr[FG_R];
 #pragma unroll
-    for (int c = 0; c < FG_C; ++c) acc[c] = 0.0;
+    for (int r = 0; r < FG_R; ++r) xr[r] = Xt + (int64_t)I.T[(int64_t)a * ell + min(t + r * nt, rows - 1)] * dp;
+    double acc[FG_R][FG_C];
+#pragma unroll
+    for (int r = 0; r < FG_R; ++r)
+#pragma unroll
+        for (int c = 0; c < FG_C; ++c) acc[r][c] = 0.0;
     for (int k0 = 0; k0 < d; k0 += FG_K) {
         const int kk = min(FG_K, d - k0);
-        // a whole stage: the row's coordinates first (their loads overlap the
+        // a whole stage: the rows' coordinates first (their loads overlap the
         // staging); rows are 16-byte aligned (dp is a multiple of 16)
-        float xv[FG_K];
+        float xv[FG_R][FG_K];
         if (kk == FG_K) {
 #pragma unroll
-            for (int j = 0; j < FG_K; j += 4) {
-                const float4 v = *reinterpret_cast<const float4 *>(xr + k0 + j);
-                xv[j] = v.x;
-                xv[j + 1] = v.y;
-                xv[j + 2] = v.z;
-                xv[j + 3] = v.w;
-            }
+            for (int r = 0; r < FG_R; ++r)
+#pragma unroll
+                for (int j = 0; j < FG_K; j += 4) {
+                    const float4 v = *reinterpret_cast<const float4 *>(xr[r] + k0 + j);
+                    xv[r][j] = v.x;
+                    xv[r][j + 1] = v.y;
+                    xv[r][j + 2] = v.z;
+                    xv[r][j + 3] = v.w;
+                }
         }
         __syncthreads();                       // sCid written; the previous stage's reads done
-        for (int e = t; e < FG_K * FG_C; e += blockDim.x) {
+        for (int e = t; e < FG_K * FG_C; e += nt) {
             const int j = e / FG_C, c = e % FG_C;
             sC[j][c] = (double)Xt[(int64_t)sCid[c] * dp + min(k0 + j, dp - 1)];
         }
@@ -110,32 +117,48 @@ __global__ __launch_bounds__(FG_MAXROW) void k_form_G(const SkelInst *__restrict
         if (kk == FG_K) {
 #pragma unroll
             for (int j = 0; j < FG_K; ++j) {
-                const double xd = (double)xv[j];
+                double xd[FG_R];
+#pragma unroll
+                for (int r = 0; r < FG_R; ++r) xd[r] = (double)xv[r][j];
 #pragma unroll
                 for (int c = 0; c < FG_C; ++c) {
-                    const double df = xd - sC[j][c];
-                    acc[c] = acc[c] + df * df;
+                    const double y = sC[j][c];
+#pragma unroll
+                    for (int r = 0; r < FG_R; ++r) {
+                        const double df = xd[r] - y;
+                        acc[r][c] = acc[r][c] + df * df;
+                    }
                 }
             }
         } else {
             // the last, partial stage (k0 + j < d <= dp)
 #pragma unroll 1
             for (int j = 0; j < kk; ++j) {
-                const double xd = (double)xr[k0 + j];
+                double xd[FG_R];
+#pragma unroll
+                for (int r = 0; r < FG_R; ++r) xd[r] = (double)xr[r][k0 + j];
 #pragma unroll
                 for (int c = 0; c < FG_C; ++c) {
-                    const double df = xd - sC[j][c];
-                    acc[c] = acc[c] + df * df;
+                    const double y = sC[j][c];
+#pragma unroll
+                    for (int r = 0; r < FG_R; ++r) {
+                        const double df = xd[r] - y;
+                        acc[r][c] = acc[r][c] + df * df;
+                    }
                 }
             }
         }
     }
-    if (t < rows) {
 #pragma unroll
-        for (int c = 0; c < FG_C; ++c) {
-            if (c >= nc) break;
-            const double hc = hpos ? hpos[sCid[c]] : h;
-            G[((int64_t)q * ncol_max + c0 + c) * ell + t] = exp(-acc[c] / (2.0 * hc * hc));
+    for (int r = 0; r < FG_R; ++r) {
+        const int row = t + r * nt;
+        if (row < rows) {
+#pragma unroll
+            for (int c = 0; c < FG_C; ++c) {
+                if (c >= nc) break;
+                const double hc = hpos ? hpos[sCid[c]] : h;
+                G[((int64_t)q * ncol_max + c0 + c) * ell + row] = exp(-acc[r][c] / (2.0 * hc * hc));
+            }
         }
     }
 }
@@ -1062,7 +1085,7 @@ void skeletonize_multi(const std::vector<askit_handle *> &hs, hipStream_t s)
             HIPC(hipMemcpyAsync(d_items, items.data(), sizeof(int2) * nb, hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_cols, dim3(nb), dim3(256), 0, s, d_inst, d_items, smax, ncm, colpos);
             {
-                dim3 gg((ncm + FG_C - 1) / FG_C, nb), gb((ell + 63) / 64 * 64);
+                dim3 gg((ncm + FG_C - 1) / FG_C, nb), gb(((ell + FG_R - 1) / FG_R + 63) / 64 * 64);
                 hipLaunchKernelGGL(k_form_G, gg, gb, 0, s, d_inst, d_items, ell, colpos, ncm, G);
                 HIPC(hipGetLastError());
             }
