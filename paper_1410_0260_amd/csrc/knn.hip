@@ -1795,7 +1795,9 @@ __global__ __launch_bounds__(256) void k_knn_refine(const float *__restrict__ Q,
                                                     int32_t *__restrict__ bad_count,
                                                     float *__restrict__ tbound)
 {
-    int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    // the row is the same for the whole wave (made explicit, so that the
+    // query row's coordinates come through scalar loads)
+    const int64_t row = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + threadIdx.x / WAVE));
     int lane = threadIdx.x % WAVE;
     if (row >= M) return;
     int j = cand[row * KNN_CAND + lane];
