@@ -424,6 +424,9 @@ __global__ __launch_bounds__(QG_T) void k_qrcp_gang(double *__restrict__ Gall, i
     const int gang = (int)(blockIdx.x / (8 * W)) * 8 + (int)(blockIdx.x % 8), w = (int)(blockIdx.x / 8) % W;
     int32_t gs = 0;                           // steps published by this gang
     unsigned long long tph[7] = {0, 0, 0, 0, 0, 0, 0};
+    // an earlier gang of this skeletonization timed out: nothing to do (the
+    // flag was set before this launch began, so every workgroup sees it)
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     if (tid == 0) s_fail = 0;
     for (int q = gang; q < nb; q += ngang) {
         __syncthreads();
@@ -878,6 +881,8 @@ struct GangScratch {
     unsigned long long *tacc = nullptr;     // ASKIT_QR_TIMING: phase cycle sums, else NULL
 };
 
+// Clears n exchange slots, and the error flag when err is given (once per
+// skeletonization: the flag then stays set once any gang timed out).
 __global__ void k_gang_reset(GangSlot *__restrict__ slots, int n, int32_t *__restrict__ err)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -885,7 +890,7 @@ __global__ void k_gang_reset(GangSlot *__restrict__ slots, int n, int32_t *__res
         slots[i].seq = 0;
         slots[i].col = -1;
     }
-    if (i == 0) *err = 0;
+    if (i == 0 && err) *err = 0;
 }
 
 // Gang launches are serialized across host threads: each needs all of its
@@ -907,7 +912,7 @@ static bool qr_gang_launch1(double *G, int ell, int ncm, const SkelInst *inst, c
     if (ngang < 8) return false;
     const int nslot = ngang * 2 * W;
     hipLaunchKernelGGL(k_gang_reset, dim3((unsigned)((nslot + 255) / 256)), dim3(256), 0, s, gs.slots, nslot,
-                       gs.err);
+                       (int32_t *)nullptr);
     HIPC(hipGetLastError());
     GangSlot *slots = gs.slots;
     double *sdata = gs.sdata;
@@ -1022,7 +1027,6 @@ void skeletonize_multi(const std::vector<askit_handle *> &hs, hipStream_t s)
     const int batch = (int)std::max<size_t>(1, std::min<size_t>((size_t)maxlev, (size_t)(4ull << 30) / per));
     double *G = (double *)ta(per * batch);
     int32_t *colpos = (int32_t *)ta(sizeof(int32_t) * (size_t)ncm * batch);
-    int2 *d_items = (int2 *)ta(sizeof(int2) * batch);
     const size_t sv_lds = sizeof(double) * (size_t)std::min(smax, ell) * SV_C;
     if (sv_lds > 64 * 1024)
         HIPC(hipFuncSetAttribute((const void *)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1056,108 +1060,129 @@ void skeletonize_multi(const std::vector<askit_handle *> &hs, hipStream_t s)
         const char *tenv = std::getenv("ASKIT_QR_TIMING");
         if (tenv && std::atoi(tenv) == 1) gsc.tacc = (unsigned long long *)ta(sizeof(unsigned long long) * 8);
     }
-    hipEvent_t q0, q1;
-    HIPC(hipEventCreate(&q0));
-    HIPC(hipEventCreate(&q1));
-    struct EvFree {
-        hipEvent_t a, b;
-        ~EvFree()
-        {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-        }
-    } evf{q0, q1};
-    double t_qr = 0.0;
+    // every level's batches of nodes (those that take the gang form first),
+    // uploaded at once: the levels then follow each other on the stream with
+    // no host wait between them (the gang diagnostic waits per level)
+    struct Batch {
+        int lev, off, nb, ng;
+    };
+    std::vector<Batch> bat;
     std::vector<int2> items;
     for (int lev = maxdepth; lev >= 1; --lev) {
-        // the level's nodes, those that take the gang form first
         std::vector<int2> all;
         for (int pass = 0; pass < 2; ++pass)
             for (size_t i = 0; i < hs.size(); ++i)
                 if (lev <= hs[i]->depth && gang_node(hs[i]) == (pass == 0))
                     for (int a : hs[i]->level_nodes[lev]) all.push_back(int2{(int)i, a});
         for (size_t b0 = 0; b0 < all.size(); b0 += batch) {
-            items.assign(all.begin() + b0, all.begin() + std::min(all.size(), b0 + batch));
-            const int nb = (int)items.size();
-            int ng = 0;                             // items [0, ng) take the gang form
-            while (ng < nb && gang_node(hs[items[ng].x])) ++ng;
-            HIPC(hipStreamSynchronize(s));          // the previous batch is done with d_items
-            HIPC(hipMemcpyAsync(d_items, items.data(), sizeof(int2) * nb, hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_cols, dim3(nb), dim3(256), 0, s, d_inst, d_items, smax, ncm, colpos);
-            {
-                dim3 gg((ncm + FG_C - 1) / FG_C, nb), gb(((ell + FG_R - 1) / FG_R + 63) / 64 * 64);
-                hipLaunchKernelGGL(k_form_G, gg, gb, 0, s, d_inst, d_items, ell, colpos, ncm, G);
-                HIPC(hipGetLastError());
-            }
-            HIPC(hipEventRecord(q0, s));
-            // every level: the node's columns in registers across a gang of
-            // workgroups (4 per node from 64 nodes on, else 8), as many gangs
-            // as fit at once, each taking nodes in turn; one workgroup per
-            // node streaming G when the gang cannot run (no cooperative
-            // launch, more than 512 columns or 288 rows)
-            bool gang = false;
-            std::unique_lock<std::mutex> glk(g_gang_mu, std::defer_lock);
-            if (use_gang && ng > 0) {
-                glk.lock();
-                if (gsc.tacc) HIPC(hipMemsetAsync(gsc.tacc, 0, sizeof(unsigned long long) * 8, s));
-                if (ell <= 16 * 8)
-                    gang = ng >= 64 ? qr_gang_launch<4, 8, 4>(G, ell, ncm, d_inst, d_items, smax, tau, ng, gsc,
-                                                             g_timeout, s)
-                                    : qr_gang_launch<8, 8, 2>(G, ell, ncm, d_inst, d_items, smax, tau, ng, gsc,
-                                                             g_timeout, s);
-                else
-                    gang = ng >= 64 ? qr_gang_launch<4, 18, 4>(G, ell, ncm, d_inst, d_items, smax, tau, ng, gsc,
-                                                              g_timeout, s)
-                                    : qr_gang_launch<8, 18, 2>(G, ell, ncm, d_inst, d_items, smax, tau, ng, gsc,
-                                                              g_timeout, s);
-                if (!gang) glk.unlock();
-            }
-            // the rest (all items when the gang did not run), streaming G
-            const int q0i = gang ? ng : 0, nrest = nb - q0i;
-            double *Gr = G + (int64_t)q0i * ncm * ell;
-            const int2 *ir = d_items + q0i;
-            if (nrest == 0) {
-            } else if (ell <= 16 * 8)
-                hipLaunchKernelGGL((k_qrcp<512, 8>), dim3((unsigned)nrest), dim3(512), 0, s, Gr, ell, ncm, d_inst,
-                                   ir, smax, tau, nrest);
-            else if (ell <= 16 * 18)
-                hipLaunchKernelGGL((k_qrcp<512, 18>), dim3((unsigned)nrest), dim3(512), 0, s, Gr, ell, ncm,
-                                   d_inst, ir, smax, tau, nrest);
-            else
-                hipLaunchKernelGGL((k_qrcp<QR_T, 0>), dim3((unsigned)nrest), dim3(QR_T), 0, s, Gr, ell, ncm,
-                                   d_inst, ir, smax, tau, nrest);
-            HIPC(hipEventRecord(q1, s));
-            if (smax <= SR_L * SR_R)
-                hipLaunchKernelGGL(k_solve_reg, dim3((ncm + SR_C - 1) / SR_C, nb), dim3(256), 0, s, G, ell, ncm,
-                                   d_inst, d_items);
-            else
-                hipLaunchKernelGGL(k_solve, dim3((ncm + SV_C - 1) / SV_C, nb), dim3(SV_T), sv_lds, s, G, ell,
-                                   ncm, d_inst, d_items);
-            hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(256), 0, s, G, ell, ncm, d_inst, d_items, colpos, smax);
+            const int nb = (int)std::min<size_t>(batch, all.size() - b0);
+            int ng = 0;
+            while (ng < nb && gang_node(hs[all[b0 + ng].x])) ++ng;
+            bat.push_back(Batch{lev, (int)items.size(), nb, ng});
+            items.insert(items.end(), all.begin() + b0, all.begin() + b0 + nb);
+        }
+    }
+    int2 *d_items_all = (int2 *)ta(sizeof(int2) * std::max<size_t>(items.size(), 1));
+    if (!items.empty())
+        HIPC(hipMemcpyAsync(d_items_all, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s));
+    // gang launches of other threads wait for this whole pass (a gang needs
+    // its workgroups co-resident)
+    std::unique_lock<std::mutex> glk(g_gang_mu, std::defer_lock);
+    if (use_gang) {
+        glk.lock();
+        hipLaunchKernelGGL(k_gang_reset, dim3(1), dim3(64), 0, s, gsc.slots, 0, gsc.err);
+        HIPC(hipGetLastError());
+    }
+    std::vector<hipEvent_t> qev;                // brackets of each batch's factorization (timing only)
+    struct QevFree {
+        std::vector<hipEvent_t> &v;
+        ~QevFree()
+        {
+            for (hipEvent_t e : v) (void)hipEventDestroy(e);
+        }
+    } qevf{qev};
+    bool any_gang = false;
+    for (const Batch &bt : bat) {
+        const int nb = bt.nb, ng = bt.ng, lev = bt.lev;
+        int2 *d_items = d_items_all + bt.off;
+        hipLaunchKernelGGL(k_cols, dim3(nb), dim3(256), 0, s, d_inst, d_items, smax, ncm, colpos);
+        {
+            dim3 gg((ncm + FG_C - 1) / FG_C, nb), gb(((ell + FG_R - 1) / FG_R + 63) / 64 * 64);
+            hipLaunchKernelGGL(k_form_G, gg, gb, 0, s, d_inst, d_items, ell, colpos, ncm, G);
             HIPC(hipGetLastError());
+        }
+        qev.resize(qev.size() + 2);
+        HIPC(hipEventCreate(&qev[qev.size() - 2]));
+        HIPC(hipEventCreate(&qev.back()));
+        HIPC(hipEventRecord(qev[qev.size() - 2], s));
+        // every level: the node's columns in registers across a gang of
+        // workgroups (4 per node from 64 nodes on, else 8), as many gangs
+        // as fit at once, each taking nodes in turn; one workgroup per
+        // node streaming G when the gang cannot run (no cooperative
+        // launch, more than 512 columns or 288 rows)
+        bool gang = false;
+        if (use_gang && ng > 0) {
+            if (gsc.tacc) HIPC(hipMemsetAsync(gsc.tacc, 0, sizeof(unsigned long long) * 8, s));
+            if (ell <= 16 * 8)
+                gang = ng >= 64 ? qr_gang_launch<4, 8, 4>(G, ell, ncm, d_inst, d_items, smax, tau, ng, gsc,
+                                                         g_timeout, s)
+                                : qr_gang_launch<8, 8, 2>(G, ell, ncm, d_inst, d_items, smax, tau, ng, gsc,
+                                                         g_timeout, s);
+            else
+                gang = ng >= 64 ? qr_gang_launch<4, 18, 4>(G, ell, ncm, d_inst, d_items, smax, tau, ng, gsc,
+                                                          g_timeout, s)
+                                : qr_gang_launch<8, 18, 2>(G, ell, ncm, d_inst, d_items, smax, tau, ng, gsc,
+                                                          g_timeout, s);
+        }
+        any_gang = any_gang || gang;
+        // the rest (all items when the gang did not run), streaming G
+        const int q0i = gang ? ng : 0, nrest = nb - q0i;
+        double *Gr = G + (int64_t)q0i * ncm * ell;
+        const int2 *ir = d_items + q0i;
+        if (nrest == 0) {
+        } else if (ell <= 16 * 8)
+            hipLaunchKernelGGL((k_qrcp<512, 8>), dim3((unsigned)nrest), dim3(512), 0, s, Gr, ell, ncm, d_inst,
+                               ir, smax, tau, nrest);
+        else if (ell <= 16 * 18)
+            hipLaunchKernelGGL((k_qrcp<512, 18>), dim3((unsigned)nrest), dim3(512), 0, s, Gr, ell, ncm,
+                               d_inst, ir, smax, tau, nrest);
+        else
+            hipLaunchKernelGGL((k_qrcp<QR_T, 0>), dim3((unsigned)nrest), dim3(QR_T), 0, s, Gr, ell, ncm,
+                               d_inst, ir, smax, tau, nrest);
+        HIPC(hipEventRecord(qev.back(), s));
+        if (smax <= SR_L * SR_R)
+            hipLaunchKernelGGL(k_solve_reg, dim3((ncm + SR_C - 1) / SR_C, nb), dim3(256), 0, s, G, ell, ncm,
+                               d_inst, d_items);
+        else
+            hipLaunchKernelGGL(k_solve, dim3((ncm + SV_C - 1) / SV_C, nb), dim3(SV_T), sv_lds, s, G, ell,
+                               ncm, d_inst, d_items);
+        hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(256), 0, s, G, ell, ncm, d_inst, d_items, colpos, smax);
+        HIPC(hipGetLastError());
+        if (gang && gsc.tacc) {
             HIPC(hipStreamSynchronize(s));
-            if (gang) {
-                int32_t herr = 0;
-                HIPC(hipMemcpy(&herr, gsc.err, sizeof(int32_t), hipMemcpyDeviceToHost));
-                glk.unlock();
-                if (herr) fail(ASKIT_ERR_DEVICE, "QR gang exchange timed out (workgroups not co-resident)");
-                if (gsc.tacc) {
-                    unsigned long long tc[8];
-                    HIPC(hipMemcpy(tc, gsc.tacc, sizeof(tc), hipMemcpyDeviceToHost));
-                    const double st = tc[6] ? (double)tc[6] : 1.0;
-                    std::fprintf(stderr,
-                                 "[askit qr timing] level %d: %d nodes, %llu workgroup pivot steps; cycles per step: "
-                                 "argmax %.0f, publish %.0f, wait %.0f, load %.0f, reflector %.0f, update %.0f\n",
-                                 lev, ng, tc[6], tc[0] / st, tc[1] / st, tc[2] / st, tc[3] / st, tc[4] / st,
-                                 tc[5] / st);
-                }
-            }
-            float ms = 0.f;
-            HIPC(hipEventElapsedTime(&ms, q0, q1));
-            t_qr += ms;
+            unsigned long long tc[8];
+            HIPC(hipMemcpy(tc, gsc.tacc, sizeof(tc), hipMemcpyDeviceToHost));
+            const double st = tc[6] ? (double)tc[6] : 1.0;
+            std::fprintf(stderr,
+                         "[askit qr timing] level %d: %d nodes, %llu workgroup pivot steps; cycles per step: "
+                         "argmax %.0f, publish %.0f, wait %.0f, load %.0f, reflector %.0f, update %.0f\n",
+                         lev, ng, tc[6], tc[0] / st, tc[1] / st, tc[2] / st, tc[3] / st, tc[4] / st, tc[5] / st);
         }
     }
     HIPC(hipStreamSynchronize(s));
+    if (any_gang) {
+        // the flag stays set once any gang exchange timed out
+        int32_t herr = 0;
+        HIPC(hipMemcpy(&herr, gsc.err, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (herr) fail(ASKIT_ERR_DEVICE, "QR gang exchange timed out (workgroups not co-resident)");
+    }
+    if (glk.owns_lock()) glk.unlock();
+    double t_qr = 0.0;
+    for (size_t e = 0; e < qev.size(); e += 2) {
+        float ms = 0.f;
+        HIPC(hipEventElapsedTime(&ms, qev[e], qev[e + 1]));
+        t_qr += ms;
+    }
     for (auto *h : hs) h->t_qr = t_qr;
 }
 
